@@ -1,0 +1,268 @@
+"""ORACLE -- test infrastructure, not part of the product path.
+
+A plain, slow CPU reference for the solver: K-word (binary64, double-double,
+triple-double, quad-double) LU with partial pivoting, substitutions, the exact
+residual, and the mixed-precision iterative refinement loop of the paper's
+Listing 1 (Kouya 2021, Sec. 2).  Only ``tests/``, ``__graft_entry__.smoke()``
+and the ``cpu_baseline`` leg of ``bench.py`` may import this package.  It
+shares no code with ``paper_2107_12550_amd``; both sides read the same seeded
+inputs from ``synth``.
+
+Arrays use the K-plane layout: a K-word n x n matrix is a float64 array of
+shape (K, n, n) whose element [w, j, i] is word w of entry (i, j) (each plane
+column-major); a K-word vector is shape (K, n).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "mwla.c")
+_LIB = os.path.join(_HERE, "libmwla_oracle.so")
+GCC_FLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-shared", "-fPIC"]
+
+# refinement status codes (same numbering as the product's C-ABI)
+CONVERGED, MAX_ITER, SINGULAR, NONFINITE = 0, 1, 2, 3
+
+
+def build() -> str:
+    """Compile the C oracle with gcc (no contraction, no fast-math)."""
+    tmp = _LIB + ".tmp"
+    subprocess.check_call(["gcc", *GCC_FLAGS, "-o", tmp, _SRC, "-lm"])
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.POINTER(ctypes.c_double)
+        I64 = ctypes.c_int64
+        L.orc_two_sum.argtypes = [I64, P, P, P, P]
+        L.orc_two_prod.argtypes = [I64, P, P, P, P]
+        L.orc_fms_vec.argtypes = [ctypes.c_int, I64, P, P, P, P]
+        L.orc_mul_vec.argtypes = [ctypes.c_int, I64, P, P, P]
+        L.orc_add_vec.argtypes = [ctypes.c_int, I64, P, P, P]
+        L.orc_recip_vec.argtypes = [ctypes.c_int, I64, P, P]
+        L.orc_round_vec.argtypes = [ctypes.c_int, ctypes.c_int, I64, P, P]
+        L.orc_key_gt_vec.argtypes = [ctypes.c_int, I64, P, P, ctypes.POINTER(ctypes.c_int32)]
+        L.orc_getrf.argtypes = [ctypes.c_int, I64, P, I64, I64, ctypes.POINTER(I64)]
+        L.orc_getrf.restype = I64
+        L.orc_getrs.argtypes = [ctypes.c_int, I64, I64, P, I64, I64, ctypes.POINTER(I64), P, I64, I64]
+        L.orc_residual.argtypes = [I64, ctypes.c_int, P, I64, I64, P, I64, P, I64, P, I64]
+        L.orc_residual.restype = I64
+        L.orc_exact_dot.argtypes = [ctypes.c_int, I64, P, P, ctypes.POINTER(ctypes.c_int32), P]
+        L.orc_exact_dot.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _c(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+# --------------------------------------------------------------------------
+# error-free transformations and K-word primitives (vectorised, word-major)
+# --------------------------------------------------------------------------
+
+def two_sum(a, b):
+    a, b = _c(a).ravel(), _c(b).ravel()
+    s, e = np.empty_like(a), np.empty_like(a)
+    lib().orc_two_sum(a.size, _p(a), _p(b), _p(s), _p(e))
+    return s, e
+
+
+def two_prod(a, b):
+    a, b = _c(a).ravel(), _c(b).ravel()
+    p, e = np.empty_like(a), np.empty_like(a)
+    lib().orc_two_prod(a.size, _p(a), _p(b), _p(p), _p(e))
+    return p, e
+
+
+def fms(K: int, c, a, b) -> np.ndarray:
+    """c - a*b for (K, n) arrays of K-word values."""
+    c, a, b = _c(c), _c(a), _c(b)
+    out = np.empty_like(a)
+    lib().orc_fms_vec(K, a.shape[1], _p(c), _p(a), _p(b), _p(out))
+    return out
+
+
+def mul(K: int, a, b) -> np.ndarray:
+    a, b = _c(a), _c(b)
+    out = np.empty_like(a)
+    lib().orc_mul_vec(K, a.shape[1], _p(a), _p(b), _p(out))
+    return out
+
+
+def add(K: int, a, b) -> np.ndarray:
+    a, b = _c(a), _c(b)
+    out = np.empty_like(a)
+    lib().orc_add_vec(K, a.shape[1], _p(a), _p(b), _p(out))
+    return out
+
+
+def recip(K: int, a) -> np.ndarray:
+    a = _c(a)
+    out = np.empty_like(a)
+    lib().orc_recip_vec(K, a.shape[1], _p(a), _p(out))
+    return out
+
+
+def round_words(K: int, src) -> np.ndarray:
+    """Renormalise m-word values (shape (m, n), m <= 4) to K words."""
+    src = _c(src)
+    m, n = src.shape
+    out = np.empty((K, n))
+    lib().orc_round_vec(K, m, n, _p(src), _p(out))
+    return out
+
+
+def key_gt(K: int, a, b) -> np.ndarray:
+    a, b = _c(a), _c(b)
+    out = np.empty(a.shape[1], dtype=np.int32)
+    lib().orc_key_gt_vec(K, a.shape[1], _p(a), _p(b), out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    return out.astype(bool)
+
+
+def exact_round(K: int, p, q=None, signs=None) -> tuple[np.ndarray, bool]:
+    """Exact sum_t s_t p_t q_t (or sum_t s_t p_t) rounded to K canonical words."""
+    p = _c(p).ravel()
+    qq = None if q is None else _c(q).ravel()
+    s = np.ones(p.size, dtype=np.int32) if signs is None else np.ascontiguousarray(signs, dtype=np.int32)
+    out = np.zeros(K)
+    bad = lib().orc_exact_dot(K, p.size, _p(p), None if qq is None else _p(qq),
+                              s.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _p(out))
+    return out, bool(bad)
+
+
+# --------------------------------------------------------------------------
+# LU, substitutions, exact residual
+# --------------------------------------------------------------------------
+
+def stage(K: int, A: np.ndarray) -> np.ndarray:
+    """Short-precision copy of an aw-word matrix (shape (aw, n, n)) in K words."""
+    aw, n, _ = A.shape
+    return round_words(K, A.reshape(aw, n * n)).reshape(K, n, n)
+
+
+def getrf(K: int, A: np.ndarray):
+    """In-place-style PA = LU of a (K, n, n) array; returns (LU, ipiv, info)."""
+    LU = _c(A).copy()
+    n = LU.shape[1]
+    ipiv = np.zeros(n, dtype=np.int64)
+    info = lib().orc_getrf(K, n, _p(LU), n, n * n, ipiv.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    return LU, ipiv, int(info)
+
+
+def getrs(K: int, LU: np.ndarray, ipiv: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """x with A x = b from the factors; b has shape (K, n) or (K, nrhs, n)."""
+    LU = _c(LU)
+    n = LU.shape[1]
+    B = _c(b).copy()
+    nrhs = 1 if B.ndim == 2 else B.shape[1]
+    ipiv = np.ascontiguousarray(ipiv, dtype=np.int64)
+    lib().orc_getrs(K, n, nrhs, _p(LU), n, n * n, ipiv.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                    _p(B), n, n * nrhs)
+    return B
+
+
+def residual(A: np.ndarray, x: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """r = b - A x exactly, rounded to canonical quad-double (shape (4, n))."""
+    A, x, b = _c(A), _c(x), _c(b)
+    aw, n, _ = A.shape
+    assert x.shape == (4, n) and b.shape == (4, n)
+    r = np.empty((4, n))
+    bad = lib().orc_residual(n, aw, _p(A), n, n * n, _p(x), n, _p(b), n, _p(r), n)
+    if bad:
+        raise FloatingPointError("residual word outside the binary64 normal range")
+    return r
+
+
+def extend(v: np.ndarray, K: int = 4) -> np.ndarray:
+    """Zero-extend a k-word vector to K words (exact)."""
+    out = np.zeros((K, v.shape[1]))
+    out[: v.shape[0]] = v
+    return out
+
+
+def norm2(v: np.ndarray) -> float:
+    """2-norm of a binary64 vector, power-of-two scaled to avoid under/overflow."""
+    v = np.abs(np.asarray(v, dtype=np.float64).ravel())
+    m = float(v.max()) if v.size else 0.0
+    if m == 0.0 or not math.isfinite(m):
+        return m
+    e = math.frexp(m)[1]
+    s = np.ldexp(v, -e)
+    return math.ldexp(math.sqrt(math.fsum((s * s).tolist())), e)
+
+
+def refine(A: np.ndarray, b: np.ndarray, K: int, max_iter: int = 30,
+           rtol: float = 0.0, atol: float = 0.0, ctol: float = 2.0 ** -208) -> dict:
+    """Mixed-precision iterative refinement, Listing 1 of the paper (Sec. 2).
+
+    A: (aw, n, n) with aw = 1 (binary64 entries) or 4 (quad-double entries).
+    b: (4, n) quad-double.  Factor precision K words; long precision is
+    quad-double with an exact residual rounded once (the reading of the
+    residual step).  Steps, in the listing's order:
+      ||A||_F; K-word copies of A and b; LU + substitution; x to long;
+      loop: r = b - A x; stop if ||r|| < sqrt(n) rtol ||A||_F ||x|| + atol
+      (the listing's test, eq. (2)) or if the previous correction satisfied
+      ||z||_inf <= ctol ||x||_inf (forward test added by this reading: the
+      residual test certifies only a backward error, ~kappa * rtol forward);
+      r <- r * 2^-e (power-of-two normalisation); K-word copy of r;
+      substitution -> z; z <- 2^e z; x <- x + z.
+    Norms are taken over leading words in binary64.  Returns a dict with
+    x (4, n), iters (corrections applied), status, info, history of ||r||.
+    """
+    A = _c(A)
+    b = _c(b)
+    aw, n, _ = A.shape
+    if not (np.isfinite(A).all() and np.isfinite(b).all()):
+        return dict(x=np.zeros((4, n)), iters=0, status=NONFINITE, info=0, history=[])
+    norm_a = norm2(A[0])
+    LU = stage(K, A)
+    bf = round_words(K, b)
+    LU, ipiv, info = getrf(K, LU)
+    if info:
+        return dict(x=np.zeros((4, n)), iters=0, status=SINGULAR, info=info, history=[],
+                    LU=LU, ipiv=ipiv)
+    x = extend(getrs(K, LU, ipiv, bf))
+    hist = []
+    iters = 0
+    status = MAX_ITER
+    thresh_c = math.sqrt(n) * rtol * norm_a
+    zmax = None
+    for _ in range(max_iter + 1):
+        r = residual(A, x, b)
+        nr = norm2(r[0])
+        nx = norm2(x[0])
+        hist.append(nr)
+        xmax = float(np.abs(x[0]).max())
+        if nr < thresh_c * nx + atol or (zmax is not None and zmax <= ctol * xmax):
+            status = CONVERGED
+            break
+        if iters == max_iter:
+            break
+        e = math.frexp(float(np.abs(r[0]).max()))[1] - 1
+        rf = round_words(K, np.ldexp(r, -e))
+        z = np.ldexp(extend(getrs(K, LU, ipiv, rf)), e)
+        zmax = float(np.abs(z[0]).max())
+        x = add(4, x, z)
+        iters += 1
+    return dict(x=x, iters=iters, status=status, info=info, history=hist, LU=LU, ipiv=ipiv)

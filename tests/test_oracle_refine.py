@@ -1,0 +1,126 @@
+"""Pins for the oracle's exact residual and its iterative-refinement loop
+(Kouya 2021, Sec. 2, Listing 1; stopping rule eq. (2) of Sec. 3).
+
+The residual is checked bit for bit against Fraction arithmetic rounded
+greedily to quad-double.  The refinement is checked against systems whose
+exact solution is known (b = A * ones formed exactly), against the
+listing's step order (max_iter = 0, 1), and against its failure cases.
+"""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from oracle import exact as X
+
+
+def rand_qd_vec(g, n, scale=1.0):
+    out = np.zeros((4, n))
+    for i in range(n):
+        q = Fraction(0)
+        for w in range(6):
+            q += Fraction(float(g.uniform(-1, 1))) * Fraction(2) ** (-53 * w)
+        out[:, i] = X.canon(q * Fraction(scale), 4)
+    return out
+
+
+@pytest.mark.parametrize("aw", [1, 4])
+def test_residual_bitexact_vs_fraction(aw):
+    g = np.random.default_rng(7 + aw)
+    for n in (1, 3, 8):
+        A = np.zeros((aw, n, n))
+        for i in range(n):
+            for j in range(n):
+                q = sum((Fraction(float(g.uniform(-1, 1))) * Fraction(2) ** (-53 * w) for w in range(aw + 1)),
+                        Fraction(0))
+                A[:, j, i] = X.canon(q, aw)
+        x = rand_qd_vec(g, n)
+        b = rand_qd_vec(g, n, scale=2.0 ** int(g.integers(-3, 4)))
+        r = O.residual(A, x, b)
+        ex = X.residual([[A[:, j, i] for j in range(n)] for i in range(n)],
+                        [x[:, j] for j in range(n)], [b[:, i] for i in range(n)])
+        for i in range(n):
+            assert list(r[:, i]) == X.canon(ex[i], 4)
+
+
+def test_residual_zero_at_exact_solution():
+    Ap, b, exact = synth.problem("uniform", 40, config=0, instance=3)
+    assert exact
+    x = np.zeros((4, 40))
+    x[0] = 1.0
+    np.testing.assert_array_equal(O.residual(Ap, x, b), 0.0)
+
+
+def max_rel_err_vs_ones(x):
+    return max(float(abs(X.value(x[:, i]) - 1)) for i in range(x.shape[1]))
+
+
+@pytest.mark.parametrize("K", [1, 2, 3, 4])
+def test_refine_uniform_reaches_qd_accuracy(K):
+    n = 64
+    Ap, b, exact = synth.problem("uniform", n, config=0, instance=1)
+    assert exact
+    res = O.refine(Ap, b, K)
+    assert res["status"] == O.CONVERGED
+    assert max_rel_err_vs_ones(res["x"]) <= 1e-60
+    # each correction gains at least ~a factor kappa*u_K: more words, fewer steps
+    assert res["iters"] <= {1: 8, 2: 5, 3: 4, 4: 3}[K]
+
+
+@pytest.mark.parametrize("K,cond", [(2, 1e10), (3, 1e10), (2, 1e15), (3, 1e15)])
+def test_refine_randsvd_reaches_qd_accuracy(K, cond):
+    n = 64
+    Ap, b, exact = synth.problem("randsvd", n, config=2, instance=0, cond=cond)
+    assert exact
+    res = O.refine(Ap, b, K)
+    assert res["status"] == O.CONVERGED
+    assert max_rel_err_vs_ones(res["x"]) <= 1e-60
+    # residual norms decrease until x reaches its quad-double rounding
+    h = res["history"]
+    assert all(h[i + 1] < h[i] for i in range(len(h) - 2))
+
+
+def test_paper_residual_test_alone_stops_at_kappa_times_rtol():
+    """With only eq. (2) (rtol near the quad-double unit roundoff) the loop
+    stops once the backward error is small; the forward error is then
+    limited by kappa * rtol, which is why the forward test is added."""
+    n = 64
+    Ap, b, _ = synth.problem("randsvd", n, config=2, instance=0, cond=1e15)
+    res = O.refine(Ap, b, 2, rtol=2.0 ** -209, ctol=0.0)
+    assert res["status"] == O.CONVERGED
+    err = max_rel_err_vs_ones(res["x"])
+    assert err <= 1e15 * 2.0 ** -209 * np.sqrt(n) * 100
+
+
+def test_refine_step_order():
+    """max_iter = 0 returns the unrefined short-precision solution; one
+    correction equals solve + getrs(residual) + update done by hand."""
+    n = 32
+    K = 2
+    Ap, b, _ = synth.problem("uniform", n, config=0, instance=5)
+    r0 = O.refine(Ap, b, K, max_iter=0)
+    LU, ipiv, info = O.getrf(K, O.stage(K, Ap))
+    x0 = O.extend(O.getrs(K, LU, ipiv, O.round_words(K, b)))
+    np.testing.assert_array_equal(r0["x"], x0)
+    assert r0["iters"] == 0 and r0["status"] == O.MAX_ITER
+    r1 = O.refine(Ap, b, K, max_iter=1)
+    r = O.residual(Ap, x0, b)
+    e = np.frexp(np.abs(r[0]).max())[1] - 1
+    z = O.getrs(K, LU, ipiv, O.round_words(K, np.ldexp(r, -e)))
+    x1 = O.add(4, x0, np.ldexp(O.extend(z), e))
+    np.testing.assert_array_equal(r1["x"], x1)
+    assert r1["iters"] == 1
+
+
+def test_refine_failure_modes():
+    # rows 1 and 3 of an integer matrix are equal: elimination is exact and
+    # meets an exactly zero pivot
+    A = np.array([[2.0, 1, 0, 1], [1, 3, 1, 0], [0, 1, 4, 1], [1, 3, 1, 0]])
+    Ap = synth.planes(A)
+    b, _ = synth.rhs_ones(Ap)
+    assert O.refine(Ap, b, 3)["status"] == O.SINGULAR
+    Ap2 = Ap.copy()
+    Ap2[0, 2, 2] = np.nan
+    assert O.refine(Ap2, b, 3)["status"] == O.NONFINITE
