@@ -1,0 +1,191 @@
+/*
+ * bnc.h -- multi-word dense linear solves on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: T. Kouya, "Accelerated Multiple Precision Direct Method and Mixed
+ * Precision Iterative Refinement on Python Programming Environment" (2021):
+ * LU decomposition with partial pivoting and forward/backward substitution
+ * in double-double (DD, 2 words), triple-double (TD, 3 words) and
+ * quad-double (QD, 4 words) arithmetic (Sec. 1-2, Table 1), driven by the
+ * mixed-precision iterative refinement of Sec. 2, Listing 1 (stopping rule
+ * eq. (2) of Sec. 3).
+ *
+ * Conventions shared by every entry point
+ *  - Storage ("K-plane"): a K-word number is an unevaluated sum of K binary64
+ *    words, leading word first.  A K-word n x n matrix is K planes of
+ *    binary64; plane w holds word w of every entry, column-major with leading
+ *    dimension lda >= n; consecutive planes are ldp >= lda*n doubles apart.
+ *    Word w of entry (i, j) is at A[w*ldp + j*lda + i].  A K-word vector of
+ *    length n is K planes ldv >= n doubles apart.
+ *  - Pointers are DEVICE pointers unless marked (host).  The caller owns
+ *    every buffer; no call frees caller memory.
+ *  - stream: a hipStream_t passed as void* (NULL = the null stream).  Calls
+ *    are asynchronous on that stream unless marked synchronous.
+ *  - Return value: BNC_OK, -i when argument i (1-based) is invalid (nothing
+ *    is launched), or a BNC_ERR_* code; bnc_last_error() describes the last
+ *    failure.
+ *  - ipiv: int64, 0-based, LAPACK swap-sequence semantics (row k was
+ *    interchanged with row ipiv[k] >= k, in order k = 0..n-1).
+ *  - Pivot choice: the first row (smallest index) whose entry has the
+ *    largest magnitude, magnitudes compared word by word after multiplying
+ *    each word by the sign of the leading word.
+ *  - Results are reproducible bit for bit: every operation order is fixed.
+ *  - Limits: n <= 16384 for the factorisation; nothing here is thread-safe
+ *    across concurrent calls that share the library scratch on one device.
+ */
+#ifndef BNC_H
+#define BNC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BNC_OK 0
+#define BNC_ERR_HIP (-100)         /* a HIP runtime or launch call failed */
+#define BNC_ERR_UNSUPPORTED (-101) /* size beyond the documented limits */
+#define BNC_ERR_WORKSPACE (-102)   /* workspace smaller than required */
+
+/* Refinement outcome (bnc_refine_result.status). */
+#define BNC_CONVERGED 0 /* a stopping test passed */
+#define BNC_MAX_ITER 1  /* max_iter corrections applied, no test passed */
+#define BNC_SINGULAR 2  /* exactly zero pivot met: no solve was attempted */
+#define BNC_NONFINITE 3 /* NaN or Inf in A or b: nothing was factorised */
+
+/*
+ * LU decomposition with partial pivoting, in place: P A = L U (Kouya 2021,
+ * Sec. 2: the K-word direct method; Listing 1 calls it on the short-precision
+ * copy of A).  _d: 1 word (binary64), _dd: 2, _td: 3, _qd: 4.
+ *   n     order of A (>= 0)
+ *   A     K-plane matrix, overwritten by L (unit lower, strictly below the
+ *         diagonal) and U (upper)
+ *   lda   leading dimension (>= max(1, n));  ldp  plane stride (>= lda*n)
+ *   ipiv  n int64 (device), pivot sequence as above
+ *   info  one int64 (device): 0, or k+1 for the first exactly zero pivot
+ *         U(k,k); the factorisation still completes (LAPACK getrf)
+ * Uses library scratch on the current device (allocated on first use).
+ */
+int bnc_getrf_d(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int64_t *info, void *stream);
+int bnc_getrf_dd(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int64_t *info, void *stream);
+int bnc_getrf_td(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int64_t *info, void *stream);
+int bnc_getrf_qd(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int64_t *info, void *stream);
+
+/*
+ * Solve A X = B with the factors of bnc_getrf_* (Kouya 2021, Sec. 2:
+ * forward and backward substitution; Listing 1 calls it for the first
+ * solution and for every correction).  Rows of B are permuted by ipiv, then
+ * L y = P b (unit lower, each y_i updated in increasing k), then U x = y
+ * (x_k = y_k * (1/u_kk), each y_i updated in decreasing k).
+ *   n, nrhs  order and number of right-hand sides (>= 0)
+ *   LU, lda, ldp, ipiv   as returned by bnc_getrf_* with the same K
+ *   B     K-plane n x nrhs matrix (leading dimension ldb, plane stride ldpb),
+ *         overwritten by X
+ * A zero pivot yields Inf/NaN in X; check info first.
+ */
+int bnc_getrs_d(int64_t n, int64_t nrhs, const double *LU, int64_t lda, int64_t ldp, const int64_t *ipiv,
+                double *B, int64_t ldb, int64_t ldpb, void *stream);
+int bnc_getrs_dd(int64_t n, int64_t nrhs, const double *LU, int64_t lda, int64_t ldp, const int64_t *ipiv,
+                 double *B, int64_t ldb, int64_t ldpb, void *stream);
+int bnc_getrs_td(int64_t n, int64_t nrhs, const double *LU, int64_t lda, int64_t ldp, const int64_t *ipiv,
+                 double *B, int64_t ldb, int64_t ldpb, void *stream);
+int bnc_getrs_qd(int64_t n, int64_t nrhs, const double *LU, int64_t lda, int64_t ldp, const int64_t *ipiv,
+                 double *B, int64_t ldb, int64_t ldpb, void *stream);
+
+/* Options of the refinement loop (host struct). */
+typedef struct bnc_refine_opts {
+    int32_t factor_words; /* K of the factorisation: 1, 2, 3 or 4 */
+    int32_t max_iter;     /* maximum number of corrections (>= 0) */
+    double rtol;          /* residual test of Listing 1 / eq. (2): stop when
+                             ||r||_2 < sqrt(n) rtol ||A||_F ||x||_2 + atol */
+    double atol;
+    double ctol;          /* forward test: stop when the last correction had
+                             ||z||_inf <= ctol ||x||_inf (0 disables) */
+} bnc_refine_opts;
+
+/* Outcome of the refinement loop (host struct, filled synchronously). */
+typedef struct bnc_refine_result {
+    int32_t status;            /* BNC_CONVERGED ... BNC_NONFINITE */
+    int32_t iters;             /* corrections applied */
+    int64_t info;              /* getrf info */
+    double resid_norm;         /* ||r||_2 of the last residual (leading words) */
+    double x_norm;             /* ||x||_2 (leading words) */
+    double a_norm;             /* ||A||_F (leading words) */
+    int32_t residual_inexact;  /* 1 if any residual row lost bits below its
+                                  exact accumulator (never for sane inputs) */
+    int32_t reserved;
+} bnc_refine_result;
+
+/* Workspace bytes bnc_refine needs for order n and K = factor_words (host). */
+size_t bnc_refine_workspace_size(int64_t n, int32_t factor_words);
+
+/*
+ * Mixed-precision iterative refinement (Kouya 2021, Sec. 2, Listing 1):
+ * short-precision (K-word) copies of A and b, LU + substitution, x to the
+ * long precision; then repeat: r = b - A x, the stopping tests, r scaled by a
+ * power of two 2^-e (the listing's normalisation), K-word copy of r,
+ * substitution -> z, x <- x + 2^e z.  The long precision is quad-double: the
+ * residual is accumulated exactly from error-free products and rounded once
+ * to canonical quad-double; x is quad-double.
+ *   n        order (>= 1)
+ *   a_words  words per entry of A: 1 (binary64) or 4 (quad-double)
+ *   A, lda, ldpa  a_words-plane matrix (not modified)
+ *   b, ldpb  4-plane right-hand side (not modified)
+ *   x, ldpx  4-plane solution (output)
+ *   work, work_bytes  caller workspace, >= bnc_refine_workspace_size(n, K)
+ *   opts     host options; result  host outcome
+ * Synchronous: returns after the loop has finished (it reads the stopping
+ * quantities back each iteration).
+ */
+int bnc_refine(int64_t n, int32_t a_words, const double *A, int64_t lda, int64_t ldpa, const double *b,
+               int64_t ldpb, double *x, int64_t ldpx, void *work, size_t work_bytes, const bnc_refine_opts *opts,
+               bnc_refine_result *result, void *stream);
+
+/*
+ * r = b - A x computed exactly and rounded once to canonical quad-double
+ * (w0 = nearest binary64 to the value, w1 nearest to the remainder, ...):
+ * the residual step of Listing 1 in the long precision.  A has a_words
+ * planes (1 or 4); x, b, r are 4-plane vectors.  *inexact (device int32)
+ * is set to 1 if a row had bits below its 476-bit accumulator window
+ * (then the row is faithful, not exactly rounded); it is not cleared.
+ * Uses library scratch.
+ */
+int bnc_residual(int64_t n, int32_t a_words, const double *A, int64_t lda, int64_t ldpa, const double *x,
+                 int64_t ldpx, const double *b, int64_t ldpb, double *r, int64_t ldpr, int32_t *inexact,
+                 void *stream);
+
+/*
+ * Element-wise K-word primitive on word-major arrays (word w of element i at
+ * p[w*n + i]); exposes the device arithmetic every routine above is built
+ * from.  op: 0 out = c - a*b, 1 out = a*b, 2 out = a+b, 3 out = 1/a,
+ * 4 out = a rounded from m = K_in words (c unused, a has 4 planes; result
+ * K words).  K in 1..4.
+ */
+#define BNC_OP_FMS 0
+#define BNC_OP_MUL 1
+#define BNC_OP_ADD 2
+#define BNC_OP_RECIP 3
+#define BNC_OP_ROUND4 4
+int bnc_mw_apply(int32_t op, int32_t K, int64_t n, const double *c, const double *a, const double *b, double *out,
+                 void *stream);
+
+/*
+ * Timing of the trailing-update launches inside bnc_getrf_* and bnc_refine:
+ * with profiling on, every trailing-update launch is bracketed by hipEvents
+ * on its stream.  bnc_profile_read synchronises on the recorded events and
+ * returns the summed milliseconds, the summed algorithmic FP64 operations
+ * (m * n * k multiply-subtracts times the per-operation count) and the number
+ * of launches since the last read, then clears them (host pointers).
+ */
+int bnc_profile_enable(int32_t on);
+int bnc_profile_read(double *ms, double *flops, int64_t *launches);
+
+const char *bnc_status_string(int32_t status);
+const char *bnc_last_error(void);
+const char *bnc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BNC_H */

@@ -1,0 +1,30 @@
+"""Multi-word (double-double / triple-double / quad-double) LU with partial
+pivoting, substitutions and mixed-precision iterative refinement on one AMD
+Instinct MI355X, after Kouya 2021 (arXiv 2107.12550), Sec. 2 and Listing 1.
+
+Every step runs in the HIP kernels of ``libbnc.so`` behind the C-ABI of
+``include/bnc.h``; this package only marshals arguments.  PyTorch provides
+device memory and the current stream.
+"""
+from .bnc import (  # noqa: F401
+    BNC_CONVERGED,
+    BNC_MAX_ITER,
+    BNC_NONFINITE,
+    BNC_SINGULAR,
+    OP_ADD,
+    OP_FMS,
+    OP_MUL,
+    OP_RECIP,
+    OP_ROUND4,
+    BncError,
+    getrf,
+    getrs,
+    lib,
+    lib_path,
+    mw_apply,
+    profile_enable,
+    profile_read,
+    refine,
+    refine_workspace_size,
+    residual,
+)

@@ -1,0 +1,168 @@
+"""ctypes binding of libbnc.so (declarations in include/bnc.h).
+
+Argument marshalling only: tensors must already live on the GPU in the
+K-plane layout, a float64 tensor of shape (K, n, n) whose element [w, j, i]
+is word w of matrix entry (i, j) (planes column-major), or (K, n) for
+vectors.  Calls run on torch's current HIP stream.  There is no CPU path: if
+the library cannot be loaded the import of this module fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+lib_path = os.path.join(_HERE, "libbnc.so")
+
+BNC_CONVERGED, BNC_MAX_ITER, BNC_SINGULAR, BNC_NONFINITE = 0, 1, 2, 3
+OP_FMS, OP_MUL, OP_ADD, OP_RECIP, OP_ROUND4 = 0, 1, 2, 3, 4
+_SUFFIX = {1: "d", 2: "dd", 3: "td", 4: "qd"}
+
+
+class BncError(RuntimeError):
+    pass
+
+
+class RefineOpts(ctypes.Structure):
+    _fields_ = [("factor_words", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("rtol", ctypes.c_double),
+                ("atol", ctypes.c_double), ("ctol", ctypes.c_double)]
+
+
+class RefineResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("info", ctypes.c_int64),
+                ("resid_norm", ctypes.c_double), ("x_norm", ctypes.c_double), ("a_norm", ctypes.c_double),
+                ("residual_inexact", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(lib_path):
+        from . import build as _b
+        _b.build()
+    L = ctypes.CDLL(lib_path)
+    I64, VP, D, I32 = ctypes.c_int64, ctypes.c_void_p, ctypes.c_double, ctypes.c_int32
+    for s in _SUFFIX.values():
+        f = getattr(L, f"bnc_getrf_{s}")
+        f.argtypes = [I64, VP, I64, I64, VP, VP, VP]
+        f.restype = ctypes.c_int
+        g = getattr(L, f"bnc_getrs_{s}")
+        g.argtypes = [I64, I64, VP, I64, I64, VP, VP, I64, I64, VP]
+        g.restype = ctypes.c_int
+    L.bnc_refine_workspace_size.argtypes = [I64, I32]
+    L.bnc_refine_workspace_size.restype = ctypes.c_size_t
+    L.bnc_refine.argtypes = [I64, I32, VP, I64, I64, VP, I64, VP, I64, VP, ctypes.c_size_t,
+                             ctypes.POINTER(RefineOpts), ctypes.POINTER(RefineResult), VP]
+    L.bnc_refine.restype = ctypes.c_int
+    L.bnc_residual.argtypes = [I64, I32, VP, I64, I64, VP, I64, VP, I64, VP, I64, VP, VP]
+    L.bnc_residual.restype = ctypes.c_int
+    L.bnc_mw_apply.argtypes = [I32, I32, I64, VP, VP, VP, VP, VP]
+    L.bnc_mw_apply.restype = ctypes.c_int
+    L.bnc_profile_enable.argtypes = [I32]
+    L.bnc_profile_read.argtypes = [ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(I64)]
+    for name in ("bnc_status_string", "bnc_last_error", "bnc_version"):
+        getattr(L, name).restype = ctypes.c_char_p
+    L.bnc_status_string.argtypes = [I32]
+    return L
+
+
+_lib = _load()
+
+
+def lib() -> ctypes.CDLL:
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise BncError(f"{what}: code {rc}: {_lib.bnc_last_error().decode()}")
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t: torch.Tensor, name: str, ndim: int):
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and t.dim() == ndim):
+        raise BncError(f"{name}: expected a contiguous float64 CUDA tensor with {ndim} dims")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def getrf(K: int, A: torch.Tensor):
+    """In-place P A = L U of a (K, n, n) tensor; returns (ipiv, info) tensors."""
+    n = A.shape[1]
+    ipiv = torch.empty(max(n, 1), dtype=torch.int64, device=A.device)
+    info = torch.empty(1, dtype=torch.int64, device=A.device)
+    f = getattr(_lib, f"bnc_getrf_{_SUFFIX[K]}")
+    _check(f(n, _dev(A, "A", 3), n, n * n, ctypes.c_void_p(ipiv.data_ptr()), ctypes.c_void_p(info.data_ptr()),
+             _stream()), "getrf")
+    return ipiv[:n], info
+
+
+def getrs(K: int, LU: torch.Tensor, ipiv: torch.Tensor, B: torch.Tensor) -> torch.Tensor:
+    """Solve in place; B is (K, n) or (K, nrhs, n)."""
+    n = LU.shape[1]
+    nrhs = 1 if B.dim() == 2 else B.shape[1]
+    f = getattr(_lib, f"bnc_getrs_{_SUFFIX[K]}")
+    if not (B.is_cuda and B.dtype == torch.float64 and B.is_contiguous()):
+        raise BncError("B: expected a contiguous float64 CUDA tensor")
+    _check(f(n, nrhs, _dev(LU, "LU", 3), n, n * n, ctypes.c_void_p(ipiv.data_ptr()), ctypes.c_void_p(B.data_ptr()),
+             n, n * nrhs, _stream()), "getrs")
+    return B
+
+
+def refine_workspace_size(n: int, K: int) -> int:
+    return int(_lib.bnc_refine_workspace_size(n, K))
+
+
+def refine(A: torch.Tensor, b: torch.Tensor, K: int, max_iter: int = 30, rtol: float = 0.0, atol: float = 0.0,
+           ctol: float = 2.0 ** -208, x: torch.Tensor | None = None, work: torch.Tensor | None = None) -> dict:
+    """Listing 1 of the paper with a K-word factorisation and a quad-double
+    long precision.  A: (aw, n, n) with aw = 1 or 4; b: (4, n).  Returns a
+    dict with x (4, n) and the outcome fields."""
+    aw, n = A.shape[0], A.shape[1]
+    if x is None:
+        x = torch.empty((4, n), dtype=torch.float64, device=A.device)
+    need = refine_workspace_size(n, K)
+    if work is None or work.numel() < need:
+        work = torch.empty(need, dtype=torch.uint8, device=A.device)
+    o = RefineOpts(K, max_iter, rtol, atol, ctol)
+    r = RefineResult()
+    _check(_lib.bnc_refine(n, aw, _dev(A, "A", 3), n, n * n, _dev(b, "b", 2), n, _dev(x, "x", 2), n,
+                           ctypes.c_void_p(work.data_ptr()), work.numel(), ctypes.byref(o), ctypes.byref(r),
+                           _stream()), "refine")
+    return dict(x=x, status=r.status, iters=r.iters, info=r.info, resid_norm=r.resid_norm, x_norm=r.x_norm,
+                a_norm=r.a_norm, residual_inexact=bool(r.residual_inexact))
+
+
+def residual(A: torch.Tensor, x: torch.Tensor, b: torch.Tensor):
+    """r = b - A x exactly, rounded to canonical quad-double; returns (r, inexact)."""
+    aw, n = A.shape[0], A.shape[1]
+    r = torch.empty((4, n), dtype=torch.float64, device=A.device)
+    flag = torch.zeros(1, dtype=torch.int32, device=A.device)
+    _check(_lib.bnc_residual(n, aw, _dev(A, "A", 3), n, n * n, _dev(x, "x", 2), n, _dev(b, "b", 2), n,
+                             ctypes.c_void_p(r.data_ptr()), n, ctypes.c_void_p(flag.data_ptr()), _stream()),
+           "residual")
+    return r, flag
+
+
+def mw_apply(op: int, K: int, a: torch.Tensor, b: torch.Tensor | None = None,
+             c: torch.Tensor | None = None) -> torch.Tensor:
+    """Element-wise K-word primitive on (K, n) tensors (a: (4, n) for OP_ROUND4)."""
+    n = a.shape[1]
+    out = torch.empty((K, n), dtype=torch.float64, device=a.device)
+
+    def p(t):
+        return None if t is None else ctypes.c_void_p(t.data_ptr())
+    _check(_lib.bnc_mw_apply(op, K, n, p(c), p(a), p(b), p(out), _stream()), "mw_apply")
+    return out
+
+
+def profile_enable(on: bool = True):
+    _lib.bnc_profile_enable(1 if on else 0)
+
+
+def profile_read():
+    ms, fl, nl = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+    _check(_lib.bnc_profile_read(ctypes.byref(ms), ctypes.byref(fl), ctypes.byref(nl)), "profile_read")
+    return ms.value, fl.value, nl.value

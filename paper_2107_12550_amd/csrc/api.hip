@@ -1,0 +1,445 @@
+// C-ABI of the solver library (declarations and contracts in include/bnc.h):
+// argument checks, library scratch, launch-timing hooks and the element-wise
+// primitive kernels.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "mw.hpp"
+
+namespace bnc {
+
+template <int K>
+int getrf_run(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int64_t *info, void *scr,
+              hipStream_t s);
+template <int K>
+int getrs_run(int64_t n, int64_t nrhs, const double *LU, int64_t lda, int64_t ldp, const int64_t *ipiv, double *B,
+              int64_t ldb, int64_t ldpb, void *scr, hipStream_t s);
+template <int K>
+int refine_run(int64_t n, int aw, const double *A, int64_t lda, int64_t ldpa, const double *b, int64_t ldpb, double *x,
+               int64_t ldpx, void *work, const bnc_refine_opts *o, bnc_refine_result *res, hipStream_t s);
+size_t getrs_scratch_bytes(int K, int64_t n);
+size_t refine_workspace_bytes(int64_t n, int K);
+size_t residual_scratch_bytes(int64_t n);
+int residual_run(int64_t n, int aw, const double *A, int64_t lda, int64_t ldpa, const double *x, int64_t ldx,
+                 const double *b, int64_t ldb, const double *rowmax, const double *xmax, const void *ebounds,
+                 double *part, double *r, int64_t ldr, int32_t *inexact, hipStream_t s);
+int minexp_run(int64_t rows, int64_t cols, int64_t ld, int words, int64_t ldp, const double *v, int *out,
+               hipStream_t s);
+int fill_i32_run(int *p, int64_t n, int v, hipStream_t s);
+int rowmax_run(int64_t n, const double *A, int64_t lda, double *rowmax, hipStream_t s);
+int absmax_run(int64_t rows, int64_t cols, int64_t ld, const double *v, unsigned long long *bits, hipStream_t s);
+
+// ---- errors -------------------------------------------------------------------
+static thread_local std::string g_last_error;
+
+int fail_hip(hipError_t e, const char *what, const char *file, int line)
+{
+    char buf[512];
+    snprintf(buf, sizeof buf, "%s failed: %s (%s:%d)", what, hipGetErrorString(e), file, line);
+    g_last_error = buf;
+    return BNC_ERR_HIP;
+}
+
+int fail_arg(int code, const char *msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+// ---- library scratch ------------------------------------------------------------
+namespace {
+constexpr int MAX_DEV = 16;
+struct Buf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+Buf g_scratch[MAX_DEV][SCR_NSLOTS];
+std::mutex g_scratch_mu;
+}  // namespace
+
+void *scratch(int slot, size_t bytes)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEV)
+        return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    Buf &b = g_scratch[dev][slot];
+    if (b.bytes < bytes) {
+        if (b.p) {
+            if (hipDeviceSynchronize() != hipSuccess || hipFree(b.p) != hipSuccess)
+                return nullptr;
+        }
+        b.p = nullptr;
+        b.bytes = 0;
+        const size_t want = bytes < (1u << 20) ? (1u << 20) : bytes;
+        if (hipMalloc(&b.p, want) != hipSuccess)
+            return nullptr;
+        b.bytes = want;
+    }
+    return b.p;
+}
+
+// ---- trailing-update timing ------------------------------------------------------
+namespace {
+struct Ev {
+    hipEvent_t a, b;
+    double flops;
+};
+bool g_prof = false;
+std::vector<Ev> g_events;
+std::mutex g_prof_mu;
+}  // namespace
+
+bool UpdateTimer::enabled() { return g_prof; }
+
+int UpdateTimer::begin(hipStream_t s)
+{
+    if (!g_prof)
+        return -1;
+    Ev e{};
+    if (hipEventCreate(&e.a) != hipSuccess || hipEventCreate(&e.b) != hipSuccess)
+        return -1;
+    hipEventRecord(e.a, s);
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_events.push_back(e);
+    return (int)g_events.size() - 1;
+}
+
+void UpdateTimer::end(int idx, hipStream_t s, double flops)
+{
+    if (idx < 0)
+        return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_events[idx].flops = flops;
+    hipEventRecord(g_events[idx].b, s);
+}
+
+// ---- element-wise primitives -------------------------------------------------------
+template <int K>
+__global__ void k_apply(int op, int64_t n, const double *__restrict__ c, const double *__restrict__ a,
+                        const double *__restrict__ b, double *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    double av[K], bv[K], cv[K], o[K];
+    if (op == BNC_OP_ROUND4) {
+        double v[4];
+#pragma unroll
+        for (int w = 0; w < 4; ++w)
+            v[w] = a[w * n + i];
+        renorm<K, 4>(v, o);
+    } else {
+        load_w<K>(a, n, i, av);
+        if (op != BNC_OP_RECIP)
+            load_w<K>(b, n, i, bv);
+        if (op == BNC_OP_FMS) {
+            load_w<K>(c, n, i, cv);
+            fms<K>(cv, av, bv, o);
+        } else if (op == BNC_OP_MUL) {
+            mul<K>(av, bv, o);
+        } else if (op == BNC_OP_ADD) {
+            add<K>(av, bv, o);
+        } else {
+            recip<K>(av, o);
+        }
+    }
+    store_w<K>(out, n, i, o);
+}
+
+}  // namespace bnc
+
+using namespace bnc;
+
+static hipStream_t S(void *s) { return (hipStream_t)s; }
+
+template <int K>
+static int getrf_entry(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int64_t *info, void *stream)
+{
+    if (n < 0)
+        return fail_arg(-1, "getrf: n < 0");
+    if (n > 0 && !A)
+        return fail_arg(-2, "getrf: A is NULL");
+    if (lda < (n > 1 ? n : 1))
+        return fail_arg(-3, "getrf: lda < max(1, n)");
+    if (K > 1 && ldp < lda * n)
+        return fail_arg(-4, "getrf: ldp < lda * n");
+    if (n > 0 && !ipiv)
+        return fail_arg(-5, "getrf: ipiv is NULL");
+    if (!info)
+        return fail_arg(-6, "getrf: info is NULL");
+    if (n > 16384)
+        return fail_arg(BNC_ERR_UNSUPPORTED, "getrf: n > 16384");
+    void *scr = scratch(SCR_GETRF, getrf_scratch_bytes(K));
+    if (!scr)
+        return fail_arg(BNC_ERR_HIP, "getrf: scratch allocation failed");
+    return getrf_run<K>(n, A, lda, ldp, ipiv, info, scr, S(stream));
+}
+
+template <int K>
+static int getrs_entry(int64_t n, int64_t nrhs, const double *LU, int64_t lda, int64_t ldp, const int64_t *ipiv,
+                       double *B, int64_t ldb, int64_t ldpb, void *stream)
+{
+    if (n < 0)
+        return fail_arg(-1, "getrs: n < 0");
+    if (nrhs < 0)
+        return fail_arg(-2, "getrs: nrhs < 0");
+    if (n > 0 && !LU)
+        return fail_arg(-3, "getrs: LU is NULL");
+    if (lda < (n > 1 ? n : 1))
+        return fail_arg(-4, "getrs: lda < max(1, n)");
+    if (K > 1 && ldp < lda * n)
+        return fail_arg(-5, "getrs: ldp < lda * n");
+    if (n > 0 && !ipiv)
+        return fail_arg(-6, "getrs: ipiv is NULL");
+    if (n > 0 && nrhs > 0 && !B)
+        return fail_arg(-7, "getrs: B is NULL");
+    if (ldb < (n > 1 ? n : 1))
+        return fail_arg(-8, "getrs: ldb < max(1, n)");
+    if (K > 1 && ldpb < ldb * nrhs)
+        return fail_arg(-9, "getrs: ldpb < ldb * nrhs");
+    if (n > 16384)
+        return fail_arg(BNC_ERR_UNSUPPORTED, "getrs: n > 16384");
+    void *scr = scratch(SCR_GETRS, getrs_scratch_bytes(K, n));
+    if (!scr)
+        return fail_arg(BNC_ERR_HIP, "getrs: scratch allocation failed");
+    return getrs_run<K>(n, nrhs, LU, lda, ldp, ipiv, B, ldb, ldpb, scr, S(stream));
+}
+
+extern "C" {
+
+int bnc_getrf_d(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int64_t *info, void *stream)
+{
+    return getrf_entry<1>(n, A, lda, ldp, ipiv, info, stream);
+}
+int bnc_getrf_dd(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int64_t *info, void *stream)
+{
+    return getrf_entry<2>(n, A, lda, ldp, ipiv, info, stream);
+}
+int bnc_getrf_td(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int64_t *info, void *stream)
+{
+    return getrf_entry<3>(n, A, lda, ldp, ipiv, info, stream);
+}
+int bnc_getrf_qd(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int64_t *info, void *stream)
+{
+    return getrf_entry<4>(n, A, lda, ldp, ipiv, info, stream);
+}
+
+int bnc_getrs_d(int64_t n, int64_t nrhs, const double *LU, int64_t lda, int64_t ldp, const int64_t *ipiv, double *B,
+                int64_t ldb, int64_t ldpb, void *stream)
+{
+    return getrs_entry<1>(n, nrhs, LU, lda, ldp, ipiv, B, ldb, ldpb, stream);
+}
+int bnc_getrs_dd(int64_t n, int64_t nrhs, const double *LU, int64_t lda, int64_t ldp, const int64_t *ipiv,
+                 double *B, int64_t ldb, int64_t ldpb, void *stream)
+{
+    return getrs_entry<2>(n, nrhs, LU, lda, ldp, ipiv, B, ldb, ldpb, stream);
+}
+int bnc_getrs_td(int64_t n, int64_t nrhs, const double *LU, int64_t lda, int64_t ldp, const int64_t *ipiv,
+                 double *B, int64_t ldb, int64_t ldpb, void *stream)
+{
+    return getrs_entry<3>(n, nrhs, LU, lda, ldp, ipiv, B, ldb, ldpb, stream);
+}
+int bnc_getrs_qd(int64_t n, int64_t nrhs, const double *LU, int64_t lda, int64_t ldp, const int64_t *ipiv,
+                 double *B, int64_t ldb, int64_t ldpb, void *stream)
+{
+    return getrs_entry<4>(n, nrhs, LU, lda, ldp, ipiv, B, ldb, ldpb, stream);
+}
+
+size_t bnc_refine_workspace_size(int64_t n, int32_t factor_words)
+{
+    if (n < 1 || factor_words < 1 || factor_words > 4)
+        return 0;
+    return refine_workspace_bytes(n, factor_words);
+}
+
+int bnc_refine(int64_t n, int32_t a_words, const double *A, int64_t lda, int64_t ldpa, const double *b, int64_t ldpb,
+               double *x, int64_t ldpx, void *work, size_t work_bytes, const bnc_refine_opts *opts,
+               bnc_refine_result *result, void *stream)
+{
+    if (n < 1)
+        return fail_arg(-1, "refine: n < 1");
+    if (a_words != 1 && a_words != 4)
+        return fail_arg(-2, "refine: a_words must be 1 or 4");
+    if (!A)
+        return fail_arg(-3, "refine: A is NULL");
+    if (lda < n)
+        return fail_arg(-4, "refine: lda < n");
+    if (a_words > 1 && ldpa < lda * n)
+        return fail_arg(-5, "refine: ldpa < lda * n");
+    if (!b)
+        return fail_arg(-6, "refine: b is NULL");
+    if (ldpb < n)
+        return fail_arg(-7, "refine: ldpb < n");
+    if (!x)
+        return fail_arg(-8, "refine: x is NULL");
+    if (ldpx < n)
+        return fail_arg(-9, "refine: ldpx < n");
+    if (!work)
+        return fail_arg(-10, "refine: work is NULL");
+    if (!opts)
+        return fail_arg(-12, "refine: opts is NULL");
+    if (opts->factor_words < 1 || opts->factor_words > 4 || opts->max_iter < 0 || !(opts->rtol >= 0) ||
+        !(opts->atol >= 0) || !(opts->ctol >= 0))
+        return fail_arg(-12, "refine: invalid options");
+    if (!result)
+        return fail_arg(-13, "refine: result is NULL");
+    if (n > 16384)
+        return fail_arg(BNC_ERR_UNSUPPORTED, "refine: n > 16384");
+    if (work_bytes < refine_workspace_bytes(n, opts->factor_words))
+        return fail_arg(-11, "refine: workspace too small");
+    switch (opts->factor_words) {
+    case 1:
+        return refine_run<1>(n, a_words, A, lda, ldpa, b, ldpb, x, ldpx, work, opts, result, S(stream));
+    case 2:
+        return refine_run<2>(n, a_words, A, lda, ldpa, b, ldpb, x, ldpx, work, opts, result, S(stream));
+    case 3:
+        return refine_run<3>(n, a_words, A, lda, ldpa, b, ldpb, x, ldpx, work, opts, result, S(stream));
+    default:
+        return refine_run<4>(n, a_words, A, lda, ldpa, b, ldpb, x, ldpx, work, opts, result, S(stream));
+    }
+}
+
+int bnc_residual(int64_t n, int32_t a_words, const double *A, int64_t lda, int64_t ldpa, const double *x,
+                 int64_t ldpx, const double *b, int64_t ldpb, double *r, int64_t ldpr, int32_t *inexact,
+                 void *stream)
+{
+    if (n < 0)
+        return fail_arg(-1, "residual: n < 0");
+    if (a_words != 1 && a_words != 4)
+        return fail_arg(-2, "residual: a_words must be 1 or 4");
+    if (n == 0)
+        return BNC_OK;
+    if (!A)
+        return fail_arg(-3, "residual: A is NULL");
+    if (lda < n)
+        return fail_arg(-4, "residual: lda < n");
+    if (a_words > 1 && ldpa < lda * n)
+        return fail_arg(-5, "residual: ldpa < lda * n");
+    if (!x)
+        return fail_arg(-6, "residual: x is NULL");
+    if (ldpx < n)
+        return fail_arg(-7, "residual: ldpx < n");
+    if (!b)
+        return fail_arg(-8, "residual: b is NULL");
+    if (ldpb < n)
+        return fail_arg(-9, "residual: ldpb < n");
+    if (!r)
+        return fail_arg(-10, "residual: r is NULL");
+    if (ldpr < n)
+        return fail_arg(-11, "residual: ldpr < n");
+    if (!inexact)
+        return fail_arg(-12, "residual: inexact is NULL");
+    const size_t need = residual_scratch_bytes(n) + (size_t)n * sizeof(double) + 512;
+    char *scr = (char *)scratch(SCR_GETRS, need);
+    if (!scr)
+        return fail_arg(BNC_ERR_HIP, "residual: scratch allocation failed");
+    double *rowmax = (double *)scr;
+    unsigned long long *xmax = (unsigned long long *)(scr + ((n * sizeof(double) + 255) / 256) * 256);
+    int *eb = (int *)((char *)xmax + 64);  // exponent bounds a, x, b
+    double *part = (double *)((char *)xmax + 256);
+    hipStream_t s = S(stream);
+    int rc;
+    if ((rc = rowmax_run(n, A, lda, rowmax, s)) || (rc = absmax_run(n, 1, n, x, xmax, s)) ||
+        (rc = fill_i32_run(eb, 3, 2000, s)) || (rc = minexp_run(n, n, lda, a_words, ldpa, A, eb, s)) ||
+        (rc = minexp_run(n, 1, n, 4, ldpx, x, eb + 1, s)) || (rc = minexp_run(n, 1, n, 4, ldpb, b, eb + 2, s)))
+        return rc;
+    return residual_run(n, a_words, A, lda, ldpa, x, ldpx, b, ldpb, rowmax, (const double *)xmax, eb, part, r, ldpr,
+                        inexact, s);
+}
+
+int bnc_mw_apply(int32_t op, int32_t K, int64_t n, const double *c, const double *a, const double *b, double *out,
+                 void *stream)
+{
+    if (op < 0 || op > 4)
+        return fail_arg(-1, "mw_apply: unknown op");
+    if (K < 1 || K > 4)
+        return fail_arg(-2, "mw_apply: K must be 1..4");
+    if (n < 0)
+        return fail_arg(-3, "mw_apply: n < 0");
+    if (n == 0)
+        return BNC_OK;
+    if (op == BNC_OP_FMS && !c)
+        return fail_arg(-4, "mw_apply: c is NULL");
+    if (!a)
+        return fail_arg(-5, "mw_apply: a is NULL");
+    if ((op == BNC_OP_FMS || op == BNC_OP_MUL || op == BNC_OP_ADD) && !b)
+        return fail_arg(-6, "mw_apply: b is NULL");
+    if (!out)
+        return fail_arg(-7, "mw_apply: out is NULL");
+    const dim3 g((unsigned)ceil_div(n, 256)), t(256);
+    hipStream_t s = S(stream);
+    switch (K) {
+    case 1:
+        hipLaunchKernelGGL(k_apply<1>, g, t, 0, s, op, n, c, a, b, out);
+        break;
+    case 2:
+        hipLaunchKernelGGL(k_apply<2>, g, t, 0, s, op, n, c, a, b, out);
+        break;
+    case 3:
+        hipLaunchKernelGGL(k_apply<3>, g, t, 0, s, op, n, c, a, b, out);
+        break;
+    default:
+        hipLaunchKernelGGL(k_apply<4>, g, t, 0, s, op, n, c, a, b, out);
+        break;
+    }
+    BNC_LAUNCH_CHECK();
+    return BNC_OK;
+}
+
+int bnc_profile_enable(int32_t on)
+{
+    g_prof = on != 0;
+    return BNC_OK;
+}
+
+int bnc_profile_read(double *ms, double *flops, int64_t *launches)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    double tms = 0.0, tf = 0.0;
+    for (auto &e : g_events) {
+        float m = 0.f;
+        BNC_HIP(hipEventSynchronize(e.b));
+        BNC_HIP(hipEventElapsedTime(&m, e.a, e.b));
+        tms += m;
+        tf += e.flops;
+        hipEventDestroy(e.a);
+        hipEventDestroy(e.b);
+    }
+    if (launches)
+        *launches = (int64_t)g_events.size();
+    g_events.clear();
+    if (ms)
+        *ms = tms;
+    if (flops)
+        *flops = tf;
+    return BNC_OK;
+}
+
+const char *bnc_status_string(int32_t status)
+{
+    switch (status) {
+    case BNC_CONVERGED:
+        return "converged";
+    case BNC_MAX_ITER:
+        return "max_iter";
+    case BNC_SINGULAR:
+        return "singular";
+    case BNC_NONFINITE:
+        return "nonfinite";
+    default:
+        return "unknown";
+    }
+}
+
+const char *bnc_last_error(void) { return g_last_error.c_str(); }
+
+const char *bnc_version(void) { return "bnc 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,56 @@
+// Shared host-side plumbing for the solver library: error reporting,
+// per-device scratch, timing of the trailing-update launches.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/bnc.h"
+
+namespace bnc {
+
+// Record a HIP failure (readable through bnc_last_error) and return the code.
+int fail_hip(hipError_t e, const char *what, const char *file, int line);
+int fail_arg(int code, const char *msg);
+
+#define BNC_HIP(x)                                                   \
+    do {                                                             \
+        hipError_t e_ = (x);                                         \
+        if (e_ != hipSuccess)                                        \
+            return ::bnc::fail_hip(e_, #x, __FILE__, __LINE__);      \
+    } while (0)
+
+#define BNC_LAUNCH_CHECK() BNC_HIP(hipGetLastError())
+
+// Library-owned device scratch for the stand-alone factor/solve entry points
+// (the refinement driver carves everything from the caller's workspace).
+// One buffer per (device, slot); grown with hipMalloc when a call needs more.
+enum ScratchSlot { SCR_GETRF = 0, SCR_GETRS = 1, SCR_NSLOTS = 2 };
+void *scratch(int slot, size_t bytes);
+
+// Timing of trailing-update launches (hipEvents on the launch stream).
+struct UpdateTimer {
+    static bool enabled();
+    // returns an event pair index or -1
+    static int begin(hipStream_t s);
+    static void end(int idx, hipStream_t s, double flops);
+};
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// FP64 operations per K-word fused multiply-subtract c - a*b of the
+// level-accumulation algorithm (a fused multiply-add counts 2): TwoProd 3,
+// plain product 1, TwoSum 6, plain add 1, summed over the fixed term lists.
+constexpr double fms_flops(int K)
+{
+    return K == 1 ? 2.0 : (K == 2 ? 27.0 : (K == 3 ? 75.0 : 158.0));
+}
+
+// Sizes of the getrf scratch (candidate rows, old pivot-position rows,
+// per-panel row-permutation pairs).
+constexpr int PANEL_NB_MAX = 64;
+constexpr int PANEL_WG_MAX = 256;
+size_t getrf_scratch_bytes(int K);
+
+}  // namespace bnc

@@ -1,0 +1,588 @@
+// Blocked right-looking LU with partial pivoting in K-word arithmetic
+// (Kouya 2021, Sec. 2: LU decomposition with partial pivoting in DD/TD/QD).
+//
+// Per panel of nb columns starting at column j0:
+//   1. k_panel: one cooperative launch factors rows j0..n-1 of the panel.
+//      Each workgroup keeps R panel rows in LDS.  Per column: local argmax
+//      -> candidate row published to global memory -> one grid barrier ->
+//      every workgroup picks the same global pivot, swaps rows in LDS, scales
+//      the column by the pivot reciprocal and updates the rest of its rows.
+//      Workgroup 0 then turns the nb swaps into (dst, src) row pairs.
+//   2. k_laswp_trsm: the same row pairs applied to every column outside the
+//      panel; right of the panel it also solves U12 = L11^-1 A12 (one wave
+//      per column, lanes = panel rows, one broadcast per pivot row).
+//   3. k_update: A22 <- A22 - L21 U12, LDS tiles, one K-word multiply-subtract
+//      per (i, j, k) in increasing k.
+// Every matrix entry sees exactly the operations of the unblocked algorithm
+// in the same order (row moves commute with the updates, each entry is
+// updated in increasing k), so the factors equal the unblocked ones bit for
+// bit.
+#include <hip/hip_cooperative_groups.h>
+
+#include "common.hpp"
+#include "mw.hpp"
+
+namespace cg = cooperative_groups;
+
+namespace bnc {
+
+constexpr int PANEL_THREADS = 256;
+constexpr int UPD_THREADS = 256;
+
+// ---------------------------------------------------------------------------
+// panel
+// ---------------------------------------------------------------------------
+
+// candidate (key, row) reduction: keep b when its key is larger, or equal
+// with a smaller row; rows < 0 mark "no candidate".
+template <int K>
+__device__ __forceinline__ bool cand_better(const double (&kb)[K], int64_t rb, const double (&ka)[K], int64_t ra)
+{
+    if (rb < 0)
+        return false;
+    if (ra < 0)
+        return true;
+    if (key_gt<K>(kb, ka))
+        return true;
+    if (key_gt<K>(ka, kb))
+        return false;
+    return rb < ra;
+}
+
+// LDS tile layout: word w, panel column c, local row r at ((w*jb + c)*R + r)
+template <int K>
+__global__ void __launch_bounds__(PANEL_THREADS)
+    k_panel(double *__restrict__ A, int64_t lda, int64_t ldp, int64_t n, int64_t j0, int jb, int R,
+            int64_t *__restrict__ ipiv, int64_t *__restrict__ info, double *__restrict__ cand,
+            int64_t *__restrict__ cidx, double *__restrict__ rowk, int64_t *__restrict__ pairs)
+{
+    extern __shared__ double smem[];
+    double *tile = smem;                   // K*jb*R
+    double *prow = tile + (size_t)K * jb * R;  // K*jb   pivot row
+    __shared__ double rk[PANEL_THREADS][K];
+    __shared__ int64_t ri[PANEL_THREADS];
+    __shared__ int s_gw;
+
+    cg::grid_group grid = cg::this_grid();
+    const int P = gridDim.x;
+    const int g = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int64_t gr0 = j0 + (int64_t)g * R;
+    const int nr = (int)((n - gr0) < R ? (n - gr0) : R);
+
+    for (int e = tid; e < jb * R; e += PANEL_THREADS) {
+        const int r = e % R, c = e / R;
+#pragma unroll
+        for (int w = 0; w < K; ++w)
+            tile[(w * jb + c) * R + r] = r < nr ? A[w * ldp + (j0 + c) * lda + gr0 + r] : 0.0;
+    }
+    __syncthreads();
+
+    for (int kk = 0; kk < jb; ++kk) {
+        const int64_t k = j0 + kk;
+        const int buf = kk & 1;
+        // ---- local argmax of column kk over owned rows >= k
+        {
+            double v[K];
+            int64_t row = -1;
+            if (tid < nr && gr0 + tid >= k) {
+                row = gr0 + tid;
+#pragma unroll
+                for (int w = 0; w < K; ++w)
+                    v[w] = tile[(w * jb + kk) * R + tid];
+            } else {
+#pragma unroll
+                for (int w = 0; w < K; ++w)
+                    v[w] = 0.0;
+            }
+#pragma unroll
+            for (int w = 0; w < K; ++w)
+                rk[tid][w] = v[w];
+            ri[tid] = row;
+            __syncthreads();
+            for (int s = PANEL_THREADS / 2; s > 0; s >>= 1) {
+                if (tid < s) {
+                    double a[K], b[K];
+#pragma unroll
+                    for (int w = 0; w < K; ++w) {
+                        a[w] = rk[tid][w];
+                        b[w] = rk[tid + s][w];
+                    }
+                    if (cand_better<K>(b, ri[tid + s], a, ri[tid])) {
+#pragma unroll
+                        for (int w = 0; w < K; ++w)
+                            rk[tid][w] = b[w];
+                        ri[tid] = ri[tid + s];
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        const int64_t lrow = ri[0];
+        // ---- publish the candidate row, and the row now at position k
+        double *cb = cand + ((size_t)(buf * P + g) * K) * jb;
+        if (lrow >= 0) {
+            const int lr = (int)(lrow - gr0);
+            for (int e = tid; e < K * jb; e += PANEL_THREADS) {
+                const int w = e / jb, c = e % jb;
+                cb[w * jb + c] = tile[(w * jb + c) * R + lr];
+            }
+        }
+        if (tid == 0)
+            cidx[buf * P + g] = lrow;
+        if (k >= gr0 && k < gr0 + nr) {
+            const int lr = (int)(k - gr0);
+            double *rb = rowk + (size_t)buf * K * jb;
+            for (int e = tid; e < K * jb; e += PANEL_THREADS) {
+                const int w = e / jb, c = e % jb;
+                rb[w * jb + c] = tile[(w * jb + c) * R + lr];
+            }
+        }
+        grid.sync();
+        // ---- global pivot: same reduction in every workgroup
+        {
+            double v[K];
+            int64_t row = -1;
+            if (tid < P) {
+                row = cidx[buf * P + tid];
+                const double *cc = cand + ((size_t)(buf * P + tid) * K) * jb;
+#pragma unroll
+                for (int w = 0; w < K; ++w)
+                    v[w] = row >= 0 ? cc[w * jb + kk] : 0.0;
+            } else {
+#pragma unroll
+                for (int w = 0; w < K; ++w)
+                    v[w] = 0.0;
+            }
+#pragma unroll
+            for (int w = 0; w < K; ++w)
+                rk[tid][w] = v[w];
+            ri[tid] = row;
+            // remember which workgroup owns each candidate: encode in the order
+            __syncthreads();
+            for (int s = PANEL_THREADS / 2; s > 0; s >>= 1) {
+                if (tid < s) {
+                    double a[K], b[K];
+#pragma unroll
+                    for (int w = 0; w < K; ++w) {
+                        a[w] = rk[tid][w];
+                        b[w] = rk[tid + s][w];
+                    }
+                    if (cand_better<K>(b, ri[tid + s], a, ri[tid])) {
+#pragma unroll
+                        for (int w = 0; w < K; ++w)
+                            rk[tid][w] = b[w];
+                        ri[tid] = ri[tid + s];
+                    }
+                }
+                __syncthreads();
+            }
+            if (tid == 0)
+                s_gw = (int)((ri[0] - j0) / R);  // owner of the pivot row
+            __syncthreads();
+        }
+        const int64_t p = ri[0];
+        const int gw = s_gw;
+        {
+            const double *cc = cand + ((size_t)(buf * P + gw) * K) * jb;
+            for (int e = tid; e < K * jb; e += PANEL_THREADS)
+                prow[e] = cc[e];
+        }
+        __syncthreads();
+        // ---- row interchange k <-> p inside the LDS tiles
+        if (k >= gr0 && k < gr0 + nr) {
+            const int lr = (int)(k - gr0);
+            for (int e = tid; e < K * jb; e += PANEL_THREADS) {
+                const int w = e / jb, c = e % jb;
+                tile[(w * jb + c) * R + lr] = prow[w * jb + c];
+            }
+        }
+        if (p != k && p >= gr0 && p < gr0 + nr) {
+            const int lr = (int)(p - gr0);
+            const double *rb = rowk + (size_t)buf * K * jb;
+            for (int e = tid; e < K * jb; e += PANEL_THREADS) {
+                const int w = e / jb, c = e % jb;
+                tile[(w * jb + c) * R + lr] = rb[w * jb + c];
+            }
+        }
+        if (g == 0 && tid == 0)
+            ipiv[k] = p;
+        __syncthreads();
+        double pv[K];
+#pragma unroll
+        for (int w = 0; w < K; ++w)
+            pv[w] = prow[w * jb + kk];
+        if (is_zero<K>(pv)) {
+            if (g == 0 && tid == 0 && *info == 0)
+                *info = k + 1;
+            continue;  // the whole column below is zero: nothing to eliminate
+        }
+        double rcp[K];
+        recip<K>(pv, rcp);
+        // ---- multipliers l_ik = a_ik * (1 / a_kk)
+        if (tid < nr && gr0 + tid > k) {
+            double a[K], l[K];
+#pragma unroll
+            for (int w = 0; w < K; ++w)
+                a[w] = tile[(w * jb + kk) * R + tid];
+            mul<K>(a, rcp, l);
+#pragma unroll
+            for (int w = 0; w < K; ++w)
+                tile[(w * jb + kk) * R + tid] = l[w];
+        }
+        __syncthreads();
+        // ---- a_ij <- a_ij - l_ik u_kj for the rest of the panel row
+        const int ncol = jb - kk - 1;
+        for (int e = tid; e < nr * ncol; e += PANEL_THREADS) {
+            const int r = e % nr, c = kk + 1 + e / nr;
+            if (gr0 + r > k) {
+                double a[K], l[K], u[K], o[K];
+#pragma unroll
+                for (int w = 0; w < K; ++w) {
+                    a[w] = tile[(w * jb + c) * R + r];
+                    l[w] = tile[(w * jb + kk) * R + r];
+                    u[w] = prow[w * jb + c];
+                }
+                fms<K>(a, l, u, o);
+#pragma unroll
+                for (int w = 0; w < K; ++w)
+                    tile[(w * jb + c) * R + r] = o[w];
+            }
+        }
+        __syncthreads();
+    }
+
+    for (int e = tid; e < jb * R; e += PANEL_THREADS) {
+        const int r = e % R, c = e / R;
+        if (r < nr) {
+#pragma unroll
+            for (int w = 0; w < K; ++w)
+                A[w * ldp + (j0 + c) * lda + gr0 + r] = tile[(w * jb + c) * R + r];
+        }
+    }
+
+    // ---- net row permutation of the nb swaps, as (dst, src) pairs:
+    //      after the swaps, row dst holds the original row src.
+    //      Lane l tracks block position j0+l and one outside slot.
+    if (g == 0 && tid < 64) {
+        __threadfence_block();
+        const int lane = tid;
+        int64_t in_c = j0 + lane;
+        int64_t out_pos = -1, out_c = -1;
+        int nout = 0;
+        for (int q = 0; q < jb; ++q) {
+            const int64_t pq = ipiv[j0 + q];
+            if (pq == j0 + q)
+                continue;
+            const int64_t ck = __shfl(in_c, q, 64);
+            if (pq < j0 + jb) {
+                const int64_t cp = __shfl(in_c, (int)(pq - j0), 64);
+                if (lane == q)
+                    in_c = cp;
+                if (lane == (int)(pq - j0))
+                    in_c = ck;
+            } else {
+                const unsigned long long m = __ballot(lane < nout && out_pos == pq);
+                int slot;
+                if (m) {
+                    slot = __ffsll(m) - 1;
+                } else {
+                    slot = nout;
+                    if (lane == slot) {
+                        out_pos = pq;
+                        out_c = pq;
+                    }
+                    ++nout;
+                }
+                const int64_t co = __shfl(out_c, slot, 64);
+                if (lane == q)
+                    in_c = co;
+                if (lane == slot)
+                    out_c = ck;
+            }
+        }
+        // pairs layout: dst[2*nbmax], src[2*nbmax]; -1 = unused
+        int64_t *dst = pairs, *src = pairs + 2 * PANEL_NB_MAX;
+        const bool in_ok = lane < jb && in_c != j0 + lane;
+        dst[lane] = in_ok ? j0 + lane : -1;
+        src[lane] = in_ok ? in_c : -1;
+        const bool out_ok = lane < nout && out_c != out_pos;
+        dst[PANEL_NB_MAX + lane] = out_ok ? out_pos : -1;
+        src[PANEL_NB_MAX + lane] = out_ok ? out_c : -1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// row interchanges outside the panel (+ U12 solve right of the panel)
+// one workgroup of 64 threads per column
+// ---------------------------------------------------------------------------
+template <int K, bool TRSM>
+__global__ void __launch_bounds__(64)
+    k_laswp_trsm(double *__restrict__ A, int64_t lda, int64_t ldp, int64_t j0, int jb, int64_t col0,
+                 const int64_t *__restrict__ pairs)
+{
+    __shared__ double stage[2 * PANEL_NB_MAX][K];
+    __shared__ double ub[K];
+    const int64_t c = col0 + blockIdx.x;
+    const int lane = threadIdx.x;
+    const int64_t *dst = pairs, *src = pairs + 2 * PANEL_NB_MAX;
+    double *colp = A + c * lda;
+    for (int t = lane; t < 2 * PANEL_NB_MAX; t += 64) {
+        const int64_t s = src[t];
+        if (s >= 0) {
+#pragma unroll
+            for (int w = 0; w < K; ++w)
+                stage[t][w] = colp[w * ldp + s];
+        }
+    }
+    __syncthreads();
+    for (int t = lane; t < 2 * PANEL_NB_MAX; t += 64) {
+        const int64_t d = dst[t];
+        if (d >= 0) {
+#pragma unroll
+            for (int w = 0; w < K; ++w)
+                colp[w * ldp + d] = stage[t][w];
+        }
+    }
+    if (!TRSM)
+        return;
+    __syncthreads();
+    __threadfence_block();
+    // forward substitution with the unit lower L11 (rows/cols j0..j0+jb-1)
+    double u[K];
+    if (lane < jb) {
+#pragma unroll
+        for (int w = 0; w < K; ++w)
+            u[w] = colp[w * ldp + j0 + lane];
+    }
+    for (int kk = 0; kk < jb; ++kk) {
+        if (lane == kk) {
+#pragma unroll
+            for (int w = 0; w < K; ++w)
+                ub[w] = u[w];
+        }
+        __syncthreads();
+        if (lane > kk && lane < jb) {
+            double l[K], uk[K], o[K];
+#pragma unroll
+            for (int w = 0; w < K; ++w) {
+                l[w] = A[w * ldp + (j0 + kk) * lda + j0 + lane];
+                uk[w] = ub[w];
+            }
+            fms<K>(u, l, uk, o);
+#pragma unroll
+            for (int w = 0; w < K; ++w)
+                u[w] = o[w];
+        }
+        __syncthreads();
+    }
+    if (lane < jb) {
+#pragma unroll
+        for (int w = 0; w < K; ++w)
+            colp[w * ldp + j0 + lane] = u[w];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// trailing update C <- C - L21 * U12
+// C(i,j) = A[r0+i, c0+j], L21(i,k) = A[r0+i, j0+k], U12(k,j) = A[j0+k, c0+j]
+// workgroup tile BM x BN, thread tile TM x TN (rows tx + (BM/TM) a,
+// columns ty + (BN/TN) b), k staged through LDS in chunks of KB.
+// ---------------------------------------------------------------------------
+template <int K, int BM, int BN, int TM, int TN, int KB>
+__global__ void __launch_bounds__(UPD_THREADS)
+    k_update(double *__restrict__ A, int64_t lda, int64_t ldp, int64_t r0, int64_t c0, int64_t m, int64_t nc,
+             int64_t j0, int kd)
+{
+    static_assert((BM / TM) * (BN / TN) == UPD_THREADS, "thread tile");
+    __shared__ double Ls[K][KB][BM];
+    __shared__ double Us[K][KB][BN];
+    constexpr int TX = BM / TM;
+    const int tid = threadIdx.x;
+    const int tx = tid % TX, ty = tid / TX;
+    const int64_t bi = (int64_t)blockIdx.x * BM, bj = (int64_t)blockIdx.y * BN;
+
+    double acc[TM][TN][K];
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b) {
+            const int64_t i = bi + tx + a * TX, j = bj + ty + b * (BN / TN);
+#pragma unroll
+            for (int w = 0; w < K; ++w)
+                acc[a][b][w] = (i < m && j < nc) ? A[w * ldp + (c0 + j) * lda + r0 + i] : 0.0;
+        }
+
+    for (int k0 = 0; k0 < kd; k0 += KB) {
+        const int kc = (kd - k0) < KB ? (kd - k0) : KB;
+        for (int e = tid; e < KB * BM; e += UPD_THREADS) {
+            const int i = e % BM, kk = e / BM;
+            const bool ok = kk < kc && bi + i < m;
+#pragma unroll
+            for (int w = 0; w < K; ++w)
+                Ls[w][kk][i] = ok ? A[w * ldp + (j0 + k0 + kk) * lda + r0 + bi + i] : 0.0;
+        }
+        for (int e = tid; e < KB * BN; e += UPD_THREADS) {
+            const int kk = e % KB, j = e / KB;
+            const bool ok = kk < kc && bj + j < nc;
+#pragma unroll
+            for (int w = 0; w < K; ++w)
+                Us[w][kk][j] = ok ? A[w * ldp + (c0 + bj + j) * lda + j0 + k0 + kk] : 0.0;
+        }
+        __syncthreads();
+        for (int kk = 0; kk < kc; ++kk) {
+            double l[TM][K], u[TN][K];
+#pragma unroll
+            for (int a = 0; a < TM; ++a)
+#pragma unroll
+                for (int w = 0; w < K; ++w)
+                    l[a][w] = Ls[w][kk][tx + a * TX];
+#pragma unroll
+            for (int b = 0; b < TN; ++b)
+#pragma unroll
+                for (int w = 0; w < K; ++w)
+                    u[b][w] = Us[w][kk][ty + b * (BN / TN)];
+#pragma unroll
+            for (int a = 0; a < TM; ++a)
+#pragma unroll
+                for (int b = 0; b < TN; ++b) {
+                    double o[K];
+                    fms<K>(acc[a][b], l[a], u[b], o);
+#pragma unroll
+                    for (int w = 0; w < K; ++w)
+                        acc[a][b][w] = o[w];
+                }
+        }
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b) {
+            const int64_t i = bi + tx + a * TX, j = bj + ty + b * (BN / TN);
+            if (i < m && j < nc) {
+#pragma unroll
+                for (int w = 0; w < K; ++w)
+                    A[w * ldp + (c0 + j) * lda + r0 + i] = acc[a][b][w];
+            }
+        }
+}
+
+template <int K>
+struct UpdCfg;
+template <>
+struct UpdCfg<1> {
+    static constexpr int BM = 64, BN = 64, TM = 4, TN = 4, KB = 16;
+};
+template <>
+struct UpdCfg<2> {
+    static constexpr int BM = 64, BN = 64, TM = 4, TN = 4, KB = 16;
+};
+template <>
+struct UpdCfg<3> {
+    static constexpr int BM = 64, BN = 64, TM = 4, TN = 4, KB = 16;
+};
+template <>
+struct UpdCfg<4> {
+    static constexpr int BM = 64, BN = 32, TM = 4, TN = 2, KB = 16;
+};
+
+// ---------------------------------------------------------------------------
+// host driver
+// ---------------------------------------------------------------------------
+size_t getrf_scratch_bytes(int K)
+{
+    const size_t cand = 2ull * PANEL_WG_MAX * K * PANEL_NB_MAX * sizeof(double);
+    const size_t cidx = 2ull * PANEL_WG_MAX * sizeof(int64_t);
+    const size_t rowk = 2ull * K * PANEL_NB_MAX * sizeof(double);
+    const size_t pairs = 4ull * PANEL_NB_MAX * sizeof(int64_t);
+    return cand + cidx + rowk + pairs + 4 * 256;
+}
+
+__global__ void k_zero_i64(int64_t *p)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        *p = 0;
+}
+
+static size_t panel_lds_bytes(int K, int jb, int R) { return ((size_t)K * jb * R + (size_t)K * jb) * sizeof(double); }
+
+template <int K>
+int getrf_run(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int64_t *info, void *scr,
+              hipStream_t s)
+{
+    if (n == 0)
+        return BNC_OK;
+    const int nb = PANEL_NB_MAX;
+    char *base = (char *)scr;
+    double *cand = (double *)base;
+    base += 2ull * PANEL_WG_MAX * K * PANEL_NB_MAX * sizeof(double);
+    int64_t *cidx = (int64_t *)base;
+    base += 2ull * PANEL_WG_MAX * sizeof(int64_t);
+    double *rowk = (double *)base;
+    base += 2ull * K * PANEL_NB_MAX * sizeof(double);
+    int64_t *pairs = (int64_t *)base;
+
+    int dev = 0;
+    BNC_HIP(hipGetDevice(&dev));
+    int ncu = 0, lds_max = 0;
+    BNC_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    BNC_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    const size_t lds_static = PANEL_THREADS * (K * sizeof(double) + sizeof(int64_t)) + 64;
+
+    hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(64), 0, s, info);
+    BNC_LAUNCH_CHECK();
+    for (int64_t j0 = 0; j0 < n; j0 += nb) {
+        const int jb = (int)((n - j0) < nb ? (n - j0) : nb);
+        const int64_t m = n - j0;
+        // rows per workgroup: 64 when the LDS allows, fewer otherwise; the
+        // grid must fit in one cooperative wave of workgroups
+        void *kfn = (void *)k_panel<K>;
+        int R = 64;
+        while (R > 8 && panel_lds_bytes(K, jb, R) + lds_static > (size_t)lds_max)
+            R /= 2;
+        const size_t lds = panel_lds_bytes(K, jb, R);
+        if (lds + lds_static > (size_t)lds_max)
+            return fail_arg(BNC_ERR_UNSUPPORTED, "getrf: panel does not fit in LDS");
+        if (hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+            (void)hipGetLastError();
+        int per_cu = 0;
+        BNC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, PANEL_THREADS, lds));
+        const int64_t coop_max = (int64_t)per_cu * ncu < PANEL_WG_MAX ? (int64_t)per_cu * ncu : PANEL_WG_MAX;
+        const int P = (int)ceil_div(m, R);
+        if (P > coop_max)
+            return fail_arg(BNC_ERR_UNSUPPORTED, "getrf: panel needs more workgroups than can be co-resident");
+        int64_t j0v = j0, nv = n;
+        int jbv = jb, Rv = R;
+        void *args[] = {&A, &lda, &ldp, &nv, &j0v, &jbv, &Rv, &ipiv, &info, &cand, &cidx, &rowk, &pairs};
+        BNC_HIP(hipLaunchCooperativeKernel(kfn, dim3(P), dim3(PANEL_THREADS), args, (unsigned)lds, s));
+        if (j0 > 0) {
+            hipLaunchKernelGGL((k_laswp_trsm<K, false>), dim3((unsigned)j0), dim3(64), 0, s, A, lda, ldp, j0, jb,
+                               (int64_t)0, (const int64_t *)pairs);
+            BNC_LAUNCH_CHECK();
+        }
+        const int64_t c0 = j0 + jb;
+        if (c0 < n) {
+            hipLaunchKernelGGL((k_laswp_trsm<K, true>), dim3((unsigned)(n - c0)), dim3(64), 0, s, A, lda, ldp, j0,
+                               jb, c0, (const int64_t *)pairs);
+            BNC_LAUNCH_CHECK();
+            using C = UpdCfg<K>;
+            const int64_t mm = n - c0;
+            dim3 grid((unsigned)ceil_div(mm, C::BM), (unsigned)ceil_div(mm, C::BN));
+            const int ev = UpdateTimer::begin(s);
+            hipLaunchKernelGGL((k_update<K, C::BM, C::BN, C::TM, C::TN, C::KB>), grid, dim3(UPD_THREADS), 0, s, A,
+                               lda, ldp, c0, c0, mm, mm, j0, jb);
+            BNC_LAUNCH_CHECK();
+            UpdateTimer::end(ev, s, (double)mm * (double)mm * (double)jb * fms_flops(K));
+        }
+    }
+    return BNC_OK;
+}
+
+template int getrf_run<1>(int64_t, double *, int64_t, int64_t, int64_t *, int64_t *, void *, hipStream_t);
+template int getrf_run<2>(int64_t, double *, int64_t, int64_t, int64_t *, int64_t *, void *, hipStream_t);
+template int getrf_run<3>(int64_t, double *, int64_t, int64_t, int64_t *, int64_t *, void *, hipStream_t);
+template int getrf_run<4>(int64_t, double *, int64_t, int64_t, int64_t *, int64_t *, void *, hipStream_t);
+
+}  // namespace bnc

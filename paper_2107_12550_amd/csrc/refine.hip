@@ -1,0 +1,822 @@
+// Mixed-precision iterative refinement (Kouya 2021, Sec. 2, Listing 1) and
+// its long-precision pieces: the exact residual, norms, the update.
+//
+// Residual r = b - A x.  Every product A_ij^(u) x_j^(w) is split exactly by
+// TwoProd; every resulting binary64 term is cut into fixed-point digits of
+// W = 34 bits over up to 40 bins anchored at the row's largest possible term
+// (an extraction (sigma + t) - sigma with sigma = 1.5 * 2^(52 + e_bin) is
+// exact and rounds t to a multiple of 2^e_bin).  The number of bins a row
+// uses reaches down to a bound on the lowest bit of any term, taken from the
+// smallest exponents of the words of A, x and b, so the digit sums are
+// exact: they stay below 2^53 units of their bin for up to 2^19 terms per
+// row.  The bins are then read as one signed integer and rounded greedily
+// to four binary64 words with round-to-nearest-even: the canonical
+// quad-double of the exact residual.  Only data spanning more than 1360
+// bits would leave bits below the window; such a row reports "inexact".
+#include <string.h>
+
+#include "common.hpp"
+#include "mw.hpp"
+
+namespace bnc {
+
+template <int K>
+int getrf_run(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int64_t *info, void *scr,
+              hipStream_t s);
+template <int K>
+int getrs_perm(int64_t n, const double *LU, int64_t lda, int64_t ldp, const int32_t *perm, const double *b,
+               int64_t ldb, double *y, int64_t ldy, hipStream_t s);
+int ipiv_to_perm(int64_t n, const int64_t *ipiv, int32_t *perm, hipStream_t s);
+
+constexpr int RB_W = 34;
+constexpr int RB_NB = 40;  // maximum bins per row
+constexpr int RES_ROWS = 64;
+constexpr int RES_WAVES = 4;
+constexpr int RED_BLOCKS = 256;  // partial-sum slots of the deterministic reductions
+
+// exponent e with 2^e <= |x| < 2^(e+1) for normal x; -1023 for zero/subnormal
+__device__ __forceinline__ int ilogb_bits(double x)
+{
+    return (int)((__double_as_longlong(x) >> 52) & 0x7ff) - 1023;
+}
+
+// frexp-style exponent used for the power-of-two normalisation:
+// e = floor(log2 m) for m > 0, and -1 for m == 0 (as frexp(0) = (0, 0)).
+__host__ __device__ inline int norm_exp(double m)
+{
+    if (m == 0.0)
+        return -1;
+    int e;
+    (void)frexp(m, &e);
+    return e - 1;
+}
+
+struct RowAnchor {
+    int e0;   // exponent of bin 0's quantum
+    int nb;   // bins in use
+    bool any; // the row has a nonzero term
+};
+
+// Exponent bounds gathered before the residual: the smallest floor(log2|v|)
+// over the nonzero words of A, x and b (2000 when there is none).
+struct ExpBounds {
+    int a, x, b;
+};
+
+// lowest bit any term can have: products of words (each word's lowest bit is
+// at least its exponent - 52) and the words of b
+__device__ __forceinline__ int lowest_bit(const ExpBounds &eb)
+{
+    int lo = 100000;
+    if (eb.a < 2000 && eb.x < 2000)
+        lo = eb.a + eb.x - 104;
+    if (eb.b < 2000)
+        lo = (eb.b - 52) < lo ? (eb.b - 52) : lo;
+    return lo;
+}
+
+__device__ __forceinline__ RowAnchor row_anchor(double amax, double xmax, double b0, int h, int elow)
+{
+    int eT = -100000;
+    if (amax > 0.0 && xmax > 0.0)
+        eT = ilogb_bits(amax) + ilogb_bits(xmax) + 2;
+    if (b0 != 0.0) {
+        const int eb = ilogb_bits(fabs(b0)) + 1;
+        eT = eT > eb ? eT : eb;
+    }
+    RowAnchor r;
+    r.any = eT > -100000;
+    int e0 = eT + h - 53;
+    if (e0 < -600)
+        e0 = -600;
+    if (e0 > 900)
+        e0 = 900;
+    r.e0 = e0;
+    // bins q = 0..nb-1 have quanta 2^(e0 - W q); the last must reach elow
+    int nb = (e0 - elow + RB_W - 1) / RB_W + 1;
+    if (nb < 1)
+        nb = 1;
+    if (nb > RB_NB)
+        nb = RB_NB;
+    if (e0 - RB_W * (nb - 1) < -1074 + 0)  // keep every quantum a normal power of two
+        nb = (e0 + 1022) / RB_W + 1;
+    r.nb = nb;
+    return r;
+}
+
+__device__ __forceinline__ void deposit(double t, const double (&sig)[RB_NB], double (&bins)[RB_NB], int nb,
+                                        double lim0, bool &bad)
+{
+    bad = bad || !(fabs(t) <= lim0);
+#pragma unroll
+    for (int b = 0; b < RB_NB; ++b) {
+        if (b < nb) {
+            const double d = (sig[b] + t) - sig[b];
+            bins[b] = bins[b] + d;
+            t = t - d;
+        }
+    }
+    bad = bad || (t != 0.0);
+}
+
+// partial bins of rows [64*bx, +64); workgroup column split sidx, each wave
+// a quarter of it: split index sidx*4 + wave
+template <int AW>
+__global__ void __launch_bounds__(RES_ROWS *RES_WAVES)
+    k_resid_partial(int64_t n, const double *__restrict__ A, int64_t lda, int64_t ldpa, const double *__restrict__ x,
+                    int64_t ldx, const double *__restrict__ b, int64_t ldb, const double *__restrict__ rowmax,
+                    const double *__restrict__ xmaxp, const ExpBounds *__restrict__ ebp, int h, int64_t chunk,
+                    double *__restrict__ part, int32_t *__restrict__ inexact)
+{
+    const int lane = threadIdx.x % RES_ROWS, wv = threadIdx.x / RES_ROWS;
+    const int64_t i = (int64_t)blockIdx.x * RES_ROWS + lane;
+    const int split = blockIdx.y * RES_WAVES + wv;
+    if (i >= n)
+        return;
+    double bins[RB_NB];
+#pragma unroll
+    for (int q = 0; q < RB_NB; ++q)
+        bins[q] = 0.0;
+    bool bad = false;
+    const double xm = *xmaxp;
+    const RowAnchor an = row_anchor(rowmax[i], xm, b[i], h, lowest_bit(*ebp));
+    const int nb = an.nb;
+    if (an.any) {
+        double sig[RB_NB];
+#pragma unroll
+        for (int q = 0; q < RB_NB; ++q)
+            sig[q] = q < nb ? 1.5 * pow2(an.e0 - RB_W * q + 52) : 0.0;
+        const double lim0 = pow2(an.e0 + 51);
+        const int64_t j0 = (int64_t)blockIdx.y * chunk;
+        const int64_t j1 = (j0 + chunk) < n ? (j0 + chunk) : n;
+        const int64_t len = j1 > j0 ? j1 - j0 : 0;
+        const int64_t q0 = j0 + (len * wv) / RES_WAVES, q1 = j0 + (len * (wv + 1)) / RES_WAVES;
+        for (int64_t j = q0; j < q1; ++j) {
+            double xv[4];
+#pragma unroll
+            for (int w = 0; w < 4; ++w)
+                xv[w] = x[w * ldx + j];
+#pragma unroll
+            for (int u = 0; u < AW; ++u) {
+                const double a = A[u * ldpa + j * lda + i];
+#pragma unroll
+                for (int w = 0; w < 4; ++w) {
+                    double lo;
+                    const double hi = two_prod(a, xv[w], lo);
+                    deposit(-hi, sig, bins, nb, lim0, bad);
+                    deposit(-lo, sig, bins, nb, lim0, bad);
+                }
+            }
+        }
+        if (split == 0) {
+#pragma unroll
+            for (int w = 0; w < 4; ++w)
+                deposit(b[w * ldb + i], sig, bins, nb, lim0, bad);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < RB_NB; ++q)
+        if (q < nb)
+            part[((int64_t)split * RB_NB + q) * n + i] = bins[q];
+    if (bad)
+        atomicOr(inexact, 1);
+}
+
+// smallest floor(log2|v|) over the nonzero words (2000 if none)
+__global__ void k_minexp(int64_t rows, int64_t cols, int64_t ld, int words, int64_t ldp, const double *__restrict__ v,
+                         int *__restrict__ out)
+{
+    __shared__ int s[256];
+    int m = 2000;
+    const int64_t n = rows * cols;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t idx = (e / rows) * ld + e % rows;
+        for (int w = 0; w < words; ++w) {
+            const double t = v[w * ldp + idx];
+            if (t != 0.0) {
+                const int ex = ilogb_bits(t);
+                m = ex < m ? ex : m;
+            }
+        }
+    }
+    s[threadIdx.x] = m;
+    __syncthreads();
+    for (int t = 128; t > 0; t >>= 1) {
+        if (threadIdx.x < t)
+            s[threadIdx.x] = s[threadIdx.x + t] < s[threadIdx.x] ? s[threadIdx.x + t] : s[threadIdx.x];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        atomicMin(out, s[0]);
+}
+
+__global__ void k_fill_i32(int *p, int64_t n, int v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        p[i] = v;
+}
+
+// ---- exact signed integer in 32-bit limbs (carry-save in int64) ------------
+constexpr int BL = 46;  // 1472 bits >= 34*39 + 53 + headroom
+
+struct Big {
+    int64_t l[BL];
+};
+
+// add v * 2^pos, v signed with |v| < 2^63, pos >= 0
+__device__ __forceinline__ void big_add(Big &B, int64_t v, int pos)
+{
+    const int L = pos >> 5, sh = pos & 31;
+    const uint64_t lo = (uint64_t)(v & 0xffffffffLL);
+    const int64_t hi = v >> 32;  // arithmetic: v = lo + hi * 2^32
+    const uint64_t los = lo << sh;
+#pragma unroll
+    for (int q = 0; q < BL; ++q) {
+        if (q == L)
+            B.l[q] += (int64_t)(los & 0xffffffffULL);
+        if (q == L + 1)
+            B.l[q] += (int64_t)(los >> 32) + hi * ((int64_t)1 << sh);
+    }
+}
+
+__device__ __forceinline__ void big_norm(Big &B)
+{
+#pragma unroll
+    for (int q = 0; q < BL - 1; ++q) {
+        const int64_t c = B.l[q] >> 32;
+        B.l[q] -= c * ((int64_t)1 << 32);
+        B.l[q + 1] += c;
+    }
+}
+
+// Round |B| (B normalised) to nearest binary64 mantissa: returns mant (0 if
+// B == 0) and the bit position of its least significant bit.
+__device__ __forceinline__ uint64_t big_round(const Big &M, int &lsb)
+{
+    int hl = -1;
+#pragma unroll
+    for (int q = BL - 1; q >= 0; --q)
+        if (hl < 0 && M.l[q] != 0)
+            hl = q;
+    if (hl < 0) {
+        lsb = 0;
+        return 0;
+    }
+    uint64_t l2 = 0, l1 = 0, l0 = 0;  // limbs hl, hl-1, hl-2
+    bool below = false;               // any bit in limbs < hl-2
+#pragma unroll
+    for (int q = 0; q < BL; ++q) {
+        const uint64_t v = (uint64_t)M.l[q];
+        if (q == hl)
+            l2 = v;
+        if (q == hl - 1)
+            l1 = v;
+        if (q == hl - 2)
+            l0 = v;
+        if (q < hl - 2 && v != 0)
+            below = true;
+    }
+    const int msb = 31 - __clz((unsigned)l2);
+    // 64 bits starting at the most significant set bit
+    const uint64_t top = (l2 << (63 - msb)) | (l1 << (31 - msb)) | (l0 >> (msb + 1));
+    const bool lowbits = (l0 & ((1ULL << (msb + 1)) - 1ULL)) != 0;
+    uint64_t mant = top >> 11;
+    const bool guard = (top >> 10) & 1ULL;
+    const bool sticky = ((top & 0x3ffULL) != 0) || lowbits || below;
+    int T = 32 * hl + msb;
+    if (guard && (sticky || (mant & 1ULL))) {
+        ++mant;
+        if (mant == (1ULL << 53)) {
+            mant >>= 1;
+            ++T;
+        }
+    }
+    lsb = T - 52;
+    return mant;
+}
+
+__global__ void __launch_bounds__(256)
+    k_resid_final(int64_t n, int S, const double *__restrict__ part, const double *__restrict__ rowmax,
+                  const double *__restrict__ xmaxp, const ExpBounds *__restrict__ ebp, const double *__restrict__ b,
+                  int h, double *__restrict__ r, int64_t ldr, int32_t *__restrict__ inexact)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    const RowAnchor an = row_anchor(rowmax[i], *xmaxp, b[i], h, lowest_bit(*ebp));
+    const int nb = an.nb;
+    double out[4] = {0.0, 0.0, 0.0, 0.0};
+    bool bad = false;
+    if (an.any) {
+        Big B;
+#pragma unroll
+        for (int q = 0; q < BL; ++q)
+            B.l[q] = 0;
+        const int elow = an.e0 - RB_W * (nb - 1);  // exponent of the integer's unit
+        for (int q = 0; q < nb; ++q) {
+            double s = 0.0;
+            for (int t = 0; t < S; ++t)
+                s = s + part[((int64_t)t * RB_NB + q) * n + i];  // S = number of splits
+            // bin q holds multiples of 2^(e0 - W q): integer digit
+            const double dig = ldexp(s, -(an.e0 - RB_W * q));
+            big_add(B, (int64_t)dig, RB_W * (nb - 1 - q));
+        }
+        for (int w = 0; w < 4; ++w) {
+            big_norm(B);
+            const bool neg = B.l[BL - 1] < 0;
+            Big M = B;
+            if (neg) {
+#pragma unroll
+                for (int q = 0; q < BL; ++q)
+                    M.l[q] = -M.l[q];
+                big_norm(M);
+            }
+            int lsb;
+            const uint64_t mant = big_round(M, lsb);
+            if (mant == 0)
+                break;
+            const int e = lsb + elow;
+            if (e + 52 > 1023 || e + 52 < -1022)
+                bad = true;
+            const double v = ldexp((double)mant, e);
+            out[w] = neg ? -v : v;
+            // B -= value: subtract mant * 2^lsb (lsb may be negative only
+            // when the integer is below 2^53, then mant's low bits are zero)
+            const int64_t sm = neg ? -(int64_t)mant : (int64_t)mant;
+            if (lsb >= 0)
+                big_add(B, -sm, lsb);
+            else
+                big_add(B, -(sm >> (-lsb)), 0);
+        }
+    }
+#pragma unroll
+    for (int w = 0; w < 4; ++w)
+        r[w * ldr + i] = out[w];
+    if (bad)
+        atomicOr(inexact, 1);
+}
+
+// ---- small vector / matrix helpers ------------------------------------------
+
+__global__ void k_fill_u64(uint64_t *p, int64_t n, uint64_t v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        p[i] = v;
+}
+
+__global__ void k_check_finite(int64_t rows, int64_t cols, int words, const double *__restrict__ p, int64_t ld,
+                               int64_t ldp, int32_t *__restrict__ flag)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= rows * cols)
+        return;
+    const int64_t i = e % rows, j = e / rows;
+    bool bad = false;
+    for (int w = 0; w < words; ++w)
+        bad = bad || !isfinite(p[w * ldp + j * ld + i]);
+    if (bad)
+        atomicOr(flag, 1);
+}
+
+// K-word copy of an aw-word matrix (renormalised)
+template <int K, int AW>
+__global__ void k_stage(int64_t n, const double *__restrict__ A, int64_t lda, int64_t ldpa, double *__restrict__ LU,
+                        int64_t ldl, int64_t ldpl)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * n)
+        return;
+    const int64_t i = e % n, j = e / n;
+    double v[AW], o[K];
+#pragma unroll
+    for (int u = 0; u < AW; ++u)
+        v[u] = A[u * ldpa + j * lda + i];
+    renorm<K, AW>(v, o);
+#pragma unroll
+    for (int w = 0; w < K; ++w)
+        LU[w * ldpl + j * ldl + i] = o[w];
+}
+
+// rowmax[i] = max_j |A0(i, j)|  (thread per row, coalesced across rows)
+__global__ void k_rowmax(int64_t n, const double *__restrict__ A, int64_t lda, double *__restrict__ rowmax)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    double m = 0.0;
+    for (int64_t j = 0; j < n; ++j)
+        m = fmax(m, fabs(A[j * lda + i]));
+    rowmax[i] = m;
+}
+
+// max |v(i, j)| over rows x cols entries (leading dimension ld), folded into
+// *bits with an integer max (non-negative doubles order like their bits)
+__global__ void k_absmax(int64_t rows, int64_t cols, int64_t ld, const double *__restrict__ v,
+                         unsigned long long *__restrict__ bits)
+{
+    __shared__ double s[256];
+    double m = 0.0;
+    const int64_t n = rows * cols;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        m = fmax(m, fabs(v[(e / rows) * ld + e % rows]));
+    s[threadIdx.x] = m;
+    __syncthreads();
+    for (int t = 128; t > 0; t >>= 1) {
+        if (threadIdx.x < t)
+            s[threadIdx.x] = fmax(s[threadIdx.x], s[threadIdx.x + t]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        atomicMax(bits, (unsigned long long)__double_as_longlong(s[0]));
+}
+
+// deterministic sum of (v_i 2^-e)^2: fixed per-block partials, then one
+// block sums the partials in order
+__global__ void k_sumsq_part(int64_t rows, int64_t cols, int64_t ld, const double *__restrict__ v,
+                             const unsigned long long *__restrict__ maxbits, double *__restrict__ part)
+{
+    __shared__ double s[256];
+    const double m = __longlong_as_double((long long)*maxbits);
+    const double sc = pow2(-(norm_exp(m) + 1));
+    double acc = 0.0;
+    const int64_t n = rows * cols;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const double t = v[(e / rows) * ld + e % rows] * sc;
+        acc = acc + t * t;
+    }
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int t = 128; t > 0; t >>= 1) {
+        if (threadIdx.x < t)
+            s[threadIdx.x] = s[threadIdx.x] + s[threadIdx.x + t];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        part[blockIdx.x] = s[0];
+}
+
+__global__ void k_sumsq_final(int nparts, const double *__restrict__ part, double *__restrict__ out)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double s = 0.0;
+        for (int t = 0; t < nparts; ++t)
+            s = s + part[t];
+        *out = s;
+    }
+}
+
+// dst (K words) = renorm(src (4 words) * 2^-e), e from the power-of-two max
+template <int K>
+__global__ void k_round_scaled(int64_t n, const double *__restrict__ src, int64_t lds_,
+                               const unsigned long long *__restrict__ maxbits, double *__restrict__ dst, int64_t ldd)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    const double sc = maxbits ? pow2(-norm_exp(__longlong_as_double((long long)*maxbits))) : 1.0;
+    double v[4], o[K];
+#pragma unroll
+    for (int w = 0; w < 4; ++w)
+        v[w] = src[w * lds_ + i] * sc;
+    renorm<K, 4>(v, o);
+#pragma unroll
+    for (int w = 0; w < K; ++w)
+        dst[w * ldd + i] = o[w];
+}
+
+// x = extend(z), quad-double from K words
+template <int K>
+__global__ void k_extend(int64_t n, const double *__restrict__ z, int64_t ldz, double *__restrict__ x, int64_t ldx)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+#pragma unroll
+    for (int w = 0; w < 4; ++w)
+        x[w * ldx + i] = w < K ? z[w * ldz + i] : 0.0;
+}
+
+// z <- z * 2^e in place (e from the residual max), then x <- x + extend(z)
+template <int K>
+__global__ void k_scale_update(int64_t n, double *__restrict__ z, int64_t ldz,
+                               const unsigned long long *__restrict__ rmaxbits, double *__restrict__ x, int64_t ldx)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    const double sc = pow2(norm_exp(__longlong_as_double((long long)*rmaxbits)));
+    double zv[4], xv[4], o[4];
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        zv[w] = w < K ? z[w * ldz + i] * sc : 0.0;
+        xv[w] = x[w * ldx + i];
+    }
+    add<4>(xv, zv, o);
+#pragma unroll
+    for (int w = 0; w < K; ++w)
+        z[w * ldz + i] = zv[w];
+#pragma unroll
+    for (int w = 0; w < 4; ++w)
+        x[w * ldx + i] = o[w];
+}
+
+__global__ void k_zero(int64_t n, double *__restrict__ p)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        p[i] = 0.0;
+}
+
+// ---- host helpers -------------------------------------------------------------
+
+static inline unsigned grid1(int64_t n, int t = 256) { return (unsigned)ceil_div(n > 0 ? n : 1, t); }
+
+static int residual_h(int64_t n, int aw)
+{
+    // h with 2^h >= 2 * terms; terms per row = 8 * aw * n + 4
+    const int64_t N = 8 * (int64_t)aw * n + 4;
+    int h = 1;
+    while (((int64_t)1 << h) < 2 * N)
+        ++h;
+    return h;
+}
+
+// workgroup column splits (each split into RES_WAVES wave splits)
+static int residual_splits(int64_t n)
+{
+    int64_t S = n / 512;
+    if (S < 1)
+        S = 1;
+    if (S > 4)
+        S = 4;
+    return (int)S;
+}
+
+size_t residual_scratch_bytes(int64_t n) { return (size_t)4 * RES_WAVES * RB_NB * n * sizeof(double) + 256; }
+
+// minimum exponents of the words of a rows x cols (ld) matrix with `words`
+// planes (ldp apart), folded into *out
+int minexp_run(int64_t rows, int64_t cols, int64_t ld, int words, int64_t ldp, const double *v, int *out,
+               hipStream_t s)
+{
+    unsigned g = grid1(rows * cols);
+    if (g > RED_BLOCKS)
+        g = RED_BLOCKS;
+    hipLaunchKernelGGL(k_minexp, dim3(g), dim3(256), 0, s, rows, cols, ld, words, ldp, v, out);
+    BNC_LAUNCH_CHECK();
+    return BNC_OK;
+}
+
+int fill_i32_run(int *p, int64_t n, int v, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid1(n)), dim3(256), 0, s, p, n, v);
+    BNC_LAUNCH_CHECK();
+    return BNC_OK;
+}
+
+// r = b - A x (exact -> canonical quad-double); rowmax, xmax and the
+// exponent bounds precomputed on the device
+int residual_run(int64_t n, int aw, const double *A, int64_t lda, int64_t ldpa, const double *x, int64_t ldx,
+                 const double *b, int64_t ldb, const double *rowmax, const double *xmax, const void *ebounds,
+                 double *part, double *r, int64_t ldr, int32_t *inexact, hipStream_t s)
+{
+    if (n == 0)
+        return BNC_OK;
+    if (8 * (int64_t)aw * n + 4 >= (1LL << 19))
+        return fail_arg(BNC_ERR_UNSUPPORTED, "residual: too many terms per row for exact accumulation");
+    const int h = residual_h(n, aw);
+    const int S = residual_splits(n);
+    const int64_t chunk = ceil_div(n, S);
+    const ExpBounds *eb = (const ExpBounds *)ebounds;
+    dim3 grid((unsigned)ceil_div(n, RES_ROWS), (unsigned)S);
+    if (aw == 1)
+        hipLaunchKernelGGL((k_resid_partial<1>), grid, dim3(RES_ROWS * RES_WAVES), 0, s, n, A, lda, ldpa, x, ldx, b,
+                           ldb, rowmax, xmax, eb, h, chunk, part, inexact);
+    else
+        hipLaunchKernelGGL((k_resid_partial<4>), grid, dim3(RES_ROWS * RES_WAVES), 0, s, n, A, lda, ldpa, x, ldx, b,
+                           ldb, rowmax, xmax, eb, h, chunk, part, inexact);
+    BNC_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_resid_final, dim3(grid1(n)), dim3(256), 0, s, n, S * RES_WAVES, (const double *)part,
+                       rowmax, xmax, eb, b, h, r, ldr, inexact);
+    BNC_LAUNCH_CHECK();
+    return BNC_OK;
+}
+
+// rowmax of |A0| and a one-element max of a vector's leading words
+int rowmax_run(int64_t n, const double *A, int64_t lda, double *rowmax, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_rowmax, dim3(grid1(n)), dim3(256), 0, s, n, A, lda, rowmax);
+    BNC_LAUNCH_CHECK();
+    return BNC_OK;
+}
+
+int absmax_run(int64_t rows, int64_t cols, int64_t ld, const double *v, unsigned long long *bits, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, (uint64_t *)bits, (int64_t)1, (uint64_t)0);
+    BNC_LAUNCH_CHECK();
+    unsigned g = grid1(rows * cols);
+    if (g > RED_BLOCKS)
+        g = RED_BLOCKS;
+    hipLaunchKernelGGL(k_absmax, dim3(g), dim3(256), 0, s, rows, cols, ld, v, bits);
+    BNC_LAUNCH_CHECK();
+    return BNC_OK;
+}
+
+int sumsq_run(int64_t rows, int64_t cols, int64_t ld, const double *v, const unsigned long long *maxbits,
+              double *part, double *out, hipStream_t s)
+{
+    unsigned g = grid1(rows * cols);
+    if (g > RED_BLOCKS)
+        g = RED_BLOCKS;
+    hipLaunchKernelGGL(k_sumsq_part, dim3(g), dim3(256), 0, s, rows, cols, ld, v, maxbits, part);
+    BNC_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_sumsq_final, dim3(1), dim3(64), 0, s, (int)g, (const double *)part, out);
+    BNC_LAUNCH_CHECK();
+    return BNC_OK;
+}
+
+// ---- the refinement driver -----------------------------------------------------
+
+static inline double bits_to_double(unsigned long long u)
+{
+    double d;
+    memcpy(&d, &u, sizeof d);
+    return d;
+}
+
+struct Scal {
+    unsigned long long amax, xmax, rmax, zmax;
+    double asq, xsq, rsq, pad;
+    int32_t nonfinite, inexact;
+    int64_t info;
+    ExpBounds eb;  // a, x, b
+    int32_t pad2;
+};
+
+struct RefineLayout {
+    size_t lu, ipiv, perm, r, v, rowmax, part, red, scal, getrf, total;
+};
+
+size_t getrf_scratch_bytes(int K);
+
+static RefineLayout refine_layout(int64_t n, int K)
+{
+    RefineLayout L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off += (bytes + 255) / 256 * 256;
+        return at;
+    };
+    L.lu = take((size_t)K * n * n * sizeof(double));
+    L.ipiv = take((size_t)n * sizeof(int64_t));
+    L.perm = take((size_t)n * sizeof(int32_t));
+    L.r = take((size_t)4 * n * sizeof(double));
+    L.v = take((size_t)K * n * sizeof(double));
+    L.rowmax = take((size_t)n * sizeof(double));
+    L.part = take(residual_scratch_bytes(n));
+    L.red = take((size_t)RED_BLOCKS * sizeof(double));
+    L.scal = take(sizeof(Scal));
+    L.getrf = take(getrf_scratch_bytes(K));
+    L.total = off;
+    return L;
+}
+
+size_t refine_workspace_bytes(int64_t n, int K) { return refine_layout(n, K).total; }
+
+template <int K>
+int refine_run(int64_t n, int aw, const double *A, int64_t lda, int64_t ldpa, const double *b, int64_t ldpb, double *x,
+               int64_t ldpx, void *work, const bnc_refine_opts *o, bnc_refine_result *res, hipStream_t s)
+{
+    const RefineLayout L = refine_layout(n, K);
+    char *W = (char *)work;
+    double *LU = (double *)(W + L.lu);
+    int64_t *ipiv = (int64_t *)(W + L.ipiv);
+    int32_t *perm = (int32_t *)(W + L.perm);
+    double *r = (double *)(W + L.r);
+    double *v = (double *)(W + L.v);
+    double *rowmax = (double *)(W + L.rowmax);
+    double *part = (double *)(W + L.part);
+    double *red = (double *)(W + L.red);
+    Scal *sc = (Scal *)(W + L.scal);
+    void *gscr = W + L.getrf;
+    const int64_t ldp = n * n;
+
+    *res = bnc_refine_result{};
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, (uint64_t *)sc, (int64_t)(sizeof(Scal) / 8), (uint64_t)0);
+    BNC_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_check_finite, dim3(grid1(n * n)), dim3(256), 0, s, n, n, aw, A, lda, ldpa, &sc->nonfinite);
+    BNC_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_check_finite, dim3(grid1(n)), dim3(256), 0, s, n, (int64_t)1, 4, b, ldpb, ldpb,
+                       &sc->nonfinite);
+    BNC_LAUNCH_CHECK();
+    Scal h{};
+    BNC_HIP(hipMemcpyAsync(&h, sc, sizeof(Scal), hipMemcpyDeviceToHost, s));
+    BNC_HIP(hipStreamSynchronize(s));
+    auto zero_x = [&]() -> int {
+        for (int w = 0; w < 4; ++w) {
+            hipLaunchKernelGGL(k_zero, dim3(grid1(n)), dim3(256), 0, s, n, x + w * ldpx);
+            BNC_LAUNCH_CHECK();
+        }
+        BNC_HIP(hipStreamSynchronize(s));
+        return BNC_OK;
+    };
+    if (h.nonfinite) {
+        res->status = BNC_NONFINITE;
+        return zero_x();
+    }
+    // ||A||_F from leading words (scaled), row maxima for the residual anchor
+    int rc;
+    if ((rc = absmax_run(n, n, lda, A, &sc->amax, s)) || (rc = sumsq_run(n, n, lda, A, &sc->amax, red, &sc->asq, s)) ||
+        (rc = rowmax_run(n, A, lda, rowmax, s)) || (rc = fill_i32_run(&sc->eb.a, 3, 2000, s)) ||
+        (rc = minexp_run(n, n, lda, aw, ldpa, A, &sc->eb.a, s)) ||
+        (rc = minexp_run(n, 1, n, 4, ldpb, b, &sc->eb.b, s)))
+        return rc;
+    // short-precision copy and factorisation
+    if (aw == 1)
+        hipLaunchKernelGGL((k_stage<K, 1>), dim3(grid1(n * n)), dim3(256), 0, s, n, A, lda, ldpa, LU, n, ldp);
+    else
+        hipLaunchKernelGGL((k_stage<K, 4>), dim3(grid1(n * n)), dim3(256), 0, s, n, A, lda, ldpa, LU, n, ldp);
+    BNC_LAUNCH_CHECK();
+    if ((rc = getrf_run<K>(n, LU, n, ldp, ipiv, &sc->info, gscr, s)))
+        return rc;
+    BNC_HIP(hipMemcpyAsync(&h, sc, sizeof(Scal), hipMemcpyDeviceToHost, s));
+    BNC_HIP(hipStreamSynchronize(s));
+    res->info = h.info;
+    const double amax = bits_to_double(h.amax);
+    res->a_norm = sqrt(h.asq) * ldexp(1.0, norm_exp(amax) + 1);
+    if (h.info) {
+        res->status = BNC_SINGULAR;
+        return zero_x();
+    }
+    if ((rc = ipiv_to_perm(n, ipiv, perm, s)))
+        return rc;
+    // first solution in K words, extended to quad-double
+    hipLaunchKernelGGL((k_round_scaled<K>), dim3(grid1(n)), dim3(256), 0, s, n, b, ldpb,
+                       (const unsigned long long *)nullptr, r, n);
+    BNC_LAUNCH_CHECK();
+    if ((rc = getrs_perm<K>(n, LU, n, ldp, perm, r, n, v, n, s)))
+        return rc;
+    hipLaunchKernelGGL((k_extend<K>), dim3(grid1(n)), dim3(256), 0, s, n, (const double *)v, n, x, ldpx);
+    BNC_LAUNCH_CHECK();
+
+    const double thresh_c = sqrt((double)n) * o->rtol * res->a_norm;
+    bool have_z = false;
+    int iters = 0;
+    int status = BNC_MAX_ITER;
+    for (int it = 0; it <= o->max_iter; ++it) {
+        if ((rc = absmax_run(n, 1, n, x, &sc->xmax, s)) || (rc = fill_i32_run(&sc->eb.x, 1, 2000, s)) ||
+            (rc = minexp_run(n, 1, n, 4, ldpx, x, &sc->eb.x, s)))
+            return rc;
+        if ((rc = residual_run(n, aw, A, lda, ldpa, x, ldpx, b, ldpb, rowmax, (const double *)&sc->xmax, &sc->eb,
+                               part, r, n, &sc->inexact, s)))
+            return rc;
+        if ((rc = absmax_run(n, 1, n, r, &sc->rmax, s)) || (rc = sumsq_run(n, 1, n, r, &sc->rmax, red, &sc->rsq, s)) ||
+            (rc = sumsq_run(n, 1, n, x, &sc->xmax, red, &sc->xsq, s)))
+            return rc;
+        BNC_HIP(hipMemcpyAsync(&h, sc, sizeof(Scal), hipMemcpyDeviceToHost, s));
+        BNC_HIP(hipStreamSynchronize(s));
+        const double rmax = bits_to_double(h.rmax), xmax = bits_to_double(h.xmax);
+        const double zmax = bits_to_double(h.zmax);
+        const double nr = rmax == 0.0 ? 0.0 : sqrt(h.rsq) * ldexp(1.0, norm_exp(rmax) + 1);
+        const double nx = xmax == 0.0 ? 0.0 : sqrt(h.xsq) * ldexp(1.0, norm_exp(xmax) + 1);
+        res->resid_norm = nr;
+        res->x_norm = nx;
+        res->residual_inexact = h.inexact ? 1 : 0;
+        if (nr < thresh_c * nx + o->atol || (have_z && zmax <= o->ctol * xmax)) {
+            status = BNC_CONVERGED;
+            break;
+        }
+        if (iters == o->max_iter)
+            break;
+        // K-word copy of r * 2^-e, correction solve, x <- x + 2^e z
+        hipLaunchKernelGGL((k_round_scaled<K>), dim3(grid1(n)), dim3(256), 0, s, n, (const double *)r, n,
+                           (const unsigned long long *)&sc->rmax, r, n);
+        BNC_LAUNCH_CHECK();
+        if ((rc = getrs_perm<K>(n, LU, n, ldp, perm, r, n, v, n, s)))
+            return rc;
+        hipLaunchKernelGGL((k_scale_update<K>), dim3(grid1(n)), dim3(256), 0, s, n, v, n,
+                           (const unsigned long long *)&sc->rmax, x, ldpx);
+        BNC_LAUNCH_CHECK();
+        if ((rc = absmax_run(n, 1, n, v, &sc->zmax, s)))
+            return rc;
+        have_z = true;
+        ++iters;
+    }
+    res->status = status;
+    res->iters = iters;
+    return BNC_OK;
+}
+
+#define INST(K)                                                                                                    \
+    template int refine_run<K>(int64_t, int, const double *, int64_t, int64_t, const double *, int64_t, double *, \
+                               int64_t, void *, const bnc_refine_opts *, bnc_refine_result *, hipStream_t);
+INST(1)
+INST(2)
+INST(3)
+INST(4)
+#undef INST
+
+}  // namespace bnc

@@ -1,0 +1,46 @@
+"""The C-ABI library loads and exports every entry point include/bnc.h
+declares (no GPU needed: nothing is called)."""
+import ctypes
+import os
+import re
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bnc.h")
+
+
+def declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bnc_\w+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    for k in ("d", "dd", "td", "qd"):
+        assert f"bnc_getrf_{k}" in names and f"bnc_getrs_{k}" in names
+    for n in ("bnc_refine", "bnc_refine_workspace_size", "bnc_residual", "bnc_mw_apply"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2107_12550_amd.bnc import lib_path
+    L = ctypes.CDLL(lib_path)
+    missing = [n for n in declared() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_host_only_entry_points():
+    import paper_2107_12550_amd as P
+    L = P.lib()
+    assert L.bnc_version().decode().startswith("bnc")
+    assert L.bnc_status_string(0) == b"converged"
+    # workspace grows with n and K; invalid arguments give 0
+    assert L.bnc_refine_workspace_size(128, 3) > 3 * 128 * 128 * 8
+    assert L.bnc_refine_workspace_size(0, 3) == 0
+    assert L.bnc_refine_workspace_size(128, 5) == 0
+    # argument errors are reported before anything touches the device
+    rc = L.bnc_getrf_td(-1, None, 1, 1, None, None, None)
+    assert rc == -1
+    rc = L.bnc_getrf_td(8, None, 8, 64, None, None, None)
+    assert rc == -2
+    assert b"NULL" in L.bnc_last_error()
