@@ -3,11 +3,13 @@
 //
 // Per panel of nb columns starting at column j0:
 //   1. k_panel: one cooperative launch factors rows j0..n-1 of the panel.
-//      Each workgroup keeps R panel rows in LDS.  Per column: local argmax
-//      -> candidate row published to global memory -> one grid barrier ->
-//      every workgroup picks the same global pivot, swaps rows in LDS, scales
-//      the column by the pivot reciprocal and updates the rest of its rows.
-//      Workgroup 0 then turns the nb swaps into (dst, src) row pairs.
+//      Each workgroup keeps R <= 64 panel rows in LDS.  Per column: every
+//      workgroup publishes its best candidate row, one grid barrier, every
+//      workgroup picks the same global pivot, swaps rows in LDS, scales the
+//      column by the pivot reciprocal and updates its rows; the next
+//      column is updated and published first so that the barrier overlaps
+//      the rest of the update.  Workgroup 0 then turns the nb swaps into
+//      (dst, src) row pairs.
 //   2. k_laswp_trsm: the same row pairs applied to every column outside the
 //      panel; right of the panel it also solves U12 = L11^-1 A12 (one wave
 //      per column, lanes = panel rows, one broadcast per pivot row).
@@ -17,12 +19,8 @@
 // in the same order (row moves commute with the updates, each entry is
 // updated in increasing k), so the factors equal the unblocked ones bit for
 // bit.
-#include <hip/hip_cooperative_groups.h>
-
 #include "common.hpp"
 #include "mw.hpp"
-
-namespace cg = cooperative_groups;
 
 namespace bnc {
 
@@ -49,24 +47,91 @@ __device__ __forceinline__ bool cand_better(const double (&kb)[K], int64_t rb, c
     return rb < ra;
 }
 
-// LDS tile layout: word w, panel column c, local row r at ((w*jb + c)*R + r)
+// Lane-wise argmax across one wave (xor butterfly); every lane ends with
+// the same (key, row): the largest key, ties to the smallest row.
+template <int K>
+__device__ __forceinline__ void wave_argmax(double (&key)[K], int &row)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        double ok[K];
+#pragma unroll
+        for (int w = 0; w < K; ++w)
+            ok[w] = __shfl_xor(key[w], off, 64);
+        const int orow = __shfl_xor(row, off, 64);
+        if (cand_better<K>(ok, orow, key, row)) {
+#pragma unroll
+            for (int w = 0; w < K; ++w)
+                key[w] = ok[w];
+            row = orow;
+        }
+    }
+}
+
+// Grid barrier on a monotonic counter, split into arrive and wait so that
+// work can overlap the wait.  The spin is bounded: on timeout the workgroup
+// records the failure and every later wait returns at once, so the grid
+// always drains.
+constexpr unsigned SPIN_LIMIT = 1u << 21;
+
+__device__ __forceinline__ void bar_arrive_wave(unsigned *bar)
+{
+    // called by one whole wave after its global stores
+    __threadfence();
+    if ((threadIdx.x & 63) == 0)
+        __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void bar_wait(unsigned *bar, unsigned target, int *abort_flag)
+{
+    if (threadIdx.x == 0) {
+        unsigned spins = 0;
+        while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                break;
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > SPIN_LIMIT) {
+                __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+        }
+    }
+    __syncthreads();
+    __threadfence();
+}
+
+// LDS tile layout: word w, panel column c, local row r at ((w*jb + c)*R + r);
+// R <= 64, so one wave holds one row per lane.
+//
+// Column kk of the panel (global k = j0 + kk), per workgroup:
+//   wait for every workgroup's candidate for column kk
+//   pick the pivot (largest key, smallest row); rebuild the pivot row and
+//   the displaced row k from their published copies, which were taken after
+//   column kk was updated but before columns > kk were: finish those columns
+//   with the previous pivot row, exactly as their owner does
+//   swap, record ipiv, reciprocal of the pivot, scale column kk
+//   wave 0: update column kk+1, find the local candidate for column kk+1,
+//   publish it (and row k+1 if owned), arrive
+//   all waves, after the copies are taken: update columns kk+2.. (overlaps
+//   the other workgroups' arrival)
 template <int K>
 __global__ void __launch_bounds__(PANEL_THREADS)
     k_panel(double *__restrict__ A, int64_t lda, int64_t ldp, int64_t n, int64_t j0, int jb, int R,
             int64_t *__restrict__ ipiv, int64_t *__restrict__ info, double *__restrict__ cand,
-            int64_t *__restrict__ cidx, double *__restrict__ rowk, int64_t *__restrict__ pairs)
+            int64_t *__restrict__ cidx, double *__restrict__ rowk, int64_t *__restrict__ pairs,
+            unsigned *__restrict__ bar, int *__restrict__ abort_flag)
 {
     extern __shared__ double smem[];
-    double *tile = smem;                   // K*jb*R
-    double *prow = tile + (size_t)K * jb * R;  // K*jb   pivot row
-    __shared__ double rk[PANEL_THREADS][K];
-    __shared__ int64_t ri[PANEL_THREADS];
-    __shared__ int s_gw;
+    double *tile = smem;                          // K*jb*R
+    double *prow = tile + (size_t)K * jb * R;     // [2][K*jb] pivot rows of this and the previous column
+    double *orow = prow + 2 * (size_t)K * jb;     // [K*jb]    displaced row k
+    __shared__ int s_p, s_gw;
+    __shared__ int s_piv[PANEL_NB_MAX];
 
-    cg::grid_group grid = cg::this_grid();
     const int P = gridDim.x;
     const int g = blockIdx.x;
     const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
     const int64_t gr0 = j0 + (int64_t)g * R;
     const int nr = (int)((n - gr0) < R ? (n - gr0) : R);
 
@@ -78,177 +143,215 @@ __global__ void __launch_bounds__(PANEL_THREADS)
     }
     __syncthreads();
 
+    // publish this workgroup's candidate for column cc (rows >= j0+cc) and
+    // the row at position j0+cc if owned; wave 0 only
+    auto publish = [&](int cc) {
+        const int b = cc & 1;
+        const int64_t kc = j0 + cc;
+        double key[K];
+        int row = -1;
+        if (lane < nr && gr0 + lane >= kc) {
+            row = (int)(gr0 + lane);
+#pragma unroll
+            for (int w = 0; w < K; ++w)
+                key[w] = tile[(w * jb + cc) * R + lane];
+        } else {
+#pragma unroll
+            for (int w = 0; w < K; ++w)
+                key[w] = 0.0;
+        }
+        wave_argmax<K>(key, row);
+        double *cb = cand + ((size_t)(b * P + g) * K) * jb;
+        if (row >= 0) {
+            const int lr = (int)(row - gr0);
+            for (int e = lane; e < K * jb; e += 64) {
+                const int w = e / jb, c = e % jb;
+                cb[e] = tile[(w * jb + c) * R + lr];
+            }
+        }
+        if (lane == 0)
+            cidx[b * P + g] = row;
+        if (kc >= gr0 && kc < gr0 + nr) {
+            const int lr = (int)(kc - gr0);
+            double *rb = rowk + (size_t)b * K * jb;
+            for (int e = lane; e < K * jb; e += 64) {
+                const int w = e / jb, c = e % jb;
+                rb[e] = tile[(w * jb + c) * R + lr];
+            }
+        }
+        bar_arrive_wave(bar);
+    };
+
+    if (wave == 0)
+        publish(0);
+
+    bool nz_prev = false;
     for (int kk = 0; kk < jb; ++kk) {
         const int64_t k = j0 + kk;
-        const int buf = kk & 1;
-        // ---- local argmax of column kk over owned rows >= k
-        {
-            double v[K];
-            int64_t row = -1;
-            if (tid < nr && gr0 + tid >= k) {
-                row = gr0 + tid;
-#pragma unroll
-                for (int w = 0; w < K; ++w)
-                    v[w] = tile[(w * jb + kk) * R + tid];
-            } else {
-#pragma unroll
-                for (int w = 0; w < K; ++w)
-                    v[w] = 0.0;
-            }
+        const int b = kk & 1;
+        double *pcur = prow + (size_t)b * K * jb;
+        const double *pprev = prow + (size_t)(b ^ 1) * K * jb;
+        bar_wait(bar, (unsigned)(kk + 1) * (unsigned)P, abort_flag);
+        // ---- global pivot (wave 0)
+        if (wave == 0) {
+            double key[K];
+            int row = -1;
 #pragma unroll
             for (int w = 0; w < K; ++w)
-                rk[tid][w] = v[w];
-            ri[tid] = row;
-            __syncthreads();
-            for (int s = PANEL_THREADS / 2; s > 0; s >>= 1) {
-                if (tid < s) {
-                    double a[K], b[K];
-#pragma unroll
-                    for (int w = 0; w < K; ++w) {
-                        a[w] = rk[tid][w];
-                        b[w] = rk[tid + s][w];
-                    }
-                    if (cand_better<K>(b, ri[tid + s], a, ri[tid])) {
-#pragma unroll
-                        for (int w = 0; w < K; ++w)
-                            rk[tid][w] = b[w];
-                        ri[tid] = ri[tid + s];
-                    }
-                }
-                __syncthreads();
-            }
-        }
-        const int64_t lrow = ri[0];
-        // ---- publish the candidate row, and the row now at position k
-        double *cb = cand + ((size_t)(buf * P + g) * K) * jb;
-        if (lrow >= 0) {
-            const int lr = (int)(lrow - gr0);
-            for (int e = tid; e < K * jb; e += PANEL_THREADS) {
-                const int w = e / jb, c = e % jb;
-                cb[w * jb + c] = tile[(w * jb + c) * R + lr];
-            }
-        }
-        if (tid == 0)
-            cidx[buf * P + g] = lrow;
-        if (k >= gr0 && k < gr0 + nr) {
-            const int lr = (int)(k - gr0);
-            double *rb = rowk + (size_t)buf * K * jb;
-            for (int e = tid; e < K * jb; e += PANEL_THREADS) {
-                const int w = e / jb, c = e % jb;
-                rb[w * jb + c] = tile[(w * jb + c) * R + lr];
-            }
-        }
-        grid.sync();
-        // ---- global pivot: same reduction in every workgroup
-        {
-            double v[K];
-            int64_t row = -1;
-            if (tid < P) {
-                row = cidx[buf * P + tid];
-                const double *cc = cand + ((size_t)(buf * P + tid) * K) * jb;
+                key[w] = 0.0;
+            for (int t = lane; t < P; t += 64) {
+                const int rr = (int)cidx[b * P + t];
+                double kv[K];
+                const double *cc = cand + ((size_t)(b * P + t) * K) * jb;
 #pragma unroll
                 for (int w = 0; w < K; ++w)
-                    v[w] = row >= 0 ? cc[w * jb + kk] : 0.0;
-            } else {
+                    kv[w] = rr >= 0 ? cc[w * jb + kk] : 0.0;
+                if (cand_better<K>(kv, rr, key, row)) {
 #pragma unroll
-                for (int w = 0; w < K; ++w)
-                    v[w] = 0.0;
-            }
-#pragma unroll
-            for (int w = 0; w < K; ++w)
-                rk[tid][w] = v[w];
-            ri[tid] = row;
-            // remember which workgroup owns each candidate: encode in the order
-            __syncthreads();
-            for (int s = PANEL_THREADS / 2; s > 0; s >>= 1) {
-                if (tid < s) {
-                    double a[K], b[K];
-#pragma unroll
-                    for (int w = 0; w < K; ++w) {
-                        a[w] = rk[tid][w];
-                        b[w] = rk[tid + s][w];
-                    }
-                    if (cand_better<K>(b, ri[tid + s], a, ri[tid])) {
-#pragma unroll
-                        for (int w = 0; w < K; ++w)
-                            rk[tid][w] = b[w];
-                        ri[tid] = ri[tid + s];
-                    }
+                    for (int w = 0; w < K; ++w)
+                        key[w] = kv[w];
+                    row = rr;
                 }
-                __syncthreads();
             }
-            if (tid == 0)
-                s_gw = (int)((ri[0] - j0) / R);  // owner of the pivot row
-            __syncthreads();
-        }
-        const int64_t p = ri[0];
-        const int gw = s_gw;
-        {
-            const double *cc = cand + ((size_t)(buf * P + gw) * K) * jb;
-            for (int e = tid; e < K * jb; e += PANEL_THREADS)
-                prow[e] = cc[e];
+            wave_argmax<K>(key, row);
+            if (lane == 0) {
+                s_p = row;
+                s_gw = (int)((row - j0) / R);
+            }
         }
         __syncthreads();
-        // ---- row interchange k <-> p inside the LDS tiles
+        const int64_t p = s_p;
+        const int gw = s_gw;
+        // ---- rebuild the pivot row (and the displaced row k for p's owner)
+        {
+            const double *cc = cand + ((size_t)(b * P + gw) * K) * jb;
+            const double *rb = rowk + (size_t)b * K * jb;
+            const bool need_o = p != k && p >= gr0 && p < gr0 + nr;
+            for (int c = tid; c < jb; c += PANEL_THREADS) {
+                double v[K], o[K];
+#pragma unroll
+                for (int w = 0; w < K; ++w)
+                    v[w] = cc[w * jb + c];
+                if (nz_prev && c > kk) {
+                    double l[K], u[K];
+#pragma unroll
+                    for (int w = 0; w < K; ++w) {
+                        l[w] = cc[w * jb + kk - 1];
+                        u[w] = pprev[w * jb + c];
+                    }
+                    fms<K>(v, l, u, o);
+#pragma unroll
+                    for (int w = 0; w < K; ++w)
+                        v[w] = o[w];
+                }
+#pragma unroll
+                for (int w = 0; w < K; ++w)
+                    pcur[w * jb + c] = v[w];
+                if (need_o) {
+#pragma unroll
+                    for (int w = 0; w < K; ++w)
+                        v[w] = rb[w * jb + c];
+                    if (nz_prev && c > kk) {
+                        double l[K], u[K];
+#pragma unroll
+                        for (int w = 0; w < K; ++w) {
+                            l[w] = rb[w * jb + kk - 1];
+                            u[w] = pprev[w * jb + c];
+                        }
+                        fms<K>(v, l, u, o);
+#pragma unroll
+                        for (int w = 0; w < K; ++w)
+                            v[w] = o[w];
+                    }
+#pragma unroll
+                    for (int w = 0; w < K; ++w)
+                        orow[w * jb + c] = v[w];
+                }
+            }
+        }
+        __syncthreads();
+        // ---- row interchange k <-> p inside the tiles
         if (k >= gr0 && k < gr0 + nr) {
             const int lr = (int)(k - gr0);
             for (int e = tid; e < K * jb; e += PANEL_THREADS) {
                 const int w = e / jb, c = e % jb;
-                tile[(w * jb + c) * R + lr] = prow[w * jb + c];
+                tile[(w * jb + c) * R + lr] = pcur[w * jb + c];
             }
         }
         if (p != k && p >= gr0 && p < gr0 + nr) {
             const int lr = (int)(p - gr0);
-            const double *rb = rowk + (size_t)buf * K * jb;
             for (int e = tid; e < K * jb; e += PANEL_THREADS) {
                 const int w = e / jb, c = e % jb;
-                tile[(w * jb + c) * R + lr] = rb[w * jb + c];
+                tile[(w * jb + c) * R + lr] = orow[w * jb + c];
             }
         }
-        if (g == 0 && tid == 0)
-            ipiv[k] = p;
-        __syncthreads();
+        if (tid == 0) {
+            s_piv[kk] = (int)p;
+            if (g == 0)
+                ipiv[k] = p;
+        }
         double pv[K];
 #pragma unroll
         for (int w = 0; w < K; ++w)
-            pv[w] = prow[w * jb + kk];
-        if (is_zero<K>(pv)) {
-            if (g == 0 && tid == 0 && *info == 0)
-                *info = k + 1;
-            continue;  // the whole column below is zero: nothing to eliminate
-        }
-        double rcp[K];
-        recip<K>(pv, rcp);
-        // ---- multipliers l_ik = a_ik * (1 / a_kk)
-        if (tid < nr && gr0 + tid > k) {
-            double a[K], l[K];
+            pv[w] = pcur[w * jb + kk];
+        const bool nz = !is_zero<K>(pv);
+        if (!nz && g == 0 && tid == 0 && *info == 0)
+            *info = k + 1;
+        __syncthreads();
+        // ---- multipliers l_ik = a_ik * (1/a_kk), rows > k (wave 0, lane = row)
+        if (nz && wave == 0 && lane < nr && gr0 + lane > k) {
+            double rcp[K], a[K], l[K];
+            recip<K>(pv, rcp);
 #pragma unroll
             for (int w = 0; w < K; ++w)
-                a[w] = tile[(w * jb + kk) * R + tid];
+                a[w] = tile[(w * jb + kk) * R + lane];
             mul<K>(a, rcp, l);
 #pragma unroll
             for (int w = 0; w < K; ++w)
-                tile[(w * jb + kk) * R + tid] = l[w];
+                tile[(w * jb + kk) * R + lane] = l[w];
         }
         __syncthreads();
-        // ---- a_ij <- a_ij - l_ik u_kj for the rest of the panel row
-        const int ncol = jb - kk - 1;
-        for (int e = tid; e < nr * ncol; e += PANEL_THREADS) {
-            const int r = e % nr, c = kk + 1 + e / nr;
-            if (gr0 + r > k) {
+        // ---- wave 0: column kk+1 first, then the next candidate
+        if (wave == 0 && kk + 1 < jb) {
+            if (nz && lane < nr && gr0 + lane > k) {
                 double a[K], l[K], u[K], o[K];
 #pragma unroll
                 for (int w = 0; w < K; ++w) {
-                    a[w] = tile[(w * jb + c) * R + r];
-                    l[w] = tile[(w * jb + kk) * R + r];
-                    u[w] = prow[w * jb + c];
+                    a[w] = tile[(w * jb + kk + 1) * R + lane];
+                    l[w] = tile[(w * jb + kk) * R + lane];
+                    u[w] = pcur[w * jb + kk + 1];
                 }
                 fms<K>(a, l, u, o);
 #pragma unroll
                 for (int w = 0; w < K; ++w)
-                    tile[(w * jb + c) * R + r] = o[w];
+                    tile[(w * jb + kk + 1) * R + lane] = o[w];
+            }
+            publish(kk + 1);
+        }
+        // the published copies must be taken before columns kk+2.. change
+        __syncthreads();
+        // ---- columns kk+2.. for rows > k (all waves; overlaps the other
+        //      workgroups' arrival at the barrier)
+        if (nz) {
+            const int ncol = jb - kk - 2;
+            for (int e = tid; e < nr * ncol; e += PANEL_THREADS) {
+                const int r = e % nr, c = kk + 2 + e / nr;
+                if (gr0 + r > k) {
+                    double a[K], l[K], u[K], o[K];
+#pragma unroll
+                    for (int w = 0; w < K; ++w) {
+                        a[w] = tile[(w * jb + c) * R + r];
+                        l[w] = tile[(w * jb + kk) * R + r];
+                        u[w] = pcur[w * jb + c];
+                    }
+                    fms<K>(a, l, u, o);
+#pragma unroll
+                    for (int w = 0; w < K; ++w)
+                        tile[(w * jb + c) * R + r] = o[w];
+                }
             }
         }
+        nz_prev = nz;
         __syncthreads();
     }
 
@@ -260,18 +363,18 @@ __global__ void __launch_bounds__(PANEL_THREADS)
                 A[w * ldp + (j0 + c) * lda + gr0 + r] = tile[(w * jb + c) * R + r];
         }
     }
+    if (g == 0 && tid == 0 && __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        *info = -1;
 
     // ---- net row permutation of the nb swaps, as (dst, src) pairs:
     //      after the swaps, row dst holds the original row src.
     //      Lane l tracks block position j0+l and one outside slot.
-    if (g == 0 && tid < 64) {
-        __threadfence_block();
-        const int lane = tid;
+    if (g == 0 && wave == 0) {
         int64_t in_c = j0 + lane;
         int64_t out_pos = -1, out_c = -1;
         int nout = 0;
         for (int q = 0; q < jb; ++q) {
-            const int64_t pq = ipiv[j0 + q];
+            const int64_t pq = s_piv[q];
             if (pq == j0 + q)
                 continue;
             const int64_t ck = __shfl(in_c, q, 64);
@@ -497,7 +600,7 @@ size_t getrf_scratch_bytes(int K)
     const size_t cidx = 2ull * PANEL_WG_MAX * sizeof(int64_t);
     const size_t rowk = 2ull * K * PANEL_NB_MAX * sizeof(double);
     const size_t pairs = 4ull * PANEL_NB_MAX * sizeof(int64_t);
-    return cand + cidx + rowk + pairs + 4 * 256;
+    return cand + cidx + rowk + pairs + 4 * 256 + 256;
 }
 
 __global__ void k_zero_i64(int64_t *p)
@@ -506,7 +609,19 @@ __global__ void k_zero_i64(int64_t *p)
         *p = 0;
 }
 
-static size_t panel_lds_bytes(int K, int jb, int R) { return ((size_t)K * jb * R + (size_t)K * jb) * sizeof(double); }
+static size_t panel_lds_bytes(int K, int jb, int R)
+{
+    return ((size_t)K * jb * R + 3 * (size_t)K * jb) * sizeof(double);
+}
+
+// reset the grid-barrier counter and abort flag of one panel launch
+__global__ void k_bar_reset(unsigned *bar, int *abort_flag)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        *bar = 0;
+        *abort_flag = 0;
+    }
+}
 
 template <int K>
 int getrf_run(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int64_t *info, void *scr,
@@ -523,13 +638,16 @@ int getrf_run(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int
     double *rowk = (double *)base;
     base += 2ull * K * PANEL_NB_MAX * sizeof(double);
     int64_t *pairs = (int64_t *)base;
+    base += 4ull * PANEL_NB_MAX * sizeof(int64_t);
+    unsigned *bar = (unsigned *)base;
+    int *abort_flag = (int *)(base + 64);
 
     int dev = 0;
     BNC_HIP(hipGetDevice(&dev));
     int ncu = 0, lds_max = 0;
     BNC_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     BNC_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    const size_t lds_static = PANEL_THREADS * (K * sizeof(double) + sizeof(int64_t)) + 64;
+    const size_t lds_static = 512;
 
     hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(64), 0, s, info);
     BNC_LAUNCH_CHECK();
@@ -555,7 +673,11 @@ int getrf_run(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int
             return fail_arg(BNC_ERR_UNSUPPORTED, "getrf: panel needs more workgroups than can be co-resident");
         int64_t j0v = j0, nv = n;
         int jbv = jb, Rv = R;
-        void *args[] = {&A, &lda, &ldp, &nv, &j0v, &jbv, &Rv, &ipiv, &info, &cand, &cidx, &rowk, &pairs};
+        void *args[] = {&A, &lda, &ldp, &nv, &j0v, &jbv, &Rv, &ipiv, &info, &cand, &cidx, &rowk, &pairs, &bar,
+                        &abort_flag};
+        hipLaunchKernelGGL(k_bar_reset, dim3(1), dim3(64), 0, s, bar, abort_flag);
+        BNC_LAUNCH_CHECK();
+        // cooperative launch: guarantees that all P workgroups are resident
         BNC_HIP(hipLaunchCooperativeKernel(kfn, dim3(P), dim3(PANEL_THREADS), args, (unsigned)lds, s));
         if (j0 > 0) {
             hipLaunchKernelGGL((k_laswp_trsm<K, false>), dim3((unsigned)j0), dim3(64), 0, s, A, lda, ldp, j0, jb,

@@ -24,8 +24,10 @@ template <int K>
 int getrf_run(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int64_t *info, void *scr,
               hipStream_t s);
 template <int K>
-int getrs_perm(int64_t n, const double *LU, int64_t lda, int64_t ldp, const int32_t *perm, const double *b,
-               int64_t ldb, double *y, int64_t ldy, hipStream_t s);
+int getrs_perm(int64_t n, const double *LU, int64_t lda, int64_t ldp, const int32_t *perm, const double *rd,
+               const double *b, int64_t ldb, double *y, int64_t ldy, hipStream_t s);
+template <int K>
+int diag_recip_run(int64_t n, const double *LU, int64_t lda, int64_t ldp, double *rd, hipStream_t s);
 int ipiv_to_perm(int64_t n, const int64_t *ipiv, int32_t *perm, hipStream_t s);
 
 constexpr int RB_W = 34;
@@ -656,7 +658,7 @@ struct Scal {
 };
 
 struct RefineLayout {
-    size_t lu, ipiv, perm, r, v, rowmax, part, red, scal, getrf, total;
+    size_t lu, ipiv, perm, rd, r, v, rowmax, part, red, scal, getrf, total;
 };
 
 size_t getrf_scratch_bytes(int K);
@@ -673,6 +675,7 @@ static RefineLayout refine_layout(int64_t n, int K)
     L.lu = take((size_t)K * n * n * sizeof(double));
     L.ipiv = take((size_t)n * sizeof(int64_t));
     L.perm = take((size_t)n * sizeof(int32_t));
+    L.rd = take((size_t)K * n * sizeof(double));
     L.r = take((size_t)4 * n * sizeof(double));
     L.v = take((size_t)K * n * sizeof(double));
     L.rowmax = take((size_t)n * sizeof(double));
@@ -695,6 +698,7 @@ int refine_run(int64_t n, int aw, const double *A, int64_t lda, int64_t ldpa, co
     double *LU = (double *)(W + L.lu);
     int64_t *ipiv = (int64_t *)(W + L.ipiv);
     int32_t *perm = (int32_t *)(W + L.perm);
+    double *rd = (double *)(W + L.rd);
     double *r = (double *)(W + L.r);
     double *v = (double *)(W + L.v);
     double *rowmax = (double *)(W + L.rowmax);
@@ -751,13 +755,13 @@ int refine_run(int64_t n, int aw, const double *A, int64_t lda, int64_t ldpa, co
         res->status = BNC_SINGULAR;
         return zero_x();
     }
-    if ((rc = ipiv_to_perm(n, ipiv, perm, s)))
+    if ((rc = ipiv_to_perm(n, ipiv, perm, s)) || (rc = diag_recip_run<K>(n, LU, n, ldp, rd, s)))
         return rc;
     // first solution in K words, extended to quad-double
     hipLaunchKernelGGL((k_round_scaled<K>), dim3(grid1(n)), dim3(256), 0, s, n, b, ldpb,
                        (const unsigned long long *)nullptr, r, n);
     BNC_LAUNCH_CHECK();
-    if ((rc = getrs_perm<K>(n, LU, n, ldp, perm, r, n, v, n, s)))
+    if ((rc = getrs_perm<K>(n, LU, n, ldp, perm, rd, r, n, v, n, s)))
         return rc;
     hipLaunchKernelGGL((k_extend<K>), dim3(grid1(n)), dim3(256), 0, s, n, (const double *)v, n, x, ldpx);
     BNC_LAUNCH_CHECK();
@@ -795,7 +799,7 @@ int refine_run(int64_t n, int aw, const double *A, int64_t lda, int64_t ldpa, co
         hipLaunchKernelGGL((k_round_scaled<K>), dim3(grid1(n)), dim3(256), 0, s, n, (const double *)r, n,
                            (const unsigned long long *)&sc->rmax, r, n);
         BNC_LAUNCH_CHECK();
-        if ((rc = getrs_perm<K>(n, LU, n, ldp, perm, r, n, v, n, s)))
+        if ((rc = getrs_perm<K>(n, LU, n, ldp, perm, rd, r, n, v, n, s)))
             return rc;
         hipLaunchKernelGGL((k_scale_update<K>), dim3(grid1(n)), dim3(256), 0, s, n, v, n,
                            (const unsigned long long *)&sc->rmax, x, ldpx);
