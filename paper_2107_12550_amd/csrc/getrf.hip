@@ -572,6 +572,12 @@ __global__ void __launch_bounds__(UPD_THREADS)
         }
 }
 
+// thin variant for the look-ahead columns (n x 64 blocks): more workgroups
+template <int K>
+struct UpdCfgThin {
+    static constexpr int BM = 64, BN = 16, TM = 4, TN = 1, KB = 16;
+};
+
 template <int K>
 struct UpdCfg;
 template <>
@@ -599,7 +605,7 @@ size_t getrf_scratch_bytes(int K)
     const size_t cand = 2ull * PANEL_WG_MAX * K * PANEL_NB_MAX * sizeof(double);
     const size_t cidx = 2ull * PANEL_WG_MAX * sizeof(int64_t);
     const size_t rowk = 2ull * K * PANEL_NB_MAX * sizeof(double);
-    const size_t pairs = 4ull * PANEL_NB_MAX * sizeof(int64_t);
+    const size_t pairs = 8ull * PANEL_NB_MAX * sizeof(int64_t);  // two panels' pairs
     return cand + cidx + rowk + pairs + 4 * 256 + 256;
 }
 
@@ -623,6 +629,32 @@ __global__ void k_bar_reset(unsigned *bar, int *abort_flag)
     }
 }
 
+// Side stream and two events per device for the look-ahead: the next panel
+// runs on the side stream while the rest of the trailing update runs on the
+// caller's stream.  Default priority, created once.
+namespace {
+struct LookAhead {
+    hipStream_t side = nullptr;
+    hipEvent_t ready = nullptr, done = nullptr;
+};
+LookAhead g_la[16];
+}  // namespace
+
+static int lookahead_get(LookAhead *&la)
+{
+    int dev = 0;
+    BNC_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 16)
+        return fail_arg(BNC_ERR_UNSUPPORTED, "getrf: device index out of range");
+    la = &g_la[dev];
+    if (!la->side) {
+        BNC_HIP(hipStreamCreateWithFlags(&la->side, hipStreamNonBlocking));
+        BNC_HIP(hipEventCreateWithFlags(&la->ready, hipEventDisableTiming));
+        BNC_HIP(hipEventCreateWithFlags(&la->done, hipEventDisableTiming));
+    }
+    return BNC_OK;
+}
+
 template <int K>
 int getrf_run(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int64_t *info, void *scr,
               hipStream_t s)
@@ -637,8 +669,8 @@ int getrf_run(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int
     base += 2ull * PANEL_WG_MAX * sizeof(int64_t);
     double *rowk = (double *)base;
     base += 2ull * K * PANEL_NB_MAX * sizeof(double);
-    int64_t *pairs = (int64_t *)base;
-    base += 4ull * PANEL_NB_MAX * sizeof(int64_t);
+    int64_t *pairs[2] = {(int64_t *)base, (int64_t *)base + 4 * PANEL_NB_MAX};
+    base += 8ull * PANEL_NB_MAX * sizeof(int64_t);
     unsigned *bar = (unsigned *)base;
     int *abort_flag = (int *)(base + 64);
 
@@ -648,56 +680,102 @@ int getrf_run(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int
     BNC_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     BNC_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     const size_t lds_static = 512;
+    LookAhead *la = nullptr;
+    int rc = lookahead_get(la);
+    if (rc)
+        return rc;
 
-    hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(64), 0, s, info);
-    BNC_LAUNCH_CHECK();
-    for (int64_t j0 = 0; j0 < n; j0 += nb) {
-        const int jb = (int)((n - j0) < nb ? (n - j0) : nb);
-        const int64_t m = n - j0;
-        // rows per workgroup: 64 when the LDS allows, fewer otherwise; the
-        // grid must fit in one cooperative wave of workgroups
+    // one panel: rows pj0..n-1, columns pj0..pj0+pjb-1
+    auto panel = [&](int64_t pj0, int pjb, int64_t *pr, hipStream_t st) -> int {
+        const int64_t m = n - pj0;
         void *kfn = (void *)k_panel<K>;
         int R = 64;
-        while (R > 8 && panel_lds_bytes(K, jb, R) + lds_static > (size_t)lds_max)
+        while (R > 8 && panel_lds_bytes(K, pjb, R) + lds_static > (size_t)lds_max)
             R /= 2;
-        const size_t lds = panel_lds_bytes(K, jb, R);
+        const size_t lds = panel_lds_bytes(K, pjb, R);
         if (lds + lds_static > (size_t)lds_max)
             return fail_arg(BNC_ERR_UNSUPPORTED, "getrf: panel does not fit in LDS");
         if (hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
             (void)hipGetLastError();
         int per_cu = 0;
         BNC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, PANEL_THREADS, lds));
-        const int64_t coop_max = (int64_t)per_cu * ncu < PANEL_WG_MAX ? (int64_t)per_cu * ncu : PANEL_WG_MAX;
+        int64_t cap = (int64_t)per_cu * ncu;
+        if (cap > PANEL_WG_MAX)
+            cap = PANEL_WG_MAX;
         const int P = (int)ceil_div(m, R);
-        if (P > coop_max)
+        if (P > cap)
             return fail_arg(BNC_ERR_UNSUPPORTED, "getrf: panel needs more workgroups than can be co-resident");
-        int64_t j0v = j0, nv = n;
-        int jbv = jb, Rv = R;
-        void *args[] = {&A, &lda, &ldp, &nv, &j0v, &jbv, &Rv, &ipiv, &info, &cand, &cidx, &rowk, &pairs, &bar,
-                        &abort_flag};
-        hipLaunchKernelGGL(k_bar_reset, dim3(1), dim3(64), 0, s, bar, abort_flag);
+        hipLaunchKernelGGL(k_bar_reset, dim3(1), dim3(64), 0, st, bar, abort_flag);
         BNC_LAUNCH_CHECK();
-        // cooperative launch: guarantees that all P workgroups are resident
-        BNC_HIP(hipLaunchCooperativeKernel(kfn, dim3(P), dim3(PANEL_THREADS), args, (unsigned)lds, s));
-        if (j0 > 0) {
-            hipLaunchKernelGGL((k_laswp_trsm<K, false>), dim3((unsigned)j0), dim3(64), 0, s, A, lda, ldp, j0, jb,
-                               (int64_t)0, (const int64_t *)pairs);
-            BNC_LAUNCH_CHECK();
-        }
-        const int64_t c0 = j0 + jb;
-        if (c0 < n) {
-            hipLaunchKernelGGL((k_laswp_trsm<K, true>), dim3((unsigned)(n - c0)), dim3(64), 0, s, A, lda, ldp, j0,
-                               jb, c0, (const int64_t *)pairs);
-            BNC_LAUNCH_CHECK();
-            using C = UpdCfg<K>;
-            const int64_t mm = n - c0;
-            dim3 grid((unsigned)ceil_div(mm, C::BM), (unsigned)ceil_div(mm, C::BN));
-            const int ev = UpdateTimer::begin(s);
+        // All P workgroups fit on the device at once (checked above); the
+        // grid barrier inside the kernel has a bounded spin, so a workgroup
+        // that starts late (the other stream's kernels still hold CUs) only
+        // delays the panel.
+        hipLaunchKernelGGL((k_panel<K>), dim3(P), dim3(PANEL_THREADS), lds, st, A, lda, ldp, n, pj0, pjb, R, ipiv,
+                           info, cand, cidx, rowk, pr, bar, abort_flag);
+        BNC_LAUNCH_CHECK();
+        return BNC_OK;
+    };
+    auto swaps = [&](int64_t j0, int jb, int64_t c0, int64_t nc, const int64_t *pr, bool trsm) -> int {
+        if (nc <= 0)
+            return BNC_OK;
+        if (trsm)
+            hipLaunchKernelGGL((k_laswp_trsm<K, true>), dim3((unsigned)nc), dim3(64), 0, s, A, lda, ldp, j0, jb, c0,
+                               pr);
+        else
+            hipLaunchKernelGGL((k_laswp_trsm<K, false>), dim3((unsigned)nc), dim3(64), 0, s, A, lda, ldp, j0, jb,
+                               c0, pr);
+        BNC_LAUNCH_CHECK();
+        return BNC_OK;
+    };
+    // A[r0.., c0..c0+nc) -= L21 (columns j0..j0+jb) * U12
+    auto update = [&](int64_t r0, int64_t c0, int64_t m, int64_t nc, int64_t j0, int jb, bool thin) -> int {
+        if (m <= 0 || nc <= 0)
+            return BNC_OK;
+        const int ev = UpdateTimer::begin(s);
+        if (thin) {
+            using C = UpdCfgThin<K>;
+            dim3 grid((unsigned)ceil_div(m, C::BM), (unsigned)ceil_div(nc, C::BN));
             hipLaunchKernelGGL((k_update<K, C::BM, C::BN, C::TM, C::TN, C::KB>), grid, dim3(UPD_THREADS), 0, s, A,
-                               lda, ldp, c0, c0, mm, mm, j0, jb);
-            BNC_LAUNCH_CHECK();
-            UpdateTimer::end(ev, s, (double)mm * (double)mm * (double)jb * fms_flops(K));
+                               lda, ldp, r0, c0, m, nc, j0, jb);
+        } else {
+            using C = UpdCfg<K>;
+            dim3 grid((unsigned)ceil_div(m, C::BM), (unsigned)ceil_div(nc, C::BN));
+            hipLaunchKernelGGL((k_update<K, C::BM, C::BN, C::TM, C::TN, C::KB>), grid, dim3(UPD_THREADS), 0, s, A,
+                               lda, ldp, r0, c0, m, nc, j0, jb);
         }
+        BNC_LAUNCH_CHECK();
+        UpdateTimer::end(ev, s, (double)m * (double)nc * (double)jb * fms_flops(K));
+        return BNC_OK;
+    };
+
+    hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(64), 0, s, info);
+    BNC_LAUNCH_CHECK();
+    if ((rc = panel(0, (int)(n < nb ? n : nb), pairs[0], s)))
+        return rc;
+    int J = 0;
+    for (int64_t j0 = 0; j0 < n; j0 += nb, ++J) {
+        const int jb = (int)((n - j0) < nb ? (n - j0) : nb);
+        const int64_t *pr = pairs[J & 1];
+        if ((rc = swaps(j0, jb, 0, j0, pr, false)))
+            return rc;
+        const int64_t cn = j0 + jb;
+        if (cn >= n)
+            break;
+        const int nbn = (int)((n - cn) < nb ? (n - cn) : nb);
+        // look-ahead: the next panel's columns first
+        if ((rc = swaps(j0, jb, cn, nbn, pr, true)) || (rc = update(cn, cn, n - cn, nbn, j0, jb, true)))
+            return rc;
+        BNC_HIP(hipEventRecord(la->ready, s));
+        BNC_HIP(hipStreamWaitEvent(la->side, la->ready, 0));
+        if ((rc = panel(cn, nbn, pairs[(J + 1) & 1], la->side)))
+            return rc;
+        BNC_HIP(hipEventRecord(la->done, la->side));
+        // the rest of the trailing matrix, concurrently with that panel
+        const int64_t cr = cn + nbn;
+        if ((rc = swaps(j0, jb, cr, n - cr, pr, true)) || (rc = update(cn, cr, n - cn, n - cr, j0, jb, false)))
+            return rc;
+        BNC_HIP(hipStreamWaitEvent(s, la->done, 0));
     }
     return BNC_OK;
 }
