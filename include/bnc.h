@@ -52,6 +52,7 @@ extern "C" {
 #define BNC_MAX_ITER 1  /* max_iter corrections applied, no test passed */
 #define BNC_SINGULAR 2  /* exactly zero pivot met: no solve was attempted */
 #define BNC_NONFINITE 3 /* NaN or Inf in A or b: nothing was factorised */
+#define BNC_BAD_SIZE 4  /* batched solve: order outside 1..256 */
 
 /*
  * LU decomposition with partial pivoting, in place: P A = L U (Kouya 2021,
@@ -140,6 +141,62 @@ size_t bnc_refine_workspace_size(int64_t n, int32_t factor_words);
 int bnc_refine(int64_t n, int32_t a_words, const double *A, int64_t lda, int64_t ldpa, const double *b,
                int64_t ldpb, double *x, int64_t ldpx, void *work, size_t work_bytes, const bnc_refine_opts *opts,
                bnc_refine_result *result, void *stream);
+
+/* Outcome of one system of a batched solve (device struct). */
+typedef struct bnc_batch_result {
+    int32_t status;           /* BNC_CONVERGED ... BNC_BAD_SIZE */
+    int32_t iters;            /* corrections applied */
+    int64_t info;             /* getrf info */
+    uint64_t t_start, t_end;  /* device wall-clock ticks (bnc_wall_clock_khz) */
+    int32_t residual_inexact;
+    int32_t reserved;
+} bnc_batch_result;
+
+/* Workspace bytes of bnc_refine_batched for K = factor_words and `slots`
+ * persistent workgroups (0 = the default) (host). */
+size_t bnc_refine_batched_workspace_size(int32_t factor_words, int32_t slots);
+
+/* The default number of persistent workgroups for K = factor_words on the
+ * current device: resident workgroups per compute unit (from the kernel's
+ * LDS and register use) times the compute units.  Negative on bad K. */
+int32_t bnc_refine_batched_default_slots(int32_t factor_words);
+
+/*
+ * Batched mixed-precision iterative refinement: bnc_refine (Kouya 2021,
+ * Sec. 2, Listing 1) on `count` independent systems of order 1..256 in one
+ * persistent launch.  Each system's x, status and corrections equal those of
+ * bnc_refine on that system alone, bit for bit.
+ *   count      number of systems
+ *   n          device int64[count]: orders
+ *   A, b, x    device arrays of device pointers: A[s] binary64 n x n
+ *              column-major (lda = n); b[s], x[s] 4-plane vectors (ldv = n)
+ *   order      device int32[count] giving the order systems are taken in
+ *              (NULL: 0..count-1); largest first balances the load
+ *   work       >= bnc_refine_batched_workspace_size(K, slots) bytes
+ *   opts       host options (as bnc_refine)
+ *   slots      persistent workgroups (0 = default)
+ *   results    device bnc_batch_result[count]
+ * Asynchronous on stream.  A system of order outside 1..256 gets BNC_BAD_SIZE.
+ */
+int bnc_refine_batched(int64_t count, const int64_t *n, const double *const *A, const double *const *b,
+                       double *const *x, const int32_t *order, void *work, size_t work_bytes,
+                       const bnc_refine_opts *opts, int32_t slots, bnc_batch_result *results, void *stream);
+
+/*
+ * Same launch captured once into a HIP graph and replayed: when *graph_exec
+ * is NULL the call captures bnc_refine_batched on `stream` (same arguments),
+ * instantiates the graph, stores it in *graph_exec and launches it; later
+ * calls with that handle only launch it (the arguments are those captured).
+ * Free the handle with bnc_graph_destroy.
+ */
+int bnc_refine_batched_graph(int64_t count, const int64_t *n, const double *const *A, const double *const *b,
+                             double *const *x, const int32_t *order, void *work, size_t work_bytes,
+                             const bnc_refine_opts *opts, int32_t slots, bnc_batch_result *results, void *stream,
+                             void **graph_exec);
+int bnc_graph_destroy(void *graph_exec);
+
+/* Tick rate of the device wall clock used by bnc_batch_result, in kHz. */
+int64_t bnc_wall_clock_khz(void);
 
 /*
  * r = b - A x computed exactly and rounded once to canonical quad-double

@@ -7,6 +7,7 @@ Every step runs in the HIP kernels of ``libbnc.so`` behind the C-ABI of
 device memory and the current stream.
 """
 from .bnc import (  # noqa: F401
+    BNC_BAD_SIZE,
     BNC_CONVERGED,
     BNC_MAX_ITER,
     BNC_NONFINITE,
@@ -16,6 +17,7 @@ from .bnc import (  # noqa: F401
     OP_MUL,
     OP_RECIP,
     OP_ROUND4,
+    BatchSolver,
     BncError,
     getrf,
     getrs,
@@ -27,4 +29,5 @@ from .bnc import (  # noqa: F401
     refine,
     refine_workspace_size,
     residual,
+    wall_clock_khz,
 )

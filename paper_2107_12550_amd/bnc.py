@@ -16,7 +16,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 lib_path = os.path.join(_HERE, "libbnc.so")
 
-BNC_CONVERGED, BNC_MAX_ITER, BNC_SINGULAR, BNC_NONFINITE = 0, 1, 2, 3
+BNC_CONVERGED, BNC_MAX_ITER, BNC_SINGULAR, BNC_NONFINITE, BNC_BAD_SIZE = 0, 1, 2, 3, 4
 OP_FMS, OP_MUL, OP_ADD, OP_RECIP, OP_ROUND4 = 0, 1, 2, 3, 4
 _SUFFIX = {1: "d", 2: "dd", 3: "td", 4: "qd"}
 
@@ -34,6 +34,12 @@ class RefineResult(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("info", ctypes.c_int64),
                 ("resid_norm", ctypes.c_double), ("x_norm", ctypes.c_double), ("a_norm", ctypes.c_double),
                 ("residual_inexact", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class BatchResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("info", ctypes.c_int64),
+                ("t_start", ctypes.c_uint64), ("t_end", ctypes.c_uint64), ("residual_inexact", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 def _load() -> ctypes.CDLL:
@@ -54,6 +60,18 @@ def _load() -> ctypes.CDLL:
     L.bnc_refine.argtypes = [I64, I32, VP, I64, I64, VP, I64, VP, I64, VP, ctypes.c_size_t,
                              ctypes.POINTER(RefineOpts), ctypes.POINTER(RefineResult), VP]
     L.bnc_refine.restype = ctypes.c_int
+    L.bnc_refine_batched_workspace_size.argtypes = [I32, I32]
+    L.bnc_refine_batched_workspace_size.restype = ctypes.c_size_t
+    L.bnc_refine_batched_default_slots.argtypes = [I32]
+    L.bnc_refine_batched_default_slots.restype = I32
+    L.bnc_refine_batched.argtypes = [I64, VP, VP, VP, VP, VP, VP, ctypes.c_size_t, ctypes.POINTER(RefineOpts), I32,
+                                     VP, VP]
+    L.bnc_refine_batched.restype = ctypes.c_int
+    L.bnc_refine_batched_graph.argtypes = [I64, VP, VP, VP, VP, VP, VP, ctypes.c_size_t, ctypes.POINTER(RefineOpts),
+                                           I32, VP, VP, ctypes.POINTER(ctypes.c_void_p)]
+    L.bnc_refine_batched_graph.restype = ctypes.c_int
+    L.bnc_graph_destroy.argtypes = [VP]
+    L.bnc_wall_clock_khz.restype = ctypes.c_int64
     L.bnc_residual.argtypes = [I64, I32, VP, I64, I64, VP, I64, VP, I64, VP, I64, VP, VP]
     L.bnc_residual.restype = ctypes.c_int
     L.bnc_mw_apply.argtypes = [I32, I32, I64, VP, VP, VP, VP, VP]
@@ -133,6 +151,74 @@ def refine(A: torch.Tensor, b: torch.Tensor, K: int, max_iter: int = 30, rtol: f
                            _stream()), "refine")
     return dict(x=x, status=r.status, iters=r.iters, info=r.info, resid_norm=r.resid_norm, x_norm=r.x_norm,
                 a_norm=r.a_norm, residual_inexact=bool(r.residual_inexact))
+
+
+class BatchSolver:
+    """Batched refined solves (bnc_refine_batched) over a fixed set of
+    systems: A_s (1, n, n) binary64 and b_s (4, n) CUDA tensors.  Device
+    pointer arrays, the largest-first order, outputs and the workspace are
+    set up once; run() launches (optionally through a captured HIP graph)."""
+
+    def __init__(self, As, bs, K: int, max_iter: int = 30, rtol: float = 0.0, atol: float = 0.0,
+                 ctol: float = 2.0 ** -208, slots: int = 0, order=None):
+        dev = As[0].device
+        self.count = len(As)
+        self.As = [a.contiguous() for a in As]
+        self.bs = [b.contiguous() for b in bs]
+        self.ns = [int(a.shape[-1]) for a in As]
+        self.xs = [torch.empty((4, n), dtype=torch.float64, device=dev) for n in self.ns]
+        self.n_dev = torch.tensor(self.ns, dtype=torch.int64, device=dev)
+        self.A_dev = torch.tensor([a.data_ptr() for a in self.As], dtype=torch.int64, device=dev)
+        self.b_dev = torch.tensor([b.data_ptr() for b in self.bs], dtype=torch.int64, device=dev)
+        self.x_dev = torch.tensor([x.data_ptr() for x in self.xs], dtype=torch.int64, device=dev)
+        if order is None:
+            order = sorted(range(self.count), key=lambda i: -self.ns[i])
+        self.order = torch.tensor(list(order), dtype=torch.int32, device=dev)
+        self.res = torch.zeros((self.count, ctypes.sizeof(BatchResult)), dtype=torch.uint8, device=dev)
+        if slots == 0:
+            slots = int(_lib.bnc_refine_batched_default_slots(K))
+            if slots <= 0:
+                raise BncError(f"refine_batched_default_slots: {_lib.bnc_last_error().decode()}")
+        self.slots = slots
+        need = int(_lib.bnc_refine_batched_workspace_size(K, slots))
+        self.work = torch.empty(need, dtype=torch.uint8, device=dev)
+        self.opts = RefineOpts(K, max_iter, rtol, atol, ctol)
+        self.graph = ctypes.c_void_p(None)
+        self.stream = None
+
+    def _args(self):
+        P = ctypes.c_void_p
+        return (self.count, P(self.n_dev.data_ptr()), P(self.A_dev.data_ptr()), P(self.b_dev.data_ptr()),
+                P(self.x_dev.data_ptr()), P(self.order.data_ptr()), P(self.work.data_ptr()), self.work.numel(),
+                ctypes.byref(self.opts), self.slots, P(self.res.data_ptr()))
+
+    def run(self, graph: bool = False):
+        if not graph:
+            _check(_lib.bnc_refine_batched(*self._args(), _stream()), "refine_batched")
+            return
+        if self.stream is None:
+            self.stream = torch.cuda.Stream()
+        with torch.cuda.stream(self.stream):
+            _check(_lib.bnc_refine_batched_graph(*self._args(), ctypes.c_void_p(self.stream.cuda_stream),
+                                                 ctypes.byref(self.graph)), "refine_batched_graph")
+        torch.cuda.current_stream().wait_stream(self.stream)
+
+    def results(self):
+        import numpy as np
+        torch.cuda.synchronize()
+        raw = self.res.cpu().numpy()
+        dt = np.dtype([("status", "<i4"), ("iters", "<i4"), ("info", "<i8"), ("t_start", "<u8"), ("t_end", "<u8"),
+                       ("residual_inexact", "<i4"), ("reserved", "<i4")])
+        return raw.view(dt).reshape(self.count)
+
+    def close(self):
+        if self.graph.value:
+            _lib.bnc_graph_destroy(self.graph)
+            self.graph = ctypes.c_void_p(None)
+
+
+def wall_clock_khz() -> int:
+    return int(_lib.bnc_wall_clock_khz())
 
 
 def residual(A: torch.Tensor, x: torch.Tensor, b: torch.Tensor):

@@ -24,6 +24,12 @@ template <int K>
 int refine_run(int64_t n, int aw, const double *A, int64_t lda, int64_t ldpa, const double *b, int64_t ldpb, double *x,
                int64_t ldpx, void *work, const bnc_refine_opts *o, bnc_refine_result *res, hipStream_t s);
 size_t getrs_scratch_bytes(int K, int64_t n);
+template <int K>
+int batch_run(int64_t count, const int64_t *n, const double *const *A, const double *const *b, double *const *x,
+              const int32_t *order, void *work, int slots, const bnc_refine_opts *o, bnc_batch_result *res,
+              hipStream_t s);
+size_t batch_workspace_bytes(int K, int slots);
+int batch_default_slots(int K);
 size_t refine_workspace_bytes(int64_t n, int K);
 size_t residual_scratch_bytes(int64_t n);
 int residual_run(int64_t n, int aw, const double *A, int64_t lda, int64_t ldpa, const double *x, int64_t ldx,
@@ -306,6 +312,102 @@ int bnc_refine(int64_t n, int32_t a_words, const double *A, int64_t lda, int64_t
     }
 }
 
+size_t bnc_refine_batched_workspace_size(int32_t factor_words, int32_t slots)
+{
+    if (factor_words < 1 || factor_words > 4 || slots < 0)
+        return 0;
+    return batch_workspace_bytes(factor_words, slots ? slots : batch_default_slots(factor_words));
+}
+
+int32_t bnc_refine_batched_default_slots(int32_t factor_words)
+{
+    if (factor_words < 1 || factor_words > 4)
+        return fail_arg(-1, "refine_batched_default_slots: factor_words outside 1..4");
+    return batch_default_slots(factor_words);
+}
+
+int bnc_refine_batched(int64_t count, const int64_t *n, const double *const *A, const double *const *b,
+                       double *const *x, const int32_t *order, void *work, size_t work_bytes,
+                       const bnc_refine_opts *opts, int32_t slots, bnc_batch_result *results, void *stream)
+{
+    if (count < 0)
+        return fail_arg(-1, "refine_batched: count < 0");
+    if (count > 0 && !n)
+        return fail_arg(-2, "refine_batched: n is NULL");
+    if (count > 0 && !A)
+        return fail_arg(-3, "refine_batched: A is NULL");
+    if (count > 0 && !b)
+        return fail_arg(-4, "refine_batched: b is NULL");
+    if (count > 0 && !x)
+        return fail_arg(-5, "refine_batched: x is NULL");
+    if (!work)
+        return fail_arg(-7, "refine_batched: work is NULL");
+    if (!opts || opts->factor_words < 1 || opts->factor_words > 4 || opts->max_iter < 0 || !(opts->rtol >= 0) ||
+        !(opts->atol >= 0) || !(opts->ctol >= 0))
+        return fail_arg(-9, "refine_batched: invalid options");
+    if (slots < 0)
+        return fail_arg(-10, "refine_batched: slots < 0");
+    if (count > 0 && !results)
+        return fail_arg(-11, "refine_batched: results is NULL");
+    const int sl = slots ? slots : batch_default_slots(opts->factor_words);
+    if (work_bytes < batch_workspace_bytes(opts->factor_words, sl))
+        return fail_arg(-8, "refine_batched: workspace too small");
+    switch (opts->factor_words) {
+    case 1:
+        return batch_run<1>(count, n, A, b, x, order, work, sl, opts, results, S(stream));
+    case 2:
+        return batch_run<2>(count, n, A, b, x, order, work, sl, opts, results, S(stream));
+    case 3:
+        return batch_run<3>(count, n, A, b, x, order, work, sl, opts, results, S(stream));
+    default:
+        return batch_run<4>(count, n, A, b, x, order, work, sl, opts, results, S(stream));
+    }
+}
+
+int bnc_refine_batched_graph(int64_t count, const int64_t *n, const double *const *A, const double *const *b,
+                             double *const *x, const int32_t *order, void *work, size_t work_bytes,
+                             const bnc_refine_opts *opts, int32_t slots, bnc_batch_result *results, void *stream,
+                             void **graph_exec)
+{
+    if (!graph_exec)
+        return fail_arg(-13, "refine_batched_graph: graph_exec is NULL");
+    hipStream_t s = S(stream);
+    if (!*graph_exec) {
+        if (!s)
+            return fail_arg(-12, "refine_batched_graph: capture needs a non-null stream");
+        BNC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        const int rc = bnc_refine_batched(count, n, A, b, x, order, work, work_bytes, opts, slots, results, stream);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(s, &g);
+        if (rc)
+            return rc;
+        if (e != hipSuccess)
+            return fail_hip(e, "hipStreamEndCapture", __FILE__, __LINE__);
+        hipGraphExec_t ge = nullptr;
+        BNC_HIP(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+        BNC_HIP(hipGraphDestroy(g));
+        *graph_exec = (void *)ge;
+    }
+    BNC_HIP(hipGraphLaunch((hipGraphExec_t)*graph_exec, s));
+    return BNC_OK;
+}
+
+int bnc_graph_destroy(void *graph_exec)
+{
+    if (graph_exec)
+        BNC_HIP(hipGraphExecDestroy((hipGraphExec_t)graph_exec));
+    return BNC_OK;
+}
+
+int64_t bnc_wall_clock_khz(void)
+{
+    int dev = 0, khz = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess)
+        return 0;
+    return khz;
+}
+
 int bnc_residual(int64_t n, int32_t a_words, const double *A, int64_t lda, int64_t ldpa, const double *x,
                  int64_t ldpx, const double *b, int64_t ldpb, double *r, int64_t ldpr, int32_t *inexact,
                  void *stream)
@@ -433,6 +535,8 @@ const char *bnc_status_string(int32_t status)
         return "singular";
     case BNC_NONFINITE:
         return "nonfinite";
+    case BNC_BAD_SIZE:
+        return "bad_size";
     default:
         return "unknown";
     }

@@ -1,0 +1,786 @@
+// Batched refined solves: Listing 1 of Kouya 2021 (Sec. 2) applied to many
+// independent systems of order n <= 256 in one persistent launch.
+//
+// Persistent workgroups (256 threads) take systems from an atomic queue in
+// the order the caller gives (largest first balances the load) and run the
+// whole path for one system at a time, every step in the same operation
+// order as the single-system solver, so each result equals it bit for bit:
+//   stage A to K words; blocked right-looking LU with 8-column panels held
+//   in LDS (pivot search by wave shuffles, whole-row swaps, reciprocal and
+//   scaling, rank-1 panel updates), U12 by forward substitution, trailing
+//   update with each thread's L21 row in registers and U12 in LDS; diagonal
+//   reciprocals; substitutions with one thread per row and one LDS broadcast
+//   per pivot; the exact residual with one thread per row; the stopping
+//   tests on workgroup reductions; the update x <- x + 2^e z.
+// Each system records its status, corrections, info and start/end wall-clock
+// ticks.
+#include "common.hpp"
+#include "exact.hpp"
+#include "mw.hpp"
+
+namespace bnc {
+
+constexpr int BT = 256;     // threads per workgroup
+constexpr int BNMAX = 256;  // largest order
+constexpr int BNB = 8;      // panel width
+constexpr int BRB = 24;     // residual bins per row (816 bits)
+
+struct BatchSlot {
+    // per persistent workgroup, reused across the systems it solves
+    double *lu;   // K planes of BNMAX*BNMAX (lda = n)
+    double *rd;   // K planes of BNMAX: 1/u_kk
+};
+
+template <int K>
+struct BatchLds {
+    double tile[K * BNB * BNMAX];  // panel [w][c][r]; reused as U12 [w][k][j]
+    double ybuf[BNMAX][K];         // broadcast slots of the substitutions
+    double xq[4][BNMAX];           // current solution (quad-double)
+    double red[BT];                // reduction scratch
+    int redi[BT];
+    double wkey[4][K];             // per-wave argmax
+    int wrow[4];
+    int perm[BNMAX];
+    int ipiv[BNMAX];
+    int s_int[4];
+};
+
+// ---- workgroup reductions ----------------------------------------------------
+
+__device__ __forceinline__ double wg_max(double v, double *red)
+{
+    const int t = threadIdx.x;
+    red[t] = v;
+    __syncthreads();
+    for (int s = BT / 2; s > 0; s >>= 1) {
+        if (t < s)
+            red[t] = fmax(red[t], red[t + s]);
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ double wg_sum(double v, double *red)
+{
+    const int t = threadIdx.x;
+    red[t] = v;
+    __syncthreads();
+    for (int s = BT / 2; s > 0; s >>= 1) {
+        if (t < s)
+            red[t] = red[t] + red[t + s];
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ int wg_min_i(int v, int *redi)
+{
+    const int t = threadIdx.x;
+    redi[t] = v;
+    __syncthreads();
+    for (int s = BT / 2; s > 0; s >>= 1) {
+        if (t < s)
+            redi[t] = redi[t + s] < redi[t] ? redi[t + s] : redi[t];
+        __syncthreads();
+    }
+    const int r = redi[0];
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ int wg_or(int v, int *redi)
+{
+    const int t = threadIdx.x;
+    redi[t] = v;
+    __syncthreads();
+    for (int s = BT / 2; s > 0; s >>= 1) {
+        if (t < s)
+            redi[t] = redi[t] | redi[t + s];
+        __syncthreads();
+    }
+    const int r = redi[0];
+    __syncthreads();
+    return r;
+}
+
+template <int K>
+__device__ __forceinline__ bool cand_better_b(const double (&kb)[K], int rb, const double (&ka)[K], int ra)
+{
+    if (rb < 0)
+        return false;
+    if (ra < 0)
+        return true;
+    if (key_gt<K>(kb, ka))
+        return true;
+    if (key_gt<K>(ka, kb))
+        return false;
+    return rb < ra;
+}
+
+// 2-norm of v over threads t < n (binary64, power-of-two scaled; the tree
+// order is fixed)
+__device__ __forceinline__ double wg_norm2(double v, bool active, double vmax, double *red)
+{
+    const double sc = pow2(-(norm_exp(vmax) + 1));
+    const double t = active ? v * sc : 0.0;
+    const double s = wg_sum(t * t, red);
+    return vmax == 0.0 ? 0.0 : sqrt(s) * pow2(norm_exp(vmax) + 1);
+}
+
+// ---- substitutions (thread i holds y_i) ---------------------------------------
+
+template <int K>
+__device__ __forceinline__ void bsolve(int n, const double *__restrict__ lu, int64_t ldp, const double *__restrict__ rd,
+                                       double (&y)[K], BatchLds<K> &S)
+{
+    const int t = threadIdx.x;
+    // forward: y_i <- y_i - l_ik y_k, k increasing
+    for (int k = 0; k < n; ++k) {
+        double l[K];
+        if (t > k && t < n) {
+#pragma unroll
+            for (int w = 0; w < K; ++w)
+                l[w] = lu[w * ldp + (int64_t)k * n + t];
+        }
+        if (t == k) {
+#pragma unroll
+            for (int w = 0; w < K; ++w)
+                S.ybuf[k][w] = y[w];
+        }
+        __syncthreads();
+        if (t > k && t < n) {
+            double yk[K], o[K];
+#pragma unroll
+            for (int w = 0; w < K; ++w)
+                yk[w] = S.ybuf[k][w];
+            fms<K>(y, l, yk, o);
+#pragma unroll
+            for (int w = 0; w < K; ++w)
+                y[w] = o[w];
+        }
+    }
+    __syncthreads();
+    // backward: x_k = y_k * (1/u_kk), then y_i <- y_i - u_ik x_k, k decreasing
+    for (int k = n - 1; k >= 0; --k) {
+        double u[K];
+        if (t < k) {
+#pragma unroll
+            for (int w = 0; w < K; ++w)
+                u[w] = lu[w * ldp + (int64_t)k * n + t];
+        }
+        if (t == k) {
+            double rk[K], xk[K];
+#pragma unroll
+            for (int w = 0; w < K; ++w)
+                rk[w] = rd[w * BNMAX + k];
+            mul<K>(y, rk, xk);
+#pragma unroll
+            for (int w = 0; w < K; ++w) {
+                y[w] = xk[w];
+                S.ybuf[k][w] = xk[w];
+            }
+        }
+        __syncthreads();
+        if (t < k) {
+            double xk[K], o[K];
+#pragma unroll
+            for (int w = 0; w < K; ++w)
+                xk[w] = S.ybuf[k][w];
+            fms<K>(y, u, xk, o);
+#pragma unroll
+            for (int w = 0; w < K; ++w)
+                y[w] = o[w];
+        }
+    }
+    __syncthreads();
+}
+
+// y_i = rf_perm[i]: gather of the K-word copy held per thread through perm
+template <int K>
+__device__ __forceinline__ void bgather(int n, double (&v)[K], BatchLds<K> &S)
+{
+    const int t = threadIdx.x;
+    if (t < n) {
+#pragma unroll
+        for (int w = 0; w < K; ++w)
+            S.ybuf[t][w] = v[w];
+    }
+    __syncthreads();
+    if (t < n) {
+        const int s = S.perm[t];
+#pragma unroll
+        for (int w = 0; w < K; ++w)
+            v[w] = S.ybuf[s][w];
+    }
+    __syncthreads();
+}
+
+// ---- the batched solver ---------------------------------------------------------
+
+template <int K>
+__global__ void __launch_bounds__(BT)
+    k_batch(int64_t count, const int64_t *__restrict__ nn, const double *const *__restrict__ As,
+            const double *const *__restrict__ bs, double *const *__restrict__ xs, const int32_t *__restrict__ order,
+            unsigned *__restrict__ queue, double *__restrict__ work, bnc_refine_opts o,
+            bnc_batch_result *__restrict__ res)
+{
+    extern __shared__ double smem_raw[];
+    BatchLds<K> &S = *reinterpret_cast<BatchLds<K> *>(smem_raw);
+    const int t = threadIdx.x;
+    const int lane = t & 63, wave = t >> 6;
+    const int64_t ldp = (int64_t)BNMAX * BNMAX;
+    double *lu = work + (size_t)blockIdx.x * ((size_t)K * BNMAX * BNMAX + (size_t)K * BNMAX);
+    double *rd = lu + (size_t)K * BNMAX * BNMAX;
+
+    for (;;) {
+        if (t == 0)
+            S.s_int[0] = (int)atomicAdd(queue, 1u);
+        __syncthreads();
+        const int64_t qi = S.s_int[0];
+        __syncthreads();
+        if (qi >= count)
+            break;
+        const int64_t sys = order ? order[qi] : qi;
+        const uint64_t t0 = wall_clock64();
+        const int64_t n64 = nn[sys];
+        bnc_batch_result out{};
+        double *x = xs[sys];
+        if (n64 < 1 || n64 > BNMAX) {
+            if (t == 0) {
+                out.status = BNC_BAD_SIZE;
+                out.t_start = t0;
+                out.t_end = wall_clock64();
+                res[sys] = out;
+            }
+            continue;
+        }
+        const int n = (int)n64;
+        const double *A = As[sys];
+        const double *b = bs[sys];
+
+        // ---- checks, row maxima, exponent bounds, ||A||_F
+        int bad = 0;
+        double rmax_i = 0.0;
+        int ea = 2000, eb = 2000;
+        for (int64_t e = t; e < (int64_t)n * n; e += BT) {
+            const double v = A[e];
+            bad |= !isfinite(v);
+            if (v != 0.0) {
+                const int ex = ilogb_bits(v);
+                ea = ex < ea ? ex : ea;
+            }
+        }
+        if (t < n) {
+            for (int w = 0; w < 4; ++w) {
+                const double v = b[w * n + t];
+                bad |= !isfinite(v);
+                if (v != 0.0) {
+                    const int ex = ilogb_bits(v);
+                    eb = ex < eb ? ex : eb;
+                }
+            }
+            for (int j = 0; j < n; ++j)
+                rmax_i = fmax(rmax_i, fabs(A[(int64_t)j * n + t]));
+        }
+        if (wg_or(bad, S.redi)) {
+            for (int e = t; e < 4 * n; e += BT)
+                x[(e / n) * n + e % n] = 0.0;
+            if (t == 0) {
+                out.status = BNC_NONFINITE;
+                out.t_start = t0;
+                out.t_end = wall_clock64();
+                res[sys] = out;
+            }
+            continue;
+        }
+        ea = wg_min_i(ea, S.redi);
+        eb = wg_min_i(eb, S.redi);
+        double anorm;
+        {
+            double am = 0.0;
+            for (int64_t e = t; e < (int64_t)n * n; e += BT)
+                am = fmax(am, fabs(A[e]));
+            am = wg_max(am, S.red);
+            const double sc = pow2(-(norm_exp(am) + 1));
+            double acc = 0.0;
+            for (int64_t e = t; e < (int64_t)n * n; e += BT) {
+                const double v = A[e] * sc;
+                acc = acc + v * v;
+            }
+            const double ss = wg_sum(acc, S.red);
+            anorm = am == 0.0 ? 0.0 : sqrt(ss) * pow2(norm_exp(am) + 1);
+        }
+
+        // ---- K-word copy of A
+        for (int64_t e = t; e < (int64_t)n * n; e += BT) {
+            lu[e] = A[e];
+#pragma unroll
+            for (int w = 1; w < K; ++w)
+                lu[w * ldp + e] = 0.0;
+        }
+        __syncthreads();
+
+        // ---- blocked LU
+        int64_t info = 0;
+        for (int j0 = 0; j0 < n; j0 += BNB) {
+            const int jb = (n - j0) < BNB ? (n - j0) : BNB;
+            const int m = n - j0;
+            for (int e = t; e < m * jb; e += BT) {
+                const int r = e % m, c = e / m;
+#pragma unroll
+                for (int w = 0; w < K; ++w)
+                    S.tile[(w * BNB + c) * BNMAX + r] = lu[w * ldp + (int64_t)(j0 + c) * n + j0 + r];
+            }
+            __syncthreads();
+            for (int kk = 0; kk < jb; ++kk) {
+                const int k = j0 + kk;
+                // pivot: rows kk..m-1 of the tile, thread = row
+                double key[K];
+                int row = -1;
+                if (t < m && t >= kk) {
+                    row = t;
+#pragma unroll
+                    for (int w = 0; w < K; ++w)
+                        key[w] = S.tile[(w * BNB + kk) * BNMAX + t];
+                } else {
+#pragma unroll
+                    for (int w = 0; w < K; ++w)
+                        key[w] = 0.0;
+                }
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) {
+                    double ok[K];
+#pragma unroll
+                    for (int w = 0; w < K; ++w)
+                        ok[w] = __shfl_xor(key[w], off, 64);
+                    const int orow = __shfl_xor(row, off, 64);
+                    if (cand_better_b<K>(ok, orow, key, row)) {
+#pragma unroll
+                        for (int w = 0; w < K; ++w)
+                            key[w] = ok[w];
+                        row = orow;
+                    }
+                }
+                if (lane == 0) {
+#pragma unroll
+                    for (int w = 0; w < K; ++w)
+                        S.wkey[wave][w] = key[w];
+                    S.wrow[wave] = row;
+                }
+                __syncthreads();
+                if (t == 0) {
+                    double bk[K];
+                    int br = -1;
+#pragma unroll
+                    for (int w = 0; w < K; ++w)
+                        bk[w] = 0.0;
+                    for (int q = 0; q < 4; ++q) {
+                        double kq[K];
+#pragma unroll
+                        for (int w = 0; w < K; ++w)
+                            kq[w] = S.wkey[q][w];
+                        if (cand_better_b<K>(kq, S.wrow[q], bk, br)) {
+#pragma unroll
+                            for (int w = 0; w < K; ++w)
+                                bk[w] = kq[w];
+                            br = S.wrow[q];
+                        }
+                    }
+                    S.s_int[1] = br;
+                    S.ipiv[k] = j0 + br;
+                }
+                __syncthreads();
+                const int pr = S.s_int[1];  // tile row of the pivot
+                if (pr != kk) {
+                    // panel columns in the tile, other columns in the workspace
+                    for (int e = t; e < jb * K; e += BT) {
+                        const int c = e % jb, w = e / jb;
+                        double *a = &S.tile[(w * BNB + c) * BNMAX];
+                        const double tmp = a[kk];
+                        a[kk] = a[pr];
+                        a[pr] = tmp;
+                    }
+                    for (int e = t; e < (n - jb) * K; e += BT) {
+                        const int cc = e % (n - jb), w = e / (n - jb);
+                        const int c = cc < j0 ? cc : cc + jb;
+                        double *col = lu + w * ldp + (int64_t)c * n;
+                        const double tmp = col[k];
+                        col[k] = col[j0 + pr];
+                        col[j0 + pr] = tmp;
+                    }
+                }
+                __syncthreads();
+                double pv[K];
+#pragma unroll
+                for (int w = 0; w < K; ++w)
+                    pv[w] = S.tile[(w * BNB + kk) * BNMAX + kk];
+                if (is_zero<K>(pv)) {
+                    if (info == 0)
+                        info = k + 1;
+                    continue;
+                }
+                if (t < m && t > kk) {
+                    double rc[K], a[K], l[K];
+                    recip<K>(pv, rc);
+#pragma unroll
+                    for (int w = 0; w < K; ++w)
+                        a[w] = S.tile[(w * BNB + kk) * BNMAX + t];
+                    mul<K>(a, rc, l);
+#pragma unroll
+                    for (int w = 0; w < K; ++w)
+                        S.tile[(w * BNB + kk) * BNMAX + t] = l[w];
+                }
+                __syncthreads();
+                const int nc = jb - kk - 1;
+                for (int e = t; e < m * nc; e += BT) {
+                    const int r = e % m, c = kk + 1 + e / m;
+                    if (r > kk) {
+                        double a[K], l[K], u[K], oo[K];
+#pragma unroll
+                        for (int w = 0; w < K; ++w) {
+                            a[w] = S.tile[(w * BNB + c) * BNMAX + r];
+                            l[w] = S.tile[(w * BNB + kk) * BNMAX + r];
+                            u[w] = S.tile[(w * BNB + c) * BNMAX + kk];
+                        }
+                        fms<K>(a, l, u, oo);
+#pragma unroll
+                        for (int w = 0; w < K; ++w)
+                            S.tile[(w * BNB + c) * BNMAX + r] = oo[w];
+                    }
+                }
+                __syncthreads();
+            }
+            // panel back to the workspace
+            for (int e = t; e < m * jb; e += BT) {
+                const int r = e % m, c = e / m;
+#pragma unroll
+                for (int w = 0; w < K; ++w)
+                    lu[w * ldp + (int64_t)(j0 + c) * n + j0 + r] = S.tile[(w * BNB + c) * BNMAX + r];
+            }
+            // every later phase reads the panel back from the workspace,
+            // written above by other threads
+            __syncthreads();
+            const int c0 = j0 + jb;
+            const int m2 = n - c0;
+            if (m2 <= 0)
+                break;
+            // trailing-update mapping: thread = (row r, column group q)
+            int R2 = 1;
+            while (R2 < m2)
+                R2 <<= 1;
+            const int G = BT / R2;
+            const int r = t % R2, q = t / R2;
+            double l21[BNB][K];
+            if (r < m2) {
+#pragma unroll
+                for (int kk = 0; kk < BNB; ++kk)
+#pragma unroll
+                    for (int w = 0; w < K; ++w)
+                        l21[kk][w] = kk < jb ? S.tile[(w * BNB + kk) * BNMAX + jb + r] : 0.0;
+            }
+            __syncthreads();
+            // U12 = L11^-1 A12: thread per column of A12
+            for (int j = t; j < m2; j += BT) {
+                double u[BNB][K];
+#pragma unroll
+                for (int kk = 0; kk < BNB; ++kk)
+#pragma unroll
+                    for (int w = 0; w < K; ++w)
+                        u[kk][w] = kk < jb ? lu[w * ldp + (int64_t)(c0 + j) * n + j0 + kk] : 0.0;
+#pragma unroll
+                for (int kk = 0; kk < BNB; ++kk) {
+                    if (kk < jb) {
+#pragma unroll
+                        for (int rr = 0; rr < BNB; ++rr) {
+                            if (rr > kk && rr < jb) {
+                                double l[K], oo[K];
+#pragma unroll
+                                for (int w = 0; w < K; ++w)
+                                    l[w] = lu[w * ldp + (int64_t)(j0 + kk) * n + j0 + rr];
+                                fms<K>(u[rr], l, u[kk], oo);
+#pragma unroll
+                                for (int w = 0; w < K; ++w)
+                                    u[rr][w] = oo[w];
+                            }
+                        }
+                    }
+                }
+#pragma unroll
+                for (int kk = 0; kk < BNB; ++kk)
+                    if (kk < jb) {
+#pragma unroll
+                        for (int w = 0; w < K; ++w) {
+                            lu[w * ldp + (int64_t)(c0 + j) * n + j0 + kk] = u[kk][w];
+                            S.tile[(w * BNB + kk) * BNMAX + j] = u[kk][w];
+                        }
+                    }
+            }
+            __syncthreads();
+            // A22 <- A22 - L21 U12, each entry in increasing k
+            if (r < m2) {
+                for (int j = q; j < m2; j += G) {
+                    double c[K];
+                    double *cp = lu + (int64_t)(c0 + j) * n + c0 + r;
+#pragma unroll
+                    for (int w = 0; w < K; ++w)
+                        c[w] = cp[w * ldp];
+#pragma unroll
+                    for (int kk = 0; kk < BNB; ++kk) {
+                        if (kk < jb) {
+                            double u[K], oo[K];
+#pragma unroll
+                            for (int w = 0; w < K; ++w)
+                                u[w] = S.tile[(w * BNB + kk) * BNMAX + j];
+                            fms<K>(c, l21[kk], u, oo);
+#pragma unroll
+                            for (int w = 0; w < K; ++w)
+                                c[w] = oo[w];
+                        }
+                    }
+#pragma unroll
+                    for (int w = 0; w < K; ++w)
+                        cp[w * ldp] = c[w];
+                }
+            }
+            __syncthreads();
+        }
+        if (info != 0) {
+            for (int e = t; e < 4 * n; e += BT)
+                x[(e / n) * n + e % n] = 0.0;
+            if (t == 0) {
+                out.status = BNC_SINGULAR;
+                out.info = info;
+                out.t_start = t0;
+                out.t_end = wall_clock64();
+                res[sys] = out;
+            }
+            __syncthreads();
+            continue;
+        }
+        // diagonal reciprocals and the row permutation
+        if (t < n) {
+            double d[K], rc[K];
+#pragma unroll
+            for (int w = 0; w < K; ++w)
+                d[w] = lu[w * ldp + (int64_t)t * n + t];
+            recip<K>(d, rc);
+#pragma unroll
+            for (int w = 0; w < K; ++w)
+                rd[w * BNMAX + t] = rc[w];
+        }
+        if (t == 0) {
+            for (int i = 0; i < n; ++i)
+                S.perm[i] = i;
+            for (int k = 0; k < n; ++k) {
+                const int p = S.ipiv[k];
+                const int tmp = S.perm[k];
+                S.perm[k] = S.perm[p];
+                S.perm[p] = tmp;
+            }
+        }
+        __syncthreads();
+
+        // ---- first solution: K-word copy of b, substitution, extend
+        double y[K];
+        if (t < n) {
+            double bw[4];
+#pragma unroll
+            for (int w = 0; w < 4; ++w)
+                bw[w] = b[w * n + t];
+            renorm<K, 4>(bw, y);
+        }
+        bgather<K>(n, y, S);
+        bsolve<K>(n, lu, ldp, rd, y, S);
+        if (t < n) {
+#pragma unroll
+            for (int w = 0; w < 4; ++w)
+                S.xq[w][t] = w < K ? y[w] : 0.0;
+        }
+        __syncthreads();
+
+        // ---- refinement loop (same tests and order as the single solver)
+        const int h = [&] {
+            const int64_t N = 8 * (int64_t)n + 4;
+            int hh = 1;
+            while (((int64_t)1 << hh) < 2 * N)
+                ++hh;
+            return hh;
+        }();
+        const double thresh_c = sqrt((double)n) * o.rtol * anorm;
+        bool have_z = false;
+        double zmax = 0.0;
+        int iters = 0, status = BNC_MAX_ITER, inexact = 0;
+        for (int it = 0; it <= o.max_iter; ++it) {
+            // x bounds
+            double xv0 = t < n ? S.xq[0][t] : 0.0;
+            int ex = 2000;
+            if (t < n)
+#pragma unroll
+                for (int w = 0; w < 4; ++w)
+                    if (S.xq[w][t] != 0.0) {
+                        const int e2 = ilogb_bits(S.xq[w][t]);
+                        ex = e2 < ex ? e2 : ex;
+                    }
+            const double xmax = wg_max(fabs(xv0), S.red);
+            ex = wg_min_i(ex, S.redi);
+            // exact residual, thread per row
+            double rr[4] = {0.0, 0.0, 0.0, 0.0};
+            int rbad = 0;
+            if (t < n) {
+                ExpBounds ebnd;
+                ebnd.a = ea;
+                ebnd.x = ex;
+                ebnd.b = eb;
+                const RowAnchor an = row_anchor<BRB>(rmax_i, xmax, b[t], h, lowest_bit(ebnd));
+                if (an.any) {
+                    double sig[BRB], bins[BRB];
+#pragma unroll
+                    for (int qb = 0; qb < BRB; ++qb) {
+                        sig[qb] = qb < an.nb ? 1.5 * pow2(an.e0 - RB_W * qb + 52) : 0.0;
+                        bins[qb] = 0.0;
+                    }
+                    const double lim0 = pow2(an.e0 + 51);
+                    bool bd = false;
+                    for (int j = 0; j < n; ++j) {
+                        const double a = A[(int64_t)j * n + t];
+#pragma unroll
+                        for (int w = 0; w < 4; ++w) {
+                            double lo;
+                            const double hi = two_prod(a, S.xq[w][j], lo);
+                            deposit(-hi, sig, bins, an.nb, lim0, bd);
+                            deposit(-lo, sig, bins, an.nb, lim0, bd);
+                        }
+                    }
+#pragma unroll
+                    for (int w = 0; w < 4; ++w)
+                        deposit(b[w * n + t], sig, bins, an.nb, lim0, bd);
+                    bd = bins_to_qd(bins, an.nb, an.e0, rr) || bd;
+                    rbad = bd ? 1 : 0;
+                }
+            }
+            inexact |= wg_or(rbad, S.redi);
+            const double rmax = wg_max(fabs(rr[0]), S.red);
+            const double nr = wg_norm2(rr[0], t < n, rmax, S.red);
+            const double nx = wg_norm2(xv0, t < n, xmax, S.red);
+            if (nr < thresh_c * nx + o.atol || (have_z && zmax <= o.ctol * xmax)) {
+                status = BNC_CONVERGED;
+                break;
+            }
+            if (iters == o.max_iter)
+                break;
+            // K-word copy of r * 2^-e, correction, x <- x + 2^e z
+            const int e = norm_exp(rmax);
+            double v[K];
+            if (t < n) {
+                double sr[4];
+#pragma unroll
+                for (int w = 0; w < 4; ++w)
+                    sr[w] = rr[w] * pow2(-e);
+                renorm<K, 4>(sr, v);
+            }
+            bgather<K>(n, v, S);
+            bsolve<K>(n, lu, ldp, rd, v, S);
+            double z0 = 0.0;
+            if (t < n) {
+                double zv[4], xv[4], oo[4];
+#pragma unroll
+                for (int w = 0; w < 4; ++w) {
+                    zv[w] = w < K ? v[w] * pow2(e) : 0.0;
+                    xv[w] = S.xq[w][t];
+                }
+                add<4>(xv, zv, oo);
+                z0 = zv[0];
+#pragma unroll
+                for (int w = 0; w < 4; ++w)
+                    S.xq[w][t] = oo[w];
+            }
+            zmax = wg_max(fabs(z0), S.red);
+            have_z = true;
+            ++iters;
+        }
+        for (int e = t; e < 4 * n; e += BT)
+            x[e] = S.xq[e / n][e % n];
+        if (t == 0) {
+            out.status = status;
+            out.iters = iters;
+            out.info = 0;
+            out.residual_inexact = inexact;
+            out.t_start = t0;
+            out.t_end = wall_clock64();
+            res[sys] = out;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_queue_reset(unsigned *q)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        *q = 0;
+}
+
+size_t batch_workspace_bytes(int K, int slots)
+{
+    return (size_t)slots * ((size_t)K * BNMAX * BNMAX + (size_t)K * BNMAX) * sizeof(double) + 256;
+}
+
+// one persistent workgroup per compute unit and resident slot (the kernel
+// needs all 512 VGPRs of a lane's wave slot: one workgroup per CU)
+template <int K>
+static int occupancy_per_cu()
+{
+    int per = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)k_batch<K>, BT, sizeof(BatchLds<K>)) !=
+            hipSuccess ||
+        per < 1)
+        per = 1;
+    return per;
+}
+
+int batch_default_slots(int K)
+{
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 256;
+    int per = K == 1 ? occupancy_per_cu<1>() : K == 2 ? occupancy_per_cu<2>() : K == 3 ? occupancy_per_cu<3>()
+                                                                                         : occupancy_per_cu<4>();
+    return per * ncu;
+}
+
+template <int K>
+int batch_run(int64_t count, const int64_t *n, const double *const *A, const double *const *b, double *const *x,
+              const int32_t *order, void *work, int slots, const bnc_refine_opts *o, bnc_batch_result *res,
+              hipStream_t s)
+{
+    if (count == 0)
+        return BNC_OK;
+    unsigned *queue = (unsigned *)work;
+    double *ws = (double *)((char *)work + 256);
+    const size_t lds = sizeof(BatchLds<K>);
+    if (hipFuncSetAttribute((const void *)k_batch<K>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
+        hipSuccess)
+        (void)hipGetLastError();
+    hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, queue);
+    BNC_LAUNCH_CHECK();
+    hipLaunchKernelGGL((k_batch<K>), dim3((unsigned)slots), dim3(BT), lds, s, count, n, A, b, x, order, queue, ws, *o,
+                       res);
+    BNC_LAUNCH_CHECK();
+    return BNC_OK;
+}
+
+#define INST(K)                                                                                                 \
+    template int batch_run<K>(int64_t, const int64_t *, const double *const *, const double *const *,          \
+                              double *const *, const int32_t *, void *, int, const bnc_refine_opts *,          \
+                              bnc_batch_result *, hipStream_t);
+INST(1)
+INST(2)
+INST(3)
+INST(4)
+#undef INST
+
+}  // namespace bnc

@@ -16,6 +16,7 @@
 #include <string.h>
 
 #include "common.hpp"
+#include "exact.hpp"
 #include "mw.hpp"
 
 namespace bnc {
@@ -30,97 +31,9 @@ template <int K>
 int diag_recip_run(int64_t n, const double *LU, int64_t lda, int64_t ldp, double *rd, hipStream_t s);
 int ipiv_to_perm(int64_t n, const int64_t *ipiv, int32_t *perm, hipStream_t s);
 
-constexpr int RB_W = 34;
-constexpr int RB_NB = 40;  // maximum bins per row
 constexpr int RES_ROWS = 64;
 constexpr int RES_WAVES = 4;
 constexpr int RED_BLOCKS = 256;  // partial-sum slots of the deterministic reductions
-
-// exponent e with 2^e <= |x| < 2^(e+1) for normal x; -1023 for zero/subnormal
-__device__ __forceinline__ int ilogb_bits(double x)
-{
-    return (int)((__double_as_longlong(x) >> 52) & 0x7ff) - 1023;
-}
-
-// frexp-style exponent used for the power-of-two normalisation:
-// e = floor(log2 m) for m > 0, and -1 for m == 0 (as frexp(0) = (0, 0)).
-__host__ __device__ inline int norm_exp(double m)
-{
-    if (m == 0.0)
-        return -1;
-    int e;
-    (void)frexp(m, &e);
-    return e - 1;
-}
-
-struct RowAnchor {
-    int e0;   // exponent of bin 0's quantum
-    int nb;   // bins in use
-    bool any; // the row has a nonzero term
-};
-
-// Exponent bounds gathered before the residual: the smallest floor(log2|v|)
-// over the nonzero words of A, x and b (2000 when there is none).
-struct ExpBounds {
-    int a, x, b;
-};
-
-// lowest bit any term can have: products of words (each word's lowest bit is
-// at least its exponent - 52) and the words of b
-__device__ __forceinline__ int lowest_bit(const ExpBounds &eb)
-{
-    int lo = 100000;
-    if (eb.a < 2000 && eb.x < 2000)
-        lo = eb.a + eb.x - 104;
-    if (eb.b < 2000)
-        lo = (eb.b - 52) < lo ? (eb.b - 52) : lo;
-    return lo;
-}
-
-__device__ __forceinline__ RowAnchor row_anchor(double amax, double xmax, double b0, int h, int elow)
-{
-    int eT = -100000;
-    if (amax > 0.0 && xmax > 0.0)
-        eT = ilogb_bits(amax) + ilogb_bits(xmax) + 2;
-    if (b0 != 0.0) {
-        const int eb = ilogb_bits(fabs(b0)) + 1;
-        eT = eT > eb ? eT : eb;
-    }
-    RowAnchor r;
-    r.any = eT > -100000;
-    int e0 = eT + h - 53;
-    if (e0 < -600)
-        e0 = -600;
-    if (e0 > 900)
-        e0 = 900;
-    r.e0 = e0;
-    // bins q = 0..nb-1 have quanta 2^(e0 - W q); the last must reach elow
-    int nb = (e0 - elow + RB_W - 1) / RB_W + 1;
-    if (nb < 1)
-        nb = 1;
-    if (nb > RB_NB)
-        nb = RB_NB;
-    if (e0 - RB_W * (nb - 1) < -1074 + 0)  // keep every quantum a normal power of two
-        nb = (e0 + 1022) / RB_W + 1;
-    r.nb = nb;
-    return r;
-}
-
-__device__ __forceinline__ void deposit(double t, const double (&sig)[RB_NB], double (&bins)[RB_NB], int nb,
-                                        double lim0, bool &bad)
-{
-    bad = bad || !(fabs(t) <= lim0);
-#pragma unroll
-    for (int b = 0; b < RB_NB; ++b) {
-        if (b < nb) {
-            const double d = (sig[b] + t) - sig[b];
-            bins[b] = bins[b] + d;
-            t = t - d;
-        }
-    }
-    bad = bad || (t != 0.0);
-}
-
 // partial bins of rows [64*bx, +64); workgroup column split sidx, each wave
 // a quarter of it: split index sidx*4 + wave
 template <int AW>
@@ -219,85 +132,6 @@ __global__ void k_fill_i32(int *p, int64_t n, int v)
         p[i] = v;
 }
 
-// ---- exact signed integer in 32-bit limbs (carry-save in int64) ------------
-constexpr int BL = 46;  // 1472 bits >= 34*39 + 53 + headroom
-
-struct Big {
-    int64_t l[BL];
-};
-
-// add v * 2^pos, v signed with |v| < 2^63, pos >= 0
-__device__ __forceinline__ void big_add(Big &B, int64_t v, int pos)
-{
-    const int L = pos >> 5, sh = pos & 31;
-    const uint64_t lo = (uint64_t)(v & 0xffffffffLL);
-    const int64_t hi = v >> 32;  // arithmetic: v = lo + hi * 2^32
-    const uint64_t los = lo << sh;
-#pragma unroll
-    for (int q = 0; q < BL; ++q) {
-        if (q == L)
-            B.l[q] += (int64_t)(los & 0xffffffffULL);
-        if (q == L + 1)
-            B.l[q] += (int64_t)(los >> 32) + hi * ((int64_t)1 << sh);
-    }
-}
-
-__device__ __forceinline__ void big_norm(Big &B)
-{
-#pragma unroll
-    for (int q = 0; q < BL - 1; ++q) {
-        const int64_t c = B.l[q] >> 32;
-        B.l[q] -= c * ((int64_t)1 << 32);
-        B.l[q + 1] += c;
-    }
-}
-
-// Round |B| (B normalised) to nearest binary64 mantissa: returns mant (0 if
-// B == 0) and the bit position of its least significant bit.
-__device__ __forceinline__ uint64_t big_round(const Big &M, int &lsb)
-{
-    int hl = -1;
-#pragma unroll
-    for (int q = BL - 1; q >= 0; --q)
-        if (hl < 0 && M.l[q] != 0)
-            hl = q;
-    if (hl < 0) {
-        lsb = 0;
-        return 0;
-    }
-    uint64_t l2 = 0, l1 = 0, l0 = 0;  // limbs hl, hl-1, hl-2
-    bool below = false;               // any bit in limbs < hl-2
-#pragma unroll
-    for (int q = 0; q < BL; ++q) {
-        const uint64_t v = (uint64_t)M.l[q];
-        if (q == hl)
-            l2 = v;
-        if (q == hl - 1)
-            l1 = v;
-        if (q == hl - 2)
-            l0 = v;
-        if (q < hl - 2 && v != 0)
-            below = true;
-    }
-    const int msb = 31 - __clz((unsigned)l2);
-    // 64 bits starting at the most significant set bit
-    const uint64_t top = (l2 << (63 - msb)) | (l1 << (31 - msb)) | (l0 >> (msb + 1));
-    const bool lowbits = (l0 & ((1ULL << (msb + 1)) - 1ULL)) != 0;
-    uint64_t mant = top >> 11;
-    const bool guard = (top >> 10) & 1ULL;
-    const bool sticky = ((top & 0x3ffULL) != 0) || lowbits || below;
-    int T = 32 * hl + msb;
-    if (guard && (sticky || (mant & 1ULL))) {
-        ++mant;
-        if (mant == (1ULL << 53)) {
-            mant >>= 1;
-            ++T;
-        }
-    }
-    lsb = T - 52;
-    return mant;
-}
-
 __global__ void __launch_bounds__(256)
     k_resid_final(int64_t n, int S, const double *__restrict__ part, const double *__restrict__ rowmax,
                   const double *__restrict__ xmaxp, const ExpBounds *__restrict__ ebp, const double *__restrict__ b,
@@ -307,50 +141,19 @@ __global__ void __launch_bounds__(256)
     if (i >= n)
         return;
     const RowAnchor an = row_anchor(rowmax[i], *xmaxp, b[i], h, lowest_bit(*ebp));
-    const int nb = an.nb;
     double out[4] = {0.0, 0.0, 0.0, 0.0};
     bool bad = false;
     if (an.any) {
-        Big B;
+        double bins[RB_NB];
 #pragma unroll
-        for (int q = 0; q < BL; ++q)
-            B.l[q] = 0;
-        const int elow = an.e0 - RB_W * (nb - 1);  // exponent of the integer's unit
-        for (int q = 0; q < nb; ++q) {
+        for (int q = 0; q < RB_NB; ++q) {
             double s = 0.0;
-            for (int t = 0; t < S; ++t)
-                s = s + part[((int64_t)t * RB_NB + q) * n + i];  // S = number of splits
-            // bin q holds multiples of 2^(e0 - W q): integer digit
-            const double dig = ldexp(s, -(an.e0 - RB_W * q));
-            big_add(B, (int64_t)dig, RB_W * (nb - 1 - q));
+            if (q < an.nb)
+                for (int t = 0; t < S; ++t)
+                    s = s + part[((int64_t)t * RB_NB + q) * n + i];  // S = number of splits
+            bins[q] = s;
         }
-        for (int w = 0; w < 4; ++w) {
-            big_norm(B);
-            const bool neg = B.l[BL - 1] < 0;
-            Big M = B;
-            if (neg) {
-#pragma unroll
-                for (int q = 0; q < BL; ++q)
-                    M.l[q] = -M.l[q];
-                big_norm(M);
-            }
-            int lsb;
-            const uint64_t mant = big_round(M, lsb);
-            if (mant == 0)
-                break;
-            const int e = lsb + elow;
-            if (e + 52 > 1023 || e + 52 < -1022)
-                bad = true;
-            const double v = ldexp((double)mant, e);
-            out[w] = neg ? -v : v;
-            // B -= value: subtract mant * 2^lsb (lsb may be negative only
-            // when the integer is below 2^53, then mant's low bits are zero)
-            const int64_t sm = neg ? -(int64_t)mant : (int64_t)mant;
-            if (lsb >= 0)
-                big_add(B, -sm, lsb);
-            else
-                big_add(B, -(sm >> (-lsb)), 0);
-        }
+        bad = bins_to_qd(bins, an.nb, an.e0, out);
     }
 #pragma unroll
     for (int w = 0; w < 4; ++w)

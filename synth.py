@@ -82,6 +82,48 @@ def rhs_ones(Ap: np.ndarray) -> tuple[np.ndarray, bool]:
     return b, exact
 
 
+def _batch_one(args):
+    config, i, n_lo, n_hi, lc_lo, lc_hi = args
+    g = rng(config, i)
+    n = int(g.integers(n_lo, n_hi + 1))
+    cond = float(10.0 ** g.uniform(lc_lo, lc_hi))
+    Ap = planes(randsvd(n, cond, g))
+    b, exact = rhs_ones(Ap)
+    return Ap, b, exact, cond
+
+
+def _one_blas_thread():
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except ImportError:
+        pass
+
+
+def batch(count: int, n_lo: int, n_hi: int, lc_lo: float, lc_hi: float, config: int = 3, workers: int = 1,
+          progress=None):
+    """`count` independent randsvd systems: system i draws n ~ U{n_lo..n_hi}
+    and cond = 10^U(lc_lo, lc_hi) from its own seed (config, i), so the batch
+    does not depend on the number of worker processes.  Returns lists of
+    A planes (1, n, n), b (4, n), exact flags and conds.  `progress(done)` is
+    called every 512 systems."""
+    jobs = [(config, i, n_lo, n_hi, lc_lo, lc_hi) for i in range(count)]
+    out = []
+    if workers > 1:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(workers, initializer=_one_blas_thread) as pool:
+            for o in pool.imap(_batch_one, jobs, chunksize=16):
+                out.append(o)
+                if progress and len(out) % 512 == 0:
+                    progress(len(out))
+    else:
+        for j in jobs:
+            out.append(_batch_one(j))
+            if progress and len(out) % 512 == 0:
+                progress(len(out))
+    return [o[0] for o in out], [o[1] for o in out], [o[2] for o in out], [o[3] for o in out]
+
+
 def problem(kind: str, n: int, config: int, instance: int = 0, cond: float = 1e3):
     """(A planes (1, n, n), b (4, n), exact flag) for a seeded workload."""
     g = rng(config, instance)
