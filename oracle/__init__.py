@@ -64,6 +64,14 @@ def lib() -> ctypes.CDLL:
         L.orc_residual.restype = I64
         L.orc_exact_dot.argtypes = [ctypes.c_int, I64, P, P, ctypes.POINTER(ctypes.c_int32), P]
         L.orc_exact_dot.restype = ctypes.c_int
+        L.orc_oz_slices.argtypes = [ctypes.c_int, ctypes.c_int, I64, P, ctypes.c_int32, P, P]
+        L.orc_oz_scale.argtypes = [I64, P]
+        L.orc_oz_scale.restype = ctypes.c_int32
+        L.orc_oz_update.argtypes = [ctypes.c_int, ctypes.c_int, I64, I64, I64, P, I64, I64, P, I64, I64,
+                                    P, I64, I64, P]
+        L.orc_oz_update.restype = ctypes.c_int
+        L.orc_getrf_ozaki.argtypes = [ctypes.c_int, I64, P, I64, I64, ctypes.POINTER(I64), I64, ctypes.c_int]
+        L.orc_getrf_ozaki.restype = I64
         _lib = L
     return _lib
 
@@ -170,6 +178,59 @@ def getrf(K: int, A: np.ndarray):
     return LU, ipiv, int(info)
 
 
+# --------------------------------------------------------------------------
+# trailing update by error-free splitting (Ozaki scheme; not in the paper)
+# --------------------------------------------------------------------------
+
+OZ_BETA = 20   # bits per slice
+OZ_SMAX = 16   # most slices
+OZ_KBMAX = 64  # widest panel for which the group sums stay exact
+
+
+def oz_scale(x0) -> int:
+    """Smallest E with |x| < 2^E for every value of x0 (0 if all zero)."""
+    x0 = _c(x0).ravel()
+    return int(lib().orc_oz_scale(x0.size, _p(x0)))
+
+
+def oz_slices(K: int, s: int, x, E: int):
+    """Cut m K-word values x (shape (K, m)) into s slices on the grids
+    2^(E - (q+1) OZ_BETA); returns (slices (s, m), remainders (K, m))."""
+    x = _c(x)
+    m = x.shape[1]
+    sl = np.empty((s, m))
+    rem = np.empty((K, m))
+    lib().orc_oz_slices(K, s, m, _p(x), E, _p(sl), _p(rem))
+    return sl, rem
+
+
+def oz_update(K: int, s: int, L, U, C):
+    """C - L U by the split scheme.  L (K, kb, m) and U (K, nc, kb) and C
+    (K, nc, m) are K-plane (column-major) blocks.  Returns (C_new, acc) with
+    acc[d, j, i] the exact group sum of diagonal d."""
+    L, U = _c(L), _c(U)
+    C = _c(C).copy()
+    _, kb, m = L.shape
+    nc = U.shape[1]
+    acc = np.empty((s, nc, m))
+    rc = lib().orc_oz_update(K, s, m, nc, kb, _p(L), m, kb * m, _p(U), kb, nc * kb, _p(C), m, nc * m, _p(acc))
+    if rc:
+        raise ValueError("oz_update: kb or s out of range")
+    return C, acc
+
+
+def getrf_ozaki(K: int, A: np.ndarray, s: int, nb: int = 64):
+    """Blocked PA = LU (panel width nb) whose trailing updates use the split
+    scheme with s slices; returns (LU, ipiv, info)."""
+    LU = _c(A).copy()
+    n = LU.shape[1]
+    ipiv = np.zeros(n, dtype=np.int64)
+    info = lib().orc_getrf_ozaki(K, n, _p(LU), n, n * n, ipiv.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), nb, s)
+    if info == -2:
+        raise ValueError("getrf_ozaki: nb or s out of range")
+    return LU, ipiv, int(info)
+
+
 def getrs(K: int, LU: np.ndarray, ipiv: np.ndarray, b: np.ndarray) -> np.ndarray:
     """x with A x = b from the factors; b has shape (K, n) or (K, nrhs, n)."""
     LU = _c(LU)
@@ -213,7 +274,7 @@ def norm2(v: np.ndarray) -> float:
 
 
 def refine(A: np.ndarray, b: np.ndarray, K: int, max_iter: int = 30,
-           rtol: float = 0.0, atol: float = 0.0, ctol: float = 2.0 ** -208) -> dict:
+           rtol: float = 0.0, atol: float = 0.0, ctol: float = 2.0 ** -208, ozaki: int = 0) -> dict:
     """Mixed-precision iterative refinement, Listing 1 of the paper (Sec. 2).
 
     A: (aw, n, n) with aw = 1 (binary64 entries) or 4 (quad-double entries).
@@ -227,8 +288,10 @@ def refine(A: np.ndarray, b: np.ndarray, K: int, max_iter: int = 30,
       residual test certifies only a backward error, ~kappa * rtol forward);
       r <- r * 2^-e (power-of-two normalisation); K-word copy of r;
       substitution -> z; z <- 2^e z; x <- x + z.
-    Norms are taken over leading words in binary64.  Returns a dict with
-    x (4, n), iters (corrections applied), status, info, history of ||r||.
+    Norms are taken over leading words in binary64.  With ozaki = s > 0 the
+    factorisation is getrf_ozaki with s slices (panel width 64) instead of
+    the plain LU.  Returns a dict with x (4, n), iters (corrections
+    applied), status, info, history of ||r||.
     """
     A = _c(A)
     b = _c(b)
@@ -238,7 +301,7 @@ def refine(A: np.ndarray, b: np.ndarray, K: int, max_iter: int = 30,
     norm_a = norm2(A[0])
     LU = stage(K, A)
     bf = round_words(K, b)
-    LU, ipiv, info = getrf(K, LU)
+    LU, ipiv, info = getrf_ozaki(K, LU, ozaki) if ozaki else getrf(K, LU)
     if info:
         return dict(x=np.zeros((4, n)), iters=0, status=SINGULAR, info=info, history=[],
                     LU=LU, ipiv=ipiv)

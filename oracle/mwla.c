@@ -453,6 +453,221 @@ void orc_getrs(int K, int64_t n, int64_t nrhs, const double *LU, int64_t lda, in
 }
 
 /* ---------------------------------------------------------------------- */
+/* Trailing update by error-free splitting (Ozaki scheme)                  */
+/* ---------------------------------------------------------------------- */
+
+/*
+ * Not in the paper: an alternative form of the blocked LU's trailing update
+ * A22 <- A22 - L21 U12 after Ozaki, Ogita, Oishi and Rump (Numer.
+ * Algorithms 59, 2012).  Each row of L21 and each column of U12 is cut into
+ * s binary64 slices of OZ_BETA bits on a power-of-two grid fixed by the
+ * row's (column's) largest leading word, so that every slice product and
+ * every sum of them below is exact in binary64.  For each diagonal
+ * d = p + q (p, q slice indices of the row and column operands) the group
+ * sum acc_d = sum_{p+q=d} sum_k L_p[i][k] U_q[k][j] is therefore an exact
+ * binary64 number, whatever the summation order; pairs with d >= s are
+ * dropped (the factor is then slightly less accurate; the refinement
+ * recovers the accuracy).  Finally a_ij <- (((a_ij - acc_0) - acc_1) ...)
+ * - acc_{s-1} in K-word arithmetic, in that order.
+ *
+ * Exactness: with a row scale E (|x| < 2^E for every entry x of the row),
+ * slice q lies on the grid g_q = 2^(E - (q+1) OZ_BETA).  Slice q is the sum
+ * over the words of the remaining value of each word rounded to the nearest
+ * multiple of g_q (ties to even), so |slice_0| <= (2^OZ_BETA + K/2) g_0 and
+ * |slice_q| <= (K 2^(OZ_BETA-1) + K/2) g_q for q >= 1, below
+ * (2^(OZ_BETA+1) + 2) g_q for K <= 4.  A group sum has at most
+ * kb (d+1) <= 64 * 16 terms, each below (2^21 + 2)^2 units of the common
+ * grid, i.e. below 2^53 units in total: exact as long as the grids stay in
+ * the normal binary64 range.
+ */
+#define OZ_BETA 20
+#define OZ_SMAX 16
+#define OZ_KBMAX 64
+
+/* Row/column scale: smallest E with |x_0| < 2^E for every leading word
+ * x_0 of the m entries (stride inc); 0 when all are zero. */
+static int oz_scale(const double *x0, int64_t m, int64_t inc)
+{
+    double mx = 0.0;
+    for (int64_t k = 0; k < m; ++k)
+        mx = fmax(mx, fabs(x0[k * inc]));
+    return mx == 0.0 ? 0 : ilogb(mx) + 1;
+}
+
+/* Cut one K-word value v (consumed: it becomes the remainder) into s
+ * slices on the grids 2^(E - (q+1) OZ_BETA). */
+static void oz_cut(int K, int s, int E, double *v, double *sl)
+{
+    for (int q = 0; q < s; ++q) {
+        int e = E - (q + 1) * OZ_BETA;
+        double acc = 0.0;
+        for (int t = 0; t < K; ++t) {
+            double rho = ldexp(nearbyint(ldexp(v[t], -e)), e);
+            v[t] -= rho;
+            acc += rho;
+        }
+        sl[q] = acc;
+    }
+}
+
+/* Vectorised for the tests: m K-word values x (word-major, word w of
+ * entry i at x[w*m + i]) -> slices sl[q*m + i] and remainders rem (same
+ * layout as x; may be NULL), all with the one scale E. */
+void orc_oz_slices(int K, int s, int64_t m, const double *x, int32_t E, double *sl, double *rem)
+{
+    double v[KMAX], o[OZ_SMAX];
+    for (int64_t i = 0; i < m; ++i) {
+        gather(K, x, m, i, v);
+        oz_cut(K, s, E, v, o);
+        for (int q = 0; q < s; ++q)
+            sl[q * m + i] = o[q];
+        if (rem)
+            scatter(K, rem, m, i, v);
+    }
+}
+
+int32_t orc_oz_scale(int64_t m, const double *x0) { return oz_scale(x0, m, 1); }
+
+/*
+ * C <- C - L U by the scheme above.  L: K planes m x kb (column-major,
+ * leading dimension ldl, plane stride ldpl); U: K planes kb x nc (ldu,
+ * ldpu); C: K planes m x nc (ldc, ldpc).  acc (may be NULL) receives the
+ * group sums, acc[(d*nc + j)*m + i].  Returns -1 when kb or s is out of
+ * range, else 0.
+ */
+int orc_oz_update(int K, int s, int64_t m, int64_t nc, int64_t kb, const double *L, int64_t ldl, int64_t ldpl,
+                  const double *U, int64_t ldu, int64_t ldpu, double *C, int64_t ldc, int64_t ldpc, double *acc)
+{
+    if (kb < 0 || kb > OZ_KBMAX || s < 1 || s > OZ_SMAX)
+        return -1;
+    if (m <= 0 || nc <= 0)
+        return 0;
+    double *Ls = malloc(sizeof(double) * (size_t)(s * m * (kb ? kb : 1)));
+    double *Us = malloc(sizeof(double) * (size_t)(s * nc * (kb ? kb : 1)));
+    double v[KMAX], o[OZ_SMAX], c[KMAX], a[KMAX], t[KMAX];
+    /* slices of the rows of L: Ls[(q*kb + k)*m + i] */
+    for (int64_t i = 0; i < m; ++i) {
+        int E = oz_scale(L + i, kb, ldl);
+        for (int64_t k = 0; k < kb; ++k) {
+            for (int w = 0; w < K; ++w)
+                v[w] = L[w * ldpl + k * ldl + i];
+            oz_cut(K, s, E, v, o);
+            for (int q = 0; q < s; ++q)
+                Ls[(q * kb + k) * m + i] = o[q];
+        }
+    }
+    /* slices of the columns of U: Us[(q*nc + j)*kb + k] */
+    for (int64_t j = 0; j < nc; ++j) {
+        int F = oz_scale(U + j * ldu, kb, 1);
+        for (int64_t k = 0; k < kb; ++k) {
+            for (int w = 0; w < K; ++w)
+                v[w] = U[w * ldpu + j * ldu + k];
+            oz_cut(K, s, F, v, o);
+            for (int q = 0; q < s; ++q)
+                Us[(q * nc + j) * kb + k] = o[q];
+        }
+    }
+    for (int64_t j = 0; j < nc; ++j)
+        for (int64_t i = 0; i < m; ++i) {
+            for (int w = 0; w < K; ++w)
+                c[w] = C[w * ldpc + j * ldc + i];
+            for (int d = 0; d < s; ++d) {
+                double g = 0.0; /* exact */
+                for (int p = 0; p <= d; ++p)
+                    for (int64_t k = 0; k < kb; ++k)
+                        g += Ls[(p * kb + k) * m + i] * Us[((d - p) * nc + j) * kb + k];
+                if (acc)
+                    acc[(d * nc + j) * m + i] = g;
+                memset(a, 0, sizeof(a));
+                a[0] = -g;
+                mw_add(K, c, a, t);
+                memcpy(c, t, sizeof(double) * K);
+            }
+            for (int w = 0; w < K; ++w)
+                C[w * ldpc + j * ldc + i] = c[w];
+        }
+    free(Ls);
+    free(Us);
+    return 0;
+}
+
+/*
+ * Blocked right-looking PA = LU with panel width nb (1..64) whose trailing
+ * update is orc_oz_update with s slices.  Per panel: the unblocked LU of
+ * the panel columns (pivot search, row swaps over all n columns,
+ * multipliers, rank-1 updates inside the panel, each entry's updates in
+ * increasing k), then U12 <- L11^-1 A12 by column-oriented forward
+ * substitution (increasing k), then the split update of A22.  Pivot rule,
+ * ipiv and info as orc_getrf.  Returns -2 on bad nb or s.
+ */
+int64_t orc_getrf_ozaki(int K, int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int64_t nb, int s)
+{
+    if (nb < 1 || nb > OZ_KBMAX || s < 1 || s > OZ_SMAX)
+        return -2;
+    int64_t info = 0;
+    double best[KMAX], v[KMAX], r[KMAX], u[KMAX], l[KMAX], o[KMAX];
+    for (int64_t j0 = 0; j0 < n; j0 += nb) {
+        int64_t jb = n - j0 < nb ? n - j0 : nb;
+        int64_t je = j0 + jb;
+        for (int64_t k = j0; k < je; ++k) {
+            int64_t p = k;
+            load(K, A, lda, ldp, k, k, best);
+            for (int64_t i = k + 1; i < n; ++i) {
+                load(K, A, lda, ldp, i, k, v);
+                if (key_gt(K, v, best)) {
+                    p = i;
+                    memcpy(best, v, sizeof(double) * K);
+                }
+            }
+            ipiv[k] = p;
+            if (p != k)
+                for (int64_t j = 0; j < n; ++j)
+                    for (int w = 0; w < K; ++w) {
+                        double tmp = AT(A, k, j, w);
+                        AT(A, k, j, w) = AT(A, p, j, w);
+                        AT(A, p, j, w) = tmp;
+                    }
+            load(K, A, lda, ldp, k, k, v);
+            if (is_zero(K, v)) {
+                if (info == 0)
+                    info = k + 1;
+                continue;
+            }
+            mw_recip(K, v, r);
+            for (int64_t i = k + 1; i < n; ++i) {
+                load(K, A, lda, ldp, i, k, v);
+                mw_mul(K, v, r, o);
+                store(K, A, lda, ldp, i, k, o);
+            }
+            for (int64_t j = k + 1; j < je; ++j) {
+                load(K, A, lda, ldp, k, j, u);
+                for (int64_t i = k + 1; i < n; ++i) {
+                    load(K, A, lda, ldp, i, k, l);
+                    load(K, A, lda, ldp, i, j, v);
+                    mw_fms(K, v, l, u, o);
+                    store(K, A, lda, ldp, i, j, o);
+                }
+            }
+        }
+        if (je >= n)
+            break;
+        for (int64_t j = je; j < n; ++j)
+            for (int64_t k = j0; k < je; ++k) {
+                load(K, A, lda, ldp, k, j, u);
+                for (int64_t i = k + 1; i < je; ++i) {
+                    load(K, A, lda, ldp, i, k, l);
+                    load(K, A, lda, ldp, i, j, v);
+                    mw_fms(K, v, l, u, o);
+                    store(K, A, lda, ldp, i, j, o);
+                }
+            }
+        orc_oz_update(K, s, n - je, n - je, jb, &AT(A, je, j0, 0), lda, ldp, &AT(A, j0, je, 0), lda, ldp,
+                      &AT(A, je, je, 0), lda, ldp, NULL);
+    }
+    return info;
+}
+
+/* ---------------------------------------------------------------------- */
 /* Exact residual                                                          */
 /* ---------------------------------------------------------------------- */
 

@@ -1,0 +1,199 @@
+"""Pins for the oracle's split form of the trailing update (error-free
+splitting after Ozaki, Ogita, Oishi and Rump, Numer. Algorithms 59 (2012)),
+the project's alternative to the K-word trailing update of the paper's LU
+(Kouya 2021, Sec. 2).
+
+What the mathematics fixes, checked here with exact rationals:
+  * the slices of a value plus its remainder equal the value exactly, each
+    slice is a multiple of its grid and within the stated magnitude bound;
+  * every group sum acc_d is exactly the rational sum of its slice products;
+  * C - L U computed this way is within the truncation + rounding bound of
+    the exact C - L U;
+  * on matrices whose exact factors are short dyadics the split LU returns
+    those factors bit for bit, for every K and slice count;
+  * refinement on top of the split factor reaches the quad-double solution.
+"""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from helpers import rand_words
+from oracle import exact as X
+
+BETA = O.OZ_BETA
+
+
+def F(v):
+    return Fraction(float(v))
+
+
+def slice_bound(K, q):
+    """|slice_q| / grid_q <= this (see the scheme's exactness argument)."""
+    return Fraction(2) ** BETA + Fraction(K, 2) if q == 0 else K * Fraction(2) ** (BETA - 1) + Fraction(K, 2)
+
+
+@pytest.mark.parametrize("K", [1, 2, 3, 4])
+def test_slices_sum_exactly_and_sit_on_their_grids(K):
+    g = np.random.default_rng(700 + K)
+    for trial in range(12):
+        m = 24
+        x = rand_words(g, K, m, spread=30)
+        E = O.oz_scale(x[0])
+        top = max(abs(v) for v in x[0])
+        assert top < 2.0 ** E and top >= 2.0 ** (E - 1)
+        for s in (1, 3, 8, 16):
+            sl, rem = O.oz_slices(K, s, x, E)
+            for i in range(m):
+                total = sum((F(v) for v in sl[:, i]), Fraction(0)) + X.value(rem[:, i])
+                assert total == X.value(x[:, i])
+                for q in range(s):
+                    grid = Fraction(2) ** (E - (q + 1) * BETA)
+                    units = F(sl[q, i]) / grid
+                    assert units.denominator == 1
+                    assert abs(units) <= slice_bound(K, q)
+                # what is left is below half a grid step per word
+                assert abs(X.value(rem[:, i])) <= K * Fraction(2) ** (E - s * BETA) / 2
+            if s == 16:  # 320 bits below the top reach every word's last bit
+                assert np.all(rem == 0.0)
+
+
+def test_scale_of_zero_and_powers_of_two():
+    assert O.oz_scale(np.zeros(5)) == 0
+    assert O.oz_scale(np.array([0.0, 1.0, -0.5])) == 1   # |x| < 2^1
+    assert O.oz_scale(np.array([-0.75])) == 0
+    assert O.oz_scale(np.array([3.0 * 2.0 ** -600])) == -598
+
+
+def blocks(g, K, m, kb, nc, spread):
+    L = np.zeros((K, kb, m))
+    U = np.zeros((K, nc, kb))
+    C = np.zeros((K, nc, m))
+    for k in range(kb):
+        L[:, k, :] = rand_words(g, K, m, spread)
+    for j in range(nc):
+        U[:, j, :] = rand_words(g, K, kb, spread)
+        C[:, j, :] = rand_words(g, K, m, spread)
+    return L, U, C
+
+
+@pytest.mark.parametrize("K", [2, 3, 4])
+def test_group_sums_are_exact_at_full_width(K):
+    """kb = 64 and s = 16: the largest group has 64 * 16 products; with
+    every entry near the top of its binade the sums come closest to 2^53
+    grid units.  Each acc_d must equal the rational sum exactly."""
+    g = np.random.default_rng(720 + K)
+    m, kb, nc, s = 3, 64, 2, 16
+    L, U, C = blocks(g, K, m, kb, nc, spread=0)
+    # push every leading word to the top of [1/2, 1)
+    L[0] = np.sign(L[0]) * (1.0 - 2.0 ** -53)
+    U[0] = np.sign(U[0]) * (1.0 - 2.0 ** -53)
+    _, acc = O.oz_update(K, s, L, U, C)
+    for i in range(m):
+        E = O.oz_scale(L[0, :, i])
+        Ls, _ = O.oz_slices(K, s, L[:, :, i], E)
+        for j in range(nc):
+            Fc = O.oz_scale(U[0, j, :])
+            Us, _ = O.oz_slices(K, s, U[:, j, :], Fc)
+            for d in range(s):
+                exact = sum((F(Ls[p, k]) * F(Us[d - p, k]) for p in range(d + 1) for k in range(kb)), Fraction(0))
+                assert F(acc[d, j, i]) == exact, (i, j, d)
+                grid = Fraction(2) ** (E + Fc - (d + 2) * BETA)
+                assert (exact / grid).denominator == 1
+                assert abs(exact / grid) < Fraction(2) ** 53
+
+
+@pytest.mark.parametrize("K", [2, 3, 4])
+@pytest.mark.parametrize("s", [2, 5, 8, 12])
+def test_update_within_truncation_and_rounding_bound(K, s):
+    g = np.random.default_rng(740 + 10 * K + s)
+    m, kb, nc = 5, 13, 4
+    L, U, C = blocks(g, K, m, kb, nc, spread=4)
+    Cn, acc = O.oz_update(K, s, L, U, C)
+    uK = Fraction(2) ** (-53 * K)
+    for i in range(m):
+        E = O.oz_scale(L[0, :, i])
+        for j in range(nc):
+            Fc = O.oz_scale(U[0, j, :])
+            lu = sum((X.value(L[:, k, i]) * X.value(U[:, j, k]) for k in range(kb)), Fraction(0))
+            exact = X.value(C[:, j, i]) - lu
+            got = X.value(Cn[:, j, i])
+            trunc = kb * Fraction(2) ** (E + Fc - s * BETA) * (Fraction(41, 10) * (s + 1) + K + 1)
+            comb = 8 * s * uK * (abs(X.value(C[:, j, i])) + sum(abs(F(a)) for a in acc[:, j, i]))
+            assert abs(got - exact) <= trunc + comb, (i, j)
+
+
+def test_update_pairs_each_row_slice_with_the_right_column_slice():
+    """A planted pairing mistake (L_p with U_p instead of U_{d-p}) would move
+    the result by about 2^-20 relative; the bound above is far tighter."""
+    g = np.random.default_rng(777)
+    K, s = 3, 6
+    L, U, C = blocks(g, K, 4, 9, 3, spread=0)
+    Cn, acc = O.oz_update(K, s, L, U, C)
+    i, j = 1, 2
+    lu = sum((X.value(L[:, k, i]) * X.value(U[:, j, k]) for k in range(9)), Fraction(0))
+    assert abs(sum(F(a) for a in acc[:, j, i]) - lu) <= abs(lu) * Fraction(2) ** -100 + Fraction(2) ** -100
+
+
+def to_planes(A, K):
+    P = np.zeros((K, A.shape[0], A.shape[0]))
+    P[0] = A.T
+    return P
+
+
+def constructed(n, g):
+    L = np.tril(g.integers(-7, 8, (n, n)) / 8.0, -1) + np.eye(n)
+    U = np.triu(g.integers(-9, 10, (n, n)).astype(float), 1)
+    U += np.diag(g.choice([-4.0, -2.0, -1.0, 1.0, 2.0, 4.0], n))
+    perm = g.permutation(n)
+    return (L @ U)[np.argsort(perm)], L, U
+
+
+@pytest.mark.parametrize("K", [1, 2, 3, 4])
+@pytest.mark.parametrize("nb,s", [(4, 2), (7, 8), (16, 16), (64, 3)])
+def test_constructed_factorisation_exact(K, nb, s):
+    g = np.random.default_rng(800 + K + nb)
+    for n in (1, 5, 33, 70):
+        A, L, U = constructed(n, g)
+        assert np.abs(A).max() < 2.0 ** 40
+        LU, ipiv, info = O.getrf_ozaki(K, to_planes(A, K), s, nb)
+        LUp, ipp, _ = O.getrf(K, to_planes(A, K))
+        assert info == 0
+        np.testing.assert_array_equal(ipiv, ipp)
+        M = LU[0].T
+        np.testing.assert_array_equal(np.tril(M, -1) + np.eye(n), L)
+        np.testing.assert_array_equal(np.triu(M), U)
+        assert np.all(LU[1:] == 0.0)
+
+
+def test_bad_parameters_rejected():
+    A = to_planes(np.eye(3), 2)
+    with pytest.raises(ValueError):
+        O.getrf_ozaki(2, A, 0)
+    with pytest.raises(ValueError):
+        O.getrf_ozaki(2, A, 17)
+    with pytest.raises(ValueError):
+        O.getrf_ozaki(2, A, 4, nb=65)
+
+
+def test_singular_info_matches_plain_lu():
+    A = np.array([[1.0, 2.0, 3.0, 1.0], [2.0, 4.0, 6.0, 2.0], [1.0, 0.0, 1.0, 5.0], [0.0, 1.0, 1.0, 1.0]])
+    for K in (2, 3):
+        _, _, info = O.getrf_ozaki(K, to_planes(A, K), 4, nb=2)
+        _, _, info_p = O.getrf(K, to_planes(A, K))
+        assert info == info_p != 0
+
+
+@pytest.mark.parametrize("K,s,cond", [(2, 4, 1e8), (3, 6, 1e10), (4, 9, 1e15), (3, 2, 1e3)])
+def test_refinement_on_split_factor_reaches_quad_double(K, s, cond):
+    """The split factor is a little less accurate than the plain K-word one;
+    the refinement loop must still end at the quad-double solution (exact
+    solution all ones, right-hand side exact in quad-double)."""
+    Ap, b, exact = synth.problem("randsvd", 130, config=1, instance=40 + s, cond=cond)
+    assert exact
+    r = O.refine(Ap, b, K, ozaki=s)
+    assert r["status"] == O.CONVERGED
+    err = max(abs(X.value(r["x"][:, i]) - 1) for i in range(130))
+    assert err <= Fraction(10) ** -60
