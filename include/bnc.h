@@ -73,6 +73,28 @@ int bnc_getrf_td(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, 
 int bnc_getrf_qd(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int64_t *info, void *stream);
 
 /*
+ * The same factorisation with the split form of the trailing update (not
+ * in the paper; the error-free splitting of Ozaki, Ogita, Oishi and Rump,
+ * Numer. Algorithms 59 (2012), run on the FP64 matrix cores).  After each
+ * 64-wide panel (pivoting, multipliers and U12 exactly as bnc_getrf_*),
+ * every row of L21 and column of U12 is cut into `slices` binary64 slices of
+ * 20 bits on a power-of-two grid fixed by its largest leading word; for each
+ * d < slices the products of slice pairs (p, d - p) are summed exactly in
+ * binary64, and a_ij <- (((a_ij - acc_0) - acc_1) ...) - acc_{slices-1} in
+ * K-word addition.  Pairs with p + q >= slices are dropped, so the factor
+ * carries about 20 * slices bits relative to each row/column scale (8 slices
+ * suit triple-double, 11 quad-double); bnc_refine recovers full accuracy.
+ * Deterministic, and independent of tiling (every group sum is exact while
+ * the row and column scales stay above about 2^-700).
+ *   factor_words  K in 1..4;  slices  1..12
+ *   the remaining arguments as bnc_getrf_* (argument errors are numbered
+ *   from n = 3)
+ * Uses library scratch (2 * 12 * 64 * n doubles for the slices).
+ */
+int bnc_getrf_ozaki(int32_t factor_words, int32_t slices, int64_t n, double *A, int64_t lda, int64_t ldp,
+                    int64_t *ipiv, int64_t *info, void *stream);
+
+/*
  * Solve A X = B with the factors of bnc_getrf_* (Kouya 2021, Sec. 2:
  * forward and backward substitution; Listing 1 calls it for the first
  * solution and for every correction).  Rows of B are permuted by ipiv, then
@@ -102,6 +124,10 @@ typedef struct bnc_refine_opts {
     double atol;
     double ctol;          /* forward test: stop when the last correction had
                              ||z||_inf <= ctol ||x||_inf (0 disables) */
+    int32_t ozaki_slices; /* 0: K-word trailing updates (bnc_getrf_*);
+                             1..12: the split form (bnc_getrf_ozaki) with
+                             that many slices.  Batched solves take 0. */
+    int32_t reserved;     /* set to 0 */
 } bnc_refine_opts;
 
 /* Outcome of the refinement loop (host struct, filled synchronously). */

@@ -20,6 +20,7 @@ from .bnc import (  # noqa: F401
     BatchSolver,
     BncError,
     getrf,
+    getrf_ozaki,
     getrs,
     lib,
     lib_path,

@@ -27,7 +27,8 @@ class BncError(RuntimeError):
 
 class RefineOpts(ctypes.Structure):
     _fields_ = [("factor_words", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("rtol", ctypes.c_double),
-                ("atol", ctypes.c_double), ("ctol", ctypes.c_double)]
+                ("atol", ctypes.c_double), ("ctol", ctypes.c_double), ("ozaki_slices", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class RefineResult(ctypes.Structure):
@@ -55,6 +56,8 @@ def _load() -> ctypes.CDLL:
         g = getattr(L, f"bnc_getrs_{s}")
         g.argtypes = [I64, I64, VP, I64, I64, VP, VP, I64, I64, VP]
         g.restype = ctypes.c_int
+    L.bnc_getrf_ozaki.argtypes = [I32, I32, I64, VP, I64, I64, VP, VP, VP]
+    L.bnc_getrf_ozaki.restype = ctypes.c_int
     L.bnc_refine_workspace_size.argtypes = [I64, I32]
     L.bnc_refine_workspace_size.restype = ctypes.c_size_t
     L.bnc_refine.argtypes = [I64, I32, VP, I64, I64, VP, I64, VP, I64, VP, ctypes.c_size_t,
@@ -117,6 +120,16 @@ def getrf(K: int, A: torch.Tensor):
     return ipiv[:n], info
 
 
+def getrf_ozaki(K: int, slices: int, A: torch.Tensor):
+    """bnc_getrf_ozaki: P A = L U with split trailing updates; returns (ipiv, info)."""
+    n = A.shape[1]
+    ipiv = torch.empty(max(n, 1), dtype=torch.int64, device=A.device)
+    info = torch.empty(1, dtype=torch.int64, device=A.device)
+    _check(_lib.bnc_getrf_ozaki(K, slices, n, _dev(A, "A", 3), n, n * n, ctypes.c_void_p(ipiv.data_ptr()),
+                                ctypes.c_void_p(info.data_ptr()), _stream()), "getrf_ozaki")
+    return ipiv[:n], info
+
+
 def getrs(K: int, LU: torch.Tensor, ipiv: torch.Tensor, B: torch.Tensor) -> torch.Tensor:
     """Solve in place; B is (K, n) or (K, nrhs, n)."""
     n = LU.shape[1]
@@ -134,17 +147,19 @@ def refine_workspace_size(n: int, K: int) -> int:
 
 
 def refine(A: torch.Tensor, b: torch.Tensor, K: int, max_iter: int = 30, rtol: float = 0.0, atol: float = 0.0,
-           ctol: float = 2.0 ** -208, x: torch.Tensor | None = None, work: torch.Tensor | None = None) -> dict:
+           ctol: float = 2.0 ** -208, x: torch.Tensor | None = None, work: torch.Tensor | None = None,
+           ozaki: int = 0) -> dict:
     """Listing 1 of the paper with a K-word factorisation and a quad-double
-    long precision.  A: (aw, n, n) with aw = 1 or 4; b: (4, n).  Returns a
-    dict with x (4, n) and the outcome fields."""
+    long precision.  A: (aw, n, n) with aw = 1 or 4; b: (4, n); ozaki = S > 0
+    factors with the split trailing update (S slices).  Returns a dict with
+    x (4, n) and the outcome fields."""
     aw, n = A.shape[0], A.shape[1]
     if x is None:
         x = torch.empty((4, n), dtype=torch.float64, device=A.device)
     need = refine_workspace_size(n, K)
     if work is None or work.numel() < need:
         work = torch.empty(need, dtype=torch.uint8, device=A.device)
-    o = RefineOpts(K, max_iter, rtol, atol, ctol)
+    o = RefineOpts(K, max_iter, rtol, atol, ctol, ozaki, 0)
     r = RefineResult()
     _check(_lib.bnc_refine(n, aw, _dev(A, "A", 3), n, n * n, _dev(b, "b", 2), n, _dev(x, "x", 2), n,
                            ctypes.c_void_p(work.data_ptr()), work.numel(), ctypes.byref(o), ctypes.byref(r),
@@ -182,7 +197,7 @@ class BatchSolver:
         self.slots = slots
         need = int(_lib.bnc_refine_batched_workspace_size(K, slots))
         self.work = torch.empty(need, dtype=torch.uint8, device=dev)
-        self.opts = RefineOpts(K, max_iter, rtol, atol, ctol)
+        self.opts = RefineOpts(K, max_iter, rtol, atol, ctol, 0, 0)
         self.graph = ctypes.c_void_p(None)
         self.stream = None
 

@@ -16,7 +16,8 @@ namespace bnc {
 
 template <int K>
 int getrf_run(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int64_t *info, void *scr,
-              hipStream_t s);
+              hipStream_t s, int oz, double *oz_buf);
+size_t oz_slices_bytes(int64_t n);
 template <int K>
 int getrs_run(int64_t n, int64_t nrhs, const double *LU, int64_t lda, int64_t ldp, const int64_t *ipiv, double *B,
               int64_t ldb, int64_t ldpb, void *scr, hipStream_t s);
@@ -166,26 +167,33 @@ using namespace bnc;
 static hipStream_t S(void *s) { return (hipStream_t)s; }
 
 template <int K>
-static int getrf_entry(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int64_t *info, void *stream)
+static int getrf_entry(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int64_t *info, void *stream,
+                       int oz = 0, int argoff = 0)
 {
     if (n < 0)
-        return fail_arg(-1, "getrf: n < 0");
+        return fail_arg(-(1 + argoff), "getrf: n < 0");
     if (n > 0 && !A)
-        return fail_arg(-2, "getrf: A is NULL");
+        return fail_arg(-(2 + argoff), "getrf: A is NULL");
     if (lda < (n > 1 ? n : 1))
-        return fail_arg(-3, "getrf: lda < max(1, n)");
+        return fail_arg(-(3 + argoff), "getrf: lda < max(1, n)");
     if (K > 1 && ldp < lda * n)
-        return fail_arg(-4, "getrf: ldp < lda * n");
+        return fail_arg(-(4 + argoff), "getrf: ldp < lda * n");
     if (n > 0 && !ipiv)
-        return fail_arg(-5, "getrf: ipiv is NULL");
+        return fail_arg(-(5 + argoff), "getrf: ipiv is NULL");
     if (!info)
-        return fail_arg(-6, "getrf: info is NULL");
+        return fail_arg(-(6 + argoff), "getrf: info is NULL");
     if (n > 16384)
         return fail_arg(BNC_ERR_UNSUPPORTED, "getrf: n > 16384");
     void *scr = scratch(SCR_GETRF, getrf_scratch_bytes(K));
     if (!scr)
         return fail_arg(BNC_ERR_HIP, "getrf: scratch allocation failed");
-    return getrf_run<K>(n, A, lda, ldp, ipiv, info, scr, S(stream));
+    double *ozb = nullptr;
+    if (oz) {
+        ozb = (double *)scratch(SCR_OZ, oz_slices_bytes(n));
+        if (!ozb)
+            return fail_arg(BNC_ERR_HIP, "getrf: scratch allocation failed");
+    }
+    return getrf_run<K>(n, A, lda, ldp, ipiv, info, scr, S(stream), oz, ozb);
 }
 
 template <int K>
@@ -235,6 +243,25 @@ int bnc_getrf_td(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, 
 int bnc_getrf_qd(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int64_t *info, void *stream)
 {
     return getrf_entry<4>(n, A, lda, ldp, ipiv, info, stream);
+}
+
+int bnc_getrf_ozaki(int32_t factor_words, int32_t slices, int64_t n, double *A, int64_t lda, int64_t ldp,
+                    int64_t *ipiv, int64_t *info, void *stream)
+{
+    if (factor_words < 1 || factor_words > 4)
+        return fail_arg(-1, "getrf_ozaki: factor_words outside 1..4");
+    if (slices < 1 || slices > OZ_SMAX)
+        return fail_arg(-2, "getrf_ozaki: slices outside 1..12");
+    switch (factor_words) {
+    case 1:
+        return getrf_entry<1>(n, A, lda, ldp, ipiv, info, stream, slices, 2);
+    case 2:
+        return getrf_entry<2>(n, A, lda, ldp, ipiv, info, stream, slices, 2);
+    case 3:
+        return getrf_entry<3>(n, A, lda, ldp, ipiv, info, stream, slices, 2);
+    default:
+        return getrf_entry<4>(n, A, lda, ldp, ipiv, info, stream, slices, 2);
+    }
 }
 
 int bnc_getrs_d(int64_t n, int64_t nrhs, const double *LU, int64_t lda, int64_t ldp, const int64_t *ipiv, double *B,
@@ -292,6 +319,7 @@ int bnc_refine(int64_t n, int32_t a_words, const double *A, int64_t lda, int64_t
     if (!opts)
         return fail_arg(-12, "refine: opts is NULL");
     if (opts->factor_words < 1 || opts->factor_words > 4 || opts->max_iter < 0 || !(opts->rtol >= 0) ||
+        opts->ozaki_slices < 0 || opts->ozaki_slices > OZ_SMAX ||
         !(opts->atol >= 0) || !(opts->ctol >= 0))
         return fail_arg(-12, "refine: invalid options");
     if (!result)
@@ -343,6 +371,7 @@ int bnc_refine_batched(int64_t count, const int64_t *n, const double *const *A, 
     if (!work)
         return fail_arg(-7, "refine_batched: work is NULL");
     if (!opts || opts->factor_words < 1 || opts->factor_words > 4 || opts->max_iter < 0 || !(opts->rtol >= 0) ||
+        opts->ozaki_slices != 0 ||
         !(opts->atol >= 0) || !(opts->ctol >= 0))
         return fail_arg(-9, "refine_batched: invalid options");
     if (slots < 0)

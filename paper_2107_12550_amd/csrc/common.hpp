@@ -26,7 +26,7 @@ int fail_arg(int code, const char *msg);
 // Library-owned device scratch for the stand-alone factor/solve entry points
 // (the refinement driver carves everything from the caller's workspace).
 // One buffer per (device, slot); grown with hipMalloc when a call needs more.
-enum ScratchSlot { SCR_GETRF = 0, SCR_GETRS = 1, SCR_NSLOTS = 2 };
+enum ScratchSlot { SCR_GETRF = 0, SCR_GETRS = 1, SCR_OZ = 2, SCR_NSLOTS = 3 };
 void *scratch(int slot, size_t bytes);
 
 // Timing of trailing-update launches (hipEvents on the launch stream).
@@ -51,6 +51,9 @@ constexpr double fms_flops(int K)
 // per-panel row-permutation pairs).
 constexpr int PANEL_NB_MAX = 64;
 constexpr int PANEL_WG_MAX = 256;
+
+// Split (Ozaki) trailing update: at most this many slices per operand.
+constexpr int OZ_SMAX = 12;
 size_t getrf_scratch_bytes(int K);
 
 }  // namespace bnc

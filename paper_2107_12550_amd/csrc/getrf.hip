@@ -656,8 +656,21 @@ static int lookahead_get(LookAhead *&la)
 }
 
 template <int K>
+int oz_split_rows_run(const double *A, int64_t lda, int64_t ldp, int64_t r0, int64_t m, int64_t j0, int kb, int s,
+                      double *SL, int64_t ldsl, hipStream_t st);
+template <int K>
+int oz_split_cols_run(const double *A, int64_t lda, int64_t ldp, int64_t j0, int kb, int64_t c0, int64_t nc, int s,
+                      double *SU, int64_t ldsu, hipStream_t st);
+template <int K>
+int oz_update_run(int s, bool thin, double *A, int64_t lda, int64_t ldp, int64_t r0, int64_t c0, int64_t m,
+                  int64_t nc, int kb, const double *SL, int64_t ldsl, const double *SU, int64_t ldsu, hipStream_t st);
+
+// oz = 0: K-word trailing updates (bit-identical to the unblocked LU).
+// oz = S in 1..OZ_SMAX: split updates with S slices (ozaki.hip); oz_buf
+// holds the slices, >= oz_slices_bytes(n) bytes.
+template <int K>
 int getrf_run(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int64_t *info, void *scr,
-              hipStream_t s)
+              hipStream_t s, int oz, double *oz_buf)
 {
     if (n == 0)
         return BNC_OK;
@@ -729,9 +742,21 @@ int getrf_run(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int
         return BNC_OK;
     };
     // A[r0.., c0..c0+nc) -= L21 (columns j0..j0+jb) * U12
+    // split form: SL holds the sliced rows cn..n-1 of the current panel,
+    // SU the sliced columns cn..n-1 of its U12 (both with leading dimension n)
+    double *SL = oz_buf, *SU = oz_buf ? oz_buf + (size_t)OZ_SMAX * PANEL_NB_MAX * n : nullptr;
     auto update = [&](int64_t r0, int64_t c0, int64_t m, int64_t nc, int64_t j0, int jb, bool thin) -> int {
         if (m <= 0 || nc <= 0)
             return BNC_OK;
+        if (oz) {
+            int rc2 = oz_split_cols_run<K>(A, lda, ldp, j0, jb, c0, nc, oz, SU + (c0 - r0), n, s);
+            if (rc2)
+                return rc2;
+            const int ev = UpdateTimer::begin(s);
+            rc2 = oz_update_run<K>(oz, thin, A, lda, ldp, r0, c0, m, nc, jb, SL, n, SU + (c0 - r0), n, s);
+            UpdateTimer::end(ev, s, 2.0 * (oz * (oz + 1) / 2) * (double)m * (double)nc * (double)jb);
+            return rc2;
+        }
         const int ev = UpdateTimer::begin(s);
         if (thin) {
             using C = UpdCfgThin<K>;
@@ -763,6 +788,8 @@ int getrf_run(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int
         if (cn >= n)
             break;
         const int nbn = (int)((n - cn) < nb ? (n - cn) : nb);
+        if (oz && (rc = oz_split_rows_run<K>(A, lda, ldp, cn, n - cn, j0, jb, oz, SL, n, s)))
+            return rc;
         // look-ahead: the next panel's columns first
         if ((rc = swaps(j0, jb, cn, nbn, pr, true)) || (rc = update(cn, cn, n - cn, nbn, j0, jb, true)))
             return rc;
@@ -780,9 +807,13 @@ int getrf_run(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int
     return BNC_OK;
 }
 
-template int getrf_run<1>(int64_t, double *, int64_t, int64_t, int64_t *, int64_t *, void *, hipStream_t);
-template int getrf_run<2>(int64_t, double *, int64_t, int64_t, int64_t *, int64_t *, void *, hipStream_t);
-template int getrf_run<3>(int64_t, double *, int64_t, int64_t, int64_t *, int64_t *, void *, hipStream_t);
-template int getrf_run<4>(int64_t, double *, int64_t, int64_t, int64_t *, int64_t *, void *, hipStream_t);
+template int getrf_run<1>(int64_t, double *, int64_t, int64_t, int64_t *, int64_t *, void *, hipStream_t, int,
+                            double *);
+template int getrf_run<2>(int64_t, double *, int64_t, int64_t, int64_t *, int64_t *, void *, hipStream_t, int,
+                            double *);
+template int getrf_run<3>(int64_t, double *, int64_t, int64_t, int64_t *, int64_t *, void *, hipStream_t, int,
+                            double *);
+template int getrf_run<4>(int64_t, double *, int64_t, int64_t, int64_t *, int64_t *, void *, hipStream_t, int,
+                            double *);
 
 }  // namespace bnc

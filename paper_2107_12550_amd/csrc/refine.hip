@@ -23,7 +23,8 @@ namespace bnc {
 
 template <int K>
 int getrf_run(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int64_t *info, void *scr,
-              hipStream_t s);
+              hipStream_t s, int oz, double *oz_buf);
+size_t oz_slices_bytes(int64_t n);
 template <int K>
 int getrs_perm(int64_t n, const double *LU, int64_t lda, int64_t ldp, const int32_t *perm, const double *rd,
                const double *b, int64_t ldb, double *y, int64_t ldy, hipStream_t s);
@@ -461,7 +462,7 @@ struct Scal {
 };
 
 struct RefineLayout {
-    size_t lu, ipiv, perm, rd, r, v, rowmax, part, red, scal, getrf, total;
+    size_t lu, ipiv, perm, rd, r, v, rowmax, part, red, scal, getrf, oz, total;
 };
 
 size_t getrf_scratch_bytes(int K);
@@ -486,6 +487,7 @@ static RefineLayout refine_layout(int64_t n, int K)
     L.red = take((size_t)RED_BLOCKS * sizeof(double));
     L.scal = take(sizeof(Scal));
     L.getrf = take(getrf_scratch_bytes(K));
+    L.oz = take(oz_slices_bytes(n));
     L.total = off;
     return L;
 }
@@ -509,6 +511,7 @@ int refine_run(int64_t n, int aw, const double *A, int64_t lda, int64_t ldpa, co
     double *red = (double *)(W + L.red);
     Scal *sc = (Scal *)(W + L.scal);
     void *gscr = W + L.getrf;
+    double *ozb = (double *)(W + L.oz);
     const int64_t ldp = n * n;
 
     *res = bnc_refine_result{};
@@ -547,7 +550,7 @@ int refine_run(int64_t n, int aw, const double *A, int64_t lda, int64_t ldpa, co
     else
         hipLaunchKernelGGL((k_stage<K, 4>), dim3(grid1(n * n)), dim3(256), 0, s, n, A, lda, ldpa, LU, n, ldp);
     BNC_LAUNCH_CHECK();
-    if ((rc = getrf_run<K>(n, LU, n, ldp, ipiv, &sc->info, gscr, s)))
+    if ((rc = getrf_run<K>(n, LU, n, ldp, ipiv, &sc->info, gscr, s, o->ozaki_slices, ozb)))
         return rc;
     BNC_HIP(hipMemcpyAsync(&h, sc, sizeof(Scal), hipMemcpyDeviceToHost, s));
     BNC_HIP(hipStreamSynchronize(s));

@@ -18,7 +18,8 @@ def test_header_declares_the_boundary():
     names = declared()
     for k in ("d", "dd", "td", "qd"):
         assert f"bnc_getrf_{k}" in names and f"bnc_getrs_{k}" in names
-    for n in ("bnc_refine", "bnc_refine_workspace_size", "bnc_residual", "bnc_mw_apply"):
+    for n in ("bnc_refine", "bnc_refine_workspace_size", "bnc_residual", "bnc_mw_apply", "bnc_getrf_ozaki",
+              "bnc_refine_batched", "bnc_refine_batched_graph"):
         assert n in names
 
 
@@ -44,3 +45,13 @@ def test_host_only_entry_points():
     rc = L.bnc_getrf_td(8, None, 8, 64, None, None, None)
     assert rc == -2
     assert b"NULL" in L.bnc_last_error()
+
+
+def test_ozaki_rejects_bad_slices_before_touching_the_device():
+    import paper_2107_12550_amd as P
+    L = P.lib()
+    assert L.bnc_getrf_ozaki(3, 0, 4, None, 4, 16, None, None, None) == -2
+    assert L.bnc_getrf_ozaki(3, 13, 4, None, 4, 16, None, None, None) == -2
+    assert L.bnc_getrf_ozaki(5, 8, 4, None, 4, 16, None, None, None) == -1
+    # argument positions continue from n = 3
+    assert L.bnc_getrf_ozaki(3, 8, -1, None, 4, 16, None, None, None) == -3
