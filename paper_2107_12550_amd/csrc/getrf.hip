@@ -68,6 +68,33 @@ __device__ __forceinline__ void wave_argmax(double (&key)[K], int &row)
     }
 }
 
+// Cross-workgroup exchange inside the panel.  Every word another workgroup
+// reads (candidate rows, their row indices, the row at the pivot position,
+// the arrival counter) is written and read with device-scope relaxed
+// atomics, which the hardware keeps coherent across the XCDs' L2 caches on
+// their own (write-through stores, loads that miss the non-coherent caches).
+// That makes a full device fence, which would write back and invalidate the
+// whole L2 while the concurrent trailing update keeps it full of dirty
+// lines, unnecessary: a workgroup waits for its own stores to complete
+// before it bumps the counter, and readers load the data only after they
+// have seen the counter reach its target.
+__device__ __forceinline__ void sh_store(double *p, double v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void sh_store(int64_t *p, int64_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double sh_load(const double *p)
+{
+    return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int64_t sh_load(const int64_t *p)
+{
+    return __hip_atomic_load(const_cast<int64_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Grid barrier on a monotonic counter, split into arrive and wait so that
 // work can overlap the wait.  The spin is bounded: on timeout the workgroup
 // records the failure and every later wait returns at once, so the grid
@@ -76,17 +103,19 @@ constexpr unsigned SPIN_LIMIT = 1u << 21;
 
 __device__ __forceinline__ void bar_arrive_wave(unsigned *bar)
 {
-    // called by one whole wave after its global stores
-    __threadfence();
+    // called by one whole wave after its sh_store()s: wait until they have
+    // completed, then count this workgroup in
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_s_waitcnt(0);
     if ((threadIdx.x & 63) == 0)
-        __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ void bar_wait(unsigned *bar, unsigned target, int *abort_flag)
 {
     if (threadIdx.x == 0) {
         unsigned spins = 0;
-        while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
                 break;
             __builtin_amdgcn_s_sleep(1);
@@ -97,7 +126,7 @@ __device__ __forceinline__ void bar_wait(unsigned *bar, unsigned target, int *ab
         }
     }
     __syncthreads();
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
 // LDS tile layout: word w, panel column c, local row r at ((w*jb + c)*R + r);
@@ -166,17 +195,17 @@ __global__ void __launch_bounds__(PANEL_THREADS)
             const int lr = (int)(row - gr0);
             for (int e = lane; e < K * jb; e += 64) {
                 const int w = e / jb, c = e % jb;
-                cb[e] = tile[(w * jb + c) * R + lr];
+                sh_store(cb + e, tile[(w * jb + c) * R + lr]);
             }
         }
         if (lane == 0)
-            cidx[b * P + g] = row;
+            sh_store(cidx + b * P + g, (int64_t)row);
         if (kc >= gr0 && kc < gr0 + nr) {
             const int lr = (int)(kc - gr0);
             double *rb = rowk + (size_t)b * K * jb;
             for (int e = lane; e < K * jb; e += 64) {
                 const int w = e / jb, c = e % jb;
-                rb[e] = tile[(w * jb + c) * R + lr];
+                sh_store(rb + e, tile[(w * jb + c) * R + lr]);
             }
         }
         bar_arrive_wave(bar);
@@ -200,12 +229,12 @@ __global__ void __launch_bounds__(PANEL_THREADS)
             for (int w = 0; w < K; ++w)
                 key[w] = 0.0;
             for (int t = lane; t < P; t += 64) {
-                const int rr = (int)cidx[b * P + t];
+                const int rr = (int)sh_load(cidx + b * P + t);
                 double kv[K];
                 const double *cc = cand + ((size_t)(b * P + t) * K) * jb;
 #pragma unroll
                 for (int w = 0; w < K; ++w)
-                    kv[w] = rr >= 0 ? cc[w * jb + kk] : 0.0;
+                    kv[w] = rr >= 0 ? sh_load(cc + w * jb + kk) : 0.0;
                 if (cand_better<K>(kv, rr, key, row)) {
 #pragma unroll
                     for (int w = 0; w < K; ++w)
@@ -231,12 +260,12 @@ __global__ void __launch_bounds__(PANEL_THREADS)
                 double v[K], o[K];
 #pragma unroll
                 for (int w = 0; w < K; ++w)
-                    v[w] = cc[w * jb + c];
+                    v[w] = sh_load(cc + w * jb + c);
                 if (nz_prev && c > kk) {
                     double l[K], u[K];
 #pragma unroll
                     for (int w = 0; w < K; ++w) {
-                        l[w] = cc[w * jb + kk - 1];
+                        l[w] = sh_load(cc + w * jb + kk - 1);
                         u[w] = pprev[w * jb + c];
                     }
                     fms<K>(v, l, u, o);
@@ -250,12 +279,12 @@ __global__ void __launch_bounds__(PANEL_THREADS)
                 if (need_o) {
 #pragma unroll
                     for (int w = 0; w < K; ++w)
-                        v[w] = rb[w * jb + c];
+                        v[w] = sh_load(rb + w * jb + c);
                     if (nz_prev && c > kk) {
                         double l[K], u[K];
 #pragma unroll
                         for (int w = 0; w < K; ++w) {
-                            l[w] = rb[w * jb + kk - 1];
+                            l[w] = sh_load(rb + w * jb + kk - 1);
                             u[w] = pprev[w * jb + c];
                         }
                         fms<K>(v, l, u, o);
