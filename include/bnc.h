@@ -53,6 +53,8 @@ extern "C" {
 #define BNC_SINGULAR 2  /* exactly zero pivot met: no solve was attempted */
 #define BNC_NONFINITE 3 /* NaN or Inf in A or b: nothing was factorised */
 #define BNC_BAD_SIZE 4  /* batched solve: order outside 1..256 */
+#define BNC_STAGNATED 5 /* corrections stopped shrinking (stagnation_ratio)
+                           and no escalation was left */
 
 /*
  * LU decomposition with partial pivoting, in place: P A = L U (Kouya 2021,
@@ -126,8 +128,16 @@ typedef struct bnc_refine_opts {
                              ||z||_inf <= ctol ||x||_inf (0 disables) */
     int32_t ozaki_slices; /* 0: K-word trailing updates (bnc_getrf_*);
                              1..12: the split form (bnc_getrf_ozaki) with
-                             that many slices.  Batched solves take 0. */
-    int32_t reserved;     /* set to 0 */
+                             that many slices for the first factorisation.
+                             Batched solves take 0. */
+    int32_t escalate;     /* 0 or 1: on stagnation or an exactly zero pivot,
+                             refactor with one more word (plain form) and
+                             go on from the current x, up to 4 words */
+    double stagnation_ratio; /* > 0: after two corrections since the last
+                             factorisation, the loop stagnates when
+                             ||z_i||_inf > stagnation_ratio ||z_(i-1)||_inf
+                             (checked after the stopping tests); 0 disables.
+                             Batched solves take 0. */
 } bnc_refine_opts;
 
 /* Outcome of the refinement loop (host struct, filled synchronously). */
@@ -140,10 +150,13 @@ typedef struct bnc_refine_result {
     double a_norm;             /* ||A||_F (leading words) */
     int32_t residual_inexact;  /* 1 if any residual row lost bits below its
                                   exact accumulator (never for sane inputs) */
+    int32_t final_words;       /* K of the last factorisation */
+    int32_t escalations;       /* refactorisations with more words */
     int32_t reserved;
 } bnc_refine_result;
 
-/* Workspace bytes bnc_refine needs for order n and K = factor_words (host). */
+/* Workspace bytes bnc_refine needs for order n and K = factor_words (host);
+ * with escalate = 1 it needs the size for factor_words = 4. */
 size_t bnc_refine_workspace_size(int64_t n, int32_t factor_words);
 
 /*

@@ -27,7 +27,7 @@ _LIB = os.path.join(_HERE, "libmwla_oracle.so")
 GCC_FLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-shared", "-fPIC"]
 
 # refinement status codes (same numbering as the product's C-ABI)
-CONVERGED, MAX_ITER, SINGULAR, NONFINITE = 0, 1, 2, 3
+CONVERGED, MAX_ITER, SINGULAR, NONFINITE, STAGNATED = 0, 1, 2, 3, 5
 
 
 def build() -> str:
@@ -274,7 +274,8 @@ def norm2(v: np.ndarray) -> float:
 
 
 def refine(A: np.ndarray, b: np.ndarray, K: int, max_iter: int = 30,
-           rtol: float = 0.0, atol: float = 0.0, ctol: float = 2.0 ** -208, ozaki: int = 0) -> dict:
+           rtol: float = 0.0, atol: float = 0.0, ctol: float = 2.0 ** -208, ozaki: int = 0,
+           escalate: bool = False, stag_ratio: float = 0.0) -> dict:
     """Mixed-precision iterative refinement, Listing 1 of the paper (Sec. 2).
 
     A: (aw, n, n) with aw = 1 (binary64 entries) or 4 (quad-double entries).
@@ -289,43 +290,80 @@ def refine(A: np.ndarray, b: np.ndarray, K: int, max_iter: int = 30,
       r <- r * 2^-e (power-of-two normalisation); K-word copy of r;
       substitution -> z; z <- 2^e z; x <- x + z.
     Norms are taken over leading words in binary64.  With ozaki = s > 0 the
-    factorisation is getrf_ozaki with s slices (panel width 64) instead of
-    the plain LU.  Returns a dict with x (4, n), iters (corrections
-    applied), status, info, history of ||r||.
+    first factorisation is getrf_ozaki with s slices (panel width 64)
+    instead of the plain LU.
+
+    Stagnation (not in the paper; the escalation rule of this project):
+    with stag_ratio > 0, once two corrections have been applied since the
+    last factorisation, the loop checks after the convergence tests whether
+    the last correction failed to shrink, ||z_i||_inf > stag_ratio *
+    ||z_(i-1)||_inf.  Then, if escalate and K < 4, A is refactored in K+1
+    words (plain LU) and the loop goes on from the current x; otherwise it
+    stops with STAGNATED.  An exactly zero pivot escalates the same way.
+    max_iter bounds the corrections over all precisions.  Returns a dict
+    with x (4, n), iters (corrections applied), status, info, history of
+    ||r||, final_words (K of the last factorisation) and escalations.
     """
     A = _c(A)
     b = _c(b)
     aw, n, _ = A.shape
+    out = dict(x=np.zeros((4, n)), iters=0, status=NONFINITE, info=0, history=[], final_words=K, escalations=0)
     if not (np.isfinite(A).all() and np.isfinite(b).all()):
-        return dict(x=np.zeros((4, n)), iters=0, status=NONFINITE, info=0, history=[])
+        return out
     norm_a = norm2(A[0])
-    LU = stage(K, A)
-    bf = round_words(K, b)
-    LU, ipiv, info = getrf_ozaki(K, LU, ozaki) if ozaki else getrf(K, LU)
+    kc = K
+    escalations = 0
+    while True:
+        LU = stage(kc, A)
+        if ozaki and kc == K:
+            LU, ipiv, info = getrf_ozaki(kc, LU, ozaki)
+        else:
+            LU, ipiv, info = getrf(kc, LU)
+        if not info or not escalate or kc == 4:
+            break
+        kc += 1
+        escalations += 1
+    out.update(final_words=kc, escalations=escalations, info=info, LU=LU, ipiv=ipiv)
     if info:
-        return dict(x=np.zeros((4, n)), iters=0, status=SINGULAR, info=info, history=[],
-                    LU=LU, ipiv=ipiv)
-    x = extend(getrs(K, LU, ipiv, bf))
+        out.update(status=SINGULAR)
+        return out
+    x = extend(getrs(kc, LU, ipiv, round_words(kc, b)))
     hist = []
     iters = 0
     status = MAX_ITER
     thresh_c = math.sqrt(n) * rtol * norm_a
-    zmax = None
+    zs = []  # ||z||_inf of the corrections since the last factorisation
     for _ in range(max_iter + 1):
         r = residual(A, x, b)
         nr = norm2(r[0])
         nx = norm2(x[0])
         hist.append(nr)
         xmax = float(np.abs(x[0]).max())
-        if nr < thresh_c * nx + atol or (zmax is not None and zmax <= ctol * xmax):
+        if nr < thresh_c * nx + atol or (zs and zs[-1] <= ctol * xmax):
             status = CONVERGED
             break
+        if stag_ratio > 0 and len(zs) >= 2 and zs[-1] > stag_ratio * zs[-2]:
+            if not escalate or kc == 4:
+                status = STAGNATED
+                break
+            while True:  # refactor in more words
+                kc += 1
+                escalations += 1
+                LU, ipiv, info = getrf(kc, stage(kc, A))
+                if not info or kc == 4:
+                    break
+            out.update(final_words=kc, escalations=escalations, info=info, LU=LU, ipiv=ipiv)
+            if info:
+                status = SINGULAR
+                break
+            zs = []
         if iters == max_iter:
             break
         e = math.frexp(float(np.abs(r[0]).max()))[1] - 1
-        rf = round_words(K, np.ldexp(r, -e))
-        z = np.ldexp(extend(getrs(K, LU, ipiv, rf)), e)
-        zmax = float(np.abs(z[0]).max())
+        rf = round_words(kc, np.ldexp(r, -e))
+        z = np.ldexp(extend(getrs(kc, LU, ipiv, rf)), e)
+        zs.append(float(np.abs(z[0]).max()))
         x = add(4, x, z)
         iters += 1
-    return dict(x=x, iters=iters, status=status, info=info, history=hist, LU=LU, ipiv=ipiv)
+    out.update(x=x, iters=iters, status=status, history=hist)
+    return out

@@ -12,6 +12,7 @@ from .bnc import (  # noqa: F401
     BNC_MAX_ITER,
     BNC_NONFINITE,
     BNC_SINGULAR,
+    BNC_STAGNATED,
     OP_ADD,
     OP_FMS,
     OP_MUL,

@@ -319,14 +319,15 @@ int bnc_refine(int64_t n, int32_t a_words, const double *A, int64_t lda, int64_t
     if (!opts)
         return fail_arg(-12, "refine: opts is NULL");
     if (opts->factor_words < 1 || opts->factor_words > 4 || opts->max_iter < 0 || !(opts->rtol >= 0) ||
-        opts->ozaki_slices < 0 || opts->ozaki_slices > OZ_SMAX ||
+        opts->ozaki_slices < 0 || opts->ozaki_slices > OZ_SMAX || (opts->escalate != 0 && opts->escalate != 1) ||
+        !(opts->stagnation_ratio >= 0) ||
         !(opts->atol >= 0) || !(opts->ctol >= 0))
         return fail_arg(-12, "refine: invalid options");
     if (!result)
         return fail_arg(-13, "refine: result is NULL");
     if (n > 16384)
         return fail_arg(BNC_ERR_UNSUPPORTED, "refine: n > 16384");
-    if (work_bytes < refine_workspace_bytes(n, opts->factor_words))
+    if (work_bytes < refine_workspace_bytes(n, opts->escalate ? 4 : opts->factor_words))
         return fail_arg(-11, "refine: workspace too small");
     switch (opts->factor_words) {
     case 1:
@@ -371,7 +372,7 @@ int bnc_refine_batched(int64_t count, const int64_t *n, const double *const *A, 
     if (!work)
         return fail_arg(-7, "refine_batched: work is NULL");
     if (!opts || opts->factor_words < 1 || opts->factor_words > 4 || opts->max_iter < 0 || !(opts->rtol >= 0) ||
-        opts->ozaki_slices != 0 ||
+        opts->ozaki_slices != 0 || opts->escalate != 0 || opts->stagnation_ratio != 0.0 ||
         !(opts->atol >= 0) || !(opts->ctol >= 0))
         return fail_arg(-9, "refine_batched: invalid options");
     if (slots < 0)
@@ -566,6 +567,8 @@ const char *bnc_status_string(int32_t status)
         return "nonfinite";
     case BNC_BAD_SIZE:
         return "bad_size";
+    case BNC_STAGNATED:
+        return "stagnated";
     default:
         return "unknown";
     }

@@ -494,11 +494,34 @@ static RefineLayout refine_layout(int64_t n, int K)
 
 size_t refine_workspace_bytes(int64_t n, int K) { return refine_layout(n, K).total; }
 
-template <int K>
-int refine_run(int64_t n, int aw, const double *A, int64_t lda, int64_t ldpa, const double *b, int64_t ldpb, double *x,
-               int64_t ldpx, void *work, const bnc_refine_opts *o, bnc_refine_result *res, hipStream_t s)
+// Dispatch a K-templated launch on the runtime word count kc (1..4).
+#define BNC_KSWITCH(kc, BODY)                     \
+    switch (kc) {                                 \
+    case 1: {                                     \
+        constexpr int KK = 1;                     \
+        BODY;                                     \
+    } break;                                      \
+    case 2: {                                     \
+        constexpr int KK = 2;                     \
+        BODY;                                     \
+    } break;                                      \
+    case 3: {                                     \
+        constexpr int KK = 3;                     \
+        BODY;                                     \
+    } break;                                      \
+    default: {                                    \
+        constexpr int KK = 4;                     \
+        BODY;                                     \
+    } break;                                      \
+    }
+
+// The refinement loop with the factor precision kc as a run-time value, so
+// that a stagnating loop can refactor in more words and go on (escalation).
+int refine_drive(int K0, int64_t n, int aw, const double *A, int64_t lda, int64_t ldpa, const double *b,
+                 int64_t ldpb, double *x, int64_t ldpx, void *work, const bnc_refine_opts *o, bnc_refine_result *res,
+                 hipStream_t s)
 {
-    const RefineLayout L = refine_layout(n, K);
+    const RefineLayout L = refine_layout(n, o->escalate ? 4 : K0);
     char *W = (char *)work;
     double *LU = (double *)(W + L.lu);
     int64_t *ipiv = (int64_t *)(W + L.ipiv);
@@ -515,6 +538,7 @@ int refine_run(int64_t n, int aw, const double *A, int64_t lda, int64_t ldpa, co
     const int64_t ldp = n * n;
 
     *res = bnc_refine_result{};
+    res->final_words = K0;
     hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, (uint64_t *)sc, (int64_t)(sizeof(Scal) / 8), (uint64_t)0);
     BNC_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_check_finite, dim3(grid1(n * n)), dim3(256), 0, s, n, n, aw, A, lda, ldpa, &sc->nonfinite);
@@ -544,36 +568,73 @@ int refine_run(int64_t n, int aw, const double *A, int64_t lda, int64_t ldpa, co
         (rc = minexp_run(n, n, lda, aw, ldpa, A, &sc->eb.a, s)) ||
         (rc = minexp_run(n, 1, n, 4, ldpb, b, &sc->eb.b, s)))
         return rc;
-    // short-precision copy and factorisation
-    if (aw == 1)
-        hipLaunchKernelGGL((k_stage<K, 1>), dim3(grid1(n * n)), dim3(256), 0, s, n, A, lda, ldpa, LU, n, ldp);
-    else
-        hipLaunchKernelGGL((k_stage<K, 4>), dim3(grid1(n * n)), dim3(256), 0, s, n, A, lda, ldpa, LU, n, ldp);
-    BNC_LAUNCH_CHECK();
-    if ((rc = getrf_run<K>(n, LU, n, ldp, ipiv, &sc->info, gscr, s, o->ozaki_slices, ozb)))
+
+    // kc-word copy of A, factorisation, pivots as a permutation, diagonal
+    // reciprocals; *info_out gets getrf's info
+    int kc = K0;
+    auto factor = [&](int oz, int64_t *info_out) -> int {
+        int rc2 = BNC_OK;
+        BNC_KSWITCH(kc, {
+            if (aw == 1)
+                hipLaunchKernelGGL((k_stage<KK, 1>), dim3(grid1(n * n)), dim3(256), 0, s, n, A, lda, ldpa, LU, n,
+                                   ldp);
+            else
+                hipLaunchKernelGGL((k_stage<KK, 4>), dim3(grid1(n * n)), dim3(256), 0, s, n, A, lda, ldpa, LU, n,
+                                   ldp);
+            BNC_LAUNCH_CHECK();
+            rc2 = getrf_run<KK>(n, LU, n, ldp, ipiv, &sc->info, gscr, s, oz, ozb);
+        });
+        if (rc2)
+            return rc2;
+        BNC_HIP(hipMemcpyAsync(&h, sc, sizeof(Scal), hipMemcpyDeviceToHost, s));
+        BNC_HIP(hipStreamSynchronize(s));
+        *info_out = h.info;
+        if (h.info)
+            return BNC_OK;
+        if ((rc2 = ipiv_to_perm(n, ipiv, perm, s)))
+            return rc2;
+        BNC_KSWITCH(kc, rc2 = diag_recip_run<KK>(n, LU, n, ldp, rd, s));
+        return rc2;
+    };
+    // v <- kc-word solve of the kc-word copy of src (scaled by 2^-e when
+    // rmax is given)
+    auto solve = [&](const double *src, int64_t lds, const unsigned long long *rmaxbits) -> int {
+        int rc2 = BNC_OK;
+        BNC_KSWITCH(kc, {
+            hipLaunchKernelGGL((k_round_scaled<KK>), dim3(grid1(n)), dim3(256), 0, s, n, src, lds, rmaxbits, r, n);
+            BNC_LAUNCH_CHECK();
+            rc2 = getrs_perm<KK>(n, LU, n, ldp, perm, rd, r, n, v, n, s);
+        });
+        return rc2;
+    };
+
+    int64_t info = 0;
+    if ((rc = factor(o->ozaki_slices, &info)))
         return rc;
-    BNC_HIP(hipMemcpyAsync(&h, sc, sizeof(Scal), hipMemcpyDeviceToHost, s));
-    BNC_HIP(hipStreamSynchronize(s));
-    res->info = h.info;
+    while (info && o->escalate && kc < 4) {
+        ++kc;
+        ++res->escalations;
+        if ((rc = factor(0, &info)))
+            return rc;
+    }
+    res->final_words = kc;
+    res->info = info;
     const double amax = bits_to_double(h.amax);
     res->a_norm = sqrt(h.asq) * ldexp(1.0, norm_exp(amax) + 1);
-    if (h.info) {
+    if (info) {
         res->status = BNC_SINGULAR;
         return zero_x();
     }
-    if ((rc = ipiv_to_perm(n, ipiv, perm, s)) || (rc = diag_recip_run<K>(n, LU, n, ldp, rd, s)))
+    // first solution in kc words, extended to quad-double
+    if ((rc = solve(b, ldpb, nullptr)))
         return rc;
-    // first solution in K words, extended to quad-double
-    hipLaunchKernelGGL((k_round_scaled<K>), dim3(grid1(n)), dim3(256), 0, s, n, b, ldpb,
-                       (const unsigned long long *)nullptr, r, n);
-    BNC_LAUNCH_CHECK();
-    if ((rc = getrs_perm<K>(n, LU, n, ldp, perm, rd, r, n, v, n, s)))
-        return rc;
-    hipLaunchKernelGGL((k_extend<K>), dim3(grid1(n)), dim3(256), 0, s, n, (const double *)v, n, x, ldpx);
+    BNC_KSWITCH(kc, hipLaunchKernelGGL((k_extend<KK>), dim3(grid1(n)), dim3(256), 0, s, n, (const double *)v, n, x,
+                                       ldpx));
     BNC_LAUNCH_CHECK();
 
     const double thresh_c = sqrt((double)n) * o->rtol * res->a_norm;
-    bool have_z = false;
+    double zlast = 0.0, zprev = 0.0;
+    int nz = 0;  // corrections since the last factorisation
     int iters = 0;
     int status = BNC_MAX_ITER;
     for (int it = 0; it <= o->max_iter; ++it) {
@@ -589,35 +650,61 @@ int refine_run(int64_t n, int aw, const double *A, int64_t lda, int64_t ldpa, co
         BNC_HIP(hipMemcpyAsync(&h, sc, sizeof(Scal), hipMemcpyDeviceToHost, s));
         BNC_HIP(hipStreamSynchronize(s));
         const double rmax = bits_to_double(h.rmax), xmax = bits_to_double(h.xmax);
-        const double zmax = bits_to_double(h.zmax);
+        if (nz > 0) {
+            zprev = zlast;
+            zlast = bits_to_double(h.zmax);
+        }
         const double nr = rmax == 0.0 ? 0.0 : sqrt(h.rsq) * ldexp(1.0, norm_exp(rmax) + 1);
         const double nx = xmax == 0.0 ? 0.0 : sqrt(h.xsq) * ldexp(1.0, norm_exp(xmax) + 1);
         res->resid_norm = nr;
         res->x_norm = nx;
         res->residual_inexact = h.inexact ? 1 : 0;
-        if (nr < thresh_c * nx + o->atol || (have_z && zmax <= o->ctol * xmax)) {
+        if (nr < thresh_c * nx + o->atol || (nz > 0 && zlast <= o->ctol * xmax)) {
             status = BNC_CONVERGED;
             break;
         }
+        if (o->stagnation_ratio > 0.0 && nz >= 2 && zlast > o->stagnation_ratio * zprev) {
+            if (!o->escalate || kc == 4) {
+                status = BNC_STAGNATED;
+                break;
+            }
+            do {
+                ++kc;
+                ++res->escalations;
+                if ((rc = factor(0, &info)))
+                    return rc;
+            } while (info && kc < 4);
+            res->final_words = kc;
+            res->info = info;
+            if (info) {
+                status = BNC_SINGULAR;
+                break;
+            }
+            nz = 0;
+        }
         if (iters == o->max_iter)
             break;
-        // K-word copy of r * 2^-e, correction solve, x <- x + 2^e z
-        hipLaunchKernelGGL((k_round_scaled<K>), dim3(grid1(n)), dim3(256), 0, s, n, (const double *)r, n,
-                           (const unsigned long long *)&sc->rmax, r, n);
-        BNC_LAUNCH_CHECK();
-        if ((rc = getrs_perm<K>(n, LU, n, ldp, perm, rd, r, n, v, n, s)))
+        // kc-word copy of r * 2^-e, correction solve, x <- x + 2^e z
+        if ((rc = solve(r, n, (const unsigned long long *)&sc->rmax)))
             return rc;
-        hipLaunchKernelGGL((k_scale_update<K>), dim3(grid1(n)), dim3(256), 0, s, n, v, n,
-                           (const unsigned long long *)&sc->rmax, x, ldpx);
+        BNC_KSWITCH(kc, hipLaunchKernelGGL((k_scale_update<KK>), dim3(grid1(n)), dim3(256), 0, s, n, v, n,
+                                           (const unsigned long long *)&sc->rmax, x, ldpx));
         BNC_LAUNCH_CHECK();
         if ((rc = absmax_run(n, 1, n, v, &sc->zmax, s)))
             return rc;
-        have_z = true;
+        ++nz;
         ++iters;
     }
     res->status = status;
     res->iters = iters;
     return BNC_OK;
+}
+
+template <int K>
+int refine_run(int64_t n, int aw, const double *A, int64_t lda, int64_t ldpa, const double *b, int64_t ldpb, double *x,
+               int64_t ldpx, void *work, const bnc_refine_opts *o, bnc_refine_result *res, hipStream_t s)
+{
+    return refine_drive(K, n, aw, A, lda, ldpa, b, ldpb, x, ldpx, work, o, res, s);
 }
 
 #define INST(K)                                                                                                    \

@@ -55,3 +55,31 @@ def test_ozaki_rejects_bad_slices_before_touching_the_device():
     assert L.bnc_getrf_ozaki(5, 8, 4, None, 4, 16, None, None, None) == -1
     # argument positions continue from n = 3
     assert L.bnc_getrf_ozaki(3, 8, -1, None, 4, 16, None, None, None) == -3
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The binding's ctypes structs have the C layout of include/bnc.h
+    (sizes and field offsets as gcc lays them out)."""
+    import subprocess
+
+    from paper_2107_12550_amd import bnc
+    structs = {"bnc_refine_opts": bnc.RefineOpts, "bnc_refine_result": bnc.RefineResult,
+               "bnc_batch_result": bnc.BatchResult}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "bnc.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
+    got = {}
+    for line in subprocess.check_output([str(exe)]).decode().splitlines():
+        c, f, v = line.split()
+        got[(c, f)] = int(v)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)

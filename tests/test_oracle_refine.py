@@ -124,3 +124,54 @@ def test_refine_failure_modes():
     Ap2 = Ap.copy()
     Ap2[0, 2, 2] = np.nan
     assert O.refine(Ap2, b, 3)["status"] == O.NONFINITE
+
+
+# ---------------------------------------------------------------------------
+# stagnation and escalation (the project's rule on top of Listing 1)
+# ---------------------------------------------------------------------------
+
+def _err_vs_ones(x):
+    from oracle import exact as X
+    return max(abs(X.value(x[:, i]) - 1) for i in range(x.shape[1]))
+
+
+def test_fp64_factor_stagnates_and_escalation_reaches_quad_double():
+    """cond(A) ~ 1e17 once rounded to binary64: with a binary64 factor the
+    contraction factor kappa * u_1 exceeds one, so the corrections stop
+    shrinking; a double-double factor has kappa * u_2 ~ 1e-15."""
+    from fractions import Fraction
+    Ap, b, exact = synth.problem("randsvd", 60, config=1, instance=5, cond=1e30)
+    assert exact
+    plain = O.refine(Ap, b, 1, max_iter=12)
+    assert plain["status"] == O.MAX_ITER
+    stag = O.refine(Ap, b, 1, max_iter=12, stag_ratio=0.5)
+    assert stag["status"] == O.STAGNATED and stag["iters"] < 12
+    esc = O.refine(Ap, b, 1, max_iter=30, stag_ratio=0.5, escalate=True)
+    assert esc["status"] == O.CONVERGED
+    assert esc["final_words"] >= 2 and esc["escalations"] == esc["final_words"] - 1
+    assert _err_vs_ones(esc["x"]) <= Fraction(10) ** -60
+
+
+def test_no_escalation_when_the_factor_suffices():
+    Ap, b, _ = synth.problem("randsvd", 60, config=1, instance=6, cond=1e3)
+    r = O.refine(Ap, b, 1, stag_ratio=0.5, escalate=True)
+    assert r["status"] == O.CONVERGED and r["final_words"] == 1 and r["escalations"] == 0
+    r0 = O.refine(Ap, b, 1)
+    np.testing.assert_array_equal(r["x"], r0["x"])
+    assert r["iters"] == r0["iters"]
+
+
+def test_zero_pivot_in_short_precision_escalates():
+    """A quad-double matrix that is exactly singular once rounded to
+    binary64 (a_11 = 1 + 2^-60 rounds to 1) but regular in double-double."""
+    from fractions import Fraction
+    A = np.zeros((4, 2, 2))
+    A[0] = np.array([[1.0, 1.0], [1.0, 1.0]]).T
+    A[1, 1, 1] = 2.0 ** -60
+    b, exact = synth.rhs_ones(A)
+    assert exact
+    r = O.refine(A, b, 1)
+    assert r["status"] == O.SINGULAR and r["info"] == 2
+    e = O.refine(A, b, 1, escalate=True)
+    assert e["status"] == O.CONVERGED and e["final_words"] == 2 and e["escalations"] == 1
+    assert _err_vs_ones(e["x"]) == Fraction(0)
