@@ -132,12 +132,14 @@ typedef struct bnc_refine_opts {
                              Batched solves take 0. */
     int32_t escalate;     /* 0 or 1: on stagnation or an exactly zero pivot,
                              refactor with one more word (plain form) and
-                             go on from the current x, up to 4 words */
+                             go on from the current x, up to 4 words.
+                             Batched solves take 0. */
     double stagnation_ratio; /* > 0: after two corrections since the last
                              factorisation, the loop stagnates when
                              ||z_i||_inf > stagnation_ratio ||z_(i-1)||_inf
                              (checked after the stopping tests); 0 disables.
-                             Batched solves take 0. */
+                             Batched solves report BNC_STAGNATED (they take
+                             escalate = 0). */
 } bnc_refine_opts;
 
 /* Outcome of the refinement loop (host struct, filled synchronously). */
@@ -236,6 +238,78 @@ int bnc_graph_destroy(void *graph_exec);
 
 /* Tick rate of the device wall clock used by bnc_batch_result, in kHz. */
 int64_t bnc_wall_clock_khz(void);
+
+/* ------------------------------------------------------------------------
+ * Learned choice of the factor precision (not in the paper: a project
+ * addition on top of its refinement loop, Sec. 2 / Listing 1).  A small
+ * network predicts from cheap binary64 features which factor precision
+ * (1..4 words) a system needs and how many corrections it will take; the
+ * escalation rule of bnc_refine_opts stays the fallback.
+ * ---------------------------------------------------------------------- */
+#define BNC_NFEATURES 24
+
+/* Workspace bytes of bnc_features for `slots` workgroups (host). */
+size_t bnc_features_workspace_size(int32_t slots);
+/* Default number of workgroups of bnc_features (two per compute unit). */
+int32_t bnc_features_default_slots(void);
+
+/*
+ * 24 binary32 features per system, features[s * 24 + f] (orders 1..256;
+ * others get zeros), each computed in binary64 and rounded:
+ *   0 log2 n;  1 log2 ||A||_F;  2-4 log2 of ||A||_1, ||A||_inf, max|a_ij|
+ *   relative to ||A||_F;  5-7 diagonal dominance |a_ii| / sum_{j!=i} |a_ij|:
+ *   log2 of its minimum and mean, fraction of rows above 1;  8 log2 of the
+ *   diagonal's 2-norm relative to ||A||_F;  9-10 log2 of the smallest over
+ *   the largest column / row 2-norm;  11 log2 ||A - A^T||_F / ||A||_F;
+ *   then a binary64 LU with partial pivoting (the bnc_getrf_d algorithm):
+ *   12 log2 max|u_ij| / max|a_ij|;  13 log2 min|u_ii| / max|u_ii|;
+ *   14 log2 max|u_ii| / ||A||_F;  15 mean log2|u_ii| - log2 max|u_ii|;
+ *   16 fraction of |u_ii| below 2^-26 max|u_ii|;  17-19 log2 of ||A||_1
+ *   times Hager's estimate of ||A^-1||_1 after 1, 2, 3 steps (Hager 1984;
+ *   Higham 1988; solves with A and A^T; an early stop repeats the last);
+ *   20 log2 ||x0||_inf ||A||_inf / ||b0||_inf and 21 log2 of the backward
+ *   error ||b0 - A x0||_inf / (||A||_inf ||x0||_inf) of the binary64
+ *   solution x0 of A x0 = b0 (b0 = leading words of b);  22 Hager steps
+ *   taken;  23 log2 max|a_ii| / max|a_ij|.  log2 of 0 is -1100; an exactly
+ *   singular binary64 factor gives 1000 + log2 ||A||_1 in 17-19, 1100 in
+ *   20 and 0 in 21-22.  Sums run in index order, so the values do not
+ *   depend on `slots`.
+ *   count, n, A, b   as bnc_refine_batched (A binary64, lda = n; b 4-plane)
+ *   features  device float[count * 24]
+ *   work      >= bnc_features_workspace_size(slots) bytes;  slots 0 = default
+ * Asynchronous on stream.
+ */
+int bnc_features(int64_t count, const int64_t *n, const double *const *A, const double *const *b, float *features,
+                 void *work, size_t work_bytes, int32_t slots, void *stream);
+
+/*
+ * Multilayer perceptron 24 -> 64 -> 64 -> 5 in binary32 with ReLU hidden
+ * layers.  params (device, bnc_mlp_param_count() floats), packed as
+ * W1[24][64] b1[64] W2[64][64] b2[64] W3[64][5] b3[5], W[i][j] mapping
+ * input i to output j.  norm (device float[48]): inputs are replaced by
+ * (x_i - norm[i]) * norm[24 + i] first.  Outputs 0-3 are the logits of the
+ * factor precision 1..4 words, output 4 predicts log2(1 + corrections).
+ */
+int32_t bnc_mlp_param_count(void);
+size_t bnc_mlp_workspace_size(int64_t batch);
+/* out: device float[batch * 5].  Asynchronous on stream. */
+int bnc_mlp_forward(int64_t batch, const float *X, const float *norm, const float *params, float *out, void *stream);
+/*
+ * Gradient of the mean loss over the batch, cross-entropy of the logits
+ * against cls (int32 in 0..3 = words - 1) plus 0.5 Huber (delta 1) of
+ * output 4 against target, with respect to params -> grads (device
+ * float[param_count]); *loss (device float) gets the mean loss.  Batch sums
+ * run in sample order (deterministic).  work >= bnc_mlp_workspace_size.
+ */
+int bnc_mlp_grad(int64_t batch, const float *X, const float *norm, const int32_t *cls, const float *target,
+                 const float *params, float *grads, float *loss, void *work, size_t work_bytes, void *stream);
+
+/* Adam step (Kingma and Ba 2015) with bias correction for step >= 1. */
+typedef struct bnc_adam_opts {
+    float lr, beta1, beta2, eps;
+    int64_t step;
+} bnc_adam_opts;
+int bnc_mlp_adam(float *params, const float *grads, float *m, float *v, const bnc_adam_opts *opts, void *stream);
 
 /*
  * r = b - A x computed exactly and rounded once to canonical quad-double

@@ -18,8 +18,11 @@ from .bnc import (  # noqa: F401
     OP_MUL,
     OP_RECIP,
     OP_ROUND4,
+    MLP,
+    NFEATURES,
     BatchSolver,
     BncError,
+    features,
     getrf,
     getrf_ozaki,
     getrs,

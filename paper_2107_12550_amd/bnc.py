@@ -38,6 +38,11 @@ class RefineResult(ctypes.Structure):
                 ("escalations", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class AdamOpts(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
+                ("step", ctypes.c_int64)]
+
+
 class BatchResult(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("info", ctypes.c_int64),
                 ("t_start", ctypes.c_uint64), ("t_end", ctypes.c_uint64), ("residual_inexact", ctypes.c_int32),
@@ -59,6 +64,20 @@ def _load() -> ctypes.CDLL:
         g.restype = ctypes.c_int
     L.bnc_getrf_ozaki.argtypes = [I32, I32, I64, VP, I64, I64, VP, VP, VP]
     L.bnc_getrf_ozaki.restype = ctypes.c_int
+    L.bnc_features_workspace_size.argtypes = [I32]
+    L.bnc_features_workspace_size.restype = ctypes.c_size_t
+    L.bnc_features_default_slots.restype = I32
+    L.bnc_features.argtypes = [I64, VP, VP, VP, VP, VP, ctypes.c_size_t, I32, VP]
+    L.bnc_features.restype = ctypes.c_int
+    L.bnc_mlp_param_count.restype = I32
+    L.bnc_mlp_workspace_size.argtypes = [I64]
+    L.bnc_mlp_workspace_size.restype = ctypes.c_size_t
+    L.bnc_mlp_forward.argtypes = [I64, VP, VP, VP, VP, VP]
+    L.bnc_mlp_forward.restype = ctypes.c_int
+    L.bnc_mlp_grad.argtypes = [I64, VP, VP, VP, VP, VP, VP, VP, VP, ctypes.c_size_t, VP]
+    L.bnc_mlp_grad.restype = ctypes.c_int
+    L.bnc_mlp_adam.argtypes = [VP, VP, VP, VP, ctypes.POINTER(AdamOpts), VP]
+    L.bnc_mlp_adam.restype = ctypes.c_int
     L.bnc_refine_workspace_size.argtypes = [I64, I32]
     L.bnc_refine_workspace_size.restype = ctypes.c_size_t
     L.bnc_refine.argtypes = [I64, I32, VP, I64, I64, VP, I64, VP, I64, VP, ctypes.c_size_t,
@@ -178,7 +197,7 @@ class BatchSolver:
     set up once; run() launches (optionally through a captured HIP graph)."""
 
     def __init__(self, As, bs, K: int, max_iter: int = 30, rtol: float = 0.0, atol: float = 0.0,
-                 ctol: float = 2.0 ** -208, slots: int = 0, order=None):
+                 ctol: float = 2.0 ** -208, slots: int = 0, order=None, stagnation_ratio: float = 0.0):
         dev = As[0].device
         self.count = len(As)
         self.As = [a.contiguous() for a in As]
@@ -200,7 +219,7 @@ class BatchSolver:
         self.slots = slots
         need = int(_lib.bnc_refine_batched_workspace_size(K, slots))
         self.work = torch.empty(need, dtype=torch.uint8, device=dev)
-        self.opts = RefineOpts(K, max_iter, rtol, atol, ctol, 0, 0, 0.0)
+        self.opts = RefineOpts(K, max_iter, rtol, atol, ctol, 0, 0, stagnation_ratio)
         self.graph = ctypes.c_void_p(None)
         self.stream = None
 
@@ -270,3 +289,76 @@ def profile_read():
     ms, fl, nl = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
     _check(_lib.bnc_profile_read(ctypes.byref(ms), ctypes.byref(fl), ctypes.byref(nl)), "profile_read")
     return ms.value, fl.value, nl.value
+
+
+# --------------------------------------------------------------------------
+# learned choice of the factor precision
+# --------------------------------------------------------------------------
+NFEATURES = 24
+
+
+def _vp(t: torch.Tensor):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def features(As, bs, slots: int = 0) -> torch.Tensor:
+    """bnc_features over lists of (1, n, n) binary64 matrices and (4, n)
+    right-hand sides (CUDA tensors); returns a (count, 24) float32 tensor."""
+    dev = As[0].device
+    count = len(As)
+    As = [a.contiguous() for a in As]
+    bs = [b.contiguous() for b in bs]
+    n = torch.tensor([int(a.shape[-1]) for a in As], dtype=torch.int64, device=dev)
+    Ap = torch.tensor([a.data_ptr() for a in As], dtype=torch.int64, device=dev)
+    bp = torch.tensor([b.data_ptr() for b in bs], dtype=torch.int64, device=dev)
+    F = torch.empty((count, NFEATURES), dtype=torch.float32, device=dev)
+    need = int(_lib.bnc_features_workspace_size(slots))
+    work = torch.empty(need, dtype=torch.uint8, device=dev)
+    _check(_lib.bnc_features(count, _vp(n), _vp(Ap), _vp(bp), _vp(F), _vp(work), need, slots, _stream()),
+           "features")
+    return F
+
+
+class MLP:
+    """Parameters, input normalisation and Adam moments of the 24-64-64-5
+    network on the device; every computation runs in the library's kernels
+    (bnc_mlp_forward / bnc_mlp_grad / bnc_mlp_adam)."""
+
+    def __init__(self, params: torch.Tensor, norm: torch.Tensor):
+        self.nparam = int(_lib.bnc_mlp_param_count())
+        if params.numel() != self.nparam or norm.numel() != 2 * NFEATURES:
+            raise BncError("MLP: wrong parameter or normalisation size")
+        self.params = params.to(torch.float32).contiguous()
+        self.norm = norm.to(torch.float32).contiguous()
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.grads = torch.zeros_like(self.params)
+        self.step = 0
+        self._work = None
+
+    def forward(self, X: torch.Tensor) -> torch.Tensor:
+        X = X.to(torch.float32).contiguous()
+        out = torch.empty((X.shape[0], 5), dtype=torch.float32, device=X.device)
+        _check(_lib.bnc_mlp_forward(X.shape[0], _vp(X), _vp(self.norm), _vp(self.params), _vp(out), _stream()),
+               "mlp_forward")
+        return out
+
+    def grad(self, X: torch.Tensor, cls: torch.Tensor, target: torch.Tensor) -> torch.Tensor:
+        """Fills self.grads; returns the mean loss as a 1-element tensor."""
+        X = X.to(torch.float32).contiguous()
+        cls = cls.to(torch.int32).contiguous()
+        target = target.to(torch.float32).contiguous()
+        B = X.shape[0]
+        need = int(_lib.bnc_mlp_workspace_size(B))
+        if self._work is None or self._work.numel() < need:
+            self._work = torch.empty(need, dtype=torch.uint8, device=X.device)
+        loss = torch.empty(1, dtype=torch.float32, device=X.device)
+        _check(_lib.bnc_mlp_grad(B, _vp(X), _vp(self.norm), _vp(cls), _vp(target), _vp(self.params), _vp(self.grads),
+                                 _vp(loss), _vp(self._work), self._work.numel(), _stream()), "mlp_grad")
+        return loss
+
+    def adam(self, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+        self.step += 1
+        o = AdamOpts(lr, beta1, beta2, eps, self.step)
+        _check(_lib.bnc_mlp_adam(_vp(self.params), _vp(self.grads), _vp(self.m), _vp(self.v), ctypes.byref(o),
+                                 _stream()), "mlp_adam")

@@ -7,7 +7,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["getrf.hip", "ozaki.hip", "getrs.hip", "refine.hip", "batch.hip", "api.hip"]
+SOURCES = ["getrf.hip", "ozaki.hip", "getrs.hip", "refine.hip", "batch.hip", "selector.hip", "api.hip"]
 LIB = os.path.join(HERE, "libbnc.so")
 ARCH = "gfx950"
 FLAGS = [

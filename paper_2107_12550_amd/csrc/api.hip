@@ -31,6 +31,18 @@ int batch_run(int64_t count, const int64_t *n, const double *const *A, const dou
               hipStream_t s);
 size_t batch_workspace_bytes(int K, int slots);
 int batch_default_slots(int K);
+size_t features_workspace_bytes(int slots);
+int features_default_slots();
+int features_run(int64_t count, const int64_t *n, const double *const *A, const double *const *b, float *F,
+                 void *work, int slots, hipStream_t s);
+int mlp_param_count();
+size_t mlp_workspace_bytes(int64_t B);
+int mlp_forward_run(int64_t B, const float *X, const float *norm, const float *P, float *O, hipStream_t s);
+int mlp_grad_run(int64_t B, const float *X, const float *norm, const int32_t *cls, const float *tgt, const float *P,
+                 float *G, float *loss, void *work, hipStream_t s);
+int mlp_adam_run(float *P, const float *G, float *M, float *V, float lr, float b1, float b2, float eps, int64_t step,
+                 hipStream_t s);
+
 size_t refine_workspace_bytes(int64_t n, int K);
 size_t residual_scratch_bytes(int64_t n);
 int residual_run(int64_t n, int aw, const double *A, int64_t lda, int64_t ldpa, const double *x, int64_t ldx,
@@ -372,7 +384,7 @@ int bnc_refine_batched(int64_t count, const int64_t *n, const double *const *A, 
     if (!work)
         return fail_arg(-7, "refine_batched: work is NULL");
     if (!opts || opts->factor_words < 1 || opts->factor_words > 4 || opts->max_iter < 0 || !(opts->rtol >= 0) ||
-        opts->ozaki_slices != 0 || opts->escalate != 0 || opts->stagnation_ratio != 0.0 ||
+        opts->ozaki_slices != 0 || opts->escalate != 0 || !(opts->stagnation_ratio >= 0) ||
         !(opts->atol >= 0) || !(opts->ctol >= 0))
         return fail_arg(-9, "refine_batched: invalid options");
     if (slots < 0)
@@ -552,6 +564,66 @@ int bnc_profile_read(double *ms, double *flops, int64_t *launches)
     if (flops)
         *flops = tf;
     return BNC_OK;
+}
+
+size_t bnc_features_workspace_size(int32_t slots)
+{
+    if (slots < 0)
+        return 0;
+    return features_workspace_bytes(slots ? slots : features_default_slots());
+}
+
+int32_t bnc_features_default_slots(void) { return features_default_slots(); }
+
+int bnc_features(int64_t count, const int64_t *n, const double *const *A, const double *const *b, float *features,
+                 void *work, size_t work_bytes, int32_t slots, void *stream)
+{
+    if (count < 0)
+        return fail_arg(-1, "features: count < 0");
+    if (count > 0 && (!n || !A || !b || !features))
+        return fail_arg(!n ? -2 : !A ? -3 : !b ? -4 : -5, "features: NULL pointer");
+    if (slots < 0)
+        return fail_arg(-8, "features: slots < 0");
+    const int sl = slots ? slots : features_default_slots();
+    if (!work || work_bytes < features_workspace_bytes(sl))
+        return fail_arg(-7, "features: workspace too small");
+    return features_run(count, n, A, b, features, work, sl, S(stream));
+}
+
+int32_t bnc_mlp_param_count(void) { return mlp_param_count(); }
+
+size_t bnc_mlp_workspace_size(int64_t batch) { return batch < 0 ? 0 : mlp_workspace_bytes(batch); }
+
+int bnc_mlp_forward(int64_t batch, const float *X, const float *norm, const float *params, float *out, void *stream)
+{
+    if (batch < 0)
+        return fail_arg(-1, "mlp_forward: batch < 0");
+    if (batch > 0 && (!X || !norm || !params || !out))
+        return fail_arg(!X ? -2 : !norm ? -3 : !params ? -4 : -5, "mlp_forward: NULL pointer");
+    return mlp_forward_run(batch, X, norm, params, out, S(stream));
+}
+
+int bnc_mlp_grad(int64_t batch, const float *X, const float *norm, const int32_t *cls, const float *target,
+                 const float *params, float *grads, float *loss, void *work, size_t work_bytes, void *stream)
+{
+    if (batch < 1)
+        return fail_arg(-1, "mlp_grad: batch < 1");
+    if (!X || !norm || !cls || !target || !params || !grads || !loss)
+        return fail_arg(!X ? -2 : !norm ? -3 : !cls ? -4 : !target ? -5 : !params ? -6 : !grads ? -7 : -8,
+                        "mlp_grad: NULL pointer");
+    if (!work || work_bytes < mlp_workspace_bytes(batch))
+        return fail_arg(-9, "mlp_grad: workspace too small");
+    return mlp_grad_run(batch, X, norm, cls, target, params, grads, loss, work, S(stream));
+}
+
+int bnc_mlp_adam(float *params, const float *grads, float *m, float *v, const bnc_adam_opts *opts, void *stream)
+{
+    if (!params || !grads || !m || !v)
+        return fail_arg(!params ? -1 : !grads ? -2 : !m ? -3 : -4, "mlp_adam: NULL pointer");
+    if (!opts || opts->step < 1 || !(opts->lr >= 0) || !(opts->beta1 >= 0 && opts->beta1 < 1) ||
+        !(opts->beta2 >= 0 && opts->beta2 < 1) || !(opts->eps > 0))
+        return fail_arg(-5, "mlp_adam: invalid options");
+    return mlp_adam_run(params, grads, m, v, opts->lr, opts->beta1, opts->beta2, opts->eps, opts->step, S(stream));
 }
 
 const char *bnc_status_string(int32_t status)

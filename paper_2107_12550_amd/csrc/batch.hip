@@ -612,7 +612,7 @@ __global__ void __launch_bounds__(BT)
         }();
         const double thresh_c = sqrt((double)n) * o.rtol * anorm;
         bool have_z = false;
-        double zmax = 0.0;
+        double zmax = 0.0, zprev = 0.0;
         int iters = 0, status = BNC_MAX_ITER, inexact = 0;
         for (int it = 0; it <= o.max_iter; ++it) {
             // x bounds
@@ -670,6 +670,10 @@ __global__ void __launch_bounds__(BT)
                 status = BNC_CONVERGED;
                 break;
             }
+            if (o.stagnation_ratio > 0.0 && iters >= 2 && zmax > o.stagnation_ratio * zprev) {
+                status = BNC_STAGNATED;
+                break;
+            }
             if (iters == o.max_iter)
                 break;
             // K-word copy of r * 2^-e, correction, x <- x + 2^e z
@@ -698,6 +702,7 @@ __global__ void __launch_bounds__(BT)
                 for (int w = 0; w < 4; ++w)
                     S.xq[w][t] = oo[w];
             }
+            zprev = zmax;
             zmax = wg_max(fabs(z0), S.red);
             have_z = true;
             ++iters;
