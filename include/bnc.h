@@ -250,7 +250,8 @@ int64_t bnc_wall_clock_khz(void);
 
 /* Workspace bytes of bnc_features for `slots` workgroups (host). */
 size_t bnc_features_workspace_size(int32_t slots);
-/* Default number of workgroups of bnc_features (two per compute unit). */
+/* Default number of workgroups of bnc_features (as many as fit on the
+ * device at once). */
 int32_t bnc_features_default_slots(void);
 
 /*
@@ -274,13 +275,15 @@ int32_t bnc_features_default_slots(void);
  *   singular binary64 factor gives 1000 + log2 ||A||_1 in 17-19, 1100 in
  *   20 and 0 in 21-22.  Sums run in index order, so the values do not
  *   depend on `slots`.
- *   count, n, A, b   as bnc_refine_batched (A binary64, lda = n; b 4-plane)
+ *   count, n, A, b, order   as bnc_refine_batched (A binary64, lda = n;
+ *             b 4-plane; order: the order systems are taken in, NULL =
+ *             0..count-1, largest first balances the load)
  *   features  device float[count * 24]
  *   work      >= bnc_features_workspace_size(slots) bytes;  slots 0 = default
  * Asynchronous on stream.
  */
-int bnc_features(int64_t count, const int64_t *n, const double *const *A, const double *const *b, float *features,
-                 void *work, size_t work_bytes, int32_t slots, void *stream);
+int bnc_features(int64_t count, const int64_t *n, const double *const *A, const double *const *b,
+                 const int32_t *order, float *features, void *work, size_t work_bytes, int32_t slots, void *stream);
 
 /*
  * Multilayer perceptron 24 -> 64 -> 64 -> 5 in binary32 with ReLU hidden

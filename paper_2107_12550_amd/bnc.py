@@ -67,7 +67,7 @@ def _load() -> ctypes.CDLL:
     L.bnc_features_workspace_size.argtypes = [I32]
     L.bnc_features_workspace_size.restype = ctypes.c_size_t
     L.bnc_features_default_slots.restype = I32
-    L.bnc_features.argtypes = [I64, VP, VP, VP, VP, VP, ctypes.c_size_t, I32, VP]
+    L.bnc_features.argtypes = [I64, VP, VP, VP, VP, VP, VP, ctypes.c_size_t, I32, VP]
     L.bnc_features.restype = ctypes.c_int
     L.bnc_mlp_param_count.restype = I32
     L.bnc_mlp_workspace_size.argtypes = [I64]
@@ -308,14 +308,16 @@ def features(As, bs, slots: int = 0) -> torch.Tensor:
     count = len(As)
     As = [a.contiguous() for a in As]
     bs = [b.contiguous() for b in bs]
-    n = torch.tensor([int(a.shape[-1]) for a in As], dtype=torch.int64, device=dev)
+    ns = [int(a.shape[-1]) for a in As]
+    n = torch.tensor(ns, dtype=torch.int64, device=dev)
     Ap = torch.tensor([a.data_ptr() for a in As], dtype=torch.int64, device=dev)
     bp = torch.tensor([b.data_ptr() for b in bs], dtype=torch.int64, device=dev)
+    order = torch.tensor(sorted(range(count), key=lambda i: -ns[i]), dtype=torch.int32, device=dev)
     F = torch.empty((count, NFEATURES), dtype=torch.float32, device=dev)
     need = int(_lib.bnc_features_workspace_size(slots))
     work = torch.empty(need, dtype=torch.uint8, device=dev)
-    _check(_lib.bnc_features(count, _vp(n), _vp(Ap), _vp(bp), _vp(F), _vp(work), need, slots, _stream()),
-           "features")
+    _check(_lib.bnc_features(count, _vp(n), _vp(Ap), _vp(bp), _vp(order), _vp(F), _vp(work), need, slots,
+                             _stream()), "features")
     return F
 
 

@@ -33,8 +33,8 @@ size_t batch_workspace_bytes(int K, int slots);
 int batch_default_slots(int K);
 size_t features_workspace_bytes(int slots);
 int features_default_slots();
-int features_run(int64_t count, const int64_t *n, const double *const *A, const double *const *b, float *F,
-                 void *work, int slots, hipStream_t s);
+int features_run(int64_t count, const int64_t *n, const double *const *A, const double *const *b,
+                 const int32_t *order, float *F, void *work, int slots, hipStream_t s);
 int mlp_param_count();
 size_t mlp_workspace_bytes(int64_t B);
 int mlp_forward_run(int64_t B, const float *X, const float *norm, const float *P, float *O, hipStream_t s);
@@ -575,19 +575,19 @@ size_t bnc_features_workspace_size(int32_t slots)
 
 int32_t bnc_features_default_slots(void) { return features_default_slots(); }
 
-int bnc_features(int64_t count, const int64_t *n, const double *const *A, const double *const *b, float *features,
-                 void *work, size_t work_bytes, int32_t slots, void *stream)
+int bnc_features(int64_t count, const int64_t *n, const double *const *A, const double *const *b,
+                 const int32_t *order, float *features, void *work, size_t work_bytes, int32_t slots, void *stream)
 {
     if (count < 0)
         return fail_arg(-1, "features: count < 0");
     if (count > 0 && (!n || !A || !b || !features))
-        return fail_arg(!n ? -2 : !A ? -3 : !b ? -4 : -5, "features: NULL pointer");
+        return fail_arg(!n ? -2 : !A ? -3 : !b ? -4 : -6, "features: NULL pointer");
     if (slots < 0)
-        return fail_arg(-8, "features: slots < 0");
+        return fail_arg(-9, "features: slots < 0");
     const int sl = slots ? slots : features_default_slots();
     if (!work || work_bytes < features_workspace_bytes(sl))
         return fail_arg(-7, "features: workspace too small");
-    return features_run(count, n, A, b, features, work, sl, S(stream));
+    return features_run(count, n, A, b, order, features, work, sl, S(stream));
 }
 
 int32_t bnc_mlp_param_count(void) { return mlp_param_count(); }

@@ -25,6 +25,7 @@ constexpr int FT = 256;     // threads per workgroup
 constexpr int FNMAX = 256;  // largest order
 constexpr int NFEAT = 24;
 constexpr int HAGER_STEPS = 3;
+constexpr int FB = 8;       // LU panel width
 constexpr double LG_CAP = 1100.0;
 
 struct FeatLds {
@@ -34,9 +35,11 @@ struct FeatLds {
     double c[FNMAX];
     double d[FNMAX];
     double e[FNMAX];
-    double rv[FT];      // reduction scratch (values)
-    int ri[FT];         // reduction scratch (indices)
+    double rv[FT / 64]; // reduction scratch: one value per wave
+    int ri[FT / 64];
     int ipiv[FNMAX];
+    double prow[FB], rowk[FB], rowp[FB];  // pivot row and the two swapped rows of a panel
+    double ub[FB][FNMAX];                 // the panel's rows of U12
     double bc[4];
     int s_i[4];
 };
@@ -49,19 +52,21 @@ __device__ __forceinline__ double lg(double x)
     return v > LG_CAP ? LG_CAP : (v < -LG_CAP ? -LG_CAP : v);
 }
 
-// exact maximum over v[0..n) of the threads' values (n <= FT); every thread
-// gets it
+// exact maximum of the threads' values (every thread gets it): a
+// butterfly inside each wave, then the four wave results in order
 __device__ double wg_max_exact(double v, FeatLds &S)
 {
-    const int t = threadIdx.x;
-    S.rv[t] = v;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        v = fmax(v, __shfl_xor(v, off, 64));
+    if (lane == 0)
+        S.rv[wave] = v;
     __syncthreads();
-    for (int off = FT / 2; off > 0; off >>= 1) {
-        if (t < off)
-            S.rv[t] = fmax(S.rv[t], S.rv[t + off]);
-        __syncthreads();
-    }
-    const double r = S.rv[0];
+    double r = S.rv[0];
+#pragma unroll
+    for (int w = 1; w < FT / 64; ++w)
+        r = fmax(r, S.rv[w]);
     __syncthreads();
     return r;
 }
@@ -74,24 +79,32 @@ __device__ double wg_min_exact(double v, FeatLds &S)
 // arg-maximum of key (ties: smallest index; keys < 0 never win)
 __device__ int wg_argmax(double key, FeatLds &S)
 {
-    const int t = threadIdx.x;
-    S.rv[t] = key;
-    S.ri[t] = t;
-    __syncthreads();
-    for (int off = FT / 2; off > 0; off >>= 1) {
-        if (t < off) {
-            const double k2 = S.rv[t + off];
-            const int i2 = S.ri[t + off];
-            if (k2 > S.rv[t] || (k2 == S.rv[t] && i2 < S.ri[t])) {
-                S.rv[t] = k2;
-                S.ri[t] = i2;
-            }
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    int idx = t;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const double k2 = __shfl_xor(key, off, 64);
+        const int i2 = __shfl_xor(idx, off, 64);
+        if (k2 > key || (k2 == key && i2 < idx)) {
+            key = k2;
+            idx = i2;
         }
-        __syncthreads();
     }
-    const int r = S.ri[0];
+    if (lane == 0) {
+        S.rv[wave] = key;
+        S.ri[wave] = idx;
+    }
     __syncthreads();
-    return r;
+    double bk = S.rv[0];
+    int bi = S.ri[0];
+#pragma unroll
+    for (int w = 1; w < FT / 64; ++w)
+        if (S.rv[w] > bk || (S.rv[w] == bk && S.ri[w] < bi)) {
+            bk = S.rv[w];
+            bi = S.ri[w];
+        }
+    __syncthreads();
+    return bi;
 }
 
 // sum of p[0..n) in index order (thread 0), broadcast
@@ -132,6 +145,8 @@ __device__ __forceinline__ double recip1(double a)
 // S.ipiv: swaps in order, forward substitution with the unit lower factor
 // (increasing k), backward substitution x_k = y_k (1/u_kk) then
 // y_i -= u_ik x_k (decreasing k)
+constexpr int PF = 8;  // substitution steps whose factor entries are loaded together
+
 __device__ void lu_solve(const double *W, int n, FeatLds &S)
 {
     const int t = threadIdx.x;
@@ -145,21 +160,50 @@ __device__ void lu_solve(const double *W, int n, FeatLds &S)
             }
         }
     __syncthreads();
-    for (int k = 0; k < n; ++k) {
-        const double yk = S.y[k];
-        if (t > k && t < n)
-            S.y[t] = fms1(S.y[t], W[(int64_t)k * n + t], yk);
-        __syncthreads();
+    for (int k0 = 0; k0 < n; k0 += PF) {
+        double l[PF];
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int k = k0 + q;
+            l[q] = (k < n && t > k && t < n) ? W[(int64_t)k * n + t] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int k = k0 + q;
+            if (k < n) {
+                const double yk = S.y[k];
+                if (t > k && t < n)
+                    S.y[t] = fms1(S.y[t], l[q], yk);
+                __syncthreads();
+            }
+        }
     }
-    for (int k = n - 1; k >= 0; --k) {
-        if (t == 0)
-            S.y[k] = mul1(S.y[k], recip1(W[(int64_t)k * n + k]));
-        __syncthreads();
-        const double xk = S.y[k];
-        if (t < k)
-            S.y[t] = fms1(S.y[t], W[(int64_t)k * n + t], xk);
-        __syncthreads();
+    // every thread forms x_k from y_k; the finished x_k go to S.d so that
+    // no thread overwrites y_k while another still reads it
+    for (int k0 = n - 1; k0 >= 0; k0 -= PF) {
+        double u[PF], d[PF];
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int k = k0 - q;
+            u[q] = (k >= 0 && t < k) ? W[(int64_t)k * n + t] : 0.0;
+            d[q] = k >= 0 ? W[(int64_t)k * n + k] : 1.0;
+        }
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int k = k0 - q;
+            if (k >= 0) {
+                const double xk = mul1(S.y[k], recip1(d[q]));
+                if (t < k)
+                    S.y[t] = fms1(S.y[t], u[q], xk);
+                else if (t == k)
+                    S.d[t] = xk;
+                __syncthreads();
+            }
+        }
     }
+    if (t < n)
+        S.y[t] = S.d[t];
+    __syncthreads();
 }
 
 // S.y <- A^-T S.y: U^T w = c (forward: w_k = w_k (1/u_kk), then
@@ -168,20 +212,47 @@ __device__ void lu_solve(const double *W, int n, FeatLds &S)
 __device__ void lu_solve_t(const double *W, int n, FeatLds &S)
 {
     const int t = threadIdx.x;
-    for (int k = 0; k < n; ++k) {
-        if (t == 0)
-            S.y[k] = mul1(S.y[k], recip1(W[(int64_t)k * n + k]));
-        __syncthreads();
-        const double wk = S.y[k];
-        if (t > k && t < n)
-            S.y[t] = fms1(S.y[t], W[(int64_t)t * n + k], wk);
-        __syncthreads();
+    for (int k0 = 0; k0 < n; k0 += PF) {
+        double u[PF], d[PF];
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int k = k0 + q;
+            u[q] = (k < n && t > k && t < n) ? W[(int64_t)t * n + k] : 0.0;
+            d[q] = k < n ? W[(int64_t)k * n + k] : 1.0;
+        }
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int k = k0 + q;
+            if (k < n) {
+                const double wk = mul1(S.y[k], recip1(d[q]));
+                if (t > k && t < n)
+                    S.y[t] = fms1(S.y[t], u[q], wk);
+                else if (t == k)
+                    S.d[t] = wk;
+                __syncthreads();
+            }
+        }
     }
-    for (int k = n - 1; k >= 0; --k) {
-        const double vk = S.y[k];
-        if (t < k)
-            S.y[t] = fms1(S.y[t], W[(int64_t)t * n + k], vk);
-        __syncthreads();
+    if (t < n)
+        S.y[t] = S.d[t];
+    __syncthreads();
+    for (int k0 = n - 1; k0 >= 0; k0 -= PF) {
+        double l[PF];
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int k = k0 - q;
+            l[q] = (k >= 0 && t < k) ? W[(int64_t)t * n + k] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int k = k0 - q;
+            if (k >= 0) {
+                const double vk = S.y[k];
+                if (t < k)
+                    S.y[t] = fms1(S.y[t], l[q], vk);
+                __syncthreads();
+            }
+        }
     }
     if (t == 0)
         for (int k = n - 1; k >= 0; --k) {
@@ -197,12 +268,21 @@ __device__ void lu_solve_t(const double *W, int n, FeatLds &S)
 
 __global__ void __launch_bounds__(FT)
     k_features(int64_t count, const int64_t *__restrict__ nn, const double *const *__restrict__ As,
-               const double *const *__restrict__ bs, float *__restrict__ F, double *__restrict__ work)
+               const double *const *__restrict__ bs, const int32_t *__restrict__ order, float *__restrict__ F,
+               unsigned *__restrict__ queue, double *__restrict__ work)
 {
     __shared__ FeatLds S;
     const int t = threadIdx.x;
     double *W = work + (size_t)blockIdx.x * FNMAX * FNMAX;
-    for (int64_t sys = blockIdx.x; sys < count; sys += gridDim.x) {
+    for (;;) {
+        if (t == 0)
+            S.s_i[0] = (int)atomicAdd(queue, 1u);
+        __syncthreads();
+        const int64_t qi = S.s_i[0];
+        __syncthreads();
+        if (qi >= count)
+            break;
+        const int64_t sys = order ? order[qi] : qi;
         const int64_t n64 = nn[sys];
         float *out = F + sys * NFEAT;
         if (n64 < 1 || n64 > FNMAX) {
@@ -221,6 +301,7 @@ __global__ void __launch_bounds__(FT)
         // ---- statistics of A: thread t as row t and as column t
         double rowabs = 0.0, rowsq = 0.0, off = 0.0, colabs = 0.0, colsq = 0.0, symsq = 0.0, amax_t = 0.0;
         if (t < n) {
+#pragma unroll 4
             for (int j = 0; j < n; ++j) {
                 const double v = A[(int64_t)j * n + t];
                 rowabs += fabs(v);
@@ -229,6 +310,7 @@ __global__ void __launch_bounds__(FT)
                     off += fabs(v);
                 amax_t = fmax(amax_t, fabs(v));
             }
+#pragma unroll 4
             for (int i = 0; i < n; ++i) {
                 const double v = A[(int64_t)t * n + i];
                 const double d = v - A[(int64_t)i * n + t];
@@ -271,34 +353,116 @@ __global__ void __launch_bounds__(FT)
         f[10] = 0.5 * (lg(wmin) - lg(wmax));
         f[11] = lg(sqrt(sym2) / fro);
 
-        // ---- binary64 LU with partial pivoting in W
+        // ---- binary64 LU with partial pivoting in W, in panels of FB
+        //      columns: every entry still sees its updates one by one in
+        //      increasing k, as in the unblocked algorithm (row swaps
+        //      commute with the updates)
         for (int e = t; e < n * n; e += FT)
             W[e] = A[e];
         __syncthreads();
         int info = 0;
-        for (int k = 0; k < n; ++k) {
-            const int p = wg_argmax((t >= k && t < n) ? fabs(W[(int64_t)k * n + t]) : -1.0, S);
-            if (t == 0)
-                S.ipiv[k] = p;
-            if (p != k)
-                for (int j = t; j < n; j += FT) {
-                    const double tmp = W[(int64_t)j * n + k];
-                    W[(int64_t)j * n + k] = W[(int64_t)j * n + p];
-                    W[(int64_t)j * n + p] = tmp;
+        for (int j0 = 0; j0 < n; j0 += FB) {
+            const int jb = n - j0 < FB ? n - j0 : FB;
+            double pr[FB];  // row t of the panel
+#pragma unroll
+            for (int c = 0; c < FB; ++c)
+                pr[c] = (t < n && c < jb) ? W[(int64_t)(j0 + c) * n + t] : 0.0;
+            unsigned zmask = 0;
+#pragma unroll
+            for (int c = 0; c < FB; ++c) {
+                if (c < jb) {
+                    const int k = j0 + c;
+                    const int p = wg_argmax((t >= k && t < n) ? fabs(pr[c]) : -1.0, S);
+                    if (t == 0)
+                        S.ipiv[k] = p;
+                    if (p != k) {
+                        if (t == p)
+#pragma unroll
+                            for (int q = 0; q < FB; ++q)
+                                S.rowp[q] = pr[q];
+                        if (t == k)
+#pragma unroll
+                            for (int q = 0; q < FB; ++q)
+                                S.rowk[q] = pr[q];
+                        __syncthreads();
+                        if (t == p)
+#pragma unroll
+                            for (int q = 0; q < FB; ++q)
+                                pr[q] = S.rowk[q];
+                        if (t == k)
+#pragma unroll
+                            for (int q = 0; q < FB; ++q)
+                                pr[q] = S.rowp[q];
+                    }
+                    if (t == k)
+#pragma unroll
+                        for (int q = 0; q < FB; ++q)
+                            S.prow[q] = pr[q];
+                    __syncthreads();
+                    const double piv = S.prow[c];
+                    if (piv == 0.0) {
+                        zmask |= 1u << c;
+                        if (info == 0)
+                            info = k + 1;
+                    } else if (t > k && t < n) {
+                        pr[c] = mul1(pr[c], recip1(piv));
+#pragma unroll
+                        for (int q = c + 1; q < FB; ++q)
+                            if (q < jb)
+                                pr[q] = fms1(pr[q], pr[c], S.prow[q]);
+                    }
+                    __syncthreads();
                 }
-            __syncthreads();
-            const double piv = W[(int64_t)k * n + k];
-            if (piv == 0.0) {
-                if (info == 0)
-                    info = k + 1;
-                continue;
             }
-            const double r = recip1(piv);
-            if (t > k && t < n) {
-                const double l = mul1(W[(int64_t)k * n + t], r);
-                W[(int64_t)k * n + t] = l;
-                for (int j = k + 1; j < n; ++j)
-                    W[(int64_t)j * n + t] = fms1(W[(int64_t)j * n + t], l, W[(int64_t)j * n + k]);
+#pragma unroll
+            for (int c = 0; c < FB; ++c)
+                if (t < n && c < jb)
+                    W[(int64_t)(j0 + c) * n + t] = pr[c];
+            // the panel's swaps on the other columns, in order
+            for (int j = t; j < n; j += FT)
+                if (j < j0 || j >= j0 + jb)
+                    for (int c = 0; c < jb; ++c) {
+                        const int k = j0 + c, p = S.ipiv[k];
+                        if (p != k) {
+                            const double tmp = W[(int64_t)j * n + k];
+                            W[(int64_t)j * n + k] = W[(int64_t)j * n + p];
+                            W[(int64_t)j * n + p] = tmp;
+                        }
+                    }
+            __syncthreads();
+            // U12: forward substitution with the panel's unit lower block;
+            // the finished rows also go to LDS for the trailing update
+            for (int j = j0 + jb + t; j < n; j += FT) {
+                double u[FB];
+#pragma unroll
+                for (int c = 0; c < FB; ++c)
+                    u[c] = c < jb ? W[(int64_t)j * n + j0 + c] : 0.0;
+#pragma unroll
+                for (int c = 0; c < FB; ++c)
+                    if (c < jb && !((zmask >> c) & 1u))
+#pragma unroll
+                        for (int q = c + 1; q < FB; ++q)
+                            if (q < jb)
+                                u[q] = fms1(u[q], W[(int64_t)(j0 + c) * n + j0 + q], u[c]);
+#pragma unroll
+                for (int c = 0; c < FB; ++c)
+                    if (c < jb) {
+                        W[(int64_t)j * n + j0 + c] = u[c];
+                        S.ub[c][j] = u[c];
+                    }
+            }
+            __syncthreads();
+            // trailing rows: a_tj -= l_tk u_kj for k = j0.. in order
+            if (t >= j0 + jb && t < n) {
+#pragma unroll 4
+                for (int j = j0 + jb; j < n; ++j) {
+                    double w = W[(int64_t)j * n + t];
+#pragma unroll
+                    for (int c = 0; c < FB; ++c)
+                        if (c < jb && !((zmask >> c) & 1u))
+                            w = fms1(w, pr[c], S.ub[c][j]);
+                    W[(int64_t)j * n + t] = w;
+                }
             }
             __syncthreads();
         }
@@ -397,24 +561,37 @@ __global__ void __launch_bounds__(FT)
     }
 }
 
-size_t features_workspace_bytes(int slots) { return (size_t)slots * FNMAX * FNMAX * sizeof(double); }
+// workspace: the queue counter (256 bytes), then one n x n matrix per slot
+size_t features_workspace_bytes(int slots) { return 256 + (size_t)slots * FNMAX * FNMAX * sizeof(double); }
+
+__global__ void k_feat_queue_reset(unsigned *q)
+{
+    if (threadIdx.x == 0)
+        *q = 0u;
+}
 
 int features_default_slots()
 {
-    int dev = 0, ncu = 0;
+    int dev = 0, ncu = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return 256;
-    return 2 * ncu;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)k_features, FT, 0) != hipSuccess || per < 1)
+        per = 1;
+    return per * ncu;
 }
 
-int features_run(int64_t count, const int64_t *n, const double *const *A, const double *const *b, float *F,
-                 void *work, int slots, hipStream_t s)
+int features_run(int64_t count, const int64_t *n, const double *const *A, const double *const *b,
+                 const int32_t *order, float *F, void *work, int slots, hipStream_t s)
 {
     if (count == 0)
         return BNC_OK;
+    unsigned *queue = (unsigned *)work;
+    double *ws = (double *)((char *)work + 256);
     const int64_t g = count < slots ? count : slots;
-    hipLaunchKernelGGL(k_features, dim3((unsigned)g), dim3(FT), 0, s, count, n, A, b, F, (double *)work);
+    hipLaunchKernelGGL(k_feat_queue_reset, dim3(1), dim3(64), 0, s, queue);
+    BNC_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_features, dim3((unsigned)g), dim3(FT), 0, s, count, n, A, b, order, F, queue, ws);
     BNC_LAUNCH_CHECK();
     return BNC_OK;
 }

@@ -101,13 +101,14 @@ def _one_blas_thread():
 
 
 def batch(count: int, n_lo: int, n_hi: int, lc_lo: float, lc_hi: float, config: int = 3, workers: int = 1,
-          progress=None):
+          progress=None, first: int = 0):
     """`count` independent randsvd systems: system i draws n ~ U{n_lo..n_hi}
-    and cond = 10^U(lc_lo, lc_hi) from its own seed (config, i), so the batch
-    does not depend on the number of worker processes.  Returns lists of
-    A planes (1, n, n), b (4, n), exact flags and conds.  `progress(done)` is
-    called every 512 systems."""
-    jobs = [(config, i, n_lo, n_hi, lc_lo, lc_hi) for i in range(count)]
+    and cond = 10^U(lc_lo, lc_hi) from its own seed (config, first + i), so
+    the batch does not depend on the number of worker processes or on how a
+    long stream is cut into batches.  Returns lists of A planes (1, n, n),
+    b (4, n), exact flags and conds.  `progress(done)` is called every 512
+    systems."""
+    jobs = [(config, first + i, n_lo, n_hi, lc_lo, lc_hi) for i in range(count)]
     out = []
     if workers > 1:
         import multiprocessing as mp
