@@ -85,19 +85,38 @@ def batch_main(args):
     ctol = 2.0 ** -150
     dAs = [torch.from_numpy(a).cuda() for a in As]
     dbs = [torch.from_numpy(b).cuda() for b in bs]
-    S = P.BatchSolver(dAs, dbs, K, ctol=ctol, slots=args.slots)
-    for i in range(args.warmup):
-        S.run(graph=True)
-        torch.cuda.synchronize()
-        log(f"[bench] warmup {i} done")
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        S.run(graph=True)
-        torch.cuda.synchronize()
-        log(f"[bench] step {i} done")
-    t1 = time.perf_counter()
+    from paper_2107_12550_amd import tuning
+    plan_path = os.path.join(ROOT, "paper_2107_12550_amd", f"batch_plan_{WORD_NAME[K].lower()}.json")
+    if args.tune:
+        log("[bench] tuning launch variants")
+        plan = tuning.tune(K, sample=512, reps=2, log=log)
+    elif os.path.exists(plan_path):
+        plan = tuning.load_plan(plan_path)
+    else:
+        plan = None
+
+    def timed(S, label):
+        for i in range(args.warmup):
+            S.run(graph=True)
+            torch.cuda.synchronize()
+            log(f"[bench] {label} warmup {i} done")
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            S.run(graph=True)
+            torch.cuda.synchronize()
+            log(f"[bench] {label} step {i} done")
+        return (time.perf_counter() - t0) * 1e3 / args.steps
+
+    S0 = P.BatchSolver(dAs, dbs, K, ctol=ctol, slots=args.slots)
+    ms_untuned = timed(S0, "untuned")
+    S0.close()
+    if plan is not None:
+        S = tuning.TunedBatchSolver(dAs, dbs, K, plan, ctol=ctol)
+        ms = timed(S, "tuned")
+    else:
+        S = P.BatchSolver(dAs, dbs, K, ctol=ctol, slots=args.slots)
+        ms = timed(S, "untuned")
     res = S.results()
-    ms = (t1 - t0) * 1e3 / args.steps
     khz = P.wall_clock_khz()
     lat_ms = (res["t_end"].astype(np.float64) - res["t_start"].astype(np.float64)) / khz
     # accuracy on a fixed sample of systems (exact solution all ones)
@@ -120,7 +139,11 @@ def batch_main(args):
         "data": "synthetic",
         "config": {"workload": f"{args.count} randsvd systems n~U[16,256] cond log-uniform [1e2,1e30] binary64 "
                                f"entries; {WORD_NAME[K]} LU + QD refinement to 1e-45, one graph launch",
-                   "count": args.count, "factor": WORD_NAME[K], "ctol": ctol, "slots": S.slots},
+                   "count": args.count, "factor": WORD_NAME[K], "ctol": ctol, "slots": S.slots,
+                   "tuning": None if plan is None else [(c["n_lo"], c["n_hi"], c["panel"], c["threads"])
+                                                        for c in plan["classes"]]},
+        "untuned_ms_per_step": ms_untuned,
+        "tuned_speedup": ms_untuned / ms,
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99)),
                        "max": float(lat_ms.max())},
         "gflops_eq_lu": work / (ms / 1e3) / 1e9,
@@ -128,6 +151,61 @@ def batch_main(args):
         "iters_mean": float(res["iters"].mean()),
         "max_rel_err_sample": mre,
         "residual_inexact": int(res["residual_inexact"].sum()),
+    }
+    print(json.dumps(line), flush=True)
+
+
+def selector_main(args):
+    """Learned precision choice on a held-out stream: `count` randsvd systems
+    n ~ U{32..256}, cond = 10^U(1, 60), binary64 entries (seed stream 6, the
+    same law as the training stream 5); target max|x - 1| <= 1e-45.  Times
+    the selector path (features + network + solves, escalating on misses)
+    against escalate-on-stagnation from one word, both in batched launches."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2107_12550_amd import selector as SEL
+    model = os.path.join(ROOT, "paper_2107_12550_amd", "selector_model.npz")
+    net = SEL.load(model)
+    chunk = 4096
+    tot = dict(baseline_ms=0.0, selector_ms=0.0, selector_predict_ms=0.0, baseline_attempts=0, selector_attempts=0,
+               baseline_solved=0, selector_solved=0, selector_escalations=0)
+    for c0 in range(0, args.count, chunk):
+        m = min(chunk, args.count - c0)
+        log(f"[bench] generating held-out systems {c0}..{c0 + m}")
+        As, bs, exact, _ = synth.batch(m, 32, 256, 1.0, 60.0, config=6, workers=min(16, os.cpu_count() or 1),
+                                       first=c0)
+        dA = [torch.from_numpy(a).cuda() for a in As]
+        db = [torch.from_numpy(b).cuda() for b in bs]
+        SEL.evaluate(net, dA, db)  # warm-up
+        r = SEL.evaluate(net, dA, db)
+        for k in tot:
+            tot[k] += r[k]
+        log(f"[bench] chunk: baseline {r['baseline_ms']:.1f} ms, selector {r['selector_ms']:.1f} ms")
+    line = {
+        "metric": "refined solves/sec with the learned precision choice (batched, to 1e-45)",
+        "value": args.count * 1e3 / tot["selector_ms"],
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 1,
+        "ms_per_step": tot["selector_ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.count} held-out randsvd systems n~U[32,256] cond 10^U(1,60) binary64 entries, "
+                               "target 1e-45; selector trained on 200000 method-labelled systems",
+                   "count": args.count},
+        "baseline": {"rule": "escalate-on-stagnation from one word", "ms": tot["baseline_ms"],
+                     "solves_per_s": args.count * 1e3 / tot["baseline_ms"], "attempts": tot["baseline_attempts"],
+                     "solved": tot["baseline_solved"]},
+        "selector": {"ms": tot["selector_ms"], "predict_ms": tot["selector_predict_ms"],
+                     "attempts": tot["selector_attempts"], "solved": tot["selector_solved"],
+                     "fallback_fraction": tot["selector_escalations"] / args.count},
+        "speedup_vs_escalation": tot["baseline_ms"] / tot["selector_ms"],
     }
     print(json.dumps(line), flush=True)
 
@@ -145,9 +223,10 @@ def main():
     ap.add_argument("--ozaki", type=int, default=-1,
                     help="single mode: also time the split trailing update with this many slices "
                          "(-1 = the default for the factor precision, 0 = plain form only)")
-    ap.add_argument("--mode", choices=["single", "batch"], default="single")
+    ap.add_argument("--mode", choices=["single", "batch", "selector"], default="single")
     ap.add_argument("--count", type=int, default=8192, help="batch mode: number of systems")
     ap.add_argument("--slots", type=int, default=0, help="batch mode: persistent workgroups (0 = auto)")
+    ap.add_argument("--tune", action="store_true", help="batch mode: tune the launch variants now")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -156,6 +235,10 @@ def main():
         sys.exit(2)
     if args.mode == "batch":
         return batch_main(args)
+    if args.mode == "selector":
+        if args.count == 8192:
+            args.count = 16384
+        return selector_main(args)
 
     import numpy as np
     import torch

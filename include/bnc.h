@@ -140,6 +140,11 @@ typedef struct bnc_refine_opts {
                              (checked after the stopping tests); 0 disables.
                              Batched solves report BNC_STAGNATED (they take
                              escalate = 0). */
+    int32_t batch_panel;  /* batched solves: LU panel width 4 or 8 (0 = 8) */
+    int32_t batch_threads; /* batched solves: threads per workgroup, 64, 128
+                             or 256 (0 = 256); systems of order above it get
+                             BNC_BAD_SIZE.  Both are tuning knobs that leave
+                             every result unchanged; bnc_refine ignores them. */
 } bnc_refine_opts;
 
 /* Outcome of the refinement loop (host struct, filled synchronously). */
@@ -197,10 +202,12 @@ typedef struct bnc_batch_result {
  * persistent workgroups (0 = the default) (host). */
 size_t bnc_refine_batched_workspace_size(int32_t factor_words, int32_t slots);
 
-/* The default number of persistent workgroups for K = factor_words on the
+/* The default number of persistent workgroups for K = factor_words, LU
+ * panel width `panel` and `threads` per workgroup (0 = defaults) on the
  * current device: resident workgroups per compute unit (from the kernel's
- * LDS and register use) times the compute units.  Negative on bad K. */
-int32_t bnc_refine_batched_default_slots(int32_t factor_words);
+ * LDS and register use) times the compute units.  Negative on bad
+ * arguments. */
+int32_t bnc_refine_batched_default_slots(int32_t factor_words, int32_t panel, int32_t threads);
 
 /*
  * Batched mixed-precision iterative refinement: bnc_refine (Kouya 2021,
@@ -217,7 +224,8 @@ int32_t bnc_refine_batched_default_slots(int32_t factor_words);
  *   opts       host options (as bnc_refine)
  *   slots      persistent workgroups (0 = default)
  *   results    device bnc_batch_result[count]
- * Asynchronous on stream.  A system of order outside 1..256 gets BNC_BAD_SIZE.
+ * Asynchronous on stream.  A system of order outside 1..256 (1..threads)
+ * gets BNC_BAD_SIZE.
  */
 int bnc_refine_batched(int64_t count, const int64_t *n, const double *const *A, const double *const *b,
                        double *const *x, const int32_t *order, void *work, size_t work_bytes,

@@ -28,7 +28,8 @@ class BncError(RuntimeError):
 class RefineOpts(ctypes.Structure):
     _fields_ = [("factor_words", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("rtol", ctypes.c_double),
                 ("atol", ctypes.c_double), ("ctol", ctypes.c_double), ("ozaki_slices", ctypes.c_int32),
-                ("escalate", ctypes.c_int32), ("stagnation_ratio", ctypes.c_double)]
+                ("escalate", ctypes.c_int32), ("stagnation_ratio", ctypes.c_double), ("batch_panel", ctypes.c_int32),
+                ("batch_threads", ctypes.c_int32)]
 
 
 class RefineResult(ctypes.Structure):
@@ -85,7 +86,7 @@ def _load() -> ctypes.CDLL:
     L.bnc_refine.restype = ctypes.c_int
     L.bnc_refine_batched_workspace_size.argtypes = [I32, I32]
     L.bnc_refine_batched_workspace_size.restype = ctypes.c_size_t
-    L.bnc_refine_batched_default_slots.argtypes = [I32]
+    L.bnc_refine_batched_default_slots.argtypes = [I32, I32, I32]
     L.bnc_refine_batched_default_slots.restype = I32
     L.bnc_refine_batched.argtypes = [I64, VP, VP, VP, VP, VP, VP, ctypes.c_size_t, ctypes.POINTER(RefineOpts), I32,
                                      VP, VP]
@@ -180,7 +181,7 @@ def refine(A: torch.Tensor, b: torch.Tensor, K: int, max_iter: int = 30, rtol: f
     need = refine_workspace_size(n, 4 if escalate else K)
     if work is None or work.numel() < need:
         work = torch.empty(need, dtype=torch.uint8, device=A.device)
-    o = RefineOpts(K, max_iter, rtol, atol, ctol, ozaki, 1 if escalate else 0, stagnation_ratio)
+    o = RefineOpts(K, max_iter, rtol, atol, ctol, ozaki, 1 if escalate else 0, stagnation_ratio, 0, 0)
     r = RefineResult()
     _check(_lib.bnc_refine(n, aw, _dev(A, "A", 3), n, n * n, _dev(b, "b", 2), n, _dev(x, "x", 2), n,
                            ctypes.c_void_p(work.data_ptr()), work.numel(), ctypes.byref(o), ctypes.byref(r),
@@ -197,7 +198,8 @@ class BatchSolver:
     set up once; run() launches (optionally through a captured HIP graph)."""
 
     def __init__(self, As, bs, K: int, max_iter: int = 30, rtol: float = 0.0, atol: float = 0.0,
-                 ctol: float = 2.0 ** -208, slots: int = 0, order=None, stagnation_ratio: float = 0.0):
+                 ctol: float = 2.0 ** -208, slots: int = 0, order=None, stagnation_ratio: float = 0.0,
+                 panel: int = 0, threads: int = 0):
         dev = As[0].device
         self.count = len(As)
         self.As = [a.contiguous() for a in As]
@@ -213,13 +215,13 @@ class BatchSolver:
         self.order = torch.tensor(list(order), dtype=torch.int32, device=dev)
         self.res = torch.zeros((self.count, ctypes.sizeof(BatchResult)), dtype=torch.uint8, device=dev)
         if slots == 0:
-            slots = int(_lib.bnc_refine_batched_default_slots(K))
+            slots = int(_lib.bnc_refine_batched_default_slots(K, panel, threads))
             if slots <= 0:
                 raise BncError(f"refine_batched_default_slots: {_lib.bnc_last_error().decode()}")
         self.slots = slots
         need = int(_lib.bnc_refine_batched_workspace_size(K, slots))
         self.work = torch.empty(need, dtype=torch.uint8, device=dev)
-        self.opts = RefineOpts(K, max_iter, rtol, atol, ctol, 0, 0, stagnation_ratio)
+        self.opts = RefineOpts(K, max_iter, rtol, atol, ctol, 0, 0, stagnation_ratio, panel, threads)
         self.graph = ctypes.c_void_p(None)
         self.stream = None
 

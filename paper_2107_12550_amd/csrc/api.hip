@@ -30,7 +30,9 @@ int batch_run(int64_t count, const int64_t *n, const double *const *A, const dou
               const int32_t *order, void *work, int slots, const bnc_refine_opts *o, bnc_batch_result *res,
               hipStream_t s);
 size_t batch_workspace_bytes(int K, int slots);
-int batch_default_slots(int K);
+int batch_default_slots(int K, int pw, int nt);
+bool batch_panel_ok(int pw);
+bool batch_threads_ok(int nt);
 size_t features_workspace_bytes(int slots);
 int features_default_slots();
 int features_run(int64_t count, const int64_t *n, const double *const *A, const double *const *b,
@@ -332,6 +334,7 @@ int bnc_refine(int64_t n, int32_t a_words, const double *A, int64_t lda, int64_t
         return fail_arg(-12, "refine: opts is NULL");
     if (opts->factor_words < 1 || opts->factor_words > 4 || opts->max_iter < 0 || !(opts->rtol >= 0) ||
         opts->ozaki_slices < 0 || opts->ozaki_slices > OZ_SMAX || (opts->escalate != 0 && opts->escalate != 1) ||
+        !batch_panel_ok(opts->batch_panel) || !batch_threads_ok(opts->batch_threads) ||
         !(opts->stagnation_ratio >= 0) ||
         !(opts->atol >= 0) || !(opts->ctol >= 0))
         return fail_arg(-12, "refine: invalid options");
@@ -357,14 +360,18 @@ size_t bnc_refine_batched_workspace_size(int32_t factor_words, int32_t slots)
 {
     if (factor_words < 1 || factor_words > 4 || slots < 0)
         return 0;
-    return batch_workspace_bytes(factor_words, slots ? slots : batch_default_slots(factor_words));
+    return batch_workspace_bytes(factor_words, slots ? slots : batch_default_slots(factor_words, 0, 0));
 }
 
-int32_t bnc_refine_batched_default_slots(int32_t factor_words)
+int32_t bnc_refine_batched_default_slots(int32_t factor_words, int32_t panel, int32_t threads)
 {
     if (factor_words < 1 || factor_words > 4)
         return fail_arg(-1, "refine_batched_default_slots: factor_words outside 1..4");
-    return batch_default_slots(factor_words);
+    if (!batch_panel_ok(panel))
+        return fail_arg(-2, "refine_batched_default_slots: panel not 0, 4 or 8");
+    if (!batch_threads_ok(threads))
+        return fail_arg(-3, "refine_batched_default_slots: threads not 0, 64, 128 or 256");
+    return batch_default_slots(factor_words, panel, threads);
 }
 
 int bnc_refine_batched(int64_t count, const int64_t *n, const double *const *A, const double *const *b,
@@ -385,13 +392,14 @@ int bnc_refine_batched(int64_t count, const int64_t *n, const double *const *A, 
         return fail_arg(-7, "refine_batched: work is NULL");
     if (!opts || opts->factor_words < 1 || opts->factor_words > 4 || opts->max_iter < 0 || !(opts->rtol >= 0) ||
         opts->ozaki_slices != 0 || opts->escalate != 0 || !(opts->stagnation_ratio >= 0) ||
+        !batch_panel_ok(opts->batch_panel) || !batch_threads_ok(opts->batch_threads) ||
         !(opts->atol >= 0) || !(opts->ctol >= 0))
         return fail_arg(-9, "refine_batched: invalid options");
     if (slots < 0)
         return fail_arg(-10, "refine_batched: slots < 0");
     if (count > 0 && !results)
         return fail_arg(-11, "refine_batched: results is NULL");
-    const int sl = slots ? slots : batch_default_slots(opts->factor_words);
+    const int sl = slots ? slots : batch_default_slots(opts->factor_words, opts->batch_panel, opts->batch_threads);
     if (work_bytes < batch_workspace_bytes(opts->factor_words, sl))
         return fail_arg(-8, "refine_batched: workspace too small");
     switch (opts->factor_words) {

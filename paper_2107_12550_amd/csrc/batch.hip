@@ -20,9 +20,9 @@
 
 namespace bnc {
 
-constexpr int BT = 256;     // threads per workgroup
-constexpr int BNMAX = 256;  // largest order
-constexpr int BNB = 8;      // panel width
+constexpr int BT_MAX = 256;  // most threads per workgroup (= largest order)
+constexpr int BNMAX = 256;   // slot layout in the workspace: orders up to 256
+constexpr int BNB_DEFAULT = 8;  // LU panel width unless tuned (4 or 8)
 constexpr int BRB = 24;     // residual bins per row (816 bits)
 
 struct BatchSlot {
@@ -31,28 +31,29 @@ struct BatchSlot {
     double *rd;   // K planes of BNMAX: 1/u_kk
 };
 
-template <int K>
+template <int K, int PW, int NT>
 struct BatchLds {
-    double tile[K * BNB * BNMAX];  // panel [w][c][r]; reused as U12 [w][k][j]
-    double ybuf[BNMAX][K];         // broadcast slots of the substitutions
-    double xq[4][BNMAX];           // current solution (quad-double)
-    double red[BT];                // reduction scratch
-    int redi[BT];
-    double wkey[4][K];             // per-wave argmax
-    int wrow[4];
-    int perm[BNMAX];
-    int ipiv[BNMAX];
+    double tile[K * PW * NT];  // panel [w][c][r]; reused as U12 [w][k][j]
+    double ybuf[NT][K];         // broadcast slots of the substitutions
+    double xq[4][NT];           // current solution (quad-double)
+    double red[NT];                // reduction scratch
+    int redi[NT];
+    double wkey[NT / 64][K];       // per-wave argmax
+    int wrow[NT / 64];
+    int perm[NT];
+    int ipiv[NT];
     int s_int[4];
 };
 
 // ---- workgroup reductions ----------------------------------------------------
 
+template <int NT>
 __device__ __forceinline__ double wg_max(double v, double *red)
 {
     const int t = threadIdx.x;
     red[t] = v;
     __syncthreads();
-    for (int s = BT / 2; s > 0; s >>= 1) {
+    for (int s = NT / 2; s > 0; s >>= 1) {
         if (t < s)
             red[t] = fmax(red[t], red[t + s]);
         __syncthreads();
@@ -62,12 +63,13 @@ __device__ __forceinline__ double wg_max(double v, double *red)
     return r;
 }
 
+template <int NT>
 __device__ __forceinline__ double wg_sum(double v, double *red)
 {
     const int t = threadIdx.x;
     red[t] = v;
     __syncthreads();
-    for (int s = BT / 2; s > 0; s >>= 1) {
+    for (int s = NT / 2; s > 0; s >>= 1) {
         if (t < s)
             red[t] = red[t] + red[t + s];
         __syncthreads();
@@ -77,12 +79,13 @@ __device__ __forceinline__ double wg_sum(double v, double *red)
     return r;
 }
 
+template <int NT>
 __device__ __forceinline__ int wg_min_i(int v, int *redi)
 {
     const int t = threadIdx.x;
     redi[t] = v;
     __syncthreads();
-    for (int s = BT / 2; s > 0; s >>= 1) {
+    for (int s = NT / 2; s > 0; s >>= 1) {
         if (t < s)
             redi[t] = redi[t + s] < redi[t] ? redi[t + s] : redi[t];
         __syncthreads();
@@ -92,12 +95,13 @@ __device__ __forceinline__ int wg_min_i(int v, int *redi)
     return r;
 }
 
+template <int NT>
 __device__ __forceinline__ int wg_or(int v, int *redi)
 {
     const int t = threadIdx.x;
     redi[t] = v;
     __syncthreads();
-    for (int s = BT / 2; s > 0; s >>= 1) {
+    for (int s = NT / 2; s > 0; s >>= 1) {
         if (t < s)
             redi[t] = redi[t] | redi[t + s];
         __syncthreads();
@@ -123,19 +127,20 @@ __device__ __forceinline__ bool cand_better_b(const double (&kb)[K], int rb, con
 
 // 2-norm of v over threads t < n (binary64, power-of-two scaled; the tree
 // order is fixed)
+template <int NT>
 __device__ __forceinline__ double wg_norm2(double v, bool active, double vmax, double *red)
 {
     const double sc = pow2(-(norm_exp(vmax) + 1));
     const double t = active ? v * sc : 0.0;
-    const double s = wg_sum(t * t, red);
+    const double s = wg_sum<NT>(t * t, red);
     return vmax == 0.0 ? 0.0 : sqrt(s) * pow2(norm_exp(vmax) + 1);
 }
 
 // ---- substitutions (thread i holds y_i) ---------------------------------------
 
-template <int K>
+template <int K, int NT, class LDS>
 __device__ __forceinline__ void bsolve(int n, const double *__restrict__ lu, int64_t ldp, const double *__restrict__ rd,
-                                       double (&y)[K], BatchLds<K> &S)
+                                       double (&y)[K], LDS &S)
 {
     const int t = threadIdx.x;
     // forward: y_i <- y_i - l_ik y_k, k increasing
@@ -200,8 +205,8 @@ __device__ __forceinline__ void bsolve(int n, const double *__restrict__ lu, int
 }
 
 // y_i = rf_perm[i]: gather of the K-word copy held per thread through perm
-template <int K>
-__device__ __forceinline__ void bgather(int n, double (&v)[K], BatchLds<K> &S)
+template <int K, int NT, class LDS>
+__device__ __forceinline__ void bgather(int n, double (&v)[K], LDS &S)
 {
     const int t = threadIdx.x;
     if (t < n) {
@@ -221,15 +226,15 @@ __device__ __forceinline__ void bgather(int n, double (&v)[K], BatchLds<K> &S)
 
 // ---- the batched solver ---------------------------------------------------------
 
-template <int K>
-__global__ void __launch_bounds__(BT)
+template <int K, int PW, int NT>
+__global__ void __launch_bounds__(NT)
     k_batch(int64_t count, const int64_t *__restrict__ nn, const double *const *__restrict__ As,
             const double *const *__restrict__ bs, double *const *__restrict__ xs, const int32_t *__restrict__ order,
             unsigned *__restrict__ queue, double *__restrict__ work, bnc_refine_opts o,
             bnc_batch_result *__restrict__ res)
 {
     extern __shared__ double smem_raw[];
-    BatchLds<K> &S = *reinterpret_cast<BatchLds<K> *>(smem_raw);
+    BatchLds<K, PW, NT> &S = *reinterpret_cast<BatchLds<K, PW, NT> *>(smem_raw);
     const int t = threadIdx.x;
     const int lane = t & 63, wave = t >> 6;
     const int64_t ldp = (int64_t)BNMAX * BNMAX;
@@ -249,7 +254,7 @@ __global__ void __launch_bounds__(BT)
         const int64_t n64 = nn[sys];
         bnc_batch_result out{};
         double *x = xs[sys];
-        if (n64 < 1 || n64 > BNMAX) {
+        if (n64 < 1 || n64 > NT) {
             if (t == 0) {
                 out.status = BNC_BAD_SIZE;
                 out.t_start = t0;
@@ -266,7 +271,7 @@ __global__ void __launch_bounds__(BT)
         int bad = 0;
         double rmax_i = 0.0;
         int ea = 2000, eb = 2000;
-        for (int64_t e = t; e < (int64_t)n * n; e += BT) {
+        for (int64_t e = t; e < (int64_t)n * n; e += NT) {
             const double v = A[e];
             bad |= !isfinite(v);
             if (v != 0.0) {
@@ -286,8 +291,8 @@ __global__ void __launch_bounds__(BT)
             for (int j = 0; j < n; ++j)
                 rmax_i = fmax(rmax_i, fabs(A[(int64_t)j * n + t]));
         }
-        if (wg_or(bad, S.redi)) {
-            for (int e = t; e < 4 * n; e += BT)
+        if (wg_or<NT>(bad, S.redi)) {
+            for (int e = t; e < 4 * n; e += NT)
                 x[(e / n) * n + e % n] = 0.0;
             if (t == 0) {
                 out.status = BNC_NONFINITE;
@@ -297,26 +302,26 @@ __global__ void __launch_bounds__(BT)
             }
             continue;
         }
-        ea = wg_min_i(ea, S.redi);
-        eb = wg_min_i(eb, S.redi);
+        ea = wg_min_i<NT>(ea, S.redi);
+        eb = wg_min_i<NT>(eb, S.redi);
         double anorm;
         {
             double am = 0.0;
-            for (int64_t e = t; e < (int64_t)n * n; e += BT)
+            for (int64_t e = t; e < (int64_t)n * n; e += NT)
                 am = fmax(am, fabs(A[e]));
-            am = wg_max(am, S.red);
+            am = wg_max<NT>(am, S.red);
             const double sc = pow2(-(norm_exp(am) + 1));
             double acc = 0.0;
-            for (int64_t e = t; e < (int64_t)n * n; e += BT) {
+            for (int64_t e = t; e < (int64_t)n * n; e += NT) {
                 const double v = A[e] * sc;
                 acc = acc + v * v;
             }
-            const double ss = wg_sum(acc, S.red);
+            const double ss = wg_sum<NT>(acc, S.red);
             anorm = am == 0.0 ? 0.0 : sqrt(ss) * pow2(norm_exp(am) + 1);
         }
 
         // ---- K-word copy of A
-        for (int64_t e = t; e < (int64_t)n * n; e += BT) {
+        for (int64_t e = t; e < (int64_t)n * n; e += NT) {
             lu[e] = A[e];
 #pragma unroll
             for (int w = 1; w < K; ++w)
@@ -326,14 +331,14 @@ __global__ void __launch_bounds__(BT)
 
         // ---- blocked LU
         int64_t info = 0;
-        for (int j0 = 0; j0 < n; j0 += BNB) {
-            const int jb = (n - j0) < BNB ? (n - j0) : BNB;
+        for (int j0 = 0; j0 < n; j0 += PW) {
+            const int jb = (n - j0) < PW ? (n - j0) : PW;
             const int m = n - j0;
-            for (int e = t; e < m * jb; e += BT) {
+            for (int e = t; e < m * jb; e += NT) {
                 const int r = e % m, c = e / m;
 #pragma unroll
                 for (int w = 0; w < K; ++w)
-                    S.tile[(w * BNB + c) * BNMAX + r] = lu[w * ldp + (int64_t)(j0 + c) * n + j0 + r];
+                    S.tile[(w * PW + c) * NT + r] = lu[w * ldp + (int64_t)(j0 + c) * n + j0 + r];
             }
             __syncthreads();
             for (int kk = 0; kk < jb; ++kk) {
@@ -345,7 +350,7 @@ __global__ void __launch_bounds__(BT)
                     row = t;
 #pragma unroll
                     for (int w = 0; w < K; ++w)
-                        key[w] = S.tile[(w * BNB + kk) * BNMAX + t];
+                        key[w] = S.tile[(w * PW + kk) * NT + t];
                 } else {
 #pragma unroll
                     for (int w = 0; w < K; ++w)
@@ -378,7 +383,7 @@ __global__ void __launch_bounds__(BT)
 #pragma unroll
                     for (int w = 0; w < K; ++w)
                         bk[w] = 0.0;
-                    for (int q = 0; q < 4; ++q) {
+                    for (int q = 0; q < NT / 64; ++q) {
                         double kq[K];
 #pragma unroll
                         for (int w = 0; w < K; ++w)
@@ -397,14 +402,14 @@ __global__ void __launch_bounds__(BT)
                 const int pr = S.s_int[1];  // tile row of the pivot
                 if (pr != kk) {
                     // panel columns in the tile, other columns in the workspace
-                    for (int e = t; e < jb * K; e += BT) {
+                    for (int e = t; e < jb * K; e += NT) {
                         const int c = e % jb, w = e / jb;
-                        double *a = &S.tile[(w * BNB + c) * BNMAX];
+                        double *a = &S.tile[(w * PW + c) * NT];
                         const double tmp = a[kk];
                         a[kk] = a[pr];
                         a[pr] = tmp;
                     }
-                    for (int e = t; e < (n - jb) * K; e += BT) {
+                    for (int e = t; e < (n - jb) * K; e += NT) {
                         const int cc = e % (n - jb), w = e / (n - jb);
                         const int c = cc < j0 ? cc : cc + jb;
                         double *col = lu + w * ldp + (int64_t)c * n;
@@ -417,7 +422,7 @@ __global__ void __launch_bounds__(BT)
                 double pv[K];
 #pragma unroll
                 for (int w = 0; w < K; ++w)
-                    pv[w] = S.tile[(w * BNB + kk) * BNMAX + kk];
+                    pv[w] = S.tile[(w * PW + kk) * NT + kk];
                 if (is_zero<K>(pv)) {
                     if (info == 0)
                         info = k + 1;
@@ -428,38 +433,38 @@ __global__ void __launch_bounds__(BT)
                     recip<K>(pv, rc);
 #pragma unroll
                     for (int w = 0; w < K; ++w)
-                        a[w] = S.tile[(w * BNB + kk) * BNMAX + t];
+                        a[w] = S.tile[(w * PW + kk) * NT + t];
                     mul<K>(a, rc, l);
 #pragma unroll
                     for (int w = 0; w < K; ++w)
-                        S.tile[(w * BNB + kk) * BNMAX + t] = l[w];
+                        S.tile[(w * PW + kk) * NT + t] = l[w];
                 }
                 __syncthreads();
                 const int nc = jb - kk - 1;
-                for (int e = t; e < m * nc; e += BT) {
+                for (int e = t; e < m * nc; e += NT) {
                     const int r = e % m, c = kk + 1 + e / m;
                     if (r > kk) {
                         double a[K], l[K], u[K], oo[K];
 #pragma unroll
                         for (int w = 0; w < K; ++w) {
-                            a[w] = S.tile[(w * BNB + c) * BNMAX + r];
-                            l[w] = S.tile[(w * BNB + kk) * BNMAX + r];
-                            u[w] = S.tile[(w * BNB + c) * BNMAX + kk];
+                            a[w] = S.tile[(w * PW + c) * NT + r];
+                            l[w] = S.tile[(w * PW + kk) * NT + r];
+                            u[w] = S.tile[(w * PW + c) * NT + kk];
                         }
                         fms<K>(a, l, u, oo);
 #pragma unroll
                         for (int w = 0; w < K; ++w)
-                            S.tile[(w * BNB + c) * BNMAX + r] = oo[w];
+                            S.tile[(w * PW + c) * NT + r] = oo[w];
                     }
                 }
                 __syncthreads();
             }
             // panel back to the workspace
-            for (int e = t; e < m * jb; e += BT) {
+            for (int e = t; e < m * jb; e += NT) {
                 const int r = e % m, c = e / m;
 #pragma unroll
                 for (int w = 0; w < K; ++w)
-                    lu[w * ldp + (int64_t)(j0 + c) * n + j0 + r] = S.tile[(w * BNB + c) * BNMAX + r];
+                    lu[w * ldp + (int64_t)(j0 + c) * n + j0 + r] = S.tile[(w * PW + c) * NT + r];
             }
             // every later phase reads the panel back from the workspace,
             // written above by other threads
@@ -472,30 +477,30 @@ __global__ void __launch_bounds__(BT)
             int R2 = 1;
             while (R2 < m2)
                 R2 <<= 1;
-            const int G = BT / R2;
+            const int G = NT / R2;
             const int r = t % R2, q = t / R2;
-            double l21[BNB][K];
+            double l21[PW][K];
             if (r < m2) {
 #pragma unroll
-                for (int kk = 0; kk < BNB; ++kk)
+                for (int kk = 0; kk < PW; ++kk)
 #pragma unroll
                     for (int w = 0; w < K; ++w)
-                        l21[kk][w] = kk < jb ? S.tile[(w * BNB + kk) * BNMAX + jb + r] : 0.0;
+                        l21[kk][w] = kk < jb ? S.tile[(w * PW + kk) * NT + jb + r] : 0.0;
             }
             __syncthreads();
             // U12 = L11^-1 A12: thread per column of A12
-            for (int j = t; j < m2; j += BT) {
-                double u[BNB][K];
+            for (int j = t; j < m2; j += NT) {
+                double u[PW][K];
 #pragma unroll
-                for (int kk = 0; kk < BNB; ++kk)
+                for (int kk = 0; kk < PW; ++kk)
 #pragma unroll
                     for (int w = 0; w < K; ++w)
                         u[kk][w] = kk < jb ? lu[w * ldp + (int64_t)(c0 + j) * n + j0 + kk] : 0.0;
 #pragma unroll
-                for (int kk = 0; kk < BNB; ++kk) {
+                for (int kk = 0; kk < PW; ++kk) {
                     if (kk < jb) {
 #pragma unroll
-                        for (int rr = 0; rr < BNB; ++rr) {
+                        for (int rr = 0; rr < PW; ++rr) {
                             if (rr > kk && rr < jb) {
                                 double l[K], oo[K];
 #pragma unroll
@@ -510,12 +515,12 @@ __global__ void __launch_bounds__(BT)
                     }
                 }
 #pragma unroll
-                for (int kk = 0; kk < BNB; ++kk)
+                for (int kk = 0; kk < PW; ++kk)
                     if (kk < jb) {
 #pragma unroll
                         for (int w = 0; w < K; ++w) {
                             lu[w * ldp + (int64_t)(c0 + j) * n + j0 + kk] = u[kk][w];
-                            S.tile[(w * BNB + kk) * BNMAX + j] = u[kk][w];
+                            S.tile[(w * PW + kk) * NT + j] = u[kk][w];
                         }
                     }
             }
@@ -529,12 +534,12 @@ __global__ void __launch_bounds__(BT)
                     for (int w = 0; w < K; ++w)
                         c[w] = cp[w * ldp];
 #pragma unroll
-                    for (int kk = 0; kk < BNB; ++kk) {
+                    for (int kk = 0; kk < PW; ++kk) {
                         if (kk < jb) {
                             double u[K], oo[K];
 #pragma unroll
                             for (int w = 0; w < K; ++w)
-                                u[w] = S.tile[(w * BNB + kk) * BNMAX + j];
+                                u[w] = S.tile[(w * PW + kk) * NT + j];
                             fms<K>(c, l21[kk], u, oo);
 #pragma unroll
                             for (int w = 0; w < K; ++w)
@@ -549,7 +554,7 @@ __global__ void __launch_bounds__(BT)
             __syncthreads();
         }
         if (info != 0) {
-            for (int e = t; e < 4 * n; e += BT)
+            for (int e = t; e < 4 * n; e += NT)
                 x[(e / n) * n + e % n] = 0.0;
             if (t == 0) {
                 out.status = BNC_SINGULAR;
@@ -593,8 +598,8 @@ __global__ void __launch_bounds__(BT)
                 bw[w] = b[w * n + t];
             renorm<K, 4>(bw, y);
         }
-        bgather<K>(n, y, S);
-        bsolve<K>(n, lu, ldp, rd, y, S);
+        bgather<K, NT>(n, y, S);
+        bsolve<K, NT>(n, lu, ldp, rd, y, S);
         if (t < n) {
 #pragma unroll
             for (int w = 0; w < 4; ++w)
@@ -625,8 +630,8 @@ __global__ void __launch_bounds__(BT)
                         const int e2 = ilogb_bits(S.xq[w][t]);
                         ex = e2 < ex ? e2 : ex;
                     }
-            const double xmax = wg_max(fabs(xv0), S.red);
-            ex = wg_min_i(ex, S.redi);
+            const double xmax = wg_max<NT>(fabs(xv0), S.red);
+            ex = wg_min_i<NT>(ex, S.redi);
             // exact residual, thread per row
             double rr[4] = {0.0, 0.0, 0.0, 0.0};
             int rbad = 0;
@@ -662,10 +667,10 @@ __global__ void __launch_bounds__(BT)
                     rbad = bd ? 1 : 0;
                 }
             }
-            inexact |= wg_or(rbad, S.redi);
-            const double rmax = wg_max(fabs(rr[0]), S.red);
-            const double nr = wg_norm2(rr[0], t < n, rmax, S.red);
-            const double nx = wg_norm2(xv0, t < n, xmax, S.red);
+            inexact |= wg_or<NT>(rbad, S.redi);
+            const double rmax = wg_max<NT>(fabs(rr[0]), S.red);
+            const double nr = wg_norm2<NT>(rr[0], t < n, rmax, S.red);
+            const double nx = wg_norm2<NT>(xv0, t < n, xmax, S.red);
             if (nr < thresh_c * nx + o.atol || (have_z && zmax <= o.ctol * xmax)) {
                 status = BNC_CONVERGED;
                 break;
@@ -686,8 +691,8 @@ __global__ void __launch_bounds__(BT)
                     sr[w] = rr[w] * pow2(-e);
                 renorm<K, 4>(sr, v);
             }
-            bgather<K>(n, v, S);
-            bsolve<K>(n, lu, ldp, rd, v, S);
+            bgather<K, NT>(n, v, S);
+            bsolve<K, NT>(n, lu, ldp, rd, v, S);
             double z0 = 0.0;
             if (t < n) {
                 double zv[4], xv[4], oo[4];
@@ -703,11 +708,11 @@ __global__ void __launch_bounds__(BT)
                     S.xq[w][t] = oo[w];
             }
             zprev = zmax;
-            zmax = wg_max(fabs(z0), S.red);
+            zmax = wg_max<NT>(fabs(z0), S.red);
             have_z = true;
             ++iters;
         }
-        for (int e = t; e < 4 * n; e += BT)
+        for (int e = t; e < 4 * n; e += NT)
             x[e] = S.xq[e / n][e % n];
         if (t == 0) {
             out.status = status;
@@ -733,28 +738,69 @@ size_t batch_workspace_bytes(int K, int slots)
     return (size_t)slots * ((size_t)K * BNMAX * BNMAX + (size_t)K * BNMAX) * sizeof(double) + 256;
 }
 
-// one persistent workgroup per compute unit and resident slot (the kernel
-// needs all 512 VGPRs of a lane's wave slot: one workgroup per CU)
-template <int K>
+// persistent workgroups per compute unit: as many as registers and LDS allow
+template <int K, int PW, int NT>
 static int occupancy_per_cu()
 {
     int per = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)k_batch<K>, BT, sizeof(BatchLds<K>)) !=
-            hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)k_batch<K, PW, NT>, NT,
+                                                     sizeof(BatchLds<K, PW, NT>)) != hipSuccess ||
         per < 1)
         per = 1;
     return per;
 }
 
-int batch_default_slots(int K)
+template <int K>
+static int occupancy_k(int pw, int nt)
+{
+    if (nt == 64)
+        return pw == 4 ? occupancy_per_cu<K, 4, 64>() : occupancy_per_cu<K, 8, 64>();
+    if (nt == 128)
+        return pw == 4 ? occupancy_per_cu<K, 4, 128>() : occupancy_per_cu<K, 8, 128>();
+    return pw == 4 ? occupancy_per_cu<K, 4, 256>() : occupancy_per_cu<K, 8, 256>();
+}
+
+bool batch_panel_ok(int pw) { return pw == 0 || pw == 4 || pw == 8; }
+bool batch_threads_ok(int nt) { return nt == 0 || nt == 64 || nt == 128 || nt == 256; }
+
+int batch_default_slots(int K, int pw, int nt)
 {
     int dev = 0, ncu = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return 256;
-    int per = K == 1 ? occupancy_per_cu<1>() : K == 2 ? occupancy_per_cu<2>() : K == 3 ? occupancy_per_cu<3>()
-                                                                                         : occupancy_per_cu<4>();
+    if (pw == 0)
+        pw = BNB_DEFAULT;
+    if (nt == 0)
+        nt = BT_MAX;
+    const int per = K == 1 ? occupancy_k<1>(pw, nt) : K == 2 ? occupancy_k<2>(pw, nt)
+                                                  : K == 3 ? occupancy_k<3>(pw, nt) : occupancy_k<4>(pw, nt);
     return per * ncu;
+}
+
+template <int K, int PW, int NT>
+static int batch_launch(int64_t count, const int64_t *n, const double *const *A, const double *const *b,
+                        double *const *x, const int32_t *order, unsigned *queue, double *ws, int slots,
+                        const bnc_refine_opts *o, bnc_batch_result *res, hipStream_t s)
+{
+    const size_t lds = sizeof(BatchLds<K, PW, NT>);
+    if (hipFuncSetAttribute((const void *)k_batch<K, PW, NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds) != hipSuccess)
+        (void)hipGetLastError();
+    hipLaunchKernelGGL((k_batch<K, PW, NT>), dim3((unsigned)slots), dim3(NT), lds, s, count, n, A, b, x, order, queue,
+                       ws, *o, res);
+    BNC_LAUNCH_CHECK();
+    return BNC_OK;
+}
+
+template <int K, int NT>
+static int batch_launch_pw(int64_t count, const int64_t *n, const double *const *A, const double *const *b,
+                           double *const *x, const int32_t *order, unsigned *queue, double *ws, int slots,
+                           const bnc_refine_opts *o, bnc_batch_result *res, hipStream_t s)
+{
+    if (o->batch_panel == 4)
+        return batch_launch<K, 4, NT>(count, n, A, b, x, order, queue, ws, slots, o, res, s);
+    return batch_launch<K, 8, NT>(count, n, A, b, x, order, queue, ws, slots, o, res, s);
 }
 
 template <int K>
@@ -766,16 +812,16 @@ int batch_run(int64_t count, const int64_t *n, const double *const *A, const dou
         return BNC_OK;
     unsigned *queue = (unsigned *)work;
     double *ws = (double *)((char *)work + 256);
-    const size_t lds = sizeof(BatchLds<K>);
-    if (hipFuncSetAttribute((const void *)k_batch<K>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
-        hipSuccess)
-        (void)hipGetLastError();
     hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, queue);
     BNC_LAUNCH_CHECK();
-    hipLaunchKernelGGL((k_batch<K>), dim3((unsigned)slots), dim3(BT), lds, s, count, n, A, b, x, order, queue, ws, *o,
-                       res);
-    BNC_LAUNCH_CHECK();
-    return BNC_OK;
+    switch (o->batch_threads) {
+    case 64:
+        return batch_launch_pw<K, 64>(count, n, A, b, x, order, queue, ws, slots, o, res, s);
+    case 128:
+        return batch_launch_pw<K, 128>(count, n, A, b, x, order, queue, ws, slots, o, res, s);
+    default:
+        return batch_launch_pw<K, 256>(count, n, A, b, x, order, queue, ws, slots, o, res, s);
+    }
 }
 
 #define INST(K)                                                                                                 \

@@ -102,3 +102,67 @@ def test_batched_bad_size(P):
     S.run()
     assert S.results()["status"][0] == P.BNC_BAD_SIZE
     torch.cuda.synchronize()
+
+
+def test_launch_variants_bitexact(P):
+    """Panel width and threads per workgroup are tuning knobs only: every
+    variant returns the same words as the oracle-checked default, and a
+    system above a variant's order limit is refused."""
+    As, bs = mixed_batch()
+    K = 2
+    ns = [a.shape[-1] for a in As]
+    ref = P.BatchSolver([dev(A) for A in As], [dev(b) for b in bs], K, ctol=CTOL)
+    ref.run()
+    r0 = ref.results()
+    x0 = [x.cpu().numpy() for x in ref.xs]
+    for nt in (64, 128, 256):
+        for pw in (4, 8):
+            say("variant threads", nt, "panel", pw)
+            S = P.BatchSolver([dev(A) for A in As], [dev(b) for b in bs], K, ctol=CTOL, panel=pw, threads=nt)
+            S.run()
+            r = S.results()
+            for i, n in enumerate(ns):
+                if n > nt:
+                    assert r["status"][i] == P.BNC_BAD_SIZE
+                    continue
+                assert r["status"][i] == r0["status"][i] and r["iters"][i] == r0["iters"][i], (nt, pw, i)
+                np.testing.assert_array_equal(S.xs[i].cpu().numpy(), x0[i])
+
+
+def test_tuned_solver_graph_replays(P):
+    """A plan that sends each size class to its own variant, eager and
+    through a captured graph replayed three times with eager work in
+    between: every system equals the oracle's refine of it alone."""
+    import torch
+    from paper_2107_12550_amd import tuning
+    As, bs = mixed_batch()
+    K = 3
+    refs = [O.refine(A, b, K, ctol=CTOL) for A, b in zip(As, bs)]
+    plan = dict(K=K, classes=[dict(n_lo=1, n_hi=64, panel=4, threads=64),
+                              dict(n_lo=65, n_hi=128, panel=8, threads=128),
+                              dict(n_lo=129, n_hi=256, panel=4, threads=256)])
+    T = tuning.TunedBatchSolver([dev(A) for A in As], [dev(b) for b in bs], K, plan, ctol=CTOL)
+    say("tuned eager")
+    T.run()
+    for rep in range(4):
+        res = T.results()
+        for i, ref in enumerate(refs):
+            assert res["status"][i] == ref["status"] and res["iters"][i] == ref["iters"], (rep, i)
+            if ref["status"] != O.SINGULAR:
+                np.testing.assert_array_equal(T.xs[i].cpu().numpy(), ref["x"], err_msg=f"rep {rep} system {i}")
+        for x in T.xs:
+            x.fill_(7.0)
+        torch.cuda.synchronize()
+        say("tuned graph replay", rep)
+        T.run(graph=True)
+        torch.cuda.synchronize()
+
+
+def test_tune_smoke(P):
+    from paper_2107_12550_amd import tuning
+    say("tune smoke")
+    plan = tuning.tune(2, sample=16, reps=1)
+    assert [(c["n_lo"], c["n_hi"]) for c in plan["classes"]] == list(tuning.CLASSES)
+    for c in plan["classes"]:
+        assert c["threads"] >= c["n_hi"] and c["panel"] in tuning.PANELS
+        assert c["trials"]
