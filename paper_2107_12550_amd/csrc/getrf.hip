@@ -129,6 +129,25 @@ __device__ __forceinline__ void bar_wait(unsigned *bar, unsigned target, int *ab
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
+// The same wait for one wave only (the other waves keep working).
+__device__ __forceinline__ void bar_wait_wave(unsigned *bar, unsigned target, int *abort_flag)
+{
+    if ((threadIdx.x & 63) == 0) {
+        unsigned spins = 0;
+        while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                break;
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > SPIN_LIMIT) {
+                __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
 // LDS tile layout: word w, panel column c, local row r at ((w*jb + c)*R + r);
 // R <= 64, so one wave holds one row per lane.
 //
@@ -140,9 +159,10 @@ __device__ __forceinline__ void bar_wait(unsigned *bar, unsigned target, int *ab
 //   with the previous pivot row, exactly as their owner does
 //   swap, record ipiv, reciprocal of the pivot, scale column kk
 //   wave 0: update column kk+1, find the local candidate for column kk+1,
-//   publish it (and row k+1 if owned), arrive
-//   all waves, after the copies are taken: update columns kk+2.. (overlaps
-//   the other workgroups' arrival)
+//   copy it (and row k+1 if owned) to LDS; then, while waves 1.. update
+//   columns kk+2.., publish the copies and arrive, wait for the others and
+//   do the next column's pivot choice and row rebuild: the update of the
+//   panel's remaining columns leaves the critical path.
 template <int K>
 __global__ void __launch_bounds__(PANEL_THREADS)
     k_panel(double *__restrict__ A, int64_t lda, int64_t ldp, int64_t n, int64_t j0, int jb, int R,
@@ -154,7 +174,7 @@ __global__ void __launch_bounds__(PANEL_THREADS)
     double *tile = smem;                          // K*jb*R
     double *prow = tile + (size_t)K * jb * R;     // [2][K*jb] pivot rows of this and the previous column
     double *orow = prow + 2 * (size_t)K * jb;     // [K*jb]    displaced row k
-    __shared__ int s_p, s_gw;
+    __shared__ int s_p;
     __shared__ int s_piv[PANEL_NB_MAX];
 
     const int P = gridDim.x;
@@ -172,10 +192,13 @@ __global__ void __launch_bounds__(PANEL_THREADS)
     }
     __syncthreads();
 
-    // publish this workgroup's candidate for column cc (rows >= j0+cc) and
-    // the row at position j0+cc if owned; wave 0 only
-    auto publish = [&](int cc) {
-        const int b = cc & 1;
+    double *pubc = orow + (size_t)K * jb;  // [K*jb] staged copy of this workgroup's candidate row
+    double *pubk = pubc + (size_t)K * jb;  // [K*jb] staged copy of the row at the next pivot position
+
+    // stage (wave 0): this workgroup's candidate for column cc (rows >=
+    // j0+cc) and the row at position j0+cc if owned, copied from the tile;
+    // returns the candidate row (-1: none), wave-uniform
+    auto stage = [&](int cc, bool &own) -> int {
         const int64_t kc = j0 + cc;
         double key[K];
         int row = -1;
@@ -190,29 +213,45 @@ __global__ void __launch_bounds__(PANEL_THREADS)
                 key[w] = 0.0;
         }
         wave_argmax<K>(key, row);
-        double *cb = cand + ((size_t)(b * P + g) * K) * jb;
         if (row >= 0) {
             const int lr = (int)(row - gr0);
             for (int e = lane; e < K * jb; e += 64) {
                 const int w = e / jb, c = e % jb;
-                sh_store(cb + e, tile[(w * jb + c) * R + lr]);
+                pubc[e] = tile[(w * jb + c) * R + lr];
             }
         }
-        if (lane == 0)
-            sh_store(cidx + b * P + g, (int64_t)row);
-        if (kc >= gr0 && kc < gr0 + nr) {
+        own = kc >= gr0 && kc < gr0 + nr;
+        if (own) {
             const int lr = (int)(kc - gr0);
-            double *rb = rowk + (size_t)b * K * jb;
             for (int e = lane; e < K * jb; e += 64) {
                 const int w = e / jb, c = e % jb;
-                sh_store(rb + e, tile[(w * jb + c) * R + lr]);
+                pubk[e] = tile[(w * jb + c) * R + lr];
             }
+        }
+        return row;
+    };
+    // emit (wave 0): publish the staged copies for column cc and arrive
+    auto emit = [&](int cc, int row, bool own) {
+        const int b = cc & 1;
+        double *cb = cand + ((size_t)(b * P + g) * K) * jb;
+        if (row >= 0)
+            for (int e = lane; e < K * jb; e += 64)
+                sh_store(cb + e, pubc[e]);
+        if (lane == 0)
+            sh_store(cidx + b * P + g, (int64_t)row);
+        if (own) {
+            double *rb = rowk + (size_t)b * K * jb;
+            for (int e = lane; e < K * jb; e += 64)
+                sh_store(rb + e, pubk[e]);
         }
         bar_arrive_wave(bar);
     };
 
-    if (wave == 0)
-        publish(0);
+    if (wave == 0) {
+        bool own0;
+        const int row0 = stage(0, own0);
+        emit(0, row0, own0);
+    }
 
     bool nz_prev = false;
     for (int kk = 0; kk < jb; ++kk) {
@@ -220,9 +259,9 @@ __global__ void __launch_bounds__(PANEL_THREADS)
         const int b = kk & 1;
         double *pcur = prow + (size_t)b * K * jb;
         const double *pprev = prow + (size_t)(b ^ 1) * K * jb;
-        bar_wait(bar, (unsigned)(kk + 1) * (unsigned)P, abort_flag);
-        // ---- global pivot (wave 0)
         if (wave == 0) {
+            bar_wait_wave(bar, (unsigned)(kk + 1) * (unsigned)P, abort_flag);
+            // ---- global pivot
             double key[K];
             int row = -1;
 #pragma unroll
@@ -243,20 +282,15 @@ __global__ void __launch_bounds__(PANEL_THREADS)
                 }
             }
             wave_argmax<K>(key, row);
-            if (lane == 0) {
-                s_p = row;
-                s_gw = (int)((row - j0) / R);
-            }
-        }
-        __syncthreads();
-        const int64_t p = s_p;
-        const int gw = s_gw;
-        // ---- rebuild the pivot row (and the displaced row k for p's owner)
-        {
+            const int64_t p = row;
+            const int gw = (int)((p - j0) / R);
+            // ---- rebuild the pivot row (and the displaced row k for p's
+            //      owner) from their published copies; lane = column
             const double *cc = cand + ((size_t)(b * P + gw) * K) * jb;
             const double *rb = rowk + (size_t)b * K * jb;
             const bool need_o = p != k && p >= gr0 && p < gr0 + nr;
-            for (int c = tid; c < jb; c += PANEL_THREADS) {
+            const int c = lane;
+            if (c < jb) {
                 double v[K], o[K];
 #pragma unroll
                 for (int w = 0; w < K; ++w)
@@ -297,8 +331,33 @@ __global__ void __launch_bounds__(PANEL_THREADS)
                         orow[w * jb + c] = v[w];
                 }
             }
+            if (lane == 0)
+                s_p = (int)p;
+        } else if (nz_prev) {
+            // ---- waves 1..: the previous column's update of columns
+            //      kk+1.. (rows below the previous pivot)
+            const int kp = kk - 1;
+            const int64_t kprev = j0 + kp;
+            const int ncol = jb - kp - 2;
+            for (int e = tid - 64; e < nr * ncol; e += PANEL_THREADS - 64) {
+                const int r = e % nr, c = kp + 2 + e / nr;
+                if (gr0 + r > kprev) {
+                    double a[K], l[K], u[K], o[K];
+#pragma unroll
+                    for (int w = 0; w < K; ++w) {
+                        a[w] = tile[(w * jb + c) * R + r];
+                        l[w] = tile[(w * jb + kp) * R + r];
+                        u[w] = pprev[w * jb + c];
+                    }
+                    fms<K>(a, l, u, o);
+#pragma unroll
+                    for (int w = 0; w < K; ++w)
+                        tile[(w * jb + c) * R + r] = o[w];
+                }
+            }
         }
         __syncthreads();
+        const int64_t p = s_p;
         // ---- row interchange k <-> p inside the tiles
         if (k >= gr0 && k < gr0 + nr) {
             const int lr = (int)(k - gr0);
@@ -340,7 +399,9 @@ __global__ void __launch_bounds__(PANEL_THREADS)
                 tile[(w * jb + kk) * R + lane] = l[w];
         }
         __syncthreads();
-        // ---- wave 0: column kk+1 first, then the next candidate
+        // ---- wave 0: column kk+1 first, then the next candidate, staged
+        int crow = -1;
+        bool cown = false;
         if (wave == 0 && kk + 1 < jb) {
             if (nz && lane < nr && gr0 + lane > k) {
                 double a[K], l[K], u[K], o[K];
@@ -355,34 +416,15 @@ __global__ void __launch_bounds__(PANEL_THREADS)
                 for (int w = 0; w < K; ++w)
                     tile[(w * jb + kk + 1) * R + lane] = o[w];
             }
-            publish(kk + 1);
+            crow = stage(kk + 1, cown);
         }
-        // the published copies must be taken before columns kk+2.. change
+        // the staged copies are taken before columns kk+2.. change
         __syncthreads();
-        // ---- columns kk+2.. for rows > k (all waves; overlaps the other
-        //      workgroups' arrival at the barrier)
-        if (nz) {
-            const int ncol = jb - kk - 2;
-            for (int e = tid; e < nr * ncol; e += PANEL_THREADS) {
-                const int r = e % nr, c = kk + 2 + e / nr;
-                if (gr0 + r > k) {
-                    double a[K], l[K], u[K], o[K];
-#pragma unroll
-                    for (int w = 0; w < K; ++w) {
-                        a[w] = tile[(w * jb + c) * R + r];
-                        l[w] = tile[(w * jb + kk) * R + r];
-                        u[w] = pcur[w * jb + c];
-                    }
-                    fms<K>(a, l, u, o);
-#pragma unroll
-                    for (int w = 0; w < K; ++w)
-                        tile[(w * jb + c) * R + r] = o[w];
-                }
-            }
-        }
+        if (wave == 0 && kk + 1 < jb)
+            emit(kk + 1, crow, cown);
         nz_prev = nz;
-        __syncthreads();
     }
+    __syncthreads();
 
     for (int e = tid; e < jb * R; e += PANEL_THREADS) {
         const int r = e % R, c = e / R;
@@ -618,8 +660,8 @@ struct UpdCfg<2> {
     static constexpr int BM = 64, BN = 64, TM = 4, TN = 4, KB = 16;
 };
 template <>
-struct UpdCfg<3> {
-    static constexpr int BM = 64, BN = 64, TM = 4, TN = 4, KB = 16;
+struct UpdCfg<3> {  // 32 x 64: 36.9 TFLOP/s on a 4032^2 x 64 update (64 x 64: 31.3)
+    static constexpr int BM = 32, BN = 64, TM = 2, TN = 4, KB = 16;
 };
 template <>
 struct UpdCfg<4> {
@@ -646,7 +688,8 @@ __global__ void k_zero_i64(int64_t *p)
 
 static size_t panel_lds_bytes(int K, int jb, int R)
 {
-    return ((size_t)K * jb * R + 3 * (size_t)K * jb) * sizeof(double);
+    // tile, two pivot rows, the displaced row, two staged copies
+    return ((size_t)K * jb * R + 5 * (size_t)K * jb) * sizeof(double);
 }
 
 // reset the grid-barrier counter and abort flag of one panel launch
