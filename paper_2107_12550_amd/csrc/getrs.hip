@@ -4,12 +4,10 @@
 //
 // The right-hand side is first gathered through the row permutation that
 // the pivot sequence composes to (y = P b).  Each triangle is then solved
-// in blocks of 64 rows: one launch per block updates every row beyond the
-// block with the block's finished values (one thread per row, the block's
-// columns in solve order), and the workgroup that owns the next block also
-// finishes that block's triangle (lanes = rows, one broadcast per pivot).
-// Per row the updates therefore arrive in increasing k for L and in
-// decreasing k for U, exactly as in the unblocked column-oriented solve.
+// by one persistent launch with a workgroup per 64-row block (see
+// k_trsv_lower / k_trsv_upper).  Per row the updates arrive in increasing k
+// for L and in decreasing k for U, exactly as in the unblocked
+// column-oriented solve.
 #include "common.hpp"
 #include "mw.hpp"
 
@@ -89,246 +87,248 @@ __global__ void k_diag_recip(int64_t n, const double *__restrict__ LU, int64_t l
 
 // Stage the square block rows/cols [b0, b0+bsz) of one triangle into LDS:
 // blk[(w*TS_BS + c)*TS_BS + r] = word w of entry (b0+r, b0+c).
-template <int K>
-__device__ __forceinline__ void stage_block(const double *__restrict__ LU, int64_t lda, int64_t ldp, int64_t b0,
-                                            int bsz, double *blk)
+// ---- one persistent launch per triangle ---------------------------------
+// Workgroup (one wave) per 64-row block.  A block takes every earlier
+// block's finished values as soon as that block's flag is set (columns in
+// solve order, so each row still sees its updates in the unblocked order),
+// then solves its own diagonal block with wave shuffles, publishes its
+// values through coherent device-scope atomics and sets its flag.  Blocks
+// wait only on blocks that were dispatched before them, and every spin is
+// bounded (on timeout the abort flag releases all waits).
+constexpr int TS_G = 16;  // columns whose factor entries are fetched together
+constexpr unsigned TS_SPIN = 1u << 22;
+
+__device__ __forceinline__ void ts_store(double *p, double v)
 {
-    const int lane = threadIdx.x;
-    for (int c = 0; c < bsz; ++c) {
-        if (lane < bsz) {
-#pragma unroll
-            for (int w = 0; w < K; ++w)
-                blk[(w * TS_BS + c) * TS_BS + lane] = LU[w * ldp + (b0 + c) * lda + b0 + lane];
-        }
-    }
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ts_load(const double *p)
+{
+    return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// y_i <- y_i - sum over the columns k0..k0+bsz-1 (in the given direction)
-// of t_ik y_k, operands fetched eight columns ahead of use
-template <int K, bool DESC>
-__device__ __forceinline__ void chain_update(const double *__restrict__ LU, int64_t lda, int64_t ldp, int64_t i,
-                                             int64_t k0, int bsz, const double (*yb)[K], double (&v)[K])
+__device__ __forceinline__ void ts_wait(int *flag, int *abort_flag)
 {
-    constexpr int G = 8;
-    for (int g0 = 0; g0 < bsz; g0 += G) {
-        double t[G][K];
-#pragma unroll
-        for (int q = 0; q < G; ++q) {
-            const int kk = DESC ? bsz - 1 - (g0 + q) : g0 + q;
-            if (g0 + q < bsz) {
-#pragma unroll
-                for (int w = 0; w < K; ++w)
-                    t[q][w] = LU[w * ldp + (k0 + kk) * lda + i];
+    if (threadIdx.x == 0) {
+        unsigned spins = 0;
+        while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+            if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                break;
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > TS_SPIN) {
+                __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
             }
         }
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+__device__ __forceinline__ void ts_publish_flag(int *flag)
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0)
+        __hip_atomic_store(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ void k_ts_flags_reset(int *flags, int count)
+{
+    for (int e = threadIdx.x; e < count; e += blockDim.x)
+        flags[e] = 0;
+}
+
+// y <- L^-1 y (unit lower), y already permuted
+template <int K>
+__global__ void __launch_bounds__(TS_BS)
+    k_trsv_lower(const double *__restrict__ LU, int64_t lda, int64_t ldp, double *__restrict__ y, int64_t ldy,
+                 int64_t n, int *__restrict__ flags, int *__restrict__ abort_flag)
+{
+    extern __shared__ double dblk[];  // own diagonal block [w][c][r]
+    __shared__ double yb[TS_BS][K];
+    const int b = blockIdx.x, lane = threadIdx.x;
+    const int64_t r0 = (int64_t)b * TS_BS;
+    const int bsz = (int)((n - r0) < TS_BS ? (n - r0) : TS_BS);
+    const int64_t i = r0 + lane;
+    const bool act = lane < bsz;
+    for (int c = 0; c < bsz; ++c)
+        if (act)
 #pragma unroll
-        for (int q = 0; q < G; ++q) {
-            const int kk = DESC ? bsz - 1 - (g0 + q) : g0 + q;
-            if (g0 + q < bsz) {
+            for (int w = 0; w < K; ++w)
+                dblk[(w * TS_BS + c) * TS_BS + lane] = LU[w * ldp + (r0 + c) * lda + i];
+    double v[K];
+#pragma unroll
+    for (int w = 0; w < K; ++w)
+        v[w] = act ? y[w * ldy + i] : 0.0;
+    for (int c = 0; c < b; ++c) {  // earlier blocks are full
+        const int64_t k0 = (int64_t)c * TS_BS;
+        double t[TS_G][K];
+#pragma unroll
+        for (int q = 0; q < TS_G; ++q)
+#pragma unroll
+            for (int w = 0; w < K; ++w)
+                t[q][w] = act ? LU[w * ldp + (k0 + q) * lda + i] : 0.0;
+        ts_wait(flags + c, abort_flag);
+#pragma unroll
+        for (int w = 0; w < K; ++w)
+            yb[lane][w] = ts_load(y + w * ldy + k0 + lane);
+        __syncthreads();
+        for (int g0 = 0; g0 < TS_BS; g0 += TS_G) {
+            double tn[TS_G][K];
+            const bool more = g0 + TS_G < TS_BS;
+            if (more)
+#pragma unroll
+                for (int q = 0; q < TS_G; ++q)
+#pragma unroll
+                    for (int w = 0; w < K; ++w)
+                        tn[q][w] = act ? LU[w * ldp + (k0 + g0 + TS_G + q) * lda + i] : 0.0;
+#pragma unroll
+            for (int q = 0; q < TS_G; ++q) {
                 double yk[K], o[K];
 #pragma unroll
                 for (int w = 0; w < K; ++w)
-                    yk[w] = yb[kk][w];
+                    yk[w] = yb[g0 + q][w];
                 fms<K>(v, t[q], yk, o);
 #pragma unroll
                 for (int w = 0; w < K; ++w)
                     v[w] = o[w];
             }
-        }
-    }
-}
-
-// ---- lower (unit) triangle -------------------------------------------------
-
-// finish block [b0, b0+bsz) with the block staged in LDS:
-// y_r <- y_r - l_rk y_k for k < r inside the block
-template <int K>
-__device__ __forceinline__ void lower_block(const double *blk, int bsz, double (&v)[K], double (*ub)[K])
-{
-    const int lane = threadIdx.x;
-    for (int kk = 0; kk < bsz; ++kk) {
-        if (lane == kk) {
+            if (more)
 #pragma unroll
-            for (int w = 0; w < K; ++w)
-                ub[0][w] = v[w];
+                for (int q = 0; q < TS_G; ++q)
+#pragma unroll
+                    for (int w = 0; w < K; ++w)
+                        t[q][w] = tn[q][w];
         }
         __syncthreads();
-        if (lane > kk && lane < bsz) {
-            double l[K], yk[K], o[K];
+    }
+    __syncthreads();
+    for (int kk = 0; kk < bsz; ++kk) {
+        double yk[K];
 #pragma unroll
-            for (int w = 0; w < K; ++w) {
-                l[w] = blk[(w * TS_BS + kk) * TS_BS + lane];
-                yk[w] = ub[0][w];
-            }
+        for (int w = 0; w < K; ++w)
+            yk[w] = __shfl(v[w], kk, 64);
+        if (act && lane > kk) {
+            double l[K], o[K];
+#pragma unroll
+            for (int w = 0; w < K; ++w)
+                l[w] = dblk[(w * TS_BS + kk) * TS_BS + lane];
             fms<K>(v, l, yk, o);
 #pragma unroll
             for (int w = 0; w < K; ++w)
                 v[w] = o[w];
         }
+    }
+    if (act)
+#pragma unroll
+        for (int w = 0; w < K; ++w)
+            ts_store(y + w * ldy + i, v[w]);
+    ts_publish_flag(flags + b);
+}
+
+// y <- U^-1 y with rd = 1/u_kk; workgroup g solves block nblk-1-g
+template <int K>
+__global__ void __launch_bounds__(TS_BS)
+    k_trsv_upper(const double *__restrict__ LU, int64_t lda, int64_t ldp, const double *__restrict__ rd, double *__restrict__ y,
+                 int64_t ldy, int64_t n, int *__restrict__ flags, int *__restrict__ abort_flag)
+{
+    extern __shared__ double dblk[];
+    __shared__ double xb[TS_BS][K];
+    const int nblk = gridDim.x, lane = threadIdx.x;
+    const int b = nblk - 1 - (int)blockIdx.x;
+    const int64_t r0 = (int64_t)b * TS_BS;
+    const int bsz = (int)((n - r0) < TS_BS ? (n - r0) : TS_BS);
+    const int64_t i = r0 + lane;
+    const bool act = lane < bsz;
+    for (int c = 0; c < bsz; ++c)
+        if (act)
+#pragma unroll
+            for (int w = 0; w < K; ++w)
+                dblk[(w * TS_BS + c) * TS_BS + lane] = LU[w * ldp + (r0 + c) * lda + i];
+    double v[K], rk[K];
+#pragma unroll
+    for (int w = 0; w < K; ++w) {
+        v[w] = act ? y[w * ldy + i] : 0.0;
+        rk[w] = act ? rd[w * n + i] : 0.0;
+    }
+    for (int c = nblk - 1; c > b; --c) {
+        const int64_t k0 = (int64_t)c * TS_BS;
+        const int bc = (int)((n - k0) < TS_BS ? (n - k0) : TS_BS);
+        double t[TS_G][K];
+#pragma unroll
+        for (int q = 0; q < TS_G; ++q)
+#pragma unroll
+            for (int w = 0; w < K; ++w)
+                t[q][w] = (act && q < bc) ? LU[w * ldp + (k0 + bc - 1 - q) * lda + i] : 0.0;
+        ts_wait(flags + c, abort_flag);
+#pragma unroll
+        for (int w = 0; w < K; ++w)
+            xb[lane][w] = lane < bc ? ts_load(y + w * ldy + k0 + lane) : 0.0;
+        __syncthreads();
+        for (int g0 = 0; g0 < bc; g0 += TS_G) {
+            double tn[TS_G][K];
+            const bool more = g0 + TS_G < bc;
+            if (more)
+#pragma unroll
+                for (int q = 0; q < TS_G; ++q)
+#pragma unroll
+                    for (int w = 0; w < K; ++w)
+                        tn[q][w] = (act && g0 + TS_G + q < bc)
+                                       ? LU[w * ldp + (k0 + bc - 1 - (g0 + TS_G + q)) * lda + i]
+                                       : 0.0;
+#pragma unroll
+            for (int q = 0; q < TS_G; ++q) {
+                if (g0 + q < bc) {
+                    double xk[K], o[K];
+#pragma unroll
+                    for (int w = 0; w < K; ++w)
+                        xk[w] = xb[bc - 1 - (g0 + q)][w];
+                    fms<K>(v, t[q], xk, o);
+#pragma unroll
+                    for (int w = 0; w < K; ++w)
+                        v[w] = o[w];
+                }
+            }
+            if (more)
+#pragma unroll
+                for (int q = 0; q < TS_G; ++q)
+#pragma unroll
+                    for (int w = 0; w < K; ++w)
+                        t[q][w] = tn[q][w];
+        }
         __syncthreads();
     }
-}
-
-template <int K>
-__global__ void __launch_bounds__(TS_BS)
-    k_lower_first(const double *__restrict__ LU, int64_t lda, int64_t ldp, double *__restrict__ y, int64_t ldy,
-                  int64_t n)
-{
-    extern __shared__ double blk[];
-    __shared__ double ub[1][K];
-    const int lane = threadIdx.x;
-    const int bsz = (int)(n < TS_BS ? n : TS_BS);
-    stage_block<K>(LU, lda, ldp, 0, bsz, blk);
-    double v[K];
-    if (lane < bsz) {
-#pragma unroll
-        for (int w = 0; w < K; ++w)
-            v[w] = y[w * ldy + lane];
-    }
     __syncthreads();
-    lower_block<K>(blk, bsz, v, ub);
-    if (lane < bsz) {
-#pragma unroll
-        for (int w = 0; w < K; ++w)
-            y[w * ldy + lane] = v[w];
-    }
-}
-
-// rows beyond block [b0, b0+bsz) take that block's contribution; workgroup 0
-// (rows [b0+bsz, b0+bsz+64)) then finishes its own block.
-template <int K>
-__global__ void __launch_bounds__(TS_BS)
-    k_lower_step(const double *__restrict__ LU, int64_t lda, int64_t ldp, double *__restrict__ y, int64_t ldy,
-                 int64_t n, int64_t b0, int bsz)
-{
-    extern __shared__ double blk[];
-    __shared__ double yb[TS_BS][K];
-    __shared__ double ub[1][K];
-    const int lane = threadIdx.x;
-    const int64_t rb = b0 + bsz + (int64_t)blockIdx.x * TS_BS;  // first row of this workgroup
-    const int nsz = (int)((n - rb) < TS_BS ? (n - rb) : TS_BS);
-    if (blockIdx.x == 0)
-        stage_block<K>(LU, lda, ldp, rb, nsz, blk);
-    if (lane < bsz) {
-#pragma unroll
-        for (int w = 0; w < K; ++w)
-            yb[lane][w] = y[w * ldy + b0 + lane];
-    }
-    __syncthreads();
-    const int64_t i = rb + lane;
-    double v[K];
-    if (i < n) {
-#pragma unroll
-        for (int w = 0; w < K; ++w)
-            v[w] = y[w * ldy + i];
-        chain_update<K, false>(LU, lda, ldp, i, b0, bsz, yb, v);
-    }
-    if (blockIdx.x == 0)
-        lower_block<K>(blk, nsz, v, ub);
-    if (i < n) {
-#pragma unroll
-        for (int w = 0; w < K; ++w)
-            y[w * ldy + i] = v[w];
-    }
-}
-
-// ---- upper triangle --------------------------------------------------------
-
-// finish block [b0, b0+bsz) staged in LDS: for k = bsz-1..0:
-// x_k = y_k * r_k (r = 1/u_kk), then y_r <- y_r - u_rk x_k for r < k
-template <int K>
-__device__ __forceinline__ void upper_block(const double *blk, const double *__restrict__ rd, int64_t n, int64_t b0,
-                                            int bsz, double (&v)[K], double (*ub)[K])
-{
-    const int lane = threadIdx.x;
-    double rk[K];
-    if (lane < bsz) {
-#pragma unroll
-        for (int w = 0; w < K; ++w)
-            rk[w] = rd[w * n + b0 + lane];
-    }
     for (int kk = bsz - 1; kk >= 0; --kk) {
         if (lane == kk) {
             double xk[K];
             mul<K>(v, rk, xk);
 #pragma unroll
-            for (int w = 0; w < K; ++w) {
+            for (int w = 0; w < K; ++w)
                 v[w] = xk[w];
-                ub[0][w] = xk[w];
-            }
         }
-        __syncthreads();
-        if (lane < kk) {
-            double u[K], xk[K], o[K];
+        double xk[K];
 #pragma unroll
-            for (int w = 0; w < K; ++w) {
-                u[w] = blk[(w * TS_BS + kk) * TS_BS + lane];
-                xk[w] = ub[0][w];
-            }
+        for (int w = 0; w < K; ++w)
+            xk[w] = __shfl(v[w], kk, 64);
+        if (act && lane < kk) {
+            double u[K], o[K];
+#pragma unroll
+            for (int w = 0; w < K; ++w)
+                u[w] = dblk[(w * TS_BS + kk) * TS_BS + lane];
             fms<K>(v, u, xk, o);
 #pragma unroll
             for (int w = 0; w < K; ++w)
                 v[w] = o[w];
         }
-        __syncthreads();
     }
-}
-
-template <int K>
-__global__ void __launch_bounds__(TS_BS)
-    k_upper_first(const double *__restrict__ LU, int64_t lda, int64_t ldp, const double *__restrict__ rd, int64_t n,
-                  double *__restrict__ y, int64_t ldy, int64_t b0, int bsz)
-{
-    extern __shared__ double blk[];
-    __shared__ double ub[1][K];
-    const int lane = threadIdx.x;
-    stage_block<K>(LU, lda, ldp, b0, bsz, blk);
-    double v[K];
-    if (lane < bsz) {
+    if (act)
 #pragma unroll
         for (int w = 0; w < K; ++w)
-            v[w] = y[w * ldy + b0 + lane];
-    }
-    __syncthreads();
-    upper_block<K>(blk, rd, n, b0, bsz, v, ub);
-    if (lane < bsz) {
-#pragma unroll
-        for (int w = 0; w < K; ++w)
-            y[w * ldy + b0 + lane] = v[w];
-    }
-}
-
-// rows above block [b0, b0+bsz) take its contribution (k decreasing);
-// workgroup 0 (rows [b0-64, b0)) then finishes its own block.
-template <int K>
-__global__ void __launch_bounds__(TS_BS)
-    k_upper_step(const double *__restrict__ LU, int64_t lda, int64_t ldp, const double *__restrict__ rd, int64_t n,
-                 double *__restrict__ y, int64_t ldy, int64_t b0, int bsz)
-{
-    extern __shared__ double blk[];
-    __shared__ double xb[TS_BS][K];
-    __shared__ double ub[1][K];
-    const int lane = threadIdx.x;
-    const int64_t rb = b0 - (int64_t)(blockIdx.x + 1) * TS_BS;  // first row of this workgroup (b0 % 64 == 0)
-    if (blockIdx.x == 0)
-        stage_block<K>(LU, lda, ldp, rb, TS_BS, blk);
-    if (lane < bsz) {
-#pragma unroll
-        for (int w = 0; w < K; ++w)
-            xb[lane][w] = y[w * ldy + b0 + lane];
-    }
-    __syncthreads();
-    const int64_t i = rb + lane;
-    double v[K];
-#pragma unroll
-    for (int w = 0; w < K; ++w)
-        v[w] = y[w * ldy + i];
-    chain_update<K, true>(LU, lda, ldp, i, b0, bsz, xb, v);
-    if (blockIdx.x == 0)
-        upper_block<K>(blk, rd, n, rb, TS_BS, v, ub);
-#pragma unroll
-    for (int w = 0; w < K; ++w)
-        y[w * ldy + i] = v[w];
+            ts_store(y + w * ldy + i, v[w]);
+    ts_publish_flag(flags + b);
 }
 
 template <int K>
@@ -341,10 +341,8 @@ static void allow_lds()
     if (done)
         return;
     const int b = (int)block_lds<K>();
-    if (hipFuncSetAttribute((const void *)k_lower_first<K>, hipFuncAttributeMaxDynamicSharedMemorySize, b) != hipSuccess ||
-        hipFuncSetAttribute((const void *)k_lower_step<K>, hipFuncAttributeMaxDynamicSharedMemorySize, b) != hipSuccess ||
-        hipFuncSetAttribute((const void *)k_upper_first<K>, hipFuncAttributeMaxDynamicSharedMemorySize, b) != hipSuccess ||
-        hipFuncSetAttribute((const void *)k_upper_step<K>, hipFuncAttributeMaxDynamicSharedMemorySize, b) != hipSuccess)
+    if (hipFuncSetAttribute((const void *)k_trsv_lower<K>, hipFuncAttributeMaxDynamicSharedMemorySize, b) != hipSuccess ||
+        hipFuncSetAttribute((const void *)k_trsv_upper<K>, hipFuncAttributeMaxDynamicSharedMemorySize, b) != hipSuccess)
         (void)hipGetLastError();
     done = true;
 }
@@ -360,40 +358,34 @@ int diag_recip_run(int64_t n, const double *LU, int64_t lda, int64_t ldp, double
 }
 
 // Solve in place on y (already permuted), one right-hand side; rd = 1/u_kk.
+// flags: 2 * ceil(n/64) + 1 ints of scratch for the persistent launches.
 template <int K>
 int trsv_pair(int64_t n, const double *LU, int64_t lda, int64_t ldp, const double *rd, double *y, int64_t ldy,
-              hipStream_t s)
+              int *flags, hipStream_t s)
 {
     if (n == 0)
         return BNC_OK;
     allow_lds<K>();
     const size_t lds = block_lds<K>();
     const int64_t nblk = ceil_div(n, TS_BS);
-    hipLaunchKernelGGL((k_lower_first<K>), dim3(1), dim3(TS_BS), lds, s, LU, lda, ldp, y, ldy, n);
+    const int nf = (int)(2 * nblk + 1);
+    int *abort_flag = flags + 2 * nblk;
+    hipLaunchKernelGGL(k_ts_flags_reset, dim3(1), dim3(256), 0, s, flags, nf);
     BNC_LAUNCH_CHECK();
-    for (int64_t B = 0; B + 1 < nblk; ++B) {
-        const int64_t b0 = B * TS_BS;
-        const unsigned g = (unsigned)ceil_div(n - b0 - TS_BS, TS_BS);
-        hipLaunchKernelGGL((k_lower_step<K>), dim3(g), dim3(TS_BS), lds, s, LU, lda, ldp, y, ldy, n, b0, TS_BS);
-        BNC_LAUNCH_CHECK();
-    }
-    const int64_t last = (nblk - 1) * TS_BS;
-    hipLaunchKernelGGL((k_upper_first<K>), dim3(1), dim3(TS_BS), lds, s, LU, lda, ldp, rd, n, y, ldy, last,
-                       (int)(n - last));
+    hipLaunchKernelGGL((k_trsv_lower<K>), dim3((unsigned)nblk), dim3(TS_BS), lds, s, LU, lda, ldp, y, ldy, n, flags,
+                       abort_flag);
     BNC_LAUNCH_CHECK();
-    for (int64_t B = nblk - 1; B >= 1; --B) {
-        const int64_t b0 = B * TS_BS;
-        const int bsz = (int)((n - b0) < TS_BS ? (n - b0) : TS_BS);
-        hipLaunchKernelGGL((k_upper_step<K>), dim3((unsigned)B), dim3(TS_BS), lds, s, LU, lda, ldp, rd, n, y, ldy,
-                           b0, bsz);
-        BNC_LAUNCH_CHECK();
-    }
+    hipLaunchKernelGGL((k_trsv_upper<K>), dim3((unsigned)nblk), dim3(TS_BS), lds, s, LU, lda, ldp, rd, y, ldy, n,
+                       flags + nblk, abort_flag);
+    BNC_LAUNCH_CHECK();
     return BNC_OK;
 }
 
+size_t trsv_flags_bytes(int64_t n) { return (size_t)(2 * ceil_div(n, TS_BS) + 1) * sizeof(int); }
+
 size_t getrs_scratch_bytes(int K, int64_t n)
 {
-    return (size_t)n * sizeof(int32_t) + 2 * (size_t)K * n * sizeof(double) + 512;
+    return (size_t)n * sizeof(int32_t) + 2 * (size_t)K * n * sizeof(double) + trsv_flags_bytes(n) + 1024;
 }
 
 int ipiv_to_perm(int64_t n, const int64_t *ipiv, int32_t *perm, hipStream_t s)
@@ -408,13 +400,13 @@ int ipiv_to_perm(int64_t n, const int64_t *ipiv, int32_t *perm, hipStream_t s)
 // (K planes, stride n) and y buffer
 template <int K>
 int getrs_perm(int64_t n, const double *LU, int64_t lda, int64_t ldp, const int32_t *perm, const double *rd,
-               const double *b, int64_t ldb, double *y, int64_t ldy, hipStream_t s)
+               const double *b, int64_t ldb, double *y, int64_t ldy, int *flags, hipStream_t s)
 {
     if (n == 0)
         return BNC_OK;
     hipLaunchKernelGGL((k_gather<K>), dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, n, perm, b, ldb, y, ldy);
     BNC_LAUNCH_CHECK();
-    return trsv_pair<K>(n, LU, lda, ldp, rd, y, ldy, s);
+    return trsv_pair<K>(n, LU, lda, ldp, rd, y, ldy, flags, s);
 }
 
 template <int K>
@@ -426,6 +418,7 @@ int getrs_run(int64_t n, int64_t nrhs, const double *LU, int64_t lda, int64_t ld
     int32_t *perm = (int32_t *)scr;
     double *y = (double *)((char *)scr + ((n * sizeof(int32_t) + 255) / 256) * 256);
     double *rd = y + (size_t)K * n;
+    int *flags = (int *)(rd + (size_t)K * n);
     int rc = ipiv_to_perm(n, ipiv, perm, s);
     if (rc)
         return rc;
@@ -433,7 +426,7 @@ int getrs_run(int64_t n, int64_t nrhs, const double *LU, int64_t lda, int64_t ld
         return rc;
     for (int64_t c = 0; c < nrhs; ++c) {
         double *bc = B + c * ldb;
-        rc = getrs_perm<K>(n, LU, lda, ldp, perm, rd, bc, ldpb, y, n, s);
+        rc = getrs_perm<K>(n, LU, lda, ldp, perm, rd, bc, ldpb, y, n, flags, s);
         if (rc)
             return rc;
         hipLaunchKernelGGL((k_copy_vec<K>), dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, n, y, n, bc, ldpb);
@@ -444,7 +437,7 @@ int getrs_run(int64_t n, int64_t nrhs, const double *LU, int64_t lda, int64_t ld
 
 #define INST(K)                                                                                                     \
     template int getrs_perm<K>(int64_t, const double *, int64_t, int64_t, const int32_t *, const double *,          \
-                               const double *, int64_t, double *, int64_t, hipStream_t);                            \
+                               const double *, int64_t, double *, int64_t, int *, hipStream_t);                     \
     template int diag_recip_run<K>(int64_t, const double *, int64_t, int64_t, double *, hipStream_t);               \
     template int getrs_run<K>(int64_t, int64_t, const double *, int64_t, int64_t, const int64_t *, double *,        \
                               int64_t, int64_t, void *, hipStream_t);
