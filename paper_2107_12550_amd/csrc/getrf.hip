@@ -175,6 +175,7 @@ __global__ void __launch_bounds__(PANEL_THREADS)
     double *prow = tile + (size_t)K * jb * R;     // [2][K*jb] pivot rows of this and the previous column
     double *orow = prow + 2 * (size_t)K * jb;     // [K*jb]    displaced row k
     __shared__ int s_p;
+    __shared__ double s_rcp[K];
     __shared__ int s_piv[PANEL_NB_MAX];
 
     const int P = gridDim.x;
@@ -268,12 +269,18 @@ __global__ void __launch_bounds__(PANEL_THREADS)
             for (int w = 0; w < K; ++w)
                 key[w] = 0.0;
             for (int t = lane; t < P; t += 64) {
-                const int rr = (int)sh_load(cidx + b * P + t);
-                double kv[K];
+                // index and key in one round trip (the key of a workgroup
+                // without a candidate is ignored)
                 const double *cc = cand + ((size_t)(b * P + t) * K) * jb;
+                double kv[K];
 #pragma unroll
                 for (int w = 0; w < K; ++w)
-                    kv[w] = rr >= 0 ? sh_load(cc + w * jb + kk) : 0.0;
+                    kv[w] = sh_load(cc + w * jb + kk);
+                const int rr = (int)sh_load(cidx + b * P + t);
+                if (rr < 0)
+#pragma unroll
+                    for (int w = 0; w < K; ++w)
+                        kv[w] = 0.0;
                 if (cand_better<K>(kv, rr, key, row)) {
 #pragma unroll
                     for (int w = 0; w < K; ++w)
@@ -284,6 +291,15 @@ __global__ void __launch_bounds__(PANEL_THREADS)
             wave_argmax<K>(key, row);
             const int64_t p = row;
             const int gw = (int)((p - j0) / R);
+            // the winner's key is the pivot (column kk of a published
+            // candidate is final): its reciprocal, while the row loads
+            if (lane == 0 && !is_zero<K>(key)) {
+                double rcp[K];
+                recip<K>(key, rcp);
+#pragma unroll
+                for (int w = 0; w < K; ++w)
+                    s_rcp[w] = rcp[w];
+            }
             // ---- rebuild the pivot row (and the displaced row k for p's
             //      owner) from their published copies; lane = column
             const double *cc = cand + ((size_t)(b * P + gw) * K) * jb;
@@ -389,7 +405,9 @@ __global__ void __launch_bounds__(PANEL_THREADS)
         // ---- multipliers l_ik = a_ik * (1/a_kk), rows > k (wave 0, lane = row)
         if (nz && wave == 0 && lane < nr && gr0 + lane > k) {
             double rcp[K], a[K], l[K];
-            recip<K>(pv, rcp);
+#pragma unroll
+            for (int w = 0; w < K; ++w)
+                rcp[w] = s_rcp[w];
 #pragma unroll
             for (int w = 0; w < K; ++w)
                 a[w] = tile[(w * jb + kk) * R + lane];
