@@ -38,6 +38,49 @@ constexpr int RES_WAVES = 4;
 constexpr int RED_BLOCKS = 256;  // partial-sum slots of the deterministic reductions
 // partial bins of rows [64*bx, +64); workgroup column split sidx, each wave
 // a quarter of it: split index sidx*4 + wave
+// the deposits of one row's slice of columns into NB bins (nb <= NB used)
+template <int AW, int NB>
+__device__ __forceinline__ void resid_slice(const double *__restrict__ A, int64_t lda, int64_t ldpa,
+                                            const double *__restrict__ x, int64_t ldx, const double *__restrict__ b,
+                                            int64_t ldb, int64_t i, int64_t q0, int64_t q1, bool with_b,
+                                            const RowAnchor &an, double *__restrict__ out, int64_t stride, bool &bad)
+{
+    const int nb = an.nb;
+    double bins[NB], sig[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        bins[q] = 0.0;
+        sig[q] = q < nb ? 1.5 * pow2(an.e0 - RB_W * q + 52) : 0.0;
+    }
+    const double lim0 = pow2(an.e0 + 51);
+    for (int64_t j = q0; j < q1; ++j) {
+        double xv[4];
+#pragma unroll
+        for (int w = 0; w < 4; ++w)
+            xv[w] = x[w * ldx + j];
+#pragma unroll
+        for (int u = 0; u < AW; ++u) {
+            const double a = A[u * ldpa + j * lda + i];
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                double lo;
+                const double hi = two_prod(a, xv[w], lo);
+                deposit(-hi, sig, bins, nb, lim0, bad);
+                deposit(-lo, sig, bins, nb, lim0, bad);
+            }
+        }
+    }
+    if (with_b) {
+#pragma unroll
+        for (int w = 0; w < 4; ++w)
+            deposit(b[w * ldb + i], sig, bins, nb, lim0, bad);
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q)
+        if (q < nb)
+            out[q * stride] = bins[q];
+}
+
 template <int AW>
 __global__ void __launch_bounds__(RES_ROWS *RES_WAVES)
     k_resid_partial(int64_t n, const double *__restrict__ A, int64_t lda, int64_t ldpa, const double *__restrict__ x,
@@ -50,51 +93,23 @@ __global__ void __launch_bounds__(RES_ROWS *RES_WAVES)
     const int split = blockIdx.y * RES_WAVES + wv;
     if (i >= n)
         return;
-    double bins[RB_NB];
-#pragma unroll
-    for (int q = 0; q < RB_NB; ++q)
-        bins[q] = 0.0;
     bool bad = false;
     const double xm = *xmaxp;
     const RowAnchor an = row_anchor(rowmax[i], xm, b[i], h, lowest_bit(*ebp));
-    const int nb = an.nb;
     if (an.any) {
-        double sig[RB_NB];
-#pragma unroll
-        for (int q = 0; q < RB_NB; ++q)
-            sig[q] = q < nb ? 1.5 * pow2(an.e0 - RB_W * q + 52) : 0.0;
-        const double lim0 = pow2(an.e0 + 51);
         const int64_t j0 = (int64_t)blockIdx.y * chunk;
         const int64_t j1 = (j0 + chunk) < n ? (j0 + chunk) : n;
         const int64_t len = j1 > j0 ? j1 - j0 : 0;
         const int64_t q0 = j0 + (len * wv) / RES_WAVES, q1 = j0 + (len * (wv + 1)) / RES_WAVES;
-        for (int64_t j = q0; j < q1; ++j) {
-            double xv[4];
-#pragma unroll
-            for (int w = 0; w < 4; ++w)
-                xv[w] = x[w * ldx + j];
-#pragma unroll
-            for (int u = 0; u < AW; ++u) {
-                const double a = A[u * ldpa + j * lda + i];
-#pragma unroll
-                for (int w = 0; w < 4; ++w) {
-                    double lo;
-                    const double hi = two_prod(a, xv[w], lo);
-                    deposit(-hi, sig, bins, nb, lim0, bad);
-                    deposit(-lo, sig, bins, nb, lim0, bad);
-                }
-            }
-        }
-        if (split == 0) {
-#pragma unroll
-            for (int w = 0; w < 4; ++w)
-                deposit(b[w * ldb + i], sig, bins, nb, lim0, bad);
-        }
+        double *out = part + (int64_t)split * RB_NB * n + i;
+        // the window is usually a few bins wide: deposit loops sized to it
+        if (an.nb <= 8)
+            resid_slice<AW, 8>(A, lda, ldpa, x, ldx, b, ldb, i, q0, q1, split == 0, an, out, n, bad);
+        else if (an.nb <= 16)
+            resid_slice<AW, 16>(A, lda, ldpa, x, ldx, b, ldb, i, q0, q1, split == 0, an, out, n, bad);
+        else
+            resid_slice<AW, RB_NB>(A, lda, ldpa, x, ldx, b, ldb, i, q0, q1, split == 0, an, out, n, bad);
     }
-#pragma unroll
-    for (int q = 0; q < RB_NB; ++q)
-        if (q < nb)
-            part[((int64_t)split * RB_NB + q) * n + i] = bins[q];
     if (bad)
         atomicOr(inexact, 1);
 }
@@ -207,15 +222,21 @@ __global__ void k_stage(int64_t n, const double *__restrict__ A, int64_t lda, in
 }
 
 // rowmax[i] = max_j |A0(i, j)|  (thread per row, coalesced across rows)
-__global__ void k_rowmax(int64_t n, const double *__restrict__ A, int64_t lda, double *__restrict__ rowmax)
+// row maxima of |A| (leading words): blockIdx.y takes a slice of the
+// columns; slices combine with an integer maximum of the bit patterns
+// (non-negative doubles order like their bits), which is exact in any order
+constexpr int ROWMAX_SPLIT = 32;
+__global__ void k_rowmax(int64_t n, const double *__restrict__ A, int64_t lda,
+                         unsigned long long *__restrict__ rowmax_bits)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n)
         return;
+    const int64_t j0 = (int64_t)blockIdx.y * n / ROWMAX_SPLIT, j1 = ((int64_t)blockIdx.y + 1) * n / ROWMAX_SPLIT;
     double m = 0.0;
-    for (int64_t j = 0; j < n; ++j)
+    for (int64_t j = j0; j < j1; ++j)
         m = fmax(m, fabs(A[j * lda + i]));
-    rowmax[i] = m;
+    atomicMax(rowmax_bits + i, (unsigned long long)__double_as_longlong(m));
 }
 
 // max |v(i, j)| over rows x cols entries (leading dimension ld), folded into
@@ -414,7 +435,10 @@ int residual_run(int64_t n, int aw, const double *A, int64_t lda, int64_t ldpa, 
 // rowmax of |A0| and a one-element max of a vector's leading words
 int rowmax_run(int64_t n, const double *A, int64_t lda, double *rowmax, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_rowmax, dim3(grid1(n)), dim3(256), 0, s, n, A, lda, rowmax);
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid1(n)), dim3(256), 0, s, (uint64_t *)rowmax, n, (uint64_t)0);
+    BNC_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_rowmax, dim3(grid1(n), ROWMAX_SPLIT), dim3(256), 0, s, n, A, lda,
+                       (unsigned long long *)rowmax);
     BNC_LAUNCH_CHECK();
     return BNC_OK;
 }
