@@ -21,6 +21,7 @@
 // bit.
 #include "common.hpp"
 #include "mw.hpp"
+#include "ozsplit.hpp"
 
 namespace bnc {
 
@@ -68,16 +69,21 @@ __device__ __forceinline__ void wave_argmax(double (&key)[K], int &row)
     }
 }
 
-// Cross-workgroup exchange inside the panel.  Every word another workgroup
-// reads (candidate rows, their row indices, the row at the pivot position,
-// the arrival counter) is written and read with device-scope relaxed
-// atomics, which the hardware keeps coherent across the XCDs' L2 caches on
-// their own (write-through stores, loads that miss the non-coherent caches).
-// That makes a full device fence, which would write back and invalidate the
-// whole L2 while the concurrent trailing update keeps it full of dirty
-// lines, unnecessary: a workgroup waits for its own stores to complete
-// before it bumps the counter, and readers load the data only after they
-// have seen the counter reach its target.
+// Cross-workgroup exchange inside the panel.  Each panel launch has an
+// exchange buffer (two, alternating between consecutive panels) holding,
+// per column kk of the panel, the row index of every workgroup's pivot
+// candidate (-1: none), a copy of every candidate row and a copy of the row
+// at position j0 + kk.  Every word of it starts as XSENT, a signalling NaN
+// that no arithmetic produces, and is written at most once per panel, so a
+// reader polls the words it needs until none is XSENT: no counters, no
+// fences, and a writer never waits for its own stores.  Words are written
+// and read with device-scope relaxed atomics, which the hardware keeps
+// coherent across the XCDs' L2 caches (write-through stores, loads that
+// miss the non-coherent caches).  A matrix that holds the XSENT bit pattern
+// itself can stall a poll; every poll is bounded and such a panel ends with
+// info = -1.
+constexpr int64_t XSENT = (int64_t)0xFFF40000DEADBEEFull;
+
 __device__ __forceinline__ void sh_store(double *p, double v)
 {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -94,62 +100,93 @@ __device__ __forceinline__ int64_t sh_load(const int64_t *p)
 {
     return __hip_atomic_load(const_cast<int64_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ bool xsent(double v) { return __double_as_longlong(v) == (long long)XSENT; }
 
-// Grid barrier on a monotonic counter, split into arrive and wait so that
-// work can overlap the wait.  The spin is bounded: on timeout the workgroup
-// records the failure and every later wait returns at once, so the grid
-// always drains.
+// Bounded polling: after SPIN_LIMIT retries (or once another workgroup has
+// given up) the lane marks the panel failed and goes on with what it has,
+// so the grid always drains.
 constexpr unsigned SPIN_LIMIT = 1u << 21;
 
-__device__ __forceinline__ void bar_arrive_wave(unsigned *bar)
-{
-    // called by one whole wave after its sh_store()s: wait until they have
-    // completed, then count this workgroup in
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_s_waitcnt(0);
-    if ((threadIdx.x & 63) == 0)
-        __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ void bar_wait(unsigned *bar, unsigned target, int *abort_flag)
-{
-    if (threadIdx.x == 0) {
-        unsigned spins = 0;
-        while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-                break;
-            __builtin_amdgcn_s_sleep(1);
-            if (++spins > SPIN_LIMIT) {
-                __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                break;
-            }
+struct Poll {
+    unsigned spins = 0;
+    bool dead = false;
+    // one more retry allowed?
+    __device__ __forceinline__ bool again(int *abort_flag)
+    {
+        if (dead)
+            return false;
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > SPIN_LIMIT ||
+            ((spins & 1023u) == 0 && __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+            __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            dead = true;
+            return false;
         }
+        return true;
     }
-    __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
+};
 
-// The same wait for one wave only (the other waves keep working).
-__device__ __forceinline__ void bar_wait_wave(unsigned *bar, unsigned target, int *abort_flag)
+// K words at p[w * stride], polled until none is XSENT
+template <int K>
+__device__ __forceinline__ void xpoll(const double *p, int stride, double (&v)[K], Poll &pl, int *abort_flag)
 {
-    if ((threadIdx.x & 63) == 0) {
-        unsigned spins = 0;
-        while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-                break;
-            __builtin_amdgcn_s_sleep(1);
-            if (++spins > SPIN_LIMIT) {
-                __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                break;
-            }
+    bool any;
+    do {
+        // every word is written once: reloading one already seen is harmless
+        any = false;
+#pragma unroll
+        for (int w = 0; w < K; ++w) {
+            v[w] = sh_load(p + w * stride);
+            any |= xsent(v[w]);
         }
-    }
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    } while (any && pl.again(abort_flag));
 }
 
-// LDS tile layout: word w, panel column c, local row r at ((w*jb + c)*R + r);
-// R <= 64, so one wave holds one row per lane.
+// Exchange buffer layout (in doubles): idx [PANEL_WG_MAX][64] (int64),
+// rows [PANEL_WG_MAX][64][K * 64] (word w, column c at w * jb + c), own
+// [64][K * 64].
+template <int K>
+constexpr size_t xbuf_words()
+{
+    return (size_t)PANEL_WG_MAX * PANEL_NB_MAX * (1 + K * PANEL_NB_MAX) + (size_t)PANEL_NB_MAX * K * PANEL_NB_MAX;
+}
+
+// Broadcast of lane l's double (l wave-uniform) through scalar registers.
+__device__ __forceinline__ double readlane_d(double v, int l)
+{
+    const long long b = __double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// wave_argmax with a fast path: the key order compares |leading word|
+// first, so when exactly one lane holds the largest |leading word| it wins
+// outright; ties on it (or no candidate at all) take the full reduction.
+template <int K>
+__device__ __forceinline__ void wave_argmax_fast(double (&key)[K], int &row)
+{
+    const double m = row >= 0 ? fabs(key[0]) : -1.0;
+    double mx = m;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        mx = fmax(mx, __shfl_xor(mx, off, 64));
+    const unsigned long long at = __ballot(row >= 0 && m == mx);
+    if (__popcll(at) == 1) {
+        const int src = __builtin_ctzll(at);
+#pragma unroll
+        for (int w = 0; w < K; ++w)
+            key[w] = readlane_d(key[w], src);
+        row = __builtin_amdgcn_readlane(row, src);
+        return;
+    }
+    wave_argmax<K>(key, row);
+}
+
+// LDS tile layout: word w, panel column c, local row r at
+// ((w*jb + c)*(R+1) + r); R <= 64, so one wave holds one row per lane, and
+// the odd stride R+1 keeps row-wise access (lane = column) free of bank
+// conflicts.
 //
 // Column kk of the panel (global k = j0 + kk), per workgroup:
 //   wait for every workgroup's candidate for column kk
@@ -158,25 +195,32 @@ __device__ __forceinline__ void bar_wait_wave(unsigned *bar, unsigned target, in
 //   column kk was updated but before columns > kk were: finish those columns
 //   with the previous pivot row, exactly as their owner does
 //   swap, record ipiv, reciprocal of the pivot, scale column kk
-//   wave 0: update column kk+1, find the local candidate for column kk+1,
-//   copy it (and row k+1 if owned) to LDS; then, while waves 1.. update
-//   columns kk+2.., publish the copies and arrive, wait for the others and
-//   do the next column's pivot choice and row rebuild: the update of the
-//   panel's remaining columns leaves the critical path.
+//   wave 0: update column kk+1, find the local candidate for column kk+1
+//   and publish it (and row k+1 if owned); then, while waves 1.. update
+//   columns kk+2.., wait for the others and do the next column's pivot
+//   choice and row rebuild: the update of the panel's remaining columns
+//   leaves the critical path.
 template <int K>
 __global__ void __launch_bounds__(PANEL_THREADS)
     k_panel(double *__restrict__ A, int64_t lda, int64_t ldp, int64_t n, int64_t j0, int jb, int R,
-            int64_t *__restrict__ ipiv, int64_t *__restrict__ info, double *__restrict__ cand,
-            int64_t *__restrict__ cidx, double *__restrict__ rowk, int64_t *__restrict__ pairs,
-            unsigned *__restrict__ bar, int *__restrict__ abort_flag)
+            int64_t *__restrict__ ipiv, int64_t *__restrict__ info, double *__restrict__ xcur,
+            double *__restrict__ xnext, int64_t *__restrict__ pairs, int *__restrict__ abort_flag, int ozs,
+            double *__restrict__ SL, int64_t ldsl)
 {
+    constexpr int KJ = K * PANEL_NB_MAX;
+    constexpr int NW = PANEL_THREADS / 64;
+    int64_t *xidx = (int64_t *)xcur;
+    double *xrow = xcur + PANEL_WG_MAX * PANEL_NB_MAX;
+    double *xown = xrow + (size_t)PANEL_WG_MAX * PANEL_NB_MAX * KJ;
+    const int RS = R + 1;
     extern __shared__ double smem[];
-    double *tile = smem;                          // K*jb*R
-    double *prow = tile + (size_t)K * jb * R;     // [2][K*jb] pivot rows of this and the previous column
-    double *orow = prow + 2 * (size_t)K * jb;     // [K*jb]    displaced row k
+    double *tile = smem;                        // K*jb*RS
+    double *prow = tile + (size_t)K * jb * RS;  // [2][K*jb] pivot rows of this and the previous column
+    double *orow = prow + 2 * (size_t)K * jb;   // [K*jb]    displaced row k
     __shared__ int s_p;
     __shared__ double s_rcp[K];
     __shared__ int s_piv[PANEL_NB_MAX];
+    auto T = [&](int w, int c, int r) -> double & { return tile[(w * jb + c) * RS + r]; };
 
     const int P = gridDim.x;
     const int g = blockIdx.x;
@@ -189,110 +233,112 @@ __global__ void __launch_bounds__(PANEL_THREADS)
         const int r = e % R, c = e / R;
 #pragma unroll
         for (int w = 0; w < K; ++w)
-            tile[(w * jb + c) * R + r] = r < nr ? A[w * ldp + (j0 + c) * lda + gr0 + r] : 0.0;
+            T(w, c, r) = r < nr ? A[w * ldp + (j0 + c) * lda + gr0 + r] : 0.0;
     }
     __syncthreads();
 
-    double *pubc = orow + (size_t)K * jb;  // [K*jb] staged copy of this workgroup's candidate row
-    double *pubk = pubc + (size_t)K * jb;  // [K*jb] staged copy of the row at the next pivot position
-
-    // stage (wave 0): this workgroup's candidate for column cc (rows >=
-    // j0+cc) and the row at position j0+cc if owned, copied from the tile;
-    // returns the candidate row (-1: none), wave-uniform
-    auto stage = [&](int cc, bool &own) -> int {
+    // wave 0: this workgroup's candidate for column cc (rows >= j0+cc) and
+    // the row at position j0+cc if owned, published straight from the tile
+    // (lane = column); returns nothing, the copies are what the others need
+    auto publish = [&](int cc) {
         const int64_t kc = j0 + cc;
         double key[K];
         int row = -1;
-        if (lane < nr && gr0 + lane >= kc) {
+        const bool cand = lane < nr && gr0 + lane >= kc;
+#pragma unroll
+        for (int w = 0; w < K; ++w)
+            key[w] = 0.0;
+        if (cand) {
             row = (int)(gr0 + lane);
 #pragma unroll
             for (int w = 0; w < K; ++w)
-                key[w] = tile[(w * jb + cc) * R + lane];
-        } else {
+                key[w] = T(w, cc, lane);
+        }
+        wave_argmax_fast<K>(key, row);
+        if (row >= 0 && lane < jb) {
+            const int lr = (int)(row - gr0);
+            double *rb = xrow + ((size_t)g * PANEL_NB_MAX + cc) * KJ;
 #pragma unroll
             for (int w = 0; w < K; ++w)
-                key[w] = 0.0;
+                sh_store(rb + w * jb + lane, T(w, lane, lr));
         }
-        wave_argmax<K>(key, row);
-        if (row >= 0) {
-            const int lr = (int)(row - gr0);
-            for (int e = lane; e < K * jb; e += 64) {
-                const int w = e / jb, c = e % jb;
-                pubc[e] = tile[(w * jb + c) * R + lr];
-            }
-        }
-        own = kc >= gr0 && kc < gr0 + nr;
-        if (own) {
+        if (kc >= gr0 && kc < gr0 + nr && lane < jb) {
             const int lr = (int)(kc - gr0);
-            for (int e = lane; e < K * jb; e += 64) {
-                const int w = e / jb, c = e % jb;
-                pubk[e] = tile[(w * jb + c) * R + lr];
-            }
+            double *ob = xown + (size_t)cc * KJ;
+#pragma unroll
+            for (int w = 0; w < K; ++w)
+                sh_store(ob + w * jb + lane, T(w, lane, lr));
         }
-        return row;
-    };
-    // emit (wave 0): publish the staged copies for column cc and arrive
-    auto emit = [&](int cc, int row, bool own) {
-        const int b = cc & 1;
-        double *cb = cand + ((size_t)(b * P + g) * K) * jb;
-        if (row >= 0)
-            for (int e = lane; e < K * jb; e += 64)
-                sh_store(cb + e, pubc[e]);
+        // the index last: a reader that sees it still polls the row words
         if (lane == 0)
-            sh_store(cidx + b * P + g, (int64_t)row);
-        if (own) {
-            double *rb = rowk + (size_t)b * K * jb;
-            for (int e = lane; e < K * jb; e += 64)
-                sh_store(rb + e, pubk[e]);
-        }
-        bar_arrive_wave(bar);
+            sh_store(xidx + g * PANEL_NB_MAX + cc, (int64_t)row);
     };
 
-    if (wave == 0) {
-        bool own0;
-        const int row0 = stage(0, own0);
-        emit(0, row0, own0);
-    }
+    if (wave == 0)
+        publish(0);
 
     bool nz_prev = false;
+    Poll pl;  // wave 0's polls; none once an earlier panel has failed
+    pl.dead = __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
     for (int kk = 0; kk < jb; ++kk) {
         const int64_t k = j0 + kk;
         const int b = kk & 1;
         double *pcur = prow + (size_t)b * K * jb;
         const double *pprev = prow + (size_t)(b ^ 1) * K * jb;
         if (wave == 0) {
-            bar_wait_wave(bar, (unsigned)(kk + 1) * (unsigned)P, abort_flag);
-            // ---- global pivot
+            // ---- global pivot: every workgroup's candidate index and key
             double key[K];
             int row = -1;
 #pragma unroll
             for (int w = 0; w < K; ++w)
                 key[w] = 0.0;
             for (int t = lane; t < P; t += 64) {
-                // index and key in one round trip (the key of a workgroup
-                // without a candidate is ignored)
-                const double *cc = cand + ((size_t)(b * P + t) * K) * jb;
+                const int64_t *ip = xidx + t * PANEL_NB_MAX + kk;
+                const double *kp = xrow + ((size_t)t * PANEL_NB_MAX + kk) * KJ + kk;
+                int64_t rr;
                 double kv[K];
+                bool wait;
+                do {
+                    rr = sh_load(ip);
+                    bool ks = false;
 #pragma unroll
-                for (int w = 0; w < K; ++w)
-                    kv[w] = sh_load(cc + w * jb + kk);
-                const int rr = (int)sh_load(cidx + b * P + t);
-                if (rr < 0)
-#pragma unroll
-                    for (int w = 0; w < K; ++w)
-                        kv[w] = 0.0;
-                if (cand_better<K>(kv, rr, key, row)) {
+                    for (int w = 0; w < K; ++w) {
+                        kv[w] = sh_load(kp + w * jb);
+                        ks |= xsent(kv[w]);
+                    }
+                    wait = rr == XSENT || (rr >= 0 && ks);
+                } while (wait && pl.again(abort_flag));
+                const int ri = (rr >= k && rr < n) ? (int)rr : -1;
+                if (cand_better<K>(kv, ri, key, row)) {
 #pragma unroll
                     for (int w = 0; w < K; ++w)
                         key[w] = kv[w];
-                    row = rr;
+                    row = ri;
                 }
             }
-            wave_argmax<K>(key, row);
-            const int64_t p = row;
+            wave_argmax_fast<K>(key, row);
+            // a failed poll can leave no valid row: keep indexing in range
+            const int64_t p = row >= 0 ? row : k;
             const int gw = (int)((p - j0) / R);
-            // the winner's key is the pivot (column kk of a published
-            // candidate is final): its reciprocal, while the row loads
+            // ---- rebuild the pivot row (and the displaced row k for p's
+            //      owner) from their published copies, lane = column: every
+            //      load is issued first, the pivot's reciprocal (its key:
+            //      column kk of a published candidate is final) is formed
+            //      while they are in flight
+            const double *cc = xrow + ((size_t)gw * PANEL_NB_MAX + kk) * KJ;
+            const double *rb = xown + (size_t)kk * KJ;
+            const bool need_o = p != k && p >= gr0 && p < gr0 + nr;
+            const int c = lane;
+            const bool live = c < jb;
+            const bool fin = nz_prev && c > kk && c < jb;
+            double v[K], l[K], vo[K], lo[K];
+#pragma unroll
+            for (int w = 0; w < K; ++w) {
+                v[w] = live ? sh_load(cc + w * jb + c) : 0.0;
+                l[w] = fin ? sh_load(cc + w * jb + kk - 1) : 0.0;
+                vo[w] = (need_o && live) ? sh_load(rb + w * jb + c) : 0.0;
+                lo[w] = (need_o && fin) ? sh_load(rb + w * jb + kk - 1) : 0.0;
+            }
             if (lane == 0 && !is_zero<K>(key)) {
                 double rcp[K];
                 recip<K>(key, rcp);
@@ -300,94 +346,79 @@ __global__ void __launch_bounds__(PANEL_THREADS)
                 for (int w = 0; w < K; ++w)
                     s_rcp[w] = rcp[w];
             }
-            // ---- rebuild the pivot row (and the displaced row k for p's
-            //      owner) from their published copies; lane = column
-            const double *cc = cand + ((size_t)(b * P + gw) * K) * jb;
-            const double *rb = rowk + (size_t)b * K * jb;
-            const bool need_o = p != k && p >= gr0 && p < gr0 + nr;
-            const int c = lane;
-            if (c < jb) {
-                double v[K], o[K];
+            for (;;) {
+                bool any = false;
 #pragma unroll
                 for (int w = 0; w < K; ++w)
-                    v[w] = sh_load(cc + w * jb + c);
-                if (nz_prev && c > kk) {
-                    double l[K], u[K];
+                    any |= xsent(v[w]) | xsent(l[w]) | xsent(vo[w]) | xsent(lo[w]);
+                if (!any || !pl.again(abort_flag))
+                    break;
 #pragma unroll
-                    for (int w = 0; w < K; ++w) {
-                        l[w] = sh_load(cc + w * jb + kk - 1);
-                        u[w] = pprev[w * jb + c];
-                    }
-                    fms<K>(v, l, u, o);
-#pragma unroll
-                    for (int w = 0; w < K; ++w)
-                        v[w] = o[w];
+                for (int w = 0; w < K; ++w) {  // written once: reloading is harmless
+                    v[w] = live ? sh_load(cc + w * jb + c) : 0.0;
+                    l[w] = fin ? sh_load(cc + w * jb + kk - 1) : 0.0;
+                    vo[w] = (need_o && live) ? sh_load(rb + w * jb + c) : 0.0;
+                    lo[w] = (need_o && fin) ? sh_load(rb + w * jb + kk - 1) : 0.0;
                 }
+            }
+            if (fin) {
+                double u[K], o[K];
 #pragma unroll
                 for (int w = 0; w < K; ++w)
-                    pcur[w * jb + c] = v[w];
+                    u[w] = pprev[w * jb + c];
+                fms<K>(v, l, u, o);
+#pragma unroll
+                for (int w = 0; w < K; ++w)
+                    v[w] = o[w];
                 if (need_o) {
+                    fms<K>(vo, lo, u, o);
 #pragma unroll
                     for (int w = 0; w < K; ++w)
-                        v[w] = sh_load(rb + w * jb + c);
-                    if (nz_prev && c > kk) {
-                        double l[K], u[K];
+                        vo[w] = o[w];
+                }
+            }
+            if (live) {
 #pragma unroll
-                        for (int w = 0; w < K; ++w) {
-                            l[w] = sh_load(rb + w * jb + kk - 1);
-                            u[w] = pprev[w * jb + c];
-                        }
-                        fms<K>(v, l, u, o);
-#pragma unroll
-                        for (int w = 0; w < K; ++w)
-                            v[w] = o[w];
-                    }
-#pragma unroll
-                    for (int w = 0; w < K; ++w)
-                        orow[w * jb + c] = v[w];
+                for (int w = 0; w < K; ++w) {
+                    pcur[w * jb + c] = v[w];
+                    if (need_o)
+                        orow[w * jb + c] = vo[w];
                 }
             }
             if (lane == 0)
                 s_p = (int)p;
         } else if (nz_prev) {
             // ---- waves 1..: the previous column's update of columns
-            //      kk+1.. (rows below the previous pivot)
+            //      kk+1.. (rows below the previous pivot), lane = row
             const int kp = kk - 1;
-            const int64_t kprev = j0 + kp;
-            const int ncol = jb - kp - 2;
-            for (int e = tid - 64; e < nr * ncol; e += PANEL_THREADS - 64) {
-                const int r = e % nr, c = kp + 2 + e / nr;
-                if (gr0 + r > kprev) {
-                    double a[K], l[K], u[K], o[K];
+            const int r = lane;
+            if (r < nr && gr0 + r > j0 + kp) {
+                double l[K];
+#pragma unroll
+                for (int w = 0; w < K; ++w)
+                    l[w] = T(w, kp, r);
+                for (int c = kp + 1 + wave; c < jb; c += NW - 1) {
+                    double a[K], u[K], o[K];
 #pragma unroll
                     for (int w = 0; w < K; ++w) {
-                        a[w] = tile[(w * jb + c) * R + r];
-                        l[w] = tile[(w * jb + kp) * R + r];
+                        a[w] = T(w, c, r);
                         u[w] = pprev[w * jb + c];
                     }
                     fms<K>(a, l, u, o);
 #pragma unroll
                     for (int w = 0; w < K; ++w)
-                        tile[(w * jb + c) * R + r] = o[w];
+                        T(w, c, r) = o[w];
                 }
             }
         }
         __syncthreads();
         const int64_t p = s_p;
-        // ---- row interchange k <-> p inside the tiles
-        if (k >= gr0 && k < gr0 + nr) {
-            const int lr = (int)(k - gr0);
-            for (int e = tid; e < K * jb; e += PANEL_THREADS) {
-                const int w = e / jb, c = e % jb;
-                tile[(w * jb + c) * R + lr] = pcur[w * jb + c];
-            }
-        }
-        if (p != k && p >= gr0 && p < gr0 + nr) {
-            const int lr = (int)(p - gr0);
-            for (int e = tid; e < K * jb; e += PANEL_THREADS) {
-                const int w = e / jb, c = e % jb;
-                tile[(w * jb + c) * R + lr] = orow[w * jb + c];
-            }
+        // ---- row interchange k <-> p inside the tiles (wave w: word w)
+        if (wave < K && lane < jb) {
+            if (k >= gr0 && k < gr0 + nr)
+                T(wave, lane, (int)(k - gr0)) = pcur[wave * jb + lane];
+            if (p != k && p >= gr0 && p < gr0 + nr)
+                T(wave, lane, (int)(p - gr0)) = orow[wave * jb + lane];
         }
         if (tid == 0) {
             s_piv[kk] = (int)p;
@@ -402,55 +433,97 @@ __global__ void __launch_bounds__(PANEL_THREADS)
         if (!nz && g == 0 && tid == 0 && *info == 0)
             *info = k + 1;
         __syncthreads();
-        // ---- multipliers l_ik = a_ik * (1/a_kk), rows > k (wave 0, lane = row)
-        if (nz && wave == 0 && lane < nr && gr0 + lane > k) {
-            double rcp[K], a[K], l[K];
-#pragma unroll
-            for (int w = 0; w < K; ++w)
-                rcp[w] = s_rcp[w];
-#pragma unroll
-            for (int w = 0; w < K; ++w)
-                a[w] = tile[(w * jb + kk) * R + lane];
-            mul<K>(a, rcp, l);
-#pragma unroll
-            for (int w = 0; w < K; ++w)
-                tile[(w * jb + kk) * R + lane] = l[w];
-        }
-        __syncthreads();
-        // ---- wave 0: column kk+1 first, then the next candidate, staged
-        int crow = -1;
-        bool cown = false;
-        if (wave == 0 && kk + 1 < jb) {
-            if (nz && lane < nr && gr0 + lane > k) {
-                double a[K], l[K], u[K], o[K];
+        if (wave == 0) {
+            // ---- multipliers l_ik = a_ik * (1/a_kk), rows > k (lane = row)
+            const bool mine = nz && lane < nr && gr0 + lane > k;
+            if (mine) {
+                double rcp[K], a[K], l[K];
 #pragma unroll
                 for (int w = 0; w < K; ++w) {
-                    a[w] = tile[(w * jb + kk + 1) * R + lane];
-                    l[w] = tile[(w * jb + kk) * R + lane];
-                    u[w] = pcur[w * jb + kk + 1];
+                    rcp[w] = s_rcp[w];
+                    a[w] = T(w, kk, lane);
                 }
-                fms<K>(a, l, u, o);
+                mul<K>(a, rcp, l);
 #pragma unroll
                 for (int w = 0; w < K; ++w)
-                    tile[(w * jb + kk + 1) * R + lane] = o[w];
+                    T(w, kk, lane) = l[w];
+                // ---- column kk+1 first, then the next candidate is published
+                if (kk + 1 < jb) {
+                    double a1[K], u[K], o[K];
+#pragma unroll
+                    for (int w = 0; w < K; ++w) {
+                        a1[w] = T(w, kk + 1, lane);
+                        u[w] = pcur[w * jb + kk + 1];
+                    }
+                    fms<K>(a1, l, u, o);
+#pragma unroll
+                    for (int w = 0; w < K; ++w)
+                        T(w, kk + 1, lane) = o[w];
+                }
             }
-            crow = stage(kk + 1, cown);
+            if (kk + 1 < jb)
+                publish(kk + 1);
         }
-        // the staged copies are taken before columns kk+2.. change
+        // waves 1.. may change columns kk+2.. only after the copies are out
         __syncthreads();
-        if (wave == 0 && kk + 1 < jb)
-            emit(kk + 1, crow, cown);
         nz_prev = nz;
     }
-    __syncthreads();
 
     for (int e = tid; e < jb * R; e += PANEL_THREADS) {
         const int r = e % R, c = e / R;
         if (r < nr) {
 #pragma unroll
             for (int w = 0; w < K; ++w)
-                A[w * ldp + (j0 + c) * lda + gr0 + r] = tile[(w * jb + c) * R + r];
+                A[w * ldp + (j0 + c) * lda + gr0 + r] = T(w, c, r);
         }
+    }
+    // split form: slices of the finished rows below the panel block (L21),
+    // SL[(q jb + c) ldsl + i] for row j0 + jb + i; PANEL_THREADS / R threads
+    // per row, each a share of the columns, the row's scale from the
+    // largest leading word over all shares
+    if (ozs > 0) {
+        __shared__ double s_mx[PANEL_THREADS];
+        const int r = tid % R, qt = tid / R, nq = PANEL_THREADS / R;
+        const int per = (jb + nq - 1) / nq;
+        const int cb = qt * per, ce = (cb + per) < jb ? (cb + per) : jb;
+        const int64_t row = gr0 + r;
+        const bool mine = r < nr && row >= j0 + jb;
+        double mx = 0.0;
+        if (mine)
+            for (int c = cb; c < ce; ++c)
+                mx = fmax(mx, fabs(T(0, c, r)));
+        s_mx[tid] = mx;  // tid = qt R + r
+        __syncthreads();
+        if (mine) {
+            for (int t = 0; t < nq; ++t)
+                mx = fmax(mx, s_mx[t * R + r]);
+            const int E = oz_scale(mx);
+            double *out = SL + (row - j0 - jb);
+            for (int c = cb; c < ce; ++c) {
+                double v[K];
+#pragma unroll
+                for (int w = 0; w < K; ++w)
+                    v[w] = T(w, c, r);
+                oz_cut_store<K>(v, E, ozs, out + (int64_t)c * ldsl, (int64_t)jb * ldsl);
+            }
+        }
+    }
+    // the next panel's exchange buffer back to XSENT: this workgroup's
+    // slots (the next panel has no more workgroups than this one) and every
+    // P-th row copy at the pivot position
+    {
+        int64_t *nidx = (int64_t *)xnext;
+        double *nrow = xnext + PANEL_WG_MAX * PANEL_NB_MAX;
+        double *nown = nrow + (size_t)PANEL_WG_MAX * PANEL_NB_MAX * KJ;
+        const double sent = __longlong_as_double((long long)XSENT);
+        if (tid < PANEL_NB_MAX)
+            sh_store(nidx + g * PANEL_NB_MAX + tid, XSENT);
+        double *rb = nrow + (size_t)g * PANEL_NB_MAX * KJ;
+        for (int e = tid; e < PANEL_NB_MAX * KJ; e += PANEL_THREADS)
+            sh_store(rb + e, sent);
+        for (int c = g; c < PANEL_NB_MAX; c += P)
+            for (int e = tid; e < KJ; e += PANEL_THREADS)
+                sh_store(nown + (size_t)c * KJ + e, sent);
     }
     if (g == 0 && tid == 0 && __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
         *info = -1;
@@ -511,10 +584,9 @@ __global__ void __launch_bounds__(PANEL_THREADS)
 template <int K, bool TRSM>
 __global__ void __launch_bounds__(64)
     k_laswp_trsm(double *__restrict__ A, int64_t lda, int64_t ldp, int64_t j0, int jb, int64_t col0,
-                 const int64_t *__restrict__ pairs)
+                 const int64_t *__restrict__ pairs, int ozs, double *__restrict__ SU, int64_t ldsu)
 {
     __shared__ double stage[2 * PANEL_NB_MAX][K];
-    __shared__ double ub[K];
     const int64_t c = col0 + blockIdx.x;
     const int lane = threadIdx.x;
     const int64_t *dst = pairs, *src = pairs + 2 * PANEL_NB_MAX;
@@ -538,40 +610,63 @@ __global__ void __launch_bounds__(64)
     }
     if (!TRSM)
         return;
+    // L11 columns are read PF steps ahead of their use (they do not
+    // depend on the solve), so the chain only waits for the arithmetic
+    constexpr int PF = 8;
+    double lp[PF][K];
+    const double *l11 = A + j0 * lda + j0 + lane;
+#pragma unroll
+    for (int q = 0; q < PF; ++q)
+#pragma unroll
+        for (int w = 0; w < K; ++w)
+            lp[q][w] = (q < jb && lane < jb) ? l11[w * ldp + (int64_t)q * lda] : 0.0;
     __syncthreads();
     __threadfence_block();
-    // forward substitution with the unit lower L11 (rows/cols j0..j0+jb-1)
+    // forward substitution with the unit lower L11 (rows/cols j0..j0+jb-1),
+    // one wave: lane kk's finished value is broadcast by a shuffle
     double u[K];
     if (lane < jb) {
 #pragma unroll
         for (int w = 0; w < K; ++w)
             u[w] = colp[w * ldp + j0 + lane];
     }
-    for (int kk = 0; kk < jb; ++kk) {
-        if (lane == kk) {
+    for (int k0 = 0; k0 < jb; k0 += PF) {
 #pragma unroll
-            for (int w = 0; w < K; ++w)
-                ub[w] = u[w];
-        }
-        __syncthreads();
-        if (lane > kk && lane < jb) {
-            double l[K], uk[K], o[K];
+        for (int q = 0; q < PF; ++q) {
+            const int kk = k0 + q;
+            if (kk < jb) {
+                double uk[K];
 #pragma unroll
-            for (int w = 0; w < K; ++w) {
-                l[w] = A[w * ldp + (j0 + kk) * lda + j0 + lane];
-                uk[w] = ub[w];
+                for (int w = 0; w < K; ++w)
+                    uk[w] = __shfl(u[w], kk, 64);
+                if (lane > kk && lane < jb) {
+                    double o[K];
+                    fms<K>(u, lp[q], uk, o);
+#pragma unroll
+                    for (int w = 0; w < K; ++w)
+                        u[w] = o[w];
+                }
+                if (kk + PF < jb && lane < jb) {
+#pragma unroll
+                    for (int w = 0; w < K; ++w)
+                        lp[q][w] = l11[w * ldp + (int64_t)(kk + PF) * lda];
+                }
             }
-            fms<K>(u, l, uk, o);
-#pragma unroll
-            for (int w = 0; w < K; ++w)
-                u[w] = o[w];
         }
-        __syncthreads();
     }
     if (lane < jb) {
 #pragma unroll
         for (int w = 0; w < K; ++w)
             colp[w * ldp + j0 + lane] = u[w];
+    }
+    // split form: the finished column's slices, SU[(q jb + k) ldsu + blockIdx.x]
+    if (ozs > 0) {
+        double mx = lane < jb ? fabs(u[0]) : 0.0;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1)
+            mx = fmax(mx, __shfl_xor(mx, off, 64));
+        if (lane < jb)
+            oz_cut_store<K>(u, oz_scale(mx), ozs, SU + (int64_t)lane * ldsu + blockIdx.x, (int64_t)jb * ldsu);
     }
 }
 
@@ -689,13 +784,25 @@ struct UpdCfg<4> {
 // ---------------------------------------------------------------------------
 // host driver
 // ---------------------------------------------------------------------------
+static size_t xbuf_words_rt(int K)
+{
+    switch (K) {
+    case 1:
+        return xbuf_words<1>();
+    case 2:
+        return xbuf_words<2>();
+    case 3:
+        return xbuf_words<3>();
+    default:
+        return xbuf_words<4>();
+    }
+}
+
 size_t getrf_scratch_bytes(int K)
 {
-    const size_t cand = 2ull * PANEL_WG_MAX * K * PANEL_NB_MAX * sizeof(double);
-    const size_t cidx = 2ull * PANEL_WG_MAX * sizeof(int64_t);
-    const size_t rowk = 2ull * K * PANEL_NB_MAX * sizeof(double);
+    const size_t xb = 2 * xbuf_words_rt(K) * sizeof(double);   // two exchange buffers
     const size_t pairs = 8ull * PANEL_NB_MAX * sizeof(int64_t);  // two panels' pairs
-    return cand + cidx + rowk + pairs + 4 * 256 + 256;
+    return xb + pairs + 256;
 }
 
 __global__ void k_zero_i64(int64_t *p)
@@ -706,17 +813,26 @@ __global__ void k_zero_i64(int64_t *p)
 
 static size_t panel_lds_bytes(int K, int jb, int R)
 {
-    // tile, two pivot rows, the displaced row, two staged copies
-    return ((size_t)K * jb * R + 5 * (size_t)K * jb) * sizeof(double);
+    // tile (row stride R + 1), two pivot rows, the displaced row
+    return ((size_t)K * jb * (R + 1) + 3 * (size_t)K * jb) * sizeof(double);
 }
 
-// reset the grid-barrier counter and abort flag of one panel launch
-__global__ void k_bar_reset(unsigned *bar, int *abort_flag)
+// start of a factorisation: clear the abort flag, and set words [0, nw) of
+// the first panel's exchange buffer to XSENT
+__global__ void k_xbuf_init(uint64_t *x, int64_t nw, int *abort_flag)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        *bar = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nw; i += stride)
+        x[i] = (uint64_t)XSENT;
+    if (blockIdx.x == 0 && threadIdx.x == 0)
         *abort_flag = 0;
-    }
+}
+
+// end of a factorisation: a failed panel exchange makes info -1
+__global__ void k_abort_check(const int *abort_flag, int64_t *info)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0 && *abort_flag)
+        *info = -1;
 }
 
 // Side stream and two events per device for the look-ahead: the next panel
@@ -746,9 +862,6 @@ static int lookahead_get(LookAhead *&la)
 }
 
 template <int K>
-int oz_split_rows_run(const double *A, int64_t lda, int64_t ldp, int64_t r0, int64_t m, int64_t j0, int kb, int s,
-                      double *SL, int64_t ldsl, hipStream_t st);
-template <int K>
 int oz_split_cols_run(const double *A, int64_t lda, int64_t ldp, int64_t j0, int kb, int64_t c0, int64_t nc, int s,
                       double *SU, int64_t ldsu, hipStream_t st);
 template <int K>
@@ -766,30 +879,26 @@ int getrf_run(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int
         return BNC_OK;
     const int nb = PANEL_NB_MAX;
     char *base = (char *)scr;
-    double *cand = (double *)base;
-    base += 2ull * PANEL_WG_MAX * K * PANEL_NB_MAX * sizeof(double);
-    int64_t *cidx = (int64_t *)base;
-    base += 2ull * PANEL_WG_MAX * sizeof(int64_t);
-    double *rowk = (double *)base;
-    base += 2ull * K * PANEL_NB_MAX * sizeof(double);
+    double *xb[2] = {(double *)base, (double *)base + xbuf_words<K>()};
+    base += 2 * xbuf_words<K>() * sizeof(double);
     int64_t *pairs[2] = {(int64_t *)base, (int64_t *)base + 4 * PANEL_NB_MAX};
     base += 8ull * PANEL_NB_MAX * sizeof(int64_t);
-    unsigned *bar = (unsigned *)base;
-    int *abort_flag = (int *)(base + 64);
+    int *abort_flag = (int *)base;
 
     int dev = 0;
     BNC_HIP(hipGetDevice(&dev));
     int ncu = 0, lds_max = 0;
     BNC_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     BNC_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    const size_t lds_static = 512;
+    const size_t lds_static = 4096;  // bound on the panel kernel's static LDS
     LookAhead *la = nullptr;
     int rc = lookahead_get(la);
     if (rc)
         return rc;
 
     // one panel: rows pj0..n-1, columns pj0..pj0+pjb-1
-    auto panel = [&](int64_t pj0, int pjb, int64_t *pr, hipStream_t st) -> int {
+    // panel number pn (its exchange buffer is xb[pn & 1]; it resets the other)
+    auto panel = [&](int pn, int64_t pj0, int pjb, int64_t *pr, double *psl, hipStream_t st) -> int {
         const int64_t m = n - pj0;
         void *kfn = (void *)k_panel<K>;
         int R = 64;
@@ -808,38 +917,57 @@ int getrf_run(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int
         const int P = (int)ceil_div(m, R);
         if (P > cap)
             return fail_arg(BNC_ERR_UNSUPPORTED, "getrf: panel needs more workgroups than can be co-resident");
-        hipLaunchKernelGGL(k_bar_reset, dim3(1), dim3(64), 0, st, bar, abort_flag);
-        BNC_LAUNCH_CHECK();
+        if (pn == 0) {
+            // slots of workgroups 0..P-1 and the pivot-row copies
+            const int64_t nw = (int64_t)PANEL_WG_MAX * PANEL_NB_MAX + (int64_t)P * PANEL_NB_MAX * K * PANEL_NB_MAX;
+            hipLaunchKernelGGL(k_xbuf_init, dim3(256), dim3(256), 0, st, (uint64_t *)xb[0], nw, abort_flag);
+            BNC_LAUNCH_CHECK();
+            const int64_t own_off = (int64_t)PANEL_WG_MAX * PANEL_NB_MAX * (1 + K * PANEL_NB_MAX);
+            hipLaunchKernelGGL(k_xbuf_init, dim3(16), dim3(256), 0, st, (uint64_t *)(xb[0] + own_off),
+                               (int64_t)PANEL_NB_MAX * K * PANEL_NB_MAX, abort_flag);
+            BNC_LAUNCH_CHECK();
+        }
         // All P workgroups fit on the device at once (checked above); the
         // grid barrier inside the kernel has a bounded spin, so a workgroup
         // that starts late (the other stream's kernels still hold CUs) only
         // delays the panel.
         hipLaunchKernelGGL((k_panel<K>), dim3(P), dim3(PANEL_THREADS), lds, st, A, lda, ldp, n, pj0, pjb, R, ipiv,
-                           info, cand, cidx, rowk, pr, bar, abort_flag);
+                           info, xb[pn & 1], xb[(pn + 1) & 1], pr, abort_flag, oz, psl, n);
         BNC_LAUNCH_CHECK();
         return BNC_OK;
     };
-    auto swaps = [&](int64_t j0, int jb, int64_t c0, int64_t nc, const int64_t *pr, bool trsm) -> int {
+    // split form: SLb[J & 1] holds the sliced rows cn..n-1 of panel J
+    // (written by the panel itself; the next panel, which runs beside this
+    // panel's trailing update, writes the other buffer), SU the sliced
+    // columns cn..n-1 of its U12; all with leading dimension n
+    double *SLb[2] = {oz_buf, oz_buf ? oz_buf + (size_t)OZ_SMAX * PANEL_NB_MAX * n : nullptr};
+    double *SU = oz_buf ? oz_buf + 2 * (size_t)OZ_SMAX * PANEL_NB_MAX * n : nullptr;
+    // row interchanges of columns c0..c0+nc-1; with trsm also U12 = L11^-1 A12
+    // there, and with osu (split form, look-ahead columns) its slices,
+    // column c0 + t at osu[t]
+    auto swaps = [&](int64_t j0, int jb, int64_t c0, int64_t nc, const int64_t *pr, bool trsm,
+                     double *osu) -> int {
         if (nc <= 0)
             return BNC_OK;
+        const int ozs = osu ? oz : 0;
         if (trsm)
             hipLaunchKernelGGL((k_laswp_trsm<K, true>), dim3((unsigned)nc), dim3(64), 0, s, A, lda, ldp, j0, jb, c0,
-                               pr);
+                               pr, ozs, osu, n);
         else
             hipLaunchKernelGGL((k_laswp_trsm<K, false>), dim3((unsigned)nc), dim3(64), 0, s, A, lda, ldp, j0, jb,
-                               c0, pr);
+                               c0, pr, 0, nullptr, n);
         BNC_LAUNCH_CHECK();
         return BNC_OK;
     };
-    // A[r0.., c0..c0+nc) -= L21 (columns j0..j0+jb) * U12
-    // split form: SL holds the sliced rows cn..n-1 of the current panel,
-    // SU the sliced columns cn..n-1 of its U12 (both with leading dimension n)
-    double *SL = oz_buf, *SU = oz_buf ? oz_buf + (size_t)OZ_SMAX * PANEL_NB_MAX * n : nullptr;
-    auto update = [&](int64_t r0, int64_t c0, int64_t m, int64_t nc, int64_t j0, int jb, bool thin) -> int {
+    // A[r0.., c0..c0+nc) -= L21 (columns j0..j0+jb) * U12; split form:
+    // the rows' slices in SL, the columns' slices already in SU (split) or
+    // cut here
+    auto update = [&](int64_t r0, int64_t c0, int64_t m, int64_t nc, int64_t j0, int jb, bool thin,
+                      const double *SL, bool split) -> int {
         if (m <= 0 || nc <= 0)
             return BNC_OK;
         if (oz) {
-            int rc2 = oz_split_cols_run<K>(A, lda, ldp, j0, jb, c0, nc, oz, SU + (c0 - r0), n, s);
+            int rc2 = split ? BNC_OK : oz_split_cols_run<K>(A, lda, ldp, j0, jb, c0, nc, oz, SU + (c0 - r0), n, s);
             if (rc2)
                 return rc2;
             const int ev = UpdateTimer::begin(s);
@@ -866,34 +994,41 @@ int getrf_run(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int
 
     hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(64), 0, s, info);
     BNC_LAUNCH_CHECK();
-    if ((rc = panel(0, (int)(n < nb ? n : nb), pairs[0], s)))
+    if ((rc = panel(0, 0, (int)(n < nb ? n : nb), pairs[0], SLb[0], s)))
         return rc;
     int J = 0;
     for (int64_t j0 = 0; j0 < n; j0 += nb, ++J) {
         const int jb = (int)((n - j0) < nb ? (n - j0) : nb);
         const int64_t *pr = pairs[J & 1];
-        if ((rc = swaps(j0, jb, 0, j0, pr, false)))
-            return rc;
         const int64_t cn = j0 + jb;
-        if (cn >= n)
+        if (cn >= n) {
+            if ((rc = swaps(j0, jb, 0, j0, pr, false, nullptr)))
+                return rc;
             break;
+        }
         const int nbn = (int)((n - cn) < nb ? (n - cn) : nb);
-        if (oz && (rc = oz_split_rows_run<K>(A, lda, ldp, cn, n - cn, j0, jb, oz, SL, n, s)))
-            return rc;
-        // look-ahead: the next panel's columns first
-        if ((rc = swaps(j0, jb, cn, nbn, pr, true)) || (rc = update(cn, cn, n - cn, nbn, j0, jb, true)))
+        double *SL = SLb[J & 1];
+        // look-ahead: the next panel's columns first (interchanges, U12 and,
+        // in the split form, its slices in one kernel; then their update)
+        if ((rc = swaps(j0, jb, cn, nbn, pr, true, oz ? SU : nullptr)) ||
+            (rc = update(cn, cn, n - cn, nbn, j0, jb, true, SL, oz != 0)))
             return rc;
         BNC_HIP(hipEventRecord(la->ready, s));
         BNC_HIP(hipStreamWaitEvent(la->side, la->ready, 0));
-        if ((rc = panel(cn, nbn, pairs[(J + 1) & 1], la->side)))
+        if ((rc = panel(J + 1, cn, nbn, pairs[(J + 1) & 1], SLb[(J + 1) & 1], la->side)))
             return rc;
         BNC_HIP(hipEventRecord(la->done, la->side));
-        // the rest of the trailing matrix, concurrently with that panel
+        // concurrently with that panel: the interchanges left of this panel
+        // and the rest of the trailing matrix
         const int64_t cr = cn + nbn;
-        if ((rc = swaps(j0, jb, cr, n - cr, pr, true)) || (rc = update(cn, cr, n - cn, n - cr, j0, jb, false)))
+        if ((rc = swaps(j0, jb, 0, j0, pr, false, nullptr)) ||
+            (rc = swaps(j0, jb, cr, n - cr, pr, true, nullptr)) ||
+            (rc = update(cn, cr, n - cn, n - cr, j0, jb, false, SL, false)))
             return rc;
         BNC_HIP(hipStreamWaitEvent(s, la->done, 0));
     }
+    hipLaunchKernelGGL(k_abort_check, dim3(1), dim3(64), 0, s, abort_flag, info);
+    BNC_LAUNCH_CHECK();
     return BNC_OK;
 }
 

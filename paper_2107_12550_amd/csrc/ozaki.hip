@@ -26,84 +26,52 @@
 // whose scale is above about 2^-700).
 #include "common.hpp"
 #include "mw.hpp"
+#include "ozsplit.hpp"
 
 namespace bnc {
 
-constexpr int OZ_BETA = 20;
 constexpr int OZ_KB = 8;  // k values staged through LDS per step
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ int oz_scale(double mx)
-{
-    int e = 0;
-    if (mx == 0.0)
-        return 0;
-    (void)frexp(mx, &e);  // mx = f 2^e, f in [1/2, 1): |x| <= mx < 2^e
-    return e;
-}
-
-// Cut the K-word value v (it becomes the remainder) into slices 0..s-1 on
-// the grids 2^(E - (q+1) BETA) and store slice q at out[q * stride].
-template <int K>
-__device__ __forceinline__ void oz_cut_store(double (&v)[K], int E, int s, double *out, int64_t stride)
-{
-    for (int q = 0; q < s; ++q) {
-        const int e = E - (q + 1) * OZ_BETA;
-        double acc = 0.0;
-#pragma unroll
-        for (int t = 0; t < K; ++t) {
-            const double rho = ldexp(rint(ldexp(v[t], -e)), e);
-            v[t] -= rho;
-            acc += rho;
-        }
-        out[q * stride] = acc;
-    }
-}
-
-// Rows r0..r0+m-1 of the panel columns j0..j0+kb-1 -> SL[(q kb + k) ldsl + i].
-template <int K>
-__global__ void __launch_bounds__(64)
-    k_oz_split_rows(const double *__restrict__ A, int64_t lda, int64_t ldp, int64_t r0, int64_t m, int64_t j0,
-                    int kb, int s, double *__restrict__ SL, int64_t ldsl)
-{
-    const int64_t i = (int64_t)blockIdx.x * 64 + threadIdx.x;
-    if (i >= m)
-        return;
-    const double *a = A + j0 * lda + r0 + i;
-    double mx = 0.0;
-    for (int k = 0; k < kb; ++k)
-        mx = fmax(mx, fabs(a[k * lda]));
-    const int E = oz_scale(mx);
-    for (int k = 0; k < kb; ++k) {
-        double v[K];
-#pragma unroll
-        for (int w = 0; w < K; ++w)
-            v[w] = a[w * ldp + k * lda];
-        oz_cut_store<K>(v, E, s, SL + (int64_t)k * ldsl + i, (int64_t)kb * ldsl);
-    }
-}
+// Splitting of U12 columns (the rows of L21 are cut by the panel as it
+// writes them back, the look-ahead columns by their triangular solve): a
+// workgroup of 256 threads takes 64 columns, four threads per column each
+// cutting a quarter of its kb <= 64 entries; the column's scale comes from
+// the maximum over the four quarters.
+constexpr int OZ_SPLIT_V = 64;  // columns per workgroup
+constexpr int OZ_SPLIT_Q = 4;   // threads per column
 
 // Columns c0..c0+nc-1 of the rows j0..j0+kb-1 -> SU[(q kb + k) ldsu + c].
 template <int K>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(OZ_SPLIT_V *OZ_SPLIT_Q)
     k_oz_split_cols(const double *__restrict__ A, int64_t lda, int64_t ldp, int64_t j0, int kb, int64_t c0,
                     int64_t nc, int s, double *__restrict__ SU, int64_t ldsu)
 {
-    const int64_t c = (int64_t)blockIdx.x * 64 + threadIdx.x;
-    if (c >= nc)
-        return;
+    __shared__ double smax[OZ_SPLIT_Q][OZ_SPLIT_V];
+    const int v = threadIdx.x % OZ_SPLIT_V, qt = threadIdx.x / OZ_SPLIT_V;
+    const int64_t c = (int64_t)blockIdx.x * OZ_SPLIT_V + v;
+    const int per = (kb + OZ_SPLIT_Q - 1) / OZ_SPLIT_Q;
+    const int k0 = qt * per, k1 = (k0 + per) < kb ? (k0 + per) : kb;
     const double *a = A + (c0 + c) * lda + j0;
     double mx = 0.0;
-    for (int k = 0; k < kb; ++k)
-        mx = fmax(mx, fabs(a[k]));
+    if (c < nc)
+        for (int k = k0; k < k1; ++k)
+            mx = fmax(mx, fabs(a[k]));
+    smax[qt][v] = mx;
+    __syncthreads();
+    if (c >= nc)
+        return;
+#pragma unroll
+    for (int t = 0; t < OZ_SPLIT_Q; ++t)
+        mx = fmax(mx, smax[t][v]);
     const int F = oz_scale(mx);
-    for (int k = 0; k < kb; ++k) {
-        double v[K];
+    for (int k = k0; k < k1; ++k) {
+        double w4[K];
 #pragma unroll
         for (int w = 0; w < K; ++w)
-            v[w] = a[w * ldp + k];
-        oz_cut_store<K>(v, F, s, SU + (int64_t)k * ldsu + c, (int64_t)kb * ldsu);
+            w4[w] = a[w * ldp + k];
+        oz_cut_store<K>(w4, F, s, SU + (int64_t)k * ldsu + c, (int64_t)kb * ldsu);
     }
 }
 
@@ -217,20 +185,9 @@ __global__ void __launch_bounds__(64 * WM * WN)
 
 size_t oz_slices_bytes(int64_t n)
 {
-    // SL and SU, OZ_SMAX slices of a 64-wide panel, n rows/columns each
-    return 2ull * OZ_SMAX * PANEL_NB_MAX * (size_t)(n > 0 ? n : 1) * sizeof(double);
-}
-
-template <int K>
-int oz_split_rows_run(const double *A, int64_t lda, int64_t ldp, int64_t r0, int64_t m, int64_t j0, int kb, int s,
-                      double *SL, int64_t ldsl, hipStream_t st)
-{
-    if (m <= 0)
-        return BNC_OK;
-    hipLaunchKernelGGL(k_oz_split_rows<K>, dim3((unsigned)ceil_div(m, 64)), dim3(64), 0, st, A, lda, ldp, r0, m, j0,
-                       kb, s, SL, ldsl);
-    BNC_LAUNCH_CHECK();
-    return BNC_OK;
+    // two SL (the current panel's and the next one's) and SU, OZ_SMAX
+    // slices of a 64-wide panel, n rows/columns each
+    return 3ull * OZ_SMAX * PANEL_NB_MAX * (size_t)(n > 0 ? n : 1) * sizeof(double);
 }
 
 template <int K>
@@ -239,8 +196,8 @@ int oz_split_cols_run(const double *A, int64_t lda, int64_t ldp, int64_t j0, int
 {
     if (nc <= 0)
         return BNC_OK;
-    hipLaunchKernelGGL(k_oz_split_cols<K>, dim3((unsigned)ceil_div(nc, 64)), dim3(64), 0, st, A, lda, ldp, j0, kb, c0,
-                       nc, s, SU, ldsu);
+    hipLaunchKernelGGL(k_oz_split_cols<K>, dim3((unsigned)ceil_div(nc, OZ_SPLIT_V)), dim3(OZ_SPLIT_V * OZ_SPLIT_Q), 0,
+                       st, A, lda, ldp, j0, kb, c0, nc, s, SU, ldsu);
     BNC_LAUNCH_CHECK();
     return BNC_OK;
 }
@@ -268,8 +225,9 @@ static int oz_update_s(bool thin, double *A, int64_t lda, int64_t ldp, int64_t r
     // 8 waves of one 16 x 16 block each (32 x 64 outputs per workgroup):
     // 46.7 TFLOP/s of slice products on a 4032^2 x 64 triple-double update
     // with 8 slices, against 24.3 for 4 waves of 32 x 16; the look-ahead
-    // columns use the same shape
-    (void)thin;
+    // columns (64 of them) take 32 x 32 tiles for twice the workgroups
+    if (thin)
+        return oz_update_launch<K, S, 2, 2, 1, 1>(A, lda, ldp, r0, c0, m, nc, kb, SL, ldsl, SU, ldsu, st);
     return oz_update_launch<K, S, 2, 4, 1, 1>(A, lda, ldp, r0, c0, m, nc, kb, SL, ldsl, SU, ldsu, st);
 }
 
@@ -305,8 +263,6 @@ int oz_update_run(int s, bool thin, double *A, int64_t lda, int64_t ldp, int64_t
 }
 
 #define OZ_INST(K)                                                                                                   \
-    template int oz_split_rows_run<K>(const double *, int64_t, int64_t, int64_t, int64_t, int64_t, int, int,        \
-                                      double *, int64_t, hipStream_t);                                              \
     template int oz_split_cols_run<K>(const double *, int64_t, int64_t, int64_t, int, int64_t, int64_t, int,        \
                                       double *, int64_t, hipStream_t);                                              \
     template int oz_update_run<K>(int, bool, double *, int64_t, int64_t, int64_t, int64_t, int64_t, int64_t, int,   \
