@@ -163,14 +163,33 @@ __device__ __forceinline__ double readlane_d(double v, int l)
 // wave_argmax with a fast path: the key order compares |leading word|
 // first, so when exactly one lane holds the largest |leading word| it wins
 // outright; ties on it (or no candidate at all) take the full reduction.
+// DPP lane move of a double (both halves with the same control)
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xF, 0xF, false);
+    const unsigned hi = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// fmax over the wave, in every lane: within each row of 16 lanes by DPP
+// (quad swaps, then half-row and row mirrors), across the four rows through
+// scalar registers
+__device__ __forceinline__ double wave_fmax(double m)
+{
+    m = fmax(m, dpp_d<0xB1>(m));   // quad_perm [1,0,3,2]
+    m = fmax(m, dpp_d<0x4E>(m));   // quad_perm [2,3,0,1]
+    m = fmax(m, dpp_d<0x141>(m));  // row_half_mirror
+    m = fmax(m, dpp_d<0x140>(m));  // row_mirror
+    return fmax(fmax(readlane_d(m, 0), readlane_d(m, 16)), fmax(readlane_d(m, 32), readlane_d(m, 48)));
+}
+
 template <int K>
 __device__ __forceinline__ void wave_argmax_fast(double (&key)[K], int &row)
 {
     const double m = row >= 0 ? fabs(key[0]) : -1.0;
-    double mx = m;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1)
-        mx = fmax(mx, __shfl_xor(mx, off, 64));
+    const double mx = wave_fmax(m);
     const unsigned long long at = __ballot(row >= 0 && m == mx);
     if (__popcll(at) == 1) {
         const int src = __builtin_ctzll(at);
@@ -397,6 +416,7 @@ __global__ void __launch_bounds__(PANEL_THREADS)
 #pragma unroll
                 for (int w = 0; w < K; ++w)
                     l[w] = T(w, kp, r);
+#pragma unroll 2
                 for (int c = kp + 1 + wave; c < jb; c += NW - 1) {
                     double a[K], u[K], o[K];
 #pragma unroll
@@ -835,13 +855,17 @@ __global__ void k_abort_check(const int *abort_flag, int64_t *info)
         *info = -1;
 }
 
-// Side stream and two events per device for the look-ahead: the next panel
-// runs on the side stream while the rest of the trailing update runs on the
-// caller's stream.  Default priority, created once.
+// Side stream and four events per device for the look-ahead: the panels
+// and the look-ahead columns' interchanges and update run in order on the
+// side stream (no cross-stream wait between a panel and the next one when
+// the trailing update keeps up), the rest of each trailing update on the
+// caller's stream.  The big update waits until the look-ahead is through,
+// so that the next panel's workgroups are resident before it fills the
+// device.  Default priority, created once.
 namespace {
 struct LookAhead {
     hipStream_t side = nullptr;
-    hipEvent_t ready = nullptr, done = nullptr;
+    hipEvent_t start = nullptr, panel = nullptr, look = nullptr, rest = nullptr;
 };
 LookAhead g_la[16];
 }  // namespace
@@ -855,8 +879,10 @@ static int lookahead_get(LookAhead *&la)
     la = &g_la[dev];
     if (!la->side) {
         BNC_HIP(hipStreamCreateWithFlags(&la->side, hipStreamNonBlocking));
-        BNC_HIP(hipEventCreateWithFlags(&la->ready, hipEventDisableTiming));
-        BNC_HIP(hipEventCreateWithFlags(&la->done, hipEventDisableTiming));
+        BNC_HIP(hipEventCreateWithFlags(&la->start, hipEventDisableTiming));
+        BNC_HIP(hipEventCreateWithFlags(&la->panel, hipEventDisableTiming));
+        BNC_HIP(hipEventCreateWithFlags(&la->look, hipEventDisableTiming));
+        BNC_HIP(hipEventCreateWithFlags(&la->rest, hipEventDisableTiming));
     }
     return BNC_OK;
 }
@@ -945,16 +971,16 @@ int getrf_run(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int
     // row interchanges of columns c0..c0+nc-1; with trsm also U12 = L11^-1 A12
     // there, and with osu (split form, look-ahead columns) its slices,
     // column c0 + t at osu[t]
-    auto swaps = [&](int64_t j0, int jb, int64_t c0, int64_t nc, const int64_t *pr, bool trsm,
-                     double *osu) -> int {
+    auto swaps = [&](int64_t j0, int jb, int64_t c0, int64_t nc, const int64_t *pr, bool trsm, double *osu,
+                     hipStream_t st) -> int {
         if (nc <= 0)
             return BNC_OK;
         const int ozs = osu ? oz : 0;
         if (trsm)
-            hipLaunchKernelGGL((k_laswp_trsm<K, true>), dim3((unsigned)nc), dim3(64), 0, s, A, lda, ldp, j0, jb, c0,
-                               pr, ozs, osu, n);
+            hipLaunchKernelGGL((k_laswp_trsm<K, true>), dim3((unsigned)nc), dim3(64), 0, st, A, lda, ldp, j0, jb,
+                               c0, pr, ozs, osu, n);
         else
-            hipLaunchKernelGGL((k_laswp_trsm<K, false>), dim3((unsigned)nc), dim3(64), 0, s, A, lda, ldp, j0, jb,
+            hipLaunchKernelGGL((k_laswp_trsm<K, false>), dim3((unsigned)nc), dim3(64), 0, st, A, lda, ldp, j0, jb,
                                c0, pr, 0, nullptr, n);
         BNC_LAUNCH_CHECK();
         return BNC_OK;
@@ -963,69 +989,79 @@ int getrf_run(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int
     // the rows' slices in SL, the columns' slices already in SU (split) or
     // cut here
     auto update = [&](int64_t r0, int64_t c0, int64_t m, int64_t nc, int64_t j0, int jb, bool thin,
-                      const double *SL, bool split) -> int {
+                      const double *SL, bool split, hipStream_t st) -> int {
         if (m <= 0 || nc <= 0)
             return BNC_OK;
         if (oz) {
-            int rc2 = split ? BNC_OK : oz_split_cols_run<K>(A, lda, ldp, j0, jb, c0, nc, oz, SU + (c0 - r0), n, s);
+            int rc2 = split ? BNC_OK : oz_split_cols_run<K>(A, lda, ldp, j0, jb, c0, nc, oz, SU + (c0 - r0), n, st);
             if (rc2)
                 return rc2;
-            const int ev = UpdateTimer::begin(s);
-            rc2 = oz_update_run<K>(oz, thin, A, lda, ldp, r0, c0, m, nc, jb, SL, n, SU + (c0 - r0), n, s);
-            UpdateTimer::end(ev, s, 2.0 * (oz * (oz + 1) / 2) * (double)m * (double)nc * (double)jb);
+            const int ev = UpdateTimer::begin(st);
+            rc2 = oz_update_run<K>(oz, thin, A, lda, ldp, r0, c0, m, nc, jb, SL, n, SU + (c0 - r0), n, st);
+            UpdateTimer::end(ev, st, 2.0 * (oz * (oz + 1) / 2) * (double)m * (double)nc * (double)jb);
             return rc2;
         }
-        const int ev = UpdateTimer::begin(s);
+        const int ev = UpdateTimer::begin(st);
         if (thin) {
             using C = UpdCfgThin<K>;
             dim3 grid((unsigned)ceil_div(m, C::BM), (unsigned)ceil_div(nc, C::BN));
-            hipLaunchKernelGGL((k_update<K, C::BM, C::BN, C::TM, C::TN, C::KB>), grid, dim3(UPD_THREADS), 0, s, A,
+            hipLaunchKernelGGL((k_update<K, C::BM, C::BN, C::TM, C::TN, C::KB>), grid, dim3(UPD_THREADS), 0, st, A,
                                lda, ldp, r0, c0, m, nc, j0, jb);
         } else {
             using C = UpdCfg<K>;
             dim3 grid((unsigned)ceil_div(m, C::BM), (unsigned)ceil_div(nc, C::BN));
-            hipLaunchKernelGGL((k_update<K, C::BM, C::BN, C::TM, C::TN, C::KB>), grid, dim3(UPD_THREADS), 0, s, A,
+            hipLaunchKernelGGL((k_update<K, C::BM, C::BN, C::TM, C::TN, C::KB>), grid, dim3(UPD_THREADS), 0, st, A,
                                lda, ldp, r0, c0, m, nc, j0, jb);
         }
         BNC_LAUNCH_CHECK();
-        UpdateTimer::end(ev, s, (double)m * (double)nc * (double)jb * fms_flops(K));
+        UpdateTimer::end(ev, st, (double)m * (double)nc * (double)jb * fms_flops(K));
         return BNC_OK;
     };
 
     hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(64), 0, s, info);
     BNC_LAUNCH_CHECK();
-    if ((rc = panel(0, 0, (int)(n < nb ? n : nb), pairs[0], SLb[0], s)))
+    hipStream_t side = la->side;
+    BNC_HIP(hipEventRecord(la->start, s));
+    BNC_HIP(hipStreamWaitEvent(side, la->start, 0));
+    if ((rc = panel(0, 0, (int)(n < nb ? n : nb), pairs[0], SLb[0], side)))
         return rc;
+    BNC_HIP(hipEventRecord(la->panel, side));
     int J = 0;
     for (int64_t j0 = 0; j0 < n; j0 += nb, ++J) {
         const int jb = (int)((n - j0) < nb ? (n - j0) : nb);
         const int64_t *pr = pairs[J & 1];
         const int64_t cn = j0 + jb;
+        // the caller's stream continues once panel J is done
+        BNC_HIP(hipStreamWaitEvent(s, la->panel, 0));
         if (cn >= n) {
-            if ((rc = swaps(j0, jb, 0, j0, pr, false, nullptr)))
+            if ((rc = swaps(j0, jb, 0, j0, pr, false, nullptr, s)))
                 return rc;
             break;
         }
         const int nbn = (int)((n - cn) < nb ? (n - cn) : nb);
         double *SL = SLb[J & 1];
-        // look-ahead: the next panel's columns first (interchanges, U12 and,
-        // in the split form, its slices in one kernel; then their update)
-        if ((rc = swaps(j0, jb, cn, nbn, pr, true, oz ? SU : nullptr)) ||
-            (rc = update(cn, cn, n - cn, nbn, j0, jb, true, SL, oz != 0)))
+        // side stream: once the previous trailing update is through, the next
+        // panel's columns (interchanges, U12 and, in the split form, its
+        // slices in one kernel; then their update), then that panel
+        if (J > 0)
+            BNC_HIP(hipStreamWaitEvent(side, la->rest, 0));
+        if ((rc = swaps(j0, jb, cn, nbn, pr, true, oz ? SU : nullptr, side)) ||
+            (rc = update(cn, cn, n - cn, nbn, j0, jb, true, SL, oz != 0, side)))
             return rc;
-        BNC_HIP(hipEventRecord(la->ready, s));
-        BNC_HIP(hipStreamWaitEvent(la->side, la->ready, 0));
-        if ((rc = panel(J + 1, cn, nbn, pairs[(J + 1) & 1], SLb[(J + 1) & 1], la->side)))
+        BNC_HIP(hipEventRecord(la->look, side));
+        if ((rc = panel(J + 1, cn, nbn, pairs[(J + 1) & 1], SLb[(J + 1) & 1], side)))
             return rc;
-        BNC_HIP(hipEventRecord(la->done, la->side));
-        // concurrently with that panel: the interchanges left of this panel
+        BNC_HIP(hipEventRecord(la->panel, side));
+        // caller's stream, concurrently: the interchanges left of this panel
         // and the rest of the trailing matrix
         const int64_t cr = cn + nbn;
-        if ((rc = swaps(j0, jb, 0, j0, pr, false, nullptr)) ||
-            (rc = swaps(j0, jb, cr, n - cr, pr, true, nullptr)) ||
-            (rc = update(cn, cr, n - cn, n - cr, j0, jb, false, SL, false)))
+        if ((rc = swaps(j0, jb, 0, j0, pr, false, nullptr, s)) ||
+            (rc = swaps(j0, jb, cr, n - cr, pr, true, nullptr, s)))
             return rc;
-        BNC_HIP(hipStreamWaitEvent(s, la->done, 0));
+        BNC_HIP(hipStreamWaitEvent(s, la->look, 0));
+        if ((rc = update(cn, cr, n - cn, n - cr, j0, jb, false, SL, false, s)))
+            return rc;
+        BNC_HIP(hipEventRecord(la->rest, s));
     }
     hipLaunchKernelGGL(k_abort_check, dim3(1), dim3(64), 0, s, abort_flag, info);
     BNC_LAUNCH_CHECK();
