@@ -88,15 +88,19 @@ __global__ void k_diag_recip(int64_t n, const double *__restrict__ LU, int64_t l
 // Stage the square block rows/cols [b0, b0+bsz) of one triangle into LDS:
 // blk[(w*TS_BS + c)*TS_BS + r] = word w of entry (b0+r, b0+c).
 // ---- one persistent launch per triangle ---------------------------------
-// Workgroup (one wave) per 64-row block.  A block takes every earlier
-// block's finished values as soon as that block's flag is set (columns in
-// solve order, so each row still sees its updates in the unblocked order),
-// then solves its own diagonal block with wave shuffles, publishes its
-// values through coherent device-scope atomics and sets its flag.  Blocks
-// wait only on blocks that were dispatched before them, and every spin is
-// bounded (on timeout the abort flag releases all waits).
-constexpr int TS_G = 16;  // columns whose factor entries are fetched together
+// Workgroup (one wave) per 64-row block.  Solved values are streamed: the
+// output planes start as XSENT (a signalling NaN that no arithmetic
+// produces) and every value is written once, by its lane, the moment it is
+// final (during the block's own diagonal solve).  A block consumes an
+// earlier block's values TS_G at a time, polling the words themselves, in
+// solve order, so each row still sees its updates in the unblocked order;
+// blocks wait only on blocks that were dispatched before them, and every
+// poll is bounded (on timeout the abort flag releases all waits and the
+// result is garbage).  A right-hand side that holds the XSENT bit pattern
+// can stall a poll in the same way.
+constexpr int TS_G = 8;  // columns fetched and consumed together
 constexpr unsigned TS_SPIN = 1u << 22;
+constexpr int64_t TS_SENT = (int64_t)0xFFF40000DEADBEEFull;
 
 __device__ __forceinline__ void ts_store(double *p, double v)
 {
@@ -106,45 +110,64 @@ __device__ __forceinline__ double ts_load(const double *p)
 {
     return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ bool ts_sent(double v) { return __double_as_longlong(v) == (long long)TS_SENT; }
 
-__device__ __forceinline__ void ts_wait(int *flag, int *abort_flag)
+// Wait until the lanes in `need` of the 64-value block at src (K planes,
+// stride n) are final; lanes that have their value put it in vb[lane].
+// `have` (per lane; set beforehand for lanes past the end of a short block,
+// which then never load) and the returned mask carry over between calls.
+template <int K>
+__device__ __forceinline__ unsigned long long ts_poll(const double *src, int64_t n, unsigned long long need,
+                                                     unsigned long long fin, bool &have, double (&vb)[TS_BS][K],
+                                                     int *abort_flag, unsigned &spins)
 {
-    if (threadIdx.x == 0) {
-        unsigned spins = 0;
-        while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
-            if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-                break;
+    const int lane = threadIdx.x;
+    while ((fin & need) != need) {
+        if (!have) {
+            double q[K];
+            bool ok = true;
+#pragma unroll
+            for (int w = 0; w < K; ++w) {
+                q[w] = ts_load(src + w * n + lane);
+                ok = ok && !ts_sent(q[w]);
+            }
+            if (ok) {
+#pragma unroll
+                for (int w = 0; w < K; ++w)
+                    vb[lane][w] = q[w];
+                have = true;
+            }
+        }
+        fin = __ballot(have);
+        if ((fin & need) != need) {
             __builtin_amdgcn_s_sleep(1);
-            if (++spins > TS_SPIN) {
+            if (++spins > TS_SPIN ||
+                ((spins & 1023u) == 0 && __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
                 __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                break;
+                spins = TS_SPIN;
+                return ~0ull;
             }
         }
     }
-    __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    return fin;
 }
 
-__device__ __forceinline__ void ts_publish_flag(int *flag)
+// both output planes to XSENT, abort flag cleared
+__global__ void k_ts_reset(uint64_t *xs, int64_t nw, int *abort_flag)
 {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    if (threadIdx.x == 0)
-        __hip_atomic_store(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nw; e += stride)
+        xs[e] = (uint64_t)TS_SENT;
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        *abort_flag = 0;
 }
 
-__global__ void k_ts_flags_reset(int *flags, int count)
-{
-    for (int e = threadIdx.x; e < count; e += blockDim.x)
-        flags[e] = 0;
-}
-
-// y <- L^-1 y (unit lower), y already permuted
+// x = L^-1 y (unit lower), y already permuted; x: K planes of stride n
 template <int K>
 __global__ void __launch_bounds__(TS_BS)
-    k_trsv_lower(const double *__restrict__ LU, int64_t lda, int64_t ldp, double *__restrict__ y, int64_t ldy,
-                 int64_t n, int *__restrict__ flags, int *__restrict__ abort_flag)
+    k_trsv_lower(const double *__restrict__ LU, int64_t lda, int64_t ldp, const double *__restrict__ y, int64_t ldy,
+                 int64_t n, double *__restrict__ x, int *__restrict__ abort_flag)
 {
     extern __shared__ double dblk[];  // own diagonal block [w][c][r]
     __shared__ double yb[TS_BS][K];
@@ -162,6 +185,7 @@ __global__ void __launch_bounds__(TS_BS)
 #pragma unroll
     for (int w = 0; w < K; ++w)
         v[w] = act ? y[w * ldy + i] : 0.0;
+    unsigned spins = 0;
     for (int c = 0; c < b; ++c) {  // earlier blocks are full
         const int64_t k0 = (int64_t)c * TS_BS;
         double t[TS_G][K];
@@ -170,12 +194,10 @@ __global__ void __launch_bounds__(TS_BS)
 #pragma unroll
             for (int w = 0; w < K; ++w)
                 t[q][w] = act ? LU[w * ldp + (k0 + q) * lda + i] : 0.0;
-        ts_wait(flags + c, abort_flag);
-#pragma unroll
-        for (int w = 0; w < K; ++w)
-            yb[lane][w] = ts_load(y + w * ldy + k0 + lane);
-        __syncthreads();
+        unsigned long long fin = 0;
+        bool have = false;
         for (int g0 = 0; g0 < TS_BS; g0 += TS_G) {
+            fin = ts_poll<K>(x + k0, n, ((1ull << TS_G) - 1) << g0, fin, have, yb, abort_flag, spins);
             double tn[TS_G][K];
             const bool more = g0 + TS_G < TS_BS;
             if (more)
@@ -202,14 +224,20 @@ __global__ void __launch_bounds__(TS_BS)
                     for (int w = 0; w < K; ++w)
                         t[q][w] = tn[q][w];
         }
-        __syncthreads();
+        __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
+    // own diagonal block: lane kk is final when its turn comes; it
+    // publishes its value before the others use it
     for (int kk = 0; kk < bsz; ++kk) {
         double yk[K];
 #pragma unroll
         for (int w = 0; w < K; ++w)
             yk[w] = __shfl(v[w], kk, 64);
+        if (lane == kk)
+#pragma unroll
+            for (int w = 0; w < K; ++w)
+                ts_store(x + w * n + i, v[w]);
         if (act && lane > kk) {
             double l[K], o[K];
 #pragma unroll
@@ -221,18 +249,15 @@ __global__ void __launch_bounds__(TS_BS)
                 v[w] = o[w];
         }
     }
-    if (act)
-#pragma unroll
-        for (int w = 0; w < K; ++w)
-            ts_store(y + w * ldy + i, v[w]);
-    ts_publish_flag(flags + b);
 }
 
-// y <- U^-1 y with rd = 1/u_kk; workgroup g solves block nblk-1-g
+// y = U^-1 x with rd = 1/u_kk; the values go to xo (streamed, K planes of
+// stride n) and to y; workgroup g solves block nblk-1-g
 template <int K>
 __global__ void __launch_bounds__(TS_BS)
-    k_trsv_upper(const double *__restrict__ LU, int64_t lda, int64_t ldp, const double *__restrict__ rd, double *__restrict__ y,
-                 int64_t ldy, int64_t n, int *__restrict__ flags, int *__restrict__ abort_flag)
+    k_trsv_upper(const double *__restrict__ LU, int64_t lda, int64_t ldp, const double *__restrict__ rd,
+                 const double *__restrict__ x, double *__restrict__ xo, double *__restrict__ y, int64_t ldy, int64_t n,
+                 int *__restrict__ abort_flag)
 {
     extern __shared__ double dblk[];
     __shared__ double xb[TS_BS][K];
@@ -250,24 +275,28 @@ __global__ void __launch_bounds__(TS_BS)
     double v[K], rk[K];
 #pragma unroll
     for (int w = 0; w < K; ++w) {
-        v[w] = act ? y[w * ldy + i] : 0.0;
+        v[w] = act ? x[w * n + i] : 0.0;
         rk[w] = act ? rd[w * n + i] : 0.0;
     }
+    unsigned spins = 0;
     for (int c = nblk - 1; c > b; --c) {
         const int64_t k0 = (int64_t)c * TS_BS;
         const int bc = (int)((n - k0) < TS_BS ? (n - k0) : TS_BS);
+        // columns in decreasing order: position q of the sweep is column
+        // bc-1-q of the block
         double t[TS_G][K];
 #pragma unroll
         for (int q = 0; q < TS_G; ++q)
 #pragma unroll
             for (int w = 0; w < K; ++w)
                 t[q][w] = (act && q < bc) ? LU[w * ldp + (k0 + bc - 1 - q) * lda + i] : 0.0;
-        ts_wait(flags + c, abort_flag);
-#pragma unroll
-        for (int w = 0; w < K; ++w)
-            xb[lane][w] = lane < bc ? ts_load(y + w * ldy + k0 + lane) : 0.0;
-        __syncthreads();
+        unsigned long long fin = 0;
+        bool have = lane >= bc;  // lanes beyond a short last block never load
         for (int g0 = 0; g0 < bc; g0 += TS_G) {
+            // the block's lanes bc-1-g0-q for q < TS_G (those >= 0)
+            const int hi = bc - 1 - g0, lo = (hi - TS_G + 1) > 0 ? (hi - TS_G + 1) : 0;
+            const unsigned long long need = (hi - lo + 1 == 64 ? ~0ull : ((1ull << (hi - lo + 1)) - 1)) << lo;
+            fin = ts_poll<K>(xo + k0, n, need, fin, have, xb, abort_flag, spins);
             double tn[TS_G][K];
             const bool more = g0 + TS_G < bc;
             if (more)
@@ -298,7 +327,7 @@ __global__ void __launch_bounds__(TS_BS)
                     for (int w = 0; w < K; ++w)
                         t[q][w] = tn[q][w];
         }
-        __syncthreads();
+        __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
     for (int kk = bsz - 1; kk >= 0; --kk) {
@@ -306,8 +335,10 @@ __global__ void __launch_bounds__(TS_BS)
             double xk[K];
             mul<K>(v, rk, xk);
 #pragma unroll
-            for (int w = 0; w < K; ++w)
+            for (int w = 0; w < K; ++w) {
                 v[w] = xk[w];
+                ts_store(xo + w * n + i, xk[w]);
+            }
         }
         double xk[K];
 #pragma unroll
@@ -327,8 +358,7 @@ __global__ void __launch_bounds__(TS_BS)
     if (act)
 #pragma unroll
         for (int w = 0; w < K; ++w)
-            ts_store(y + w * ldy + i, v[w]);
-    ts_publish_flag(flags + b);
+            y[w * ldy + i] = v[w];
 }
 
 template <int K>
@@ -358,34 +388,37 @@ int diag_recip_run(int64_t n, const double *LU, int64_t lda, int64_t ldp, double
 }
 
 // Solve in place on y (already permuted), one right-hand side; rd = 1/u_kk.
-// flags: 2 * ceil(n/64) + 1 ints of scratch for the persistent launches.
+// ws: trsv_ws_bytes(n) bytes of scratch (the two streamed planes sets and
+// the abort flag of the persistent launches).
 template <int K>
 int trsv_pair(int64_t n, const double *LU, int64_t lda, int64_t ldp, const double *rd, double *y, int64_t ldy,
-              int *flags, hipStream_t s)
+              void *ws, hipStream_t s)
 {
     if (n == 0)
         return BNC_OK;
     allow_lds<K>();
     const size_t lds = block_lds<K>();
     const int64_t nblk = ceil_div(n, TS_BS);
-    const int nf = (int)(2 * nblk + 1);
-    int *abort_flag = flags + 2 * nblk;
-    hipLaunchKernelGGL(k_ts_flags_reset, dim3(1), dim3(256), 0, s, flags, nf);
+    double *x1 = (double *)ws, *x2 = x1 + (size_t)K * n;
+    int *abort_flag = (int *)(x2 + (size_t)K * n);
+    hipLaunchKernelGGL(k_ts_reset, dim3((unsigned)(ceil_div(2 * K * n, 256) < 64 ? ceil_div(2 * K * n, 256) : 64)),
+                       dim3(256), 0, s, (uint64_t *)x1, (int64_t)(2 * K * n), abort_flag);
     BNC_LAUNCH_CHECK();
-    hipLaunchKernelGGL((k_trsv_lower<K>), dim3((unsigned)nblk), dim3(TS_BS), lds, s, LU, lda, ldp, y, ldy, n, flags,
+    hipLaunchKernelGGL((k_trsv_lower<K>), dim3((unsigned)nblk), dim3(TS_BS), lds, s, LU, lda, ldp, y, ldy, n, x1,
                        abort_flag);
     BNC_LAUNCH_CHECK();
-    hipLaunchKernelGGL((k_trsv_upper<K>), dim3((unsigned)nblk), dim3(TS_BS), lds, s, LU, lda, ldp, rd, y, ldy, n,
-                       flags + nblk, abort_flag);
+    hipLaunchKernelGGL((k_trsv_upper<K>), dim3((unsigned)nblk), dim3(TS_BS), lds, s, LU, lda, ldp, rd, x1, x2, y, ldy,
+                       n, abort_flag);
     BNC_LAUNCH_CHECK();
     return BNC_OK;
 }
 
-size_t trsv_flags_bytes(int64_t n) { return (size_t)(2 * ceil_div(n, TS_BS) + 1) * sizeof(int); }
+// up to four words per value
+size_t trsv_ws_bytes(int64_t n) { return 2 * 4 * (size_t)(n > 0 ? n : 1) * sizeof(double) + 256; }
 
 size_t getrs_scratch_bytes(int K, int64_t n)
 {
-    return (size_t)n * sizeof(int32_t) + 2 * (size_t)K * n * sizeof(double) + trsv_flags_bytes(n) + 1024;
+    return (size_t)n * sizeof(int32_t) + 2 * (size_t)K * n * sizeof(double) + trsv_ws_bytes(n) + 1024;
 }
 
 int ipiv_to_perm(int64_t n, const int64_t *ipiv, int32_t *perm, hipStream_t s)
@@ -400,13 +433,13 @@ int ipiv_to_perm(int64_t n, const int64_t *ipiv, int32_t *perm, hipStream_t s)
 // (K planes, stride n) and y buffer
 template <int K>
 int getrs_perm(int64_t n, const double *LU, int64_t lda, int64_t ldp, const int32_t *perm, const double *rd,
-               const double *b, int64_t ldb, double *y, int64_t ldy, int *flags, hipStream_t s)
+               const double *b, int64_t ldb, double *y, int64_t ldy, void *ws, hipStream_t s)
 {
     if (n == 0)
         return BNC_OK;
     hipLaunchKernelGGL((k_gather<K>), dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, n, perm, b, ldb, y, ldy);
     BNC_LAUNCH_CHECK();
-    return trsv_pair<K>(n, LU, lda, ldp, rd, y, ldy, flags, s);
+    return trsv_pair<K>(n, LU, lda, ldp, rd, y, ldy, ws, s);
 }
 
 template <int K>
@@ -418,7 +451,7 @@ int getrs_run(int64_t n, int64_t nrhs, const double *LU, int64_t lda, int64_t ld
     int32_t *perm = (int32_t *)scr;
     double *y = (double *)((char *)scr + ((n * sizeof(int32_t) + 255) / 256) * 256);
     double *rd = y + (size_t)K * n;
-    int *flags = (int *)(rd + (size_t)K * n);
+    void *ws = (void *)(rd + (size_t)K * n);
     int rc = ipiv_to_perm(n, ipiv, perm, s);
     if (rc)
         return rc;
@@ -426,7 +459,7 @@ int getrs_run(int64_t n, int64_t nrhs, const double *LU, int64_t lda, int64_t ld
         return rc;
     for (int64_t c = 0; c < nrhs; ++c) {
         double *bc = B + c * ldb;
-        rc = getrs_perm<K>(n, LU, lda, ldp, perm, rd, bc, ldpb, y, n, flags, s);
+        rc = getrs_perm<K>(n, LU, lda, ldp, perm, rd, bc, ldpb, y, n, ws, s);
         if (rc)
             return rc;
         hipLaunchKernelGGL((k_copy_vec<K>), dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, n, y, n, bc, ldpb);
@@ -437,7 +470,7 @@ int getrs_run(int64_t n, int64_t nrhs, const double *LU, int64_t lda, int64_t ld
 
 #define INST(K)                                                                                                     \
     template int getrs_perm<K>(int64_t, const double *, int64_t, int64_t, const int32_t *, const double *,          \
-                               const double *, int64_t, double *, int64_t, int *, hipStream_t);                     \
+                               const double *, int64_t, double *, int64_t, void *, hipStream_t);                    \
     template int diag_recip_run<K>(int64_t, const double *, int64_t, int64_t, double *, hipStream_t);               \
     template int getrs_run<K>(int64_t, int64_t, const double *, int64_t, int64_t, const int64_t *, double *,        \
                               int64_t, int64_t, void *, hipStream_t);

@@ -27,8 +27,8 @@ int getrf_run(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int
 size_t oz_slices_bytes(int64_t n);
 template <int K>
 int getrs_perm(int64_t n, const double *LU, int64_t lda, int64_t ldp, const int32_t *perm, const double *rd,
-               const double *b, int64_t ldb, double *y, int64_t ldy, int *flags, hipStream_t s);
-size_t trsv_flags_bytes(int64_t n);
+               const double *b, int64_t ldb, double *y, int64_t ldy, void *ws, hipStream_t s);
+size_t trsv_ws_bytes(int64_t n);
 template <int K>
 int diag_recip_run(int64_t n, const double *LU, int64_t lda, int64_t ldp, double *rd, hipStream_t s);
 int ipiv_to_perm(int64_t n, const int64_t *ipiv, int32_t *perm, hipStream_t s);
@@ -513,7 +513,7 @@ static RefineLayout refine_layout(int64_t n, int K)
     L.scal = take(sizeof(Scal));
     L.getrf = take(getrf_scratch_bytes(K));
     L.oz = take(oz_slices_bytes(n));
-    L.flags = take(trsv_flags_bytes(n));
+    L.flags = take(trsv_ws_bytes(n));
     L.total = off;
     return L;
 }
@@ -561,7 +561,7 @@ int refine_drive(int K0, int64_t n, int aw, const double *A, int64_t lda, int64_
     Scal *sc = (Scal *)(W + L.scal);
     void *gscr = W + L.getrf;
     double *ozb = (double *)(W + L.oz);
-    int *tsflags = (int *)(W + L.flags);
+    void *tsflags = (void *)(W + L.flags);
     const int64_t ldp = n * n;
 
     *res = bnc_refine_result{};
