@@ -230,8 +230,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(systems are independent; see DESIGN.md for how the solver would shard)", file=sys.stderr)
+        print("bench.py measures one GPU only: the solver has no multi-GPU path "
+              "(independent systems would simply be split across GPUs)", file=sys.stderr)
         sys.exit(2)
     if args.mode == "batch":
         return batch_main(args)

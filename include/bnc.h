@@ -66,7 +66,11 @@ extern "C" {
  *   lda   leading dimension (>= max(1, n));  ldp  plane stride (>= lda*n)
  *   ipiv  n int64 (device), pivot sequence as above
  *   info  one int64 (device): 0, or k+1 for the first exactly zero pivot
- *         U(k,k); the factorisation still completes (LAPACK getrf)
+ *         U(k,k); the factorisation still completes (LAPACK getrf).  -1:
+ *         the panel's cross-workgroup exchange timed out (it cannot happen
+ *         on finite input; an entry holding the exchange's sentinel, the
+ *         signalling NaN 0xFFF40000DEADBEEF, can cause it); the factors are
+ *         then invalid
  * Uses library scratch on the current device (allocated on first use).
  */
 int bnc_getrf_d(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int64_t *info, void *stream);
@@ -106,7 +110,9 @@ int bnc_getrf_ozaki(int32_t factor_words, int32_t slices, int64_t n, double *A, 
  *   LU, lda, ldp, ipiv   as returned by bnc_getrf_* with the same K
  *   B     K-plane n x nrhs matrix (leading dimension ldb, plane stride ldpb),
  *         overwritten by X
- * A zero pivot yields Inf/NaN in X; check info first.
+ * A zero pivot yields Inf/NaN in X; check info first.  A right-hand side
+ * holding the signalling NaN 0xFFF40000DEADBEEF can stall the substitutions'
+ * bounded polls (the result is then invalid).
  */
 int bnc_getrs_d(int64_t n, int64_t nrhs, const double *LU, int64_t lda, int64_t ldp, const int64_t *ipiv,
                 double *B, int64_t ldb, int64_t ldpb, void *stream);

@@ -112,6 +112,15 @@ __device__ __forceinline__ double ts_load(const double *p)
 }
 __device__ __forceinline__ bool ts_sent(double v) { return __double_as_longlong(v) == (long long)TS_SENT; }
 
+// lane l's double (l wave-uniform) to every lane, through scalar registers
+__device__ __forceinline__ double ts_bcast(double v, int l)
+{
+    const long long b = __double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // Wait until the lanes in `need` of the 64-value block at src (K planes,
 // stride n) are final; lanes that have their value put it in vb[lane].
 // `have` (per lane; set beforehand for lanes past the end of a short block,
@@ -233,7 +242,7 @@ __global__ void __launch_bounds__(TS_BS)
         double yk[K];
 #pragma unroll
         for (int w = 0; w < K; ++w)
-            yk[w] = __shfl(v[w], kk, 64);
+            yk[w] = ts_bcast(v[w], kk);
         if (lane == kk)
 #pragma unroll
             for (int w = 0; w < K; ++w)
@@ -343,7 +352,7 @@ __global__ void __launch_bounds__(TS_BS)
         double xk[K];
 #pragma unroll
         for (int w = 0; w < K; ++w)
-            xk[w] = __shfl(v[w], kk, 64);
+            xk[w] = ts_bcast(v[w], kk);
         if (act && lane < kk) {
             double u[K], o[K];
 #pragma unroll
