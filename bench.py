@@ -29,7 +29,7 @@ sys.path.insert(0, ROOT)
 METRIC = "refined solves/sec + DD/TD LU GFLOPS-eq at n=4096, QD-accurate, vs plain GPU"
 FP64_PEAK_TFLOPS = 78.6  # MI355X FP64, vector and matrix alike: 256 CUs x 2.4 GHz x 128 flop/clk
 FMS_FLOPS = {1: 2, 2: 27, 3: 75, 4: 158}  # FP64 flops per K-word multiply-subtract (FMA = 2)
-DEFAULT_SLICES = {1: 3, 2: 6, 3: 6, 4: 11}  # split form: measured fastest to QD accuracy (TD: 6)
+DEFAULT_SLICES = {1: 3, 2: 6, 3: 5, 4: 11}  # split form: measured fastest to QD accuracy (TD: 5)
 WORD_NAME = {1: "FP64", 2: "DD", 3: "TD", 4: "QD"}
 
 

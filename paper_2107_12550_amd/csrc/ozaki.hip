@@ -104,21 +104,42 @@ __global__ void __launch_bounds__(64 * WM * WN)
             for (int b = 0; b < FJ; ++b)
                 acc[d][a][b] = d4{0.0, 0.0, 0.0, 0.0};
 
-    for (int kc = 0; kc < kb; kc += OZ_KB) {
-        __syncthreads();
-        for (int t = tid; t < S * OZ_KB * BM; t += NT) {
+    // the next chunk's slices are fetched into registers while the current
+    // one is multiplied out of LDS
+    constexpr int NL = (S * OZ_KB * BM + NT - 1) / NT, NU = (S * OZ_KB * BN + NT - 1) / NT;
+    double lr[NL], ur[NU];
+    auto fetch = [&](int kc) {
+#pragma unroll
+        for (int v = 0; v < NL; ++v) {
+            const int t = tid + v * NT;
             const int i = t % BM, k = (t / BM) % OZ_KB, q = t / (BM * OZ_KB);
             const int64_t row = bi0 + i;
             const int kk = kc + k;
-            Ls[t] = (row < m && kk < kb) ? SL[((int64_t)q * kb + kk) * ldsl + row] : 0.0;
+            lr[v] = (t < S * OZ_KB * BM && row < m && kk < kb) ? SL[((int64_t)q * kb + kk) * ldsl + row] : 0.0;
         }
-        for (int t = tid; t < S * OZ_KB * BN; t += NT) {
+#pragma unroll
+        for (int v = 0; v < NU; ++v) {
+            const int t = tid + v * NT;
             const int j = t % BN, k = (t / BN) % OZ_KB, q = t / (BN * OZ_KB);
             const int64_t col = bj0 + j;
             const int kk = kc + k;
-            Us[t] = (col < nc && kk < kb) ? SU[((int64_t)q * kb + kk) * ldsu + col] : 0.0;
+            ur[v] = (t < S * OZ_KB * BN && col < nc && kk < kb) ? SU[((int64_t)q * kb + kk) * ldsu + col] : 0.0;
         }
+    };
+    fetch(0);
+    for (int kc = 0; kc < kb; kc += OZ_KB) {
         __syncthreads();
+#pragma unroll
+        for (int v = 0; v < NL; ++v)
+            if (tid + v * NT < S * OZ_KB * BM)
+                Ls[tid + v * NT] = lr[v];
+#pragma unroll
+        for (int v = 0; v < NU; ++v)
+            if (tid + v * NT < S * OZ_KB * BN)
+                Us[tid + v * NT] = ur[v];
+        __syncthreads();
+        if (kc + OZ_KB < kb)
+            fetch(kc + OZ_KB);
 #pragma unroll 1
         for (int ks = 0; ks < OZ_KB; ks += 4) {
             const int kr = ks + (lane >> 4);

@@ -149,6 +149,27 @@ __global__ void k_fill_i32(int *p, int64_t n, int v)
         p[i] = v;
 }
 
+// Sum of the S partial digit sums of bin q of row i into partial slot 0
+// (thread per (row, bin); every partial sum is a sum of a subset of the
+// row's digits, so each addition is exact and the order does not matter).
+__global__ void __launch_bounds__(256)
+    k_resid_sum(int64_t n, int S, double *__restrict__ part, const double *__restrict__ rowmax,
+                const double *__restrict__ xmaxp, const ExpBounds *__restrict__ ebp, const double *__restrict__ b,
+                int h)
+{
+    const int64_t i = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
+    const int q = (int)blockIdx.y * 4 + (int)(threadIdx.x >> 6);
+    if (i >= n || q >= RB_NB)
+        return;
+    const RowAnchor an = row_anchor(rowmax[i], *xmaxp, b[i], h, lowest_bit(*ebp));
+    if (!an.any || q >= an.nb)
+        return;
+    double s = 0.0;
+    for (int t = 0; t < S; ++t)
+        s = s + part[((int64_t)t * RB_NB + q) * n + i];
+    part[(int64_t)q * n + i] = s;
+}
+
 __global__ void __launch_bounds__(256)
     k_resid_final(int64_t n, int S, const double *__restrict__ part, const double *__restrict__ rowmax,
                   const double *__restrict__ xmaxp, const ExpBounds *__restrict__ ebp, const double *__restrict__ b,
@@ -371,18 +392,23 @@ static int residual_h(int64_t n, int aw)
     return h;
 }
 
-// workgroup column splits (each split into RES_WAVES wave splits)
+// workgroup column splits (each split into RES_WAVES wave splits): enough
+// waves to hide the deposit chains' latency (about four per SIMD at n = 4096)
+constexpr int RES_SPLITS_MAX = 16;
 static int residual_splits(int64_t n)
 {
-    int64_t S = n / 512;
+    int64_t S = n / 256;
     if (S < 1)
         S = 1;
-    if (S > 4)
-        S = 4;
+    if (S > RES_SPLITS_MAX)
+        S = RES_SPLITS_MAX;
     return (int)S;
 }
 
-size_t residual_scratch_bytes(int64_t n) { return (size_t)4 * RES_WAVES * RB_NB * n * sizeof(double) + 256; }
+size_t residual_scratch_bytes(int64_t n)
+{
+    return (size_t)RES_SPLITS_MAX * RES_WAVES * RB_NB * n * sizeof(double) + 256;
+}
 
 // minimum exponents of the words of a rows x cols (ld) matrix with `words`
 // planes (ldp apart), folded into *out
@@ -426,8 +452,11 @@ int residual_run(int64_t n, int aw, const double *A, int64_t lda, int64_t ldpa, 
         hipLaunchKernelGGL((k_resid_partial<4>), grid, dim3(RES_ROWS * RES_WAVES), 0, s, n, A, lda, ldpa, x, ldx, b,
                            ldb, rowmax, xmax, eb, h, chunk, part, inexact);
     BNC_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_resid_final, dim3(grid1(n)), dim3(256), 0, s, n, S * RES_WAVES, (const double *)part,
-                       rowmax, xmax, eb, b, h, r, ldr, inexact);
+    hipLaunchKernelGGL(k_resid_sum, dim3((unsigned)ceil_div(n, 64), (unsigned)ceil_div(RB_NB, 4)), dim3(256), 0, s, n,
+                       S * RES_WAVES, part, rowmax, xmax, eb, b, h);
+    BNC_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_resid_final, dim3(grid1(n)), dim3(256), 0, s, n, 1, (const double *)part, rowmax, xmax, eb,
+                       b, h, r, ldr, inexact);
     BNC_LAUNCH_CHECK();
     return BNC_OK;
 }
