@@ -227,6 +227,9 @@ def main():
     ap.add_argument("--count", type=int, default=8192, help="batch mode: number of systems")
     ap.add_argument("--slots", type=int, default=0, help="batch mode: persistent workgroups (0 = auto)")
     ap.add_argument("--tune", action="store_true", help="batch mode: tune the launch variants now")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="single mode: first run one plain device copy of this many MiB (the reference "
+                         "kernel that scales hardware byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -248,6 +251,15 @@ def main():
 
     n, K = args.n, args.factor
     oz = args.ozaki if args.ozaki >= 0 else DEFAULT_SLICES[K]
+    if args.calib_copy_mib > 0:
+        words = args.calib_copy_mib * (1 << 20) // 8
+        src = torch.ones(words, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy: {args.calib_copy_mib} MiB read, {args.calib_copy_mib} MiB written")
+        del src, dst
     log(f"[bench] generating randsvd n={n} cond={args.cond:g}")
     Ap, b, exact = synth.problem("randsvd", n, config=2, instance=0, cond=args.cond)
     log(f"[bench] rhs exact in quad-double: {exact}")

@@ -930,9 +930,13 @@ int getrf_run(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int
         int R = 64;
         while (R > 8 && panel_lds_bytes(K, pjb, R) + lds_static > (size_t)lds_max)
             R /= 2;
-        const size_t lds = panel_lds_bytes(K, pjb, R);
-        if (lds + lds_static > (size_t)lds_max)
+        if (panel_lds_bytes(K, pjb, R) + lds_static > (size_t)lds_max)
             return fail_arg(BNC_ERR_UNSUPPORTED, "getrf: panel does not fit in LDS");
+        // split form: the panel asks for all of a CU's LDS, so no update
+        // workgroup shares its CU (the matrix-core update would slow the
+        // latency-bound panel down; the vector update is the bottleneck of
+        // the K-word form, which keeps every CU for it)
+        const size_t lds = oz ? (size_t)lds_max - lds_static : panel_lds_bytes(K, pjb, R);
         if (hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
             (void)hipGetLastError();
         int per_cu = 0;
