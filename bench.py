@@ -29,6 +29,15 @@ sys.path.insert(0, ROOT)
 METRIC = "refined solves/sec + DD/TD LU GFLOPS-eq at n=4096, QD-accurate, vs plain GPU"
 FP64_PEAK_TFLOPS = 78.6  # MI355X FP64, vector and matrix alike: 256 CUs x 2.4 GHz x 128 flop/clk
 FMS_FLOPS = {1: 2, 2: 27, 3: 75, 4: 158}  # FP64 flops per K-word multiply-subtract (FMA = 2)
+# FP64 VALU instructions per K-word multiply-subtract (SQ_INSTS_VALU_{ADD,MUL,FMA}_F64 per
+# launch of the TD update: 63 + 6 + 3 = 72 per multiply-subtract); the add-dominated mix caps
+# the flop fraction near 52%, the issue fraction (instructions against half the flop peak) not
+FMS_INSTS = {1: 1, 2: 26, 3: 72, 4: 152}
+# HBM bytes per trailing-update launch (mean over the launches of one factorisation, both tile
+# shapes) from rocprofv3 FETCH_SIZE / WRITE_SIZE passes, each scaled by what the counter reads
+# on a plain 256 MiB device copy (fetch x2.000, write x1.000): profiles/counters_td_randsvd_n4096.md.
+# Valid for the kernels they were taken on only: (form, factor words, n, slices).
+MEASURED_TRAFFIC = {("ozaki", 3, 4096, 5): 2.203e8, ("plain", 3, 4096, 0): 1.875e8}
 DEFAULT_SLICES = {1: 3, 2: 6, 3: 5, 4: 11}  # split form: measured fastest to QD accuracy (TD: 5)
 WORD_NAME = {1: "FP64", 2: "DD", 3: "TD", 4: "QD"}
 
@@ -313,8 +322,13 @@ def main():
         else:
             roof = {"kernel": f"k_update<{K}> (trailing update, vector FP64)", "bound": "alu",
                     "flops_per_launch": f"{FMS_FLOPS[K]} * m * nc * kb (K-word multiply-subtracts)"}
+        traffic = MEASURED_TRAFFIC.get(("ozaki" if slices else "plain", K, n, slices))
+        if not slices:
+            # FP64 issue fraction: instructions issued against half the flop peak
+            roof["issue_frac"] = achieved * FMS_INSTS[K] / FMS_FLOPS[K] / (FP64_PEAK_TFLOPS / 2)
         roof.update({"achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None, "launches": upd_launches,
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic, "traffic_unit": "bytes per launch",
+                     "launches": upd_launches,
                      "avg_launch_ms": upd_ms / max(upd_launches, 1)})
         return {"ms_per_step": ms, "solves_per_s": 1e3 / ms, "iters": out["iters"], "status": out["status"],
                 "max_rel_err": mre, "getrf_ms": t_getrf * 1e3, "gflops_eq": (2.0 * n ** 3 / 3.0) / t_getrf / 1e9,
