@@ -219,6 +219,88 @@ def selector_main(args):
     print(json.dumps(line), flush=True)
 
 
+def sweep_main(args):
+    """Direct-method sweep without refinement: DD/TD/QD getrf + getrs on randsvd matrices (binary64 entries,
+    b = A * ones exact) at n = 1024 and 2048, cond 1e3, 1e15 and 1e30, with the forward error against the exact
+    solution, the normwise backward error from the exact residual and GFLOPS-eq of the factorisation; then the
+    latency of one small refined solve (uniform n = 128, TD factor, refined to quad-double accuracy)."""
+    import numpy as np
+    import torch
+
+    import paper_2107_12550_amd as P
+    import synth
+
+    def timed(fn, reps=3):
+        best = float("inf")
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        return best
+
+    rows = []
+    for n in (1024, 2048):
+        for cond in (1e3, 1e15, 1e30):
+            Ap, b, exact = synth.problem("randsvd", n, config=1, instance=n, cond=cond)
+            dA = torch.from_numpy(Ap).cuda()
+            db = torch.from_numpy(b).cuda()
+            anorm = float(dA[0].abs().sum(dim=0).max())  # inf-norm of A (rows of A are columns of the plane)
+            bnorm = float(db[0].abs().max())
+            for K in (2, 3, 4):
+                LU0 = torch.zeros((K, n, n), dtype=torch.float64, device="cuda")
+                LU0[0].copy_(dA[0])
+                LU = torch.empty_like(LU0)
+                state = {}
+
+                def fact():
+                    LU.copy_(LU0)
+                    state["ipiv"], state["info"] = P.getrf(K, LU)
+
+                t_f = timed(fact)  # includes the copy of LU0 (a few us)
+                X = torch.empty((K, n), dtype=torch.float64, device="cuda")
+
+                def solve():
+                    X.copy_(db[:K])
+                    P.getrs(K, LU, state["ipiv"], X)
+
+                t_s = timed(solve)
+                xq = torch.zeros((4, n), dtype=torch.float64, device="cuda")
+                xq[:K].copy_(X)
+                err = float(max_rel_err_vs_ones(xq.cpu().numpy())) if exact else None
+                r, _ = P.residual(dA, xq, db)
+                xnorm = float(xq[0].abs().max())
+                berr = float(r[0].abs().max()) / (anorm * xnorm + bnorm)
+                rows.append({"n": n, "cond": cond, "factor": WORD_NAME[K], "getrf_ms": t_f,
+                             "gflops_eq": (2.0 * n ** 3 / 3.0) / (t_f / 1e3) / 1e9, "getrs_ms": t_s,
+                             "info": int(state["info"].item()), "max_rel_err": err, "backward_error": berr})
+                log(f"[sweep] n={n} cond={cond:g} {WORD_NAME[K]}: getrf {t_f:.2f} ms, getrs {t_s:.3f} ms, "
+                    f"err {err:.2e}, berr {berr:.2e}")
+    # one small refined solve, latency bound
+    n = 128
+    Ap, b, exact = synth.problem("uniform", n, config=0, instance=n)
+    dA = torch.from_numpy(Ap).cuda()
+    db = torch.from_numpy(b).cuda()
+    dx = torch.empty((4, n), dtype=torch.float64, device="cuda")
+    work = torch.empty(P.refine_workspace_size(n, 3), dtype=torch.uint8, device="cuda")
+    for _ in range(5):
+        out = P.refine(dA, db, 3, x=dx, work=work)
+    reps = 50
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        out = P.refine(dA, db, 3, x=dx, work=work)
+    torch.cuda.synchronize()
+    us = (time.perf_counter() - t0) * 1e6 / reps
+    small = {"n": n, "kind": "uniform", "factor": "TD", "us_per_solve": us, "iters": out["iters"],
+             "status": out["status"], "max_rel_err": float(max_rel_err_vs_ones(dx.cpu().numpy()))}
+    print(json.dumps({"metric": "direct-method sweep (no refinement) and small refined-solve latency",
+                      "data": "synthetic", "dtype": "f64", "sweep": rows, "small_refined": small}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -232,7 +314,7 @@ def main():
     ap.add_argument("--ozaki", type=int, default=-1,
                     help="single mode: also time the split trailing update with this many slices "
                          "(-1 = the default for the factor precision, 0 = plain form only)")
-    ap.add_argument("--mode", choices=["single", "batch", "selector"], default="single")
+    ap.add_argument("--mode", choices=["single", "batch", "selector", "sweep"], default="single")
     ap.add_argument("--count", type=int, default=8192, help="batch mode: number of systems")
     ap.add_argument("--slots", type=int, default=0, help="batch mode: persistent workgroups (0 = auto)")
     ap.add_argument("--tune", action="store_true", help="batch mode: tune the launch variants now")
@@ -247,6 +329,8 @@ def main():
         sys.exit(2)
     if args.mode == "batch":
         return batch_main(args)
+    if args.mode == "sweep":
+        return sweep_main(args)
     if args.mode == "selector":
         if args.count == 8192:
             args.count = 16384
