@@ -47,7 +47,7 @@ def max_err_vs_ones(x):
     return float(np.max(np.abs((x[0] - 1.0) + x[1] + x[2] + x[3])))
 
 
-@pytest.mark.parametrize("oz", [0, 8])
+@pytest.mark.parametrize("oz", [0, 5, 8])
 def test_fullsize_refine_reaches_quad_double(P, problem, oz):
     Ap, b = problem
     say("refine n", N, "ozaki", oz)
@@ -64,7 +64,7 @@ def permuted_rows(ipiv, n):
     return perm
 
 
-@pytest.mark.parametrize("oz", [0, 8])
+@pytest.mark.parametrize("oz", [0, 5, 8])
 def test_fullsize_factor_backward_error_sampled(P, problem, oz):
     Ap, _ = problem
     K = 3
@@ -106,3 +106,18 @@ def test_fullsize_factor_backward_error_sampled(P, problem, oz):
         if oz:  # dropped slice pairs, relative to the row and column scales
             bound += 64 * (oz + 2) * 2.0 ** (-20 * oz) * (m + 1) * np.abs(Lw[0]).max() * np.abs(Uw[0]).max()
         assert abs(r[0]) <= bound + 1e-300, (i, j, r[0], bound)
+
+
+@pytest.mark.parametrize("oz", [0, 5])
+def test_beyond_one_panel_workgroup_per_64_rows(P, oz):
+    """n = 4160: the first panels have 65 workgroups and the substitutions 65
+    blocks, one more than at n = 4096, with a 64-row tail everywhere; the
+    refined solution must still reach 1e-60."""
+    n = 4160
+    say("generating randsvd n", n)
+    Ap, b, exact = synth.problem("randsvd", n, config=2, instance=1, cond=1e8)
+    assert exact
+    say("refine n", n, "ozaki", oz)
+    out = P.refine(dev(Ap), dev(b), 3, ozaki=oz)
+    assert out["status"] == P.BNC_CONVERGED and out["info"] == 0
+    assert max_err_vs_ones(host(out["x"])) <= 1e-60
