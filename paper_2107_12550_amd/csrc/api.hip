@@ -198,7 +198,7 @@ static int getrf_entry(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *
         return fail_arg(-(6 + argoff), "getrf: info is NULL");
     if (n > 16384)
         return fail_arg(BNC_ERR_UNSUPPORTED, "getrf: n > 16384");
-    void *scr = scratch(SCR_GETRF, getrf_scratch_bytes(K));
+    void *scr = scratch(SCR_GETRF, getrf_scratch_bytes(K, n));
     if (!scr)
         return fail_arg(BNC_ERR_HIP, "getrf: scratch allocation failed");
     double *ozb = nullptr;

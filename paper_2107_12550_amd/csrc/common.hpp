@@ -54,6 +54,6 @@ constexpr int PANEL_WG_MAX = 256;
 
 // Split (Ozaki) trailing update: at most this many slices per operand.
 constexpr int OZ_SMAX = 12;
-size_t getrf_scratch_bytes(int K);
+size_t getrf_scratch_bytes(int K, int64_t n);
 
 }  // namespace bnc

@@ -142,13 +142,20 @@ __device__ __forceinline__ void xpoll(const double *p, int stride, double (&v)[K
     } while (any && pl.again(abort_flag));
 }
 
-// Exchange buffer layout (in doubles): idx [PANEL_WG_MAX][64] (int64),
-// rows [PANEL_WG_MAX][64][K * 64] (word w, column c at w * jb + c), own
-// [64][K * 64].
-template <int K>
-constexpr size_t xbuf_words()
+// Exchange buffer layout (in doubles), for up to ps workgroups: idx
+// [ps][64] (int64), rows [ps][64][K * 64] (word w, column c at w * jb + c),
+// own [64][K * 64].
+static size_t xbuf_words(int K, int ps)
 {
-    return (size_t)PANEL_WG_MAX * PANEL_NB_MAX * (1 + K * PANEL_NB_MAX) + (size_t)PANEL_NB_MAX * K * PANEL_NB_MAX;
+    return (size_t)ps * PANEL_NB_MAX * (1 + K * PANEL_NB_MAX) + (size_t)PANEL_NB_MAX * K * PANEL_NB_MAX;
+}
+
+// workgroup slots of a factorisation of order n: panels have at least 8
+// rows per workgroup
+static int panel_slots(int64_t n)
+{
+    const int64_t s = (n + 7) / 8;
+    return (int)(s < 1 ? 1 : (s > PANEL_WG_MAX ? PANEL_WG_MAX : s));
 }
 
 // Broadcast of lane l's double (l wave-uniform) through scalar registers.
@@ -223,14 +230,14 @@ template <int K>
 __global__ void __launch_bounds__(PANEL_THREADS)
     k_panel(double *__restrict__ A, int64_t lda, int64_t ldp, int64_t n, int64_t j0, int jb, int R,
             int64_t *__restrict__ ipiv, int64_t *__restrict__ info, double *__restrict__ xcur,
-            double *__restrict__ xnext, int64_t *__restrict__ pairs, int *__restrict__ abort_flag, int ozs,
+            double *__restrict__ xnext, int ps, int64_t *__restrict__ pairs, int *__restrict__ abort_flag, int ozs,
             double *__restrict__ SL, int64_t ldsl)
 {
     constexpr int KJ = K * PANEL_NB_MAX;
     constexpr int NW = PANEL_THREADS / 64;
     int64_t *xidx = (int64_t *)xcur;
-    double *xrow = xcur + PANEL_WG_MAX * PANEL_NB_MAX;
-    double *xown = xrow + (size_t)PANEL_WG_MAX * PANEL_NB_MAX * KJ;
+    double *xrow = xcur + (size_t)ps * PANEL_NB_MAX;
+    double *xown = xrow + (size_t)ps * PANEL_NB_MAX * KJ;
     const int RS = R + 1;
     extern __shared__ double smem[];
     double *tile = smem;                        // K*jb*RS
@@ -533,8 +540,8 @@ __global__ void __launch_bounds__(PANEL_THREADS)
     // P-th row copy at the pivot position
     {
         int64_t *nidx = (int64_t *)xnext;
-        double *nrow = xnext + PANEL_WG_MAX * PANEL_NB_MAX;
-        double *nown = nrow + (size_t)PANEL_WG_MAX * PANEL_NB_MAX * KJ;
+        double *nrow = xnext + (size_t)ps * PANEL_NB_MAX;
+        double *nown = nrow + (size_t)ps * PANEL_NB_MAX * KJ;
         const double sent = __longlong_as_double((long long)XSENT);
         if (tid < PANEL_NB_MAX)
             sh_store(nidx + g * PANEL_NB_MAX + tid, XSENT);
@@ -804,24 +811,10 @@ struct UpdCfg<4> {
 // ---------------------------------------------------------------------------
 // host driver
 // ---------------------------------------------------------------------------
-static size_t xbuf_words_rt(int K)
+size_t getrf_scratch_bytes(int K, int64_t n)
 {
-    switch (K) {
-    case 1:
-        return xbuf_words<1>();
-    case 2:
-        return xbuf_words<2>();
-    case 3:
-        return xbuf_words<3>();
-    default:
-        return xbuf_words<4>();
-    }
-}
-
-size_t getrf_scratch_bytes(int K)
-{
-    const size_t xb = 2 * xbuf_words_rt(K) * sizeof(double);   // two exchange buffers
-    const size_t pairs = 8ull * PANEL_NB_MAX * sizeof(int64_t);  // two panels' pairs
+    const size_t xb = 2 * xbuf_words(K, panel_slots(n)) * sizeof(double);  // two exchange buffers
+    const size_t pairs = 8ull * PANEL_NB_MAX * sizeof(int64_t);           // two panels' pairs
     return xb + pairs + 256;
 }
 
@@ -905,8 +898,10 @@ int getrf_run(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int
         return BNC_OK;
     const int nb = PANEL_NB_MAX;
     char *base = (char *)scr;
-    double *xb[2] = {(double *)base, (double *)base + xbuf_words<K>()};
-    base += 2 * xbuf_words<K>() * sizeof(double);
+    const int ps = panel_slots(n);
+    const size_t xw = xbuf_words(K, ps);
+    double *xb[2] = {(double *)base, (double *)base + xw};
+    base += 2 * xw * sizeof(double);
     int64_t *pairs[2] = {(int64_t *)base, (int64_t *)base + 4 * PANEL_NB_MAX};
     base += 8ull * PANEL_NB_MAX * sizeof(int64_t);
     int *abort_flag = (int *)base;
@@ -942,17 +937,17 @@ int getrf_run(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int
         int per_cu = 0;
         BNC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, PANEL_THREADS, lds));
         int64_t cap = (int64_t)per_cu * ncu;
-        if (cap > PANEL_WG_MAX)
-            cap = PANEL_WG_MAX;
+        if (cap > ps)
+            cap = ps;
         const int P = (int)ceil_div(m, R);
         if (P > cap)
             return fail_arg(BNC_ERR_UNSUPPORTED, "getrf: panel needs more workgroups than can be co-resident");
         if (pn == 0) {
             // slots of workgroups 0..P-1 and the pivot-row copies
-            const int64_t nw = (int64_t)PANEL_WG_MAX * PANEL_NB_MAX + (int64_t)P * PANEL_NB_MAX * K * PANEL_NB_MAX;
+            const int64_t nw = (int64_t)ps * PANEL_NB_MAX + (int64_t)P * PANEL_NB_MAX * K * PANEL_NB_MAX;
             hipLaunchKernelGGL(k_xbuf_init, dim3(256), dim3(256), 0, st, (uint64_t *)xb[0], nw, abort_flag);
             BNC_LAUNCH_CHECK();
-            const int64_t own_off = (int64_t)PANEL_WG_MAX * PANEL_NB_MAX * (1 + K * PANEL_NB_MAX);
+            const int64_t own_off = (int64_t)ps * PANEL_NB_MAX * (1 + K * PANEL_NB_MAX);
             hipLaunchKernelGGL(k_xbuf_init, dim3(16), dim3(256), 0, st, (uint64_t *)(xb[0] + own_off),
                                (int64_t)PANEL_NB_MAX * K * PANEL_NB_MAX, abort_flag);
             BNC_LAUNCH_CHECK();
@@ -962,7 +957,7 @@ int getrf_run(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int
         // that starts late (the other stream's kernels still hold CUs) only
         // delays the panel.
         hipLaunchKernelGGL((k_panel<K>), dim3(P), dim3(PANEL_THREADS), lds, st, A, lda, ldp, n, pj0, pjb, R, ipiv,
-                           info, xb[pn & 1], xb[(pn + 1) & 1], pr, abort_flag, oz, psl, n);
+                           info, xb[pn & 1], xb[(pn + 1) & 1], ps, pr, abort_flag, oz, psl, n);
         BNC_LAUNCH_CHECK();
         return BNC_OK;
     };

@@ -519,7 +519,7 @@ struct RefineLayout {
     size_t lu, ipiv, perm, rd, r, v, rowmax, part, red, scal, getrf, oz, flags, total;
 };
 
-size_t getrf_scratch_bytes(int K);
+size_t getrf_scratch_bytes(int K, int64_t n);
 
 static RefineLayout refine_layout(int64_t n, int K)
 {
@@ -540,7 +540,7 @@ static RefineLayout refine_layout(int64_t n, int K)
     L.part = take(residual_scratch_bytes(n));
     L.red = take((size_t)RED_BLOCKS * sizeof(double));
     L.scal = take(sizeof(Scal));
-    L.getrf = take(getrf_scratch_bytes(K));
+    L.getrf = take(getrf_scratch_bytes(K, n));
     L.oz = take(oz_slices_bytes(n));
     L.flags = take(trsv_ws_bytes(n));
     L.total = off;
