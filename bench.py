@@ -245,14 +245,16 @@ def sweep_main(args):
     rows = []
     for n in (1024, 2048):
         for cond in (1e3, 1e15, 1e30):
-            Ap, b, exact = synth.problem("randsvd", n, config=1, instance=n, cond=cond)
+            kind = "randsvd" if cond <= 1e15 else "randsvd_words"
+            Ap, b, exact = synth.problem(kind, n, config=1, instance=n, cond=cond)
             dA = torch.from_numpy(Ap).cuda()
             db = torch.from_numpy(b).cuda()
             anorm = float(dA[0].abs().sum(dim=0).max())  # inf-norm of A (rows of A are columns of the plane)
             bnorm = float(db[0].abs().max())
             for K in (2, 3, 4):
                 LU0 = torch.zeros((K, n, n), dtype=torch.float64, device="cuda")
-                LU0[0].copy_(dA[0])
+                aw = min(K, dA.shape[0])
+                LU0[:aw].copy_(dA[:aw])
                 LU = torch.empty_like(LU0)
                 state = {}
 
@@ -274,7 +276,8 @@ def sweep_main(args):
                 r, _ = P.residual(dA, xq, db)
                 xnorm = float(xq[0].abs().max())
                 berr = float(r[0].abs().max()) / (anorm * xnorm + bnorm)
-                rows.append({"n": n, "cond": cond, "factor": WORD_NAME[K], "getrf_ms": t_f,
+                rows.append({"n": n, "cond": cond, "entries": "binary64" if kind == "randsvd" else "qd-words",
+                             "factor": WORD_NAME[K], "getrf_ms": t_f,
                              "gflops_eq": (2.0 * n ** 3 / 3.0) / (t_f / 1e3) / 1e9, "getrs_ms": t_s,
                              "info": int(state["info"].item()), "max_rel_err": err, "backward_error": berr})
                 log(f"[sweep] n={n} cond={cond:g} {WORD_NAME[K]}: getrf {t_f:.2f} ms, getrs {t_s:.3f} ms, "
@@ -343,7 +346,9 @@ def main():
     import synth
 
     n, K = args.n, args.factor
-    oz = args.ozaki if args.ozaki >= 0 else DEFAULT_SLICES[K]
+    # the split factor's accuracy must beat the condition number: more slices
+    # above 1e15 (measured at 1e25: 5 slices need 11 corrections, 7 need 4)
+    oz = args.ozaki if args.ozaki >= 0 else DEFAULT_SLICES[K] + (2 if args.cond > 1e15 else 0)
     if args.calib_copy_mib > 0:
         words = args.calib_copy_mib * (1 << 20) // 8
         src = torch.ones(words, dtype=torch.float64, device="cuda")
@@ -353,8 +358,11 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] calibration copy: {args.calib_copy_mib} MiB read, {args.calib_copy_mib} MiB written")
         del src, dst
-    log(f"[bench] generating randsvd n={n} cond={args.cond:g}")
-    Ap, b, exact = synth.problem("randsvd", n, config=2, instance=0, cond=args.cond)
+    # above 1e15 binary64 entries cannot carry the condition number: the
+    # matrix is stored in quad-double words instead
+    kind = "randsvd" if args.cond <= 1e15 else "randsvd_words"
+    log(f"[bench] generating {kind} n={n} cond={args.cond:g}")
+    Ap, b, exact = synth.problem(kind, n, config=2, instance=0, cond=args.cond)
     log(f"[bench] rhs exact in quad-double: {exact}")
     dA = torch.from_numpy(Ap).cuda()
     db = torch.from_numpy(b).cuda()
@@ -384,7 +392,8 @@ def main():
         mre = max_rel_err_vs_ones(x) if exact else None
         # factorisation alone (no staging): GFLOPS-eq = (2 n^3 / 3) / t_getrf
         LU0 = torch.zeros((K, n, n), dtype=torch.float64, device="cuda")
-        LU0[0].copy_(dA[0])
+        aw = min(K, dA.shape[0])
+        LU0[:aw].copy_(dA[:aw])  # (the factor itself renormalises the words it is given)
         LU = torch.empty_like(LU0)
         times = []
         for i in range(3):
@@ -439,7 +448,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": f"randsvd n={n} cond={args.cond:g} binary64 entries, b=A*ones exact; "
+            "workload": f"randsvd n={n} cond={args.cond:g} "
+                        f"{'binary64' if kind == 'randsvd' else 'quad-double-word'} entries, b=A*ones exact; "
                         f"{WORD_NAME[K]} LU + quad-double refinement to QD accuracy",
             "n": n, "cond": args.cond, "factor": WORD_NAME[K], "long_precision": "QD (exact residual)",
             "form": best_name,

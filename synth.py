@@ -2,7 +2,8 @@
 
 This module only draws random matrices and forms exact right-hand sides; it
 holds none of the solver's multi-word arithmetic and imports neither the
-product package nor the oracle.
+product package nor the oracle (it may use torch's library GEMM for exact
+products of small-integer slice matrices).
 
 The paper's own test problem (Kouya 2021, Sec. 3: A = R D R^-1 with an
 unpublished random R, x = [0..n-1]) has no published seed, so the workloads
@@ -11,6 +12,9 @@ here are seeded stand-ins with the same structure the solver is exercised on:
   * ``randsvd``: A = U diag(sigma) V^T with U, V Haar-orthogonal (QR of a
     Gaussian matrix with the R-diagonal sign fix, Mezzadri 2007) and sigma
     geometrically spaced from 1 down to 1/cond, rounded to binary64 entries;
+  * ``randsvd_words``: the same product kept to about 150 bits per row in up
+    to four binary64 words per entry, for condition numbers that binary64
+    entries cannot carry (above about 1e15);
   * right-hand side b = A * ones computed exactly and rounded to canonical
     quad-double words, so the exact solution of the stored system is all
     ones whenever the rounding is exact (reported as ``exact``).
@@ -52,6 +56,136 @@ def randsvd(n: int, cond: float, g: np.random.Generator) -> np.ndarray:
     i = np.arange(n, dtype=np.float64)
     sigma = cond ** (-i / max(n - 1, 1))
     return (U * sigma) @ V.T
+
+
+def _split(x):
+    """Veltkamp split: x = hi + lo, hi with at most 26 significant bits."""
+    c = 134217729.0 * x
+    hi = c - (c - x)
+    return hi, x - hi
+
+
+def _prod_exact(a, b):
+    """p + e == a * b exactly (Dekker; numpy has no fused multiply-add)."""
+    p = a * b
+    ah, al = _split(a)
+    bh, bl = _split(b)
+    e = ((ah * bh - p) + ah * bl + al * bh) + al * bl
+    return p, e
+
+
+def _sum_exact(a, b):
+    s = a + b
+    bb = s - a
+    return s, (a - (s - bb)) + (b - bb)
+
+
+def _exact_matmul(n: int):
+    """a @ b.T for slice matrices whose every partial sum is exact in
+    binary64 (so any summation order gives the same result): a library GEMM
+    on the GPU when torch has one and the matrices are large, else numpy."""
+    try:
+        import torch
+        if n >= 512 and torch.cuda.is_available():
+            def mm(a, b):
+                ta = torch.from_numpy(a).cuda()
+                tb = torch.from_numpy(b).cuda()
+                return (ta @ tb.T.contiguous()).cpu().numpy()
+            return mm
+    except ImportError:
+        pass
+    return lambda a, b: a @ b.T
+
+
+def randsvd_words(n: int, cond: float, g: np.random.Generator, bits: int = 150) -> np.ndarray:
+    """U diag(sigma) V^T for matrices too ill-conditioned for binary64 entries
+    (rounding each entry to 53 bits would perturb A by about 1e-16 ||A|| and
+    cap its condition number near 1e17): the same U, V, sigma as ``randsvd``,
+    the product formed to about `bits` bits below each row's scale and kept
+    as up to four binary64 words per entry.  Every entry of row i is a
+    multiple of one power of two 2^G_i (about 2^-`bits` times the row's
+    largest possible entry), so each row sum has few enough bits for the
+    quad-double right-hand side to hold it exactly.  Returns K-plane words
+    (4, n, n).
+
+    Formation: W = U diag(sigma) exactly as two words (Dekker products); W
+    and V are cut into beta-bit slices on per-row grids, every slice product
+    W_p V_q^T is exact in binary64 (2 (beta + 1) + log2 n <= 53 bits), the
+    pairs above the target are summed, each entry rounded to the row grid
+    and accumulated exactly in 50-bit integer limbs, then written back as a
+    non-overlapping binary64 expansion."""
+    U = haar(n, g)
+    V = haar(n, g)
+    i = np.arange(n, dtype=np.float64)
+    sigma = cond ** (-i / max(n - 1, 1))
+    Whi, Wlo = _prod_exact(U, sigma[None, :])
+    lg = max(1, math.ceil(math.log2(max(n, 2))))
+    beta = (53 - lg) // 2 - 1
+    # row scales (|x| < 2^E over the row) of W and V
+    E = np.frexp(np.abs(Whi).max(axis=1))[1].astype(np.int64)
+    F = np.frexp(np.abs(V).max(axis=1))[1].astype(np.int64)
+    nq_w = -(-(bits + lg + 8) // beta)
+    nq_v = -(-(53 + 40) // beta)
+
+    def cut(words, scale, count):
+        rem = [w.copy() for w in words]
+        out = []
+        for q in range(count):
+            e = (scale - (q + 1) * beta)[:, None]
+            sl = np.zeros_like(rem[0])
+            for t in range(len(rem)):
+                rho = np.ldexp(np.rint(np.ldexp(rem[t], -e)), e)
+                rem[t] = rem[t] - rho
+                sl = sl + rho  # exact: both on the grid 2^e, below 2^(beta + 2) units
+            out.append(sl)
+        return out
+
+    Ws = cut([Whi, Wlo], E, nq_w)
+    Vs = cut([V], F, nq_v)
+    mm = _exact_matmul(n)
+    Fmax = int(F.max())
+    G = E + Fmax - bits  # row grid of A
+    LB = 50
+    limbs = [np.zeros((n, n), dtype=np.int64) for _ in range(5)]
+    pmax = (bits + lg + 3) // beta  # pairs p + q above this stay below the grid
+    for p_ in range(nq_w):
+        for q_ in range(nq_v):
+            if p_ + q_ > pmax:
+                continue
+            x = mm(Ws[p_], Vs[q_])  # W_p V_q^T, exact
+            for k in range(4, 0, -1):
+                sc = (G + LB * k)[:, None]
+                t = np.trunc(np.ldexp(x, -sc))
+                limbs[k] += t.astype(np.int64)
+                x = x - np.ldexp(t, sc)
+            limbs[0] += np.rint(np.ldexp(x, -G[:, None])).astype(np.int64)
+
+    def carry():
+        for k in range(4):
+            c = limbs[k] >> LB
+            limbs[k] -= c << LB
+            limbs[k + 1] += c
+
+    carry()  # limbs 0..3 in [0, 2^LB), the sign in limb 4 (0 or -1)
+    neg = limbs[4] < 0
+    for k in range(5):
+        limbs[k] = np.where(neg, -limbs[k], limbs[k])
+    carry()  # magnitudes: limbs 0..3 in [0, 2^LB), limb 4 zero
+    if np.any(limbs[4] != 0):
+        raise RuntimeError("randsvd_words: entry beyond the limb range")
+    sgn = np.where(neg, -1.0, 1.0)
+    terms = [sgn * np.ldexp(limbs[k].astype(np.float64), (G + LB * k)[:, None]) for k in range(4)]
+    # disjoint 50-bit ranges of one sign, most significant last: exact sums
+    # carried from the bottom up put the value's leading 53 bits in the top
+    # word and pass what is left down; repeated on the remainder words this
+    # gives a four-word expansion with each word below half an ulp of the
+    # one before (every step an exact two-sum, so the value is unchanged)
+    for top in range(3, 0, -1):
+        for _ in range(2):
+            for k in range(top):
+                terms[k + 1], terms[k] = _sum_exact(terms[k + 1], terms[k])
+    W4 = np.stack([terms[3], terms[2], terms[1], terms[0]])
+    return np.ascontiguousarray(W4.transpose(0, 2, 1))
 
 
 def planes(A: np.ndarray) -> np.ndarray:
@@ -126,14 +260,16 @@ def batch(count: int, n_lo: int, n_hi: int, lc_lo: float, lc_hi: float, config: 
 
 
 def problem(kind: str, n: int, config: int, instance: int = 0, cond: float = 1e3):
-    """(A planes (1, n, n), b (4, n), exact flag) for a seeded workload."""
+    """(A planes (aw, n, n), b (4, n), exact flag) for a seeded workload;
+    ``randsvd_words`` gives quad-double-word entries (aw = 4)."""
     g = rng(config, instance)
     if kind == "uniform":
-        A = uniform(n, g)
+        Ap = planes(uniform(n, g))
     elif kind == "randsvd":
-        A = randsvd(n, cond, g)
+        Ap = planes(randsvd(n, cond, g))
+    elif kind == "randsvd_words":
+        Ap = randsvd_words(n, cond, g)
     else:
         raise ValueError(kind)
-    Ap = planes(A)
     b, exact = rhs_ones(Ap)
     return Ap, b, exact
