@@ -111,21 +111,24 @@ __device__ __forceinline__ void deposit(double t, const double (&sig)[NBMAX], do
 }
 
 // ---- exact signed integer in 32-bit limbs (carry-save in int64) ------------
-constexpr int BL = 46;  // 1472 bits >= 34*39 + 53 + headroom
-
+// Limbs for the integer of NB bins: digits below 2^53 units of their bin, the
+// top bin's unit at bit W (NB - 1), plus carry and sign headroom.
+template <int NB>
 struct Big {
-    int64_t l[BL];
+    static constexpr int L = (NB * RB_W + 53 + 64 + 31) / 32;
+    int64_t l[L];
 };
 
 // add v * 2^pos, v signed with |v| < 2^63, pos >= 0
-__device__ __forceinline__ void big_add(Big &B, int64_t v, int pos)
+template <int NB>
+__device__ __forceinline__ void big_add(Big<NB> &B, int64_t v, int pos)
 {
     const int L = pos >> 5, sh = pos & 31;
     const uint64_t lo = (uint64_t)(v & 0xffffffffLL);
     const int64_t hi = v >> 32;  // arithmetic: v = lo + hi * 2^32
     const uint64_t los = lo << sh;
 #pragma unroll
-    for (int q = 0; q < BL; ++q) {
+    for (int q = 0; q < Big<NB>::L; ++q) {
         if (q == L)
             B.l[q] += (int64_t)(los & 0xffffffffULL);
         if (q == L + 1)
@@ -133,23 +136,35 @@ __device__ __forceinline__ void big_add(Big &B, int64_t v, int pos)
     }
 }
 
-__device__ __forceinline__ void big_norm(Big &B)
+template <int NB>
+__device__ __forceinline__ void big_norm(Big<NB> &B)
 {
 #pragma unroll
-    for (int q = 0; q < BL - 1; ++q) {
+    for (int q = 0; q < Big<NB>::L - 1; ++q) {
         const int64_t c = B.l[q] >> 32;
         B.l[q] -= c * ((int64_t)1 << 32);
         B.l[q + 1] += c;
     }
 }
 
-// Round |B| (B normalised) to nearest binary64 mantissa: returns mant (0 if
-// B == 0) and the bit position of its least significant bit.
-__device__ __forceinline__ uint64_t big_round(const Big &M, int &lsb)
+template <int NB>
+__device__ __forceinline__ void big_neg(Big<NB> &B)
 {
+#pragma unroll
+    for (int q = 0; q < Big<NB>::L; ++q)
+        B.l[q] = -B.l[q];
+}
+
+// Round |B| (B normalised, non-negative) to nearest binary64 mantissa:
+// returns mant (0 if B == 0) and the bit position of its least significant
+// bit.
+template <int NB>
+__device__ __forceinline__ uint64_t big_round(const Big<NB> &M, int &lsb)
+{
+    constexpr int BLN = Big<NB>::L;
     int hl = -1;
 #pragma unroll
-    for (int q = BL - 1; q >= 0; --q)
+    for (int q = BLN - 1; q >= 0; --q)
         if (hl < 0 && M.l[q] != 0)
             hl = q;
     if (hl < 0) {
@@ -159,7 +174,7 @@ __device__ __forceinline__ uint64_t big_round(const Big &M, int &lsb)
     uint64_t l2 = 0, l1 = 0, l0 = 0;  // limbs hl, hl-1, hl-2
     bool below = false;               // any bit in limbs < hl-2
 #pragma unroll
-    for (int q = 0; q < BL; ++q) {
+    for (int q = 0; q < BLN; ++q) {
         const uint64_t v = (uint64_t)M.l[q];
         if (q == hl)
             l2 = v;
@@ -192,7 +207,8 @@ __device__ __forceinline__ uint64_t big_round(const Big &M, int &lsb)
 
 // Canonical quad-double of the exact sum held in bins[0..nb) (bin q holds a
 // multiple of 2^(e0 - W q)); returns true if a word fell outside the binary64
-// normal range.
+// normal range.  The integer is kept as its magnitude while a word is rounded
+// off it (negated in place), so one limb array suffices.
 template <int NBMAX>
 __device__ __forceinline__ bool bins_to_qd(const double (&bins)[NBMAX], int nb, int e0, double (&out)[4])
 {
@@ -200,9 +216,9 @@ __device__ __forceinline__ bool bins_to_qd(const double (&bins)[NBMAX], int nb, 
 #pragma unroll
     for (int w = 0; w < 4; ++w)
         out[w] = 0.0;
-    Big B;
+    Big<NBMAX> B;
 #pragma unroll
-    for (int q = 0; q < BL; ++q)
+    for (int q = 0; q < Big<NBMAX>::L; ++q)
         B.l[q] = 0;
     const int elow = e0 - RB_W * (nb - 1);  // exponent of the integer's unit
 #pragma unroll
@@ -215,16 +231,13 @@ __device__ __forceinline__ bool bins_to_qd(const double (&bins)[NBMAX], int nb, 
     }
     for (int w = 0; w < 4; ++w) {
         big_norm(B);
-        const bool neg = B.l[BL - 1] < 0;
-        Big M = B;
+        const bool neg = B.l[Big<NBMAX>::L - 1] < 0;
         if (neg) {
-#pragma unroll
-            for (int q = 0; q < BL; ++q)
-                M.l[q] = -M.l[q];
-            big_norm(M);
+            big_neg(B);
+            big_norm(B);
         }
         int lsb;
-        const uint64_t mant = big_round(M, lsb);
+        const uint64_t mant = big_round(B, lsb);
         if (mant == 0)
             break;
         const int e = lsb + elow;
@@ -232,13 +245,14 @@ __device__ __forceinline__ bool bins_to_qd(const double (&bins)[NBMAX], int nb, 
             bad = true;
         const double v = ldexp((double)mant, e);
         out[w] = neg ? -v : v;
-        // B -= value: subtract mant * 2^lsb (lsb may be negative only when the
-        // integer is below 2^53, then mant's low bits are zero)
-        const int64_t sm = neg ? -(int64_t)mant : (int64_t)mant;
+        // |value| -= mant * 2^lsb (lsb may be negative only when the integer
+        // is below 2^53, then mant's low bits are zero), then back to the sign
         if (lsb >= 0)
-            big_add(B, -sm, lsb);
+            big_add(B, -(int64_t)mant, lsb);
         else
-            big_add(B, -(sm >> (-lsb)), 0);
+            big_add(B, -((int64_t)mant >> (-lsb)), 0);
+        if (neg)
+            big_neg(B);
     }
     return bad;
 }
