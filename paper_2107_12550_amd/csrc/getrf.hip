@@ -4,17 +4,22 @@
 // Per panel of nb columns starting at column j0:
 //   1. k_panel: one cooperative launch factors rows j0..n-1 of the panel.
 //      Each workgroup keeps R <= 64 panel rows in LDS.  Per column: every
-//      workgroup publishes its best candidate row, one grid barrier, every
+//      workgroup publishes its best candidate row into an exchange slot and
+//      reads everyone else's (polling the words themselves), every
 //      workgroup picks the same global pivot, swaps rows in LDS, scales the
 //      column by the pivot reciprocal and updates its rows; the next
-//      column is updated and published first so that the barrier overlaps
-//      the rest of the update.  Workgroup 0 then turns the nb swaps into
-//      (dst, src) row pairs.
+//      column is updated and published first, so the exchange overlaps the
+//      rest of the update.  Workgroup 0 then turns the nb swaps into
+//      (dst, src) row pairs.  In the split form the panel also cuts its
+//      finished L21 rows into slices.
 //   2. k_laswp_trsm: the same row pairs applied to every column outside the
 //      panel; right of the panel it also solves U12 = L11^-1 A12 (one wave
-//      per column, lanes = panel rows, one broadcast per pivot row).
+//      per column, lanes = panel rows, one broadcast per pivot row) and, for
+//      the look-ahead columns of the split form, cuts them into slices.
 //   3. k_update: A22 <- A22 - L21 U12, LDS tiles, one K-word multiply-subtract
-//      per (i, j, k) in increasing k.
+//      per (i, j, k) in increasing k (or the split form, ozaki.hip).
+// The next panel's columns are updated first and that panel runs on a side
+// stream while the rest of the trailing update proceeds (look-ahead).
 // Every matrix entry sees exactly the operations of the unblocked algorithm
 // in the same order (row moves commute with the updates, each entry is
 // updated in increasing k), so the factors equal the unblocked ones bit for
