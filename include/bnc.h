@@ -71,7 +71,10 @@ extern "C" {
  *         on finite input; an entry holding the exchange's sentinel, the
  *         signalling NaN 0xFFF40000DEADBEEF, can cause it); the factors are
  *         then invalid
- * Uses library scratch on the current device (allocated on first use).
+ * Uses library scratch on the current device (allocated on first use) and
+ * the library's look-ahead stream and events of that device: calls that use
+ * them (getrf, getrs, and the factorisations inside bnc_refine) must not run
+ * concurrently on one device, from several host threads or streams.
  */
 int bnc_getrf_d(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int64_t *info, void *stream);
 int bnc_getrf_dd(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int64_t *info, void *stream);
