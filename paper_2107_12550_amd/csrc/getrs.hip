@@ -339,6 +339,10 @@ __global__ void __launch_bounds__(TS_BS)
         __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
+    // the loads of v and rd are complete here; waiting for them explicitly
+    // keeps the compiler from placing a full vector-memory wait at the head
+    // of the loop below, where it would also wait for each published store
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
     for (int kk = bsz - 1; kk >= 0; --kk) {
         if (lane == kk) {
             double xk[K];
