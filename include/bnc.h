@@ -113,6 +113,7 @@ int bnc_getrf_ozaki(int32_t factor_words, int32_t slices, int64_t n, double *A, 
  *   LU, lda, ldp, ipiv   as returned by bnc_getrf_* with the same K
  *   B     K-plane n x nrhs matrix (leading dimension ldb, plane stride ldpb),
  *         overwritten by X
+ * An ipiv entry outside [k, n) is taken as no interchange.
  * A zero pivot yields Inf/NaN in X; check info first.  A right-hand side
  * holding the signalling NaN 0xFFF40000DEADBEEF can stall the substitutions'
  * bounded polls (the result is then invalid).

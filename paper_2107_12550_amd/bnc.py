@@ -158,6 +158,8 @@ def getrs(K: int, LU: torch.Tensor, ipiv: torch.Tensor, B: torch.Tensor) -> torc
     f = getattr(_lib, f"bnc_getrs_{_SUFFIX[K]}")
     if not (B.is_cuda and B.dtype == torch.float64 and B.is_contiguous()):
         raise BncError("B: expected a contiguous float64 CUDA tensor")
+    if not (ipiv.is_cuda and ipiv.dtype == torch.int64 and ipiv.is_contiguous() and ipiv.numel() >= n):
+        raise BncError("ipiv: expected a contiguous int64 CUDA tensor of n entries")
     _check(f(n, nrhs, _dev(LU, "LU", 3), n, n * n, ctypes.c_void_p(ipiv.data_ptr()), ctypes.c_void_p(B.data_ptr()),
              n, n * nrhs, _stream()), "getrs")
     return B

@@ -1057,13 +1057,17 @@ int getrf_run(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int
             return rc;
         BNC_HIP(hipEventRecord(la->panel, side));
         // caller's stream, concurrently: the interchanges left of this panel
-        // and the rest of the trailing matrix
+        // and the rest of the trailing matrix; in the split form the rest
+        // columns are sliced before the wait for the look-ahead columns (the
+        // slices of the two column ranges are disjoint)
         const int64_t cr = cn + nbn;
         if ((rc = swaps(j0, jb, 0, j0, pr, false, nullptr, s)) ||
             (rc = swaps(j0, jb, cr, n - cr, pr, true, nullptr, s)))
             return rc;
+        if (oz && cr < n && (rc = oz_split_cols_run<K>(A, lda, ldp, j0, jb, cr, n - cr, oz, SU + nbn, n, s)))
+            return rc;
         BNC_HIP(hipStreamWaitEvent(s, la->look, 0));
-        if ((rc = update(cn, cr, n - cn, n - cr, j0, jb, false, SL, false, s)))
+        if ((rc = update(cn, cr, n - cn, n - cr, j0, jb, false, SL, oz != 0, s)))
             return rc;
         BNC_HIP(hipEventRecord(la->rest, s));
     }

@@ -16,29 +16,48 @@ namespace bnc {
 constexpr int TS_BS = 64;  // block rows; equals the workgroup size
 
 // perm[i] = original index of the row that ends at position i after the
-// swaps k = 0..n-1 (one thread walks the sequence in LDS).
+// swaps k = 0..n-1.  Each thread follows one original row through the whole
+// sequence (the swap k moves the row at position k to ipiv[k] and the row
+// at ipiv[k] to k), then writes its index at its final position.  The
+// pivots pass through LDS in chunks, read four at a time one group ahead of
+// their use.  An entry outside [k, n) is taken as no interchange, so the
+// result is always a permutation of 0..n-1 and every write stays in perm.
+constexpr int PERM_CHUNK = 4096;
 __global__ void __launch_bounds__(256) k_ipiv_to_perm(int64_t n, const int64_t *__restrict__ ipiv,
                                                       int32_t *__restrict__ perm)
 {
-    extern __shared__ int32_t sp[];
-    int32_t *p = sp;          // n
-    int32_t *iv = sp + n;     // n
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-        p[i] = (int32_t)i;
-        iv[i] = (int32_t)ipiv[i];
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int64_t k = 0; k < n; ++k) {
-            const int32_t q = iv[k];
-            const int32_t t = p[k];
-            p[k] = p[q];
-            p[q] = t;
+    __shared__ int4 sp4[PERM_CHUNK / 4];
+    int32_t *sp = (int32_t *)sp4;
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t pos = (int32_t)(r < n ? r : 0);
+    for (int64_t c0 = 0; c0 < n; c0 += PERM_CHUNK) {
+        const int len = (int)((n - c0) < PERM_CHUNK ? (n - c0) : PERM_CHUNK);
+        __syncthreads();
+        for (int e = threadIdx.x; e < PERM_CHUNK; e += blockDim.x) {
+            const int64_t k = c0 + e;
+            int32_t p = (int32_t)k;  // padding past n: no interchange
+            if (e < len) {
+                const int64_t q = ipiv[k];
+                if (q >= k && q < n)
+                    p = (int32_t)q;
+            }
+            sp[e] = p;
+        }
+        __syncthreads();
+        const int ng = (len + 3) / 4;
+        int4 cur = sp4[0];
+        for (int g = 0; g < ng; ++g) {
+            const int4 nxt = sp4[g + 1 < ng ? g + 1 : g];
+            const int32_t k = (int32_t)c0 + 4 * g;
+            pos = pos == k ? cur.x : (pos == cur.x ? k : pos);
+            pos = pos == k + 1 ? cur.y : (pos == cur.y ? k + 1 : pos);
+            pos = pos == k + 2 ? cur.z : (pos == cur.z ? k + 2 : pos);
+            pos = pos == k + 3 ? cur.w : (pos == cur.w ? k + 3 : pos);
+            cur = nxt;
         }
     }
-    __syncthreads();
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x)
-        perm[i] = p[i];
+    if (r < n)
+        perm[pos] = (int32_t)r;
 }
 
 template <int K>
@@ -436,8 +455,9 @@ size_t getrs_scratch_bytes(int K, int64_t n)
 
 int ipiv_to_perm(int64_t n, const int64_t *ipiv, int32_t *perm, hipStream_t s)
 {
-    const size_t lds = 2 * (size_t)n * sizeof(int32_t);
-    hipLaunchKernelGGL(k_ipiv_to_perm, dim3(1), dim3(256), lds, s, n, ipiv, perm);
+    if (n == 0)
+        return BNC_OK;
+    hipLaunchKernelGGL(k_ipiv_to_perm, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, n, ipiv, perm);
     BNC_LAUNCH_CHECK();
     return BNC_OK;
 }

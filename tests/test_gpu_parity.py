@@ -76,6 +76,38 @@ def test_getrf_getrs_bitexact(P, K, n):
     np.testing.assert_array_equal(host(dB), X)
 
 
+@pytest.mark.parametrize("K,n", [(2, 300), (3, 257), (1, 64)])
+def test_getrs_any_swap_sequence_bitexact(P, K, n):
+    """Substitutions with a pivot sequence that no factorisation produced
+    (random targets, repeats, no-op swaps) follow the oracle bit for bit;
+    entries outside [k, n) act as no interchange."""
+    import torch
+    g = np.random.default_rng(4400 + n)
+    Ap, b, _ = synth.problem("uniform", n, config=0, instance=300 + n)
+    LU, _, info = O.getrf(K, O.stage(K, Ap))
+    assert info == 0
+    ipiv = np.array([g.integers(k, n) for k in range(n)], dtype=np.int64)
+    ipiv[::7] = np.arange(n)[::7]
+    ipiv[n // 2:n // 2 + 5] = n - 1
+    bf = O.round_words(K, b)
+    say("getrs any ipiv K", K, "n", n)
+    dLU, dx = dev(LU), dev(bf)
+    P.getrs(K, dLU, torch.from_numpy(ipiv).cuda(), dx)
+    np.testing.assert_array_equal(host(dx), O.getrs(K, LU, ipiv, bf))
+    bad = ipiv.copy()
+    idx = np.arange(3, n, 11)
+    bad[idx] = np.where(idx % 2 == 0, -1, n + 5)
+    bad[5] = 2
+    noop = ipiv.copy()
+    noop[idx] = idx
+    noop[5] = 5
+    dy, dz = dev(bf), dev(bf)
+    P.getrs(K, dLU, torch.from_numpy(bad).cuda(), dy)
+    P.getrs(K, dLU, torch.from_numpy(noop).cuda(), dz)
+    np.testing.assert_array_equal(host(dy), host(dz))
+    np.testing.assert_array_equal(host(dz), O.getrs(K, LU, noop, bf))
+
+
 @pytest.mark.parametrize("K", [1, 3])
 def test_getrf_randsvd_illconditioned_bitexact(P, K):
     n = 160
