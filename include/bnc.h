@@ -87,12 +87,14 @@ int bnc_getrf_qd(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, 
  * Numer. Algorithms 59 (2012), run on the FP64 matrix cores).  After each
  * 64-wide panel (pivoting, multipliers and U12 exactly as bnc_getrf_*),
  * every row of L21 and column of U12 is cut into `slices` binary64 slices of
- * 20 bits on a power-of-two grid fixed by its largest leading word; for each
- * d < slices the products of slice pairs (p, d - p) are summed exactly in
- * binary64, and a_ij <- (((a_ij - acc_0) - acc_1) ...) - acc_{slices-1} in
- * K-word addition.  Pairs with p + q >= slices are dropped, so the factor
- * carries about 20 * slices bits relative to each row/column scale (8 slices
- * suit triple-double, 11 quad-double); bnc_refine recovers full accuracy.
+ * bnc_oz_beta(K, slices) bits on a power-of-two grid fixed by its largest
+ * leading word; for each d < slices the products of slice pairs (p, d - p)
+ * are summed exactly in binary64, and a_ij <- (((a_ij - acc_0) - acc_1) ...)
+ * - acc_{slices-1} in K-word addition.  Pairs with p + q >= slices are
+ * dropped, so the factor carries about beta * slices bits relative to each
+ * row/column scale (5 slices of 22 bits match double-double, 5-6 of 21
+ * come near triple-double, 11 of 20 quad-double); bnc_refine recovers full
+ * accuracy.
  * Deterministic, and independent of tiling (every group sum is exact while
  * the row and column scales stay above about 2^-700).
  *   factor_words  K in 1..4;  slices  1..12
@@ -102,6 +104,17 @@ int bnc_getrf_qd(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, 
  */
 int bnc_getrf_ozaki(int32_t factor_words, int32_t slices, int64_t n, double *A, int64_t lda, int64_t ldp,
                     int64_t *ipiv, int64_t *info, void *stream);
+
+/*
+ * Slice width of the split form: the widest slice (at most 26 bits) for
+ * which every group sum of a depth-64 update of K-word values cut into
+ * `slices` slices stays below 2^53 steps of its grid, hence exact.  Slice q
+ * is below (2^beta + K/2) steps for q = 0 and (K 2^(beta-1) + K/2) for
+ * q > 0, and group d adds 64 (d + 1) products.  Host function, no GPU use.
+ *   factor_words  K in 1..4;  slices  1..12
+ * Returns beta, or -1 for arguments out of range.
+ */
+int bnc_oz_beta(int32_t factor_words, int32_t slices);
 
 /*
  * Solve A X = B with the factors of bnc_getrf_* (Kouya 2021, Sec. 2:

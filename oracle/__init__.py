@@ -67,6 +67,8 @@ def lib() -> ctypes.CDLL:
         L.orc_oz_slices.argtypes = [ctypes.c_int, ctypes.c_int, I64, P, ctypes.c_int32, P, P]
         L.orc_oz_scale.argtypes = [I64, P]
         L.orc_oz_scale.restype = ctypes.c_int32
+        L.orc_oz_beta.argtypes = [ctypes.c_int, ctypes.c_int]
+        L.orc_oz_beta.restype = ctypes.c_int
         L.orc_oz_update.argtypes = [ctypes.c_int, ctypes.c_int, I64, I64, I64, P, I64, I64, P, I64, I64,
                                     P, I64, I64, P]
         L.orc_oz_update.restype = ctypes.c_int
@@ -182,9 +184,18 @@ def getrf(K: int, A: np.ndarray):
 # trailing update by error-free splitting (Ozaki scheme; not in the paper)
 # --------------------------------------------------------------------------
 
-OZ_BETA = 20   # bits per slice
 OZ_SMAX = 16   # most slices
 OZ_KBMAX = 64  # widest panel for which the group sums stay exact
+
+
+def oz_beta(K: int, s: int) -> int:
+    """Bits per slice for K-word values cut into s slices: the widest slice
+    (at most 26 bits) for which every group sum of a depth-64 update stays
+    below 2^53 units of its grid, so that it is exact."""
+    b = int(lib().orc_oz_beta(K, s))
+    if b < 0:
+        raise ValueError("oz_beta: K or s out of range")
+    return b
 
 
 def oz_scale(x0) -> int:
@@ -195,7 +206,8 @@ def oz_scale(x0) -> int:
 
 def oz_slices(K: int, s: int, x, E: int):
     """Cut m K-word values x (shape (K, m)) into s slices on the grids
-    2^(E - (q+1) OZ_BETA); returns (slices (s, m), remainders (K, m))."""
+    2^(E - (q+1) beta), beta = oz_beta(K, s); returns (slices (s, m),
+    remainders (K, m))."""
     x = _c(x)
     m = x.shape[1]
     sl = np.empty((s, m))

@@ -460,7 +460,7 @@ void orc_getrs(int K, int64_t n, int64_t nrhs, const double *LU, int64_t lda, in
  * Not in the paper: an alternative form of the blocked LU's trailing update
  * A22 <- A22 - L21 U12 after Ozaki, Ogita, Oishi and Rump (Numer.
  * Algorithms 59, 2012).  Each row of L21 and each column of U12 is cut into
- * s binary64 slices of OZ_BETA bits on a power-of-two grid fixed by the
+ * s binary64 slices of beta bits on a power-of-two grid fixed by the
  * row's (column's) largest leading word, so that every slice product and
  * every sum of them below is exact in binary64.  For each diagonal
  * d = p + q (p, q slice indices of the row and column operands) the group
@@ -471,18 +471,46 @@ void orc_getrs(int K, int64_t n, int64_t nrhs, const double *LU, int64_t lda, in
  * - acc_{s-1} in K-word arithmetic, in that order.
  *
  * Exactness: with a row scale E (|x| < 2^E for every entry x of the row),
- * slice q lies on the grid g_q = 2^(E - (q+1) OZ_BETA).  Slice q is the sum
+ * slice q lies on the grid g_q = 2^(E - (q+1) beta).  Slice q is the sum
  * over the words of the remaining value of each word rounded to the nearest
- * multiple of g_q (ties to even), so |slice_0| <= (2^OZ_BETA + K/2) g_0 and
- * |slice_q| <= (K 2^(OZ_BETA-1) + K/2) g_q for q >= 1, below
- * (2^(OZ_BETA+1) + 2) g_q for K <= 4.  A group sum has at most
- * kb (d+1) <= 64 * 16 terms, each below (2^21 + 2)^2 units of the common
- * grid, i.e. below 2^53 units in total: exact as long as the grids stay in
- * the normal binary64 range.
+ * multiple of g_q (ties to even), so |slice_0| <= (2^beta + K/2) g_0 and
+ * |slice_q| <= (K 2^(beta-1) + K/2) g_q for q >= 1.  All products of one
+ * group d share the grid g_p g_(d-p), and the group has kb (d+1) of them,
+ * kb <= 64.  The slice width beta therefore depends on K and s: it is the
+ * largest width (at most 26) for which the bound on every group sum,
+ * 64 * sum_p |slice_p| |slice_(d-p)| over d < s, stays below 2^53 units of
+ * the group's grid; then every product and every partial sum is an exact
+ * binary64 number as long as the grids stay in the normal range.  For
+ * s = 16 and K >= 3 this gives 20 bits; a double-double factor with 5
+ * slices gets 22 (110 bits, more than the factor's 106).
  */
-#define OZ_BETA 20
 #define OZ_SMAX 16
 #define OZ_KBMAX 64
+
+static int oz_beta(int K, int s)
+{
+    for (int beta = 26; beta > 1; --beta) {
+        /* bounds in half units of the grid, so that they are integers */
+        unsigned __int128 b[OZ_SMAX];
+        for (int q = 0; q < s; ++q)
+            b[q] = q == 0 ? ((unsigned __int128)1 << (beta + 1)) + (unsigned)K
+                          : (unsigned __int128)K * ((unsigned __int128)1 << beta) + (unsigned)K;
+        int ok = 1;
+        for (int d = 0; d < s && ok; ++d) {
+            unsigned __int128 g = 0;
+            for (int p = 0; p <= d; ++p)
+                g += b[p] * b[d - p];
+            /* OZ_KBMAX * g / 4 < 2^53 */
+            ok = OZ_KBMAX * g < ((unsigned __int128)1 << 55);
+        }
+        if (ok)
+            return beta;
+    }
+    return 1;
+}
+
+int orc_oz_beta(int K, int s) { return (K < 1 || K > KMAX || s < 1 || s > OZ_SMAX) ? -1 : oz_beta(K, s); }
+
 
 /* Row/column scale: smallest E with |x_0| < 2^E for every leading word
  * x_0 of the m entries (stride inc); 0 when all are zero. */
@@ -495,11 +523,12 @@ static int oz_scale(const double *x0, int64_t m, int64_t inc)
 }
 
 /* Cut one K-word value v (consumed: it becomes the remainder) into s
- * slices on the grids 2^(E - (q+1) OZ_BETA). */
+ * slices on the grids 2^(E - (q+1) beta), beta = oz_beta(K, s). */
 static void oz_cut(int K, int s, int E, double *v, double *sl)
 {
+    const int beta = oz_beta(K, s);
     for (int q = 0; q < s; ++q) {
-        int e = E - (q + 1) * OZ_BETA;
+        int e = E - (q + 1) * beta;
         double acc = 0.0;
         for (int t = 0; t < K; ++t) {
             double rho = ldexp(nearbyint(ldexp(v[t], -e)), e);

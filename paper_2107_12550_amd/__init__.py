@@ -29,6 +29,7 @@ from .bnc import (  # noqa: F401
     lib,
     lib_path,
     mw_apply,
+    oz_beta,
     profile_enable,
     profile_read,
     refine,

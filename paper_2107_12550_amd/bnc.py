@@ -65,6 +65,8 @@ def _load() -> ctypes.CDLL:
         g.restype = ctypes.c_int
     L.bnc_getrf_ozaki.argtypes = [I32, I32, I64, VP, I64, I64, VP, VP, VP]
     L.bnc_getrf_ozaki.restype = ctypes.c_int
+    L.bnc_oz_beta.argtypes = [I32, I32]
+    L.bnc_oz_beta.restype = ctypes.c_int
     L.bnc_features_workspace_size.argtypes = [I32]
     L.bnc_features_workspace_size.restype = ctypes.c_size_t
     L.bnc_features_default_slots.restype = I32
@@ -163,6 +165,15 @@ def getrs(K: int, LU: torch.Tensor, ipiv: torch.Tensor, B: torch.Tensor) -> torc
     _check(f(n, nrhs, _dev(LU, "LU", 3), n, n * n, ctypes.c_void_p(ipiv.data_ptr()), ctypes.c_void_p(B.data_ptr()),
              n, n * nrhs, _stream()), "getrs")
     return B
+
+
+def oz_beta(K: int, slices: int) -> int:
+    """Bits per slice of the split form for K-word values cut into `slices`
+    slices (host query)."""
+    b = int(_lib.bnc_oz_beta(K, slices))
+    if b < 0:
+        raise BncError("oz_beta: K or slices out of range")
+    return b
 
 
 def refine_workspace_size(n: int, K: int) -> int:

@@ -11,6 +11,7 @@
 
 #include "common.hpp"
 #include "mw.hpp"
+#include "ozsplit.hpp"
 
 namespace bnc {
 
@@ -257,6 +258,13 @@ int bnc_getrf_td(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, 
 int bnc_getrf_qd(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int64_t *info, void *stream)
 {
     return getrf_entry<4>(n, A, lda, ldp, ipiv, info, stream);
+}
+
+int bnc_oz_beta(int32_t factor_words, int32_t slices)
+{
+    if (factor_words < 1 || factor_words > 4 || slices < 1 || slices > OZ_SMAX)
+        return -1;
+    return oz_beta(factor_words, slices);
 }
 
 int bnc_getrf_ozaki(int32_t factor_words, int32_t slices, int64_t n, double *A, int64_t lda, int64_t ldp,

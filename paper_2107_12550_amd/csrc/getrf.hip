@@ -530,13 +530,14 @@ __global__ void __launch_bounds__(PANEL_THREADS)
             for (int t = 0; t < nq; ++t)
                 mx = fmax(mx, s_mx[t * R + r]);
             const int E = oz_scale(mx);
+            const int beta = oz_beta(K, ozs);
             double *out = SL + (row - j0 - jb);
             for (int c = cb; c < ce; ++c) {
                 double v[K];
 #pragma unroll
                 for (int w = 0; w < K; ++w)
                     v[w] = T(w, c, r);
-                oz_cut_store<K>(v, E, ozs, out + (int64_t)c * ldsl, (int64_t)jb * ldsl);
+                oz_cut_store<K>(v, E, ozs, beta, out + (int64_t)c * ldsl, (int64_t)jb * ldsl);
             }
         }
     }
@@ -698,7 +699,8 @@ __global__ void __launch_bounds__(64)
         for (int off = 32; off > 0; off >>= 1)
             mx = fmax(mx, __shfl_xor(mx, off, 64));
         if (lane < jb)
-            oz_cut_store<K>(u, oz_scale(mx), ozs, SU + (int64_t)lane * ldsu + blockIdx.x, (int64_t)jb * ldsu);
+            oz_cut_store<K>(u, oz_scale(mx), ozs, oz_beta(K, ozs), SU + (int64_t)lane * ldsu + blockIdx.x,
+                            (int64_t)jb * ldsu);
     }
 }
 

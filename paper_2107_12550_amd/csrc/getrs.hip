@@ -256,9 +256,14 @@ __global__ void __launch_bounds__(TS_BS)
     }
     __syncthreads();
     // own diagonal block: lane kk is final when its turn comes; it
-    // publishes its value before the others use it
+    // publishes its value before the others use it.  The block's next
+    // column is read from LDS one step ahead (all 64 columns are there).
+    double l[K];
+#pragma unroll
+    for (int w = 0; w < K; ++w)
+        l[w] = dblk[(w * TS_BS) * TS_BS + lane];
     for (int kk = 0; kk < bsz; ++kk) {
-        double yk[K];
+        double yk[K], ln[K];
 #pragma unroll
         for (int w = 0; w < K; ++w)
             yk[w] = ts_bcast(v[w], kk);
@@ -266,16 +271,20 @@ __global__ void __launch_bounds__(TS_BS)
 #pragma unroll
             for (int w = 0; w < K; ++w)
                 ts_store(x + w * n + i, v[w]);
-        if (act && lane > kk) {
-            double l[K], o[K];
+        const int kn = kk + 1 < TS_BS ? kk + 1 : kk;
 #pragma unroll
-            for (int w = 0; w < K; ++w)
-                l[w] = dblk[(w * TS_BS + kk) * TS_BS + lane];
+        for (int w = 0; w < K; ++w)
+            ln[w] = dblk[(w * TS_BS + kn) * TS_BS + lane];
+        if (act && lane > kk) {
+            double o[K];
             fms<K>(v, l, yk, o);
 #pragma unroll
             for (int w = 0; w < K; ++w)
                 v[w] = o[w];
         }
+#pragma unroll
+        for (int w = 0; w < K; ++w)
+            l[w] = ln[w];
     }
 }
 
@@ -362,6 +371,12 @@ __global__ void __launch_bounds__(TS_BS)
     // keeps the compiler from placing a full vector-memory wait at the head
     // of the loop below, where it would also wait for each published store
     __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    // own diagonal block in decreasing order; the next column is read
+    // from LDS one step ahead
+    double u[K];
+#pragma unroll
+    for (int w = 0; w < K; ++w)
+        u[w] = dblk[(w * TS_BS + (bsz > 0 ? bsz - 1 : 0)) * TS_BS + lane];
     for (int kk = bsz - 1; kk >= 0; --kk) {
         if (lane == kk) {
             double xk[K];
@@ -372,20 +387,24 @@ __global__ void __launch_bounds__(TS_BS)
                 ts_store(xo + w * n + i, xk[w]);
             }
         }
-        double xk[K];
+        double xk[K], un[K];
 #pragma unroll
         for (int w = 0; w < K; ++w)
             xk[w] = ts_bcast(v[w], kk);
-        if (act && lane < kk) {
-            double u[K], o[K];
+        const int kn = kk > 0 ? kk - 1 : 0;
 #pragma unroll
-            for (int w = 0; w < K; ++w)
-                u[w] = dblk[(w * TS_BS + kk) * TS_BS + lane];
+        for (int w = 0; w < K; ++w)
+            un[w] = dblk[(w * TS_BS + kn) * TS_BS + lane];
+        if (act && lane < kk) {
+            double o[K];
             fms<K>(v, u, xk, o);
 #pragma unroll
             for (int w = 0; w < K; ++w)
                 v[w] = o[w];
         }
+#pragma unroll
+        for (int w = 0; w < K; ++w)
+            u[w] = un[w];
     }
     if (act)
 #pragma unroll

@@ -66,12 +66,13 @@ __global__ void __launch_bounds__(OZ_SPLIT_V *OZ_SPLIT_Q)
     for (int t = 0; t < OZ_SPLIT_Q; ++t)
         mx = fmax(mx, smax[t][v]);
     const int F = oz_scale(mx);
+    const int beta = oz_beta(K, s);
     for (int k = k0; k < k1; ++k) {
         double w4[K];
 #pragma unroll
         for (int w = 0; w < K; ++w)
             w4[w] = a[w * ldp + k];
-        oz_cut_store<K>(w4, F, s, SU + (int64_t)k * ldsu + c, (int64_t)kb * ldsu);
+        oz_cut_store<K>(w4, F, s, beta, SU + (int64_t)k * ldsu + c, (int64_t)kb * ldsu);
     }
 }
 

@@ -57,6 +57,19 @@ def test_ozaki_rejects_bad_slices_before_touching_the_device():
     assert L.bnc_getrf_ozaki(3, 8, -1, None, 4, 16, None, None, None) == -3
 
 
+def test_slice_width_agrees_with_the_oracle():
+    """The library's slice width (its own closed form) equals the oracle's
+    (every group summed out) for every factor length and slice count."""
+    import oracle as O
+    import paper_2107_12550_amd as P
+    for K in (1, 2, 3, 4):
+        for s in range(1, 13):
+            assert P.oz_beta(K, s) == O.oz_beta(K, s), (K, s)
+    assert P.lib().bnc_oz_beta(2, 0) == -1
+    assert P.lib().bnc_oz_beta(5, 4) == -1
+    assert P.lib().bnc_oz_beta(2, 13) == -1
+
+
 def test_struct_layouts_match_the_header(tmp_path):
     """The binding's ctypes structs have the C layout of include/bnc.h
     (sizes and field offsets as gcc lays them out)."""

@@ -23,16 +23,40 @@ import synth
 from helpers import rand_words
 from oracle import exact as X
 
-BETA = O.OZ_BETA
-
-
 def F(v):
     return Fraction(float(v))
 
 
-def slice_bound(K, q):
+def slice_bound(K, q, beta):
     """|slice_q| / grid_q <= this (see the scheme's exactness argument)."""
-    return Fraction(2) ** BETA + Fraction(K, 2) if q == 0 else K * Fraction(2) ** (BETA - 1) + Fraction(K, 2)
+    return Fraction(2) ** beta + Fraction(K, 2) if q == 0 else K * Fraction(2) ** (beta - 1) + Fraction(K, 2)
+
+
+def group_bound(K, s, beta, kb=64):
+    """Largest possible |acc_d| over d < s, in units of the group's grid."""
+    b = [slice_bound(K, q, beta) for q in range(s)]
+    return max(kb * sum(b[p] * b[d - p] for p in range(d + 1)) for d in range(s))
+
+
+@pytest.mark.parametrize("K", [1, 2, 3, 4])
+def test_slice_width_is_the_widest_exact_one(K):
+    """beta(K, s) keeps every group sum of a depth-64 update below 2^53
+    grid units and one more bit would not; the widths the forms use: 22 for
+    a double-double factor with 5 slices (110 bits, above its 106), 21 for
+    triple-double with 5, 20 for quad-double with 11 and for 16 slices of
+    triple- or quad-double."""
+    for s in range(1, O.OZ_SMAX + 1):
+        beta = O.oz_beta(K, s)
+        assert group_bound(K, s, beta) < Fraction(2) ** 53
+        assert beta == 26 or group_bound(K, s, beta + 1) >= Fraction(2) ** 53
+        if s > 1:
+            assert beta <= O.oz_beta(K, s - 1)
+    assert O.oz_beta(2, 5) == 22 and O.oz_beta(3, 5) == 21 and O.oz_beta(4, 11) == 20
+    assert O.oz_beta(3, 16) == O.oz_beta(4, 16) == 20
+    with pytest.raises(ValueError):
+        O.oz_beta(K, 0)
+    with pytest.raises(ValueError):
+        O.oz_beta(K, O.OZ_SMAX + 1)
 
 
 @pytest.mark.parametrize("K", [1, 2, 3, 4])
@@ -44,18 +68,19 @@ def test_slices_sum_exactly_and_sit_on_their_grids(K):
         E = O.oz_scale(x[0])
         top = max(abs(v) for v in x[0])
         assert top < 2.0 ** E and top >= 2.0 ** (E - 1)
-        for s in (1, 3, 8, 16):
+        for s in (1, 3, 5, 8, 16):
             sl, rem = O.oz_slices(K, s, x, E)
+            beta = O.oz_beta(K, s)
             for i in range(m):
                 total = sum((F(v) for v in sl[:, i]), Fraction(0)) + X.value(rem[:, i])
                 assert total == X.value(x[:, i])
                 for q in range(s):
-                    grid = Fraction(2) ** (E - (q + 1) * BETA)
+                    grid = Fraction(2) ** (E - (q + 1) * beta)
                     units = F(sl[q, i]) / grid
                     assert units.denominator == 1
-                    assert abs(units) <= slice_bound(K, q)
+                    assert abs(units) <= slice_bound(K, q, beta)
                 # what is left is below half a grid step per word
-                assert abs(X.value(rem[:, i])) <= K * Fraction(2) ** (E - s * BETA) / 2
+                assert abs(X.value(rem[:, i])) <= K * Fraction(2) ** (E - s * beta) / 2
             if s == 16:  # 320 bits below the top reach every word's last bit
                 assert np.all(rem == 0.0)
 
@@ -79,18 +104,22 @@ def blocks(g, K, m, kb, nc, spread):
     return L, U, C
 
 
-@pytest.mark.parametrize("K", [2, 3, 4])
-def test_group_sums_are_exact_at_full_width(K):
-    """kb = 64 and s = 16: the largest group has 64 * 16 products; with
-    every entry near the top of its binade the sums come closest to 2^53
-    grid units.  Each acc_d must equal the rational sum exactly."""
-    g = np.random.default_rng(720 + K)
-    m, kb, nc, s = 3, 64, 2, 16
+@pytest.mark.parametrize("K,s", [(2, 16), (3, 16), (4, 16), (2, 5), (2, 7), (3, 5), (4, 11), (1, 3)])
+def test_group_sums_are_exact_at_full_width(K, s):
+    """kb = 64: the largest group has 64 * s products; with every entry near
+    the top of its binade and the lower words near half a step of the grid
+    the sums come closest to the bound.  Each acc_d must equal the rational
+    sum exactly, at the widest slices beta(K, s) allows."""
+    g = np.random.default_rng(720 + K + 31 * s)
+    m, kb, nc = 3, 64, 2
+    beta = O.oz_beta(K, s)
     L, U, C = blocks(g, K, m, kb, nc, spread=0)
-    # push every leading word to the top of [1/2, 1)
-    L[0] = np.sign(L[0]) * (1.0 - 2.0 ** -53)
-    U[0] = np.sign(U[0]) * (1.0 - 2.0 ** -53)
+    # push every leading word to the top of [1/2, 1), signs aligned so that
+    # the group sums add up instead of cancelling
+    L[0] = 1.0 - 2.0 ** -53
+    U[0] = 1.0 - 2.0 ** -53
     _, acc = O.oz_update(K, s, L, U, C)
+    largest = Fraction(0)
     for i in range(m):
         E = O.oz_scale(L[0, :, i])
         Ls, _ = O.oz_slices(K, s, L[:, :, i], E)
@@ -100,9 +129,12 @@ def test_group_sums_are_exact_at_full_width(K):
             for d in range(s):
                 exact = sum((F(Ls[p, k]) * F(Us[d - p, k]) for p in range(d + 1) for k in range(kb)), Fraction(0))
                 assert F(acc[d, j, i]) == exact, (i, j, d)
-                grid = Fraction(2) ** (E + Fc - (d + 2) * BETA)
+                grid = Fraction(2) ** (E + Fc - (d + 2) * beta)
                 assert (exact / grid).denominator == 1
                 assert abs(exact / grid) < Fraction(2) ** 53
+                largest = max(largest, abs(exact / grid))
+    # the test reaches the bound's order of magnitude (within a factor 16)
+    assert largest * 16 > group_bound(K, s, beta) / (s if s > 1 else 1)
 
 
 @pytest.mark.parametrize("K", [2, 3, 4])
@@ -120,7 +152,8 @@ def test_update_within_truncation_and_rounding_bound(K, s):
             lu = sum((X.value(L[:, k, i]) * X.value(U[:, j, k]) for k in range(kb)), Fraction(0))
             exact = X.value(C[:, j, i]) - lu
             got = X.value(Cn[:, j, i])
-            trunc = kb * Fraction(2) ** (E + Fc - s * BETA) * (Fraction(41, 10) * (s + 1) + K + 1)
+            beta = O.oz_beta(K, s)
+            trunc = kb * Fraction(2) ** (E + Fc - s * beta) * (Fraction(41, 10) * (s + 1) + K + 1)
             comb = 8 * s * uK * (abs(X.value(C[:, j, i])) + sum(abs(F(a)) for a in acc[:, j, i]))
             assert abs(got - exact) <= trunc + comb, (i, j)
 
