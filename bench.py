@@ -33,12 +33,13 @@ FMS_FLOPS = {1: 2, 2: 27, 3: 75, 4: 158}  # FP64 flops per K-word multiply-subtr
 # launch of the TD update: 63 + 6 + 3 = 72 per multiply-subtract); the add-dominated mix caps
 # the flop fraction near 52%, the issue fraction (instructions against half the flop peak) not
 FMS_INSTS = {1: 1, 2: 26, 3: 72, 4: 152}
-# HBM bytes per trailing-update launch (mean over the launches of one factorisation, both tile
-# shapes) from rocprofv3 FETCH_SIZE / WRITE_SIZE passes, each scaled by what the counter reads
-# on a plain 256 MiB device copy (fetch x2.000, write x1.000): profiles/counters_update_randsvd_n4096.md.
-# Valid for the kernels they were taken on only: (form, factor words, n, slices).
-MEASURED_TRAFFIC = {("ozaki", 3, 4096, 5): 2.203e8, ("plain", 3, 4096, 0): 1.875e8,
-                    ("ozaki", 2, 4096, 5): 1.692e8, ("plain", 2, 4096, 0): 1.283e8}
+# HBM bytes per big-tile trailing-update launch (the launches the library times; mean over one
+# factorisation) from rocprofv3 FETCH_SIZE / WRITE_SIZE passes, each scaled by what the counter
+# reads on a plain 256 MiB device copy (fetch x2.000, write x1.000):
+# profiles/counters_update_randsvd_n4096.md.  Valid for the kernels they were taken on only:
+# (form, factor words, n, slices).
+MEASURED_TRAFFIC = {("ozaki", 3, 4096, 5): 4.270e8, ("plain", 3, 4096, 0): 3.598e8,
+                    ("ozaki", 2, 4096, 5): 3.261e8, ("plain", 2, 4096, 0): 2.467e8}
 DEFAULT_SLICES = {1: 3, 2: 5, 3: 5, 4: 11}  # split form: measured fastest to QD accuracy (DD, TD: 5)
 WORD_NAME = {1: "FP64", 2: "DD", 3: "TD", 4: "QD"}
 
@@ -411,10 +412,10 @@ def main():
         t_getrf = min(times) / 1e3
         achieved = upd_flops / (upd_ms / 1e3) / 1e12 if upd_ms > 0 else 0.0
         if slices:
-            roof = {"kernel": f"k_oz_update<{K},{slices}> (split trailing update, FP64 MFMA)", "bound": "mfma",
+            roof = {"kernel": f"k_oz_update<{K},{slices}> big tile (split trailing update, FP64 MFMA)", "bound": "mfma",
                     "flops_per_launch": "2 * S(S+1)/2 * m * nc * kb (slice-pair products)"}
         else:
-            roof = {"kernel": f"k_update<{K}> (trailing update, vector FP64)", "bound": "alu",
+            roof = {"kernel": f"k_update<{K}> big tile (trailing update, vector FP64)", "bound": "alu",
                     "flops_per_launch": f"{FMS_FLOPS[K]} * m * nc * kb (K-word multiply-subtracts)"}
         traffic = MEASURED_TRAFFIC.get(("ozaki" if slices else "plain", K, n, slices))
         if not slices:

@@ -375,8 +375,10 @@ int bnc_mw_apply(int32_t op, int32_t K, int64_t n, const double *c, const double
 
 /*
  * Timing of the trailing-update launches inside bnc_getrf_* and bnc_refine:
- * with profiling on, every trailing-update launch is bracketed by hipEvents
- * on its stream.  bnc_profile_read synchronises on the recorded events and
+ * with profiling on, every big-tile trailing-update launch (the update of
+ * the columns right of the look-ahead panel, on the caller's stream) is
+ * bracketed by hipEvents on its stream; the thin look-ahead launches are
+ * not timed.  bnc_profile_read synchronises on the recorded events and
  * returns the summed milliseconds, the summed algorithmic FP64 operations
  * (m * n * k multiply-subtracts times the per-operation count) and the number
  * of launches since the last read, then clears them (host pointers).
