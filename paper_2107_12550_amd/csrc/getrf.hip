@@ -612,79 +612,89 @@ __global__ void __launch_bounds__(PANEL_THREADS)
 
 // ---------------------------------------------------------------------------
 // row interchanges outside the panel (+ U12 solve right of the panel)
-// one workgroup of 64 threads per column
+// one workgroup of one wave per column
 // ---------------------------------------------------------------------------
+// Lane l moves pairs l and PANEL_NB_MAX + l.  Every source is read before
+// any destination is written: the stores use the loaded words, so they
+// issue only after the wave's loads have returned.  Pairs l < PANEL_NB_MAX
+// are the block rows (destination j0 + l); with the U12 solve, row j0 + l
+// after the interchanges is lane l's own loaded word (or the untouched
+// row), so the solve starts from registers and its result is the only
+// store to the block rows.
 template <int K, bool TRSM>
 __global__ void __launch_bounds__(64)
     k_laswp_trsm(double *__restrict__ A, int64_t lda, int64_t ldp, int64_t j0, int jb, int64_t col0,
                  const int64_t *__restrict__ pairs, int ozs, double *__restrict__ SU, int64_t ldsu)
 {
-    __shared__ double stage[2 * PANEL_NB_MAX][K];
     const int64_t c = col0 + blockIdx.x;
     const int lane = threadIdx.x;
     const int64_t *dst = pairs, *src = pairs + 2 * PANEL_NB_MAX;
     double *colp = A + c * lda;
-    for (int t = lane; t < 2 * PANEL_NB_MAX; t += 64) {
-        const int64_t s = src[t];
-        if (s >= 0) {
+    const int64_t s0 = src[lane], s1 = src[PANEL_NB_MAX + lane];
+    const int64_t d0 = dst[lane], d1 = dst[PANEL_NB_MAX + lane];
+    double v0[K], v1[K];
 #pragma unroll
-            for (int w = 0; w < K; ++w)
-                stage[t][w] = colp[w * ldp + s];
-        }
+    for (int w = 0; w < K; ++w) {
+        v0[w] = s0 >= 0 ? colp[w * ldp + s0] : 0.0;
+        v1[w] = s1 >= 0 ? colp[w * ldp + s1] : 0.0;
     }
-    __syncthreads();
-    for (int t = lane; t < 2 * PANEL_NB_MAX; t += 64) {
-        const int64_t d = dst[t];
-        if (d >= 0) {
-#pragma unroll
-            for (int w = 0; w < K; ++w)
-                colp[w * ldp + d] = stage[t][w];
-        }
-    }
-    if (!TRSM)
-        return;
     // L11 columns are read PF steps ahead of their use (they do not
     // depend on the solve), so the chain only waits for the arithmetic
     constexpr int PF = 8;
-    double lp[PF][K];
-    const double *l11 = A + j0 * lda + j0 + lane;
-#pragma unroll
-    for (int q = 0; q < PF; ++q)
-#pragma unroll
-        for (int w = 0; w < K; ++w)
-            lp[q][w] = (q < jb && lane < jb) ? l11[w * ldp + (int64_t)q * lda] : 0.0;
-    __syncthreads();
-    __threadfence_block();
-    // forward substitution with the unit lower L11 (rows/cols j0..j0+jb-1),
-    // one wave: lane kk's finished value is broadcast by a shuffle
-    double u[K];
-    if (lane < jb) {
+    // (every prefetch is an unconditional load from an in-bounds address:
+    // lanes past jb read row j0 + jb - 1 and steps past the end re-read the
+    // last column, so the compiler can count the loads in flight)
+    double lp[PF][K], u[K];
+    const double *l11 = A + j0 * lda + j0 + (lane < jb ? lane : jb - 1);
+    if (TRSM) {
+        // the block row as it stands, loaded with the pairs' words (one
+        // round trip); lane l's own pair replaces it when there is one
 #pragma unroll
         for (int w = 0; w < K; ++w)
-            u[w] = colp[w * ldp + j0 + lane];
+            u[w] = lane < jb ? colp[w * ldp + j0 + lane] : 0.0;
+#pragma unroll
+        for (int q = 0; q < PF; ++q)
+#pragma unroll
+            for (int w = 0; w < K; ++w)
+                lp[q][w] = l11[w * ldp + (int64_t)(q < jb ? q : jb - 1) * lda];
+#pragma unroll
+        for (int w = 0; w < K; ++w)
+            u[w] = s0 >= 0 ? v0[w] : u[w];
     }
+    if (d1 >= 0)
+#pragma unroll
+        for (int w = 0; w < K; ++w)
+            colp[w * ldp + d1] = v1[w];
+    if (!TRSM) {
+        if (d0 >= 0)
+#pragma unroll
+            for (int w = 0; w < K; ++w)
+                colp[w * ldp + d0] = v0[w];
+        return;
+    }
+    // forward substitution with the unit lower L11 (rows/cols j0..j0+jb-1):
+    // lane kk's finished value is broadcast through scalar registers.  The
+    // steps run in whole groups of PF (at most 64 steps); a step past jb
+    // changes no lane.
     for (int k0 = 0; k0 < jb; k0 += PF) {
 #pragma unroll
         for (int q = 0; q < PF; ++q) {
             const int kk = k0 + q;
-            if (kk < jb) {
-                double uk[K];
+            double uk[K];
+#pragma unroll
+            for (int w = 0; w < K; ++w)
+                uk[w] = readlane_d(u[w], kk);
+            if (lane > kk && lane < jb) {
+                double o[K];
+                fms<K>(u, lp[q], uk, o);
 #pragma unroll
                 for (int w = 0; w < K; ++w)
-                    uk[w] = __shfl(u[w], kk, 64);
-                if (lane > kk && lane < jb) {
-                    double o[K];
-                    fms<K>(u, lp[q], uk, o);
-#pragma unroll
-                    for (int w = 0; w < K; ++w)
-                        u[w] = o[w];
-                }
-                if (kk + PF < jb && lane < jb) {
-#pragma unroll
-                    for (int w = 0; w < K; ++w)
-                        lp[q][w] = l11[w * ldp + (int64_t)(kk + PF) * lda];
-                }
+                    u[w] = o[w];
             }
+            const int kn = kk + PF < jb ? kk + PF : jb - 1;
+#pragma unroll
+            for (int w = 0; w < K; ++w)
+                lp[q][w] = l11[w * ldp + (int64_t)kn * lda];
         }
     }
     if (lane < jb) {
