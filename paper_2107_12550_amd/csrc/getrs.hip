@@ -107,17 +107,24 @@ __global__ void k_diag_recip(int64_t n, const double *__restrict__ LU, int64_t l
 // Stage the square block rows/cols [b0, b0+bsz) of one triangle into LDS:
 // blk[(w*TS_BS + c)*TS_BS + r] = word w of entry (b0+r, b0+c).
 // ---- one persistent launch per triangle ---------------------------------
-// Workgroup (one wave) per 64-row block.  Solved values are streamed: the
+// Workgroup per 64-row block, two waves.  Solved values are streamed: the
 // output planes start as XSENT (a signalling NaN that no arithmetic
 // produces) and every value is written once, by its lane, the moment it is
-// final (during the block's own diagonal solve).  A block consumes an
-// earlier block's values TS_G at a time, polling the words themselves, in
-// solve order, so each row still sees its updates in the unblocked order;
-// blocks wait only on blocks that were dispatched before them, and every
-// poll is bounded (on timeout the abort flag releases all waits and the
-// result is garbage).  A right-hand side that holds the XSENT bit pattern
-// can stall a poll in the same way.
-constexpr int TS_G = 8;  // columns fetched and consumed together
+// final (during the block's own diagonal solve).  Wave 1 fetches the
+// earlier blocks' values in solve order, polling the words themselves,
+// into a two-slot LDS ring; each lane stamps its entry with the block's
+// tag once its words are there.  Wave 0 consumes them TS_G columns at a
+// time, waiting on the stamps in LDS, so each row still sees its updates
+// in the unblocked order, then solves its own diagonal block.  Keeping the
+// polls in their own wave keeps their memory waits away from wave 0, whose
+// loads of the triangle's entries stay TS_PF groups ahead of their use.
+// Blocks wait only on blocks dispatched before them, and every wait is
+// bounded (on timeout the abort flag releases all waits and the result is
+// garbage).  A right-hand side that holds the XSENT bit pattern can stall
+// a poll in the same way.
+constexpr int TS_G = 8;   // columns consumed together
+constexpr int TS_NG = TS_BS / TS_G;  // groups per block
+constexpr int TS_PF = 4;  // groups of entries in flight (wave 0)
 constexpr unsigned TS_SPIN = 1u << 22;
 constexpr int64_t TS_SENT = (int64_t)0xFFF40000DEADBEEFull;
 
@@ -140,17 +147,31 @@ __device__ __forceinline__ double ts_bcast(double v, int l)
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-// Wait until the lanes in `need` of the 64-value block at src (K planes,
-// stride n) are final; lanes that have their value put it in vb[lane].
-// `have` (per lane; set beforehand for lanes past the end of a short block,
-// which then never load) and the returned mask carry over between calls.
-template <int K>
-__device__ __forceinline__ unsigned long long ts_poll(const double *src, int64_t n, unsigned long long need,
-                                                     unsigned long long fin, bool &have, double (&vb)[TS_BS][K],
-                                                     int *abort_flag, unsigned &spins)
+// One more round of a bounded wait: false once the spin budget is spent or
+// another wave has raised the abort flag (then it is raised here too and
+// every later wait of this wave gives up at once).
+__device__ __forceinline__ bool ts_again(unsigned &spins, int *abort_flag)
 {
-    const int lane = threadIdx.x;
-    while ((fin & need) != need) {
+    __builtin_amdgcn_s_sleep(1);
+    if (++spins > TS_SPIN ||
+        ((spins & 1023u) == 0 && __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+        __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        spins = TS_SPIN;
+        return false;
+    }
+    return true;
+}
+
+// Wave 1: lanes [0, cnt) of the 64-value block at src (K planes, stride n)
+// into slot[lane] as soon as their words are final, each entry stamped
+// with tag after its words are in LDS.
+template <int K>
+__device__ __forceinline__ void ts_fetch(const double *src, int64_t n, int cnt, int tag, double (*slot)[K],
+                                         int *stamp, unsigned &spins, int *abort_flag)
+{
+    const int lane = threadIdx.x & 63;
+    bool have = lane >= cnt;
+    for (;;) {
         if (!have) {
             double q[K];
             bool ok = true;
@@ -162,23 +183,36 @@ __device__ __forceinline__ unsigned long long ts_poll(const double *src, int64_t
             if (ok) {
 #pragma unroll
                 for (int w = 0; w < K; ++w)
-                    vb[lane][w] = q[w];
+                    slot[lane][w] = q[w];
+                __hip_atomic_store(&stamp[lane], tag, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
                 have = true;
             }
         }
-        fin = __ballot(have);
-        if ((fin & need) != need) {
-            __builtin_amdgcn_s_sleep(1);
-            if (++spins > TS_SPIN ||
-                ((spins & 1023u) == 0 && __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
-                __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                spins = TS_SPIN;
-                return ~0ull;
-            }
-        }
+        if (__ballot(!have) == 0ull || !ts_again(spins, abort_flag))
+            break;
     }
-    __builtin_amdgcn_wave_barrier();
-    return fin;
+}
+
+// Wave 0: until the entries of the lanes in `need` carry tag.
+__device__ __forceinline__ void ts_wait(const int *stamp, unsigned long long need, int tag, unsigned &spins,
+                                        int *abort_flag)
+{
+    const int lane = threadIdx.x & 63;
+    for (;;) {
+        const bool ok = __hip_atomic_load(const_cast<int *>(&stamp[lane]), __ATOMIC_ACQUIRE,
+                                          __HIP_MEMORY_SCOPE_WORKGROUP) == tag;
+        if ((__ballot(ok) & need) == need || !ts_again(spins, abort_flag))
+            break;
+    }
+}
+
+// Wave 1: until wave 0 has finished `want` blocks (a slot is reused two
+// blocks later).
+__device__ __forceinline__ void ts_wait_done(const int *done, int want, unsigned &spins, int *abort_flag)
+{
+    while (__hip_atomic_load(const_cast<int *>(done), __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < want)
+        if (!ts_again(spins, abort_flag))
+            break;
 }
 
 // both output planes to XSENT, abort flag cleared
@@ -193,68 +227,92 @@ __global__ void k_ts_reset(uint64_t *xs, int64_t nw, int *abort_flag)
 
 // x = L^-1 y (unit lower), y already permuted; x: K planes of stride n
 template <int K>
-__global__ void __launch_bounds__(TS_BS)
+__global__ void __launch_bounds__(2 * TS_BS)
     k_trsv_lower(const double *__restrict__ LU, int64_t lda, int64_t ldp, const double *__restrict__ y, int64_t ldy,
                  int64_t n, double *__restrict__ x, int *__restrict__ abort_flag)
 {
     extern __shared__ double dblk[];  // own diagonal block [w][c][r]
-    __shared__ double yb[TS_BS][K];
-    const int b = blockIdx.x, lane = threadIdx.x;
+    __shared__ double yb[2][TS_BS][K];
+    __shared__ int stamp[2][TS_BS];
+    __shared__ int done;
+    const int b = blockIdx.x, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t r0 = (int64_t)b * TS_BS;
     const int bsz = (int)((n - r0) < TS_BS ? (n - r0) : TS_BS);
     const int64_t i = r0 + lane;
     const bool act = lane < bsz;
-    for (int c = 0; c < bsz; ++c)
+#pragma unroll 2
+    for (int c = wave; c < bsz; c += 2)
         if (act)
 #pragma unroll
             for (int w = 0; w < K; ++w)
                 dblk[(w * TS_BS + c) * TS_BS + lane] = LU[w * ldp + (r0 + c) * lda + i];
+    stamp[wave][lane] = 0;
+    if (threadIdx.x == 0)
+        done = 0;
+    __syncthreads();
+    unsigned spins = 0;
+    if (wave == 1) {  // earlier blocks are full
+        for (int c = 0; c < b; ++c) {
+            if (c >= 2)
+                ts_wait_done(&done, c - 1, spins, abort_flag);
+            ts_fetch<K>(x + (int64_t)c * TS_BS, n, TS_BS, c + 1, yb[c & 1], stamp[c & 1], spins, abort_flag);
+        }
+        return;
+    }
     double v[K];
 #pragma unroll
     for (int w = 0; w < K; ++w)
         v[w] = act ? y[w * ldy + i] : 0.0;
-    unsigned spins = 0;
-    for (int c = 0; c < b; ++c) {  // earlier blocks are full
-        const int64_t k0 = (int64_t)c * TS_BS;
-        double t[TS_G][K];
+    // group G = columns G*TS_G.. of the earlier blocks; its L entries are
+    // loaded TS_PF groups ahead, unconditionally from in-bounds addresses
+    // (lanes past a short block read its last row, groups past the end
+    // re-read the last one), so the loads in flight can be counted; those
+    // lanes' values are never stored
+    const int64_t ic = r0 + (act ? lane : bsz - 1);
+    const int NG = b * TS_NG;
+    double tr[TS_PF][TS_G][K];
+    auto fetch = [&](int G, double (&t)[TS_G][K]) {
+        const int64_t k = (int64_t)(G < NG ? G : NG - 1) * TS_G;
 #pragma unroll
         for (int q = 0; q < TS_G; ++q)
 #pragma unroll
             for (int w = 0; w < K; ++w)
-                t[q][w] = act ? LU[w * ldp + (k0 + q) * lda + i] : 0.0;
-        unsigned long long fin = 0;
-        bool have = false;
-        for (int g0 = 0; g0 < TS_BS; g0 += TS_G) {
-            fin = ts_poll<K>(x + k0, n, ((1ull << TS_G) - 1) << g0, fin, have, yb, abort_flag, spins);
-            double tn[TS_G][K];
-            const bool more = g0 + TS_G < TS_BS;
-            if (more)
+                t[q][w] = LU[w * ldp + (k + q) * lda + ic];
+    };
+    if (NG > 0)
 #pragma unroll
-                for (int q = 0; q < TS_G; ++q)
+        for (int p = 0; p < TS_PF; ++p)
+            fetch(p, tr[p]);
+    for (int G0 = 0; G0 < NG; G0 += TS_PF) {  // NG is a multiple of TS_PF
 #pragma unroll
-                    for (int w = 0; w < K; ++w)
-                        tn[q][w] = act ? LU[w * ldp + (k0 + g0 + TS_G + q) * lda + i] : 0.0;
+        for (int p = 0; p < TS_PF; ++p) {
+            const int G = G0 + p;
+            const int c = G / TS_NG, g0 = (G % TS_NG) * TS_G;
+            ts_wait(stamp[c & 1], 0xFFull << g0, c + 1, spins, abort_flag);
 #pragma unroll
             for (int q = 0; q < TS_G; ++q) {
                 double yk[K], o[K];
 #pragma unroll
                 for (int w = 0; w < K; ++w)
-                    yk[w] = yb[g0 + q][w];
-                fms<K>(v, t[q], yk, o);
+                    yk[w] = yb[c & 1][g0 + q][w];
+                fms<K>(v, tr[p][q], yk, o);
 #pragma unroll
                 for (int w = 0; w < K; ++w)
                     v[w] = o[w];
             }
-            if (more)
+            // the group's arithmetic is done here, before the next wait (it
+            // would otherwise sink past it, to where v is next used)
 #pragma unroll
-                for (int q = 0; q < TS_G; ++q)
-#pragma unroll
-                    for (int w = 0; w < K; ++w)
-                        t[q][w] = tn[q][w];
+            for (int w = 0; w < K; ++w)
+                __asm__ volatile("" ::"v"(v[w]) : "memory");
+            if (g0 + TS_G == TS_BS && lane == 0)
+                __hip_atomic_store(&done, c + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            // the refill stays after the group's arithmetic, so that it
+            // reuses the group's registers instead of doubling them
+            __builtin_amdgcn_sched_barrier(0);
+            fetch(G + TS_PF, tr[p]);
         }
-        __builtin_amdgcn_wave_barrier();
     }
-    __syncthreads();
     // own diagonal block: lane kk is final when its turn comes; it
     // publishes its value before the others use it.  The block's next
     // column is read from LDS one step ahead (all 64 columns are there).
@@ -291,82 +349,110 @@ __global__ void __launch_bounds__(TS_BS)
 // y = U^-1 x with rd = 1/u_kk; the values go to xo (streamed, K planes of
 // stride n) and to y; workgroup g solves block nblk-1-g
 template <int K>
-__global__ void __launch_bounds__(TS_BS)
+__global__ void __launch_bounds__(2 * TS_BS)
     k_trsv_upper(const double *__restrict__ LU, int64_t lda, int64_t ldp, const double *__restrict__ rd,
                  const double *__restrict__ x, double *__restrict__ xo, double *__restrict__ y, int64_t ldy, int64_t n,
                  int *__restrict__ abort_flag)
 {
     extern __shared__ double dblk[];
-    __shared__ double xb[TS_BS][K];
-    const int nblk = gridDim.x, lane = threadIdx.x;
+    __shared__ double xb[2][TS_BS][K];
+    __shared__ int stamp[2][TS_BS];
+    __shared__ int done;
+    const int nblk = gridDim.x, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int b = nblk - 1 - (int)blockIdx.x;
     const int64_t r0 = (int64_t)b * TS_BS;
     const int bsz = (int)((n - r0) < TS_BS ? (n - r0) : TS_BS);
     const int64_t i = r0 + lane;
     const bool act = lane < bsz;
-    for (int c = 0; c < bsz; ++c)
+#pragma unroll 2
+    for (int c = wave; c < bsz; c += 2)
         if (act)
 #pragma unroll
             for (int w = 0; w < K; ++w)
                 dblk[(w * TS_BS + c) * TS_BS + lane] = LU[w * ldp + (r0 + c) * lda + i];
+    stamp[wave][lane] = 0;
+    if (threadIdx.x == 0)
+        done = 0;
+    __syncthreads();
+    // the blocks after this one, in solve order e = 0.. (block nblk-1-e;
+    // only e = 0 can be short)
+    const int ne = nblk - 1 - b;
+    unsigned spins = 0;
+    if (wave == 1) {
+        for (int e = 0; e < ne; ++e) {
+            const int64_t k0 = (int64_t)(nblk - 1 - e) * TS_BS;
+            const int bc = (int)((n - k0) < TS_BS ? (n - k0) : TS_BS);
+            if (e >= 2)
+                ts_wait_done(&done, e - 1, spins, abort_flag);
+            ts_fetch<K>(xo + k0, n, bc, e + 1, xb[e & 1], stamp[e & 1], spins, abort_flag);
+        }
+        return;
+    }
     double v[K], rk[K];
 #pragma unroll
     for (int w = 0; w < K; ++w) {
         v[w] = act ? x[w * n + i] : 0.0;
         rk[w] = act ? rd[w * n + i] : 0.0;
     }
-    unsigned spins = 0;
-    for (int c = nblk - 1; c > b; --c) {
-        const int64_t k0 = (int64_t)c * TS_BS;
+    // group G: sweep positions (G % TS_NG)*TS_G.. of block e = G / TS_NG,
+    // position p being column bc-1-p of the block (columns in decreasing
+    // order); U entries loaded TS_PF groups ahead from clamped in-bounds
+    // addresses, as in the lower solve
+    const int64_t ic = r0 + (act ? lane : bsz - 1);
+    const int NG = ne * TS_NG;
+    double tr[TS_PF][TS_G][K];
+    auto fetch = [&](int G, double (&t)[TS_G][K]) {
+        const int Gc = G < NG ? G : NG - 1;
+        const int64_t k0 = (int64_t)(nblk - 1 - Gc / TS_NG) * TS_BS;
         const int bc = (int)((n - k0) < TS_BS ? (n - k0) : TS_BS);
-        // columns in decreasing order: position q of the sweep is column
-        // bc-1-q of the block
-        double t[TS_G][K];
 #pragma unroll
-        for (int q = 0; q < TS_G; ++q)
+        for (int q = 0; q < TS_G; ++q) {
+            const int ps = (Gc % TS_NG) * TS_G + q;
+            const int pc = ps < bc ? ps : bc - 1;
 #pragma unroll
             for (int w = 0; w < K; ++w)
-                t[q][w] = (act && q < bc) ? LU[w * ldp + (k0 + bc - 1 - q) * lda + i] : 0.0;
-        unsigned long long fin = 0;
-        bool have = lane >= bc;  // lanes beyond a short last block never load
-        for (int g0 = 0; g0 < bc; g0 += TS_G) {
-            // the block's lanes bc-1-g0-q for q < TS_G (those >= 0)
-            const int hi = bc - 1 - g0, lo = (hi - TS_G + 1) > 0 ? (hi - TS_G + 1) : 0;
-            const unsigned long long need = (hi - lo + 1 == 64 ? ~0ull : ((1ull << (hi - lo + 1)) - 1)) << lo;
-            fin = ts_poll<K>(xo + k0, n, need, fin, have, xb, abort_flag, spins);
-            double tn[TS_G][K];
-            const bool more = g0 + TS_G < bc;
-            if (more)
+                t[q][w] = LU[w * ldp + (k0 + bc - 1 - pc) * lda + ic];
+        }
+    };
+    if (NG > 0)
 #pragma unroll
-                for (int q = 0; q < TS_G; ++q)
+        for (int p = 0; p < TS_PF; ++p)
+            fetch(p, tr[p]);
+    for (int G0 = 0; G0 < NG; G0 += TS_PF) {  // NG is a multiple of TS_PF
 #pragma unroll
-                    for (int w = 0; w < K; ++w)
-                        tn[q][w] = (act && g0 + TS_G + q < bc)
-                                       ? LU[w * ldp + (k0 + bc - 1 - (g0 + TS_G + q)) * lda + i]
-                                       : 0.0;
+        for (int p = 0; p < TS_PF; ++p) {
+            const int G = G0 + p;
+            const int e = G / TS_NG, g0 = (G % TS_NG) * TS_G;
+            const int64_t k0 = (int64_t)(nblk - 1 - e) * TS_BS;
+            const int bc = (int)((n - k0) < TS_BS ? (n - k0) : TS_BS);
+            if (g0 < bc) {
+                // the block's lanes bc-1-g0-q for q < TS_G (those >= 0)
+                const int hi = bc - 1 - g0, lo = (hi - TS_G + 1) > 0 ? (hi - TS_G + 1) : 0;
+                const unsigned long long need = ((1ull << (hi - lo + 1)) - 1) << lo;
+                ts_wait(stamp[e & 1], need, e + 1, spins, abort_flag);
 #pragma unroll
-            for (int q = 0; q < TS_G; ++q) {
-                if (g0 + q < bc) {
-                    double xk[K], o[K];
+                for (int q = 0; q < TS_G; ++q) {
+                    if (g0 + q < bc) {
+                        double xk[K], o[K];
 #pragma unroll
-                    for (int w = 0; w < K; ++w)
-                        xk[w] = xb[bc - 1 - (g0 + q)][w];
-                    fms<K>(v, t[q], xk, o);
+                        for (int w = 0; w < K; ++w)
+                            xk[w] = xb[e & 1][bc - 1 - (g0 + q)][w];
+                        fms<K>(v, tr[p][q], xk, o);
 #pragma unroll
-                    for (int w = 0; w < K; ++w)
-                        v[w] = o[w];
+                        for (int w = 0; w < K; ++w)
+                            v[w] = o[w];
+                    }
                 }
             }
-            if (more)
 #pragma unroll
-                for (int q = 0; q < TS_G; ++q)
-#pragma unroll
-                    for (int w = 0; w < K; ++w)
-                        t[q][w] = tn[q][w];
+            for (int w = 0; w < K; ++w)  // as in the lower solve
+                __asm__ volatile("" ::"v"(v[w]) : "memory");
+            if (g0 + TS_G == TS_BS && lane == 0)
+                __hip_atomic_store(&done, e + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __builtin_amdgcn_sched_barrier(0);  // as in the lower solve
+            fetch(G + TS_PF, tr[p]);
         }
-        __builtin_amdgcn_wave_barrier();
     }
-    __syncthreads();
     // the loads of v and rd are complete here; waiting for them explicitly
     // keeps the compiler from placing a full vector-memory wait at the head
     // of the loop below, where it would also wait for each published store
@@ -455,10 +541,10 @@ int trsv_pair(int64_t n, const double *LU, int64_t lda, int64_t ldp, const doubl
     hipLaunchKernelGGL(k_ts_reset, dim3((unsigned)(ceil_div(2 * K * n, 256) < 64 ? ceil_div(2 * K * n, 256) : 64)),
                        dim3(256), 0, s, (uint64_t *)x1, (int64_t)(2 * K * n), abort_flag);
     BNC_LAUNCH_CHECK();
-    hipLaunchKernelGGL((k_trsv_lower<K>), dim3((unsigned)nblk), dim3(TS_BS), lds, s, LU, lda, ldp, y, ldy, n, x1,
+    hipLaunchKernelGGL((k_trsv_lower<K>), dim3((unsigned)nblk), dim3(2 * TS_BS), lds, s, LU, lda, ldp, y, ldy, n, x1,
                        abort_flag);
     BNC_LAUNCH_CHECK();
-    hipLaunchKernelGGL((k_trsv_upper<K>), dim3((unsigned)nblk), dim3(TS_BS), lds, s, LU, lda, ldp, rd, x1, x2, y, ldy,
+    hipLaunchKernelGGL((k_trsv_upper<K>), dim3((unsigned)nblk), dim3(2 * TS_BS), lds, s, LU, lda, ldp, rd, x1, x2, y, ldy,
                        n, abort_flag);
     BNC_LAUNCH_CHECK();
     return BNC_OK;
