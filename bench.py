@@ -166,6 +166,71 @@ def batch_main(args):
     print(json.dumps(line), flush=True)
 
 
+def gemm_main(args):
+    """Multi-word GEMM C <- C - A B (bnc_gemm_*), m = n = k = `gemm_n`,
+    random multi-word operands resident on the device; `steps` timed launches
+    per factor length (DD and TD), HIP events on the launch's stream."""
+    import numpy as np
+    import torch
+
+    import paper_2107_12550_amd as P
+    n = args.gemm_n
+    forms = {}
+    for K in (2, 3):
+        g = torch.Generator(device="cuda").manual_seed(2107 + K)
+        A = torch.empty((K, n, n), dtype=torch.float64, device="cuda")
+        B = torch.empty_like(A)
+        C0 = torch.empty_like(A)
+        for T in (A, B, C0):
+            T[0].uniform_(-1.0, 1.0, generator=g)
+            for w in range(1, K):  # lower words a little below half an ulp of the one above
+                T[w].copy_(T[w - 1] * 2.0 ** -54)
+        C = C0.clone()
+        for _ in range(max(args.warmup, 1)):
+            P.gemm(K, A, B, C)
+        torch.cuda.synchronize()
+        s = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(args.steps):
+            P.gemm(K, A, B, C)
+        e1.record(s)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        fms = float(n) ** 3
+        achieved = fms * FMS_FLOPS[K] / (ms / 1e3) / 1e12
+        forms[WORD_NAME[K]] = {
+            "ms_per_launch": ms, "gflops_eq": 2.0 * fms / (ms / 1e3) / 1e9,
+            "roofline": {"kernel": f"k_update<{K}> big tile (multi-word GEMM)", "bound": "alu",
+                         "flops_per_launch": f"{FMS_FLOPS[K]} * m * n * k (K-word multiply-subtracts)",
+                         "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": achieved / FP64_PEAK_TFLOPS,
+                         "issue_frac": achieved * FMS_INSTS[K] / FMS_FLOPS[K] / (FP64_PEAK_TFLOPS / 2),
+                         "traffic": None}}
+        log(f"[bench] gemm {WORD_NAME[K]} n={n}: {ms:.2f} ms per launch, {forms[WORD_NAME[K]]['gflops_eq']:.0f} "
+            f"GFLOPS-eq")
+        del A, B, C, C0
+    line = {
+        "metric": f"multi-word GEMM GFLOPS-eq (2mnk / time), m=n=k={n}, TD", "value": forms["TD"]["gflops_eq"],
+        "unit": "GFLOPS-eq", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": forms["TD"]["ms_per_launch"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"C <- C - A B, K-plane {n}x{n} operands, random words", "n": n},
+        "roofline": forms["TD"]["roofline"], "forms": forms}
+    if not args.no_cpu_baseline:
+        import oracle as O
+        nc = 640
+        rng = np.random.default_rng(7)
+        A = rng.uniform(-1, 1, (3, nc, nc))
+        A[1:] *= 2.0 ** -54
+        t0 = time.perf_counter()
+        O.gemm(3, A, A, A)
+        dt = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": 2.0 * nc ** 3 / dt / 1e9, "unit": "GFLOPS-eq", "cores": 1, "kind": "oracle",
+                                "sample": f"oracle TD gemm at m=n=k={nc}: {dt:.1f} s, single thread"}
+    print(json.dumps(line), flush=True)
+
+
 def selector_main(args):
     """Learned precision choice on a held-out stream: `count` randsvd systems
     n ~ U{32..256}, cond = 10^U(1, 60), binary64 entries (seed stream 6, the
@@ -319,7 +384,8 @@ def main():
     ap.add_argument("--ozaki", type=int, default=-1,
                     help="single mode: also time the split trailing update with this many slices "
                          "(-1 = the default for the factor precision, 0 = plain form only)")
-    ap.add_argument("--mode", choices=["single", "batch", "selector", "sweep"], default="single")
+    ap.add_argument("--mode", choices=["single", "batch", "selector", "sweep", "gemm"], default="single")
+    ap.add_argument("--gemm-n", type=int, default=4096, help="gemm mode: m = n = k")
     ap.add_argument("--count", type=int, default=8192, help="batch mode: number of systems")
     ap.add_argument("--slots", type=int, default=0, help="batch mode: persistent workgroups (0 = auto)")
     ap.add_argument("--tune", action="store_true", help="batch mode: tune the launch variants now")
@@ -336,6 +402,8 @@ def main():
         return batch_main(args)
     if args.mode == "sweep":
         return sweep_main(args)
+    if args.mode == "gemm":
+        return gemm_main(args)
     if args.mode == "selector":
         if args.count == 8192:
             args.count = 16384

@@ -140,6 +140,36 @@ int bnc_getrs_td(int64_t n, int64_t nrhs, const double *LU, int64_t lda, int64_t
 int bnc_getrs_qd(int64_t n, int64_t nrhs, const double *LU, int64_t lda, int64_t ldp, const int64_t *ipiv,
                  double *B, int64_t ldb, int64_t ldpb, void *stream);
 
+/*
+ * Multi-word matrix multiply-subtract C <- C - A B (Kouya 2021, Sec. 2 and
+ * Fig. 1: the block matrix multiplication of the multi-word library the
+ * direct methods are built on; here the LU's K-word trailing-update kernel,
+ * exported).  Every entry gets c_ij <- fms(c_ij, a_il, b_lj) for l = 0..k-1
+ * in increasing l, one K-word multiply-subtract each, so the result does
+ * not depend on tiling and equals the plain triple loop bit for bit.
+ * Negating B (exact, word by word) turns it into C + A B; with C = 0 and -B
+ * it gives A B.
+ *   m, n, k   C is m x n, A m x k, B k x n (>= 0; nothing happens when any
+ *             is 0)
+ *   A, lda, ldpa   K-plane, column-major, lda >= max(1, m), plane stride
+ *                  ldpa >= lda * k (ignored for K = 1)
+ *   B, ldb, ldpb   K-plane, ldb >= max(1, k), ldpb >= ldb * n
+ *   C, ldc, ldpc   K-plane, ldc >= max(1, m), ldpc >= ldc * n; must not
+ *                  overlap A or B
+ * Words of A and B need not be normalised; C's words come out as the
+ * multiply-subtract leaves them.  No scratch.  Argument errors as above
+ * (-i for argument i); BNC_ERR_UNSUPPORTED when n > 1048560, m > 2^31 or
+ * k > 2^30.
+ */
+int bnc_gemm_d(int64_t m, int64_t n, int64_t k, const double *A, int64_t lda, int64_t ldpa, const double *B,
+               int64_t ldb, int64_t ldpb, double *C, int64_t ldc, int64_t ldpc, void *stream);
+int bnc_gemm_dd(int64_t m, int64_t n, int64_t k, const double *A, int64_t lda, int64_t ldpa, const double *B,
+                int64_t ldb, int64_t ldpb, double *C, int64_t ldc, int64_t ldpc, void *stream);
+int bnc_gemm_td(int64_t m, int64_t n, int64_t k, const double *A, int64_t lda, int64_t ldpa, const double *B,
+                int64_t ldb, int64_t ldpb, double *C, int64_t ldc, int64_t ldpc, void *stream);
+int bnc_gemm_qd(int64_t m, int64_t n, int64_t k, const double *A, int64_t lda, int64_t ldpa, const double *B,
+                int64_t ldb, int64_t ldpb, double *C, int64_t ldc, int64_t ldpc, void *stream);
+
 /* Options of the refinement loop (host struct). */
 typedef struct bnc_refine_opts {
     int32_t factor_words; /* K of the factorisation: 1, 2, 3 or 4 */

@@ -67,6 +67,7 @@ def lib() -> ctypes.CDLL:
         L.orc_oz_slices.argtypes = [ctypes.c_int, ctypes.c_int, I64, P, ctypes.c_int32, P, P]
         L.orc_oz_scale.argtypes = [I64, P]
         L.orc_oz_scale.restype = ctypes.c_int32
+        L.orc_gemm.argtypes = [ctypes.c_int, I64, I64, I64, P, I64, I64, P, I64, I64, P, I64, I64]
         L.orc_oz_beta.argtypes = [ctypes.c_int, ctypes.c_int]
         L.orc_oz_beta.restype = ctypes.c_int
         L.orc_oz_update.argtypes = [ctypes.c_int, ctypes.c_int, I64, I64, I64, P, I64, I64, P, I64, I64,
@@ -253,6 +254,21 @@ def getrs(K: int, LU: np.ndarray, ipiv: np.ndarray, b: np.ndarray) -> np.ndarray
     lib().orc_getrs(K, n, nrhs, _p(LU), n, n * n, ipiv.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                     _p(B), n, n * nrhs)
     return B
+
+
+def gemm(K: int, A: np.ndarray, B: np.ndarray, C: np.ndarray) -> np.ndarray:
+    """C - A B in K-word arithmetic (Sec. 2, Fig. 1: the library's block
+    matrix multiplication): every entry takes its k multiply-subtracts in
+    increasing k.  A (K, k, m), B (K, n, k), C (K, n, m), K-plane column-major
+    (column index first); returns the new C."""
+    A, B = _c(A), _c(B)
+    C = _c(C).copy()
+    _, k, m = A.shape
+    n = B.shape[1]
+    assert B.shape[2] == k and C.shape[1] == n and C.shape[2] == m
+    lib().orc_gemm(K, m, n, k, _p(A), max(m, 1), max(m, 1) * k, _p(B), max(k, 1), max(k, 1) * n, _p(C), max(m, 1),
+                   max(m, 1) * n)
+    return C
 
 
 def residual(A: np.ndarray, x: np.ndarray, b: np.ndarray) -> np.ndarray:

@@ -260,6 +260,35 @@ void orc_fms_vec(int K, int64_t n, const double *c, const double *a, const doubl
     }
 }
 
+/*
+ * Multi-word matrix multiply-subtract C <- C - A B (the block matrix
+ * multiplication of the multi-word library, Sec. 2 and Fig. 1), as its
+ * definition: every entry c_ij <- fms(c_ij, a_il, b_lj) for l = 0..k-1 in
+ * increasing l.  K-plane column-major matrices: word w of A(i, l) at
+ * A[w*ldpa + l*lda + i], and likewise for B and C.
+ */
+void orc_gemm(int K, int64_t m, int64_t n, int64_t k, const double *A, int64_t lda, int64_t ldpa, const double *B,
+              int64_t ldb, int64_t ldpb, double *C, int64_t ldc, int64_t ldpc)
+{
+    for (int64_t j = 0; j < n; ++j)
+        for (int64_t i = 0; i < m; ++i) {
+            double c[KMAX], a[KMAX], b[KMAX], o[KMAX];
+            for (int w = 0; w < K; ++w)
+                c[w] = C[w * ldpc + j * ldc + i];
+            for (int64_t l = 0; l < k; ++l) {
+                for (int w = 0; w < K; ++w) {
+                    a[w] = A[w * ldpa + l * lda + i];
+                    b[w] = B[w * ldpb + j * ldb + l];
+                }
+                mw_fms(K, c, a, b, o);
+                for (int w = 0; w < K; ++w)
+                    c[w] = o[w];
+            }
+            for (int w = 0; w < K; ++w)
+                C[w * ldpc + j * ldc + i] = c[w];
+        }
+}
+
 void orc_mul_vec(int K, int64_t n, const double *a, const double *b, double *out)
 {
     for (int64_t i = 0; i < n; ++i) {

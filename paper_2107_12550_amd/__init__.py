@@ -23,6 +23,7 @@ from .bnc import (  # noqa: F401
     BatchSolver,
     BncError,
     features,
+    gemm,
     getrf,
     getrf_ozaki,
     getrs,

@@ -65,6 +65,10 @@ def _load() -> ctypes.CDLL:
         g.restype = ctypes.c_int
     L.bnc_getrf_ozaki.argtypes = [I32, I32, I64, VP, I64, I64, VP, VP, VP]
     L.bnc_getrf_ozaki.restype = ctypes.c_int
+    for s in _SUFFIX.values():
+        gm = getattr(L, f"bnc_gemm_{s}")
+        gm.argtypes = [I64, I64, I64, VP, I64, I64, VP, I64, I64, VP, I64, I64, VP]
+        gm.restype = ctypes.c_int
     L.bnc_oz_beta.argtypes = [I32, I32]
     L.bnc_oz_beta.restype = ctypes.c_int
     L.bnc_features_workspace_size.argtypes = [I32]
@@ -165,6 +169,23 @@ def getrs(K: int, LU: torch.Tensor, ipiv: torch.Tensor, B: torch.Tensor) -> torc
     _check(f(n, nrhs, _dev(LU, "LU", 3), n, n * n, ctypes.c_void_p(ipiv.data_ptr()), ctypes.c_void_p(B.data_ptr()),
              n, n * nrhs, _stream()), "getrs")
     return B
+
+
+def gemm(K: int, A: torch.Tensor, B: torch.Tensor, C: torch.Tensor) -> torch.Tensor:
+    """C <- C - A B in K-word arithmetic, in place.  A (K, k, m), B (K, n, k)
+    and C (K, n, m) are K-plane column-major tensors (column index first)."""
+    for name, t in (("A", A), ("B", B), ("C", C)):
+        if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and t.dim() == 3 and t.shape[0] == K):
+            raise BncError(f"{name}: expected a contiguous float64 CUDA tensor of shape (K, cols, rows)")
+    _, k, m = A.shape
+    n = B.shape[1]
+    if B.shape[2] != k or C.shape[1] != n or C.shape[2] != m:
+        raise BncError("gemm: shapes do not match")
+    f = getattr(_lib, f"bnc_gemm_{_SUFFIX[K]}")
+    vp = lambda t: ctypes.c_void_p(t.data_ptr())  # noqa: E731
+    _check(f(m, n, k, vp(A), max(m, 1), max(m, 1) * k, vp(B), max(k, 1), max(k, 1) * n, vp(C), max(m, 1),
+             max(m, 1) * n, _stream()), "gemm")
+    return C
 
 
 def oz_beta(K: int, slices: int) -> int:

@@ -241,6 +241,39 @@ static int getrs_entry(int64_t n, int64_t nrhs, const double *LU, int64_t lda, i
     return getrs_run<K>(n, nrhs, LU, lda, ldp, ipiv, B, ldb, ldpb, scr, S(stream));
 }
 
+template <int K>
+static int gemm_entry(int64_t m, int64_t n, int64_t k, const double *A, int64_t lda, int64_t ldpa, const double *B,
+                      int64_t ldb, int64_t ldpb, double *C, int64_t ldc, int64_t ldpc, void *stream)
+{
+    if (m < 0)
+        return fail_arg(-1, "gemm: m < 0");
+    if (n < 0)
+        return fail_arg(-2, "gemm: n < 0");
+    if (k < 0)
+        return fail_arg(-3, "gemm: k < 0");
+    if (m > 0 && k > 0 && !A)
+        return fail_arg(-4, "gemm: A is NULL");
+    if (lda < (m > 1 ? m : 1))
+        return fail_arg(-5, "gemm: lda < max(1, m)");
+    if (K > 1 && ldpa < lda * k)
+        return fail_arg(-6, "gemm: ldpa < lda * k");
+    if (k > 0 && n > 0 && !B)
+        return fail_arg(-7, "gemm: B is NULL");
+    if (ldb < (k > 1 ? k : 1))
+        return fail_arg(-8, "gemm: ldb < max(1, k)");
+    if (K > 1 && ldpb < ldb * n)
+        return fail_arg(-9, "gemm: ldpb < ldb * n");
+    if (m > 0 && n > 0 && !C)
+        return fail_arg(-10, "gemm: C is NULL");
+    if (ldc < (m > 1 ? m : 1))
+        return fail_arg(-11, "gemm: ldc < max(1, m)");
+    if (K > 1 && ldpc < ldc * n)
+        return fail_arg(-12, "gemm: ldpc < ldc * n");
+    if (n > 65535LL * 16 || m > ((int64_t)1 << 31) || k > ((int64_t)1 << 30))
+        return fail_arg(BNC_ERR_UNSUPPORTED, "gemm: m, n or k too large for one launch");
+    return gemm_run<K>(m, n, k, A, lda, ldpa, B, ldb, ldpb, C, ldc, ldpc, S(stream));
+}
+
 extern "C" {
 
 int bnc_getrf_d(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int64_t *info, void *stream)
@@ -258,6 +291,27 @@ int bnc_getrf_td(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, 
 int bnc_getrf_qd(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int64_t *info, void *stream)
 {
     return getrf_entry<4>(n, A, lda, ldp, ipiv, info, stream);
+}
+
+int bnc_gemm_d(int64_t m, int64_t n, int64_t k, const double *A, int64_t lda, int64_t ldpa, const double *B,
+              int64_t ldb, int64_t ldpb, double *C, int64_t ldc, int64_t ldpc, void *stream)
+{
+    return gemm_entry<1>(m, n, k, A, lda, ldpa, B, ldb, ldpb, C, ldc, ldpc, stream);
+}
+int bnc_gemm_dd(int64_t m, int64_t n, int64_t k, const double *A, int64_t lda, int64_t ldpa, const double *B,
+               int64_t ldb, int64_t ldpb, double *C, int64_t ldc, int64_t ldpc, void *stream)
+{
+    return gemm_entry<2>(m, n, k, A, lda, ldpa, B, ldb, ldpb, C, ldc, ldpc, stream);
+}
+int bnc_gemm_td(int64_t m, int64_t n, int64_t k, const double *A, int64_t lda, int64_t ldpa, const double *B,
+               int64_t ldb, int64_t ldpb, double *C, int64_t ldc, int64_t ldpc, void *stream)
+{
+    return gemm_entry<3>(m, n, k, A, lda, ldpa, B, ldb, ldpb, C, ldc, ldpc, stream);
+}
+int bnc_gemm_qd(int64_t m, int64_t n, int64_t k, const double *A, int64_t lda, int64_t ldpa, const double *B,
+               int64_t ldb, int64_t ldpb, double *C, int64_t ldc, int64_t ldpc, void *stream)
+{
+    return gemm_entry<4>(m, n, k, A, lda, ldpa, B, ldb, ldpb, C, ldc, ldpc, stream);
 }
 
 int bnc_oz_beta(int32_t factor_words, int32_t slices)

@@ -55,5 +55,8 @@ constexpr int PANEL_WG_MAX = 256;
 // Split (Ozaki) trailing update: at most this many slices per operand.
 constexpr int OZ_SMAX = 12;
 size_t getrf_scratch_bytes(int K, int64_t n);
+template <int K>
+int gemm_run(int64_t m, int64_t n, int64_t k, const double *A, int64_t lda, int64_t ldpa, const double *B,
+             int64_t ldb, int64_t ldpb, double *C, int64_t ldc, int64_t ldpc, hipStream_t s);
 
 }  // namespace bnc

@@ -715,16 +715,26 @@ __global__ void __launch_bounds__(64)
 }
 
 // ---------------------------------------------------------------------------
-// trailing update C <- C - L21 * U12
-// C(i,j) = A[r0+i, c0+j], L21(i,k) = A[r0+i, j0+k], U12(k,j) = A[j0+k, c0+j]
+// multiply-subtract C <- C - L U on K-plane views (pointer, column stride,
+// plane stride): C m x nc, L m x kd, U kd x nc.  The trailing update of the
+// LU passes views of its own matrix: C(i,j) = A[r0+i, c0+j],
+// L21(i,k) = A[r0+i, j0+k], U12(k,j) = A[j0+k, c0+j]; the multi-word GEMM
+// passes three matrices.  Each entry of C is updated in increasing k, one
+// K-word multiply-subtract per k.
 // workgroup tile BM x BN, thread tile TM x TN (rows tx + (BM/TM) a,
 // columns ty + (BN/TN) b), k staged through LDS in chunks of KB.
 // ---------------------------------------------------------------------------
+struct MwView {
+    const double *p;
+    int64_t ld, ldp;
+};
+
 template <int K, int BM, int BN, int TM, int TN, int KB>
 __global__ void __launch_bounds__(UPD_THREADS)
-    k_update(double *__restrict__ A, int64_t lda, int64_t ldp, int64_t r0, int64_t c0, int64_t m, int64_t nc,
-             int64_t j0, int kd)
+    k_update(double *__restrict__ Cp, int64_t ldc, int64_t ldpc, MwView Lv, MwView Uv, int64_t m, int64_t nc, int kd)
 {
+    const double *__restrict__ Lp = Lv.p;
+    const double *__restrict__ Up = Uv.p;
     static_assert((BM / TM) * (BN / TN) == UPD_THREADS, "thread tile");
     __shared__ double Ls[K][KB][BM];
     __shared__ double Us[K][KB][BN];
@@ -741,7 +751,7 @@ __global__ void __launch_bounds__(UPD_THREADS)
             const int64_t i = bi + tx + a * TX, j = bj + ty + b * (BN / TN);
 #pragma unroll
             for (int w = 0; w < K; ++w)
-                acc[a][b][w] = (i < m && j < nc) ? A[w * ldp + (c0 + j) * lda + r0 + i] : 0.0;
+                acc[a][b][w] = (i < m && j < nc) ? Cp[w * ldpc + j * ldc + i] : 0.0;
         }
 
     for (int k0 = 0; k0 < kd; k0 += KB) {
@@ -751,14 +761,14 @@ __global__ void __launch_bounds__(UPD_THREADS)
             const bool ok = kk < kc && bi + i < m;
 #pragma unroll
             for (int w = 0; w < K; ++w)
-                Ls[w][kk][i] = ok ? A[w * ldp + (j0 + k0 + kk) * lda + r0 + bi + i] : 0.0;
+                Ls[w][kk][i] = ok ? Lp[w * Lv.ldp + (k0 + kk) * Lv.ld + bi + i] : 0.0;
         }
         for (int e = tid; e < KB * BN; e += UPD_THREADS) {
             const int kk = e % KB, j = e / KB;
             const bool ok = kk < kc && bj + j < nc;
 #pragma unroll
             for (int w = 0; w < K; ++w)
-                Us[w][kk][j] = ok ? A[w * ldp + (c0 + bj + j) * lda + j0 + k0 + kk] : 0.0;
+                Us[w][kk][j] = ok ? Up[w * Uv.ldp + (bj + j) * Uv.ld + k0 + kk] : 0.0;
         }
         __syncthreads();
         for (int kk = 0; kk < kc; ++kk) {
@@ -795,7 +805,7 @@ __global__ void __launch_bounds__(UPD_THREADS)
             if (i < m && j < nc) {
 #pragma unroll
                 for (int w = 0; w < K; ++w)
-                    A[w * ldp + (c0 + j) * lda + r0 + i] = acc[a][b][w];
+                    Cp[w * ldpc + j * ldc + i] = acc[a][b][w];
             }
         }
 }
@@ -1020,16 +1030,18 @@ int getrf_run(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int
             return rc2;
         }
         const int ev = thin ? -1 : UpdateTimer::begin(st);
+        double *Cv = A + c0 * lda + r0;
+        const MwView Lv{A + j0 * lda + r0, lda, ldp}, Uv{A + c0 * lda + j0, lda, ldp};
         if (thin) {
             using C = UpdCfgThin<K>;
             dim3 grid((unsigned)ceil_div(m, C::BM), (unsigned)ceil_div(nc, C::BN));
-            hipLaunchKernelGGL((k_update<K, C::BM, C::BN, C::TM, C::TN, C::KB>), grid, dim3(UPD_THREADS), 0, st, A,
-                               lda, ldp, r0, c0, m, nc, j0, jb);
+            hipLaunchKernelGGL((k_update<K, C::BM, C::BN, C::TM, C::TN, C::KB>), grid, dim3(UPD_THREADS), 0, st, Cv,
+                               lda, ldp, Lv, Uv, m, nc, jb);
         } else {
             using C = UpdCfg<K>;
             dim3 grid((unsigned)ceil_div(m, C::BM), (unsigned)ceil_div(nc, C::BN));
-            hipLaunchKernelGGL((k_update<K, C::BM, C::BN, C::TM, C::TN, C::KB>), grid, dim3(UPD_THREADS), 0, st, A,
-                               lda, ldp, r0, c0, m, nc, j0, jb);
+            hipLaunchKernelGGL((k_update<K, C::BM, C::BN, C::TM, C::TN, C::KB>), grid, dim3(UPD_THREADS), 0, st, Cv,
+                               lda, ldp, Lv, Uv, m, nc, jb);
         }
         BNC_LAUNCH_CHECK();
         UpdateTimer::end(ev, st, (double)m * (double)nc * (double)jb * fms_flops(K));
@@ -1089,6 +1101,31 @@ int getrf_run(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int
     BNC_LAUNCH_CHECK();
     return BNC_OK;
 }
+
+// C <- C - A B on K-plane matrices (A m x k, B k x n, C m x n), one launch
+// of the trailing-update kernel with its big tile; every entry of C sees
+// its k multiply-subtracts in increasing k.
+template <int K>
+int gemm_run(int64_t m, int64_t n, int64_t k, const double *A, int64_t lda, int64_t ldpa, const double *B,
+             int64_t ldb, int64_t ldpb, double *C, int64_t ldc, int64_t ldpc, hipStream_t s)
+{
+    if (m == 0 || n == 0 || k == 0)
+        return BNC_OK;
+    using Cf = UpdCfg<K>;
+    const dim3 grid((unsigned)ceil_div(m, Cf::BM), (unsigned)ceil_div(n, Cf::BN));
+    const MwView Lv{A, lda, ldpa}, Uv{B, ldb, ldpb};
+    hipLaunchKernelGGL((k_update<K, Cf::BM, Cf::BN, Cf::TM, Cf::TN, Cf::KB>), grid, dim3(UPD_THREADS), 0, s, C, ldc,
+                       ldpc, Lv, Uv, m, n, (int)k);
+    BNC_LAUNCH_CHECK();
+    return BNC_OK;
+}
+#define GEMM_INST(K)                                                                                               \
+    template int gemm_run<K>(int64_t, int64_t, int64_t, const double *, int64_t, int64_t, const double *, int64_t, \
+                             int64_t, double *, int64_t, int64_t, hipStream_t);
+GEMM_INST(1)
+GEMM_INST(2)
+GEMM_INST(3)
+GEMM_INST(4)
 
 template int getrf_run<1>(int64_t, double *, int64_t, int64_t, int64_t *, int64_t *, void *, hipStream_t, int,
                             double *);

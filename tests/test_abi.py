@@ -70,6 +70,17 @@ def test_slice_width_agrees_with_the_oracle():
     assert P.lib().bnc_oz_beta(2, 13) == -1
 
 
+def test_gemm_rejects_bad_arguments_before_touching_the_device():
+    import paper_2107_12550_amd as P
+    L = P.lib()
+    assert L.bnc_gemm_td(-1, 1, 1, None, 1, 1, None, 1, 1, None, 1, 1, None) == -1
+    assert L.bnc_gemm_td(4, 4, 4, None, 4, 16, None, 4, 16, None, 4, 16, None) == -4
+    assert L.bnc_gemm_td(4, 4, 4, 8, 3, 16, 8, 4, 16, 8, 4, 16, None) == -5
+    assert L.bnc_gemm_td(4, 4, 4, 8, 4, 15, 8, 4, 16, 8, 4, 16, None) == -6
+    assert L.bnc_gemm_qd(4, 4, 4, 8, 4, 16, 8, 4, 16, 8, 4, 15, None) == -12
+    assert L.bnc_gemm_d(3, 2, 0, None, 3, 0, None, 1, 2, 8, 3, 6, None) == 0  # k = 0: nothing to do
+
+
 def test_struct_layouts_match_the_header(tmp_path):
     """The binding's ctypes structs have the C layout of include/bnc.h
     (sizes and field offsets as gcc lays them out)."""
