@@ -97,7 +97,8 @@ def _exact_matmul(n: int):
     return lambda a, b: a @ b.T
 
 
-def randsvd_words(n: int, cond: float, g: np.random.Generator, bits: int = 150) -> np.ndarray:
+def randsvd_words(n: int, cond: float, g: np.random.Generator, bits: int = 150, symmetric: bool = False,
+                  sigma: np.ndarray | None = None) -> np.ndarray:
     """U diag(sigma) V^T for matrices too ill-conditioned for binary64 entries
     (rounding each entry to 53 bits would perturb A by about 1e-16 ||A|| and
     cap its condition number near 1e17): the same U, V, sigma as ``randsvd``,
@@ -113,11 +114,14 @@ def randsvd_words(n: int, cond: float, g: np.random.Generator, bits: int = 150) 
     W_p V_q^T is exact in binary64 (2 (beta + 1) + log2 n <= 53 bits), the
     pairs above the target are summed, each entry rounded to the row grid
     and accumulated exactly in 50-bit integer limbs, then written back as a
-    non-overlapping binary64 expansion."""
+    non-overlapping binary64 expansion.  ``symmetric`` takes V = U
+    (A = U diag(sigma) U^T, the paper's R D R^-1 with an orthogonal R);
+    ``sigma`` replaces the geometric singular values."""
     U = haar(n, g)
-    V = haar(n, g)
+    V = U if symmetric else haar(n, g)
     i = np.arange(n, dtype=np.float64)
-    sigma = cond ** (-i / max(n - 1, 1))
+    if sigma is None:
+        sigma = cond ** (-i / max(n - 1, 1))
     Whi, Wlo = _prod_exact(U, sigma[None, :])
     lg = max(1, math.ceil(math.log2(max(n, 2))))
     beta = (53 - lg) // 2 - 1
@@ -214,6 +218,53 @@ def rhs_ones(Ap: np.ndarray) -> tuple[np.ndarray, bool]:
         if math.fsum(terms + [-v for v in ws]) != 0.0:
             exact = False
     return b, exact
+
+
+def paper_sigma(n: int) -> np.ndarray:
+    """The paper's diagonal (Sec. 3): d_i = 10^(-26 (i-1)/n), i = 1..n, so
+    that kappa_2(A) = 10^(26 (n-1)/n) for A = R D R^-1 with R orthogonal."""
+    return 10.0 ** (-26.0 * np.arange(n, dtype=np.float64) / n)
+
+
+def rhs_int(Ap: np.ndarray, xs: np.ndarray) -> tuple[np.ndarray, bool]:
+    """b = A xs for integer xs (|xs| < 2^11), rounded greedily to 4 binary64
+    words as in ``rhs_ones``: every word of A is cut into its top 42 bits and
+    the rest (at most 11 bits), so both products with xs_j are exact binary64
+    numbers and ``math.fsum`` sums them exactly.  ``exact`` as in
+    ``rhs_ones``."""
+    aw, n, _ = Ap.shape
+    xs = np.asarray(xs, dtype=np.float64)
+    assert np.all(xs == np.rint(xs)) and np.all(np.abs(xs) < 2.0 ** 11)
+    m, e = np.frexp(Ap)
+    hi = np.ldexp(np.trunc(np.ldexp(m, 42)), e - 42)
+    lo = Ap - hi
+    # word w of A(i, j) is Ap[w, j, i]
+    terms = np.concatenate([(hi * xs[None, :, None]).transpose(2, 0, 1).reshape(n, aw * n),
+                            (lo * xs[None, :, None]).transpose(2, 0, 1).reshape(n, aw * n)], axis=1)
+    b = np.zeros((4, n))
+    exact = True
+    for i in range(n):
+        tl = terms[i].tolist()
+        ws = []
+        for _ in range(4):
+            ws.append(math.fsum(tl + [-v for v in ws]))
+        b[:, i] = ws
+        if math.fsum(tl + [-v for v in ws]) != 0.0:
+            exact = False
+    return b, exact
+
+
+def paper_problem(n: int, instance: int = 0, config: int = 7) -> tuple[np.ndarray, np.ndarray, bool, np.ndarray]:
+    """The paper's test system (Sec. 3): A = R D R^-1 with d_i = 10^(-26 (i-1)/n)
+    and, here, R a Haar-orthogonal matrix (R^-1 = R^T; the paper does not
+    publish its R), entries kept as quad-double words; true solution
+    x = [0, 1, ..., n-1], b = A x exact in quad-double.  Returns
+    (A planes (4, n, n), b (4, n), exact, x)."""
+    g = rng(config, instance)
+    Ap = randsvd_words(n, 0.0, g, symmetric=True, sigma=paper_sigma(n))
+    xs = np.arange(n, dtype=np.float64)
+    b, exact = rhs_int(Ap, xs)
+    return Ap, b, exact, xs
 
 
 def _batch_one(args):

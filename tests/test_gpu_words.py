@@ -39,3 +39,21 @@ def test_refine_word_entries_bitexact(P, K, oz, n, cond):
     if ref["status"] == O.CONVERGED:
         x = ref["x"]
         assert float(np.max(np.abs((x[0] - 1.0) + x[1] + x[2] + x[3]))) <= 1e-60
+
+
+@pytest.mark.parametrize("K,oz", [(2, 0), (3, 0), (3, 5)])
+def test_paper_system_bitexact(P, K, oz):
+    """The paper's test system (Sec. 3: A = R D R^-1, d_i = 10^(-26 (i-1)/n),
+    x = [0..n-1]) at n = 100 (two panels and a ragged one): the refined
+    solution, status and correction count equal the oracle's bit for bit, and
+    the solution is x to quad-double accuracy."""
+    Ap, b, exact, xs = synth.paper_problem(100, instance=3)
+    assert exact
+    say("paper system K", K, "oz", oz)
+    ref = O.refine(Ap, b, K, ozaki=oz)
+    out = P.refine(dev(Ap), dev(b), K, ozaki=oz)
+    assert out["status"] == ref["status"] == O.CONVERGED and out["iters"] == ref["iters"]
+    x = host(out["x"])
+    np.testing.assert_array_equal(x, ref["x"])
+    err = np.abs((x[0] - xs) + x[1:].sum(axis=0)) / np.maximum(xs, 1.0)
+    assert err.max() < 1e-60

@@ -56,3 +56,29 @@ def test_randsvd_words_keeps_the_condition_number():
     smin = min(abs(v) for v in s)
     smax = max(abs(v) for v in s)
     assert 0.5e30 < smax / smin < 2e30
+
+
+def test_paper_problem_condition_number_and_exact_rhs():
+    """The paper's system (Sec. 3): A = R D R^-1 with d_i = 10^(-26 (i-1)/n)
+    has kappa_2(A) = 10^(26 (n-1)/n) (R orthogonal here), and b = A x for
+    x = [0, 1, ..., n-1] holds exactly in the four words of b; A is
+    symmetric up to its entries' row grids (~2^-150 of the row scale)."""
+    import mpmath
+    n = 24
+    Ap, b, exact, xs = synth.paper_problem(n, instance=1)
+    assert exact
+    np.testing.assert_array_equal(xs, np.arange(n))
+    for i in range(n):
+        s = sum((Fraction(float(Ap[w, j, i])) * int(xs[j]) for w in range(4) for j in range(n)), Fraction(0))
+        assert s == sum((Fraction(float(v)) for v in b[:, i]), Fraction(0))
+    mpmath.mp.prec = 400
+    M = mpmath.matrix(n, n)
+    for i in range(n):
+        for j in range(n):
+            M[i, j] = sum(mpmath.mpf(float(Ap[w, j, i])) for w in range(4))
+    amax = max(abs(M[i, j]) for i in range(n) for j in range(n))
+    assert max(abs(M[i, j] - M[j, i]) for i in range(n) for j in range(n)) <= amax * mpmath.mpf(2) ** -140
+    s = mpmath.svd_r(M, compute_uv=False)
+    ratio = max(abs(v) for v in s) / min(abs(v) for v in s)
+    want = mpmath.mpf(10) ** (mpmath.mpf(26) * (n - 1) / n)
+    assert abs(ratio / want - 1) < 0.01
