@@ -63,3 +63,36 @@ def test_gemm_large_sampled(P):
         i, j = int(g.integers(m)), int(g.integers(n))
         want = O.gemm(K, A[:, :, i:i + 1], B[:, j:j + 1, :], C[:, j:j + 1, i:i + 1])
         np.testing.assert_array_equal(got[:, j, i], want[:, 0, 0], err_msg=f"entry ({i}, {j})")
+
+
+@pytest.mark.parametrize("K", [2, 3])
+def test_gemm_padded_strides_through_the_abi(P, K):
+    """Leading dimensions and plane strides larger than the matrices (views
+    into bigger K-plane buffers), called through the C-ABI directly: the
+    padding is left untouched and the product equals the oracle's."""
+    import ctypes
+    import torch
+    m, n, k = 45, 37, 70
+    lda, ldb, ldc = 53, 81, 64
+    ldpa, ldpb, ldpc = lda * k + 11, ldb * n + 5, ldc * n + 7
+    g = np.random.default_rng(77 + K)
+    A, B, C = words(g, K, k, m), words(g, K, n, k), words(g, K, n, m)
+    want = O.gemm(K, A, B, C)
+
+    def pad(X, ld, ldp, fill):
+        rows, cols = X.shape[2], X.shape[1]
+        buf = np.full(K * ldp, fill)
+        for w in range(K):
+            for c in range(cols):
+                buf[w * ldp + c * ld: w * ldp + c * ld + rows] = X[w, c]
+        return buf
+
+    bA, bB, bC = pad(A, lda, ldpa, 7.0), pad(B, ldb, ldpb, 9.0), pad(C, ldc, ldpc, -3.0)
+    dA, dB, dC = (torch.from_numpy(x).cuda() for x in (bA, bB, bC))
+    f = getattr(P.lib(), {2: "bnc_gemm_dd", 3: "bnc_gemm_td"}[K])
+    vp = lambda t: ctypes.c_void_p(t.data_ptr())  # noqa: E731
+    say("gemm padded K", K)
+    assert f(m, n, k, vp(dA), lda, ldpa, vp(dB), ldb, ldpb, vp(dC), ldc, ldpc, None) == 0
+    got = host(dC)
+    exp = pad(want, ldc, ldpc, -3.0)
+    np.testing.assert_array_equal(got, exp)
