@@ -53,22 +53,47 @@ __device__ __forceinline__ void resid_slice(const double *__restrict__ A, int64_
         sig[q] = q < nb ? 1.5 * pow2(an.e0 - RB_W * q + 52) : 0.0;
     }
     const double lim0 = pow2(an.e0 + 51);
-    for (int64_t j = q0; j < q1; ++j) {
-        double xv[4];
+    // column j's words of x and of A are loaded one column ahead, two
+    // register sets taking turns (the loads are unconditional, the next
+    // index clamped to the slice), so the deposits of one column run while
+    // the next column's loads are in flight
+    auto load = [&](int64_t j, double (&xv)[4], double (&av)[AW]) {
 #pragma unroll
         for (int w = 0; w < 4; ++w)
             xv[w] = x[w * ldx + j];
 #pragma unroll
-        for (int u = 0; u < AW; ++u) {
-            const double a = A[u * ldpa + j * lda + i];
+        for (int u = 0; u < AW; ++u)
+            av[u] = A[u * ldpa + j * lda + i];
+    };
+    auto col = [&](const double (&xv)[4], const double (&av)[AW]) {
+#pragma unroll
+        for (int u = 0; u < AW; ++u)
 #pragma unroll
             for (int w = 0; w < 4; ++w) {
                 double lo;
-                const double hi = two_prod(a, xv[w], lo);
+                const double hi = two_prod(av[u], xv[w], lo);
                 deposit(-hi, sig, bins, nb, lim0, bad);
                 deposit(-lo, sig, bins, nb, lim0, bad);
             }
+    };
+    int64_t j = q0;
+    if (NB > 16) {  // the rare wide windows: plain loop (their bins already fill the registers)
+        for (; j < q1; ++j) {
+            double xv[4], av[AW];
+            load(j, xv, av);
+            col(xv, av);
         }
+    } else if (j < q1) {
+        double x0[4], a0[AW], x1[4], a1[AW];
+        load(j, x0, a0);
+        for (; j + 1 < q1; j += 2) {
+            load(j + 1, x1, a1);
+            col(x0, a0);
+            load(j + 2 < q1 ? j + 2 : q1 - 1, x0, a0);
+            col(x1, a1);
+        }
+        if (j < q1)  // odd count: x0, a0 hold column q1 - 1
+            col(x0, a0);
     }
     if (with_b) {
 #pragma unroll
