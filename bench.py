@@ -40,6 +40,9 @@ FMS_INSTS = {1: 1, 2: 26, 3: 72, 4: 152}
 # (form, factor words, n, slices).
 MEASURED_TRAFFIC = {("ozaki", 3, 4096, 5): 4.270e8, ("plain", 3, 4096, 0): 3.598e8,
                     ("ozaki", 2, 4096, 5): 3.261e8, ("plain", 2, 4096, 0): 2.467e8}
+# HBM bytes per multi-word GEMM launch at m = n = k = 4096 (bench.py --mode gemm), the same two counter
+# passes and copy scaling: profiles/counters_gemm_n4096.md.  Valid for that kernel and size only.
+MEASURED_GEMM_TRAFFIC = {(2, 4096): 7.508e9, (3, 4096): 2.274e10}
 DEFAULT_SLICES = {1: 3, 2: 5, 3: 5, 4: 11}  # split form: measured fastest to QD accuracy (DD, TD: 5)
 WORD_NAME = {1: "FP64", 2: "DD", 3: "TD", 4: "QD"}
 
@@ -206,7 +209,7 @@ def gemm_main(args):
                          "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                          "frac": achieved / FP64_PEAK_TFLOPS,
                          "issue_frac": achieved * FMS_INSTS[K] / FMS_FLOPS[K] / (FP64_PEAK_TFLOPS / 2),
-                         "traffic": None}}
+                         "traffic": MEASURED_GEMM_TRAFFIC.get((K, n)), "traffic_unit": "bytes per launch"}}
         log(f"[bench] gemm {WORD_NAME[K]} n={n}: {ms:.2f} ms per launch, {forms[WORD_NAME[K]]['gflops_eq']:.0f} "
             f"GFLOPS-eq")
         del A, B, C, C0
@@ -461,14 +464,26 @@ def main():
     ap.add_argument("--slots", type=int, default=0, help="batch mode: persistent workgroups (0 = auto)")
     ap.add_argument("--tune", action="store_true", help="batch mode: tune the launch variants now")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
-                    help="single mode: first run one plain device copy of this many MiB (the reference "
-                         "kernel that scales hardware byte counters)")
+                    help="first run one plain device copy of this many MiB (the reference kernel that "
+                         "scales hardware byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: the solver has no multi-GPU path "
               "(independent systems would simply be split across GPUs)", file=sys.stderr)
         sys.exit(2)
+    if args.calib_copy_mib > 0:
+        # one plain device copy first: the reference kernel that scales the
+        # hardware byte counters of the kernels measured after it
+        import torch
+        words = args.calib_copy_mib * (1 << 20) // 8
+        src = torch.ones(words, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy: {args.calib_copy_mib} MiB read, {args.calib_copy_mib} MiB written")
+        del src, dst
     if args.mode == "batch":
         return batch_main(args)
     if args.mode == "sweep":
@@ -492,15 +507,6 @@ def main():
     # the split factor's accuracy must beat the condition number: more slices
     # above 1e15 (measured at 1e25: 5 slices need 11 corrections, 7 need 4)
     oz = args.ozaki if args.ozaki >= 0 else DEFAULT_SLICES[K] + (2 if args.cond > 1e15 else 0)
-    if args.calib_copy_mib > 0:
-        words = args.calib_copy_mib * (1 << 20) // 8
-        src = torch.ones(words, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        log(f"[bench] calibration copy: {args.calib_copy_mib} MiB read, {args.calib_copy_mib} MiB written")
-        del src, dst
     # above 1e15 binary64 entries cannot carry the condition number: the
     # matrix is stored in quad-double words instead
     kind = "randsvd" if args.cond <= 1e15 else "randsvd_words"
