@@ -149,3 +149,94 @@ def test_key_order_is_magnitude_order_on_canonical(K):
     gt = O.key_gt(K, a, b)
     for i in range(n):
         assert gt[i] == (abs(value(a[:, i])) > abs(value(b[:, i])))
+
+
+def _spread_words(g, m, n, gap):
+    """m-word values whose words are random binary64 numbers `gap` bits
+    apart (gap < 53: overlapping words, not canonical)."""
+    out = np.zeros((m, n))
+    for i in range(n):
+        e = int(g.integers(-20, 21))
+        for w in range(m):
+            out[w, i] = np.ldexp(g.uniform(-1, 1), e - gap * w)
+    return out
+
+
+@pytest.mark.parametrize("m", [2, 3, 4])
+def test_round_words_canonical_input_is_greedy_rounding(m):
+    """Long -> short conversion of Listing 1 (the K-word copies of A, b and
+    every residual): m canonical words rounded to K < m words equal the
+    canonical K-word rounding of their exact value (w0 = RN(v), w1 = RN(v -
+    w0), ...), bit for bit.  Dropping, mis-signing or double-rounding any
+    folded word breaks this."""
+    g = np.random.default_rng(600 + m)
+    src = rand_words(g, m, 1500, spread=30)
+    for K in range(1, m):
+        out = O.round_words(K, src)
+        for i in range(src.shape[1]):
+            assert list(out[:, i]) == canon(value(src[:, i]), K), (m, K, i)
+
+
+@pytest.mark.parametrize("m", [3, 4])
+@pytest.mark.parametrize("gap", [30, 45, 53, 60])
+def test_round_words_general_input_bound(m, gap):
+    """Non-canonical m-word inputs (overlapping words, or the last two words
+    nearly cancelling): the K-word result is within 2^(-53K) |v| of the
+    exact value v for every K < m, and K = m keeps the value exactly."""
+    g = np.random.default_rng(700 + 10 * m + gap)
+    src = _spread_words(g, m, 1200, gap)
+    src[m - 1, ::3] = -src[m - 2, ::3] * (1 - 2.0 ** -30)   # trailing words cancel
+    u = {K: Fraction(2) ** (-53 * K) for K in range(1, 5)}
+    for K in range(1, m + 1):
+        out = O.round_words(K, src)
+        for i in range(src.shape[1]):
+            v = value(src[:, i])
+            if K == m:
+                assert value(out[:, i]) == v
+            else:
+                assert abs(value(out[:, i]) - v) <= u[K] * abs(v), (m, K, gap, i)
+
+
+def test_round_words_widening_is_exact():
+    """Short -> long (K >= m): the value is kept and the extra words are 0."""
+    g = np.random.default_rng(800)
+    src = rand_words(g, 2, 500)
+    out = O.round_words(4, src)
+    np.testing.assert_array_equal(out[2:], 0.0)
+    for i in range(src.shape[1]):
+        assert value(out[:, i]) == value(src[:, i])
+
+
+def _exact_sqrt_sum_sq(v):
+    """sqrt(sum v_i^2) of binary64 values to about 120 bits, from the exact
+    rational sum of squares (integer square root of the scaled sum)."""
+    import math
+    s = sum((Fraction(float(x)) ** 2 for x in v), Fraction(0))
+    if s == 0:
+        return Fraction(0)
+    # s = p / q; sqrt(s) ~ isqrt(p * q * 4^t) / (q * 2^t)
+    t = 130
+    return Fraction(math.isqrt(s.numerator * s.denominator * 4 ** t), s.denominator * 2 ** t)
+
+
+def test_norm2_against_exact():
+    """The 2-norm of Listing 1's stopping test (||r||_2, ||x||_2, ||A||_F of
+    leading words): the squares of the scaled entries are rounded once each,
+    summed with correct rounding and square-rooted once, so the result is
+    within 2 ulp (2^-51 relative) of the exact norm, also for entries near
+    the overflow and underflow thresholds."""
+    g = np.random.default_rng(900)
+    cases = [np.array([3.0, 4.0]), np.array([0.0, -0.0]), np.array([-7.5]), np.array([1e300, 1e300]),
+             np.array([1e-300, 3e-310, -2e-300]), np.array([2.0 ** 600, -(2.0 ** 601)])]
+    for n in (1, 2, 17, 256, 4096):
+        cases.append(g.uniform(-1, 1, size=n) * 2.0 ** int(g.integers(-900, 900)))
+        cases.append(adversarial_doubles(g, n))
+    for v in cases:
+        got = O.norm2(v)
+        ref = _exact_sqrt_sum_sq(v)
+        if ref == 0:
+            assert got == 0.0
+            continue
+        assert abs(Fraction(got) - ref) <= Fraction(2) ** -51 * ref, (v[:4], got, float(ref))
+    assert O.norm2(np.array([3.0, 4.0])) == 5.0
+    assert O.norm2(np.array([-7.5])) == 7.5
