@@ -24,7 +24,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mwla.c")
 _LIB = os.path.join(_HERE, "libmwla_oracle.so")
-GCC_FLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-shared", "-fPIC"]
+GCC_FLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-shared", "-fPIC"]
 
 # refinement status codes (same numbering as the product's C-ABI)
 CONVERGED, MAX_ITER, SINGULAR, NONFINITE, STAGNATED = 0, 1, 2, 3, 5
@@ -75,8 +75,22 @@ def lib() -> ctypes.CDLL:
         L.orc_oz_update.restype = ctypes.c_int
         L.orc_getrf_ozaki.argtypes = [ctypes.c_int, I64, P, I64, I64, ctypes.POINTER(I64), I64, ctypes.c_int]
         L.orc_getrf_ozaki.restype = I64
+        L.orc_set_threads.argtypes = [ctypes.c_int]
+        L.orc_set_threads.restype = ctypes.c_int
+        L.orc_get_threads.restype = ctypes.c_int
         _lib = L
     return _lib
+
+
+def set_threads(n: int) -> int:
+    """Threads the oracle's loops over independent columns and rows use
+    (n < 1: the OpenMP default); returns the number in effect.  Results do
+    not depend on it."""
+    return int(lib().orc_set_threads(int(n)))
+
+
+def threads() -> int:
+    return int(lib().orc_get_threads())
 
 
 def _p(a: np.ndarray):

@@ -25,16 +25,34 @@
  * word w of every entry, column-major with leading dimension lda, and the
  * planes are ldp doubles apart.  Word 0 is the leading word.
  *
- * Build: gcc -O2 -ffp-contract=off -fno-fast-math -shared -fPIC
+ * Build: gcc -O2 -ffp-contract=off -fno-fast-math -fopenmp -shared -fPIC
  * (no contraction: every rounding below happens exactly as written).
+ *
+ * Threads: the loops over independent columns (LU updates, substitution of
+ * U12, matrix products) and rows (residual) are shared out with OpenMP.
+ * Every entry still receives its operations in the order stated at each
+ * routine, so the results do not depend on the number of threads
+ * (orc_set_threads(1) gives the serial program).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
 #define KMAX 4
 #define LVMAX 32
+
+/* Number of OpenMP threads the loops below use (n < 1: the runtime's
+ * default); returns the number in effect. */
+int orc_set_threads(int n)
+{
+    if (n >= 1)
+        omp_set_num_threads(n);
+    return omp_get_max_threads();
+}
+
+int orc_get_threads(void) { return omp_get_max_threads(); }
 
 /* ---------------------------------------------------------------------- */
 /* Error-free transformations                                              */
@@ -270,6 +288,7 @@ void orc_fms_vec(int K, int64_t n, const double *c, const double *a, const doubl
 void orc_gemm(int K, int64_t m, int64_t n, int64_t k, const double *A, int64_t lda, int64_t ldpa, const double *B,
               int64_t ldb, int64_t ldpb, double *C, int64_t ldc, int64_t ldpc)
 {
+#pragma omp parallel for schedule(dynamic, 1)
     for (int64_t j = 0; j < n; ++j)
         for (int64_t i = 0; i < m; ++i) {
             double c[KMAX], a[KMAX], b[KMAX], o[KMAX];
@@ -380,7 +399,7 @@ static int is_zero(int K, const double *v)
 int64_t orc_getrf(int K, int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv)
 {
     int64_t info = 0;
-    double best[KMAX], v[KMAX], r[KMAX], u[KMAX], l[KMAX], o[KMAX];
+    double best[KMAX], v[KMAX], r[KMAX], o[KMAX];
     for (int64_t k = 0; k < n; ++k) {
         int64_t p = k;
         load(K, A, lda, ldp, k, k, best);
@@ -412,13 +431,15 @@ int64_t orc_getrf(int K, int64_t n, double *A, int64_t lda, int64_t ldp, int64_t
             mw_mul(K, v, r, o);
             store(K, A, lda, ldp, i, k, o);
         }
+#pragma omp parallel for schedule(static) if (n - k > 32)
         for (int64_t j = k + 1; j < n; ++j) {
+            double u[KMAX], l[KMAX], w[KMAX], q[KMAX];
             load(K, A, lda, ldp, k, j, u);
             for (int64_t i = k + 1; i < n; ++i) {
                 load(K, A, lda, ldp, i, k, l);
-                load(K, A, lda, ldp, i, j, v);
-                mw_fms(K, v, l, u, o);
-                store(K, A, lda, ldp, i, j, o);
+                load(K, A, lda, ldp, i, j, w);
+                mw_fms(K, w, l, u, q);
+                store(K, A, lda, ldp, i, j, q);
             }
         }
     }
@@ -602,9 +623,10 @@ int orc_oz_update(int K, int s, int64_t m, int64_t nc, int64_t kb, const double 
         return 0;
     double *Ls = malloc(sizeof(double) * (size_t)(s * m * (kb ? kb : 1)));
     double *Us = malloc(sizeof(double) * (size_t)(s * nc * (kb ? kb : 1)));
-    double v[KMAX], o[OZ_SMAX], c[KMAX], a[KMAX], t[KMAX];
     /* slices of the rows of L: Ls[(q*kb + k)*m + i] */
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < m; ++i) {
+        double v[KMAX], o[OZ_SMAX];
         int E = oz_scale(L + i, kb, ldl);
         for (int64_t k = 0; k < kb; ++k) {
             for (int w = 0; w < K; ++w)
@@ -615,7 +637,9 @@ int orc_oz_update(int K, int s, int64_t m, int64_t nc, int64_t kb, const double 
         }
     }
     /* slices of the columns of U: Us[(q*nc + j)*kb + k] */
+#pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < nc; ++j) {
+        double v[KMAX], o[OZ_SMAX];
         int F = oz_scale(U + j * ldu, kb, 1);
         for (int64_t k = 0; k < kb; ++k) {
             for (int w = 0; w < K; ++w)
@@ -625,8 +649,10 @@ int orc_oz_update(int K, int s, int64_t m, int64_t nc, int64_t kb, const double 
                 Us[(q * nc + j) * kb + k] = o[q];
         }
     }
+#pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < nc; ++j)
         for (int64_t i = 0; i < m; ++i) {
+            double c[KMAX], a[KMAX], t[KMAX];
             for (int w = 0; w < K; ++w)
                 c[w] = C[w * ldpc + j * ldc + i];
             for (int d = 0; d < s; ++d) {
@@ -663,7 +689,7 @@ int64_t orc_getrf_ozaki(int K, int64_t n, double *A, int64_t lda, int64_t ldp, i
     if (nb < 1 || nb > OZ_KBMAX || s < 1 || s > OZ_SMAX)
         return -2;
     int64_t info = 0;
-    double best[KMAX], v[KMAX], r[KMAX], u[KMAX], l[KMAX], o[KMAX];
+    double best[KMAX], v[KMAX], r[KMAX], o[KMAX];
     for (int64_t j0 = 0; j0 < n; j0 += nb) {
         int64_t jb = n - j0 < nb ? n - j0 : nb;
         int64_t je = j0 + jb;
@@ -697,26 +723,30 @@ int64_t orc_getrf_ozaki(int K, int64_t n, double *A, int64_t lda, int64_t ldp, i
                 mw_mul(K, v, r, o);
                 store(K, A, lda, ldp, i, k, o);
             }
+#pragma omp parallel for schedule(static) if (n - k > 32)
             for (int64_t j = k + 1; j < je; ++j) {
+                double u[KMAX], l[KMAX], w[KMAX], q[KMAX];
                 load(K, A, lda, ldp, k, j, u);
                 for (int64_t i = k + 1; i < n; ++i) {
                     load(K, A, lda, ldp, i, k, l);
-                    load(K, A, lda, ldp, i, j, v);
-                    mw_fms(K, v, l, u, o);
-                    store(K, A, lda, ldp, i, j, o);
+                    load(K, A, lda, ldp, i, j, w);
+                    mw_fms(K, w, l, u, q);
+                    store(K, A, lda, ldp, i, j, q);
                 }
             }
         }
         if (je >= n)
             break;
+#pragma omp parallel for schedule(static)
         for (int64_t j = je; j < n; ++j)
             for (int64_t k = j0; k < je; ++k) {
+                double u[KMAX], l[KMAX], w[KMAX], q[KMAX];
                 load(K, A, lda, ldp, k, j, u);
                 for (int64_t i = k + 1; i < je; ++i) {
                     load(K, A, lda, ldp, i, k, l);
-                    load(K, A, lda, ldp, i, j, v);
-                    mw_fms(K, v, l, u, o);
-                    store(K, A, lda, ldp, i, j, o);
+                    load(K, A, lda, ldp, i, j, w);
+                    mw_fms(K, w, l, u, q);
+                    store(K, A, lda, ldp, i, j, q);
                 }
             }
         orc_oz_update(K, s, n - je, n - je, jb, &AT(A, je, j0, 0), lda, ldp, &AT(A, j0, je, 0), lda, ldp,
@@ -898,8 +928,9 @@ int64_t orc_residual(int64_t n, int aw, const double *A, int64_t lda, int64_t ld
                      int64_t ldx, const double *b, int64_t ldb, double *r, int64_t ldr)
 {
     int64_t bad_rows = 0;
-    bigfix_t *acc = (bigfix_t *)malloc(sizeof(bigfix_t));
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : bad_rows)
     for (int64_t i = 0; i < n; ++i) {
+        bigfix_t *acc = (bigfix_t *)malloc(sizeof(bigfix_t));
         memset(acc, 0, sizeof(bigfix_t));
         for (int w = 0; w < 4; ++w)
             bf_add_double(acc, b[w * ldb + i], +1);
@@ -914,8 +945,8 @@ int64_t orc_residual(int64_t n, int aw, const double *A, int64_t lda, int64_t ld
             ++bad_rows;
         for (int w = 0; w < 4; ++w)
             r[w * ldr + i] = o[w];
+        free(acc);
     }
-    free(acc);
     return bad_rows;
 }
 
