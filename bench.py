@@ -273,12 +273,14 @@ def paper_main(args):
         LU0 = torch.zeros((K, n, n), dtype=torch.float64, device="cuda")
         LU0.copy_(dA[:K])
         LU = torch.empty_like(LU0)
+        wf = torch.empty(P.getrf_workspace_size(K, n), dtype=torch.uint8, device="cuda")
+        ws = torch.empty(P.getrs_workspace_size(K, n), dtype=torch.uint8, device="cuda")
 
         def direct():
             LU.copy_(LU0)
-            ipiv, info = P.getrf(K, LU)
+            ipiv, info = P.getrf(K, LU, work=wf)
             x = db[:K].clone()
-            P.getrs(K, LU, ipiv, x)
+            P.getrs(K, LU, ipiv, x, work=ws)
             return x
 
         ms_d, xd = timed(direct, args.steps)
@@ -397,17 +399,19 @@ def sweep_main(args):
                 LU0[:aw].copy_(dA[:aw])
                 LU = torch.empty_like(LU0)
                 state = {}
+                wf = torch.empty(P.getrf_workspace_size(K, n), dtype=torch.uint8, device="cuda")
+                ws = torch.empty(P.getrs_workspace_size(K, n), dtype=torch.uint8, device="cuda")
 
                 def fact():
                     LU.copy_(LU0)
-                    state["ipiv"], state["info"] = P.getrf(K, LU)
+                    state["ipiv"], state["info"] = P.getrf(K, LU, work=wf)
 
                 t_f = timed(fact)  # includes the copy of LU0 (a few us)
                 X = torch.empty((K, n), dtype=torch.float64, device="cuda")
 
                 def solve():
                     X.copy_(db[:K])
-                    P.getrs(K, LU, state["ipiv"], X)
+                    P.getrs(K, LU, state["ipiv"], X, work=ws)
 
                 t_s = timed(solve)
                 xq = torch.zeros((4, n), dtype=torch.float64, device="cuda")
@@ -544,15 +548,16 @@ def main():
         aw = min(K, dA.shape[0])
         LU0[:aw].copy_(dA[:aw])  # (the factor itself renormalises the words it is given)
         LU = torch.empty_like(LU0)
+        wf = torch.empty(P.getrf_workspace_size(K, n, slices), dtype=torch.uint8, device="cuda")
         times = []
         for i in range(3):
             LU.copy_(LU0)
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
             if slices:
-                P.getrf_ozaki(K, slices, LU)
+                P.getrf_ozaki(K, slices, LU, work=wf)
             else:
-                P.getrf(K, LU)
+                P.getrf(K, LU, work=wf)
             e1.record()
             torch.cuda.synchronize()
             times.append(e0.elapsed_time(e1))

@@ -17,7 +17,8 @@
  *    Word w of entry (i, j) is at A[w*ldp + j*lda + i].  A K-word vector of
  *    length n is K planes ldv >= n doubles apart.
  *  - Pointers are DEVICE pointers unless marked (host).  The caller owns
- *    every buffer; no call frees caller memory.
+ *    every buffer, workspaces included (sized by the *_workspace_size
+ *    queries); no call allocates or frees device memory.
  *  - stream: a hipStream_t passed as void* (NULL = the null stream).  Calls
  *    are asynchronous on that stream unless marked synchronous.
  *  - Return value: BNC_OK, -i when argument i (1-based) is invalid (nothing
@@ -29,8 +30,10 @@
  *    largest magnitude, magnitudes compared word by word after multiplying
  *    each word by the sign of the leading word.
  *  - Results are reproducible bit for bit: every operation order is fixed.
- *  - Limits: n <= 16384 for the factorisation; nothing here is thread-safe
- *    across concurrent calls that share the library scratch on one device.
+ *  - Limits: n <= 16384 for the factorisation.  The factorisations use one
+ *    side stream and four events per device, created on the first call and
+ *    released at process exit: factorisations (bnc_getrf_*, and those inside
+ *    bnc_refine) must not run concurrently on one device.
  */
 #ifndef BNC_H
 #define BNC_H
@@ -46,6 +49,9 @@ extern "C" {
 #define BNC_ERR_HIP (-100)         /* a HIP runtime or launch call failed */
 #define BNC_ERR_UNSUPPORTED (-101) /* size beyond the documented limits */
 #define BNC_ERR_WORKSPACE (-102)   /* workspace smaller than required */
+#define BNC_ERR_TIMEOUT (-103)     /* a bounded wait between workgroups gave up
+                                      (bnc_refine; the asynchronous calls
+                                      report it through their info) */
 
 /* Refinement outcome (bnc_refine_result.status). */
 #define BNC_CONVERGED 0 /* a stopping test passed */
@@ -71,15 +77,18 @@ extern "C" {
  *         on finite input; an entry holding the exchange's sentinel, the
  *         signalling NaN 0xFFF40000DEADBEEF, can cause it); the factors are
  *         then invalid
- * Uses library scratch on the current device (allocated on first use) and
- * the library's look-ahead stream and events of that device: calls that use
- * them (getrf, getrs, and the factorisations inside bnc_refine) must not run
- * concurrently on one device, from several host threads or streams.
+ *   work, work_bytes  caller workspace (device), at least
+ *         bnc_getrf_workspace_size(K, 0, n) bytes (NULL allowed for n = 0):
+ *         the panel exchange buffers; BNC_ERR_WORKSPACE if smaller
  */
-int bnc_getrf_d(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int64_t *info, void *stream);
-int bnc_getrf_dd(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int64_t *info, void *stream);
-int bnc_getrf_td(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int64_t *info, void *stream);
-int bnc_getrf_qd(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int64_t *info, void *stream);
+int bnc_getrf_d(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int64_t *info, void *work,
+                size_t work_bytes, void *stream);
+int bnc_getrf_dd(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int64_t *info, void *work,
+                 size_t work_bytes, void *stream);
+int bnc_getrf_td(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int64_t *info, void *work,
+                 size_t work_bytes, void *stream);
+int bnc_getrf_qd(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int64_t *info, void *work,
+                 size_t work_bytes, void *stream);
 
 /*
  * The same factorisation with the split form of the trailing update (not
@@ -99,11 +108,16 @@ int bnc_getrf_qd(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, 
  * the row and column scales stay above about 2^-700).
  *   factor_words  K in 1..4;  slices  1..12
  *   the remaining arguments as bnc_getrf_* (argument errors are numbered
- *   from n = 3)
- * Uses library scratch (2 * 12 * 64 * n doubles for the slices).
+ *   from n = 3); the workspace, bnc_getrf_workspace_size(K, slices, n)
+ *   bytes, also holds the slices (3 * 12 * 64 * n doubles).
  */
 int bnc_getrf_ozaki(int32_t factor_words, int32_t slices, int64_t n, double *A, int64_t lda, int64_t ldp,
-                    int64_t *ipiv, int64_t *info, void *stream);
+                    int64_t *ipiv, int64_t *info, void *work, size_t work_bytes, void *stream);
+
+/* Workspace bytes of bnc_getrf_* (slices = 0) and bnc_getrf_ozaki (slices
+ * 1..12) for K = factor_words and order n (host; 0 for n = 0 or arguments
+ * out of range). */
+size_t bnc_getrf_workspace_size(int32_t factor_words, int32_t slices, int64_t n);
 
 /*
  * Slice width of the split form: the widest slice (at most 26 bits) for
@@ -126,19 +140,26 @@ int bnc_oz_beta(int32_t factor_words, int32_t slices);
  *   LU, lda, ldp, ipiv   as returned by bnc_getrf_* with the same K
  *   B     K-plane n x nrhs matrix (leading dimension ldb, plane stride ldpb),
  *         overwritten by X
+ *   info  one int64 (device, may be NULL): 0, or -1 when a bounded wait of
+ *         the streamed substitutions gave up (a right-hand side holding the
+ *         signalling NaN 0xFFF40000DEADBEEF can cause it); X is then invalid
+ *   work, work_bytes  caller workspace, >= bnc_getrs_workspace_size(K, n)
+ *         bytes (NULL allowed when n or nrhs is 0)
  * An ipiv entry outside [k, n) is taken as no interchange.
- * A zero pivot yields Inf/NaN in X; check info first.  A right-hand side
- * holding the signalling NaN 0xFFF40000DEADBEEF can stall the substitutions'
- * bounded polls (the result is then invalid).
+ * A zero pivot yields Inf/NaN in X; check getrf's info first.
  */
 int bnc_getrs_d(int64_t n, int64_t nrhs, const double *LU, int64_t lda, int64_t ldp, const int64_t *ipiv,
-                double *B, int64_t ldb, int64_t ldpb, void *stream);
+                double *B, int64_t ldb, int64_t ldpb, int64_t *info, void *work, size_t work_bytes, void *stream);
 int bnc_getrs_dd(int64_t n, int64_t nrhs, const double *LU, int64_t lda, int64_t ldp, const int64_t *ipiv,
-                 double *B, int64_t ldb, int64_t ldpb, void *stream);
+                 double *B, int64_t ldb, int64_t ldpb, int64_t *info, void *work, size_t work_bytes, void *stream);
 int bnc_getrs_td(int64_t n, int64_t nrhs, const double *LU, int64_t lda, int64_t ldp, const int64_t *ipiv,
-                 double *B, int64_t ldb, int64_t ldpb, void *stream);
+                 double *B, int64_t ldb, int64_t ldpb, int64_t *info, void *work, size_t work_bytes, void *stream);
 int bnc_getrs_qd(int64_t n, int64_t nrhs, const double *LU, int64_t lda, int64_t ldp, const int64_t *ipiv,
-                 double *B, int64_t ldb, int64_t ldpb, void *stream);
+                 double *B, int64_t ldb, int64_t ldpb, int64_t *info, void *work, size_t work_bytes, void *stream);
+
+/* Workspace bytes of bnc_getrs_* for K = factor_words and order n (host;
+ * 0 for n = 0 or arguments out of range). */
+size_t bnc_getrs_workspace_size(int32_t factor_words, int64_t n);
 
 /*
  * Multi-word matrix multiply-subtract C <- C - A B (Kouya 2021, Sec. 2 and
@@ -235,7 +256,8 @@ size_t bnc_refine_workspace_size(int64_t n, int32_t factor_words);
  *   work, work_bytes  caller workspace, >= bnc_refine_workspace_size(n, K)
  *   opts     host options; result  host outcome
  * Synchronous: returns after the loop has finished (it reads the stopping
- * quantities back each iteration).
+ * quantities back each iteration).  BNC_ERR_TIMEOUT when a bounded wait of
+ * a factorisation or substitution gave up (x is then invalid).
  */
 int bnc_refine(int64_t n, int32_t a_words, const double *A, int64_t lda, int64_t ldpa, const double *b,
                int64_t ldpb, double *x, int64_t ldpx, void *work, size_t work_bytes, const bnc_refine_opts *opts,
@@ -382,11 +404,13 @@ int bnc_mlp_adam(float *params, const float *grads, float *m, float *v, const bn
  * planes (1 or 4); x, b, r are 4-plane vectors.  *inexact (device int32)
  * is set to 1 if a row had bits below its 476-bit accumulator window
  * (then the row is faithful, not exactly rounded); it is not cleared.
- * Uses library scratch.
+ * work, work_bytes: >= bnc_residual_workspace_size(n) bytes (row maxima and
+ * the partial bin sums).
  */
 int bnc_residual(int64_t n, int32_t a_words, const double *A, int64_t lda, int64_t ldpa, const double *x,
                  int64_t ldpx, const double *b, int64_t ldpb, double *r, int64_t ldpr, int32_t *inexact,
-                 void *stream);
+                 void *work, size_t work_bytes, void *stream);
+size_t bnc_residual_workspace_size(int64_t n);
 
 /*
  * Element-wise K-word primitive on word-major arrays (word w of element i at
@@ -415,6 +439,16 @@ int bnc_mw_apply(int32_t op, int32_t K, int64_t n, const double *c, const double
  */
 int bnc_profile_enable(int32_t on);
 int bnc_profile_read(double *ms, double *flops, int64_t *launches);
+
+/*
+ * Test hook for the timeout paths (not for production use): with bit 0 set,
+ * every factorisation raises its exchange's abort flag right after clearing
+ * it, so every panel poll gives up at once and the factorisation reports
+ * info = -1; with bit 1 set, every substitution does the same with its
+ * streamed values (getrs info = -1).  Every kernel still runs to its end,
+ * reading and writing only in-bounds memory.  0 turns it off.  Host-global.
+ */
+int bnc_test_force_timeout(int32_t bits);
 
 const char *bnc_status_string(int32_t status);
 const char *bnc_last_error(void);

@@ -9,6 +9,10 @@ device memory and the current stream.
 from .bnc import (  # noqa: F401
     BNC_BAD_SIZE,
     BNC_CONVERGED,
+    BNC_ERR_HIP,
+    BNC_ERR_TIMEOUT,
+    BNC_ERR_UNSUPPORTED,
+    BNC_ERR_WORKSPACE,
     BNC_MAX_ITER,
     BNC_NONFINITE,
     BNC_SINGULAR,
@@ -26,7 +30,9 @@ from .bnc import (  # noqa: F401
     gemm,
     getrf,
     getrf_ozaki,
+    getrf_workspace_size,
     getrs,
+    getrs_workspace_size,
     lib,
     lib_path,
     mw_apply,
@@ -36,5 +42,7 @@ from .bnc import (  # noqa: F401
     refine,
     refine_workspace_size,
     residual,
+    residual_workspace_size,
+    test_force_timeout,
     wall_clock_khz,
 )

@@ -17,12 +17,15 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 lib_path = os.path.join(_HERE, "libbnc.so")
 
 BNC_CONVERGED, BNC_MAX_ITER, BNC_SINGULAR, BNC_NONFINITE, BNC_BAD_SIZE, BNC_STAGNATED = 0, 1, 2, 3, 4, 5
+BNC_ERR_HIP, BNC_ERR_UNSUPPORTED, BNC_ERR_WORKSPACE, BNC_ERR_TIMEOUT = -100, -101, -102, -103
 OP_FMS, OP_MUL, OP_ADD, OP_RECIP, OP_ROUND4 = 0, 1, 2, 3, 4
 _SUFFIX = {1: "d", 2: "dd", 3: "td", 4: "qd"}
 
 
 class BncError(RuntimeError):
-    pass
+    def __init__(self, msg: str, code: int = 0):
+        super().__init__(msg)
+        self.code = code
 
 
 class RefineOpts(ctypes.Structure):
@@ -56,15 +59,24 @@ def _load() -> ctypes.CDLL:
         _b.build()
     L = ctypes.CDLL(lib_path)
     I64, VP, D, I32 = ctypes.c_int64, ctypes.c_void_p, ctypes.c_double, ctypes.c_int32
+    SZ = ctypes.c_size_t
     for s in _SUFFIX.values():
         f = getattr(L, f"bnc_getrf_{s}")
-        f.argtypes = [I64, VP, I64, I64, VP, VP, VP]
+        f.argtypes = [I64, VP, I64, I64, VP, VP, VP, SZ, VP]
         f.restype = ctypes.c_int
         g = getattr(L, f"bnc_getrs_{s}")
-        g.argtypes = [I64, I64, VP, I64, I64, VP, VP, I64, I64, VP]
+        g.argtypes = [I64, I64, VP, I64, I64, VP, VP, I64, I64, VP, VP, SZ, VP]
         g.restype = ctypes.c_int
-    L.bnc_getrf_ozaki.argtypes = [I32, I32, I64, VP, I64, I64, VP, VP, VP]
+    L.bnc_getrf_ozaki.argtypes = [I32, I32, I64, VP, I64, I64, VP, VP, VP, SZ, VP]
     L.bnc_getrf_ozaki.restype = ctypes.c_int
+    L.bnc_getrf_workspace_size.argtypes = [I32, I32, I64]
+    L.bnc_getrf_workspace_size.restype = SZ
+    L.bnc_getrs_workspace_size.argtypes = [I32, I64]
+    L.bnc_getrs_workspace_size.restype = SZ
+    L.bnc_residual_workspace_size.argtypes = [I64]
+    L.bnc_residual_workspace_size.restype = SZ
+    L.bnc_test_force_timeout.argtypes = [I32]
+    L.bnc_test_force_timeout.restype = ctypes.c_int
     for s in _SUFFIX.values():
         gm = getattr(L, f"bnc_gemm_{s}")
         gm.argtypes = [I64, I64, I64, VP, I64, I64, VP, I64, I64, VP, I64, I64, VP]
@@ -102,7 +114,7 @@ def _load() -> ctypes.CDLL:
     L.bnc_refine_batched_graph.restype = ctypes.c_int
     L.bnc_graph_destroy.argtypes = [VP]
     L.bnc_wall_clock_khz.restype = ctypes.c_int64
-    L.bnc_residual.argtypes = [I64, I32, VP, I64, I64, VP, I64, VP, I64, VP, I64, VP, VP]
+    L.bnc_residual.argtypes = [I64, I32, VP, I64, I64, VP, I64, VP, I64, VP, I64, VP, VP, SZ, VP]
     L.bnc_residual.restype = ctypes.c_int
     L.bnc_mw_apply.argtypes = [I32, I32, I64, VP, VP, VP, VP, VP]
     L.bnc_mw_apply.restype = ctypes.c_int
@@ -123,7 +135,7 @@ def lib() -> ctypes.CDLL:
 
 def _check(rc: int, what: str):
     if rc != 0:
-        raise BncError(f"{what}: code {rc}: {_lib.bnc_last_error().decode()}")
+        raise BncError(f"{what}: code {rc}: {_lib.bnc_last_error().decode()}", rc)
 
 
 def _stream():
@@ -136,29 +148,52 @@ def _dev(t: torch.Tensor, name: str, ndim: int):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def getrf(K: int, A: torch.Tensor):
+def _workspace(nbytes: int, device, work: torch.Tensor | None = None) -> torch.Tensor:
+    if work is not None and work.numel() >= nbytes:
+        return work
+    return torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)
+
+
+def getrf_workspace_size(K: int, n: int, slices: int = 0) -> int:
+    return int(_lib.bnc_getrf_workspace_size(K, slices, n))
+
+
+def getrs_workspace_size(K: int, n: int) -> int:
+    return int(_lib.bnc_getrs_workspace_size(K, n))
+
+
+def residual_workspace_size(n: int) -> int:
+    return int(_lib.bnc_residual_workspace_size(n))
+
+
+def getrf(K: int, A: torch.Tensor, work: torch.Tensor | None = None):
     """In-place P A = L U of a (K, n, n) tensor; returns (ipiv, info) tensors."""
     n = A.shape[1]
     ipiv = torch.empty(max(n, 1), dtype=torch.int64, device=A.device)
     info = torch.empty(1, dtype=torch.int64, device=A.device)
+    work = _workspace(getrf_workspace_size(K, n), A.device, work)
     f = getattr(_lib, f"bnc_getrf_{_SUFFIX[K]}")
     _check(f(n, _dev(A, "A", 3), n, n * n, ctypes.c_void_p(ipiv.data_ptr()), ctypes.c_void_p(info.data_ptr()),
-             _stream()), "getrf")
+             ctypes.c_void_p(work.data_ptr()), work.numel(), _stream()), "getrf")
     return ipiv[:n], info
 
 
-def getrf_ozaki(K: int, slices: int, A: torch.Tensor):
+def getrf_ozaki(K: int, slices: int, A: torch.Tensor, work: torch.Tensor | None = None):
     """bnc_getrf_ozaki: P A = L U with split trailing updates; returns (ipiv, info)."""
     n = A.shape[1]
     ipiv = torch.empty(max(n, 1), dtype=torch.int64, device=A.device)
     info = torch.empty(1, dtype=torch.int64, device=A.device)
+    work = _workspace(getrf_workspace_size(K, n, slices) if 1 <= slices <= 12 else 0, A.device, work)
     _check(_lib.bnc_getrf_ozaki(K, slices, n, _dev(A, "A", 3), n, n * n, ctypes.c_void_p(ipiv.data_ptr()),
-                                ctypes.c_void_p(info.data_ptr()), _stream()), "getrf_ozaki")
+                                ctypes.c_void_p(info.data_ptr()), ctypes.c_void_p(work.data_ptr()), work.numel(),
+                                _stream()), "getrf_ozaki")
     return ipiv[:n], info
 
 
-def getrs(K: int, LU: torch.Tensor, ipiv: torch.Tensor, B: torch.Tensor) -> torch.Tensor:
-    """Solve in place; B is (K, n) or (K, nrhs, n)."""
+def getrs(K: int, LU: torch.Tensor, ipiv: torch.Tensor, B: torch.Tensor, info: torch.Tensor | None = None,
+          work: torch.Tensor | None = None) -> torch.Tensor:
+    """Solve in place; B is (K, n) or (K, nrhs, n).  info (optional int64
+    device tensor) gets 0, or -1 if the substitutions' bounded waits gave up."""
     n = LU.shape[1]
     nrhs = 1 if B.dim() == 2 else B.shape[1]
     f = getattr(_lib, f"bnc_getrs_{_SUFFIX[K]}")
@@ -166,9 +201,18 @@ def getrs(K: int, LU: torch.Tensor, ipiv: torch.Tensor, B: torch.Tensor) -> torc
         raise BncError("B: expected a contiguous float64 CUDA tensor")
     if not (ipiv.is_cuda and ipiv.dtype == torch.int64 and ipiv.is_contiguous() and ipiv.numel() >= n):
         raise BncError("ipiv: expected a contiguous int64 CUDA tensor of n entries")
+    if info is not None and not (info.is_cuda and info.dtype == torch.int64):
+        raise BncError("info: expected an int64 CUDA tensor")
+    work = _workspace(getrs_workspace_size(K, n), LU.device, work)
     _check(f(n, nrhs, _dev(LU, "LU", 3), n, n * n, ctypes.c_void_p(ipiv.data_ptr()), ctypes.c_void_p(B.data_ptr()),
-             n, n * nrhs, _stream()), "getrs")
+             n, n * nrhs, None if info is None else ctypes.c_void_p(info.data_ptr()),
+             ctypes.c_void_p(work.data_ptr()), work.numel(), _stream()), "getrs")
     return B
+
+
+def test_force_timeout(bits: int):
+    """Timeout test hook of the library (bnc_test_force_timeout)."""
+    _check(_lib.bnc_test_force_timeout(bits), "test_force_timeout")
 
 
 def gemm(K: int, A: torch.Tensor, B: torch.Tensor, C: torch.Tensor) -> torch.Tensor:
@@ -299,9 +343,10 @@ def residual(A: torch.Tensor, x: torch.Tensor, b: torch.Tensor):
     aw, n = A.shape[0], A.shape[1]
     r = torch.empty((4, n), dtype=torch.float64, device=A.device)
     flag = torch.zeros(1, dtype=torch.int32, device=A.device)
+    work = _workspace(residual_workspace_size(n), A.device)
     _check(_lib.bnc_residual(n, aw, _dev(A, "A", 3), n, n * n, _dev(x, "x", 2), n, _dev(b, "b", 2), n,
-                             ctypes.c_void_p(r.data_ptr()), n, ctypes.c_void_p(flag.data_ptr()), _stream()),
-           "residual")
+                             ctypes.c_void_p(r.data_ptr()), n, ctypes.c_void_p(flag.data_ptr()),
+                             ctypes.c_void_p(work.data_ptr()), work.numel(), _stream()), "residual")
     return r, flag
 
 

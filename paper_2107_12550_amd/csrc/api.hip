@@ -1,6 +1,6 @@
 // C-ABI of the solver library (declarations and contracts in include/bnc.h):
-// argument checks, library scratch, launch-timing hooks and the element-wise
-// primitive kernels.
+// argument checks, workspace size queries, launch-timing hooks and the
+// element-wise primitive kernels.
 #include <math.h>
 #include <stdio.h>
 #include <string.h>
@@ -21,11 +21,12 @@ int getrf_run(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int
 size_t oz_slices_bytes(int64_t n);
 template <int K>
 int getrs_run(int64_t n, int64_t nrhs, const double *LU, int64_t lda, int64_t ldp, const int64_t *ipiv, double *B,
-              int64_t ldb, int64_t ldpb, void *scr, hipStream_t s);
+              int64_t ldb, int64_t ldpb, int64_t *info, void *scr, hipStream_t s);
+size_t getrf_workspace_bytes(int K, int64_t n, int oz);
 template <int K>
 int refine_run(int64_t n, int aw, const double *A, int64_t lda, int64_t ldpa, const double *b, int64_t ldpb, double *x,
                int64_t ldpx, void *work, const bnc_refine_opts *o, bnc_refine_result *res, hipStream_t s);
-size_t getrs_scratch_bytes(int K, int64_t n);
+size_t getrs_workspace_bytes(int K, int64_t n);
 template <int K>
 int batch_run(int64_t count, const int64_t *n, const double *const *A, const double *const *b, double *const *x,
               const int32_t *order, void *work, int slots, const bnc_refine_opts *o, bnc_batch_result *res,
@@ -47,15 +48,10 @@ int mlp_adam_run(float *P, const float *G, float *M, float *V, float lr, float b
                  hipStream_t s);
 
 size_t refine_workspace_bytes(int64_t n, int K);
-size_t residual_scratch_bytes(int64_t n);
-int residual_run(int64_t n, int aw, const double *A, int64_t lda, int64_t ldpa, const double *x, int64_t ldx,
-                 const double *b, int64_t ldb, const double *rowmax, const double *xmax, const void *ebounds,
-                 double *part, double *r, int64_t ldr, int32_t *inexact, hipStream_t s);
-int minexp_run(int64_t rows, int64_t cols, int64_t ld, int words, int64_t ldp, const double *v, int *out,
-               hipStream_t s);
-int fill_i32_run(int *p, int64_t n, int v, hipStream_t s);
-int rowmax_run(int64_t n, const double *A, int64_t lda, double *rowmax, hipStream_t s);
-int absmax_run(int64_t rows, int64_t cols, int64_t ld, const double *v, unsigned long long *bits, hipStream_t s);
+size_t residual_workspace_bytes(int64_t n);
+int residual_ws_run(int64_t n, int aw, const double *A, int64_t lda, int64_t ldpa, const double *x, int64_t ldpx,
+                    const double *b, int64_t ldpb, double *r, int64_t ldpr, int32_t *inexact, void *work,
+                    hipStream_t s);
 
 // ---- errors -------------------------------------------------------------------
 static thread_local std::string g_last_error;
@@ -74,38 +70,12 @@ int fail_arg(int code, const char *msg)
     return code;
 }
 
-// ---- library scratch ------------------------------------------------------------
+// ---- timeout test hook -------------------------------------------------------------
 namespace {
-constexpr int MAX_DEV = 16;
-struct Buf {
-    void *p = nullptr;
-    size_t bytes = 0;
-};
-Buf g_scratch[MAX_DEV][SCR_NSLOTS];
-std::mutex g_scratch_mu;
+int g_force_timeout = 0;
 }  // namespace
 
-void *scratch(int slot, size_t bytes)
-{
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEV)
-        return nullptr;
-    std::lock_guard<std::mutex> lk(g_scratch_mu);
-    Buf &b = g_scratch[dev][slot];
-    if (b.bytes < bytes) {
-        if (b.p) {
-            if (hipDeviceSynchronize() != hipSuccess || hipFree(b.p) != hipSuccess)
-                return nullptr;
-        }
-        b.p = nullptr;
-        b.bytes = 0;
-        const size_t want = bytes < (1u << 20) ? (1u << 20) : bytes;
-        if (hipMalloc(&b.p, want) != hipSuccess)
-            return nullptr;
-        b.bytes = want;
-    }
-    return b.p;
-}
+int force_timeout_bits() { return g_force_timeout; }
 
 // ---- trailing-update timing ------------------------------------------------------
 namespace {
@@ -127,7 +97,7 @@ int UpdateTimer::begin(hipStream_t s)
     Ev e{};
     if (hipEventCreate(&e.a) != hipSuccess || hipEventCreate(&e.b) != hipSuccess)
         return -1;
-    hipEventRecord(e.a, s);
+    (void)hipEventRecord(e.a, s);
     std::lock_guard<std::mutex> lk(g_prof_mu);
     g_events.push_back(e);
     return (int)g_events.size() - 1;
@@ -139,7 +109,7 @@ void UpdateTimer::end(int idx, hipStream_t s, double flops)
         return;
     std::lock_guard<std::mutex> lk(g_prof_mu);
     g_events[idx].flops = flops;
-    hipEventRecord(g_events[idx].b, s);
+    (void)hipEventRecord(g_events[idx].b, s);
 }
 
 // ---- element-wise primitives -------------------------------------------------------
@@ -182,8 +152,8 @@ using namespace bnc;
 static hipStream_t S(void *s) { return (hipStream_t)s; }
 
 template <int K>
-static int getrf_entry(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int64_t *info, void *stream,
-                       int oz = 0, int argoff = 0)
+static int getrf_entry(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int64_t *info, void *work,
+                       size_t work_bytes, void *stream, int oz = 0, int argoff = 0)
 {
     if (n < 0)
         return fail_arg(-(1 + argoff), "getrf: n < 0");
@@ -199,21 +169,18 @@ static int getrf_entry(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *
         return fail_arg(-(6 + argoff), "getrf: info is NULL");
     if (n > 16384)
         return fail_arg(BNC_ERR_UNSUPPORTED, "getrf: n > 16384");
-    void *scr = scratch(SCR_GETRF, getrf_scratch_bytes(K, n));
-    if (!scr)
-        return fail_arg(BNC_ERR_HIP, "getrf: scratch allocation failed");
-    double *ozb = nullptr;
-    if (oz) {
-        ozb = (double *)scratch(SCR_OZ, oz_slices_bytes(n));
-        if (!ozb)
-            return fail_arg(BNC_ERR_HIP, "getrf: scratch allocation failed");
-    }
-    return getrf_run<K>(n, A, lda, ldp, ipiv, info, scr, S(stream), oz, ozb);
+    if (n > 0 && !work)
+        return fail_arg(-(7 + argoff), "getrf: work is NULL");
+    if (work_bytes < getrf_workspace_bytes(K, n, oz))
+        return fail_arg(BNC_ERR_WORKSPACE, "getrf: workspace smaller than bnc_getrf_workspace_size");
+    double *ozb = oz && n > 0 ? (double *)((char *)work + align256(getrf_scratch_bytes(K, n))) : nullptr;
+    return getrf_run<K>(n, A, lda, ldp, ipiv, info, work, S(stream), oz, ozb);
 }
 
 template <int K>
 static int getrs_entry(int64_t n, int64_t nrhs, const double *LU, int64_t lda, int64_t ldp, const int64_t *ipiv,
-                       double *B, int64_t ldb, int64_t ldpb, void *stream)
+                       double *B, int64_t ldb, int64_t ldpb, int64_t *info, void *work, size_t work_bytes,
+                       void *stream)
 {
     if (n < 0)
         return fail_arg(-1, "getrs: n < 0");
@@ -235,10 +202,11 @@ static int getrs_entry(int64_t n, int64_t nrhs, const double *LU, int64_t lda, i
         return fail_arg(-9, "getrs: ldpb < ldb * nrhs");
     if (n > 16384)
         return fail_arg(BNC_ERR_UNSUPPORTED, "getrs: n > 16384");
-    void *scr = scratch(SCR_GETRS, getrs_scratch_bytes(K, n));
-    if (!scr)
-        return fail_arg(BNC_ERR_HIP, "getrs: scratch allocation failed");
-    return getrs_run<K>(n, nrhs, LU, lda, ldp, ipiv, B, ldb, ldpb, scr, S(stream));
+    if (n > 0 && nrhs > 0 && !work)
+        return fail_arg(-11, "getrs: work is NULL");
+    if (work_bytes < getrs_workspace_bytes(K, n))
+        return fail_arg(BNC_ERR_WORKSPACE, "getrs: workspace smaller than bnc_getrs_workspace_size");
+    return getrs_run<K>(n, nrhs, LU, lda, ldp, ipiv, B, ldb, ldpb, info, work, S(stream));
 }
 
 template <int K>
@@ -276,21 +244,25 @@ static int gemm_entry(int64_t m, int64_t n, int64_t k, const double *A, int64_t 
 
 extern "C" {
 
-int bnc_getrf_d(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int64_t *info, void *stream)
+int bnc_getrf_d(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int64_t *info, void *work,
+                size_t work_bytes, void *stream)
 {
-    return getrf_entry<1>(n, A, lda, ldp, ipiv, info, stream);
+    return getrf_entry<1>(n, A, lda, ldp, ipiv, info, work, work_bytes, stream);
 }
-int bnc_getrf_dd(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int64_t *info, void *stream)
+int bnc_getrf_dd(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int64_t *info, void *work,
+                 size_t work_bytes, void *stream)
 {
-    return getrf_entry<2>(n, A, lda, ldp, ipiv, info, stream);
+    return getrf_entry<2>(n, A, lda, ldp, ipiv, info, work, work_bytes, stream);
 }
-int bnc_getrf_td(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int64_t *info, void *stream)
+int bnc_getrf_td(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int64_t *info, void *work,
+                 size_t work_bytes, void *stream)
 {
-    return getrf_entry<3>(n, A, lda, ldp, ipiv, info, stream);
+    return getrf_entry<3>(n, A, lda, ldp, ipiv, info, work, work_bytes, stream);
 }
-int bnc_getrf_qd(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int64_t *info, void *stream)
+int bnc_getrf_qd(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int64_t *info, void *work,
+                 size_t work_bytes, void *stream)
 {
-    return getrf_entry<4>(n, A, lda, ldp, ipiv, info, stream);
+    return getrf_entry<4>(n, A, lda, ldp, ipiv, info, work, work_bytes, stream);
 }
 
 int bnc_gemm_d(int64_t m, int64_t n, int64_t k, const double *A, int64_t lda, int64_t ldpa, const double *B,
@@ -321,8 +293,37 @@ int bnc_oz_beta(int32_t factor_words, int32_t slices)
     return oz_beta(factor_words, slices);
 }
 
+size_t bnc_getrf_workspace_size(int32_t factor_words, int32_t slices, int64_t n)
+{
+    if (factor_words < 1 || factor_words > 4 || slices < 0 || slices > OZ_SMAX || n < 0 || n > 16384)
+        return 0;
+    return getrf_workspace_bytes(factor_words, n, slices);
+}
+
+size_t bnc_getrs_workspace_size(int32_t factor_words, int64_t n)
+{
+    if (factor_words < 1 || factor_words > 4 || n < 0 || n > 16384)
+        return 0;
+    return getrs_workspace_bytes(factor_words, n);
+}
+
+size_t bnc_residual_workspace_size(int64_t n)
+{
+    if (n < 0)
+        return 0;
+    return residual_workspace_bytes(n);
+}
+
+int bnc_test_force_timeout(int32_t bits)
+{
+    if (bits < 0 || bits > 3)
+        return fail_arg(-1, "test_force_timeout: bits outside 0..3");
+    g_force_timeout = bits;
+    return BNC_OK;
+}
+
 int bnc_getrf_ozaki(int32_t factor_words, int32_t slices, int64_t n, double *A, int64_t lda, int64_t ldp,
-                    int64_t *ipiv, int64_t *info, void *stream)
+                    int64_t *ipiv, int64_t *info, void *work, size_t work_bytes, void *stream)
 {
     if (factor_words < 1 || factor_words > 4)
         return fail_arg(-1, "getrf_ozaki: factor_words outside 1..4");
@@ -330,35 +331,35 @@ int bnc_getrf_ozaki(int32_t factor_words, int32_t slices, int64_t n, double *A, 
         return fail_arg(-2, "getrf_ozaki: slices outside 1..12");
     switch (factor_words) {
     case 1:
-        return getrf_entry<1>(n, A, lda, ldp, ipiv, info, stream, slices, 2);
+        return getrf_entry<1>(n, A, lda, ldp, ipiv, info, work, work_bytes, stream, slices, 2);
     case 2:
-        return getrf_entry<2>(n, A, lda, ldp, ipiv, info, stream, slices, 2);
+        return getrf_entry<2>(n, A, lda, ldp, ipiv, info, work, work_bytes, stream, slices, 2);
     case 3:
-        return getrf_entry<3>(n, A, lda, ldp, ipiv, info, stream, slices, 2);
+        return getrf_entry<3>(n, A, lda, ldp, ipiv, info, work, work_bytes, stream, slices, 2);
     default:
-        return getrf_entry<4>(n, A, lda, ldp, ipiv, info, stream, slices, 2);
+        return getrf_entry<4>(n, A, lda, ldp, ipiv, info, work, work_bytes, stream, slices, 2);
     }
 }
 
-int bnc_getrs_d(int64_t n, int64_t nrhs, const double *LU, int64_t lda, int64_t ldp, const int64_t *ipiv, double *B,
-                int64_t ldb, int64_t ldpb, void *stream)
+int bnc_getrs_d(int64_t n, int64_t nrhs, const double *LU, int64_t lda, int64_t ldp, const int64_t *ipiv,
+                double *B, int64_t ldb, int64_t ldpb, int64_t *info, void *work, size_t work_bytes, void *stream)
 {
-    return getrs_entry<1>(n, nrhs, LU, lda, ldp, ipiv, B, ldb, ldpb, stream);
+    return getrs_entry<1>(n, nrhs, LU, lda, ldp, ipiv, B, ldb, ldpb, info, work, work_bytes, stream);
 }
 int bnc_getrs_dd(int64_t n, int64_t nrhs, const double *LU, int64_t lda, int64_t ldp, const int64_t *ipiv,
-                 double *B, int64_t ldb, int64_t ldpb, void *stream)
+                 double *B, int64_t ldb, int64_t ldpb, int64_t *info, void *work, size_t work_bytes, void *stream)
 {
-    return getrs_entry<2>(n, nrhs, LU, lda, ldp, ipiv, B, ldb, ldpb, stream);
+    return getrs_entry<2>(n, nrhs, LU, lda, ldp, ipiv, B, ldb, ldpb, info, work, work_bytes, stream);
 }
 int bnc_getrs_td(int64_t n, int64_t nrhs, const double *LU, int64_t lda, int64_t ldp, const int64_t *ipiv,
-                 double *B, int64_t ldb, int64_t ldpb, void *stream)
+                 double *B, int64_t ldb, int64_t ldpb, int64_t *info, void *work, size_t work_bytes, void *stream)
 {
-    return getrs_entry<3>(n, nrhs, LU, lda, ldp, ipiv, B, ldb, ldpb, stream);
+    return getrs_entry<3>(n, nrhs, LU, lda, ldp, ipiv, B, ldb, ldpb, info, work, work_bytes, stream);
 }
 int bnc_getrs_qd(int64_t n, int64_t nrhs, const double *LU, int64_t lda, int64_t ldp, const int64_t *ipiv,
-                 double *B, int64_t ldb, int64_t ldpb, void *stream)
+                 double *B, int64_t ldb, int64_t ldpb, int64_t *info, void *work, size_t work_bytes, void *stream)
 {
-    return getrs_entry<4>(n, nrhs, LU, lda, ldp, ipiv, B, ldb, ldpb, stream);
+    return getrs_entry<4>(n, nrhs, LU, lda, ldp, ipiv, B, ldb, ldpb, info, work, work_bytes, stream);
 }
 
 size_t bnc_refine_workspace_size(int64_t n, int32_t factor_words)
@@ -522,7 +523,7 @@ int64_t bnc_wall_clock_khz(void)
 
 int bnc_residual(int64_t n, int32_t a_words, const double *A, int64_t lda, int64_t ldpa, const double *x,
                  int64_t ldpx, const double *b, int64_t ldpb, double *r, int64_t ldpr, int32_t *inexact,
-                 void *stream)
+                 void *work, size_t work_bytes, void *stream)
 {
     if (n < 0)
         return fail_arg(-1, "residual: n < 0");
@@ -550,22 +551,11 @@ int bnc_residual(int64_t n, int32_t a_words, const double *A, int64_t lda, int64
         return fail_arg(-11, "residual: ldpr < n");
     if (!inexact)
         return fail_arg(-12, "residual: inexact is NULL");
-    const size_t need = residual_scratch_bytes(n) + (size_t)n * sizeof(double) + 512;
-    char *scr = (char *)scratch(SCR_GETRS, need);
-    if (!scr)
-        return fail_arg(BNC_ERR_HIP, "residual: scratch allocation failed");
-    double *rowmax = (double *)scr;
-    unsigned long long *xmax = (unsigned long long *)(scr + ((n * sizeof(double) + 255) / 256) * 256);
-    int *eb = (int *)((char *)xmax + 64);  // exponent bounds a, x, b
-    double *part = (double *)((char *)xmax + 256);
-    hipStream_t s = S(stream);
-    int rc;
-    if ((rc = rowmax_run(n, A, lda, rowmax, s)) || (rc = absmax_run(n, 1, n, x, xmax, s)) ||
-        (rc = fill_i32_run(eb, 3, 2000, s)) || (rc = minexp_run(n, n, lda, a_words, ldpa, A, eb, s)) ||
-        (rc = minexp_run(n, 1, n, 4, ldpx, x, eb + 1, s)) || (rc = minexp_run(n, 1, n, 4, ldpb, b, eb + 2, s)))
-        return rc;
-    return residual_run(n, a_words, A, lda, ldpa, x, ldpx, b, ldpb, rowmax, (const double *)xmax, eb, part, r, ldpr,
-                        inexact, s);
+    if (!work)
+        return fail_arg(-13, "residual: work is NULL");
+    if (work_bytes < residual_workspace_bytes(n))
+        return fail_arg(BNC_ERR_WORKSPACE, "residual: workspace smaller than bnc_residual_workspace_size");
+    return residual_ws_run(n, a_words, A, lda, ldpa, x, ldpx, b, ldpb, r, ldpr, inexact, work, S(stream));
 }
 
 int bnc_mw_apply(int32_t op, int32_t K, int64_t n, const double *c, const double *a, const double *b, double *out,
@@ -623,8 +613,8 @@ int bnc_profile_read(double *ms, double *flops, int64_t *launches)
         BNC_HIP(hipEventElapsedTime(&m, e.a, e.b));
         tms += m;
         tf += e.flops;
-        hipEventDestroy(e.a);
-        hipEventDestroy(e.b);
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
     }
     if (launches)
         *launches = (int64_t)g_events.size();

@@ -1,5 +1,5 @@
 // Shared host-side plumbing for the solver library: error reporting,
-// per-device scratch, timing of the trailing-update launches.
+// workspace sizes, timing of the trailing-update launches.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -23,11 +23,14 @@ int fail_arg(int code, const char *msg);
 
 #define BNC_LAUNCH_CHECK() BNC_HIP(hipGetLastError())
 
-// Library-owned device scratch for the stand-alone factor/solve entry points
-// (the refinement driver carves everything from the caller's workspace).
-// One buffer per (device, slot); grown with hipMalloc when a call needs more.
-enum ScratchSlot { SCR_GETRF = 0, SCR_GETRS = 1, SCR_OZ = 2, SCR_NSLOTS = 3 };
-void *scratch(int slot, size_t bytes);
+// Every entry point works in memory the caller passes in: no call
+// allocates.  Sub-buffers of a workspace start on 256-byte boundaries.
+inline size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+// Test hook: raise the abort flag of the bounded waits right after each
+// factorisation (bit 0) or substitution (bit 1) has cleared it, so that every
+// wait gives up at once and the timeout paths run (bnc_test_force_timeout).
+int force_timeout_bits();
 
 // Timing of trailing-update launches (hipEvents on the launch stream).
 struct UpdateTimer {

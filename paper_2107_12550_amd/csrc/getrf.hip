@@ -24,6 +24,9 @@
 // in the same order (row moves commute with the updates, each entry is
 // updated in increasing k), so the factors equal the unblocked ones bit for
 // bit.
+#include <cstdlib>
+#include <mutex>
+
 #include "common.hpp"
 #include "mw.hpp"
 #include "ozsplit.hpp"
@@ -845,6 +848,17 @@ size_t getrf_scratch_bytes(int K, int64_t n)
     return xb + pairs + 256;
 }
 
+size_t oz_slices_bytes(int64_t n);
+
+// Workspace of a stand-alone factorisation: the exchange buffers, pairs and
+// abort flag, then (split form) the slices.
+size_t getrf_workspace_bytes(int K, int64_t n, int oz)
+{
+    if (n <= 0)
+        return 0;
+    return align256(getrf_scratch_bytes(K, n)) + (oz ? oz_slices_bytes(n) : 0);
+}
+
 __global__ void k_zero_i64(int64_t *p)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0)
@@ -868,6 +882,13 @@ __global__ void k_xbuf_init(uint64_t *x, int64_t nw, int *abort_flag)
         *abort_flag = 0;
 }
 
+// the timeout test hook: every poll of the factorisation gives up at once
+__global__ void k_xbuf_raise(int *abort_flag)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        *abort_flag = 1;
+}
+
 // end of a factorisation: a failed panel exchange makes info -1
 __global__ void k_abort_check(const int *abort_flag, int64_t *info)
 {
@@ -888,6 +909,29 @@ struct LookAhead {
     hipEvent_t start = nullptr, panel = nullptr, look = nullptr, rest = nullptr;
 };
 LookAhead g_la[16];
+std::once_flag g_la_exit;
+
+// at process exit, before the HIP runtime's own teardown (registered
+// earlier, so it runs later): release every device's stream and events
+void lookahead_release()
+{
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess)
+        return;
+    for (int d = 0; d < 16; ++d) {
+        LookAhead &la = g_la[d];
+        if (!la.side || hipSetDevice(d) != hipSuccess)
+            continue;
+        (void)hipStreamSynchronize(la.side);
+        (void)hipEventDestroy(la.start);
+        (void)hipEventDestroy(la.panel);
+        (void)hipEventDestroy(la.look);
+        (void)hipEventDestroy(la.rest);
+        (void)hipStreamDestroy(la.side);
+        la = LookAhead{};
+    }
+    (void)hipSetDevice(cur);
+}
 }  // namespace
 
 static int lookahead_get(LookAhead *&la)
@@ -896,6 +940,7 @@ static int lookahead_get(LookAhead *&la)
     BNC_HIP(hipGetDevice(&dev));
     if (dev < 0 || dev >= 16)
         return fail_arg(BNC_ERR_UNSUPPORTED, "getrf: device index out of range");
+    std::call_once(g_la_exit, [] { std::atexit(lookahead_release); });
     la = &g_la[dev];
     if (!la->side) {
         BNC_HIP(hipStreamCreateWithFlags(&la->side, hipStreamNonBlocking));
@@ -978,6 +1023,10 @@ int getrf_run(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int
             hipLaunchKernelGGL(k_xbuf_init, dim3(16), dim3(256), 0, st, (uint64_t *)(xb[0] + own_off),
                                (int64_t)PANEL_NB_MAX * K * PANEL_NB_MAX, abort_flag);
             BNC_LAUNCH_CHECK();
+            if (force_timeout_bits() & 1) {
+                hipLaunchKernelGGL(k_xbuf_raise, dim3(1), dim3(64), 0, st, abort_flag);
+                BNC_LAUNCH_CHECK();
+            }
         }
         // All P workgroups fit on the device at once (checked above); the
         // grid barrier inside the kernel has a bounded spin, so a workgroup

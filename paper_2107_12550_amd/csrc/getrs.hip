@@ -225,6 +225,25 @@ __global__ void k_ts_reset(uint64_t *xs, int64_t nw, int *abort_flag)
         *abort_flag = 0;
 }
 
+// raise the abort flag (the timeout test hook) / report it: info = -1
+__global__ void k_ts_raise(int *abort_flag)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        *abort_flag = 1;
+}
+
+__global__ void k_ts_info(const int *abort_flag, int64_t *info)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0 && *abort_flag)
+        *info = -1;
+}
+
+__global__ void k_ts_zero(int64_t *info)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        *info = 0;
+}
+
 // x = L^-1 y (unit lower), y already permuted; x: K planes of stride n
 template <int K>
 __global__ void __launch_bounds__(2 * TS_BS)
@@ -526,10 +545,11 @@ int diag_recip_run(int64_t n, const double *LU, int64_t lda, int64_t ldp, double
 
 // Solve in place on y (already permuted), one right-hand side; rd = 1/u_kk.
 // ws: trsv_ws_bytes(n) bytes of scratch (the two streamed planes sets and
-// the abort flag of the persistent launches).
+// the abort flag of the persistent launches).  info (nullable): set to -1
+// when a bounded wait of the pair gave up (never cleared here).
 template <int K>
 int trsv_pair(int64_t n, const double *LU, int64_t lda, int64_t ldp, const double *rd, double *y, int64_t ldy,
-              void *ws, hipStream_t s)
+              void *ws, hipStream_t s, int64_t *info)
 {
     if (n == 0)
         return BNC_OK;
@@ -541,21 +561,31 @@ int trsv_pair(int64_t n, const double *LU, int64_t lda, int64_t ldp, const doubl
     hipLaunchKernelGGL(k_ts_reset, dim3((unsigned)(ceil_div(2 * K * n, 256) < 64 ? ceil_div(2 * K * n, 256) : 64)),
                        dim3(256), 0, s, (uint64_t *)x1, (int64_t)(2 * K * n), abort_flag);
     BNC_LAUNCH_CHECK();
+    if (force_timeout_bits() & 2) {
+        hipLaunchKernelGGL(k_ts_raise, dim3(1), dim3(64), 0, s, abort_flag);
+        BNC_LAUNCH_CHECK();
+    }
     hipLaunchKernelGGL((k_trsv_lower<K>), dim3((unsigned)nblk), dim3(2 * TS_BS), lds, s, LU, lda, ldp, y, ldy, n, x1,
                        abort_flag);
     BNC_LAUNCH_CHECK();
     hipLaunchKernelGGL((k_trsv_upper<K>), dim3((unsigned)nblk), dim3(2 * TS_BS), lds, s, LU, lda, ldp, rd, x1, x2, y, ldy,
                        n, abort_flag);
     BNC_LAUNCH_CHECK();
+    if (info) {
+        hipLaunchKernelGGL(k_ts_info, dim3(1), dim3(64), 0, s, (const int *)abort_flag, info);
+        BNC_LAUNCH_CHECK();
+    }
     return BNC_OK;
 }
 
 // up to four words per value
 size_t trsv_ws_bytes(int64_t n) { return 2 * 4 * (size_t)(n > 0 ? n : 1) * sizeof(double) + 256; }
 
-size_t getrs_scratch_bytes(int K, int64_t n)
+size_t getrs_workspace_bytes(int K, int64_t n)
 {
-    return (size_t)n * sizeof(int32_t) + 2 * (size_t)K * n * sizeof(double) + trsv_ws_bytes(n) + 1024;
+    if (n <= 0)
+        return 0;
+    return align256((size_t)n * sizeof(int32_t)) + 2 * (size_t)K * n * sizeof(double) + trsv_ws_bytes(n) + 1024;
 }
 
 int ipiv_to_perm(int64_t n, const int64_t *ipiv, int32_t *perm, hipStream_t s)
@@ -571,19 +601,25 @@ int ipiv_to_perm(int64_t n, const int64_t *ipiv, int32_t *perm, hipStream_t s)
 // (K planes, stride n) and y buffer
 template <int K>
 int getrs_perm(int64_t n, const double *LU, int64_t lda, int64_t ldp, const int32_t *perm, const double *rd,
-               const double *b, int64_t ldb, double *y, int64_t ldy, void *ws, hipStream_t s)
+               const double *b, int64_t ldb, double *y, int64_t ldy, void *ws, hipStream_t s, int64_t *info)
 {
     if (n == 0)
         return BNC_OK;
     hipLaunchKernelGGL((k_gather<K>), dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, n, perm, b, ldb, y, ldy);
     BNC_LAUNCH_CHECK();
-    return trsv_pair<K>(n, LU, lda, ldp, rd, y, ldy, ws, s);
+    return trsv_pair<K>(n, LU, lda, ldp, rd, y, ldy, ws, s, info);
 }
 
+// scr: getrs_workspace_bytes(K, n) bytes; info (nullable) gets 0, or -1 if
+// a bounded wait of the substitutions gave up
 template <int K>
 int getrs_run(int64_t n, int64_t nrhs, const double *LU, int64_t lda, int64_t ldp, const int64_t *ipiv, double *B,
-              int64_t ldb, int64_t ldpb, void *scr, hipStream_t s)
+              int64_t ldb, int64_t ldpb, int64_t *info, void *scr, hipStream_t s)
 {
+    if (info) {
+        hipLaunchKernelGGL(k_ts_zero, dim3(1), dim3(64), 0, s, info);
+        BNC_LAUNCH_CHECK();
+    }
     if (n == 0 || nrhs == 0)
         return BNC_OK;
     int32_t *perm = (int32_t *)scr;
@@ -597,7 +633,7 @@ int getrs_run(int64_t n, int64_t nrhs, const double *LU, int64_t lda, int64_t ld
         return rc;
     for (int64_t c = 0; c < nrhs; ++c) {
         double *bc = B + c * ldb;
-        rc = getrs_perm<K>(n, LU, lda, ldp, perm, rd, bc, ldpb, y, n, ws, s);
+        rc = getrs_perm<K>(n, LU, lda, ldp, perm, rd, bc, ldpb, y, n, ws, s, info);
         if (rc)
             return rc;
         hipLaunchKernelGGL((k_copy_vec<K>), dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, n, y, n, bc, ldpb);
@@ -608,10 +644,10 @@ int getrs_run(int64_t n, int64_t nrhs, const double *LU, int64_t lda, int64_t ld
 
 #define INST(K)                                                                                                     \
     template int getrs_perm<K>(int64_t, const double *, int64_t, int64_t, const int32_t *, const double *,          \
-                               const double *, int64_t, double *, int64_t, void *, hipStream_t);                    \
+                               const double *, int64_t, double *, int64_t, void *, hipStream_t, int64_t *);         \
     template int diag_recip_run<K>(int64_t, const double *, int64_t, int64_t, double *, hipStream_t);               \
     template int getrs_run<K>(int64_t, int64_t, const double *, int64_t, int64_t, const int64_t *, double *,        \
-                              int64_t, int64_t, void *, hipStream_t);
+                              int64_t, int64_t, int64_t *, void *, hipStream_t);
 INST(1)
 INST(2)
 INST(3)

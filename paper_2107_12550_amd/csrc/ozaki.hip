@@ -9,12 +9,14 @@
 //   * every row i of L21 gets the scale E_i (|l_ik| < 2^E_i for all k, from
 //     the leading words) and is cut into S slices; slice q is the sum over
 //     the words of what is left of l_ik, each word rounded to the nearest
-//     multiple of 2^(E_i - (q+1) BETA) (ties to even), BETA = 20 bits;
-//     columns of U12 likewise with scales F_j;
+//     multiple of 2^(E_i - (q+1) beta) (ties to even), beta = oz_beta(K, S)
+//     bits (22 for a double-double factor with 5 slices, 21 for
+//     triple-double with 5); columns of U12 likewise with scales F_j;
 //   * the group sums acc_d = sum_{p+q=d} sum_k L_p(i,k) U_q(k,j), d < S, are
 //     formed with v_mfma_f64_16x16x4.  Every product and every partial sum is
-//     a multiple of 2^(E_i + F_j - (d+2) BETA) below 2^53 of those units
-//     (kb (d+1) <= 64 * 12 products of at most (2^21 + 2)^2 units each), so
+//     a multiple of 2^(E_i + F_j - (d+2) beta) below 2^53 of those units
+//     (oz_beta is the widest width for which the kb (d+1) <= 64 S products
+//     of group d, each bounded by the slices' sizes, stay below 2^53), so
 //     each acc_d is exact whatever the order the matrix core adds in;
 //   * a_ij <- (((a_ij - acc_0) - acc_1) ...) - acc_{S-1} in K-word addition,
 //     in that order.

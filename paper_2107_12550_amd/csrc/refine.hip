@@ -27,7 +27,7 @@ int getrf_run(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int
 size_t oz_slices_bytes(int64_t n);
 template <int K>
 int getrs_perm(int64_t n, const double *LU, int64_t lda, int64_t ldp, const int32_t *perm, const double *rd,
-               const double *b, int64_t ldb, double *y, int64_t ldy, void *ws, hipStream_t s);
+               const double *b, int64_t ldb, double *y, int64_t ldy, void *ws, hipStream_t s, int64_t *info);
 size_t trsv_ws_bytes(int64_t n);
 template <int K>
 int diag_recip_run(int64_t n, const double *LU, int64_t lda, int64_t ldp, double *rd, hipStream_t s);
@@ -486,6 +486,38 @@ int residual_run(int64_t n, int aw, const double *A, int64_t lda, int64_t ldpa, 
     return BNC_OK;
 }
 
+// Stand-alone residual (bnc_residual) in a caller workspace: row maxima,
+// the vector maximum and exponent bounds, then the partial bins.
+size_t residual_workspace_bytes(int64_t n)
+{
+    if (n <= 0)
+        return 0;
+    return align256((size_t)n * sizeof(double)) + 256 + residual_scratch_bytes(n);
+}
+
+int rowmax_run(int64_t n, const double *A, int64_t lda, double *rowmax, hipStream_t s);
+int absmax_run(int64_t rows, int64_t cols, int64_t ld, const double *v, unsigned long long *bits, hipStream_t s);
+
+int residual_ws_run(int64_t n, int aw, const double *A, int64_t lda, int64_t ldpa, const double *x, int64_t ldpx,
+                    const double *b, int64_t ldpb, double *r, int64_t ldpr, int32_t *inexact, void *work,
+                    hipStream_t s)
+{
+    if (n == 0)
+        return BNC_OK;
+    char *W = (char *)work;
+    double *rowmax = (double *)W;
+    unsigned long long *xmax = (unsigned long long *)(W + align256((size_t)n * sizeof(double)));
+    int *eb = (int *)((char *)xmax + 64);  // exponent bounds a, x, b
+    double *part = (double *)((char *)xmax + 256);
+    int rc;
+    if ((rc = rowmax_run(n, A, lda, rowmax, s)) || (rc = absmax_run(n, 1, n, x, xmax, s)) ||
+        (rc = fill_i32_run(eb, 3, 2000, s)) || (rc = minexp_run(n, n, lda, aw, ldpa, A, eb, s)) ||
+        (rc = minexp_run(n, 1, n, 4, ldpx, x, eb + 1, s)) || (rc = minexp_run(n, 1, n, 4, ldpb, b, eb + 2, s)))
+        return rc;
+    return residual_run(n, aw, A, lda, ldpa, x, ldpx, b, ldpb, rowmax, (const double *)xmax, eb, part, r, ldpr,
+                        inexact, s);
+}
+
 // rowmax of |A0| and a one-element max of a vector's leading words
 int rowmax_run(int64_t n, const double *A, int64_t lda, double *rowmax, hipStream_t s)
 {
@@ -535,8 +567,9 @@ struct Scal {
     unsigned long long amax, xmax, rmax, zmax;
     double asq, xsq, rsq, pad;
     int32_t nonfinite, inexact;
-    int64_t info;
-    ExpBounds eb;  // a, x, b
+    int64_t info;   // getrf info of the last factorisation (-1: exchange timed out)
+    int64_t tinfo;  // -1 once a substitution's bounded wait gave up
+    ExpBounds eb;   // a, x, b
     int32_t pad2;
 };
 
@@ -684,20 +717,23 @@ int refine_drive(int K0, int64_t n, int aw, const double *A, int64_t lda, int64_
         BNC_KSWITCH(kc, {
             hipLaunchKernelGGL((k_round_scaled<KK>), dim3(grid1(n)), dim3(256), 0, s, n, src, lds, rmaxbits, r, n);
             BNC_LAUNCH_CHECK();
-            rc2 = getrs_perm<KK>(n, LU, n, ldp, perm, rd, r, n, v, n, tsflags, s);
+            rc2 = getrs_perm<KK>(n, LU, n, ldp, perm, rd, r, n, v, n, tsflags, s, &sc->tinfo);
         });
         return rc2;
     };
 
+    const auto timed_out = [&]() { return fail_arg(BNC_ERR_TIMEOUT, "refine: a bounded wait gave up"); };
     int64_t info = 0;
     if ((rc = factor(o->ozaki_slices, &info)))
         return rc;
-    while (info && o->escalate && kc < 4) {
+    while (info > 0 && o->escalate && kc < 4) {
         ++kc;
         ++res->escalations;
         if ((rc = factor(0, &info)))
             return rc;
     }
+    if (info < 0)
+        return timed_out();
     res->final_words = kc;
     res->info = info;
     const double amax = bits_to_double(h.amax);
@@ -730,6 +766,8 @@ int refine_drive(int K0, int64_t n, int aw, const double *A, int64_t lda, int64_
             return rc;
         BNC_HIP(hipMemcpyAsync(&h, sc, sizeof(Scal), hipMemcpyDeviceToHost, s));
         BNC_HIP(hipStreamSynchronize(s));
+        if (h.tinfo)
+            return timed_out();
         const double rmax = bits_to_double(h.rmax), xmax = bits_to_double(h.xmax);
         if (nz > 0) {
             zprev = zlast;
@@ -754,7 +792,9 @@ int refine_drive(int K0, int64_t n, int aw, const double *A, int64_t lda, int64_
                 ++res->escalations;
                 if ((rc = factor(0, &info)))
                     return rc;
-            } while (info && kc < 4);
+            } while (info > 0 && kc < 4);
+            if (info < 0)
+                return timed_out();
             res->final_words = kc;
             res->info = info;
             if (info) {

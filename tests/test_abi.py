@@ -19,7 +19,8 @@ def test_header_declares_the_boundary():
     for k in ("d", "dd", "td", "qd"):
         assert f"bnc_getrf_{k}" in names and f"bnc_getrs_{k}" in names
     for n in ("bnc_refine", "bnc_refine_workspace_size", "bnc_residual", "bnc_mw_apply", "bnc_getrf_ozaki",
-              "bnc_refine_batched", "bnc_refine_batched_graph"):
+              "bnc_refine_batched", "bnc_refine_batched_graph", "bnc_getrf_workspace_size",
+              "bnc_getrs_workspace_size", "bnc_residual_workspace_size"):
         assert n in names
 
 
@@ -40,21 +41,57 @@ def test_host_only_entry_points():
     assert L.bnc_refine_workspace_size(0, 3) == 0
     assert L.bnc_refine_workspace_size(128, 5) == 0
     # argument errors are reported before anything touches the device
-    rc = L.bnc_getrf_td(-1, None, 1, 1, None, None, None)
+    rc = L.bnc_getrf_td(-1, None, 1, 1, None, None, None, 0, None)
     assert rc == -1
-    rc = L.bnc_getrf_td(8, None, 8, 64, None, None, None)
+    rc = L.bnc_getrf_td(8, None, 8, 64, None, None, None, 0, None)
     assert rc == -2
     assert b"NULL" in L.bnc_last_error()
+
+
+def test_workspace_queries():
+    """Every stand-alone call takes its scratch from the caller: the size
+    queries grow with n and K, cover the split form's slices, give 0 for
+    n = 0 and for arguments out of range, and a call whose workspace is
+    missing or too small is refused before anything is launched."""
+    import paper_2107_12550_amd as P
+    L = P.lib()
+    for K in (1, 2, 3, 4):
+        a, b = P.getrf_workspace_size(K, 1024), P.getrf_workspace_size(K, 2048)
+        assert 0 < a < b
+        assert P.getrf_workspace_size(K, 2048, 5) >= b + 3 * 12 * 64 * 2048 * 8
+        assert P.getrf_workspace_size(K, 0) == 0
+        assert 0 < P.getrs_workspace_size(K, 100) < P.getrs_workspace_size(K, 200)
+        assert P.getrs_workspace_size(K, 0) == 0
+    assert P.getrf_workspace_size(2, 4096) < P.getrf_workspace_size(4, 4096)
+    assert P.getrf_workspace_size(5, 64) == 0 and P.getrf_workspace_size(2, 64, 13) == 0
+    assert P.getrf_workspace_size(2, 16385) == 0 and P.getrs_workspace_size(0, 8) == 0
+    assert 0 < P.residual_workspace_size(64) < P.residual_workspace_size(128)
+    assert P.residual_workspace_size(0) == 0
+    # pointers are never dereferenced on these paths: fake non-NULL addresses
+    A, ip, inf = 1 << 20, 2 << 20, 3 << 20
+    need = P.getrf_workspace_size(3, 8)
+    assert L.bnc_getrf_td(8, A, 8, 64, ip, inf, None, need, None) == -7
+    assert L.bnc_getrf_td(8, A, 8, 64, ip, inf, 4 << 20, need - 1, None) == P.BNC_ERR_WORKSPACE
+    assert L.bnc_getrf_ozaki(2, 5, 8, A, 8, 64, ip, inf, 4 << 20, P.getrf_workspace_size(2, 8), None) == \
+        P.BNC_ERR_WORKSPACE
+    need = P.getrs_workspace_size(2, 8)
+    assert L.bnc_getrs_dd(8, 1, A, 8, 64, ip, A, 8, 8, None, None, need, None) == -11
+    assert L.bnc_getrs_dd(8, 1, A, 8, 64, ip, A, 8, 8, None, 4 << 20, need - 1, None) == P.BNC_ERR_WORKSPACE
+    assert L.bnc_residual(8, 1, A, 8, 64, A, 8, A, 8, A, 8, inf, None, 0, None) == -13
+    assert L.bnc_residual(8, 1, A, 8, 64, A, 8, A, 8, A, 8, inf, 4 << 20, 16, None) == P.BNC_ERR_WORKSPACE
+    # n = 0 needs no workspace and launches nothing
+    assert L.bnc_getrs_qd(0, 1, None, 1, 0, None, None, 1, 1, None, None, 0, None) == 0
+    assert L.bnc_test_force_timeout(4) == -1 and L.bnc_test_force_timeout(0) == 0
 
 
 def test_ozaki_rejects_bad_slices_before_touching_the_device():
     import paper_2107_12550_amd as P
     L = P.lib()
-    assert L.bnc_getrf_ozaki(3, 0, 4, None, 4, 16, None, None, None) == -2
-    assert L.bnc_getrf_ozaki(3, 13, 4, None, 4, 16, None, None, None) == -2
-    assert L.bnc_getrf_ozaki(5, 8, 4, None, 4, 16, None, None, None) == -1
+    assert L.bnc_getrf_ozaki(3, 0, 4, None, 4, 16, None, None, None, 0, None) == -2
+    assert L.bnc_getrf_ozaki(3, 13, 4, None, 4, 16, None, None, None, 0, None) == -2
+    assert L.bnc_getrf_ozaki(5, 8, 4, None, 4, 16, None, None, None, 0, None) == -1
     # argument positions continue from n = 3
-    assert L.bnc_getrf_ozaki(3, 8, -1, None, 4, 16, None, None, None) == -3
+    assert L.bnc_getrf_ozaki(3, 8, -1, None, 4, 16, None, None, None, 0, None) == -3
 
 
 def test_slice_width_agrees_with_the_oracle():
