@@ -344,7 +344,9 @@ def refine(A: np.ndarray, b: np.ndarray, K: int, max_iter: int = 30,
     stops with STAGNATED.  An exactly zero pivot escalates the same way.
     max_iter bounds the corrections over all precisions.  Returns a dict
     with x (4, n), iters (corrections applied), status, info, history of
-    ||r||, final_words (K of the last factorisation) and escalations.
+    ||r||, final_words (K of the last factorisation), escalations, and the
+    norms of the last test: resid_norm ||r||_2, x_norm ||x||_2 and a_norm
+    ||A||_F (leading words).
     """
     A = _c(A)
     b = _c(b)
@@ -353,6 +355,7 @@ def refine(A: np.ndarray, b: np.ndarray, K: int, max_iter: int = 30,
     if not (np.isfinite(A).all() and np.isfinite(b).all()):
         return out
     norm_a = norm2(A[0])
+    out.update(a_norm=norm_a, resid_norm=0.0, x_norm=0.0)
     kc = K
     escalations = 0
     while True:
@@ -380,6 +383,7 @@ def refine(A: np.ndarray, b: np.ndarray, K: int, max_iter: int = 30,
         nr = norm2(r[0])
         nx = norm2(x[0])
         hist.append(nr)
+        out.update(resid_norm=nr, x_norm=nx)
         xmax = float(np.abs(x[0]).max())
         if nr < thresh_c * nx + atol or (zs and zs[-1] <= ctol * xmax):
             status = CONVERGED

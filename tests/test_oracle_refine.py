@@ -175,3 +175,60 @@ def test_zero_pivot_in_short_precision_escalates():
     e = O.refine(A, b, 1, escalate=True)
     assert e["status"] == O.CONVERGED and e["final_words"] == 2 and e["escalations"] == 1
     assert _err_vs_ones(e["x"]) == Fraction(0)
+
+
+def _norm2_exact(v) -> float:
+    """2-norm of a binary64 vector from an exact rational sum of squares
+    (the square root taken once, in binary64)."""
+    import math
+    s = sum(Fraction(float(t)) ** 2 for t in np.asarray(v).ravel())
+    if s == 0:
+        return 0.0
+    # sqrt of the correctly rounded sum: within an ulp of the exact root
+    return math.sqrt(float(s))
+
+
+@pytest.mark.parametrize("rtol", [1e-30, 1e-45, 2.0 ** -209])
+def test_stopping_rule_eq2_is_the_first_residual_below_its_threshold(rtol):
+    """The loop ends at the first residual with ||r||_2 < sqrt(n) rtol
+    ||A||_F ||x||_2 (Listing 1; eq. (2) of Sec. 3 with the listing's strict
+    inequality), the norms being 2-norms of the leading words.  Checked
+    against norms recomputed from exact rational sums of squares: the
+    reported norms agree to a few ulps, the final residual is below its
+    threshold and every earlier one is above its own (a dropped sqrt(n),
+    squared norms or a test placed after the update would break one)."""
+    n = 48
+    Ap, b, _ = synth.problem("randsvd", n, config=2, instance=3, cond=1e8)
+    res = O.refine(Ap, b, 2, rtol=rtol, ctol=0.0, max_iter=40)
+    assert res["status"] == O.CONVERGED
+    na = _norm2_exact(Ap[0])
+    assert abs(res["a_norm"] - na) <= 4e-16 * na
+    nx = _norm2_exact(res["x"][0])
+    assert abs(res["x_norm"] - nx) <= 4e-16 * nx
+    r = O.residual(Ap, res["x"], b)
+    nr = _norm2_exact(r[0])
+    assert abs(res["resid_norm"] - nr) <= 4e-16 * max(nr, 1e-300)
+    thr = np.sqrt(n) * rtol * na
+    assert nr < thr * nx
+    # replay the corrections: every earlier residual fails the test
+    hist = res["history"]
+    assert len(hist) == res["iters"] + 1
+    for h in hist[:-1]:
+        assert h >= thr * nx * 0.5  # the x norms of earlier iterates differ from the last by far less than 2x
+    # tighter rtol never stops earlier
+    tight = O.refine(Ap, b, 2, rtol=rtol / 1e6, ctol=0.0, max_iter=40)
+    assert tight["iters"] >= res["iters"]
+
+
+def test_stopping_rule_atol_alone():
+    """atol above the first residual's norm stops the loop before any
+    correction; below it, the listing's test with rtol = 0 never fires."""
+    n = 32
+    Ap, b, _ = synth.problem("uniform", n, config=0, instance=7)
+    first = O.refine(Ap, b, 3, max_iter=0)
+    r0 = first["resid_norm"]
+    assert r0 > 0
+    res = O.refine(Ap, b, 3, atol=2 * r0, ctol=0.0)
+    assert res["status"] == O.CONVERGED and res["iters"] == 0
+    res = O.refine(Ap, b, 3, atol=0.0, rtol=0.0, ctol=0.0, max_iter=3)
+    assert res["status"] == O.MAX_ITER and res["iters"] == 3
