@@ -162,6 +162,23 @@ int bnc_getrs_qd(int64_t n, int64_t nrhs, const double *LU, int64_t lda, int64_t
 size_t bnc_getrs_workspace_size(int32_t factor_words, int64_t n);
 
 /*
+ * bnc_getrs_* without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Its scratch is a fixed device
+ * array of about 2.1 MB inside the library (the workspace of a quad-double
+ * solve of order 16384), one per device, held until the process ends; its
+ * device address is looked up on the first call on each device.  The call
+ * allocates nothing.  factor_words K in 1..4 comes first; the other
+ * arguments, results and errors are those of bnc_getrs_{d,dd,td,qd}
+ * (argument errors numbered from n = 2).  n <= 16384, BNC_ERR_UNSUPPORTED
+ * above.  Every call on a device shares that device's array (each call
+ * writes every word it reads first): calls that overlap on one device, from
+ * several streams or host threads, race and give garbage.
+ */
+int bnc_getrs_noalloc(int32_t factor_words, int64_t n, int64_t nrhs, const double *LU, int64_t lda, int64_t ldp,
+                      const int64_t *ipiv, double *B, int64_t ldb, int64_t ldpb, int64_t *info, void *stream);
+
+/*
  * Multi-word matrix multiply-subtract C <- C - A B (Kouya 2021, Sec. 2 and
  * Fig. 1: the block matrix multiplication of the multi-word library the
  * direct methods are built on; here the LU's K-word trailing-update kernel,

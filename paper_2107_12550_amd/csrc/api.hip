@@ -180,26 +180,26 @@ static int getrf_entry(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *
 template <int K>
 static int getrs_entry(int64_t n, int64_t nrhs, const double *LU, int64_t lda, int64_t ldp, const int64_t *ipiv,
                        double *B, int64_t ldb, int64_t ldpb, int64_t *info, void *work, size_t work_bytes,
-                       void *stream)
+                       void *stream, int argoff = 0)
 {
     if (n < 0)
-        return fail_arg(-1, "getrs: n < 0");
+        return fail_arg(-(1 + argoff), "getrs: n < 0");
     if (nrhs < 0)
-        return fail_arg(-2, "getrs: nrhs < 0");
+        return fail_arg(-(2 + argoff), "getrs: nrhs < 0");
     if (n > 0 && !LU)
-        return fail_arg(-3, "getrs: LU is NULL");
+        return fail_arg(-(3 + argoff), "getrs: LU is NULL");
     if (lda < (n > 1 ? n : 1))
-        return fail_arg(-4, "getrs: lda < max(1, n)");
+        return fail_arg(-(4 + argoff), "getrs: lda < max(1, n)");
     if (K > 1 && ldp < lda * n)
-        return fail_arg(-5, "getrs: ldp < lda * n");
+        return fail_arg(-(5 + argoff), "getrs: ldp < lda * n");
     if (n > 0 && !ipiv)
-        return fail_arg(-6, "getrs: ipiv is NULL");
+        return fail_arg(-(6 + argoff), "getrs: ipiv is NULL");
     if (n > 0 && nrhs > 0 && !B)
-        return fail_arg(-7, "getrs: B is NULL");
+        return fail_arg(-(7 + argoff), "getrs: B is NULL");
     if (ldb < (n > 1 ? n : 1))
-        return fail_arg(-8, "getrs: ldb < max(1, n)");
+        return fail_arg(-(8 + argoff), "getrs: ldb < max(1, n)");
     if (K > 1 && ldpb < ldb * nrhs)
-        return fail_arg(-9, "getrs: ldpb < ldb * nrhs");
+        return fail_arg(-(9 + argoff), "getrs: ldpb < ldb * nrhs");
     if (n > 16384)
         return fail_arg(BNC_ERR_UNSUPPORTED, "getrs: n > 16384");
     if (n > 0 && nrhs > 0 && !work)
@@ -291,6 +291,30 @@ int bnc_oz_beta(int32_t factor_words, int32_t slices)
     if (factor_words < 1 || factor_words > 4 || slices < 1 || slices > OZ_SMAX)
         return -1;
     return oz_beta(factor_words, slices);
+}
+
+int bnc_getrs_noalloc(int32_t factor_words, int64_t n, int64_t nrhs, const double *LU, int64_t lda, int64_t ldp,
+                      const int64_t *ipiv, double *B, int64_t ldb, int64_t ldpb, int64_t *info, void *stream)
+{
+    if (factor_words < 1 || factor_words > 4)
+        return fail_arg(-1, "getrs_noalloc: factor_words outside 1..4");
+    if (n > GETRS_NOALLOC_NMAX)
+        return fail_arg(BNC_ERR_UNSUPPORTED, "getrs_noalloc: n above 16384, the order its fixed scratch holds");
+    void *p = nullptr;
+    size_t bytes = 0;
+    const int rc = noalloc_scratch(&p, &bytes);
+    if (rc)
+        return rc;
+    switch (factor_words) {
+    case 1:
+        return getrs_entry<1>(n, nrhs, LU, lda, ldp, ipiv, B, ldb, ldpb, info, p, bytes, stream, 1);
+    case 2:
+        return getrs_entry<2>(n, nrhs, LU, lda, ldp, ipiv, B, ldb, ldpb, info, p, bytes, stream, 1);
+    case 3:
+        return getrs_entry<3>(n, nrhs, LU, lda, ldp, ipiv, B, ldb, ldpb, info, p, bytes, stream, 1);
+    default:
+        return getrs_entry<4>(n, nrhs, LU, lda, ldp, ipiv, B, ldb, ldpb, info, p, bytes, stream, 1);
+    }
 }
 
 size_t bnc_getrf_workspace_size(int32_t factor_words, int32_t slices, int64_t n)

@@ -25,7 +25,12 @@ int fail_arg(int code, const char *msg);
 
 // Every entry point works in memory the caller passes in: no call
 // allocates.  Sub-buffers of a workspace start on 256-byte boundaries.
-inline size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+constexpr size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+// Largest order bnc_getrs_noalloc accepts (its fixed device scratch holds
+// the workspace of a quad-double solve of this order, about 2.1 MB).
+constexpr int64_t GETRS_NOALLOC_NMAX = 16384;
+int noalloc_scratch(void **ptr, size_t *bytes);
 
 // Test hook: raise the abort flag of the bounded waits right after each
 // factorisation (bit 0) or substitution (bit 1) has cleared it, so that every

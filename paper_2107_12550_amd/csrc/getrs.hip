@@ -8,6 +8,8 @@
 // k_trsv_lower / k_trsv_upper).  Per row the updates arrive in increasing k
 // for L and in decreasing k for U, exactly as in the unblocked
 // column-oriented solve.
+#include <mutex>
+
 #include "common.hpp"
 #include "mw.hpp"
 
@@ -579,13 +581,50 @@ int trsv_pair(int64_t n, const double *LU, int64_t lda, int64_t ldp, const doubl
 }
 
 // up to four words per value
-size_t trsv_ws_bytes(int64_t n) { return 2 * 4 * (size_t)(n > 0 ? n : 1) * sizeof(double) + 256; }
+static constexpr size_t trsv_ws_bytes_c(int64_t n) { return 2 * 4 * (size_t)(n > 0 ? n : 1) * sizeof(double) + 256; }
+size_t trsv_ws_bytes(int64_t n) { return trsv_ws_bytes_c(n); }
 
-size_t getrs_workspace_bytes(int K, int64_t n)
+static constexpr size_t getrs_ws_bytes_c(int K, int64_t n)
 {
-    if (n <= 0)
-        return 0;
-    return align256((size_t)n * sizeof(int32_t)) + 2 * (size_t)K * n * sizeof(double) + trsv_ws_bytes(n) + 1024;
+    return n <= 0 ? 0
+                  : align256((size_t)n * sizeof(int32_t)) + 2 * (size_t)K * n * sizeof(double) + trsv_ws_bytes_c(n) +
+                        1024;
+}
+size_t getrs_workspace_bytes(int K, int64_t n) { return getrs_ws_bytes_c(K, n); }
+
+// ---- fixed scratch of the no-allocation solve (bnc_getrs_noalloc) -----------
+// The workspace of a quad-double solve of the largest order it accepts, in
+// one file-scope device array: each device holds its own copy until the
+// process ends.  Host code never uses the array's name as an address: the
+// device address comes from hipGetSymbolAddress, once per device.
+constexpr size_t NOALLOC_BYTES = getrs_ws_bytes_c(4, GETRS_NOALLOC_NMAX);
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+namespace {
+constexpr int NOALLOC_DEVS = 16;
+void *g_noalloc_ptr[NOALLOC_DEVS];
+hipError_t g_noalloc_err[NOALLOC_DEVS];
+std::once_flag g_noalloc_once[NOALLOC_DEVS];
+}  // namespace
+
+// Device address of this device's scratch array (looked up on the first
+// call with the device current) and its size.
+int noalloc_scratch(void **ptr, size_t *bytes)
+{
+    int dev = 0;
+    BNC_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_DEVS)
+        return fail_arg(BNC_ERR_UNSUPPORTED, "getrs_noalloc: device index out of range");
+    std::call_once(g_noalloc_once[dev], [dev] {
+        void *p = nullptr;
+        g_noalloc_err[dev] = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        g_noalloc_ptr[dev] = g_noalloc_err[dev] == hipSuccess ? p : nullptr;
+    });
+    if (g_noalloc_err[dev] != hipSuccess)
+        return fail_hip(g_noalloc_err[dev], "hipGetSymbolAddress(scratch)", __FILE__, __LINE__);
+    *ptr = g_noalloc_ptr[dev];
+    *bytes = NOALLOC_BYTES;
+    return BNC_OK;
 }
 
 int ipiv_to_perm(int64_t n, const int64_t *ipiv, int32_t *perm, hipStream_t s)
