@@ -60,7 +60,7 @@ def lib() -> ctypes.CDLL:
         L.orc_getrf.argtypes = [ctypes.c_int, I64, P, I64, I64, ctypes.POINTER(I64)]
         L.orc_getrf.restype = I64
         L.orc_getrs.argtypes = [ctypes.c_int, I64, I64, P, I64, I64, ctypes.POINTER(I64), P, I64, I64]
-        L.orc_residual.argtypes = [I64, ctypes.c_int, P, I64, I64, P, I64, P, I64, P, I64]
+        L.orc_residual.argtypes = [I64, ctypes.c_int, ctypes.c_int, P, I64, I64, P, I64, P, I64, P, I64]
         L.orc_residual.restype = I64
         L.orc_exact_dot.argtypes = [ctypes.c_int, I64, P, P, ctypes.POINTER(ctypes.c_int32), P]
         L.orc_exact_dot.restype = ctypes.c_int
@@ -150,7 +150,7 @@ def recip(K: int, a) -> np.ndarray:
 
 
 def round_words(K: int, src) -> np.ndarray:
-    """Renormalise m-word values (shape (m, n), m <= 4) to K words."""
+    """Renormalise m-word values (shape (m, n), m <= 8) to K <= 8 words."""
     src = _c(src)
     m, n = src.shape
     out = np.empty((K, n))
@@ -286,12 +286,14 @@ def gemm(K: int, A: np.ndarray, B: np.ndarray, C: np.ndarray) -> np.ndarray:
 
 
 def residual(A: np.ndarray, x: np.ndarray, b: np.ndarray) -> np.ndarray:
-    """r = b - A x exactly, rounded to canonical quad-double (shape (4, n))."""
+    """r = b - A x exactly, rounded to the canonical L-word form, L = the
+    words of x and b (4: quad-double; 8: the 424-bit long precision)."""
     A, x, b = _c(A), _c(x), _c(b)
     aw, n, _ = A.shape
-    assert x.shape == (4, n) and b.shape == (4, n)
-    r = np.empty((4, n))
-    bad = lib().orc_residual(n, aw, _p(A), n, n * n, _p(x), n, _p(b), n, _p(r), n)
+    lw = x.shape[0]
+    assert lw in (4, 8) and x.shape == (lw, n) and b.shape == (lw, n)
+    r = np.empty((lw, n))
+    bad = lib().orc_residual(n, aw, lw, _p(A), n, n * n, _p(x), n, _p(b), n, _p(r), n)
     if bad:
         raise FloatingPointError("residual word outside the binary64 normal range")
     return r
@@ -317,13 +319,16 @@ def norm2(v: np.ndarray) -> float:
 
 def refine(A: np.ndarray, b: np.ndarray, K: int, max_iter: int = 30,
            rtol: float = 0.0, atol: float = 0.0, ctol: float = 2.0 ** -208, ozaki: int = 0,
-           escalate: bool = False, stag_ratio: float = 0.0) -> dict:
+           escalate: bool = False, stag_ratio: float = 0.0, long_words: int = 4) -> dict:
     """Mixed-precision iterative refinement, Listing 1 of the paper (Sec. 2).
 
     A: (aw, n, n) with aw = 1 (binary64 entries) or 4 (quad-double entries).
-    b: (4, n) quad-double.  Factor precision K words; long precision is
-    quad-double with an exact residual rounded once (the reading of the
-    residual step).  Steps, in the listing's order:
+    b: (m, n), m <= long_words words (zero-extended).  Factor precision K
+    words; the long precision is L = long_words binary64 words, 4
+    (quad-double) or 8 (424 bits, the long precision of the paper's Table
+    2), with an exact residual rounded once to L words (the reading of the
+    residual step); x and the update x + z are L-word.  Steps, in the
+    listing's order:
       ||A||_F; K-word copies of A and b; LU + substitution; x to long;
       loop: r = b - A x; stop if ||r|| < sqrt(n) rtol ||A||_F ||x|| + atol
       (the listing's test, eq. (2)) or if the previous correction satisfied
@@ -349,9 +354,11 @@ def refine(A: np.ndarray, b: np.ndarray, K: int, max_iter: int = 30,
     ||A||_F (leading words).
     """
     A = _c(A)
-    b = _c(b)
+    lw = long_words
+    assert lw in (4, 8) and b.shape[0] <= lw
+    b = extend(_c(b), lw)
     aw, n, _ = A.shape
-    out = dict(x=np.zeros((4, n)), iters=0, status=NONFINITE, info=0, history=[], final_words=K, escalations=0)
+    out = dict(x=np.zeros((lw, n)), iters=0, status=NONFINITE, info=0, history=[], final_words=K, escalations=0)
     if not (np.isfinite(A).all() and np.isfinite(b).all()):
         return out
     norm_a = norm2(A[0])
@@ -372,7 +379,7 @@ def refine(A: np.ndarray, b: np.ndarray, K: int, max_iter: int = 30,
     if info:
         out.update(status=SINGULAR)
         return out
-    x = extend(getrs(kc, LU, ipiv, round_words(kc, b)))
+    x = extend(getrs(kc, LU, ipiv, round_words(kc, b)), lw)
     hist = []
     iters = 0
     status = MAX_ITER
@@ -407,9 +414,9 @@ def refine(A: np.ndarray, b: np.ndarray, K: int, max_iter: int = 30,
             break
         e = math.frexp(float(np.abs(r[0]).max()))[1] - 1
         rf = round_words(kc, np.ldexp(r, -e))
-        z = np.ldexp(extend(getrs(kc, LU, ipiv, rf)), e)
+        z = np.ldexp(extend(getrs(kc, LU, ipiv, rf), lw), e)
         zs.append(float(np.abs(z[0]).max()))
-        x = add(4, x, z)
+        x = add(lw, x, z)
         iters += 1
     out.update(x=x, iters=iters, status=status, history=hist)
     return out

@@ -40,7 +40,8 @@
 #include <stdlib.h>
 #include <string.h>
 
-#define KMAX 4
+#define KMAX 4  /* words of a factor */
+#define WMAX 8  /* words of a long-precision value (424 bits) */
 #define LVMAX 32
 
 /* Number of OpenMP threads the loops below use (n < 1: the runtime's
@@ -152,7 +153,7 @@ static void level_sum(int K, level_t *L, double *out)
  */
 static void mw_fms(int K, const double *c, const double *a, const double *b, double *out)
 {
-    level_t L[KMAX];
+    level_t L[WMAX];
     for (int lv = 0; lv < K; ++lv)
         L[lv].n = 0;
     double sg = 1.0;
@@ -174,7 +175,7 @@ static void mw_fms(int K, const double *c, const double *a, const double *b, dou
             }
         }
     }
-    double lvl[KMAX];
+    double lvl[WMAX];
     level_sum(K, L, lvl);
     renorm(K, lvl, K, out);
 }
@@ -187,13 +188,13 @@ static void mw_mul(int K, const double *a, const double *b, double *out)
 /* a + b: level lv gets (a_lv, b_lv); then level_sum and renorm. */
 static void mw_add(int K, const double *a, const double *b, double *out)
 {
-    level_t L[KMAX];
+    level_t L[WMAX];
     for (int lv = 0; lv < K; ++lv) {
         L[lv].n = 0;
         push(&L[lv], a[lv]);
         push(&L[lv], b[lv]);
     }
-    double lvl[KMAX];
+    double lvl[WMAX];
     level_sum(K, L, lvl);
     renorm(K, lvl, K, out);
 }
@@ -207,7 +208,7 @@ static int recip_steps(int K) { return K == 1 ? 0 : (K == 2 ? 1 : 2); }
  */
 static void mw_recip(int K, const double *a, double *out)
 {
-    double r[KMAX] = {0}, e[KMAX], nr[KMAX], one[KMAX] = {0};
+    double r[WMAX] = {0}, e[WMAX], nr[WMAX], one[WMAX] = {0};
     one[0] = 1.0;
     r[0] = 1.0 / a[0];
     for (int it = 0; it < recip_steps(K); ++it) {
@@ -269,7 +270,7 @@ void orc_two_prod(int64_t n, const double *a, const double *b, double *p, double
 void orc_fms_vec(int K, int64_t n, const double *c, const double *a, const double *b, double *out)
 {
     for (int64_t i = 0; i < n; ++i) {
-        double cv[KMAX], av[KMAX], bv[KMAX], o[KMAX];
+        double cv[WMAX], av[WMAX], bv[WMAX], o[WMAX];
         gather(K, c, n, i, cv);
         gather(K, a, n, i, av);
         gather(K, b, n, i, bv);
@@ -291,7 +292,7 @@ void orc_gemm(int K, int64_t m, int64_t n, int64_t k, const double *A, int64_t l
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t j = 0; j < n; ++j)
         for (int64_t i = 0; i < m; ++i) {
-            double c[KMAX], a[KMAX], b[KMAX], o[KMAX];
+            double c[WMAX], a[WMAX], b[WMAX], o[WMAX];
             for (int w = 0; w < K; ++w)
                 c[w] = C[w * ldpc + j * ldc + i];
             for (int64_t l = 0; l < k; ++l) {
@@ -311,7 +312,7 @@ void orc_gemm(int K, int64_t m, int64_t n, int64_t k, const double *A, int64_t l
 void orc_mul_vec(int K, int64_t n, const double *a, const double *b, double *out)
 {
     for (int64_t i = 0; i < n; ++i) {
-        double av[KMAX], bv[KMAX], o[KMAX];
+        double av[WMAX], bv[WMAX], o[WMAX];
         gather(K, a, n, i, av);
         gather(K, b, n, i, bv);
         mw_mul(K, av, bv, o);
@@ -322,7 +323,7 @@ void orc_mul_vec(int K, int64_t n, const double *a, const double *b, double *out
 void orc_add_vec(int K, int64_t n, const double *a, const double *b, double *out)
 {
     for (int64_t i = 0; i < n; ++i) {
-        double av[KMAX], bv[KMAX], o[KMAX];
+        double av[WMAX], bv[WMAX], o[WMAX];
         gather(K, a, n, i, av);
         gather(K, b, n, i, bv);
         mw_add(K, av, bv, o);
@@ -333,18 +334,18 @@ void orc_add_vec(int K, int64_t n, const double *a, const double *b, double *out
 void orc_recip_vec(int K, int64_t n, const double *a, double *out)
 {
     for (int64_t i = 0; i < n; ++i) {
-        double av[KMAX], o[KMAX];
+        double av[WMAX], o[WMAX];
         gather(K, a, n, i, av);
         mw_recip(K, av, o);
         scatter(K, out, n, i, o);
     }
 }
 
-/* Round m-word values (m <= 4, word-major, stride n) to K words. */
+/* Round m-word values (m <= 8, word-major, stride n) to K <= 8 words. */
 void orc_round_vec(int K, int m, int64_t n, const double *src, double *out)
 {
     for (int64_t i = 0; i < n; ++i) {
-        double v[KMAX], o[KMAX];
+        double v[WMAX], o[WMAX];
         gather(m, src, n, i, v);
         renorm(K, v, m, o);
         scatter(K, out, n, i, o);
@@ -355,7 +356,7 @@ void orc_round_vec(int K, int m, int64_t n, const double *src, double *out)
 void orc_key_gt_vec(int K, int64_t n, const double *a, const double *b, int32_t *gt)
 {
     for (int64_t i = 0; i < n; ++i) {
-        double av[KMAX], bv[KMAX];
+        double av[WMAX], bv[WMAX];
         gather(K, a, n, i, av);
         gather(K, b, n, i, bv);
         gt[i] = key_gt(K, av, bv);
@@ -399,7 +400,7 @@ static int is_zero(int K, const double *v)
 int64_t orc_getrf(int K, int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv)
 {
     int64_t info = 0;
-    double best[KMAX], v[KMAX], r[KMAX], o[KMAX];
+    double best[WMAX], v[WMAX], r[WMAX], o[WMAX];
     for (int64_t k = 0; k < n; ++k) {
         int64_t p = k;
         load(K, A, lda, ldp, k, k, best);
@@ -433,7 +434,7 @@ int64_t orc_getrf(int K, int64_t n, double *A, int64_t lda, int64_t ldp, int64_t
         }
 #pragma omp parallel for schedule(static) if (n - k > 32)
         for (int64_t j = k + 1; j < n; ++j) {
-            double u[KMAX], l[KMAX], w[KMAX], q[KMAX];
+            double u[WMAX], l[WMAX], w[WMAX], q[WMAX];
             load(K, A, lda, ldp, k, j, u);
             for (int64_t i = k + 1; i < n; ++i) {
                 load(K, A, lda, ldp, i, k, l);
@@ -457,7 +458,7 @@ int64_t orc_getrf(int K, int64_t n, double *A, int64_t lda, int64_t ldp, int64_t
 void orc_getrs(int K, int64_t n, int64_t nrhs, const double *LU, int64_t lda, int64_t ldp,
                const int64_t *ipiv, double *B, int64_t ldb, int64_t ldpb)
 {
-    double yk[KMAX], v[KMAX], l[KMAX], o[KMAX], r[KMAX];
+    double yk[WMAX], v[WMAX], l[WMAX], o[WMAX], r[WMAX];
 #define BT(i, c, w) B[(int64_t)(w) * ldpb + (int64_t)(c) * ldb + (i)]
     for (int64_t c = 0; c < nrhs; ++c) {
         for (int64_t k = 0; k < n; ++k) {
@@ -594,7 +595,7 @@ static void oz_cut(int K, int s, int E, double *v, double *sl)
  * layout as x; may be NULL), all with the one scale E. */
 void orc_oz_slices(int K, int s, int64_t m, const double *x, int32_t E, double *sl, double *rem)
 {
-    double v[KMAX], o[OZ_SMAX];
+    double v[WMAX], o[OZ_SMAX];
     for (int64_t i = 0; i < m; ++i) {
         gather(K, x, m, i, v);
         oz_cut(K, s, E, v, o);
@@ -626,7 +627,7 @@ int orc_oz_update(int K, int s, int64_t m, int64_t nc, int64_t kb, const double 
     /* slices of the rows of L: Ls[(q*kb + k)*m + i] */
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < m; ++i) {
-        double v[KMAX], o[OZ_SMAX];
+        double v[WMAX], o[OZ_SMAX];
         int E = oz_scale(L + i, kb, ldl);
         for (int64_t k = 0; k < kb; ++k) {
             for (int w = 0; w < K; ++w)
@@ -639,7 +640,7 @@ int orc_oz_update(int K, int s, int64_t m, int64_t nc, int64_t kb, const double 
     /* slices of the columns of U: Us[(q*nc + j)*kb + k] */
 #pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < nc; ++j) {
-        double v[KMAX], o[OZ_SMAX];
+        double v[WMAX], o[OZ_SMAX];
         int F = oz_scale(U + j * ldu, kb, 1);
         for (int64_t k = 0; k < kb; ++k) {
             for (int w = 0; w < K; ++w)
@@ -652,7 +653,7 @@ int orc_oz_update(int K, int s, int64_t m, int64_t nc, int64_t kb, const double 
 #pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < nc; ++j)
         for (int64_t i = 0; i < m; ++i) {
-            double c[KMAX], a[KMAX], t[KMAX];
+            double c[WMAX], a[WMAX], t[WMAX];
             for (int w = 0; w < K; ++w)
                 c[w] = C[w * ldpc + j * ldc + i];
             for (int d = 0; d < s; ++d) {
@@ -689,7 +690,7 @@ int64_t orc_getrf_ozaki(int K, int64_t n, double *A, int64_t lda, int64_t ldp, i
     if (nb < 1 || nb > OZ_KBMAX || s < 1 || s > OZ_SMAX)
         return -2;
     int64_t info = 0;
-    double best[KMAX], v[KMAX], r[KMAX], o[KMAX];
+    double best[WMAX], v[WMAX], r[WMAX], o[WMAX];
     for (int64_t j0 = 0; j0 < n; j0 += nb) {
         int64_t jb = n - j0 < nb ? n - j0 : nb;
         int64_t je = j0 + jb;
@@ -725,7 +726,7 @@ int64_t orc_getrf_ozaki(int K, int64_t n, double *A, int64_t lda, int64_t ldp, i
             }
 #pragma omp parallel for schedule(static) if (n - k > 32)
             for (int64_t j = k + 1; j < je; ++j) {
-                double u[KMAX], l[KMAX], w[KMAX], q[KMAX];
+                double u[WMAX], l[WMAX], w[WMAX], q[WMAX];
                 load(K, A, lda, ldp, k, j, u);
                 for (int64_t i = k + 1; i < n; ++i) {
                     load(K, A, lda, ldp, i, k, l);
@@ -740,7 +741,7 @@ int64_t orc_getrf_ozaki(int K, int64_t n, double *A, int64_t lda, int64_t ldp, i
 #pragma omp parallel for schedule(static)
         for (int64_t j = je; j < n; ++j)
             for (int64_t k = j0; k < je; ++k) {
-                double u[KMAX], l[KMAX], w[KMAX], q[KMAX];
+                double u[WMAX], l[WMAX], w[WMAX], q[WMAX];
                 load(K, A, lda, ldp, k, j, u);
                 for (int64_t i = k + 1; i < je; ++i) {
                     load(K, A, lda, ldp, i, k, l);
@@ -918,13 +919,15 @@ static int bf_to_words(bigfix_t *A, int K, double *out)
 }
 
 /*
- * r = b - A x, computed exactly and rounded once to the canonical 4-word
- * form.  A has aw words (1: binary64 entries, 4: quad-double entries),
- * column-major n x n per plane (lda, ldpa); x, b, r are 4-plane vectors
- * (plane strides ldx, ldb, ldr).  Returns the number of rows whose rounded
- * words fell outside the binary64 normal range (0 for every workload here).
+ * r = b - A x, computed exactly and rounded once to the canonical lw-word
+ * form (lw = 4: quad-double; lw = 8: the 424-bit long precision of the
+ * paper's Table 2).  A has aw words (1: binary64 entries, 4: quad-double
+ * entries), column-major n x n per plane (lda, ldpa); x, b, r are lw-plane
+ * vectors (plane strides ldx, ldb, ldr).  Returns the number of rows whose
+ * rounded words fell outside the binary64 normal range (0 for every
+ * workload here).
  */
-int64_t orc_residual(int64_t n, int aw, const double *A, int64_t lda, int64_t ldpa, const double *x,
+int64_t orc_residual(int64_t n, int aw, int lw, const double *A, int64_t lda, int64_t ldpa, const double *x,
                      int64_t ldx, const double *b, int64_t ldb, double *r, int64_t ldr)
 {
     int64_t bad_rows = 0;
@@ -932,18 +935,18 @@ int64_t orc_residual(int64_t n, int aw, const double *A, int64_t lda, int64_t ld
     for (int64_t i = 0; i < n; ++i) {
         bigfix_t *acc = (bigfix_t *)malloc(sizeof(bigfix_t));
         memset(acc, 0, sizeof(bigfix_t));
-        for (int w = 0; w < 4; ++w)
+        for (int w = 0; w < lw; ++w)
             bf_add_double(acc, b[w * ldb + i], +1);
         for (int64_t j = 0; j < n; ++j)
             for (int u = 0; u < aw; ++u) {
                 double a = A[u * ldpa + j * lda + i];
-                for (int w = 0; w < 4; ++w)
+                for (int w = 0; w < lw; ++w)
                     bf_add_product(acc, a, x[w * ldx + j], -1);
             }
-        double o[4];
-        if (bf_to_words(acc, 4, o))
+        double o[WMAX];
+        if (bf_to_words(acc, lw, o))
             ++bad_rows;
-        for (int w = 0; w < 4; ++w)
+        for (int w = 0; w < lw; ++w)
             r[w * ldr + i] = o[w];
         free(acc);
     }

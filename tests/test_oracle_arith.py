@@ -240,3 +240,54 @@ def test_norm2_against_exact():
         assert abs(Fraction(got) - ref) <= Fraction(2) ** -51 * ref, (v[:4], got, float(ref))
     assert O.norm2(np.array([3.0, 4.0])) == 5.0
     assert O.norm2(np.array([-7.5])) == 7.5
+
+
+# ---- the 424-bit long precision (8 words; Table 2 of Kouya 2021) -----------
+
+def test_eight_word_add_bound_and_identities():
+    """x <- x + z of the refinement in the 8-word long precision: within
+    4 * 2^-424 (|a| + |b|) of the exact sum (Fraction), non-overlapping
+    words, and exact identities; half the cases add a correction 2^-60 to
+    2^-300 the size of x, as the refinement does."""
+    g = np.random.default_rng(950)
+    K, n = 8, 600
+    a = rand_words(g, K, n)
+    b = rand_words(g, K, n)
+    b[:, ::2] = np.ldexp(b[:, ::2], -g.integers(60, 300, size=b[:, ::2].shape[1]))
+    s = O.add(K, a, b)
+    u = Fraction(2) ** (-53 * K)
+    for i in range(n):
+        av, bv = value(a[:, i]), value(b[:, i])
+        assert abs(value(s[:, i]) - (av + bv)) <= 4 * u * (abs(av) + abs(bv)), i
+    for w in range(K - 1):
+        assert np.all(np.abs(s[w + 1]) <= np.ldexp(np.abs(s[w]), -51))
+    np.testing.assert_array_equal(O.add(K, a, np.zeros((K, n))), a)
+    np.testing.assert_array_equal(O.add(K, a, -a), np.zeros((K, n)))
+
+
+def test_eight_word_to_short_rounding_is_greedy():
+    """The 424-bit residual rounded to the factor's K words (the listing's
+    long -> short conversion) is the canonical K-word rounding of its exact
+    value, for every K < 8, and K = 8 keeps it exactly."""
+    g = np.random.default_rng(951)
+    src = rand_words(g, 8, 400, spread=40)
+    for K in (1, 2, 3, 4, 8):
+        out = O.round_words(K, src)
+        for i in range(src.shape[1]):
+            if K == 8:
+                assert value(out[:, i]) == value(src[:, i])
+            else:
+                assert list(out[:, i]) == canon(value(src[:, i]), K), (K, i)
+
+
+def test_exact_rounding_to_eight_words_matches_fraction():
+    g = np.random.default_rng(952)
+    for trial in range(40):
+        m = int(g.integers(1, 40))
+        p = adversarial_doubles(g, m)
+        q = adversarial_doubles(g, m)
+        s = g.choice([-1, 1], size=m).astype(np.int32)
+        got, bad = O.exact_round(8, p, q, s)
+        exact = sum((int(s[t]) * Fraction(p[t]) * Fraction(q[t]) for t in range(m)), Fraction(0))
+        assert not bad
+        assert list(got) == canon(exact, 8)

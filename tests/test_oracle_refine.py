@@ -232,3 +232,99 @@ def test_stopping_rule_atol_alone():
     assert res["status"] == O.CONVERGED and res["iters"] == 0
     res = O.refine(Ap, b, 3, atol=0.0, rtol=0.0, ctol=0.0, max_iter=3)
     assert res["status"] == O.MAX_ITER and res["iters"] == 3
+
+
+# ---- the 424-bit long precision (8 words), the setting of Table 2 --------
+
+def rand_words_vec(g, L, n, scale=1.0):
+    out = np.zeros((L, n))
+    for i in range(n):
+        q = Fraction(0)
+        for w in range(L + 2):
+            q += Fraction(float(g.uniform(-1, 1))) * Fraction(2) ** (-53 * w)
+        out[:, i] = X.canon(q * Fraction(scale), L)
+    return out
+
+
+@pytest.mark.parametrize("aw", [1, 4])
+def test_residual_eight_words_bitexact_vs_fraction(aw):
+    g = np.random.default_rng(17 + aw)
+    for n in (1, 3, 7):
+        A = np.zeros((aw, n, n))
+        for i in range(n):
+            for j in range(n):
+                q = sum((Fraction(float(g.uniform(-1, 1))) * Fraction(2) ** (-53 * w) for w in range(aw + 1)),
+                        Fraction(0))
+                A[:, j, i] = X.canon(q, aw)
+        x = rand_words_vec(g, 8, n)
+        b = rand_words_vec(g, 8, n, scale=2.0 ** int(g.integers(-3, 4)))
+        r = O.residual(A, x, b)
+        ex = X.residual([[A[:, j, i] for j in range(n)] for i in range(n)],
+                        [x[:, j] for j in range(n)], [b[:, i] for i in range(n)])
+        for i in range(n):
+            assert list(r[:, i]) == X.canon(ex[i], 8)
+
+
+def max_rel_err(x, xs):
+    """max_i |x_i - xs_i| / |xs_i| (xs_i = 0: absolute) from the exact value
+    of each L-word entry."""
+    m = Fraction(0)
+    for i in range(x.shape[1]):
+        t = Fraction(float(xs[i]))
+        d = abs(X.value(x[:, i]) - t)
+        m = max(m, d / abs(t) if t != 0 else d)
+    return float(m)
+
+
+@pytest.mark.parametrize("K", [2, 3, 4])
+def test_long_precision_goes_beyond_quad_double(K):
+    """With an 8-word x and residual the refinement is no longer limited by
+    the quad-double floor (~1e-64): the forward test at 2^-415 gives x* = 1
+    to better than 1e-120, and eq. (2) with the paper's rtol = 1e-100 stops
+    with a forward error below kappa * sqrt(n) * 1e-100."""
+    n = 64
+    Ap, b, exact = synth.problem("randsvd", n, config=2, instance=0, cond=1e10)
+    assert exact
+    res = O.refine(Ap, b, K, long_words=8, ctol=2.0 ** -415)
+    assert res["status"] == O.CONVERGED and res["x"].shape == (8, n)
+    assert max_rel_err(res["x"], np.ones(n)) <= 1e-120
+    res = O.refine(Ap, b, K, long_words=8, ctol=0.0, rtol=1e-100)
+    assert res["status"] == O.CONVERGED
+    assert max_rel_err(res["x"], np.ones(n)) <= 1e10 * np.sqrt(n) * 1e-100
+
+
+def test_long_precision_needed_for_rtol_1e_minus_100():
+    """A right-hand side whose solution has no short representation (random
+    424-bit b): eq. (2) with rtol = 1e-100 is met in the 8-word long
+    precision, while a quad-double x cannot bring the residual below about
+    2^-212 |A| |x| and the loop runs out of corrections."""
+    n = 48
+    Ap, _, _ = synth.problem("randsvd", n, config=2, instance=5, cond=1e6)
+    g = np.random.default_rng(5)
+    b8 = rand_words_vec(g, 8, n)
+    res = O.refine(Ap, b8, 3, long_words=8, ctol=0.0, rtol=1e-100)
+    assert res["status"] == O.CONVERGED
+    thr = np.sqrt(n) * 1e-100 * res["a_norm"]
+    assert res["resid_norm"] < thr * res["x_norm"]
+    q = O.refine(Ap, O.round_words(4, b8), 3, long_words=4, ctol=0.0, rtol=1e-100, max_iter=8)
+    assert q["status"] == O.MAX_ITER
+    assert q["resid_norm"] > thr * q["x_norm"]
+
+
+def test_paper_system_table2_setting():
+    """The paper's system A = R D R^-1 (kappa_2 = 10^(26 (n-1)/n)), x = [0..n-1],
+    refined from DD, TD and QD factors in the 424-bit long precision with
+    eq. (2), rtol = 1e-100 (Table 2's setting, here at n = 40): every factor
+    reaches a maximum relative error below kappa * sqrt(n) * 1e-100, and more
+    factor words need fewer corrections (Table 2: 15 / 2 / 1 at n = 2000)."""
+    n = 40
+    Ap, b, exact, xs = synth.paper_problem(n)
+    assert exact
+    iters = {}
+    for K in (2, 3, 4):
+        res = O.refine(Ap, b, K, long_words=8, ctol=0.0, rtol=1e-100, max_iter=40)
+        assert res["status"] == O.CONVERGED
+        kappa = 10.0 ** (26 * (n - 1) / n)
+        assert max_rel_err(res["x"], xs) <= kappa * np.sqrt(n) * 1e-100, K
+        iters[K] = res["iters"]
+    assert iters[2] > iters[3] >= iters[4] >= 1
