@@ -236,6 +236,11 @@ typedef struct bnc_refine_opts {
                              or 256 (0 = 256); systems of order above it get
                              BNC_BAD_SIZE.  Both are tuning knobs that leave
                              every result unchanged; bnc_refine ignores them. */
+    int32_t long_words;   /* words of the long precision (x, b and the
+                             residual): 4 (quad-double; 0 means 4) or 8
+                             (424 bits, the long precision of Table 2).
+                             Batched solves take 0 or 4. */
+    int32_t reserved;     /* 0 */
 } bnc_refine_opts;
 
 /* Outcome of the refinement loop (host struct, filled synchronously). */
@@ -262,14 +267,16 @@ size_t bnc_refine_workspace_size(int64_t n, int32_t factor_words);
  * short-precision (K-word) copies of A and b, LU + substitution, x to the
  * long precision; then repeat: r = b - A x, the stopping tests, r scaled by a
  * power of two 2^-e (the listing's normalisation), K-word copy of r,
- * substitution -> z, x <- x + 2^e z.  The long precision is quad-double: the
- * residual is accumulated exactly from error-free products and rounded once
- * to canonical quad-double; x is quad-double.
+ * substitution -> z, x <- x + 2^e z.  The long precision is L =
+ * opts->long_words binary64 words, quad-double (L = 4) or 424 bits (L = 8,
+ * the long precision of Table 2): the residual is accumulated exactly from
+ * error-free products and rounded once to its canonical L-word form; x and
+ * the update are L-word.
  *   n        order (>= 1)
  *   a_words  words per entry of A: 1 (binary64) or 4 (quad-double)
  *   A, lda, ldpa  a_words-plane matrix (not modified)
- *   b, ldpb  4-plane right-hand side (not modified)
- *   x, ldpx  4-plane solution (output)
+ *   b, ldpb  L-plane right-hand side (not modified)
+ *   x, ldpx  L-plane solution (output)
  *   work, work_bytes  caller workspace, >= bnc_refine_workspace_size(n, K)
  *   opts     host options; result  host outcome
  * Synchronous: returns after the loop has finished (it reads the stopping
@@ -415,18 +422,20 @@ typedef struct bnc_adam_opts {
 int bnc_mlp_adam(float *params, const float *grads, float *m, float *v, const bnc_adam_opts *opts, void *stream);
 
 /*
- * r = b - A x computed exactly and rounded once to canonical quad-double
+ * r = b - A x computed exactly and rounded once to its canonical L-word form
  * (w0 = nearest binary64 to the value, w1 nearest to the remainder, ...):
  * the residual step of Listing 1 in the long precision.  A has a_words
- * planes (1 or 4); x, b, r are 4-plane vectors.  *inexact (device int32)
- * is set to 1 if a row had bits below its 476-bit accumulator window
- * (then the row is faithful, not exactly rounded); it is not cleared.
+ * planes (1 or 4); x, b, r are L-plane vectors, L = long_words (4 or 8).
+ * *inexact (device int32) is set to 1 if a row had bits below its
+ * 1360-bit accumulator window (then the row is faithful, not exactly
+ * rounded); it is not cleared.  Rows may hold at most 2^19 - 1 terms
+ * (2 a_words L n + L), else BNC_ERR_UNSUPPORTED.
  * work, work_bytes: >= bnc_residual_workspace_size(n) bytes (row maxima and
  * the partial bin sums).
  */
-int bnc_residual(int64_t n, int32_t a_words, const double *A, int64_t lda, int64_t ldpa, const double *x,
-                 int64_t ldpx, const double *b, int64_t ldpb, double *r, int64_t ldpr, int32_t *inexact,
-                 void *work, size_t work_bytes, void *stream);
+int bnc_residual(int64_t n, int32_t a_words, int32_t long_words, const double *A, int64_t lda, int64_t ldpa,
+                 const double *x, int64_t ldpx, const double *b, int64_t ldpb, double *r, int64_t ldpr,
+                 int32_t *inexact, void *work, size_t work_bytes, void *stream);
 size_t bnc_residual_workspace_size(int64_t n);
 
 /*

@@ -32,7 +32,7 @@ class RefineOpts(ctypes.Structure):
     _fields_ = [("factor_words", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("rtol", ctypes.c_double),
                 ("atol", ctypes.c_double), ("ctol", ctypes.c_double), ("ozaki_slices", ctypes.c_int32),
                 ("escalate", ctypes.c_int32), ("stagnation_ratio", ctypes.c_double), ("batch_panel", ctypes.c_int32),
-                ("batch_threads", ctypes.c_int32)]
+                ("batch_threads", ctypes.c_int32), ("long_words", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class RefineResult(ctypes.Structure):
@@ -114,7 +114,7 @@ def _load() -> ctypes.CDLL:
     L.bnc_refine_batched_graph.restype = ctypes.c_int
     L.bnc_graph_destroy.argtypes = [VP]
     L.bnc_wall_clock_khz.restype = ctypes.c_int64
-    L.bnc_residual.argtypes = [I64, I32, VP, I64, I64, VP, I64, VP, I64, VP, I64, VP, VP, SZ, VP]
+    L.bnc_residual.argtypes = [I64, I32, I32, VP, I64, I64, VP, I64, VP, I64, VP, I64, VP, VP, SZ, VP]
     L.bnc_residual.restype = ctypes.c_int
     L.bnc_mw_apply.argtypes = [I32, I32, I64, VP, VP, VP, VP, VP]
     L.bnc_mw_apply.restype = ctypes.c_int
@@ -247,19 +247,19 @@ def refine_workspace_size(n: int, K: int) -> int:
 
 def refine(A: torch.Tensor, b: torch.Tensor, K: int, max_iter: int = 30, rtol: float = 0.0, atol: float = 0.0,
            ctol: float = 2.0 ** -208, x: torch.Tensor | None = None, work: torch.Tensor | None = None,
-           ozaki: int = 0, escalate: bool = False, stagnation_ratio: float = 0.0) -> dict:
-    """Listing 1 of the paper with a K-word factorisation and a quad-double
-    long precision.  A: (aw, n, n) with aw = 1 or 4; b: (4, n); ozaki = S > 0
-    factors with the split trailing update (S slices); escalate and
-    stagnation_ratio as in bnc_refine_opts.  Returns a dict with x (4, n)
-    and the outcome fields."""
+           ozaki: int = 0, escalate: bool = False, stagnation_ratio: float = 0.0, long_words: int = 4) -> dict:
+    """Listing 1 of the paper with a K-word factorisation and an L-word long
+    precision, L = long_words (4: quad-double, 8: 424 bits).  A: (aw, n, n)
+    with aw = 1 or 4; b: (L, n); ozaki = S > 0 factors with the split
+    trailing update (S slices); escalate and stagnation_ratio as in
+    bnc_refine_opts.  Returns a dict with x (L, n) and the outcome fields."""
     aw, n = A.shape[0], A.shape[1]
     if x is None:
-        x = torch.empty((4, n), dtype=torch.float64, device=A.device)
+        x = torch.empty((long_words, n), dtype=torch.float64, device=A.device)
     need = refine_workspace_size(n, 4 if escalate else K)
     if work is None or work.numel() < need:
         work = torch.empty(need, dtype=torch.uint8, device=A.device)
-    o = RefineOpts(K, max_iter, rtol, atol, ctol, ozaki, 1 if escalate else 0, stagnation_ratio, 0, 0)
+    o = RefineOpts(K, max_iter, rtol, atol, ctol, ozaki, 1 if escalate else 0, stagnation_ratio, 0, 0, long_words, 0)
     r = RefineResult()
     _check(_lib.bnc_refine(n, aw, _dev(A, "A", 3), n, n * n, _dev(b, "b", 2), n, _dev(x, "x", 2), n,
                            ctypes.c_void_p(work.data_ptr()), work.numel(), ctypes.byref(o), ctypes.byref(r),
@@ -299,7 +299,7 @@ class BatchSolver:
         self.slots = slots
         need = int(_lib.bnc_refine_batched_workspace_size(K, slots))
         self.work = torch.empty(need, dtype=torch.uint8, device=dev)
-        self.opts = RefineOpts(K, max_iter, rtol, atol, ctol, 0, 0, stagnation_ratio, panel, threads)
+        self.opts = RefineOpts(K, max_iter, rtol, atol, ctol, 0, 0, stagnation_ratio, panel, threads, 0, 0)
         self.graph = ctypes.c_void_p(None)
         self.stream = None
 
@@ -339,12 +339,16 @@ def wall_clock_khz() -> int:
 
 
 def residual(A: torch.Tensor, x: torch.Tensor, b: torch.Tensor):
-    """r = b - A x exactly, rounded to canonical quad-double; returns (r, inexact)."""
+    """r = b - A x exactly, rounded to its canonical L-word form (L = the
+    words of x and b, 4 or 8); returns (r, inexact)."""
     aw, n = A.shape[0], A.shape[1]
-    r = torch.empty((4, n), dtype=torch.float64, device=A.device)
+    lw = x.shape[0]
+    if b.shape[0] != lw:
+        raise BncError("residual: x and b must have the same number of words")
+    r = torch.empty((lw, n), dtype=torch.float64, device=A.device)
     flag = torch.zeros(1, dtype=torch.int32, device=A.device)
     work = _workspace(residual_workspace_size(n), A.device)
-    _check(_lib.bnc_residual(n, aw, _dev(A, "A", 3), n, n * n, _dev(x, "x", 2), n, _dev(b, "b", 2), n,
+    _check(_lib.bnc_residual(n, aw, lw, _dev(A, "A", 3), n, n * n, _dev(x, "x", 2), n, _dev(b, "b", 2), n,
                              ctypes.c_void_p(r.data_ptr()), n, ctypes.c_void_p(flag.data_ptr()),
                              ctypes.c_void_p(work.data_ptr()), work.numel(), _stream()), "residual")
     return r, flag

@@ -49,8 +49,8 @@ int mlp_adam_run(float *P, const float *G, float *M, float *V, float lr, float b
 
 size_t refine_workspace_bytes(int64_t n, int K);
 size_t residual_workspace_bytes(int64_t n);
-int residual_ws_run(int64_t n, int aw, const double *A, int64_t lda, int64_t ldpa, const double *x, int64_t ldpx,
-                    const double *b, int64_t ldpb, double *r, int64_t ldpr, int32_t *inexact, void *work,
+int residual_ws_run(int64_t n, int aw, int lw, const double *A, int64_t lda, int64_t ldpa, const double *x,
+                    int64_t ldpx, const double *b, int64_t ldpb, double *r, int64_t ldpr, int32_t *inexact, void *work,
                     hipStream_t s);
 
 // ---- errors -------------------------------------------------------------------
@@ -422,7 +422,7 @@ int bnc_refine(int64_t n, int32_t a_words, const double *A, int64_t lda, int64_t
     if (opts->factor_words < 1 || opts->factor_words > 4 || opts->max_iter < 0 || !(opts->rtol >= 0) ||
         opts->ozaki_slices < 0 || opts->ozaki_slices > OZ_SMAX || (opts->escalate != 0 && opts->escalate != 1) ||
         !batch_panel_ok(opts->batch_panel) || !batch_threads_ok(opts->batch_threads) ||
-        !(opts->stagnation_ratio >= 0) ||
+        !(opts->stagnation_ratio >= 0) || (opts->long_words != 0 && opts->long_words != 4 && opts->long_words != 8) ||
         !(opts->atol >= 0) || !(opts->ctol >= 0))
         return fail_arg(-12, "refine: invalid options");
     if (!result)
@@ -479,6 +479,7 @@ int bnc_refine_batched(int64_t count, const int64_t *n, const double *const *A, 
         return fail_arg(-7, "refine_batched: work is NULL");
     if (!opts || opts->factor_words < 1 || opts->factor_words > 4 || opts->max_iter < 0 || !(opts->rtol >= 0) ||
         opts->ozaki_slices != 0 || opts->escalate != 0 || !(opts->stagnation_ratio >= 0) ||
+        (opts->long_words != 0 && opts->long_words != 4) ||
         !batch_panel_ok(opts->batch_panel) || !batch_threads_ok(opts->batch_threads) ||
         !(opts->atol >= 0) || !(opts->ctol >= 0))
         return fail_arg(-9, "refine_batched: invalid options");
@@ -545,41 +546,44 @@ int64_t bnc_wall_clock_khz(void)
     return khz;
 }
 
-int bnc_residual(int64_t n, int32_t a_words, const double *A, int64_t lda, int64_t ldpa, const double *x,
-                 int64_t ldpx, const double *b, int64_t ldpb, double *r, int64_t ldpr, int32_t *inexact,
-                 void *work, size_t work_bytes, void *stream)
+int bnc_residual(int64_t n, int32_t a_words, int32_t long_words, const double *A, int64_t lda, int64_t ldpa,
+                 const double *x, int64_t ldpx, const double *b, int64_t ldpb, double *r, int64_t ldpr,
+                 int32_t *inexact, void *work, size_t work_bytes, void *stream)
 {
     if (n < 0)
         return fail_arg(-1, "residual: n < 0");
     if (a_words != 1 && a_words != 4)
         return fail_arg(-2, "residual: a_words must be 1 or 4");
+    if (long_words != 4 && long_words != 8)
+        return fail_arg(-3, "residual: long_words must be 4 or 8");
     if (n == 0)
         return BNC_OK;
     if (!A)
-        return fail_arg(-3, "residual: A is NULL");
+        return fail_arg(-4, "residual: A is NULL");
     if (lda < n)
-        return fail_arg(-4, "residual: lda < n");
+        return fail_arg(-5, "residual: lda < n");
     if (a_words > 1 && ldpa < lda * n)
-        return fail_arg(-5, "residual: ldpa < lda * n");
+        return fail_arg(-6, "residual: ldpa < lda * n");
     if (!x)
-        return fail_arg(-6, "residual: x is NULL");
+        return fail_arg(-7, "residual: x is NULL");
     if (ldpx < n)
-        return fail_arg(-7, "residual: ldpx < n");
+        return fail_arg(-8, "residual: ldpx < n");
     if (!b)
-        return fail_arg(-8, "residual: b is NULL");
+        return fail_arg(-9, "residual: b is NULL");
     if (ldpb < n)
-        return fail_arg(-9, "residual: ldpb < n");
+        return fail_arg(-10, "residual: ldpb < n");
     if (!r)
-        return fail_arg(-10, "residual: r is NULL");
+        return fail_arg(-11, "residual: r is NULL");
     if (ldpr < n)
-        return fail_arg(-11, "residual: ldpr < n");
+        return fail_arg(-12, "residual: ldpr < n");
     if (!inexact)
-        return fail_arg(-12, "residual: inexact is NULL");
+        return fail_arg(-13, "residual: inexact is NULL");
     if (!work)
-        return fail_arg(-13, "residual: work is NULL");
+        return fail_arg(-14, "residual: work is NULL");
     if (work_bytes < residual_workspace_bytes(n))
         return fail_arg(BNC_ERR_WORKSPACE, "residual: workspace smaller than bnc_residual_workspace_size");
-    return residual_ws_run(n, a_words, A, lda, ldpa, x, ldpx, b, ldpb, r, ldpr, inexact, work, S(stream));
+    return residual_ws_run(n, a_words, long_words, A, lda, ldpa, x, ldpx, b, ldpb, r, ldpr, inexact, work,
+                           S(stream));
 }
 
 int bnc_mw_apply(int32_t op, int32_t K, int64_t n, const double *c, const double *a, const double *b, double *out,

@@ -1,6 +1,6 @@
-// Exact accumulation of a residual row and its canonical quad-double
-// rounding (the long-precision residual step of Listing 1, Kouya 2021
-// Sec. 2, read as: products split exactly, summed exactly, rounded once).
+// Exact accumulation of a residual row and its canonical rounding to the
+// long precision (the residual step of Listing 1, Kouya 2021 Sec. 2, read
+// as: products split exactly, summed exactly, rounded once).
 //
 // Terms are binary64 numbers (TwoProd halves of A_ij^(u) x_j^(w), and the
 // words of b_i).  Each term is cut into fixed-point digits of W = 34 bits
@@ -10,7 +10,7 @@
 // a bound on the lowest bit of any term (smallest exponents of the words of
 // A, x and b), so every digit sum is exact while the row has < 2^19 terms.
 // The bins are then read as one signed integer (32-bit limbs in int64,
-// carry-save) and rounded greedily to four binary64 words with
+// carry-save) and rounded greedily to four (or eight) binary64 words with
 // round-to-nearest-even.
 #pragma once
 
@@ -205,16 +205,18 @@ __device__ __forceinline__ uint64_t big_round(const Big<NB> &M, int &lsb)
 }
 
 
-// Canonical quad-double of the exact sum held in bins[0..nb) (bin q holds a
-// multiple of 2^(e0 - W q)); returns true if a word fell outside the binary64
-// normal range.  The integer is kept as its magnitude while a word is rounded
-// off it (negated in place), so one limb array suffices.
-template <int NBMAX>
-__device__ __forceinline__ bool bins_to_qd(const double (&bins)[NBMAX], int nb, int e0, double (&out)[4])
+// Canonical LW-word form (greedy round-to-nearest: quad-double for LW = 4,
+// the 424-bit long precision for LW = 8) of the exact sum held in
+// bins[0..nb) (bin q holds a multiple of 2^(e0 - W q)); returns true if a
+// word fell outside the binary64 normal range.  The integer is kept as its
+// magnitude while a word is rounded off it (negated in place), so one limb
+// array suffices.
+template <int NBMAX, int LW>
+__device__ __forceinline__ bool bins_to_words(const double (&bins)[NBMAX], int nb, int e0, double (&out)[LW])
 {
     bool bad = false;
 #pragma unroll
-    for (int w = 0; w < 4; ++w)
+    for (int w = 0; w < LW; ++w)
         out[w] = 0.0;
     Big<NBMAX> B;
 #pragma unroll
@@ -229,7 +231,7 @@ __device__ __forceinline__ bool bins_to_qd(const double (&bins)[NBMAX], int nb, 
             big_add(B, (int64_t)dig, RB_W * (nb - 1 - q));
         }
     }
-    for (int w = 0; w < 4; ++w) {
+    for (int w = 0; w < LW; ++w) {
         big_norm(B);
         const bool neg = B.l[Big<NBMAX>::L - 1] < 0;
         if (neg) {
@@ -255,6 +257,12 @@ __device__ __forceinline__ bool bins_to_qd(const double (&bins)[NBMAX], int nb, 
             big_neg(B);
     }
     return bad;
+}
+
+template <int NBMAX>
+__device__ __forceinline__ bool bins_to_qd(const double (&bins)[NBMAX], int nb, int e0, double (&out)[4])
+{
+    return bins_to_words<NBMAX, 4>(bins, nb, e0, out);
 }
 
 }  // namespace bnc

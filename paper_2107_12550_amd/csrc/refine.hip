@@ -1,5 +1,7 @@
 // Mixed-precision iterative refinement (Kouya 2021, Sec. 2, Listing 1) and
-// its long-precision pieces: the exact residual, norms, the update.
+// its long-precision pieces: the exact residual, norms, the update.  The
+// long precision is LW binary64 words: 4 (quad-double) or 8 (424 bits, the
+// long precision of the paper's Table 2).
 //
 // Residual r = b - A x.  Every product A_ij^(u) x_j^(w) is split exactly by
 // TwoProd; every resulting binary64 term is cut into fixed-point digits of
@@ -10,8 +12,8 @@
 // smallest exponents of the words of A, x and b, so the digit sums are
 // exact: they stay below 2^53 units of their bin for up to 2^19 terms per
 // row.  The bins are then read as one signed integer and rounded greedily
-// to four binary64 words with round-to-nearest-even: the canonical
-// quad-double of the exact residual.  Only data spanning more than 1360
+// to LW binary64 words with round-to-nearest-even: the canonical LW-word
+// form of the exact residual.  Only data spanning more than 1360
 // bits would leave bits below the window; such a row reports "inexact".
 #include <string.h>
 
@@ -39,7 +41,7 @@ constexpr int RED_BLOCKS = 256;  // partial-sum slots of the deterministic reduc
 // partial bins of rows [64*bx, +64); workgroup column split sidx, each wave
 // a quarter of it: split index sidx*4 + wave
 // the deposits of one row's slice of columns into NB bins (nb <= NB used)
-template <int AW, int NB>
+template <int AW, int LW, int NB>
 __device__ __forceinline__ void resid_slice(const double *__restrict__ A, int64_t lda, int64_t ldpa,
                                             const double *__restrict__ x, int64_t ldx, const double *__restrict__ b,
                                             int64_t ldb, int64_t i, int64_t q0, int64_t q1, bool with_b,
@@ -57,19 +59,19 @@ __device__ __forceinline__ void resid_slice(const double *__restrict__ A, int64_
     // register sets taking turns (the loads are unconditional, the next
     // index clamped to the slice), so the deposits of one column run while
     // the next column's loads are in flight
-    auto load = [&](int64_t j, double (&xv)[4], double (&av)[AW]) {
+    auto load = [&](int64_t j, double (&xv)[LW], double (&av)[AW]) {
 #pragma unroll
-        for (int w = 0; w < 4; ++w)
+        for (int w = 0; w < LW; ++w)
             xv[w] = x[w * ldx + j];
 #pragma unroll
         for (int u = 0; u < AW; ++u)
             av[u] = A[u * ldpa + j * lda + i];
     };
-    auto col = [&](const double (&xv)[4], const double (&av)[AW]) {
+    auto col = [&](const double (&xv)[LW], const double (&av)[AW]) {
 #pragma unroll
         for (int u = 0; u < AW; ++u)
 #pragma unroll
-            for (int w = 0; w < 4; ++w) {
+            for (int w = 0; w < LW; ++w) {
                 double lo;
                 const double hi = two_prod(av[u], xv[w], lo);
                 deposit(-hi, sig, bins, nb, lim0, bad);
@@ -79,12 +81,12 @@ __device__ __forceinline__ void resid_slice(const double *__restrict__ A, int64_
     int64_t j = q0;
     if (NB > 16) {  // the rare wide windows: plain loop (their bins already fill the registers)
         for (; j < q1; ++j) {
-            double xv[4], av[AW];
+            double xv[LW], av[AW];
             load(j, xv, av);
             col(xv, av);
         }
     } else if (j < q1) {
-        double x0[4], a0[AW], x1[4], a1[AW];
+        double x0[LW], a0[AW], x1[LW], a1[AW];
         load(j, x0, a0);
         for (; j + 1 < q1; j += 2) {
             load(j + 1, x1, a1);
@@ -97,7 +99,7 @@ __device__ __forceinline__ void resid_slice(const double *__restrict__ A, int64_
     }
     if (with_b) {
 #pragma unroll
-        for (int w = 0; w < 4; ++w)
+        for (int w = 0; w < LW; ++w)
             deposit(b[w * ldb + i], sig, bins, nb, lim0, bad);
     }
 #pragma unroll
@@ -106,7 +108,7 @@ __device__ __forceinline__ void resid_slice(const double *__restrict__ A, int64_
             out[q * stride] = bins[q];
 }
 
-template <int AW>
+template <int AW, int LW>
 __global__ void __launch_bounds__(RES_ROWS *RES_WAVES)
     k_resid_partial(int64_t n, const double *__restrict__ A, int64_t lda, int64_t ldpa, const double *__restrict__ x,
                     int64_t ldx, const double *__restrict__ b, int64_t ldb, const double *__restrict__ rowmax,
@@ -129,11 +131,11 @@ __global__ void __launch_bounds__(RES_ROWS *RES_WAVES)
         double *out = part + (int64_t)split * RB_NB * n + i;
         // the window is usually a few bins wide: deposit loops sized to it
         if (an.nb <= 8)
-            resid_slice<AW, 8>(A, lda, ldpa, x, ldx, b, ldb, i, q0, q1, split == 0, an, out, n, bad);
+            resid_slice<AW, LW, 8>(A, lda, ldpa, x, ldx, b, ldb, i, q0, q1, split == 0, an, out, n, bad);
         else if (an.nb <= 16)
-            resid_slice<AW, 16>(A, lda, ldpa, x, ldx, b, ldb, i, q0, q1, split == 0, an, out, n, bad);
+            resid_slice<AW, LW, 16>(A, lda, ldpa, x, ldx, b, ldb, i, q0, q1, split == 0, an, out, n, bad);
         else
-            resid_slice<AW, RB_NB>(A, lda, ldpa, x, ldx, b, ldb, i, q0, q1, split == 0, an, out, n, bad);
+            resid_slice<AW, LW, RB_NB>(A, lda, ldpa, x, ldx, b, ldb, i, q0, q1, split == 0, an, out, n, bad);
     }
     if (bad)
         atomicOr(inexact, 1);
@@ -195,6 +197,7 @@ __global__ void __launch_bounds__(256)
     part[(int64_t)q * n + i] = s;
 }
 
+template <int LW>
 __global__ void __launch_bounds__(256)
     k_resid_final(int64_t n, int S, const double *__restrict__ part, const double *__restrict__ rowmax,
                   const double *__restrict__ xmaxp, const ExpBounds *__restrict__ ebp, const double *__restrict__ b,
@@ -204,7 +207,10 @@ __global__ void __launch_bounds__(256)
     if (i >= n)
         return;
     const RowAnchor an = row_anchor(rowmax[i], *xmaxp, b[i], h, lowest_bit(*ebp));
-    double out[4] = {0.0, 0.0, 0.0, 0.0};
+    double out[LW];
+#pragma unroll
+    for (int w = 0; w < LW; ++w)
+        out[w] = 0.0;
     bool bad = false;
     if (an.any) {
         double bins[RB_NB];
@@ -216,10 +222,10 @@ __global__ void __launch_bounds__(256)
                     s = s + part[((int64_t)t * RB_NB + q) * n + i];  // S = number of splits
             bins[q] = s;
         }
-        bad = bins_to_qd(bins, an.nb, an.e0, out);
+        bad = bins_to_words<RB_NB, LW>(bins, an.nb, an.e0, out);
     }
 #pragma unroll
-    for (int w = 0; w < 4; ++w)
+    for (int w = 0; w < LW; ++w)
         r[w * ldr + i] = out[w];
     if (bad)
         atomicOr(inexact, 1);
@@ -341,8 +347,8 @@ __global__ void k_sumsq_final(int nparts, const double *__restrict__ part, doubl
     }
 }
 
-// dst (K words) = renorm(src (4 words) * 2^-e), e from the power-of-two max
-template <int K>
+// dst (K words) = renorm(src (LW words) * 2^-e), e from the power-of-two max
+template <int K, int LW>
 __global__ void k_round_scaled(int64_t n, const double *__restrict__ src, int64_t lds_,
                                const unsigned long long *__restrict__ maxbits, double *__restrict__ dst, int64_t ldd)
 {
@@ -350,30 +356,31 @@ __global__ void k_round_scaled(int64_t n, const double *__restrict__ src, int64_
     if (i >= n)
         return;
     const double sc = maxbits ? pow2(-norm_exp(__longlong_as_double((long long)*maxbits))) : 1.0;
-    double v[4], o[K];
+    double v[LW], o[K];
 #pragma unroll
-    for (int w = 0; w < 4; ++w)
+    for (int w = 0; w < LW; ++w)
         v[w] = src[w * lds_ + i] * sc;
-    renorm<K, 4>(v, o);
+    renorm<K, LW>(v, o);
 #pragma unroll
     for (int w = 0; w < K; ++w)
         dst[w * ldd + i] = o[w];
 }
 
-// x = extend(z), quad-double from K words
-template <int K>
+// x = extend(z), LW words from K words
+template <int K, int LW>
 __global__ void k_extend(int64_t n, const double *__restrict__ z, int64_t ldz, double *__restrict__ x, int64_t ldx)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n)
         return;
 #pragma unroll
-    for (int w = 0; w < 4; ++w)
+    for (int w = 0; w < LW; ++w)
         x[w * ldx + i] = w < K ? z[w * ldz + i] : 0.0;
 }
 
 // z <- z * 2^e in place (e from the residual max), then x <- x + extend(z)
-template <int K>
+// in LW-word addition
+template <int K, int LW>
 __global__ void k_scale_update(int64_t n, double *__restrict__ z, int64_t ldz,
                                const unsigned long long *__restrict__ rmaxbits, double *__restrict__ x, int64_t ldx)
 {
@@ -381,18 +388,18 @@ __global__ void k_scale_update(int64_t n, double *__restrict__ z, int64_t ldz,
     if (i >= n)
         return;
     const double sc = pow2(norm_exp(__longlong_as_double((long long)*rmaxbits)));
-    double zv[4], xv[4], o[4];
+    double zv[LW], xv[LW], o[LW];
 #pragma unroll
-    for (int w = 0; w < 4; ++w) {
+    for (int w = 0; w < LW; ++w) {
         zv[w] = w < K ? z[w * ldz + i] * sc : 0.0;
         xv[w] = x[w * ldx + i];
     }
-    add<4>(xv, zv, o);
+    add<LW>(xv, zv, o);
 #pragma unroll
     for (int w = 0; w < K; ++w)
         z[w * ldz + i] = zv[w];
 #pragma unroll
-    for (int w = 0; w < 4; ++w)
+    for (int w = 0; w < LW; ++w)
         x[w * ldx + i] = o[w];
 }
 
@@ -407,10 +414,12 @@ __global__ void k_zero(int64_t n, double *__restrict__ p)
 
 static inline unsigned grid1(int64_t n, int t = 256) { return (unsigned)ceil_div(n > 0 ? n : 1, t); }
 
-static int residual_h(int64_t n, int aw)
+static int64_t residual_terms(int64_t n, int aw, int lw) { return 2 * (int64_t)aw * lw * n + lw; }
+
+static int residual_h(int64_t n, int aw, int lw)
 {
-    // h with 2^h >= 2 * terms; terms per row = 8 * aw * n + 4
-    const int64_t N = 8 * (int64_t)aw * n + 4;
+    // h with 2^h >= 2 * terms; terms per row = 2 * aw * lw * n + lw
+    const int64_t N = residual_terms(n, aw, lw);
     int h = 1;
     while (((int64_t)1 << h) < 2 * N)
         ++h;
@@ -455,33 +464,44 @@ int fill_i32_run(int *p, int64_t n, int v, hipStream_t s)
     return BNC_OK;
 }
 
-// r = b - A x (exact -> canonical quad-double); rowmax, xmax and the
-// exponent bounds precomputed on the device
-int residual_run(int64_t n, int aw, const double *A, int64_t lda, int64_t ldpa, const double *x, int64_t ldx,
+// r = b - A x (exact -> canonical lw-word form); rowmax, xmax and the
+// exponent bounds precomputed on the device; x, b, r have lw words
+int residual_run(int64_t n, int aw, int lw, const double *A, int64_t lda, int64_t ldpa, const double *x, int64_t ldx,
                  const double *b, int64_t ldb, const double *rowmax, const double *xmax, const void *ebounds,
                  double *part, double *r, int64_t ldr, int32_t *inexact, hipStream_t s)
 {
     if (n == 0)
         return BNC_OK;
-    if (8 * (int64_t)aw * n + 4 >= (1LL << 19))
+    if (residual_terms(n, aw, lw) >= (1LL << 19))
         return fail_arg(BNC_ERR_UNSUPPORTED, "residual: too many terms per row for exact accumulation");
-    const int h = residual_h(n, aw);
+    const int h = residual_h(n, aw, lw);
     const int S = residual_splits(n);
     const int64_t chunk = ceil_div(n, S);
     const ExpBounds *eb = (const ExpBounds *)ebounds;
     dim3 grid((unsigned)ceil_div(n, RES_ROWS), (unsigned)S);
-    if (aw == 1)
-        hipLaunchKernelGGL((k_resid_partial<1>), grid, dim3(RES_ROWS * RES_WAVES), 0, s, n, A, lda, ldpa, x, ldx, b,
-                           ldb, rowmax, xmax, eb, h, chunk, part, inexact);
+    const dim3 t(RES_ROWS * RES_WAVES);
+    if (aw == 1 && lw == 4)
+        hipLaunchKernelGGL((k_resid_partial<1, 4>), grid, t, 0, s, n, A, lda, ldpa, x, ldx, b, ldb, rowmax, xmax, eb,
+                           h, chunk, part, inexact);
+    else if (aw == 4 && lw == 4)
+        hipLaunchKernelGGL((k_resid_partial<4, 4>), grid, t, 0, s, n, A, lda, ldpa, x, ldx, b, ldb, rowmax, xmax, eb,
+                           h, chunk, part, inexact);
+    else if (aw == 1)
+        hipLaunchKernelGGL((k_resid_partial<1, 8>), grid, t, 0, s, n, A, lda, ldpa, x, ldx, b, ldb, rowmax, xmax, eb,
+                           h, chunk, part, inexact);
     else
-        hipLaunchKernelGGL((k_resid_partial<4>), grid, dim3(RES_ROWS * RES_WAVES), 0, s, n, A, lda, ldpa, x, ldx, b,
-                           ldb, rowmax, xmax, eb, h, chunk, part, inexact);
+        hipLaunchKernelGGL((k_resid_partial<4, 8>), grid, t, 0, s, n, A, lda, ldpa, x, ldx, b, ldb, rowmax, xmax, eb,
+                           h, chunk, part, inexact);
     BNC_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_resid_sum, dim3((unsigned)ceil_div(n, 64), (unsigned)ceil_div(RB_NB, 4)), dim3(256), 0, s, n,
                        S * RES_WAVES, part, rowmax, xmax, eb, b, h);
     BNC_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_resid_final, dim3(grid1(n)), dim3(256), 0, s, n, 1, (const double *)part, rowmax, xmax, eb,
-                       b, h, r, ldr, inexact);
+    if (lw == 4)
+        hipLaunchKernelGGL(k_resid_final<4>, dim3(grid1(n)), dim3(256), 0, s, n, 1, (const double *)part, rowmax, xmax,
+                           eb, b, h, r, ldr, inexact);
+    else
+        hipLaunchKernelGGL(k_resid_final<8>, dim3(grid1(n)), dim3(256), 0, s, n, 1, (const double *)part, rowmax, xmax,
+                           eb, b, h, r, ldr, inexact);
     BNC_LAUNCH_CHECK();
     return BNC_OK;
 }
@@ -498,8 +518,8 @@ size_t residual_workspace_bytes(int64_t n)
 int rowmax_run(int64_t n, const double *A, int64_t lda, double *rowmax, hipStream_t s);
 int absmax_run(int64_t rows, int64_t cols, int64_t ld, const double *v, unsigned long long *bits, hipStream_t s);
 
-int residual_ws_run(int64_t n, int aw, const double *A, int64_t lda, int64_t ldpa, const double *x, int64_t ldpx,
-                    const double *b, int64_t ldpb, double *r, int64_t ldpr, int32_t *inexact, void *work,
+int residual_ws_run(int64_t n, int aw, int lw, const double *A, int64_t lda, int64_t ldpa, const double *x,
+                    int64_t ldpx, const double *b, int64_t ldpb, double *r, int64_t ldpr, int32_t *inexact, void *work,
                     hipStream_t s)
 {
     if (n == 0)
@@ -512,9 +532,9 @@ int residual_ws_run(int64_t n, int aw, const double *A, int64_t lda, int64_t ldp
     int rc;
     if ((rc = rowmax_run(n, A, lda, rowmax, s)) || (rc = absmax_run(n, 1, n, x, xmax, s)) ||
         (rc = fill_i32_run(eb, 3, 2000, s)) || (rc = minexp_run(n, n, lda, aw, ldpa, A, eb, s)) ||
-        (rc = minexp_run(n, 1, n, 4, ldpx, x, eb + 1, s)) || (rc = minexp_run(n, 1, n, 4, ldpb, b, eb + 2, s)))
+        (rc = minexp_run(n, 1, n, lw, ldpx, x, eb + 1, s)) || (rc = minexp_run(n, 1, n, lw, ldpb, b, eb + 2, s)))
         return rc;
-    return residual_run(n, aw, A, lda, ldpa, x, ldpx, b, ldpb, rowmax, (const double *)xmax, eb, part, r, ldpr,
+    return residual_run(n, aw, lw, A, lda, ldpa, x, ldpx, b, ldpb, rowmax, (const double *)xmax, eb, part, r, ldpr,
                         inexact, s);
 }
 
@@ -592,7 +612,7 @@ static RefineLayout refine_layout(int64_t n, int K)
     L.ipiv = take((size_t)n * sizeof(int64_t));
     L.perm = take((size_t)n * sizeof(int32_t));
     L.rd = take((size_t)K * n * sizeof(double));
-    L.r = take((size_t)4 * n * sizeof(double));
+    L.r = take((size_t)8 * n * sizeof(double));  // up to 8 long words
     L.v = take((size_t)K * n * sizeof(double));
     L.rowmax = take((size_t)n * sizeof(double));
     L.part = take(residual_scratch_bytes(n));
@@ -628,8 +648,19 @@ size_t refine_workspace_bytes(int64_t n, int K) { return refine_layout(n, K).tot
     } break;                                      \
     }
 
+// Dispatch on the long precision lw (4 or 8 words).
+#define BNC_LSWITCH(lw, BODY)          \
+    if ((lw) == 8) {                   \
+        constexpr int LL = 8;          \
+        BODY;                          \
+    } else {                           \
+        constexpr int LL = 4;          \
+        BODY;                          \
+    }
+
 // The refinement loop with the factor precision kc as a run-time value, so
 // that a stagnating loop can refactor in more words and go on (escalation).
+// The long precision (x, b, r) has lw = opts->long_words words (0: 4).
 int refine_drive(int K0, int64_t n, int aw, const double *A, int64_t lda, int64_t ldpa, const double *b,
                  int64_t ldpb, double *x, int64_t ldpx, void *work, const bnc_refine_opts *o, bnc_refine_result *res,
                  hipStream_t s)
@@ -650,6 +681,7 @@ int refine_drive(int K0, int64_t n, int aw, const double *A, int64_t lda, int64_
     double *ozb = (double *)(W + L.oz);
     void *tsflags = (void *)(W + L.flags);
     const int64_t ldp = n * n;
+    const int lw = o->long_words ? o->long_words : 4;
 
     *res = bnc_refine_result{};
     res->final_words = K0;
@@ -657,14 +689,14 @@ int refine_drive(int K0, int64_t n, int aw, const double *A, int64_t lda, int64_
     BNC_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_check_finite, dim3(grid1(n * n)), dim3(256), 0, s, n, n, aw, A, lda, ldpa, &sc->nonfinite);
     BNC_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_check_finite, dim3(grid1(n)), dim3(256), 0, s, n, (int64_t)1, 4, b, ldpb, ldpb,
+    hipLaunchKernelGGL(k_check_finite, dim3(grid1(n)), dim3(256), 0, s, n, (int64_t)1, lw, b, ldpb, ldpb,
                        &sc->nonfinite);
     BNC_LAUNCH_CHECK();
     Scal h{};
     BNC_HIP(hipMemcpyAsync(&h, sc, sizeof(Scal), hipMemcpyDeviceToHost, s));
     BNC_HIP(hipStreamSynchronize(s));
     auto zero_x = [&]() -> int {
-        for (int w = 0; w < 4; ++w) {
+        for (int w = 0; w < lw; ++w) {
             hipLaunchKernelGGL(k_zero, dim3(grid1(n)), dim3(256), 0, s, n, x + w * ldpx);
             BNC_LAUNCH_CHECK();
         }
@@ -680,7 +712,7 @@ int refine_drive(int K0, int64_t n, int aw, const double *A, int64_t lda, int64_
     if ((rc = absmax_run(n, n, lda, A, &sc->amax, s)) || (rc = sumsq_run(n, n, lda, A, &sc->amax, red, &sc->asq, s)) ||
         (rc = rowmax_run(n, A, lda, rowmax, s)) || (rc = fill_i32_run(&sc->eb.a, 3, 2000, s)) ||
         (rc = minexp_run(n, n, lda, aw, ldpa, A, &sc->eb.a, s)) ||
-        (rc = minexp_run(n, 1, n, 4, ldpb, b, &sc->eb.b, s)))
+        (rc = minexp_run(n, 1, n, lw, ldpb, b, &sc->eb.b, s)))
         return rc;
 
     // kc-word copy of A, factorisation, pivots as a permutation, diagonal
@@ -715,7 +747,8 @@ int refine_drive(int K0, int64_t n, int aw, const double *A, int64_t lda, int64_
     auto solve = [&](const double *src, int64_t lds, const unsigned long long *rmaxbits) -> int {
         int rc2 = BNC_OK;
         BNC_KSWITCH(kc, {
-            hipLaunchKernelGGL((k_round_scaled<KK>), dim3(grid1(n)), dim3(256), 0, s, n, src, lds, rmaxbits, r, n);
+            BNC_LSWITCH(lw, hipLaunchKernelGGL((k_round_scaled<KK, LL>), dim3(grid1(n)), dim3(256), 0, s, n, src,
+                                               lds, rmaxbits, r, n));
             BNC_LAUNCH_CHECK();
             rc2 = getrs_perm<KK>(n, LU, n, ldp, perm, rd, r, n, v, n, tsflags, s, &sc->tinfo);
         });
@@ -745,8 +778,8 @@ int refine_drive(int K0, int64_t n, int aw, const double *A, int64_t lda, int64_
     // first solution in kc words, extended to quad-double
     if ((rc = solve(b, ldpb, nullptr)))
         return rc;
-    BNC_KSWITCH(kc, hipLaunchKernelGGL((k_extend<KK>), dim3(grid1(n)), dim3(256), 0, s, n, (const double *)v, n, x,
-                                       ldpx));
+    BNC_KSWITCH(kc, BNC_LSWITCH(lw, hipLaunchKernelGGL((k_extend<KK, LL>), dim3(grid1(n)), dim3(256), 0, s, n,
+                                                       (const double *)v, n, x, ldpx)));
     BNC_LAUNCH_CHECK();
 
     const double thresh_c = sqrt((double)n) * o->rtol * res->a_norm;
@@ -756,9 +789,9 @@ int refine_drive(int K0, int64_t n, int aw, const double *A, int64_t lda, int64_
     int status = BNC_MAX_ITER;
     for (int it = 0; it <= o->max_iter; ++it) {
         if ((rc = absmax_run(n, 1, n, x, &sc->xmax, s)) || (rc = fill_i32_run(&sc->eb.x, 1, 2000, s)) ||
-            (rc = minexp_run(n, 1, n, 4, ldpx, x, &sc->eb.x, s)))
+            (rc = minexp_run(n, 1, n, lw, ldpx, x, &sc->eb.x, s)))
             return rc;
-        if ((rc = residual_run(n, aw, A, lda, ldpa, x, ldpx, b, ldpb, rowmax, (const double *)&sc->xmax, &sc->eb,
+        if ((rc = residual_run(n, aw, lw, A, lda, ldpa, x, ldpx, b, ldpb, rowmax, (const double *)&sc->xmax, &sc->eb,
                                part, r, n, &sc->inexact, s)))
             return rc;
         if ((rc = absmax_run(n, 1, n, r, &sc->rmax, s)) || (rc = sumsq_run(n, 1, n, r, &sc->rmax, red, &sc->rsq, s)) ||
@@ -808,8 +841,8 @@ int refine_drive(int K0, int64_t n, int aw, const double *A, int64_t lda, int64_
         // kc-word copy of r * 2^-e, correction solve, x <- x + 2^e z
         if ((rc = solve(r, n, (const unsigned long long *)&sc->rmax)))
             return rc;
-        BNC_KSWITCH(kc, hipLaunchKernelGGL((k_scale_update<KK>), dim3(grid1(n)), dim3(256), 0, s, n, v, n,
-                                           (const unsigned long long *)&sc->rmax, x, ldpx));
+        BNC_KSWITCH(kc, BNC_LSWITCH(lw, hipLaunchKernelGGL((k_scale_update<KK, LL>), dim3(grid1(n)), dim3(256), 0, s,
+                                                           n, v, n, (const unsigned long long *)&sc->rmax, x, ldpx)));
         BNC_LAUNCH_CHECK();
         if ((rc = absmax_run(n, 1, n, v, &sc->zmax, s)))
             return rc;

@@ -77,8 +77,9 @@ def test_workspace_queries():
     need = P.getrs_workspace_size(2, 8)
     assert L.bnc_getrs_dd(8, 1, A, 8, 64, ip, A, 8, 8, None, None, need, None) == -11
     assert L.bnc_getrs_dd(8, 1, A, 8, 64, ip, A, 8, 8, None, 4 << 20, need - 1, None) == P.BNC_ERR_WORKSPACE
-    assert L.bnc_residual(8, 1, A, 8, 64, A, 8, A, 8, A, 8, inf, None, 0, None) == -13
-    assert L.bnc_residual(8, 1, A, 8, 64, A, 8, A, 8, A, 8, inf, 4 << 20, 16, None) == P.BNC_ERR_WORKSPACE
+    assert L.bnc_residual(8, 1, 4, A, 8, 64, A, 8, A, 8, A, 8, inf, None, 0, None) == -14
+    assert L.bnc_residual(8, 1, 4, A, 8, 64, A, 8, A, 8, A, 8, inf, 4 << 20, 16, None) == P.BNC_ERR_WORKSPACE
+    assert L.bnc_residual(8, 1, 5, A, 8, 64, A, 8, A, 8, A, 8, inf, 4 << 20, 1 << 30, None) == -3
     # n = 0 needs no workspace and launches nothing
     assert L.bnc_getrs_qd(0, 1, None, 1, 0, None, None, 1, 1, None, None, 0, None) == 0
     assert L.bnc_test_force_timeout(4) == -1 and L.bnc_test_force_timeout(0) == 0
