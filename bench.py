@@ -6,15 +6,17 @@ K-word copy of A, blocked LU with partial pivoting, substitution, then the
 refinement loop (exact residual rounded to quad-double, stopping tests,
 correction solve, update) until the solution is quad-double accurate.
 Workload: randsvd matrix n = 4096, cond 1e10, binary64 entries, b = A * ones
-formed exactly in quad-double, triple-double factorisation (Kouya 2021,
-Sec. 2 / Listing 1; the TD + long-precision variant of Table 2).
+formed exactly in quad-double (Kouya 2021, Sec. 2 / Listing 1).
 
-Both factorisation forms are timed on the same input: K-word trailing
-updates on the vector ALUs, and the split (Ozaki) form on the FP64 matrix
-cores; the headline is the faster one that reaches quad-double accuracy.
+Every factorisation form is timed on the same input: the plain triple-double
+path (K-word trailing updates on the vector ALUs, the reference GPU path),
+the plain double-double path, and the split (Ozaki) forms on the FP64 matrix
+cores with a triple-double factor and with a double-double one at two slice
+counts; the headline is the fastest form that reaches quad-double accuracy.
 Prints one JSON line with the metric, per-form results, the dominant
-kernel's measured rate against the FP64 peak, and the oracle's rate on the
-host cores.
+kernel's measured rate against the FP64 peak, and the oracle's time for the
+same solve on the host cores.  Other modes: --mode paper (the paper's own
+system and its Table 2 setting), batch, selector, sweep, gemm.
 """
 import argparse
 import json
@@ -43,7 +45,9 @@ MEASURED_TRAFFIC = {("ozaki", 3, 4096, 5): 4.270e8, ("plain", 3, 4096, 0): 3.598
 # HBM bytes per multi-word GEMM launch at m = n = k = 4096 (bench.py --mode gemm), the same two counter
 # passes and copy scaling: profiles/counters_gemm_n4096.md.  Valid for that kernel and size only.
 MEASURED_GEMM_TRAFFIC = {(2, 4096): 7.508e9, (3, 4096): 2.274e10}
-DEFAULT_SLICES = {1: 3, 2: 5, 3: 5, 4: 11}  # split form: measured fastest to QD accuracy (DD, TD: 5)
+DEFAULT_SLICES = {1: 3, 2: 5, 3: 5, 4: 11}  # split form of the requested factor (TD: 5)
+# double-double split forms timed beside it (cond <= 1e15, above): the headline takes the faster
+DD_SLICES = {False: (4, 5), True: (6, 7)}
 WORD_NAME = {1: "FP64", 2: "DD", 3: "TD", 4: "QD"}
 
 
@@ -60,21 +64,48 @@ def max_rel_err_vs_ones(x):
     return float(worst)
 
 
-def cpu_baseline(n_gpu, factor, cond, n_cpu):
-    import numpy as np  # noqa: F401
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(Ap, b, factor, slices, n_small=(1024, 2048), cond=1e10):
+    """The oracle (plain C, OpenMP over independent columns and rows, every
+    entry in the serial operation order) on this host's cores: one refined
+    solve of the benchmark's own input in the headline form (no scaling),
+    and the same form at the smaller orders of the direct-method sweep."""
     import oracle
     import synth
-    Ap, b, _ = synth.problem("randsvd", n_cpu, config=2, instance=0, cond=cond)
+    threads = oracle.set_threads(0)
+    n = Ap.shape[1]
     t0 = time.perf_counter()
-    res = oracle.refine(Ap, b, factor)
+    res = oracle.refine(Ap, b, factor, ozaki=slices)
     dt = time.perf_counter() - t0
+    form = f"{WORD_NAME[factor]} factor" + (f", split update {slices} slices" if slices else "") + \
+        ", exact quad-double residual"
+    small = {}
+    for m in n_small:
+        As, bs, _ = synth.problem("randsvd", m, config=1, instance=0, cond=cond)
+        t1 = time.perf_counter()
+        r = oracle.refine(As, bs, factor, ozaki=slices)
+        small[str(m)] = {"seconds": time.perf_counter() - t1, "corrections": r["iters"], "status": r["status"]}
     return {
-        "value": (1.0 / dt) * (n_cpu / n_gpu) ** 3,
+        "value": 1.0 / dt,
         "unit": "solves/s",
-        "cores": 1,
+        "cores": threads,
+        "nproc": os.cpu_count(),
+        "cpu_model": cpu_model(),
         "kind": "oracle",
-        "sample": (f"oracle refine ({WORD_NAME[factor]} factor, exact residual) on randsvd n={n_cpu} cond={cond:g}: "
-                   f"{dt:.1f} s, {res['iters']} corrections, single thread; rate scaled by (n_cpu/n)^3 to n={n_gpu}"),
+        "sample": (f"one refined solve of the benchmark's input (n={n}, {form}) by the oracle: {dt:.1f} s, "
+                   f"{res['iters']} corrections, status {res['status']}, {threads} OpenMP threads; "
+                   f"also measured at n={', '.join(small)} (cond {cond:g})"),
+        "measured": small,
     }
 
 
@@ -239,10 +270,14 @@ def paper_main(args):
     R Haar-orthogonal (the paper's R is unpublished), quad-double-word entries,
     x = [0..n-1], b = A x exact in quad-double; n = `paper_n`.  For DD, TD and
     QD factors: the direct method (K-word getrf + getrs, as the paper's
-    Table 1) and the mixed-precision refinement to quad-double (Table 2):
-    time, corrections and the largest relative error of the solution's
-    elements (absolute for the zero element)."""
-    import numpy as np
+    Table 1); the mixed-precision refinement in the paper's own setting
+    (Table 2): long precision of 424 bits (8 binary64 words for x and the
+    exact residual), stopping rule eq. (2) with rtol = 1e-100; and the same
+    refinement to quad-double accuracy (4 words, forward test 2^-208).  For
+    each: time, corrections and the largest relative error of the solution's
+    elements (absolute for the zero element).  The split forms (7 slices,
+    this condition number) are timed in the 424-bit setting too."""
+    import numpy as np  # noqa: F401
     import torch
 
     import paper_2107_12550_amd as P
@@ -252,9 +287,11 @@ def paper_main(args):
     Ap, b, exact, xs = synth.paper_problem(n)
     dA = torch.from_numpy(Ap).cuda()
     db = torch.from_numpy(b).cuda()
+    db8 = torch.zeros((8, n), dtype=torch.float64, device="cuda")
+    db8[:4].copy_(db)
     xt = torch.from_numpy(xs).cuda()
 
-    def max_re(xw):  # xw (K, n): the words' sum minus i, leading difference exact
+    def max_re(xw):  # xw (L, n): the words' sum minus i, leading difference exact
         err = (xw[0] - xt) + xw[1:].sum(dim=0) if xw.shape[0] > 1 else (xw[0] - xt)
         rel = err.abs() / torch.clamp(xt, min=1.0)
         return float(rel.max())
@@ -268,41 +305,53 @@ def paper_main(args):
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) * 1e3 / reps, out
 
-    rows = {}
+    direct, table2, qd = {}, {}, {}
     for K in (2, 3, 4):
+        name = WORD_NAME[K]
         LU0 = torch.zeros((K, n, n), dtype=torch.float64, device="cuda")
         LU0.copy_(dA[:K])
         LU = torch.empty_like(LU0)
         wf = torch.empty(P.getrf_workspace_size(K, n), dtype=torch.uint8, device="cuda")
         ws = torch.empty(P.getrs_workspace_size(K, n), dtype=torch.uint8, device="cuda")
 
-        def direct():
+        def direct_solve():
             LU.copy_(LU0)
             ipiv, info = P.getrf(K, LU, work=wf)
             x = db[:K].clone()
             P.getrs(K, LU, ipiv, x, work=ws)
             return x
 
-        ms_d, xd = timed(direct, args.steps)
+        ms_d, xd = timed(direct_solve, args.steps)
+        direct[name] = {"ms": ms_d, "max_re": max_re(xd)}
+        del LU0, LU
         work = torch.empty(P.refine_workspace_size(n, K), dtype=torch.uint8, device="cuda")
+        for slices in ((0, 7) if K < 4 else (0,)):
+            form = name + ("" if not slices else f"-ozaki{slices}")
+            dx8 = torch.empty((8, n), dtype=torch.float64, device="cuda")
+            ms8, o8 = timed(lambda: P.refine(dA, db8, K, x=dx8, work=work, long_words=8, rtol=1e-100, ctol=0.0,
+                                             max_iter=40, ozaki=slices), args.steps)
+            table2[form] = {"ms": ms8, "max_re": max_re(o8["x"]), "corrections": o8["iters"],
+                            "status": o8["status"]}
+            log(f"[bench] paper n={n} {form} + 424-bit refinement (eq. (2), rtol 1e-100): {ms8:.1f} ms, "
+                f"{o8['iters']} corrections, Max.RE {table2[form]['max_re']:.1e}")
         dx = torch.empty((4, n), dtype=torch.float64, device="cuda")
         ms_r, out = timed(lambda: P.refine(dA, db, K, x=dx, work=work), args.steps)
-        rows[WORD_NAME[K]] = {"direct_ms": ms_d, "direct_max_re": max_re(xd), "refined_ms": ms_r,
-                              "refined_max_re": max_re(out["x"]), "corrections": out["iters"],
-                              "status": out["status"]}
-        log(f"[bench] paper n={n} {WORD_NAME[K]}: direct {ms_d:.1f} ms Max.RE {rows[WORD_NAME[K]]['direct_max_re']:.1e}; "
-            f"refined {ms_r:.1f} ms, {out['iters']} corrections, Max.RE {rows[WORD_NAME[K]]['refined_max_re']:.1e}")
-        del LU0, LU, work
-    best = min(rows, key=lambda k: rows[k]["refined_ms"])
+        qd[name] = {"ms": ms_r, "max_re": max_re(out["x"]), "corrections": out["iters"], "status": out["status"]}
+        log(f"[bench] paper n={n} {name}: direct {ms_d:.1f} ms Max.RE {direct[name]['max_re']:.1e}; "
+            f"QD-accurate refinement {ms_r:.1f} ms, {out['iters']} corrections, Max.RE {qd[name]['max_re']:.1e}")
+        del work
+    ok = {k: v for k, v in table2.items() if v["status"] == P.BNC_CONVERGED}
+    best = min(ok or table2, key=lambda k: table2[k]["ms"])
     line = {
-        "metric": f"paper's system A = R D R^-1 (n={n}, kappa=1e{26 * (n - 1) / n:.2f}): QD-accurate refined solves/sec",
-        "value": 1e3 / rows[best]["refined_ms"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
-        "ms_per_step": rows[best]["refined_ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "metric": f"paper's system A = R D R^-1 (n={n}, kappa=1e{26 * (n - 1) / n:.2f}): refined solves/sec in "
+                  f"the paper's setting (424-bit long precision, eq. (2) with rtol = 1e-100)",
+        "value": 1e3 / table2[best]["ms"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": table2[best]["ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"A = R D R^-1, R Haar-orthogonal, d_i = 10^(-26(i-1)/n), QD-word entries, "
                                f"x = [0..n-1], b exact in QD", "n": n, "rhs_exact": bool(exact),
-                   "factor": best},
-        "forms": rows}
+                   "form": best},
+        "table2_424bit": table2, "direct": direct, "qd_refinement": qd}
     print(json.dumps(line), flush=True)
 
 
@@ -456,7 +505,6 @@ def main():
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--factor", type=int, default=3, help="words of the factorisation: 1..4")
     ap.add_argument("--cond", type=float, default=1e10)
-    ap.add_argument("--cpu-n", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--ozaki", type=int, default=-1,
                     help="single mode: also time the split trailing update with this many slices "
@@ -581,16 +629,21 @@ def main():
                 "status": out["status"], "max_rel_err": mre, "getrf_ms": t_getrf * 1e3,
                 "gflops_eq": (2.0 * n ** 3 / 3.0) / t_getrf / 1e9, "roofline": roof}
 
-    # the plain K-word path is the reference; the split (precision) form runs
-    # with the same factor and, for a triple-double factor by default, with a
-    # double-double one as well (the refinement recovers quad-double accuracy
-    # from either)
+    # the plain K-word path of the requested factor is the reference GPU
+    # path; the plain double-double path reaches the same accuracy too.  The
+    # split (precision) form runs with the same factor and, for a
+    # triple-double factor by default, with a double-double one at two slice
+    # counts (the refinement recovers quad-double accuracy from each); the
+    # headline is whichever form is fastest end to end
     forms = {"plain": measure(0)}
+    if K == 3 and args.ozaki < 0:
+        forms["plain-dd"] = measure(0, 2)
     if oz:
         forms[f"ozaki{oz}"] = measure(oz)
         if K == 3 and args.ozaki < 0:
-            oz2 = DEFAULT_SLICES[2] + (2 if args.cond > 1e15 else 0)
-            forms[f"dd-ozaki{oz2}"] = measure(oz2, 2)
+            hi = args.cond > 1e15
+            for oz2 in DD_SLICES[hi]:
+                forms[f"dd-ozaki{oz2}"] = measure(oz2, 2)
     # headline: the faster form among those that reached quad-double accuracy
     ok = {k: v for k, v in forms.items() if v["status"] == P.BNC_CONVERGED and (v["max_rel_err"] or 0.0) <= 1e-60}
     best_name = min(ok or forms, key=lambda k: forms[k]["ms_per_step"])
@@ -624,12 +677,22 @@ def main():
         "forms": forms,
     }
     if oz:
-        # split forms against the plain path of the requested factor, same accuracy
+        # every form against the plain path of the requested factor (the
+        # reference GPU path), and against the fastest plain path, all at the
+        # same accuracy
+        plains = [k for k in ok if k.startswith("plain")]
+        fastest_plain = min(plains or ["plain"], key=lambda k: forms[k]["ms_per_step"])
         line["speedup_vs_plain"] = {k: forms["plain"]["ms_per_step"] / v["ms_per_step"]
                                     for k, v in forms.items() if k != "plain"}
+        line["speedup_vs_fastest_plain"] = {"plain_form": fastest_plain, **{
+            k: forms[fastest_plain]["ms_per_step"] / v["ms_per_step"] for k, v in forms.items()
+            if not k.startswith("plain")}}
     if not args.no_cpu_baseline:
-        log(f"[bench] cpu baseline: oracle at n={args.cpu_n}")
-        line["cpu_baseline"] = cpu_baseline(n, K, args.cond, args.cpu_n)
+        bf = 2 if best_name.startswith("dd-") or best_name == "plain-dd" else K
+        bs_ = int(best_name.rsplit("ozaki", 1)[1]) if "ozaki" in best_name else 0
+        log(f"[bench] cpu baseline: the oracle on the host cores, n={n}, {WORD_NAME[bf]} factor, slices {bs_}")
+        line["cpu_baseline"] = cpu_baseline(Ap, b, bf, bs_, cond=args.cond)
+        log(f"[bench] cpu baseline: {line['cpu_baseline']['sample']}")
     print(json.dumps(line), flush=True)
 
 
