@@ -164,6 +164,16 @@ def batch_main(args):
     res = S.results()
     khz = P.wall_clock_khz()
     lat_ms = (res["t_end"].astype(np.float64) - res["t_start"].astype(np.float64)) / khz
+    fac_ms = (res["t_factored"].astype(np.float64) - res["t_start"].astype(np.float64)) / khz
+    nsys = np.array([a.shape[-1] for a in As])
+    split = {}
+    for lo, hi in ((16, 64), (65, 128), (129, 192), (193, 256)):
+        sel = (nsys >= lo) & (nsys <= hi)
+        if sel.any():
+            split[f"{lo}-{hi}"] = {"systems": int(sel.sum()), "factor_ms_mean": float(fac_ms[sel].mean()),
+                                   "refine_ms_mean": float((lat_ms - fac_ms)[sel].mean())}
+    log(f"[bench] per-system device time: factorisation {fac_ms.sum():.0f} ms, refinement "
+        f"{(lat_ms - fac_ms).sum():.0f} ms (summed over systems); by order: {split}")
     # accuracy on a fixed sample of systems (exact solution all ones)
     sample = list(range(0, args.count, max(1, args.count // 256)))
     mre = max(max_rel_err_vs_ones(S.xs[i].cpu().numpy()) for i in sample if exact[i])
@@ -192,6 +202,7 @@ def batch_main(args):
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99)),
                        "max": float(lat_ms.max())},
         "gflops_eq_lu": work / (ms / 1e3) / 1e9,
+        "device_time_split": {"factor_frac": float(fac_ms.sum() / lat_ms.sum()), "by_order": split},
         "status_counts": {int(k): int(v) for k, v in zip(*np.unique(res["status"], return_counts=True))},
         "iters_mean": float(res["iters"].mean()),
         "max_rel_err_sample": mre,
@@ -370,7 +381,8 @@ def selector_main(args):
     net = SEL.load(model)
     chunk = 4096
     tot = dict(baseline_ms=0.0, selector_ms=0.0, selector_predict_ms=0.0, baseline_attempts=0, selector_attempts=0,
-               baseline_solved=0, selector_solved=0, selector_escalations=0)
+               baseline_solved=0, selector_solved=0, selector_escalations=0, baseline_wrong=0, selector_wrong=0,
+               dd_ms=0.0, dd_attempts=0, dd_solved=0, dd_wrong=0)
     for c0 in range(0, args.count, chunk):
         m = min(chunk, args.count - c0)
         log(f"[bench] generating held-out systems {c0}..{c0 + m}")
@@ -382,7 +394,8 @@ def selector_main(args):
         r = SEL.evaluate(net, dA, db)
         for k in tot:
             tot[k] += r[k]
-        log(f"[bench] chunk: baseline {r['baseline_ms']:.1f} ms, selector {r['selector_ms']:.1f} ms")
+        log(f"[bench] chunk: escalation from one word {r['baseline_ms']:.1f} ms, fixed start at DD "
+            f"{r['dd_ms']:.1f} ms, selector {r['selector_ms']:.1f} ms")
     line = {
         "metric": "refined solves/sec with the learned precision choice (batched, to 1e-45)",
         "value": args.count * 1e3 / tot["selector_ms"],
@@ -401,11 +414,16 @@ def selector_main(args):
                    "count": args.count},
         "baseline": {"rule": "escalate-on-stagnation from one word", "ms": tot["baseline_ms"],
                      "solves_per_s": args.count * 1e3 / tot["baseline_ms"], "attempts": tot["baseline_attempts"],
-                     "solved": tot["baseline_solved"]},
+                     "solved": tot["baseline_solved"], "converged_but_wrong": tot["baseline_wrong"]},
+        "fixed_dd": {"rule": "escalate-on-stagnation from two words (double-double)", "ms": tot["dd_ms"],
+                     "solves_per_s": args.count * 1e3 / tot["dd_ms"], "attempts": tot["dd_attempts"],
+                     "solved": tot["dd_solved"], "converged_but_wrong": tot["dd_wrong"]},
         "selector": {"ms": tot["selector_ms"], "predict_ms": tot["selector_predict_ms"],
                      "attempts": tot["selector_attempts"], "solved": tot["selector_solved"],
+                     "converged_but_wrong": tot["selector_wrong"],
                      "fallback_fraction": tot["selector_escalations"] / args.count},
         "speedup_vs_escalation": tot["baseline_ms"] / tot["selector_ms"],
+        "speedup_vs_fixed_dd": tot["dd_ms"] / tot["selector_ms"],
     }
     print(json.dumps(line), flush=True)
 

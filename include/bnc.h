@@ -295,6 +295,8 @@ typedef struct bnc_batch_result {
     uint64_t t_start, t_end;  /* device wall-clock ticks (bnc_wall_clock_khz) */
     int32_t residual_inexact;
     int32_t reserved;
+    uint64_t t_factored;      /* tick at the end of the factorisation (t_start
+                                 when none was made) */
 } bnc_batch_result;
 
 /* Workspace bytes of bnc_refine_batched for K = factor_words and `slots`

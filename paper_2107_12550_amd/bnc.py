@@ -50,7 +50,7 @@ class AdamOpts(ctypes.Structure):
 class BatchResult(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("info", ctypes.c_int64),
                 ("t_start", ctypes.c_uint64), ("t_end", ctypes.c_uint64), ("residual_inexact", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("reserved", ctypes.c_int32), ("t_factored", ctypes.c_uint64)]
 
 
 def _load() -> ctypes.CDLL:
@@ -325,7 +325,7 @@ class BatchSolver:
         torch.cuda.synchronize()
         raw = self.res.cpu().numpy()
         dt = np.dtype([("status", "<i4"), ("iters", "<i4"), ("info", "<i8"), ("t_start", "<u8"), ("t_end", "<u8"),
-                       ("residual_inexact", "<i4"), ("reserved", "<i4")])
+                       ("residual_inexact", "<i4"), ("reserved", "<i4"), ("t_factored", "<u8")])
         return raw.view(dt).reshape(self.count)
 
     def close(self):

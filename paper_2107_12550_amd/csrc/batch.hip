@@ -258,6 +258,7 @@ __global__ void __launch_bounds__(NT)
             if (t == 0) {
                 out.status = BNC_BAD_SIZE;
                 out.t_start = t0;
+                out.t_factored = t0;
                 out.t_end = wall_clock64();
                 res[sys] = out;
             }
@@ -297,6 +298,7 @@ __global__ void __launch_bounds__(NT)
             if (t == 0) {
                 out.status = BNC_NONFINITE;
                 out.t_start = t0;
+                out.t_factored = t0;
                 out.t_end = wall_clock64();
                 res[sys] = out;
             }
@@ -553,6 +555,7 @@ __global__ void __launch_bounds__(NT)
             }
             __syncthreads();
         }
+        const uint64_t t_fact = wall_clock64();
         if (info != 0) {
             for (int e = t; e < 4 * n; e += NT)
                 x[(e / n) * n + e % n] = 0.0;
@@ -560,6 +563,7 @@ __global__ void __launch_bounds__(NT)
                 out.status = BNC_SINGULAR;
                 out.info = info;
                 out.t_start = t0;
+                out.t_factored = t_fact;
                 out.t_end = wall_clock64();
                 res[sys] = out;
             }
@@ -720,6 +724,7 @@ __global__ void __launch_bounds__(NT)
             out.info = 0;
             out.residual_inexact = inexact;
             out.t_start = t0;
+            out.t_factored = t_fact;
             out.t_end = wall_clock64();
             res[sys] = out;
         }

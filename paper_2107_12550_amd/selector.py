@@ -9,10 +9,15 @@ whose refinement reaches the target accuracy (forward error against the
 exact solution); its step count is the number of corrections that took.  A 24-64-64-5 network (bnc_mlp_*) learns class and
 log2(1 + steps) from the 24 features of bnc_features.
 
-In use, each system starts at the predicted precision; systems that do not
-reach the target (stagnation or no convergence) escalate one word at a
-time, which is the plain escalate-on-stagnation rule started one or more
-rungs higher.  evaluate() compares that with the rule started at one word.
+In use, each system starts at the predicted precision; systems whose
+refinement loop does not report convergence (stagnation or no convergence
+within the correction limit: the loop's own status, the exact solution being
+unknown in use) escalate one word at a time, which is the plain
+escalate-on-stagnation rule started one or more rungs higher.  evaluate()
+compares that with the rule started at one word and with a fixed start at
+two words; afterwards, each path's solutions are checked against the exact
+solution, and a system that converged to a wrong answer counts as a failure
+of that path.
 
 Every number is computed by the library's kernels; this module batches
 systems, keeps the books and moves tensors.
@@ -61,10 +66,11 @@ def solve_at(As, bs, K: int) -> dict:
     ms = e0.elapsed_time(e1)
     khz = bnc.wall_clock_khz()
     err = max_err_vs_ones(S.xs)
-    ok = (res["status"] == bnc.BNC_CONVERGED) & (err <= TARGET)
+    converged = res["status"] == bnc.BNC_CONVERGED
+    ok = converged & (err <= TARGET)
     lat = (res["t_end"].astype(np.float64) - res["t_start"].astype(np.float64)) / khz
-    out = dict(ok=ok, iters=res["iters"].astype(np.int64), status=res["status"].copy(), latency_ms=lat,
-               total_ms=ms, xs=S.xs, err=err)
+    out = dict(ok=ok, converged=converged, iters=res["iters"].astype(np.int64), status=res["status"].copy(),
+               latency_ms=lat, total_ms=ms, xs=S.xs, err=err)
     S.close()
     return out
 
@@ -150,14 +156,19 @@ def predict(net: bnc.MLP, F: torch.Tensor):
 
 
 def escalate_from(As, bs, start_words) -> dict:
-    """Refine each system starting at its start precision; those that miss
-    TARGET move up one word and are refined again (one batched launch per
-    precision, in increasing order).  Returns total device time, per-system
-    final precision, number of escalations and success."""
+    """Refine each system starting at its start precision; those whose loop
+    does not report convergence (its own status: stagnated or out of
+    corrections) move up one word and are refined again (one batched launch
+    per precision, in increasing order).  The exact solution plays no part
+    in the decisions; afterwards each returned solution is checked against
+    it.  Returns total device time, per-system final precision, number of
+    escalations, `solved` (the loop converged) and `accurate` (converged
+    and within TARGET of the exact solution)."""
     count = len(As)
     cur = np.asarray(start_words, dtype=np.int64).copy()
     done = np.zeros(count, dtype=bool)
-    ok_all = np.zeros(count, dtype=bool)
+    conv_all = np.zeros(count, dtype=bool)
+    acc_all = np.zeros(count, dtype=bool)
     total = 0.0
     launches = 0
     escal = 0
@@ -168,22 +179,28 @@ def escalate_from(As, bs, start_words) -> dict:
         r = solve_at([As[i] for i in idx], [bs[i] for i in idx], K)
         total += r["total_ms"]
         launches += 1
-        good = r["ok"]
+        good = r["converged"]
         done[idx[good]] = True
-        ok_all[idx[good]] = True
+        conv_all[idx[good]] = True
+        acc_all[idx[good]] = r["err"][good] <= TARGET
         bad = idx[~good]
         if K < 4:
             cur[bad] = K + 1
             escal += bad.size
         else:
             done[bad] = True
-    return dict(total_ms=total, launches=launches, escalations=int(escal), final_words=cur, solved=ok_all)
+    return dict(total_ms=total, launches=launches, escalations=int(escal), final_words=cur, solved=conv_all,
+                accurate=acc_all)
 
 
 def evaluate(net: bnc.MLP, As, bs) -> dict:
     """Selector (features + inference + escalation from the predicted
-    precision) against the escalate-on-stagnation rule from one word."""
+    precision) against the escalate-on-stagnation rule from one word and
+    from a fixed two words (double-double).  `*_solved`: systems whose loop
+    converged; `*_wrong`: of those, the ones whose solution misses TARGET
+    against the exact solution (failures of that path)."""
     base = escalate_from(As, bs, np.ones(len(As), dtype=np.int64))
+    dd = escalate_from(As, bs, np.full(len(As), 2, dtype=np.int64))
     e0, e1 = _events()
     e0.record()
     F = bnc.features(As, bs)
@@ -196,13 +213,18 @@ def evaluate(net: bnc.MLP, As, bs) -> dict:
         count=len(As),
         baseline_ms=base["total_ms"], baseline_escalations=base["escalations"],
         baseline_solved=int(base["solved"].sum()),
+        baseline_wrong=int((base["solved"] & ~base["accurate"]).sum()),
+        dd_ms=dd["total_ms"], dd_escalations=dd["escalations"], dd_solved=int(dd["solved"].sum()),
+        dd_wrong=int((dd["solved"] & ~dd["accurate"]).sum()), dd_attempts=int(len(As) + dd["escalations"]),
         selector_ms=t_pred + sel["total_ms"], selector_predict_ms=t_pred, selector_solve_ms=sel["total_ms"],
         selector_escalations=sel["escalations"], selector_solved=int(sel["solved"].sum()),
+        selector_wrong=int((sel["solved"] & ~sel["accurate"]).sum()),
         fallback_fraction=float(np.mean(sel["final_words"] != cls + 1)),
         baseline_attempts=int(len(As) + base["escalations"]), selector_attempts=int(len(As) + sel["escalations"]),
         predicted_class_counts=np.bincount(cls, minlength=4).tolist(),
         baseline_final_counts=np.bincount(base["final_words"] - 1, minlength=4).tolist(),
         speedup=base["total_ms"] / max(t_pred + sel["total_ms"], 1e-9),
+        speedup_vs_dd=dd["total_ms"] / max(t_pred + sel["total_ms"], 1e-9),
     )
 
 
