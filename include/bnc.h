@@ -53,6 +53,9 @@ extern "C" {
                                       (bnc_refine; the asynchronous calls
                                       report it through their info) */
 
+/* bnc_refine_opts.factor_words: let the learned selector choose. */
+#define BNC_AUTO 0
+
 /* Refinement outcome (bnc_refine_result.status). */
 #define BNC_CONVERGED 0 /* a stopping test passed */
 #define BNC_MAX_ITER 1  /* max_iter corrections applied, no test passed */
@@ -210,7 +213,9 @@ int bnc_gemm_qd(int64_t m, int64_t n, int64_t k, const double *A, int64_t lda, i
 
 /* Options of the refinement loop (host struct). */
 typedef struct bnc_refine_opts {
-    int32_t factor_words; /* K of the factorisation: 1, 2, 3 or 4 */
+    int32_t factor_words; /* K of the factorisation: 1, 2, 3 or 4; 0 (BNC_AUTO,
+                             bnc_refine only): chosen by the learned
+                             selector, see selector_params */
     int32_t max_iter;     /* maximum number of corrections (>= 0) */
     double rtol;          /* residual test of Listing 1 / eq. (2): stop when
                              ||r||_2 < sqrt(n) rtol ||A||_F ||x||_2 + atol */
@@ -241,6 +246,17 @@ typedef struct bnc_refine_opts {
                              (424 bits, the long precision of Table 2).
                              Batched solves take 0 or 4. */
     int32_t reserved;     /* 0 */
+    const float *selector_params; /* factor_words = 0: the network's
+                             parameters (device, bnc_mlp_param_count()
+                             floats) and input normalisation (device, 48
+                             floats), as for bnc_mlp_forward.  bnc_refine
+                             computes the 24 features of the system
+                             (bnc_features; orders 1..256, the leading words
+                             of A), runs the network and factors with the
+                             predicted number of words; escalation (when
+                             enabled) stays the fallback.  For orders above
+                             256 it starts at 2 words.  Ignored otherwise. */
+    const float *selector_norm;
 } bnc_refine_opts;
 
 /* Outcome of the refinement loop (host struct, filled synchronously). */
@@ -255,11 +271,14 @@ typedef struct bnc_refine_result {
                                   exact accumulator (never for sane inputs) */
     int32_t final_words;       /* K of the last factorisation */
     int32_t escalations;       /* refactorisations with more words */
-    int32_t reserved;
+    int32_t first_words;       /* K of the first factorisation (the
+                                  requested or, with factor_words = 0, the
+                                  selector's choice) */
 } bnc_refine_result;
 
 /* Workspace bytes bnc_refine needs for order n and K = factor_words (host);
- * with escalate = 1 it needs the size for factor_words = 4. */
+ * with escalate = 1 it needs the size for factor_words = 4; factor_words = 0
+ * (the selector) covers every choice and the features. */
 size_t bnc_refine_workspace_size(int64_t n, int32_t factor_words);
 
 /*

@@ -7,6 +7,7 @@ Every step runs in the HIP kernels of ``libbnc.so`` behind the C-ABI of
 device memory and the current stream.
 """
 from .bnc import (  # noqa: F401
+    BNC_AUTO,
     BNC_BAD_SIZE,
     BNC_CONVERGED,
     BNC_ERR_HIP,

@@ -17,6 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 lib_path = os.path.join(_HERE, "libbnc.so")
 
 BNC_CONVERGED, BNC_MAX_ITER, BNC_SINGULAR, BNC_NONFINITE, BNC_BAD_SIZE, BNC_STAGNATED = 0, 1, 2, 3, 4, 5
+BNC_AUTO = 0
 BNC_ERR_HIP, BNC_ERR_UNSUPPORTED, BNC_ERR_WORKSPACE, BNC_ERR_TIMEOUT = -100, -101, -102, -103
 OP_FMS, OP_MUL, OP_ADD, OP_RECIP, OP_ROUND4 = 0, 1, 2, 3, 4
 _SUFFIX = {1: "d", 2: "dd", 3: "td", 4: "qd"}
@@ -32,14 +33,15 @@ class RefineOpts(ctypes.Structure):
     _fields_ = [("factor_words", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("rtol", ctypes.c_double),
                 ("atol", ctypes.c_double), ("ctol", ctypes.c_double), ("ozaki_slices", ctypes.c_int32),
                 ("escalate", ctypes.c_int32), ("stagnation_ratio", ctypes.c_double), ("batch_panel", ctypes.c_int32),
-                ("batch_threads", ctypes.c_int32), ("long_words", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("batch_threads", ctypes.c_int32), ("long_words", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("selector_params", ctypes.c_void_p), ("selector_norm", ctypes.c_void_p)]
 
 
 class RefineResult(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("info", ctypes.c_int64),
                 ("resid_norm", ctypes.c_double), ("x_norm", ctypes.c_double), ("a_norm", ctypes.c_double),
                 ("residual_inexact", ctypes.c_int32), ("final_words", ctypes.c_int32),
-                ("escalations", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("escalations", ctypes.c_int32), ("first_words", ctypes.c_int32)]
 
 
 class AdamOpts(ctypes.Structure):
@@ -247,26 +249,35 @@ def refine_workspace_size(n: int, K: int) -> int:
 
 def refine(A: torch.Tensor, b: torch.Tensor, K: int, max_iter: int = 30, rtol: float = 0.0, atol: float = 0.0,
            ctol: float = 2.0 ** -208, x: torch.Tensor | None = None, work: torch.Tensor | None = None,
-           ozaki: int = 0, escalate: bool = False, stagnation_ratio: float = 0.0, long_words: int = 4) -> dict:
+           ozaki: int = 0, escalate: bool = False, stagnation_ratio: float = 0.0, long_words: int = 4,
+           selector: "MLP | None" = None) -> dict:
     """Listing 1 of the paper with a K-word factorisation and an L-word long
     precision, L = long_words (4: quad-double, 8: 424 bits).  A: (aw, n, n)
     with aw = 1 or 4; b: (L, n); ozaki = S > 0 factors with the split
     trailing update (S slices); escalate and stagnation_ratio as in
-    bnc_refine_opts.  Returns a dict with x (L, n) and the outcome fields."""
+    bnc_refine_opts.  K = BNC_AUTO (0) with `selector` (an MLP) lets the
+    library's features and network choose the first factor's words.
+    Returns a dict with x (L, n) and the outcome fields."""
     aw, n = A.shape[0], A.shape[1]
     if x is None:
         x = torch.empty((long_words, n), dtype=torch.float64, device=A.device)
-    need = refine_workspace_size(n, 4 if escalate else K)
+    need = refine_workspace_size(n, 0 if K == BNC_AUTO else (4 if escalate else K))
     if work is None or work.numel() < need:
         work = torch.empty(need, dtype=torch.uint8, device=A.device)
-    o = RefineOpts(K, max_iter, rtol, atol, ctol, ozaki, 1 if escalate else 0, stagnation_ratio, 0, 0, long_words, 0)
+    o = RefineOpts(K, max_iter, rtol, atol, ctol, ozaki, 1 if escalate else 0, stagnation_ratio, 0, 0, long_words, 0,
+                   None, None)
+    if K == BNC_AUTO:
+        if selector is None:
+            raise BncError("refine: K = BNC_AUTO needs a selector network")
+        o.selector_params = selector.params.data_ptr()
+        o.selector_norm = selector.norm.data_ptr()
     r = RefineResult()
     _check(_lib.bnc_refine(n, aw, _dev(A, "A", 3), n, n * n, _dev(b, "b", 2), n, _dev(x, "x", 2), n,
                            ctypes.c_void_p(work.data_ptr()), work.numel(), ctypes.byref(o), ctypes.byref(r),
                            _stream()), "refine")
     return dict(x=x, status=r.status, iters=r.iters, info=r.info, resid_norm=r.resid_norm, x_norm=r.x_norm,
                 a_norm=r.a_norm, residual_inexact=bool(r.residual_inexact), final_words=r.final_words,
-                escalations=r.escalations)
+                escalations=r.escalations, first_words=r.first_words)
 
 
 class BatchSolver:
@@ -299,7 +310,8 @@ class BatchSolver:
         self.slots = slots
         need = int(_lib.bnc_refine_batched_workspace_size(K, slots))
         self.work = torch.empty(need, dtype=torch.uint8, device=dev)
-        self.opts = RefineOpts(K, max_iter, rtol, atol, ctol, 0, 0, stagnation_ratio, panel, threads, 0, 0)
+        self.opts = RefineOpts(K, max_iter, rtol, atol, ctol, 0, 0, stagnation_ratio, panel, threads, 0, 0, None,
+                               None)
         self.graph = ctypes.c_void_p(None)
         self.stream = None
 

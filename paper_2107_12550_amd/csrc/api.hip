@@ -48,6 +48,9 @@ int mlp_adam_run(float *P, const float *G, float *M, float *V, float lr, float b
                  hipStream_t s);
 
 size_t refine_workspace_bytes(int64_t n, int K);
+int refine_drive(int K0, int64_t n, int aw, const double *A, int64_t lda, int64_t ldpa, const double *b,
+                 int64_t ldpb, double *x, int64_t ldpx, void *work, const bnc_refine_opts *o, bnc_refine_result *res,
+                 hipStream_t s);
 size_t residual_workspace_bytes(int64_t n);
 int residual_ws_run(int64_t n, int aw, int lw, const double *A, int64_t lda, int64_t ldpa, const double *x,
                     int64_t ldpx, const double *b, int64_t ldpb, double *r, int64_t ldpr, int32_t *inexact, void *work,
@@ -388,7 +391,7 @@ int bnc_getrs_qd(int64_t n, int64_t nrhs, const double *LU, int64_t lda, int64_t
 
 size_t bnc_refine_workspace_size(int64_t n, int32_t factor_words)
 {
-    if (n < 1 || factor_words < 1 || factor_words > 4)
+    if (n < 1 || factor_words < 0 || factor_words > 4)
         return 0;
     return refine_workspace_bytes(n, factor_words);
 }
@@ -419,7 +422,10 @@ int bnc_refine(int64_t n, int32_t a_words, const double *A, int64_t lda, int64_t
         return fail_arg(-10, "refine: work is NULL");
     if (!opts)
         return fail_arg(-12, "refine: opts is NULL");
-    if (opts->factor_words < 1 || opts->factor_words > 4 || opts->max_iter < 0 || !(opts->rtol >= 0) ||
+    const bool autok = opts->factor_words == BNC_AUTO;
+    if (autok && (!opts->selector_params || !opts->selector_norm))
+        return fail_arg(-12, "refine: factor_words = 0 needs the selector's parameters and normalisation");
+    if ((!autok && (opts->factor_words < 1 || opts->factor_words > 4)) || opts->max_iter < 0 || !(opts->rtol >= 0) ||
         opts->ozaki_slices < 0 || opts->ozaki_slices > OZ_SMAX || (opts->escalate != 0 && opts->escalate != 1) ||
         !batch_panel_ok(opts->batch_panel) || !batch_threads_ok(opts->batch_threads) ||
         !(opts->stagnation_ratio >= 0) || (opts->long_words != 0 && opts->long_words != 4 && opts->long_words != 8) ||
@@ -429,8 +435,10 @@ int bnc_refine(int64_t n, int32_t a_words, const double *A, int64_t lda, int64_t
         return fail_arg(-13, "refine: result is NULL");
     if (n > 16384)
         return fail_arg(BNC_ERR_UNSUPPORTED, "refine: n > 16384");
-    if (work_bytes < refine_workspace_bytes(n, opts->escalate ? 4 : opts->factor_words))
+    if (work_bytes < refine_workspace_bytes(n, autok ? 0 : (opts->escalate ? 4 : opts->factor_words)))
         return fail_arg(-11, "refine: workspace too small");
+    if (autok)
+        return refine_drive(0, n, a_words, A, lda, ldpa, b, ldpb, x, ldpx, work, opts, result, S(stream));
     switch (opts->factor_words) {
     case 1:
         return refine_run<1>(n, a_words, A, lda, ldpa, b, ldpb, x, ldpx, work, opts, result, S(stream));

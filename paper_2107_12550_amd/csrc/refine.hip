@@ -31,6 +31,11 @@ template <int K>
 int getrs_perm(int64_t n, const double *LU, int64_t lda, int64_t ldp, const int32_t *perm, const double *rd,
                const double *b, int64_t ldb, double *y, int64_t ldy, void *ws, hipStream_t s, int64_t *info);
 size_t trsv_ws_bytes(int64_t n);
+size_t features_workspace_bytes(int slots);
+int features_run(int64_t count, const int64_t *n, const double *const *A, const double *const *b,
+                 const int32_t *order, float *F, void *work, int slots, hipStream_t s);
+int mlp_forward_run(int64_t B, const float *X, const float *norm, const float *P, float *O, hipStream_t s);
+constexpr int64_t SEL_NMAX = 256;  // orders the features kernel takes
 template <int K>
 int diag_recip_run(int64_t n, const double *LU, int64_t lda, int64_t ldp, double *rd, hipStream_t s);
 int ipiv_to_perm(int64_t n, const int64_t *ipiv, int32_t *perm, hipStream_t s);
@@ -594,12 +599,30 @@ struct Scal {
 };
 
 struct RefineLayout {
-    size_t lu, ipiv, perm, rd, r, v, rowmax, part, red, scal, getrf, oz, flags, total;
+    size_t lu, ipiv, perm, rd, r, v, rowmax, part, red, scal, getrf, oz, flags, sel, total;
 };
+
+// the selector's scratch (factor_words = 0): the order and the pointers
+// the features kernel reads, 24 features, 5 outputs, a contiguous copy of
+// A's leading plane, the features workspace
+struct SelScratch {
+    int64_t n;
+    const double *A;
+    const double *b;
+    int64_t pad;
+    float F[24];
+    float O[8];
+};
+static size_t sel_bytes(int64_t n)
+{
+    if (n > SEL_NMAX)
+        return 0;
+    return align256(sizeof(SelScratch)) + align256((size_t)n * n * sizeof(double)) + features_workspace_bytes(1);
+}
 
 size_t getrf_scratch_bytes(int K, int64_t n);
 
-static RefineLayout refine_layout(int64_t n, int K)
+static RefineLayout refine_layout(int64_t n, int K, bool sel = false)
 {
     RefineLayout L;
     size_t off = 0;
@@ -621,11 +644,30 @@ static RefineLayout refine_layout(int64_t n, int K)
     L.getrf = take(getrf_scratch_bytes(K, n));
     L.oz = take(oz_slices_bytes(n));
     L.flags = take(trsv_ws_bytes(n));
+    L.sel = take(sel ? sel_bytes(n) : 0);
     L.total = off;
     return L;
 }
 
-size_t refine_workspace_bytes(int64_t n, int K) { return refine_layout(n, K).total; }
+// K = 0: the selector's choice (any K, plus its scratch)
+size_t refine_workspace_bytes(int64_t n, int K) { return refine_layout(n, K ? K : 4, K == 0).total; }
+
+__global__ void k_sel_setup(SelScratch *S, int64_t n, const double *A, const double *b)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        S->n = n;
+        S->A = A;
+        S->b = b;
+    }
+}
+
+// dst (n x n, contiguous) = the leading plane of A (leading dimension lda)
+__global__ void k_copy_plane(int64_t n, const double *__restrict__ A, int64_t lda, double *__restrict__ dst)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n * n)
+        dst[e] = A[(e / n) * lda + e % n];
+}
 
 // Dispatch a K-templated launch on the runtime word count kc (1..4).
 #define BNC_KSWITCH(kc, BODY)                     \
@@ -665,7 +707,7 @@ int refine_drive(int K0, int64_t n, int aw, const double *A, int64_t lda, int64_
                  int64_t ldpb, double *x, int64_t ldpx, void *work, const bnc_refine_opts *o, bnc_refine_result *res,
                  hipStream_t s)
 {
-    const RefineLayout L = refine_layout(n, o->escalate ? 4 : K0);
+    const RefineLayout L = refine_layout(n, (o->escalate || K0 == 0) ? 4 : K0, K0 == 0);
     char *W = (char *)work;
     double *LU = (double *)(W + L.lu);
     int64_t *ipiv = (int64_t *)(W + L.ipiv);
@@ -684,6 +726,35 @@ int refine_drive(int K0, int64_t n, int aw, const double *A, int64_t lda, int64_
     const int lw = o->long_words ? o->long_words : 4;
 
     *res = bnc_refine_result{};
+    if (K0 == 0) {
+        // the learned choice: features of the system (leading words of A,
+        // contiguous copy), the network, the largest logit (ties: fewer
+        // words); orders the features kernel does not take start at 2
+        K0 = 2;
+        if (n <= SEL_NMAX) {
+            char *SW = W + L.sel;
+            SelScratch *ss = (SelScratch *)SW;
+            double *Ac = (double *)(SW + align256(sizeof(SelScratch)));
+            void *fws = (void *)((char *)Ac + align256((size_t)n * n * sizeof(double)));
+            hipLaunchKernelGGL(k_copy_plane, dim3(grid1(n * n)), dim3(256), 0, s, n, A, lda, Ac);
+            BNC_LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_sel_setup, dim3(1), dim3(64), 0, s, ss, n, (const double *)Ac, b);
+            BNC_LAUNCH_CHECK();
+            int rc0;
+            if ((rc0 = features_run(1, &ss->n, &ss->A, &ss->b, nullptr, ss->F, fws, 1, s)) ||
+                (rc0 = mlp_forward_run(1, ss->F, o->selector_norm, o->selector_params, ss->O, s)))
+                return rc0;
+            float O[8];
+            BNC_HIP(hipMemcpyAsync(O, ss->O, sizeof O, hipMemcpyDeviceToHost, s));
+            BNC_HIP(hipStreamSynchronize(s));
+            int best = 0;
+            for (int c = 1; c < 4; ++c)
+                if (O[c] > O[best])
+                    best = c;
+            K0 = best + 1;
+        }
+    }
+    res->first_words = K0;
     res->final_words = K0;
     hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, (uint64_t *)sc, (int64_t)(sizeof(Scal) / 8), (uint64_t)0);
     BNC_LAUNCH_CHECK();
