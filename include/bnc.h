@@ -64,6 +64,9 @@ extern "C" {
 #define BNC_BAD_SIZE 4  /* batched solve: order outside 1..256 */
 #define BNC_STAGNATED 5 /* corrections stopped shrinking (stagnation_ratio)
                            and no escalation was left */
+#define BNC_TIMED_OUT 6 /* bnc_refine_async: a bounded wait between
+                           workgroups gave up (bnc_refine returns
+                           BNC_ERR_TIMEOUT instead); x is invalid */
 
 /*
  * LU decomposition with partial pivoting, in place: P A = L U (Kouya 2021,
@@ -305,6 +308,29 @@ size_t bnc_refine_workspace_size(int64_t n, int32_t factor_words);
 int bnc_refine(int64_t n, int32_t a_words, const double *A, int64_t lda, int64_t ldpa, const double *b,
                int64_t ldpb, double *x, int64_t ldpx, void *work, size_t work_bytes, const bnc_refine_opts *opts,
                bnc_refine_result *result, void *stream);
+
+/*
+ * bnc_refine with every decision taken on the device, for callers that
+ * need an asynchronous call or want to capture the solve into a HIP graph
+ * (Kouya 2021, Sec. 2, Listing 1: the same steps, tests and results as
+ * bnc_refine).  All max_iter + 1 iterations are enqueued; the stopping
+ * tests run in a small kernel after each residual and, once they (or a
+ * failure) have decided, a flag in the workspace makes every later kernel
+ * of the loop return at once.  Nothing is read back and nothing allocated:
+ * the call returns after enqueueing, and the sequence can be captured
+ * (replays reset the flags themselves).  Arguments as bnc_refine, except:
+ *   opts     factor_words 1..4 (no BNC_AUTO) and escalate = 0; stagnation
+ *            ends the loop with BNC_STAGNATED
+ *   result   DEVICE bnc_refine_result, valid once the stream has reached
+ *            the end of the call; a timed-out bounded wait gives status
+ *            BNC_TIMED_OUT
+ * x, status, corrections and norms equal those of bnc_refine bit for bit.
+ * The first factorisation on a device creates the library's look-ahead
+ * stream: make one call outside a capture first.
+ */
+int bnc_refine_async(int64_t n, int32_t a_words, const double *A, int64_t lda, int64_t ldpa, const double *b,
+                     int64_t ldpb, double *x, int64_t ldpx, void *work, size_t work_bytes,
+                     const bnc_refine_opts *opts, bnc_refine_result *result, void *stream);
 
 /* Outcome of one system of a batched solve (device struct). */
 typedef struct bnc_batch_result {

@@ -18,6 +18,7 @@ from .bnc import (  # noqa: F401
     BNC_NONFINITE,
     BNC_SINGULAR,
     BNC_STAGNATED,
+    BNC_TIMED_OUT,
     OP_ADD,
     OP_FMS,
     OP_MUL,
@@ -41,6 +42,9 @@ from .bnc import (  # noqa: F401
     profile_enable,
     profile_read,
     refine,
+    refine_async,
+    refine_result,
+    refine_result_bytes,
     refine_workspace_size,
     residual,
     residual_workspace_size,

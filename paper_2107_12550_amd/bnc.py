@@ -18,6 +18,7 @@ lib_path = os.path.join(_HERE, "libbnc.so")
 
 BNC_CONVERGED, BNC_MAX_ITER, BNC_SINGULAR, BNC_NONFINITE, BNC_BAD_SIZE, BNC_STAGNATED = 0, 1, 2, 3, 4, 5
 BNC_AUTO = 0
+BNC_TIMED_OUT = 6
 BNC_ERR_HIP, BNC_ERR_UNSUPPORTED, BNC_ERR_WORKSPACE, BNC_ERR_TIMEOUT = -100, -101, -102, -103
 OP_FMS, OP_MUL, OP_ADD, OP_RECIP, OP_ROUND4 = 0, 1, 2, 3, 4
 _SUFFIX = {1: "d", 2: "dd", 3: "td", 4: "qd"}
@@ -104,6 +105,9 @@ def _load() -> ctypes.CDLL:
     L.bnc_refine.argtypes = [I64, I32, VP, I64, I64, VP, I64, VP, I64, VP, ctypes.c_size_t,
                              ctypes.POINTER(RefineOpts), ctypes.POINTER(RefineResult), VP]
     L.bnc_refine.restype = ctypes.c_int
+    L.bnc_refine_async.argtypes = [I64, I32, VP, I64, I64, VP, I64, VP, I64, VP, ctypes.c_size_t,
+                                   ctypes.POINTER(RefineOpts), VP, VP]
+    L.bnc_refine_async.restype = ctypes.c_int
     L.bnc_refine_batched_workspace_size.argtypes = [I32, I32]
     L.bnc_refine_batched_workspace_size.restype = ctypes.c_size_t
     L.bnc_refine_batched_default_slots.argtypes = [I32, I32, I32]
@@ -278,6 +282,35 @@ def refine(A: torch.Tensor, b: torch.Tensor, K: int, max_iter: int = 30, rtol: f
     return dict(x=x, status=r.status, iters=r.iters, info=r.info, resid_norm=r.resid_norm, x_norm=r.x_norm,
                 a_norm=r.a_norm, residual_inexact=bool(r.residual_inexact), final_words=r.final_words,
                 escalations=r.escalations, first_words=r.first_words)
+
+
+def refine_async(A: torch.Tensor, b: torch.Tensor, K: int, result: torch.Tensor, x: torch.Tensor,
+                 work: torch.Tensor, max_iter: int = 30, rtol: float = 0.0, atol: float = 0.0,
+                 ctol: float = 2.0 ** -208, ozaki: int = 0, stagnation_ratio: float = 0.0, long_words: int = 4):
+    """bnc_refine_async: the refinement with its loop driven on the device,
+    enqueued on the current stream (capturable).  result: a uint8 CUDA
+    tensor of sizeof(bnc_refine_result) bytes that receives the outcome;
+    read it with refine_result() once the stream is through."""
+    aw, n = A.shape[0], A.shape[1]
+    if result.numel() < ctypes.sizeof(RefineResult) or result.dtype != torch.uint8 or not result.is_cuda:
+        raise BncError("result: expected a CUDA uint8 tensor of sizeof(bnc_refine_result) bytes")
+    o = RefineOpts(K, max_iter, rtol, atol, ctol, ozaki, 0, stagnation_ratio, 0, 0, long_words, 0, None, None)
+    _check(_lib.bnc_refine_async(n, aw, _dev(A, "A", 3), n, n * n, _dev(b, "b", 2), n, _dev(x, "x", 2), n,
+                                 ctypes.c_void_p(work.data_ptr()), work.numel(), ctypes.byref(o),
+                                 ctypes.c_void_p(result.data_ptr()), _stream()), "refine_async")
+
+
+def refine_result(result: torch.Tensor) -> dict:
+    """Outcome fields from a device bnc_refine_result (synchronises)."""
+    raw = result.cpu().numpy().tobytes()[:ctypes.sizeof(RefineResult)]
+    r = RefineResult.from_buffer_copy(raw)
+    return dict(status=r.status, iters=r.iters, info=r.info, resid_norm=r.resid_norm, x_norm=r.x_norm,
+                a_norm=r.a_norm, residual_inexact=bool(r.residual_inexact), final_words=r.final_words,
+                escalations=r.escalations, first_words=r.first_words)
+
+
+def refine_result_bytes() -> int:
+    return ctypes.sizeof(RefineResult)
 
 
 class BatchSolver:

@@ -51,6 +51,10 @@ size_t refine_workspace_bytes(int64_t n, int K);
 int refine_drive(int K0, int64_t n, int aw, const double *A, int64_t lda, int64_t ldpa, const double *b,
                  int64_t ldpb, double *x, int64_t ldpx, void *work, const bnc_refine_opts *o, bnc_refine_result *res,
                  hipStream_t s);
+template <int K>
+int refine_async_run(int64_t n, int aw, const double *A, int64_t lda, int64_t ldpa, const double *b, int64_t ldpb,
+                     double *x, int64_t ldpx, void *work, const bnc_refine_opts *o, bnc_refine_result *res,
+                     hipStream_t s);
 size_t residual_workspace_bytes(int64_t n);
 int residual_ws_run(int64_t n, int aw, int lw, const double *A, int64_t lda, int64_t ldpa, const double *x,
                     int64_t ldpx, const double *b, int64_t ldpb, double *r, int64_t ldpr, int32_t *inexact, void *work,
@@ -451,6 +455,53 @@ int bnc_refine(int64_t n, int32_t a_words, const double *A, int64_t lda, int64_t
     }
 }
 
+int bnc_refine_async(int64_t n, int32_t a_words, const double *A, int64_t lda, int64_t ldpa, const double *b,
+                     int64_t ldpb, double *x, int64_t ldpx, void *work, size_t work_bytes,
+                     const bnc_refine_opts *opts, bnc_refine_result *result, void *stream)
+{
+    if (n < 1)
+        return fail_arg(-1, "refine_async: n < 1");
+    if (a_words != 1 && a_words != 4)
+        return fail_arg(-2, "refine_async: a_words must be 1 or 4");
+    if (!A)
+        return fail_arg(-3, "refine_async: A is NULL");
+    if (lda < n)
+        return fail_arg(-4, "refine_async: lda < n");
+    if (a_words > 1 && ldpa < lda * n)
+        return fail_arg(-5, "refine_async: ldpa < lda * n");
+    if (!b)
+        return fail_arg(-6, "refine_async: b is NULL");
+    if (ldpb < n)
+        return fail_arg(-7, "refine_async: ldpb < n");
+    if (!x)
+        return fail_arg(-8, "refine_async: x is NULL");
+    if (ldpx < n)
+        return fail_arg(-9, "refine_async: ldpx < n");
+    if (!work)
+        return fail_arg(-10, "refine_async: work is NULL");
+    if (!opts || opts->factor_words < 1 || opts->factor_words > 4 || opts->escalate != 0 || opts->max_iter < 0 ||
+        !(opts->rtol >= 0) || !(opts->atol >= 0) || !(opts->ctol >= 0) || !(opts->stagnation_ratio >= 0) ||
+        opts->ozaki_slices < 0 || opts->ozaki_slices > OZ_SMAX ||
+        (opts->long_words != 0 && opts->long_words != 4 && opts->long_words != 8))
+        return fail_arg(-12, "refine_async: invalid options (factor_words 1..4, escalate 0)");
+    if (!result)
+        return fail_arg(-13, "refine_async: result is NULL");
+    if (n > 16384)
+        return fail_arg(BNC_ERR_UNSUPPORTED, "refine_async: n > 16384");
+    if (work_bytes < refine_workspace_bytes(n, opts->factor_words))
+        return fail_arg(-11, "refine_async: workspace too small");
+    switch (opts->factor_words) {
+    case 1:
+        return refine_async_run<1>(n, a_words, A, lda, ldpa, b, ldpb, x, ldpx, work, opts, result, S(stream));
+    case 2:
+        return refine_async_run<2>(n, a_words, A, lda, ldpa, b, ldpb, x, ldpx, work, opts, result, S(stream));
+    case 3:
+        return refine_async_run<3>(n, a_words, A, lda, ldpa, b, ldpb, x, ldpx, work, opts, result, S(stream));
+    default:
+        return refine_async_run<4>(n, a_words, A, lda, ldpa, b, ldpb, x, ldpx, work, opts, result, S(stream));
+    }
+}
+
 size_t bnc_refine_batched_workspace_size(int32_t factor_words, int32_t slots)
 {
     if (factor_words < 1 || factor_words > 4 || slots < 0)
@@ -737,6 +788,8 @@ const char *bnc_status_string(int32_t status)
         return "bad_size";
     case BNC_STAGNATED:
         return "stagnated";
+    case BNC_TIMED_OUT:
+        return "timed_out";
     default:
         return "unknown";
     }

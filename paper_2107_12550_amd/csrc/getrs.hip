@@ -15,6 +15,11 @@
 
 namespace bnc {
 
+// skip flag of the device-driven refinement loop (nullptr: run)
+#define TS_SKIP_IF(skip)      \
+    if ((skip) && *(skip))    \
+        return;
+
 constexpr int TS_BS = 64;  // block rows; equals the workgroup size
 
 // perm[i] = original index of the row that ends at position i after the
@@ -64,8 +69,9 @@ __global__ void __launch_bounds__(256) k_ipiv_to_perm(int64_t n, const int64_t *
 
 template <int K>
 __global__ void k_gather(int64_t n, const int32_t *__restrict__ perm, const double *__restrict__ src, int64_t lds_,
-                         double *__restrict__ dst, int64_t ldd)
+                         double *__restrict__ dst, int64_t ldd, const int *__restrict__ skip)
 {
+    TS_SKIP_IF(skip);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n)
         return;
@@ -218,8 +224,9 @@ __device__ __forceinline__ void ts_wait_done(const int *done, int want, unsigned
 }
 
 // both output planes to XSENT, abort flag cleared
-__global__ void k_ts_reset(uint64_t *xs, int64_t nw, int *abort_flag)
+__global__ void k_ts_reset(uint64_t *xs, int64_t nw, int *abort_flag, const int *__restrict__ skip)
 {
+    TS_SKIP_IF(skip);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nw; e += stride)
         xs[e] = (uint64_t)TS_SENT;
@@ -234,8 +241,9 @@ __global__ void k_ts_raise(int *abort_flag)
         *abort_flag = 1;
 }
 
-__global__ void k_ts_info(const int *abort_flag, int64_t *info)
+__global__ void k_ts_info(const int *abort_flag, int64_t *info, const int *__restrict__ skip)
 {
+    TS_SKIP_IF(skip);
     if (blockIdx.x == 0 && threadIdx.x == 0 && *abort_flag)
         *info = -1;
 }
@@ -250,8 +258,9 @@ __global__ void k_ts_zero(int64_t *info)
 template <int K>
 __global__ void __launch_bounds__(2 * TS_BS)
     k_trsv_lower(const double *__restrict__ LU, int64_t lda, int64_t ldp, const double *__restrict__ y, int64_t ldy,
-                 int64_t n, double *__restrict__ x, int *__restrict__ abort_flag)
+                 int64_t n, double *__restrict__ x, int *__restrict__ abort_flag, const int *__restrict__ skip)
 {
+    TS_SKIP_IF(skip);  // every thread of the grid reads the same flag
     extern __shared__ double dblk[];  // own diagonal block [w][c][r]
     __shared__ double yb[2][TS_BS][K];
     __shared__ int stamp[2][TS_BS];
@@ -373,8 +382,9 @@ template <int K>
 __global__ void __launch_bounds__(2 * TS_BS)
     k_trsv_upper(const double *__restrict__ LU, int64_t lda, int64_t ldp, const double *__restrict__ rd,
                  const double *__restrict__ x, double *__restrict__ xo, double *__restrict__ y, int64_t ldy, int64_t n,
-                 int *__restrict__ abort_flag)
+                 int *__restrict__ abort_flag, const int *__restrict__ skip)
 {
+    TS_SKIP_IF(skip);
     extern __shared__ double dblk[];
     __shared__ double xb[2][TS_BS][K];
     __shared__ int stamp[2][TS_BS];
@@ -551,7 +561,7 @@ int diag_recip_run(int64_t n, const double *LU, int64_t lda, int64_t ldp, double
 // when a bounded wait of the pair gave up (never cleared here).
 template <int K>
 int trsv_pair(int64_t n, const double *LU, int64_t lda, int64_t ldp, const double *rd, double *y, int64_t ldy,
-              void *ws, hipStream_t s, int64_t *info)
+              void *ws, hipStream_t s, int64_t *info, const int *skip)
 {
     if (n == 0)
         return BNC_OK;
@@ -561,20 +571,20 @@ int trsv_pair(int64_t n, const double *LU, int64_t lda, int64_t ldp, const doubl
     double *x1 = (double *)ws, *x2 = x1 + (size_t)K * n;
     int *abort_flag = (int *)(x2 + (size_t)K * n);
     hipLaunchKernelGGL(k_ts_reset, dim3((unsigned)(ceil_div(2 * K * n, 256) < 64 ? ceil_div(2 * K * n, 256) : 64)),
-                       dim3(256), 0, s, (uint64_t *)x1, (int64_t)(2 * K * n), abort_flag);
+                       dim3(256), 0, s, (uint64_t *)x1, (int64_t)(2 * K * n), abort_flag, skip);
     BNC_LAUNCH_CHECK();
     if (force_timeout_bits() & 2) {
         hipLaunchKernelGGL(k_ts_raise, dim3(1), dim3(64), 0, s, abort_flag);
         BNC_LAUNCH_CHECK();
     }
     hipLaunchKernelGGL((k_trsv_lower<K>), dim3((unsigned)nblk), dim3(2 * TS_BS), lds, s, LU, lda, ldp, y, ldy, n, x1,
-                       abort_flag);
+                       abort_flag, skip);
     BNC_LAUNCH_CHECK();
     hipLaunchKernelGGL((k_trsv_upper<K>), dim3((unsigned)nblk), dim3(2 * TS_BS), lds, s, LU, lda, ldp, rd, x1, x2, y, ldy,
-                       n, abort_flag);
+                       n, abort_flag, skip);
     BNC_LAUNCH_CHECK();
     if (info) {
-        hipLaunchKernelGGL(k_ts_info, dim3(1), dim3(64), 0, s, (const int *)abort_flag, info);
+        hipLaunchKernelGGL(k_ts_info, dim3(1), dim3(64), 0, s, (const int *)abort_flag, info, skip);
         BNC_LAUNCH_CHECK();
     }
     return BNC_OK;
@@ -640,13 +650,15 @@ int ipiv_to_perm(int64_t n, const int64_t *ipiv, int32_t *perm, hipStream_t s)
 // (K planes, stride n) and y buffer
 template <int K>
 int getrs_perm(int64_t n, const double *LU, int64_t lda, int64_t ldp, const int32_t *perm, const double *rd,
-               const double *b, int64_t ldb, double *y, int64_t ldy, void *ws, hipStream_t s, int64_t *info)
+               const double *b, int64_t ldb, double *y, int64_t ldy, void *ws, hipStream_t s, int64_t *info,
+               const int *skip)
 {
     if (n == 0)
         return BNC_OK;
-    hipLaunchKernelGGL((k_gather<K>), dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, n, perm, b, ldb, y, ldy);
+    hipLaunchKernelGGL((k_gather<K>), dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, n, perm, b, ldb, y, ldy,
+                       skip);
     BNC_LAUNCH_CHECK();
-    return trsv_pair<K>(n, LU, lda, ldp, rd, y, ldy, ws, s, info);
+    return trsv_pair<K>(n, LU, lda, ldp, rd, y, ldy, ws, s, info, skip);
 }
 
 // scr: getrs_workspace_bytes(K, n) bytes; info (nullable) gets 0, or -1 if
@@ -672,7 +684,7 @@ int getrs_run(int64_t n, int64_t nrhs, const double *LU, int64_t lda, int64_t ld
         return rc;
     for (int64_t c = 0; c < nrhs; ++c) {
         double *bc = B + c * ldb;
-        rc = getrs_perm<K>(n, LU, lda, ldp, perm, rd, bc, ldpb, y, n, ws, s, info);
+        rc = getrs_perm<K>(n, LU, lda, ldp, perm, rd, bc, ldpb, y, n, ws, s, info, nullptr);
         if (rc)
             return rc;
         hipLaunchKernelGGL((k_copy_vec<K>), dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, n, y, n, bc, ldpb);
@@ -683,7 +695,8 @@ int getrs_run(int64_t n, int64_t nrhs, const double *LU, int64_t lda, int64_t ld
 
 #define INST(K)                                                                                                     \
     template int getrs_perm<K>(int64_t, const double *, int64_t, int64_t, const int32_t *, const double *,          \
-                               const double *, int64_t, double *, int64_t, void *, hipStream_t, int64_t *);         \
+                               const double *, int64_t, double *, int64_t, void *, hipStream_t, int64_t *,          \
+                               const int *);                                                                        \
     template int diag_recip_run<K>(int64_t, const double *, int64_t, int64_t, double *, hipStream_t);               \
     template int getrs_run<K>(int64_t, int64_t, const double *, int64_t, int64_t, const int64_t *, double *,        \
                               int64_t, int64_t, int64_t *, void *, hipStream_t);

@@ -23,13 +23,21 @@
 
 namespace bnc {
 
+// Kernels of the refinement loop take an optional device flag: when it is
+// set they return at once (the device-driven loop of bnc_refine_async skips
+// the iterations after its stopping tests have fired).  nullptr: run.
+#define BNC_SKIP_IF(skip)     \
+    if ((skip) && *(skip))    \
+        return;
+
 template <int K>
 int getrf_run(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int64_t *info, void *scr,
               hipStream_t s, int oz, double *oz_buf);
 size_t oz_slices_bytes(int64_t n);
 template <int K>
 int getrs_perm(int64_t n, const double *LU, int64_t lda, int64_t ldp, const int32_t *perm, const double *rd,
-               const double *b, int64_t ldb, double *y, int64_t ldy, void *ws, hipStream_t s, int64_t *info);
+               const double *b, int64_t ldb, double *y, int64_t ldy, void *ws, hipStream_t s, int64_t *info,
+               const int *skip = nullptr);
 size_t trsv_ws_bytes(int64_t n);
 size_t features_workspace_bytes(int slots);
 int features_run(int64_t count, const int64_t *n, const double *const *A, const double *const *b,
@@ -118,8 +126,9 @@ __global__ void __launch_bounds__(RES_ROWS *RES_WAVES)
     k_resid_partial(int64_t n, const double *__restrict__ A, int64_t lda, int64_t ldpa, const double *__restrict__ x,
                     int64_t ldx, const double *__restrict__ b, int64_t ldb, const double *__restrict__ rowmax,
                     const double *__restrict__ xmaxp, const ExpBounds *__restrict__ ebp, int h, int64_t chunk,
-                    double *__restrict__ part, int32_t *__restrict__ inexact)
+                    double *__restrict__ part, int32_t *__restrict__ inexact, const int *__restrict__ skip)
 {
+    BNC_SKIP_IF(skip);
     const int lane = threadIdx.x % RES_ROWS, wv = threadIdx.x / RES_ROWS;
     const int64_t i = (int64_t)blockIdx.x * RES_ROWS + lane;
     const int split = blockIdx.y * RES_WAVES + wv;
@@ -148,8 +157,9 @@ __global__ void __launch_bounds__(RES_ROWS *RES_WAVES)
 
 // smallest floor(log2|v|) over the nonzero words (2000 if none)
 __global__ void k_minexp(int64_t rows, int64_t cols, int64_t ld, int words, int64_t ldp, const double *__restrict__ v,
-                         int *__restrict__ out)
+                         int *__restrict__ out, const int *__restrict__ skip)
 {
+    BNC_SKIP_IF(skip);
     __shared__ int s[256];
     int m = 2000;
     const int64_t n = rows * cols;
@@ -174,8 +184,9 @@ __global__ void k_minexp(int64_t rows, int64_t cols, int64_t ld, int words, int6
         atomicMin(out, s[0]);
 }
 
-__global__ void k_fill_i32(int *p, int64_t n, int v)
+__global__ void k_fill_i32(int *p, int64_t n, int v, const int *__restrict__ skip)
 {
+    BNC_SKIP_IF(skip);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n)
         p[i] = v;
@@ -187,8 +198,9 @@ __global__ void k_fill_i32(int *p, int64_t n, int v)
 __global__ void __launch_bounds__(256)
     k_resid_sum(int64_t n, int S, double *__restrict__ part, const double *__restrict__ rowmax,
                 const double *__restrict__ xmaxp, const ExpBounds *__restrict__ ebp, const double *__restrict__ b,
-                int h)
+                int h, const int *__restrict__ skip)
 {
+    BNC_SKIP_IF(skip);
     const int64_t i = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
     const int q = (int)blockIdx.y * 4 + (int)(threadIdx.x >> 6);
     if (i >= n || q >= RB_NB)
@@ -206,8 +218,10 @@ template <int LW>
 __global__ void __launch_bounds__(256)
     k_resid_final(int64_t n, int S, const double *__restrict__ part, const double *__restrict__ rowmax,
                   const double *__restrict__ xmaxp, const ExpBounds *__restrict__ ebp, const double *__restrict__ b,
-                  int h, double *__restrict__ r, int64_t ldr, int32_t *__restrict__ inexact)
+                  int h, double *__restrict__ r, int64_t ldr, int32_t *__restrict__ inexact,
+                  const int *__restrict__ skip)
 {
+    BNC_SKIP_IF(skip);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n)
         return;
@@ -238,8 +252,9 @@ __global__ void __launch_bounds__(256)
 
 // ---- small vector / matrix helpers ------------------------------------------
 
-__global__ void k_fill_u64(uint64_t *p, int64_t n, uint64_t v)
+__global__ void k_fill_u64(uint64_t *p, int64_t n, uint64_t v, const int *__restrict__ skip)
 {
+    BNC_SKIP_IF(skip);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n)
         p[i] = v;
@@ -299,8 +314,9 @@ __global__ void k_rowmax(int64_t n, const double *__restrict__ A, int64_t lda,
 // max |v(i, j)| over rows x cols entries (leading dimension ld), folded into
 // *bits with an integer max (non-negative doubles order like their bits)
 __global__ void k_absmax(int64_t rows, int64_t cols, int64_t ld, const double *__restrict__ v,
-                         unsigned long long *__restrict__ bits)
+                         unsigned long long *__restrict__ bits, const int *__restrict__ skip)
 {
+    BNC_SKIP_IF(skip);
     __shared__ double s[256];
     double m = 0.0;
     const int64_t n = rows * cols;
@@ -320,8 +336,10 @@ __global__ void k_absmax(int64_t rows, int64_t cols, int64_t ld, const double *_
 // deterministic sum of (v_i 2^-e)^2: fixed per-block partials, then one
 // block sums the partials in order
 __global__ void k_sumsq_part(int64_t rows, int64_t cols, int64_t ld, const double *__restrict__ v,
-                             const unsigned long long *__restrict__ maxbits, double *__restrict__ part)
+                             const unsigned long long *__restrict__ maxbits, double *__restrict__ part,
+                             const int *__restrict__ skip)
 {
+    BNC_SKIP_IF(skip);
     __shared__ double s[256];
     const double m = __longlong_as_double((long long)*maxbits);
     const double sc = pow2(-(norm_exp(m) + 1));
@@ -342,8 +360,10 @@ __global__ void k_sumsq_part(int64_t rows, int64_t cols, int64_t ld, const doubl
         part[blockIdx.x] = s[0];
 }
 
-__global__ void k_sumsq_final(int nparts, const double *__restrict__ part, double *__restrict__ out)
+__global__ void k_sumsq_final(int nparts, const double *__restrict__ part, double *__restrict__ out,
+                              const int *__restrict__ skip)
 {
+    BNC_SKIP_IF(skip);
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         double s = 0.0;
         for (int t = 0; t < nparts; ++t)
@@ -355,8 +375,10 @@ __global__ void k_sumsq_final(int nparts, const double *__restrict__ part, doubl
 // dst (K words) = renorm(src (LW words) * 2^-e), e from the power-of-two max
 template <int K, int LW>
 __global__ void k_round_scaled(int64_t n, const double *__restrict__ src, int64_t lds_,
-                               const unsigned long long *__restrict__ maxbits, double *__restrict__ dst, int64_t ldd)
+                               const unsigned long long *__restrict__ maxbits, double *__restrict__ dst, int64_t ldd,
+                               const int *__restrict__ skip)
 {
+    BNC_SKIP_IF(skip);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n)
         return;
@@ -373,8 +395,10 @@ __global__ void k_round_scaled(int64_t n, const double *__restrict__ src, int64_
 
 // x = extend(z), LW words from K words
 template <int K, int LW>
-__global__ void k_extend(int64_t n, const double *__restrict__ z, int64_t ldz, double *__restrict__ x, int64_t ldx)
+__global__ void k_extend(int64_t n, const double *__restrict__ z, int64_t ldz, double *__restrict__ x, int64_t ldx,
+                         const int *__restrict__ skip)
 {
+    BNC_SKIP_IF(skip);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n)
         return;
@@ -387,8 +411,10 @@ __global__ void k_extend(int64_t n, const double *__restrict__ z, int64_t ldz, d
 // in LW-word addition
 template <int K, int LW>
 __global__ void k_scale_update(int64_t n, double *__restrict__ z, int64_t ldz,
-                               const unsigned long long *__restrict__ rmaxbits, double *__restrict__ x, int64_t ldx)
+                               const unsigned long long *__restrict__ rmaxbits, double *__restrict__ x, int64_t ldx,
+                               const int *__restrict__ skip)
 {
+    BNC_SKIP_IF(skip);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n)
         return;
@@ -452,19 +478,19 @@ size_t residual_scratch_bytes(int64_t n)
 // minimum exponents of the words of a rows x cols (ld) matrix with `words`
 // planes (ldp apart), folded into *out
 int minexp_run(int64_t rows, int64_t cols, int64_t ld, int words, int64_t ldp, const double *v, int *out,
-               hipStream_t s)
+               hipStream_t s, const int *skip = nullptr)
 {
     unsigned g = grid1(rows * cols);
     if (g > RED_BLOCKS)
         g = RED_BLOCKS;
-    hipLaunchKernelGGL(k_minexp, dim3(g), dim3(256), 0, s, rows, cols, ld, words, ldp, v, out);
+    hipLaunchKernelGGL(k_minexp, dim3(g), dim3(256), 0, s, rows, cols, ld, words, ldp, v, out, skip);
     BNC_LAUNCH_CHECK();
     return BNC_OK;
 }
 
-int fill_i32_run(int *p, int64_t n, int v, hipStream_t s)
+int fill_i32_run(int *p, int64_t n, int v, hipStream_t s, const int *skip = nullptr)
 {
-    hipLaunchKernelGGL(k_fill_i32, dim3(grid1(n)), dim3(256), 0, s, p, n, v);
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid1(n)), dim3(256), 0, s, p, n, v, skip);
     BNC_LAUNCH_CHECK();
     return BNC_OK;
 }
@@ -473,7 +499,7 @@ int fill_i32_run(int *p, int64_t n, int v, hipStream_t s)
 // exponent bounds precomputed on the device; x, b, r have lw words
 int residual_run(int64_t n, int aw, int lw, const double *A, int64_t lda, int64_t ldpa, const double *x, int64_t ldx,
                  const double *b, int64_t ldb, const double *rowmax, const double *xmax, const void *ebounds,
-                 double *part, double *r, int64_t ldr, int32_t *inexact, hipStream_t s)
+                 double *part, double *r, int64_t ldr, int32_t *inexact, hipStream_t s, const int *skip = nullptr)
 {
     if (n == 0)
         return BNC_OK;
@@ -487,26 +513,26 @@ int residual_run(int64_t n, int aw, int lw, const double *A, int64_t lda, int64_
     const dim3 t(RES_ROWS * RES_WAVES);
     if (aw == 1 && lw == 4)
         hipLaunchKernelGGL((k_resid_partial<1, 4>), grid, t, 0, s, n, A, lda, ldpa, x, ldx, b, ldb, rowmax, xmax, eb,
-                           h, chunk, part, inexact);
+                           h, chunk, part, inexact, skip);
     else if (aw == 4 && lw == 4)
         hipLaunchKernelGGL((k_resid_partial<4, 4>), grid, t, 0, s, n, A, lda, ldpa, x, ldx, b, ldb, rowmax, xmax, eb,
-                           h, chunk, part, inexact);
+                           h, chunk, part, inexact, skip);
     else if (aw == 1)
         hipLaunchKernelGGL((k_resid_partial<1, 8>), grid, t, 0, s, n, A, lda, ldpa, x, ldx, b, ldb, rowmax, xmax, eb,
-                           h, chunk, part, inexact);
+                           h, chunk, part, inexact, skip);
     else
         hipLaunchKernelGGL((k_resid_partial<4, 8>), grid, t, 0, s, n, A, lda, ldpa, x, ldx, b, ldb, rowmax, xmax, eb,
-                           h, chunk, part, inexact);
+                           h, chunk, part, inexact, skip);
     BNC_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_resid_sum, dim3((unsigned)ceil_div(n, 64), (unsigned)ceil_div(RB_NB, 4)), dim3(256), 0, s, n,
-                       S * RES_WAVES, part, rowmax, xmax, eb, b, h);
+                       S * RES_WAVES, part, rowmax, xmax, eb, b, h, skip);
     BNC_LAUNCH_CHECK();
     if (lw == 4)
         hipLaunchKernelGGL(k_resid_final<4>, dim3(grid1(n)), dim3(256), 0, s, n, 1, (const double *)part, rowmax, xmax,
-                           eb, b, h, r, ldr, inexact);
+                           eb, b, h, r, ldr, inexact, skip);
     else
         hipLaunchKernelGGL(k_resid_final<8>, dim3(grid1(n)), dim3(256), 0, s, n, 1, (const double *)part, rowmax, xmax,
-                           eb, b, h, r, ldr, inexact);
+                           eb, b, h, r, ldr, inexact, skip);
     BNC_LAUNCH_CHECK();
     return BNC_OK;
 }
@@ -521,7 +547,8 @@ size_t residual_workspace_bytes(int64_t n)
 }
 
 int rowmax_run(int64_t n, const double *A, int64_t lda, double *rowmax, hipStream_t s);
-int absmax_run(int64_t rows, int64_t cols, int64_t ld, const double *v, unsigned long long *bits, hipStream_t s);
+int absmax_run(int64_t rows, int64_t cols, int64_t ld, const double *v, unsigned long long *bits, hipStream_t s,
+               const int *skip = nullptr);
 
 int residual_ws_run(int64_t n, int aw, int lw, const double *A, int64_t lda, int64_t ldpa, const double *x,
                     int64_t ldpx, const double *b, int64_t ldpb, double *r, int64_t ldpr, int32_t *inexact, void *work,
@@ -546,7 +573,8 @@ int residual_ws_run(int64_t n, int aw, int lw, const double *A, int64_t lda, int
 // rowmax of |A0| and a one-element max of a vector's leading words
 int rowmax_run(int64_t n, const double *A, int64_t lda, double *rowmax, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_fill_u64, dim3(grid1(n)), dim3(256), 0, s, (uint64_t *)rowmax, n, (uint64_t)0);
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid1(n)), dim3(256), 0, s, (uint64_t *)rowmax, n, (uint64_t)0,
+                       (const int *)nullptr);
     BNC_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_rowmax, dim3(grid1(n), ROWMAX_SPLIT), dim3(256), 0, s, n, A, lda,
                        (unsigned long long *)rowmax);
@@ -554,27 +582,28 @@ int rowmax_run(int64_t n, const double *A, int64_t lda, double *rowmax, hipStrea
     return BNC_OK;
 }
 
-int absmax_run(int64_t rows, int64_t cols, int64_t ld, const double *v, unsigned long long *bits, hipStream_t s)
+int absmax_run(int64_t rows, int64_t cols, int64_t ld, const double *v, unsigned long long *bits, hipStream_t s,
+               const int *skip)
 {
-    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, (uint64_t *)bits, (int64_t)1, (uint64_t)0);
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, (uint64_t *)bits, (int64_t)1, (uint64_t)0, skip);
     BNC_LAUNCH_CHECK();
     unsigned g = grid1(rows * cols);
     if (g > RED_BLOCKS)
         g = RED_BLOCKS;
-    hipLaunchKernelGGL(k_absmax, dim3(g), dim3(256), 0, s, rows, cols, ld, v, bits);
+    hipLaunchKernelGGL(k_absmax, dim3(g), dim3(256), 0, s, rows, cols, ld, v, bits, skip);
     BNC_LAUNCH_CHECK();
     return BNC_OK;
 }
 
 int sumsq_run(int64_t rows, int64_t cols, int64_t ld, const double *v, const unsigned long long *maxbits,
-              double *part, double *out, hipStream_t s)
+              double *part, double *out, hipStream_t s, const int *skip = nullptr)
 {
     unsigned g = grid1(rows * cols);
     if (g > RED_BLOCKS)
         g = RED_BLOCKS;
-    hipLaunchKernelGGL(k_sumsq_part, dim3(g), dim3(256), 0, s, rows, cols, ld, v, maxbits, part);
+    hipLaunchKernelGGL(k_sumsq_part, dim3(g), dim3(256), 0, s, rows, cols, ld, v, maxbits, part, skip);
     BNC_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_sumsq_final, dim3(1), dim3(64), 0, s, (int)g, (const double *)part, out);
+    hipLaunchKernelGGL(k_sumsq_final, dim3(1), dim3(64), 0, s, (int)g, (const double *)part, out, skip);
     BNC_LAUNCH_CHECK();
     return BNC_OK;
 }
@@ -596,7 +625,12 @@ struct Scal {
     int64_t tinfo;  // -1 once a substitution's bounded wait gave up
     ExpBounds eb;   // a, x, b
     int32_t pad2;
+    // the device-driven loop (bnc_refine_async): done is the kernels' skip
+    // flag, set once a stopping test or a failure has decided the outcome
+    int32_t done, status, iters, nz;
+    double zlast, zprev, thresh_c, a_norm, resid_norm, x_norm;
 };
+static_assert(sizeof(Scal) % 8 == 0, "Scal is cleared as 64-bit words");
 
 struct RefineLayout {
     size_t lu, ipiv, perm, rd, r, v, rowmax, part, red, scal, getrf, oz, flags, sel, total;
@@ -756,7 +790,8 @@ int refine_drive(int K0, int64_t n, int aw, const double *A, int64_t lda, int64_
     }
     res->first_words = K0;
     res->final_words = K0;
-    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, (uint64_t *)sc, (int64_t)(sizeof(Scal) / 8), (uint64_t)0);
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, (uint64_t *)sc, (int64_t)(sizeof(Scal) / 8), (uint64_t)0,
+                       (const int *)nullptr);
     BNC_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_check_finite, dim3(grid1(n * n)), dim3(256), 0, s, n, n, aw, A, lda, ldpa, &sc->nonfinite);
     BNC_LAUNCH_CHECK();
@@ -819,7 +854,7 @@ int refine_drive(int K0, int64_t n, int aw, const double *A, int64_t lda, int64_
         int rc2 = BNC_OK;
         BNC_KSWITCH(kc, {
             BNC_LSWITCH(lw, hipLaunchKernelGGL((k_round_scaled<KK, LL>), dim3(grid1(n)), dim3(256), 0, s, n, src,
-                                               lds, rmaxbits, r, n));
+                                               lds, rmaxbits, r, n, (const int *)nullptr));
             BNC_LAUNCH_CHECK();
             rc2 = getrs_perm<KK>(n, LU, n, ldp, perm, rd, r, n, v, n, tsflags, s, &sc->tinfo);
         });
@@ -850,7 +885,7 @@ int refine_drive(int K0, int64_t n, int aw, const double *A, int64_t lda, int64_
     if ((rc = solve(b, ldpb, nullptr)))
         return rc;
     BNC_KSWITCH(kc, BNC_LSWITCH(lw, hipLaunchKernelGGL((k_extend<KK, LL>), dim3(grid1(n)), dim3(256), 0, s, n,
-                                                       (const double *)v, n, x, ldpx)));
+                                                       (const double *)v, n, x, ldpx, (const int *)nullptr)));
     BNC_LAUNCH_CHECK();
 
     const double thresh_c = sqrt((double)n) * o->rtol * res->a_norm;
@@ -913,7 +948,8 @@ int refine_drive(int K0, int64_t n, int aw, const double *A, int64_t lda, int64_
         if ((rc = solve(r, n, (const unsigned long long *)&sc->rmax)))
             return rc;
         BNC_KSWITCH(kc, BNC_LSWITCH(lw, hipLaunchKernelGGL((k_scale_update<KK, LL>), dim3(grid1(n)), dim3(256), 0, s,
-                                                           n, v, n, (const unsigned long long *)&sc->rmax, x, ldpx)));
+                                                           n, v, n, (const unsigned long long *)&sc->rmax, x, ldpx,
+                                                           (const int *)nullptr)));
         BNC_LAUNCH_CHECK();
         if ((rc = absmax_run(n, 1, n, v, &sc->zmax, s)))
             return rc;
@@ -922,6 +958,208 @@ int refine_drive(int K0, int64_t n, int aw, const double *A, int64_t lda, int64_
     }
     res->status = status;
     res->iters = iters;
+    return BNC_OK;
+}
+
+// ---- the device-driven loop (bnc_refine_async) ---------------------------------
+// The same steps and tests as refine_drive, with every decision taken on the
+// device: all max_iter + 1 iterations are launched, and once the tests (or
+// a failure) have decided the outcome the flag sc->done makes every later
+// kernel of the loop return at once.  No host synchronisation, no
+// allocation: the sequence can be captured into a HIP graph and replayed
+// (the flags are cleared by a kernel at its start).
+
+__global__ void k_async_checked(Scal *sc)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0 && sc->nonfinite) {
+        sc->done = 1;
+        sc->status = BNC_NONFINITE;
+    }
+}
+
+// ||A||_F from the scaled sum of squares, and the listing's threshold
+// sqrt(n) rtol ||A||_F (the host driver's formulas)
+__global__ void k_async_anorm(Scal *sc, int64_t n, double rtol)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const double amax = __longlong_as_double((long long)sc->amax);
+        sc->a_norm = sqrt(sc->asq) * ldexp(1.0, norm_exp(amax) + 1);
+        sc->thresh_c = sqrt((double)n) * rtol * sc->a_norm;
+    }
+}
+
+// after the factorisation: an exactly zero pivot or a timed-out exchange
+// ends the loop
+__global__ void k_async_factored(Scal *sc)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0 && !sc->done && sc->info != 0) {
+        sc->done = 1;
+        sc->status = sc->info > 0 ? BNC_SINGULAR : BNC_TIMED_OUT;
+    }
+}
+
+// x = 0 when the loop ended before the first solution
+__global__ void k_async_zero_x(int64_t n, int lw, double *__restrict__ x, int64_t ldx, const Scal *__restrict__ sc)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && sc->done)
+        for (int w = 0; w < lw; ++w)
+            x[w * ldx + i] = 0.0;
+}
+
+// the stopping tests at the top of an iteration, in the host driver's order
+__global__ void k_async_tests(Scal *sc, double atol, double ctol, double stag, int max_iter)
+{
+    if (blockIdx.x != 0 || threadIdx.x != 0 || sc->done)
+        return;
+    const double rmax = __longlong_as_double((long long)sc->rmax), xmax = __longlong_as_double((long long)sc->xmax);
+    if (sc->nz > 0) {
+        sc->zprev = sc->zlast;
+        sc->zlast = __longlong_as_double((long long)sc->zmax);
+    }
+    const double nr = rmax == 0.0 ? 0.0 : sqrt(sc->rsq) * ldexp(1.0, norm_exp(rmax) + 1);
+    const double nx = xmax == 0.0 ? 0.0 : sqrt(sc->xsq) * ldexp(1.0, norm_exp(xmax) + 1);
+    sc->resid_norm = nr;
+    sc->x_norm = nx;
+    int st = -1;
+    if (sc->tinfo)
+        st = BNC_TIMED_OUT;
+    else if (nr < sc->thresh_c * nx + atol || (sc->nz > 0 && sc->zlast <= ctol * xmax))
+        st = BNC_CONVERGED;
+    else if (stag > 0.0 && sc->nz >= 2 && sc->zlast > stag * sc->zprev)
+        st = BNC_STAGNATED;
+    else if (sc->iters == max_iter)
+        st = BNC_MAX_ITER;
+    if (st >= 0) {
+        sc->status = st;
+        sc->done = 1;
+    }
+}
+
+__global__ void k_async_corrected(Scal *sc)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0 && !sc->done) {
+        ++sc->nz;
+        ++sc->iters;
+    }
+}
+
+__global__ void k_async_finish(const Scal *__restrict__ sc, int K, bnc_refine_result *__restrict__ res)
+{
+    if (blockIdx.x != 0 || threadIdx.x != 0)
+        return;
+    bnc_refine_result r{};
+    r.status = sc->done ? sc->status : BNC_MAX_ITER;
+    const bool rejected = r.status == BNC_NONFINITE;  // nothing was factorised
+    r.iters = sc->iters;
+    r.info = rejected ? 0 : sc->info;
+    r.resid_norm = sc->resid_norm;
+    r.x_norm = sc->x_norm;
+    r.a_norm = rejected ? 0.0 : sc->a_norm;
+    r.residual_inexact = sc->inexact ? 1 : 0;
+    r.final_words = K;
+    r.escalations = 0;
+    r.first_words = K;
+    *res = r;
+}
+
+template <int K>
+int refine_async_run(int64_t n, int aw, const double *A, int64_t lda, int64_t ldpa, const double *b, int64_t ldpb,
+                     double *x, int64_t ldpx, void *work, const bnc_refine_opts *o, bnc_refine_result *res,
+                     hipStream_t s)
+{
+    const RefineLayout L = refine_layout(n, K);
+    char *W = (char *)work;
+    double *LU = (double *)(W + L.lu);
+    int64_t *ipiv = (int64_t *)(W + L.ipiv);
+    int32_t *perm = (int32_t *)(W + L.perm);
+    double *rd = (double *)(W + L.rd);
+    double *r = (double *)(W + L.r);
+    double *v = (double *)(W + L.v);
+    double *rowmax = (double *)(W + L.rowmax);
+    double *part = (double *)(W + L.part);
+    double *red = (double *)(W + L.red);
+    Scal *sc = (Scal *)(W + L.scal);
+    void *gscr = W + L.getrf;
+    double *ozb = (double *)(W + L.oz);
+    void *tsflags = (void *)(W + L.flags);
+    const int64_t ldp = n * n;
+    const int lw = o->long_words ? o->long_words : 4;
+    const int *skip = &sc->done;
+    const unsigned long long *rmaxb = &sc->rmax;
+    int rc;
+
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, (uint64_t *)sc, (int64_t)(sizeof(Scal) / 8), (uint64_t)0,
+                       (const int *)nullptr);
+    BNC_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_check_finite, dim3(grid1(n * n)), dim3(256), 0, s, n, n, aw, A, lda, ldpa, &sc->nonfinite);
+    BNC_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_check_finite, dim3(grid1(n)), dim3(256), 0, s, n, (int64_t)1, lw, b, ldpb, ldpb,
+                       &sc->nonfinite);
+    BNC_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_async_checked, dim3(1), dim3(64), 0, s, sc);
+    BNC_LAUNCH_CHECK();
+    if ((rc = absmax_run(n, n, lda, A, &sc->amax, s)) || (rc = sumsq_run(n, n, lda, A, &sc->amax, red, &sc->asq, s)) ||
+        (rc = rowmax_run(n, A, lda, rowmax, s)) || (rc = fill_i32_run(&sc->eb.a, 3, 2000, s)) ||
+        (rc = minexp_run(n, n, lda, aw, ldpa, A, &sc->eb.a, s)) ||
+        (rc = minexp_run(n, 1, n, lw, ldpb, b, &sc->eb.b, s)))
+        return rc;
+    hipLaunchKernelGGL(k_async_anorm, dim3(1), dim3(64), 0, s, sc, n, o->rtol);
+    BNC_LAUNCH_CHECK();
+    // K-word copy of A and the factorisation (run unconditionally: on a
+    // rejected input its result is simply not used)
+    if (aw == 1)
+        hipLaunchKernelGGL((k_stage<K, 1>), dim3(grid1(n * n)), dim3(256), 0, s, n, A, lda, ldpa, LU, n, ldp);
+    else
+        hipLaunchKernelGGL((k_stage<K, 4>), dim3(grid1(n * n)), dim3(256), 0, s, n, A, lda, ldpa, LU, n, ldp);
+    BNC_LAUNCH_CHECK();
+    if ((rc = getrf_run<K>(n, LU, n, ldp, ipiv, &sc->info, gscr, s, o->ozaki_slices, ozb)))
+        return rc;
+    hipLaunchKernelGGL(k_async_factored, dim3(1), dim3(64), 0, s, sc);
+    BNC_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_async_zero_x, dim3(grid1(n)), dim3(256), 0, s, n, lw, x, ldpx, (const Scal *)sc);
+    BNC_LAUNCH_CHECK();
+    if ((rc = ipiv_to_perm(n, ipiv, perm, s)) || (rc = diag_recip_run<K>(n, LU, n, ldp, rd, s)))
+        return rc;
+    // v <- K-word solve of the K-word copy of src (scaled by 2^-e when rmax
+    // is given)
+    auto solve = [&](const double *src, int64_t lds, const unsigned long long *rmaxbits) -> int {
+        BNC_LSWITCH(lw, hipLaunchKernelGGL((k_round_scaled<K, LL>), dim3(grid1(n)), dim3(256), 0, s, n, src, lds,
+                                           rmaxbits, r, n, skip));
+        BNC_LAUNCH_CHECK();
+        return getrs_perm<K>(n, LU, n, ldp, perm, rd, r, n, v, n, tsflags, s, &sc->tinfo, skip);
+    };
+    if ((rc = solve(b, ldpb, nullptr)))
+        return rc;
+    BNC_LSWITCH(lw, hipLaunchKernelGGL((k_extend<K, LL>), dim3(grid1(n)), dim3(256), 0, s, n, (const double *)v, n, x,
+                                       ldpx, skip));
+    BNC_LAUNCH_CHECK();
+    for (int it = 0; it <= o->max_iter; ++it) {
+        if ((rc = absmax_run(n, 1, n, x, &sc->xmax, s, skip)) || (rc = fill_i32_run(&sc->eb.x, 1, 2000, s, skip)) ||
+            (rc = minexp_run(n, 1, n, lw, ldpx, x, &sc->eb.x, s, skip)) ||
+            (rc = residual_run(n, aw, lw, A, lda, ldpa, x, ldpx, b, ldpb, rowmax, (const double *)&sc->xmax, &sc->eb,
+                               part, r, n, &sc->inexact, s, skip)) ||
+            (rc = absmax_run(n, 1, n, r, &sc->rmax, s, skip)) ||
+            (rc = sumsq_run(n, 1, n, r, &sc->rmax, red, &sc->rsq, s, skip)) ||
+            (rc = sumsq_run(n, 1, n, x, &sc->xmax, red, &sc->xsq, s, skip)))
+            return rc;
+        hipLaunchKernelGGL(k_async_tests, dim3(1), dim3(64), 0, s, sc, o->atol, o->ctol, o->stagnation_ratio,
+                           o->max_iter);
+        BNC_LAUNCH_CHECK();
+        if (it == o->max_iter)
+            break;  // the tests above have ended the loop
+        if ((rc = solve(r, n, rmaxb)))
+            return rc;
+        BNC_LSWITCH(lw, hipLaunchKernelGGL((k_scale_update<K, LL>), dim3(grid1(n)), dim3(256), 0, s, n, v, n, rmaxb,
+                                           x, ldpx, skip));
+        BNC_LAUNCH_CHECK();
+        if ((rc = absmax_run(n, 1, n, v, &sc->zmax, s, skip)))
+            return rc;
+        hipLaunchKernelGGL(k_async_corrected, dim3(1), dim3(64), 0, s, sc);
+        BNC_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(k_async_finish, dim3(1), dim3(64), 0, s, (const Scal *)sc, K, res);
+    BNC_LAUNCH_CHECK();
     return BNC_OK;
 }
 
@@ -934,7 +1172,10 @@ int refine_run(int64_t n, int aw, const double *A, int64_t lda, int64_t ldpa, co
 
 #define INST(K)                                                                                                    \
     template int refine_run<K>(int64_t, int, const double *, int64_t, int64_t, const double *, int64_t, double *, \
-                               int64_t, void *, const bnc_refine_opts *, bnc_refine_result *, hipStream_t);
+                               int64_t, void *, const bnc_refine_opts *, bnc_refine_result *, hipStream_t);     \
+    template int refine_async_run<K>(int64_t, int, const double *, int64_t, int64_t, const double *, int64_t,     \
+                                     double *, int64_t, void *, const bnc_refine_opts *, bnc_refine_result *,     \
+                                     hipStream_t);
 INST(1)
 INST(2)
 INST(3)
