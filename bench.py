@@ -493,26 +493,72 @@ def sweep_main(args):
                              "info": int(state["info"].item()), "max_rel_err": err, "backward_error": berr})
                 log(f"[sweep] n={n} cond={cond:g} {WORD_NAME[K]}: getrf {t_f:.2f} ms, getrs {t_s:.3f} ms, "
                     f"err {err:.2e}, berr {berr:.2e}")
-    # one small refined solve, latency bound
-    n = 128
+    small = small_solve_latency(128)
+    print(json.dumps({"metric": "direct-method sweep (no refinement) and small refined-solve latency",
+                      "data": "synthetic", "dtype": "f64", "sweep": rows, "small_refined": small}))
+
+
+def small_solve_latency(n, K=3, reps=50):
+    """Latency of one small refined solve (uniform n, K-word factor, refined
+    to quad-double accuracy): through bnc_refine (host-driven loop, one
+    readback per iteration), through bnc_refine_async (device-driven loop,
+    enqueued), and as a replay of that call captured into a HIP graph."""
+    import torch
+
+    import paper_2107_12550_amd as P
+    import synth
     Ap, b, exact = synth.problem("uniform", n, config=0, instance=n)
     dA = torch.from_numpy(Ap).cuda()
     db = torch.from_numpy(b).cuda()
     dx = torch.empty((4, n), dtype=torch.float64, device="cuda")
-    work = torch.empty(P.refine_workspace_size(n, 3), dtype=torch.uint8, device="cuda")
-    for _ in range(5):
-        out = P.refine(dA, db, 3, x=dx, work=work)
-    reps = 50
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        out = P.refine(dA, db, 3, x=dx, work=work)
-    torch.cuda.synchronize()
-    us = (time.perf_counter() - t0) * 1e6 / reps
-    small = {"n": n, "kind": "uniform", "factor": "TD", "us_per_solve": us, "iters": out["iters"],
+    work = torch.empty(P.refine_workspace_size(n, K), dtype=torch.uint8, device="cuda")
+    res = torch.zeros(P.refine_result_bytes(), dtype=torch.uint8, device="cuda")
+
+    def timed(fn):
+        for _ in range(5):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e6 / reps
+
+    state = {}
+
+    def sync_solve():
+        state["out"] = P.refine(dA, db, K, x=dx, work=work)
+
+    us_sync = timed(sync_solve)
+    out = state["out"]
+    small = {"n": n, "kind": "uniform", "factor": WORD_NAME[K], "us_per_solve": us_sync, "iters": out["iters"],
              "status": out["status"], "max_rel_err": float(max_rel_err_vs_ones(dx.cpu().numpy()))}
-    print(json.dumps({"metric": "direct-method sweep (no refinement) and small refined-solve latency",
-                      "data": "synthetic", "dtype": "f64", "sweep": rows, "small_refined": small}))
+    # the device-driven loop enqueues max_iter + 1 iterations whatever it
+    # needs: the default cap, and a cap of a few corrections above need
+    for cap in (30, out["iters"] + 2):
+        us_async = timed(lambda: P.refine_async(dA, db, K, res, dx, work, max_iter=cap))
+        g = torch.cuda.CUDAGraph()
+        st = torch.cuda.Stream()
+        st.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(st):
+            with torch.cuda.graph(g, stream=st, capture_error_mode="thread_local"):
+                P.refine_async(dA, db, K, res, dx, work, max_iter=cap)
+        torch.cuda.current_stream().wait_stream(st)
+        us_graph = timed(g.replay)
+        r = P.refine_result(res)
+        assert r["status"] == out["status"] and r["iters"] == out["iters"]
+        small[f"max_iter_{cap}"] = {"us_per_solve_async": us_async, "us_per_solve_graph": us_graph}
+        log(f"[bench] refined solve n={n} {WORD_NAME[K]}: bnc_refine {us_sync:.0f} us; max_iter {cap}: "
+            f"bnc_refine_async {us_async:.0f} us, graph replay {us_graph:.0f} us ({out['iters']} corrections)")
+        del g
+    return small
+
+
+def latency_main(args):
+    rows = [small_solve_latency(n) for n in (128, 512)]
+    print(json.dumps({"metric": "small refined-solve latency (us): host-driven, device-driven, graph replay",
+                      "data": "synthetic", "dtype": "f64", "value": rows[0]["us_per_solve"], "unit": "us",
+                      "higher_is_better": False, "rows": rows}), flush=True)
 
 
 def main():
@@ -527,7 +573,8 @@ def main():
     ap.add_argument("--ozaki", type=int, default=-1,
                     help="single mode: also time the split trailing update with this many slices "
                          "(-1 = the default for the factor precision, 0 = plain form only)")
-    ap.add_argument("--mode", choices=["single", "batch", "selector", "sweep", "gemm", "paper"], default="single")
+    ap.add_argument("--mode", choices=["single", "batch", "selector", "sweep", "gemm", "paper", "latency"],
+                    default="single")
     ap.add_argument("--paper-n", type=int, default=2000, help="paper mode: order of the paper's system")
     ap.add_argument("--gemm-n", type=int, default=4096, help="gemm mode: m = n = k")
     ap.add_argument("--count", type=int, default=8192, help="batch mode: number of systems")
@@ -562,6 +609,8 @@ def main():
         return gemm_main(args)
     if args.mode == "paper":
         return paper_main(args)
+    if args.mode == "latency":
+        return latency_main(args)
     if args.mode == "selector":
         if args.count == 8192:
             args.count = 16384
