@@ -41,7 +41,8 @@ FMS_INSTS = {1: 1, 2: 26, 3: 72, 4: 152}
 # profiles/counters_update_randsvd_n4096.md.  Valid for the kernels they were taken on only:
 # (form, factor words, n, slices).
 MEASURED_TRAFFIC = {("ozaki", 3, 4096, 5): 4.270e8, ("plain", 3, 4096, 0): 3.598e8,
-                    ("ozaki", 2, 4096, 5): 3.261e8, ("plain", 2, 4096, 0): 2.467e8}
+                    ("ozaki", 2, 4096, 5): 3.261e8, ("plain", 2, 4096, 0): 2.467e8,
+                    ("ozaki", 2, 4096, 4): 2.847e8}
 # HBM bytes per multi-word GEMM launch at m = n = k = 4096 (bench.py --mode gemm), the same two counter
 # passes and copy scaling: profiles/counters_gemm_n4096.md.  Valid for that kernel and size only.
 MEASURED_GEMM_TRAFFIC = {(2, 4096): 7.508e9, (3, 4096): 2.274e10}
