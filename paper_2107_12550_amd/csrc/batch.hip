@@ -24,6 +24,8 @@ constexpr int BT_MAX = 256;  // most threads per workgroup (= largest order)
 constexpr int BNMAX = 256;   // slot layout in the workspace: orders up to 256
 constexpr int BNB_DEFAULT = 8;  // LU panel width unless tuned (4 or 8)
 constexpr int BRB = 24;     // residual bins per row (816 bits)
+constexpr int BJ = 4;       // trailing-update columns per thread at once
+constexpr int RPF = 4;      // residual: columns of A loaded ahead
 
 struct BatchSlot {
     // per persistent workgroup, reused across the systems it solves
@@ -143,13 +145,20 @@ __device__ __forceinline__ void bsolve(int n, const double *__restrict__ lu, int
                                        double (&y)[K], LDS &S)
 {
     const int t = threadIdx.x;
-    // forward: y_i <- y_i - l_ik y_k, k increasing
+    const int tc = t < n ? t : n - 1;  // in-bounds row for the prefetches
+    // forward: y_i <- y_i - l_ik y_k, k increasing; column k + 1's entry is
+    // loaded a step ahead (unconditionally, from an in-bounds address)
+    double ln[K];
+#pragma unroll
+    for (int w = 0; w < K; ++w)
+        ln[w] = lu[w * ldp + tc];
     for (int k = 0; k < n; ++k) {
         double l[K];
-        if (t > k && t < n) {
+        const int kn = k + 1 < n ? k + 1 : k;
 #pragma unroll
-            for (int w = 0; w < K; ++w)
-                l[w] = lu[w * ldp + (int64_t)k * n + t];
+        for (int w = 0; w < K; ++w) {
+            l[w] = ln[w];
+            ln[w] = lu[w * ldp + (int64_t)kn * n + tc];
         }
         if (t == k) {
 #pragma unroll
@@ -169,13 +178,19 @@ __device__ __forceinline__ void bsolve(int n, const double *__restrict__ lu, int
         }
     }
     __syncthreads();
-    // backward: x_k = y_k * (1/u_kk), then y_i <- y_i - u_ik x_k, k decreasing
+    // backward: x_k = y_k * (1/u_kk), then y_i <- y_i - u_ik x_k, k
+    // decreasing; column k - 1's entry loaded a step ahead
+    double un[K];
+#pragma unroll
+    for (int w = 0; w < K; ++w)
+        un[w] = lu[w * ldp + (int64_t)(n - 1) * n + tc];
     for (int k = n - 1; k >= 0; --k) {
         double u[K];
-        if (t < k) {
+        const int kn = k > 0 ? k - 1 : 0;
 #pragma unroll
-            for (int w = 0; w < K; ++w)
-                u[w] = lu[w * ldp + (int64_t)k * n + t];
+        for (int w = 0; w < K; ++w) {
+            u[w] = un[w];
+            un[w] = lu[w * ldp + (int64_t)kn * n + tc];
         }
         if (t == k) {
             double rk[K], xk[K];
@@ -527,9 +542,58 @@ __global__ void __launch_bounds__(NT)
                     }
             }
             __syncthreads();
-            // A22 <- A22 - L21 U12, each entry in increasing k
+            // A22 <- A22 - L21 U12, each entry in increasing k.  A thread
+            // takes BJ of its columns at once: their multiply-subtract
+            // chains are independent, so they interleave and hide each
+            // other's latency (one chain per thread left the FP64 pipes
+            // idle at one wave per SIMD)
             if (r < m2) {
-                for (int j = q; j < m2; j += G) {
+                int j = q;
+                // the next group's entries are loaded while this group is
+                // updated (unconditional loads from clamped columns)
+                double c[BJ][K];
+                auto load_group = [&](int jg, double (&cc)[BJ][K]) {
+#pragma unroll
+                    for (int bj = 0; bj < BJ; ++bj) {
+                        const int jc = jg + bj * G < m2 ? jg + bj * G : m2 - 1;
+                        const double *cp = lu + (int64_t)(c0 + jc) * n + c0 + r;
+#pragma unroll
+                        for (int w = 0; w < K; ++w)
+                            cc[bj][w] = cp[w * ldp];
+                    }
+                };
+                if (j + (BJ - 1) * G < m2)
+                    load_group(j, c);
+                for (; j + (BJ - 1) * G < m2; j += BJ * G) {
+                    double cn[BJ][K];
+                    load_group(j + BJ * G, cn);
+#pragma unroll
+                    for (int kk = 0; kk < PW; ++kk) {
+                        if (kk < jb) {
+#pragma unroll
+                            for (int bj = 0; bj < BJ; ++bj) {
+                                double u[K], oo[K];
+#pragma unroll
+                                for (int w = 0; w < K; ++w)
+                                    u[w] = S.tile[(w * PW + kk) * NT + j + bj * G];
+                                fms<K>(c[bj], l21[kk], u, oo);
+#pragma unroll
+                                for (int w = 0; w < K; ++w)
+                                    c[bj][w] = oo[w];
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int bj = 0; bj < BJ; ++bj) {
+                        double *cp = lu + (int64_t)(c0 + j + bj * G) * n + c0 + r;
+#pragma unroll
+                        for (int w = 0; w < K; ++w) {
+                            cp[w * ldp] = c[bj][w];
+                            c[bj][w] = cn[bj][w];
+                        }
+                    }
+                }
+                for (; j < m2; j += G) {
                     double c[K];
                     double *cp = lu + (int64_t)(c0 + j) * n + c0 + r;
 #pragma unroll
@@ -636,40 +700,63 @@ __global__ void __launch_bounds__(NT)
                     }
             const double xmax = wg_max<NT>(fabs(xv0), S.red);
             ex = wg_min_i<NT>(ex, S.redi);
-            // exact residual, thread per row
+            // exact residual, thread per row; the wave's lanes deposit into
+            // a common number of bins (the largest row's) so that the bin
+            // loop is uniform and each column's eight terms interleave
             double rr[4] = {0.0, 0.0, 0.0, 0.0};
             int rbad = 0;
+            RowAnchor an{};
+            an.any = false;
             if (t < n) {
                 ExpBounds ebnd;
                 ebnd.a = ea;
                 ebnd.x = ex;
                 ebnd.b = eb;
-                const RowAnchor an = row_anchor<BRB>(rmax_i, xmax, b[t], h, lowest_bit(ebnd));
-                if (an.any) {
-                    double sig[BRB], bins[BRB];
+                an = row_anchor<BRB>(rmax_i, xmax, b[t], h, lowest_bit(ebnd));
+            }
+            const int nbu = wave_max_nb(t < n && an.any ? an.nb : 0);
+            if (t < n && an.any) {
+                double bins[BRB];
 #pragma unroll
-                    for (int qb = 0; qb < BRB; ++qb) {
-                        sig[qb] = qb < an.nb ? 1.5 * pow2(an.e0 - RB_W * qb + 52) : 0.0;
-                        bins[qb] = 0.0;
-                    }
-                    const double lim0 = pow2(an.e0 + 51);
-                    bool bd = false;
-                    for (int j = 0; j < n; ++j) {
-                        const double a = A[(int64_t)j * n + t];
+                for (int qb = 0; qb < BRB; ++qb)
+                    bins[qb] = 0.0;
+                const double sg0 = 1.5 * pow2(an.e0 + 52);  // bin 0's extraction constant
+                const double lim0 = pow2(an.e0 + 51);
+                bool bd = false;
+                // column j's entry of A is loaded RPF columns ahead
+                // (unconditional loads from a clamped index)
+                const double *Arow = A + t;
+                double apf[RPF];
 #pragma unroll
-                        for (int w = 0; w < 4; ++w) {
-                            double lo;
-                            const double hi = two_prod(a, S.xq[w][j], lo);
-                            deposit(-hi, sig, bins, an.nb, lim0, bd);
-                            deposit(-lo, sig, bins, an.nb, lim0, bd);
+                for (int p = 0; p < RPF; ++p)
+                    apf[p] = Arow[(int64_t)(p < n ? p : n - 1) * n];
+                for (int j0 = 0; j0 < n; j0 += RPF) {
+#pragma unroll
+                    for (int p = 0; p < RPF; ++p) {
+                        const int j = j0 + p;
+                        const double a = apf[p];
+                        const int jn = j + RPF < n ? j + RPF : n - 1;
+                        apf[p] = Arow[(int64_t)jn * n];
+                        if (j < n) {
+                            double tt[8];
+#pragma unroll
+                            for (int w = 0; w < 4; ++w) {
+                                double lo;
+                                const double hi = two_prod(a, S.xq[w][j], lo);
+                                tt[2 * w] = -hi;
+                                tt[2 * w + 1] = -lo;
+                            }
+                            deposit_many(tt, sg0, bins, an.nb, nbu, lim0, bd);
                         }
                     }
-#pragma unroll
-                    for (int w = 0; w < 4; ++w)
-                        deposit(b[w * n + t], sig, bins, an.nb, lim0, bd);
-                    bd = bins_to_qd(bins, an.nb, an.e0, rr) || bd;
-                    rbad = bd ? 1 : 0;
                 }
+                double tb[4];
+#pragma unroll
+                for (int w = 0; w < 4; ++w)
+                    tb[w] = b[w * n + t];
+                deposit_many(tb, sg0, bins, an.nb, nbu, lim0, bd);
+                bd = bins_to_qd(bins, an.nb, an.e0, rr) || bd;
+                rbad = bd ? 1 : 0;
             }
             inexact |= wg_or<NT>(rbad, S.redi);
             const double rmax = wg_max<NT>(fabs(rr[0]), S.red);

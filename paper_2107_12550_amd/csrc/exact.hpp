@@ -110,6 +110,64 @@ __device__ __forceinline__ void deposit(double t, const double (&sig)[NBMAX], do
     bad = bad || (t != 0.0);
 }
 
+// Deposit NT terms at once, bin by bin, for bins q < nbu, nbu the same for
+// every lane of the wave (the largest of their rows' bin counts, so the
+// loop has no per-lane branch and the terms' chains interleave): each term
+// gives its digit of bin q (extraction constant sg0 2^(-W q), an exact
+// scaling while the quanta are normal) and keeps the rest; the digits are
+// summed pairwise and added to the bin.  Every partial sum of a bin's
+// digits is exact (below 2^53 of its quanta), so the grouping does not
+// change the bins.  A row's terms have no bits below its own nb bins, so
+// the bins past them receive zero digits; a nonzero digit there, or a term
+// with bits left after nbu bins, marks the row as inexact, as a term with
+// bits left after nb bins does in deposit.
+template <int NBMAX, int NT>
+__device__ __forceinline__ void deposit_many(double (&tt)[NT], double sg0, double (&bins)[NBMAX], int nb, int nbu,
+                                             double lim0, bool &bad)
+{
+    constexpr double STEP = 1.0 / (double)(1ull << RB_W);
+#pragma unroll
+    for (int k = 0; k < NT; ++k)
+        bad = bad || !(fabs(tt[k]) <= lim0);
+    double sg = sg0;
+#pragma unroll
+    for (int q = 0; q < NBMAX; ++q) {
+        if (q < nbu) {
+            double d[NT];
+            bool nz = false;
+#pragma unroll
+            for (int k = 0; k < NT; ++k) {
+                d[k] = (sg + tt[k]) - sg;
+                tt[k] = tt[k] - d[k];
+                nz = nz | (d[k] != 0.0);
+            }
+            bad = bad | (nz & (q >= nb));
+#pragma unroll
+            for (int st = 1; st < NT; st *= 2)
+#pragma unroll
+                for (int k = 0; k + st < NT; k += 2 * st)
+                    d[k] = d[k] + d[k + st];
+            bins[q] = bins[q] + d[0];
+            sg = sg * STEP;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NT; ++k)
+        bad = bad | (tt[k] != 0.0);
+}
+
+// The largest of the wave's bin counts (lanes without a row give 0), as a
+// wave-uniform value.
+__device__ __forceinline__ int wave_max_nb(int nb)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const int o = __shfl_xor(nb, off, 64);
+        nb = o > nb ? o : nb;
+    }
+    return __builtin_amdgcn_readfirstlane(nb);
+}
+
 // ---- exact signed integer in 32-bit limbs (carry-save in int64) ------------
 // Limbs for the integer of NB bins: digits below 2^53 units of their bin, the
 // top bin's unit at bit W (NB - 1), plus carry and sign headroom.
@@ -211,29 +269,34 @@ __device__ __forceinline__ uint64_t big_round(const Big<NB> &M, int &lsb)
 // word fell outside the binary64 normal range.  The integer is kept as its
 // magnitude while a word is rounded off it (negated in place), so one limb
 // array suffices.
-template <int NBMAX, int LW>
-__device__ __forceinline__ bool bins_to_words(const double (&bins)[NBMAX], int nb, int e0, double (&out)[LW])
+// Add the digits of bins[0..cnt) = bins q0.. of a row with nb bins (bin q
+// holds multiples of 2^(e0 - W q)) into the row's integer, whose unit is the
+// last bin's quantum.
+template <int NB, int CNT>
+__device__ __forceinline__ void bins_into_big(Big<NB> &B, const double (&bins)[CNT], int q0, int nb, int e0)
+{
+#pragma unroll
+    for (int c = 0; c < CNT; ++c) {
+        const int q = q0 + c;
+        if (q < nb) {
+            const double dig = ldexp(bins[c], -(e0 - RB_W * q));
+            big_add(B, (int64_t)dig, RB_W * (nb - 1 - q));
+        }
+    }
+}
+
+// Canonical LW-word rounding of the row's integer (unit 2^elow); returns
+// true if a word fell outside the binary64 normal range.
+template <int NB, int LW>
+__device__ __forceinline__ bool big_to_words(Big<NB> &B, int elow, double (&out)[LW])
 {
     bool bad = false;
 #pragma unroll
     for (int w = 0; w < LW; ++w)
         out[w] = 0.0;
-    Big<NBMAX> B;
-#pragma unroll
-    for (int q = 0; q < Big<NBMAX>::L; ++q)
-        B.l[q] = 0;
-    const int elow = e0 - RB_W * (nb - 1);  // exponent of the integer's unit
-#pragma unroll
-    for (int q = 0; q < NBMAX; ++q) {
-        if (q < nb) {
-            // bin q holds multiples of 2^(e0 - W q): integer digit
-            const double dig = ldexp(bins[q], -(e0 - RB_W * q));
-            big_add(B, (int64_t)dig, RB_W * (nb - 1 - q));
-        }
-    }
     for (int w = 0; w < LW; ++w) {
         big_norm(B);
-        const bool neg = B.l[Big<NBMAX>::L - 1] < 0;
+        const bool neg = B.l[Big<NB>::L - 1] < 0;
         if (neg) {
             big_neg(B);
             big_norm(B);
@@ -257,6 +320,17 @@ __device__ __forceinline__ bool bins_to_words(const double (&bins)[NBMAX], int n
             big_neg(B);
     }
     return bad;
+}
+
+template <int NBMAX, int LW>
+__device__ __forceinline__ bool bins_to_words(const double (&bins)[NBMAX], int nb, int e0, double (&out)[LW])
+{
+    Big<NBMAX> B;
+#pragma unroll
+    for (int q = 0; q < Big<NBMAX>::L; ++q)
+        B.l[q] = 0;
+    bins_into_big(B, bins, 0, nb, e0);
+    return big_to_words(B, e0 - RB_W * (nb - 1), out);
 }
 
 template <int NBMAX>
