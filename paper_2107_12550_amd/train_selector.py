@@ -68,13 +68,14 @@ def main():
             for k, v in r.items():
                 if isinstance(v, list):
                     tot[k] = [a + b for a, b in zip(tot[k], v)]
-                elif k not in ("speedup", "fallback_fraction"):
+                elif k not in ("speedup", "speedup_vs_dd", "fallback_fraction"):
                     tot[k] += v
         log(f"[selector] held-out {c0 + m}/{args.test}: baseline {r['baseline_ms']:.1f} ms, "
             f"selector {r['selector_ms']:.1f} ms")
     lc = np.concatenate([a for a, _ in labels])
     lp = np.concatenate([b for _, b in labels])
     tot["speedup"] = tot["baseline_ms"] / tot["selector_ms"]
+    tot["speedup_vs_dd"] = tot["dd_ms"] / tot["selector_ms"]
     tot["fallback_fraction"] = tot["selector_escalations"] / tot["count"]
     tot["under_predicted_fraction"] = float(np.mean(lp < lc))
     tot["heldout_accuracy"] = float(np.mean(lp == lc))
