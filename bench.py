@@ -203,6 +203,15 @@ def batch_main(args):
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99)),
                        "max": float(lat_ms.max())},
         "gflops_eq_lu": work / (ms / 1e3) / 1e9,
+        # the batched kernel does the whole refined solve; the algorithmic
+        # count is the LU's K-word multiply-subtracts alone (n^3/3 per system,
+        # FMS_FLOPS[K] flops each), so the fraction is a lower bound
+        "roofline": {"kernel": f"k_batch<{K},panel,threads> (whole refined solves, one launch per size class)",
+                     "bound": "alu", "flops_per_launch": f"{FMS_FLOPS[K]} * sum(n^3/3) (LU multiply-subtracts only)",
+                     "achieved": work / 2.0 * FMS_FLOPS[K] / (ms / 1e3) / 1e12, "peak": FP64_PEAK_TFLOPS,
+                     "unit": "TFLOP/s",
+                     "frac": work / 2.0 * FMS_FLOPS[K] / (ms / 1e3) / 1e12 / FP64_PEAK_TFLOPS,
+                     "traffic": None},
         "device_time_split": {"factor_frac": float(fac_ms.sum() / lat_ms.sum()), "by_order": split},
         "status_counts": {int(k): int(v) for k, v in zip(*np.unique(res["status"], return_counts=True))},
         "iters_mean": float(res["iters"].mean()),
