@@ -50,6 +50,7 @@ DEFAULT_SLICES = {1: 3, 2: 5, 3: 5, 4: 11}  # split form of the requested factor
 # double-double split forms timed beside it (cond <= 1e15, above): the headline takes the faster
 DD_SLICES = {False: (4, 5), True: (6, 7)}
 WORD_NAME = {1: "FP64", 2: "DD", 3: "TD", 4: "QD"}
+WORDS_ABOVE = 1e15  # batched workload: quad-double-word entries above this condition
 
 
 def log(*a):
@@ -112,7 +113,9 @@ def cpu_baseline(Ap, b, factor, slices, n_small=(1024, 2048), cond=1e10):
 
 def batch_main(args):
     """Batched form: `count` independent randsvd systems, n ~ U{16..256},
-    cond log-uniform in [1e2, 1e30], binary64 entries, triple-double LU +
+    cond log-uniform in [1e2, 1e30], binary64 entries up to cond 1e15 and
+    quad-double-word entries above (a binary64 copy cannot hold a larger
+    condition), triple-double LU +
     quad-double refinement to ~1e-45 (forward test 2^-150), all in one
     persistent launch replayed from a captured HIP graph."""
     import numpy as np
@@ -122,7 +125,8 @@ def batch_main(args):
     t0 = time.perf_counter()
     As, bs, exact, conds = synth.batch(args.count, 16, 256, 2.0, 30.0, config=3,
                                        workers=min(16, os.cpu_count() or 1),
-                                       progress=lambda d: log(f"[bench] generated {d}/{args.count}"))
+                                       progress=lambda d: log(f"[bench] generated {d}/{args.count}"),
+                                       words_above=WORDS_ABOVE)
     log(f"[bench] generated in {time.perf_counter() - t0:.1f} s")
     import torch
 
@@ -179,6 +183,7 @@ def batch_main(args):
     sample = list(range(0, args.count, max(1, args.count // 256)))
     mre = max(max_rel_err_vs_ones(S.xs[i].cpu().numpy()) for i in sample if exact[i])
     ns = np.array([a.shape[-1] for a in As], dtype=np.float64)
+    nwords = int(sum(a.shape[0] == 4 for a in As))
     work = float(np.sum(2.0 * ns ** 3 / 3.0))
     line = {
         "metric": "refined solves/sec (batched)",
@@ -193,8 +198,9 @@ def batch_main(args):
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"{args.count} randsvd systems n~U[16,256] cond log-uniform [1e2,1e30] binary64 "
-                               f"entries; {WORD_NAME[K]} LU + QD refinement to 1e-45, one graph launch",
+        "config": {"workload": f"{args.count} randsvd systems n~U[16,256] cond log-uniform [1e2,1e30], binary64 "
+                               f"entries up to cond 1e15, quad-double words above ({nwords} systems); "
+                               f"{WORD_NAME[K]} LU + QD refinement to 1e-45, one graph launch",
                    "count": args.count, "factor": WORD_NAME[K], "ctol": ctol, "slots": S.slots,
                    "tuning": None if plan is None else [(c["n_lo"], c["n_hi"], c["panel"], c["threads"])
                                                         for c in plan["classes"]]},

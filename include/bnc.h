@@ -61,7 +61,8 @@ extern "C" {
 #define BNC_MAX_ITER 1  /* max_iter corrections applied, no test passed */
 #define BNC_SINGULAR 2  /* exactly zero pivot met: no solve was attempted */
 #define BNC_NONFINITE 3 /* NaN or Inf in A or b: nothing was factorised */
-#define BNC_BAD_SIZE 4  /* batched solve: order outside 1..256 */
+#define BNC_BAD_SIZE 4  /* batched solve: order outside 1..threads (at most
+                           512) or words of A not 1 or 4 */
 #define BNC_STAGNATED 5 /* corrections stopped shrinking (stagnation_ratio)
                            and no escalation was left */
 #define BNC_TIMED_OUT 6 /* bnc_refine_async: a bounded wait between
@@ -240,8 +241,8 @@ typedef struct bnc_refine_opts {
                              Batched solves report BNC_STAGNATED (they take
                              escalate = 0). */
     int32_t batch_panel;  /* batched solves: LU panel width 4 or 8 (0 = 8) */
-    int32_t batch_threads; /* batched solves: threads per workgroup, 64, 128
-                             or 256 (0 = 256); systems of order above it get
+    int32_t batch_threads; /* batched solves: threads per workgroup, 64, 128,
+                             256 or 512 (0 = 256); systems of order above it get
                              BNC_BAD_SIZE.  Both are tuning knobs that leave
                              every result unchanged; bnc_refine ignores them. */
     int32_t long_words;   /* words of the long precision (x, b and the
@@ -344,9 +345,10 @@ typedef struct bnc_batch_result {
                                  when none was made) */
 } bnc_batch_result;
 
-/* Workspace bytes of bnc_refine_batched for K = factor_words and `slots`
- * persistent workgroups (0 = the default) (host). */
-size_t bnc_refine_batched_workspace_size(int32_t factor_words, int32_t slots);
+/* Workspace bytes of bnc_refine_batched for K = factor_words, `slots`
+ * persistent workgroups (0 = the default) of `threads` threads (0 = 256)
+ * (host; 0 for invalid arguments). */
+size_t bnc_refine_batched_workspace_size(int32_t factor_words, int32_t slots, int32_t threads);
 
 /* The default number of persistent workgroups for K = factor_words, LU
  * panel width `panel` and `threads` per workgroup (0 = defaults) on the
@@ -357,25 +359,31 @@ int32_t bnc_refine_batched_default_slots(int32_t factor_words, int32_t panel, in
 
 /*
  * Batched mixed-precision iterative refinement: bnc_refine (Kouya 2021,
- * Sec. 2, Listing 1) on `count` independent systems of order 1..256 in one
+ * Sec. 2, Listing 1) on `count` independent systems of order 1..512 in one
  * persistent launch.  Each system's x, status and corrections equal those of
  * bnc_refine on that system alone, bit for bit.
  *   count      number of systems
  *   n          device int64[count]: orders
- *   A, b, x    device arrays of device pointers: A[s] binary64 n x n
- *              column-major (lda = n); b[s], x[s] 4-plane vectors (ldv = n)
+ *   a_words    device int32[count]: words per entry of A[s], 1 (binary64)
+ *              or 4 (quad-double words, for matrices whose condition a
+ *              binary64 copy cannot hold); NULL: all 1
+ *   A, b, x    device arrays of device pointers: A[s] a_words[s] planes of
+ *              n x n, column-major (lda = n, plane stride n*n); b[s], x[s]
+ *              4-plane vectors (ldv = n)
  *   order      device int32[count] giving the order systems are taken in
  *              (NULL: 0..count-1); largest first balances the load
- *   work       >= bnc_refine_batched_workspace_size(K, slots) bytes
- *   opts       host options (as bnc_refine)
+ *   work       >= bnc_refine_batched_workspace_size(K, slots, threads) bytes
+ *   opts       host options (as bnc_refine); opts->batch_threads bounds the
+ *              orders one launch takes (0 = 256; 512 for orders above 256)
  *   slots      persistent workgroups (0 = default)
  *   results    device bnc_batch_result[count]
- * Asynchronous on stream.  A system of order outside 1..256 (1..threads)
- * gets BNC_BAD_SIZE.
+ * Asynchronous on stream.  A system of order outside 1..threads, or with a
+ * word count other than 1 or 4, gets BNC_BAD_SIZE.
  */
-int bnc_refine_batched(int64_t count, const int64_t *n, const double *const *A, const double *const *b,
-                       double *const *x, const int32_t *order, void *work, size_t work_bytes,
-                       const bnc_refine_opts *opts, int32_t slots, bnc_batch_result *results, void *stream);
+int bnc_refine_batched(int64_t count, const int64_t *n, const int32_t *a_words, const double *const *A,
+                       const double *const *b, double *const *x, const int32_t *order, void *work,
+                       size_t work_bytes, const bnc_refine_opts *opts, int32_t slots, bnc_batch_result *results,
+                       void *stream);
 
 /*
  * Same launch captured once into a HIP graph and replayed: when *graph_exec
@@ -384,10 +392,10 @@ int bnc_refine_batched(int64_t count, const int64_t *n, const double *const *A, 
  * calls with that handle only launch it (the arguments are those captured).
  * Free the handle with bnc_graph_destroy.
  */
-int bnc_refine_batched_graph(int64_t count, const int64_t *n, const double *const *A, const double *const *b,
-                             double *const *x, const int32_t *order, void *work, size_t work_bytes,
-                             const bnc_refine_opts *opts, int32_t slots, bnc_batch_result *results, void *stream,
-                             void **graph_exec);
+int bnc_refine_batched_graph(int64_t count, const int64_t *n, const int32_t *a_words, const double *const *A,
+                             const double *const *b, double *const *x, const int32_t *order, void *work,
+                             size_t work_bytes, const bnc_refine_opts *opts, int32_t slots,
+                             bnc_batch_result *results, void *stream, void **graph_exec);
 int bnc_graph_destroy(void *graph_exec);
 
 /* Tick rate of the device wall clock used by bnc_batch_result, in kHz. */

@@ -108,15 +108,15 @@ def _load() -> ctypes.CDLL:
     L.bnc_refine_async.argtypes = [I64, I32, VP, I64, I64, VP, I64, VP, I64, VP, ctypes.c_size_t,
                                    ctypes.POINTER(RefineOpts), VP, VP]
     L.bnc_refine_async.restype = ctypes.c_int
-    L.bnc_refine_batched_workspace_size.argtypes = [I32, I32]
+    L.bnc_refine_batched_workspace_size.argtypes = [I32, I32, I32]
     L.bnc_refine_batched_workspace_size.restype = ctypes.c_size_t
     L.bnc_refine_batched_default_slots.argtypes = [I32, I32, I32]
     L.bnc_refine_batched_default_slots.restype = I32
-    L.bnc_refine_batched.argtypes = [I64, VP, VP, VP, VP, VP, VP, ctypes.c_size_t, ctypes.POINTER(RefineOpts), I32,
-                                     VP, VP]
+    L.bnc_refine_batched.argtypes = [I64, VP, VP, VP, VP, VP, VP, VP, ctypes.c_size_t, ctypes.POINTER(RefineOpts),
+                                     I32, VP, VP]
     L.bnc_refine_batched.restype = ctypes.c_int
-    L.bnc_refine_batched_graph.argtypes = [I64, VP, VP, VP, VP, VP, VP, ctypes.c_size_t, ctypes.POINTER(RefineOpts),
-                                           I32, VP, VP, ctypes.POINTER(ctypes.c_void_p)]
+    L.bnc_refine_batched_graph.argtypes = [I64, VP, VP, VP, VP, VP, VP, VP, ctypes.c_size_t,
+                                           ctypes.POINTER(RefineOpts), I32, VP, VP, ctypes.POINTER(ctypes.c_void_p)]
     L.bnc_refine_batched_graph.restype = ctypes.c_int
     L.bnc_graph_destroy.argtypes = [VP]
     L.bnc_wall_clock_khz.restype = ctypes.c_int64
@@ -315,9 +315,11 @@ def refine_result_bytes() -> int:
 
 class BatchSolver:
     """Batched refined solves (bnc_refine_batched) over a fixed set of
-    systems: A_s (1, n, n) binary64 and b_s (4, n) CUDA tensors.  Device
-    pointer arrays, the largest-first order, outputs and the workspace are
-    set up once; run() launches (optionally through a captured HIP graph)."""
+    systems: A_s (aw, n, n) planes (aw = 1 binary64 or 4 quad-double words)
+    and b_s (4, n) CUDA tensors.  Device pointer arrays, the largest-first
+    order, outputs and the workspace are set up once; run() launches
+    (optionally through a captured HIP graph).  threads = 0 takes 256, or
+    512 when some order is above 256."""
 
     def __init__(self, As, bs, K: int, max_iter: int = 30, rtol: float = 0.0, atol: float = 0.0,
                  ctol: float = 2.0 ** -208, slots: int = 0, order=None, stagnation_ratio: float = 0.0,
@@ -329,6 +331,10 @@ class BatchSolver:
         self.ns = [int(a.shape[-1]) for a in As]
         self.xs = [torch.empty((4, n), dtype=torch.float64, device=dev) for n in self.ns]
         self.n_dev = torch.tensor(self.ns, dtype=torch.int64, device=dev)
+        self.aw_dev = torch.tensor([int(a.shape[0]) if a.dim() == 3 else 1 for a in self.As], dtype=torch.int32,
+                                   device=dev)
+        if threads == 0 and self.ns and max(self.ns) > 256:
+            threads = 512
         self.A_dev = torch.tensor([a.data_ptr() for a in self.As], dtype=torch.int64, device=dev)
         self.b_dev = torch.tensor([b.data_ptr() for b in self.bs], dtype=torch.int64, device=dev)
         self.x_dev = torch.tensor([x.data_ptr() for x in self.xs], dtype=torch.int64, device=dev)
@@ -341,7 +347,7 @@ class BatchSolver:
             if slots <= 0:
                 raise BncError(f"refine_batched_default_slots: {_lib.bnc_last_error().decode()}")
         self.slots = slots
-        need = int(_lib.bnc_refine_batched_workspace_size(K, slots))
+        need = int(_lib.bnc_refine_batched_workspace_size(K, slots, threads))
         self.work = torch.empty(need, dtype=torch.uint8, device=dev)
         self.opts = RefineOpts(K, max_iter, rtol, atol, ctol, 0, 0, stagnation_ratio, panel, threads, 0, 0, None,
                                None)
@@ -350,7 +356,8 @@ class BatchSolver:
 
     def _args(self):
         P = ctypes.c_void_p
-        return (self.count, P(self.n_dev.data_ptr()), P(self.A_dev.data_ptr()), P(self.b_dev.data_ptr()),
+        return (self.count, P(self.n_dev.data_ptr()), P(self.aw_dev.data_ptr()), P(self.A_dev.data_ptr()),
+                P(self.b_dev.data_ptr()),
                 P(self.x_dev.data_ptr()), P(self.order.data_ptr()), P(self.work.data_ptr()), self.work.numel(),
                 ctypes.byref(self.opts), self.slots, P(self.res.data_ptr()))
 

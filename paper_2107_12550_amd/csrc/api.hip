@@ -28,10 +28,10 @@ int refine_run(int64_t n, int aw, const double *A, int64_t lda, int64_t ldpa, co
                int64_t ldpx, void *work, const bnc_refine_opts *o, bnc_refine_result *res, hipStream_t s);
 size_t getrs_workspace_bytes(int K, int64_t n);
 template <int K>
-int batch_run(int64_t count, const int64_t *n, const double *const *A, const double *const *b, double *const *x,
-              const int32_t *order, void *work, int slots, const bnc_refine_opts *o, bnc_batch_result *res,
-              hipStream_t s);
-size_t batch_workspace_bytes(int K, int slots);
+int batch_run(int64_t count, const int64_t *n, const int32_t *aw, const double *const *A, const double *const *b,
+              double *const *x, const int32_t *order, void *work, int slots, const bnc_refine_opts *o,
+              bnc_batch_result *res, hipStream_t s);
+size_t batch_workspace_bytes(int K, int slots, int threads);
 int batch_default_slots(int K, int pw, int nt);
 bool batch_panel_ok(int pw);
 bool batch_threads_ok(int nt);
@@ -502,11 +502,12 @@ int bnc_refine_async(int64_t n, int32_t a_words, const double *A, int64_t lda, i
     }
 }
 
-size_t bnc_refine_batched_workspace_size(int32_t factor_words, int32_t slots)
+size_t bnc_refine_batched_workspace_size(int32_t factor_words, int32_t slots, int32_t threads)
 {
-    if (factor_words < 1 || factor_words > 4 || slots < 0)
+    if (factor_words < 1 || factor_words > 4 || slots < 0 || !batch_threads_ok(threads))
         return 0;
-    return batch_workspace_bytes(factor_words, slots ? slots : batch_default_slots(factor_words, 0, 0));
+    return batch_workspace_bytes(factor_words, slots ? slots : batch_default_slots(factor_words, 0, threads),
+                                 threads);
 }
 
 int32_t bnc_refine_batched_default_slots(int32_t factor_words, int32_t panel, int32_t threads)
@@ -516,64 +517,66 @@ int32_t bnc_refine_batched_default_slots(int32_t factor_words, int32_t panel, in
     if (!batch_panel_ok(panel))
         return fail_arg(-2, "refine_batched_default_slots: panel not 0, 4 or 8");
     if (!batch_threads_ok(threads))
-        return fail_arg(-3, "refine_batched_default_slots: threads not 0, 64, 128 or 256");
+        return fail_arg(-3, "refine_batched_default_slots: threads not 0, 64, 128, 256 or 512");
     return batch_default_slots(factor_words, panel, threads);
 }
 
-int bnc_refine_batched(int64_t count, const int64_t *n, const double *const *A, const double *const *b,
-                       double *const *x, const int32_t *order, void *work, size_t work_bytes,
-                       const bnc_refine_opts *opts, int32_t slots, bnc_batch_result *results, void *stream)
+int bnc_refine_batched(int64_t count, const int64_t *n, const int32_t *a_words, const double *const *A,
+                       const double *const *b, double *const *x, const int32_t *order, void *work,
+                       size_t work_bytes, const bnc_refine_opts *opts, int32_t slots, bnc_batch_result *results,
+                       void *stream)
 {
     if (count < 0)
         return fail_arg(-1, "refine_batched: count < 0");
     if (count > 0 && !n)
         return fail_arg(-2, "refine_batched: n is NULL");
     if (count > 0 && !A)
-        return fail_arg(-3, "refine_batched: A is NULL");
+        return fail_arg(-4, "refine_batched: A is NULL");
     if (count > 0 && !b)
-        return fail_arg(-4, "refine_batched: b is NULL");
+        return fail_arg(-5, "refine_batched: b is NULL");
     if (count > 0 && !x)
-        return fail_arg(-5, "refine_batched: x is NULL");
+        return fail_arg(-6, "refine_batched: x is NULL");
     if (!work)
-        return fail_arg(-7, "refine_batched: work is NULL");
+        return fail_arg(-8, "refine_batched: work is NULL");
     if (!opts || opts->factor_words < 1 || opts->factor_words > 4 || opts->max_iter < 0 || !(opts->rtol >= 0) ||
         opts->ozaki_slices != 0 || opts->escalate != 0 || !(opts->stagnation_ratio >= 0) ||
         (opts->long_words != 0 && opts->long_words != 4) ||
         !batch_panel_ok(opts->batch_panel) || !batch_threads_ok(opts->batch_threads) ||
         !(opts->atol >= 0) || !(opts->ctol >= 0))
-        return fail_arg(-9, "refine_batched: invalid options");
+        return fail_arg(-10, "refine_batched: invalid options");
     if (slots < 0)
-        return fail_arg(-10, "refine_batched: slots < 0");
+        return fail_arg(-11, "refine_batched: slots < 0");
     if (count > 0 && !results)
-        return fail_arg(-11, "refine_batched: results is NULL");
+        return fail_arg(-12, "refine_batched: results is NULL");
     const int sl = slots ? slots : batch_default_slots(opts->factor_words, opts->batch_panel, opts->batch_threads);
-    if (work_bytes < batch_workspace_bytes(opts->factor_words, sl))
-        return fail_arg(-8, "refine_batched: workspace too small");
+    if (work_bytes < batch_workspace_bytes(opts->factor_words, sl, opts->batch_threads))
+        return fail_arg(-9, "refine_batched: workspace too small");
     switch (opts->factor_words) {
     case 1:
-        return batch_run<1>(count, n, A, b, x, order, work, sl, opts, results, S(stream));
+        return batch_run<1>(count, n, a_words, A, b, x, order, work, sl, opts, results, S(stream));
     case 2:
-        return batch_run<2>(count, n, A, b, x, order, work, sl, opts, results, S(stream));
+        return batch_run<2>(count, n, a_words, A, b, x, order, work, sl, opts, results, S(stream));
     case 3:
-        return batch_run<3>(count, n, A, b, x, order, work, sl, opts, results, S(stream));
+        return batch_run<3>(count, n, a_words, A, b, x, order, work, sl, opts, results, S(stream));
     default:
-        return batch_run<4>(count, n, A, b, x, order, work, sl, opts, results, S(stream));
+        return batch_run<4>(count, n, a_words, A, b, x, order, work, sl, opts, results, S(stream));
     }
 }
 
-int bnc_refine_batched_graph(int64_t count, const int64_t *n, const double *const *A, const double *const *b,
-                             double *const *x, const int32_t *order, void *work, size_t work_bytes,
-                             const bnc_refine_opts *opts, int32_t slots, bnc_batch_result *results, void *stream,
-                             void **graph_exec)
+int bnc_refine_batched_graph(int64_t count, const int64_t *n, const int32_t *a_words, const double *const *A,
+                             const double *const *b, double *const *x, const int32_t *order, void *work,
+                             size_t work_bytes, const bnc_refine_opts *opts, int32_t slots,
+                             bnc_batch_result *results, void *stream, void **graph_exec)
 {
     if (!graph_exec)
-        return fail_arg(-13, "refine_batched_graph: graph_exec is NULL");
+        return fail_arg(-14, "refine_batched_graph: graph_exec is NULL");
     hipStream_t s = S(stream);
     if (!*graph_exec) {
         if (!s)
-            return fail_arg(-12, "refine_batched_graph: capture needs a non-null stream");
+            return fail_arg(-13, "refine_batched_graph: capture needs a non-null stream");
         BNC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        const int rc = bnc_refine_batched(count, n, A, b, x, order, work, work_bytes, opts, slots, results, stream);
+        const int rc =
+            bnc_refine_batched(count, n, a_words, A, b, x, order, work, work_bytes, opts, slots, results, stream);
         hipGraph_t g = nullptr;
         const hipError_t e = hipStreamEndCapture(s, &g);
         if (rc)

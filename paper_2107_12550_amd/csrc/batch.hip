@@ -1,11 +1,13 @@
 // Batched refined solves: Listing 1 of Kouya 2021 (Sec. 2) applied to many
-// independent systems of order n <= 256 in one persistent launch.
+// independent systems of order n <= 512 in one persistent launch.
 //
-// Persistent workgroups (256 threads) take systems from an atomic queue in
+// Persistent workgroups (64..512 threads, one per row of the largest system
+// they take) take systems from an atomic queue in
 // the order the caller gives (largest first balances the load) and run the
 // whole path for one system at a time, every step in the same operation
 // order as the single-system solver, so each result equals it bit for bit:
-//   stage A to K words; blocked right-looking LU with 8-column panels held
+//   stage A (binary64 or quad-double words per entry, system by system)
+//   to K words; blocked right-looking LU with 8-column panels held
 //   in LDS (pivot search by wave shuffles, whole-row swaps, reciprocal and
 //   scaling, rank-1 panel updates), U12 by forward substitution, trailing
 //   update with each thread's L21 row in registers and U12 in LDS; diagonal
@@ -20,18 +22,21 @@
 
 namespace bnc {
 
-constexpr int BT_MAX = 256;  // most threads per workgroup (= largest order)
-constexpr int BNMAX = 256;   // slot layout in the workspace: orders up to 256
+constexpr int BT_MAX = 512;  // most threads per workgroup (= largest order)
+constexpr int BT_DEFAULT = 256;  // threads per workgroup unless chosen
+constexpr size_t BLDS_MAX = 160 * 1024;  // LDS of one compute unit
 constexpr int BNB_DEFAULT = 8;  // LU panel width unless tuned (4 or 8)
 constexpr int BRB = 24;     // residual bins per row (816 bits)
 constexpr int BJ = 4;       // trailing-update columns per thread at once
 constexpr int RPF = 4;      // residual: columns of A loaded ahead
 
-struct BatchSlot {
-    // per persistent workgroup, reused across the systems it solves
-    double *lu;   // K planes of BNMAX*BNMAX (lda = n)
-    double *rd;   // K planes of BNMAX: 1/u_kk
-};
+// Per persistent workgroup of NT threads, reused across the systems it
+// solves: the LU (K planes of NT*NT, lda = n), then 1/u_kk (K planes of NT).
+template <int K, int NT>
+constexpr size_t slot_doubles()
+{
+    return (size_t)K * NT * NT + (size_t)K * NT;
+}
 
 template <int K, int PW, int NT>
 struct BatchLds {
@@ -196,7 +201,7 @@ __device__ __forceinline__ void bsolve(int n, const double *__restrict__ lu, int
             double rk[K], xk[K];
 #pragma unroll
             for (int w = 0; w < K; ++w)
-                rk[w] = rd[w * BNMAX + k];
+                rk[w] = rd[w * NT + k];
             mul<K>(y, rk, xk);
 #pragma unroll
             for (int w = 0; w < K; ++w) {
@@ -239,11 +244,59 @@ __device__ __forceinline__ void bgather(int n, double (&v)[K], LDS &S)
     __syncthreads();
 }
 
+// ---- exact residual ------------------------------------------------------------
+
+// Deposits of -A(t, :) x into row t's bins: each product of a word of
+// A(t, j) and a word of x_j as its two exact halves, column by column (the
+// sum is exact, so the order of the deposits does not matter).  A's words
+// are loaded PF columns ahead, unconditionally from clamped columns.
+template <int AW, int NT>
+__device__ __forceinline__ void resid_row_terms(int n, const double *__restrict__ Arow, int64_t nn2,
+                                                const double (&xq)[4][NT], double sg0, double (&bins)[BRB], int nb,
+                                                int nbu, double lim0, bool &bd)
+{
+    constexpr int PF = AW == 1 ? RPF : 2;
+    double apf[PF][AW];
+#pragma unroll
+    for (int p = 0; p < PF; ++p)
+#pragma unroll
+        for (int u = 0; u < AW; ++u)
+            apf[p][u] = Arow[u * nn2 + (int64_t)(p < n ? p : n - 1) * n];
+    for (int j0 = 0; j0 < n; j0 += PF) {
+#pragma unroll
+        for (int p = 0; p < PF; ++p) {
+            const int j = j0 + p;
+            double a[AW];
+            const int jn = j + PF < n ? j + PF : n - 1;
+#pragma unroll
+            for (int u = 0; u < AW; ++u) {
+                a[u] = apf[p][u];
+                apf[p][u] = Arow[u * nn2 + (int64_t)jn * n];
+            }
+            if (j < n) {
+#pragma unroll
+                for (int u = 0; u < AW; ++u) {
+                    double tt[8];
+#pragma unroll
+                    for (int w = 0; w < 4; ++w) {
+                        double lo;
+                        const double hi = two_prod(a[u], xq[w][j], lo);
+                        tt[2 * w] = -hi;
+                        tt[2 * w + 1] = -lo;
+                    }
+                    deposit_many(tt, sg0, bins, nb, nbu, lim0, bd);
+                }
+            }
+        }
+    }
+}
+
 // ---- the batched solver ---------------------------------------------------------
 
 template <int K, int PW, int NT>
 __global__ void __launch_bounds__(NT)
-    k_batch(int64_t count, const int64_t *__restrict__ nn, const double *const *__restrict__ As,
+    k_batch(int64_t count, const int64_t *__restrict__ nn, const int32_t *__restrict__ aws,
+            const double *const *__restrict__ As,
             const double *const *__restrict__ bs, double *const *__restrict__ xs, const int32_t *__restrict__ order,
             unsigned *__restrict__ queue, double *__restrict__ work, bnc_refine_opts o,
             bnc_batch_result *__restrict__ res)
@@ -252,9 +305,9 @@ __global__ void __launch_bounds__(NT)
     BatchLds<K, PW, NT> &S = *reinterpret_cast<BatchLds<K, PW, NT> *>(smem_raw);
     const int t = threadIdx.x;
     const int lane = t & 63, wave = t >> 6;
-    const int64_t ldp = (int64_t)BNMAX * BNMAX;
-    double *lu = work + (size_t)blockIdx.x * ((size_t)K * BNMAX * BNMAX + (size_t)K * BNMAX);
-    double *rd = lu + (size_t)K * BNMAX * BNMAX;
+    const int64_t ldp = (int64_t)NT * NT;
+    double *lu = work + (size_t)blockIdx.x * slot_doubles<K, NT>();
+    double *rd = lu + (size_t)K * NT * NT;
 
     for (;;) {
         if (t == 0)
@@ -267,9 +320,10 @@ __global__ void __launch_bounds__(NT)
         const int64_t sys = order ? order[qi] : qi;
         const uint64_t t0 = wall_clock64();
         const int64_t n64 = nn[sys];
+        const int aw = aws ? aws[sys] : 1;  // words per entry of A
         bnc_batch_result out{};
         double *x = xs[sys];
-        if (n64 < 1 || n64 > NT) {
+        if (n64 < 1 || n64 > NT || (aw != 1 && aw != 4)) {
             if (t == 0) {
                 out.status = BNC_BAD_SIZE;
                 out.t_start = t0;
@@ -283,11 +337,14 @@ __global__ void __launch_bounds__(NT)
         const double *A = As[sys];
         const double *b = bs[sys];
 
-        // ---- checks, row maxima, exponent bounds, ||A||_F
+        const int64_t nn2 = (int64_t)n * n;  // plane stride of A's words
+
+        // ---- checks, row maxima (leading words), exponent bounds (every
+        // word), ||A||_F (leading words)
         int bad = 0;
         double rmax_i = 0.0;
         int ea = 2000, eb = 2000;
-        for (int64_t e = t; e < (int64_t)n * n; e += NT) {
+        for (int64_t e = t; e < (int64_t)aw * nn2; e += NT) {
             const double v = A[e];
             bad |= !isfinite(v);
             if (v != 0.0) {
@@ -337,12 +394,25 @@ __global__ void __launch_bounds__(NT)
             anorm = am == 0.0 ? 0.0 : sqrt(ss) * pow2(norm_exp(am) + 1);
         }
 
-        // ---- K-word copy of A
-        for (int64_t e = t; e < (int64_t)n * n; e += NT) {
-            lu[e] = A[e];
+        // ---- K-word copy of A (quad-double words renormalised to K)
+        if (aw == 1) {
+            for (int64_t e = t; e < nn2; e += NT) {
+                lu[e] = A[e];
 #pragma unroll
-            for (int w = 1; w < K; ++w)
-                lu[w * ldp + e] = 0.0;
+                for (int w = 1; w < K; ++w)
+                    lu[w * ldp + e] = 0.0;
+            }
+        } else {
+            for (int64_t e = t; e < nn2; e += NT) {
+                double v[4], o[K];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    v[u] = A[u * nn2 + e];
+                renorm<K, 4>(v, o);
+#pragma unroll
+                for (int w = 0; w < K; ++w)
+                    lu[w * ldp + e] = o[w];
+            }
         }
         __syncthreads();
 
@@ -643,7 +713,7 @@ __global__ void __launch_bounds__(NT)
             recip<K>(d, rc);
 #pragma unroll
             for (int w = 0; w < K; ++w)
-                rd[w * BNMAX + t] = rc[w];
+                rd[w * NT + t] = rc[w];
         }
         if (t == 0) {
             for (int i = 0; i < n; ++i)
@@ -723,33 +793,10 @@ __global__ void __launch_bounds__(NT)
                 const double sg0 = 1.5 * pow2(an.e0 + 52);  // bin 0's extraction constant
                 const double lim0 = pow2(an.e0 + 51);
                 bool bd = false;
-                // column j's entry of A is loaded RPF columns ahead
-                // (unconditional loads from a clamped index)
-                const double *Arow = A + t;
-                double apf[RPF];
-#pragma unroll
-                for (int p = 0; p < RPF; ++p)
-                    apf[p] = Arow[(int64_t)(p < n ? p : n - 1) * n];
-                for (int j0 = 0; j0 < n; j0 += RPF) {
-#pragma unroll
-                    for (int p = 0; p < RPF; ++p) {
-                        const int j = j0 + p;
-                        const double a = apf[p];
-                        const int jn = j + RPF < n ? j + RPF : n - 1;
-                        apf[p] = Arow[(int64_t)jn * n];
-                        if (j < n) {
-                            double tt[8];
-#pragma unroll
-                            for (int w = 0; w < 4; ++w) {
-                                double lo;
-                                const double hi = two_prod(a, S.xq[w][j], lo);
-                                tt[2 * w] = -hi;
-                                tt[2 * w + 1] = -lo;
-                            }
-                            deposit_many(tt, sg0, bins, an.nb, nbu, lim0, bd);
-                        }
-                    }
-                }
+                if (aw == 1)
+                    resid_row_terms<1>(n, A + t, nn2, S.xq, sg0, bins, an.nb, nbu, lim0, bd);
+                else
+                    resid_row_terms<4>(n, A + t, nn2, S.xq, sg0, bins, an.nb, nbu, lim0, bd);
                 double tb[4];
 #pragma unroll
                 for (int w = 0; w < 4; ++w)
@@ -825,9 +872,11 @@ __global__ void k_queue_reset(unsigned *q)
         *q = 0;
 }
 
-size_t batch_workspace_bytes(int K, int slots)
+// the queue counter (256 bytes), then one slot per workgroup
+size_t batch_workspace_bytes(int K, int slots, int threads)
 {
-    return (size_t)slots * ((size_t)K * BNMAX * BNMAX + (size_t)K * BNMAX) * sizeof(double) + 256;
+    const size_t nt = threads ? (size_t)threads : (size_t)BT_DEFAULT;
+    return (size_t)slots * ((size_t)K * nt * nt + (size_t)K * nt) * sizeof(double) + 256;
 }
 
 // persistent workgroups per compute unit: as many as registers and LDS allow
@@ -842,18 +891,43 @@ static int occupancy_per_cu()
     return per;
 }
 
+// The panel width actually launched: 8-wide panels whose LDS would not fit
+// a compute unit (four words at 512 threads) fall back to 4 (the width
+// changes no result).
+template <int K, int NT>
+constexpr int panel_fit(int pw)
+{
+    return (pw == 4 || sizeof(BatchLds<K, 8, NT>) > BLDS_MAX) ? 4 : 8;
+}
+
+template <int K, int NT>
+static int occupancy_pw(int pw)
+{
+    static_assert(sizeof(BatchLds<K, 4, NT>) <= BLDS_MAX, "batched LDS exceeds a compute unit");
+    if constexpr (sizeof(BatchLds<K, 8, NT>) <= BLDS_MAX) {
+        if (panel_fit<K, NT>(pw) == 8)
+            return occupancy_per_cu<K, 8, NT>();
+    }
+    return occupancy_per_cu<K, 4, NT>();
+}
+
 template <int K>
 static int occupancy_k(int pw, int nt)
 {
-    if (nt == 64)
-        return pw == 4 ? occupancy_per_cu<K, 4, 64>() : occupancy_per_cu<K, 8, 64>();
-    if (nt == 128)
-        return pw == 4 ? occupancy_per_cu<K, 4, 128>() : occupancy_per_cu<K, 8, 128>();
-    return pw == 4 ? occupancy_per_cu<K, 4, 256>() : occupancy_per_cu<K, 8, 256>();
+    switch (nt) {
+    case 64:
+        return occupancy_pw<K, 64>(pw);
+    case 128:
+        return occupancy_pw<K, 128>(pw);
+    case 256:
+        return occupancy_pw<K, 256>(pw);
+    default:
+        return occupancy_pw<K, 512>(pw);
+    }
 }
 
 bool batch_panel_ok(int pw) { return pw == 0 || pw == 4 || pw == 8; }
-bool batch_threads_ok(int nt) { return nt == 0 || nt == 64 || nt == 128 || nt == 256; }
+bool batch_threads_ok(int nt) { return nt == 0 || nt == 64 || nt == 128 || nt == 256 || nt == 512; }
 
 int batch_default_slots(int K, int pw, int nt)
 {
@@ -864,41 +938,43 @@ int batch_default_slots(int K, int pw, int nt)
     if (pw == 0)
         pw = BNB_DEFAULT;
     if (nt == 0)
-        nt = BT_MAX;
+        nt = BT_DEFAULT;
     const int per = K == 1 ? occupancy_k<1>(pw, nt) : K == 2 ? occupancy_k<2>(pw, nt)
                                                   : K == 3 ? occupancy_k<3>(pw, nt) : occupancy_k<4>(pw, nt);
     return per * ncu;
 }
 
 template <int K, int PW, int NT>
-static int batch_launch(int64_t count, const int64_t *n, const double *const *A, const double *const *b,
-                        double *const *x, const int32_t *order, unsigned *queue, double *ws, int slots,
-                        const bnc_refine_opts *o, bnc_batch_result *res, hipStream_t s)
+static int batch_launch(int64_t count, const int64_t *n, const int32_t *aw, const double *const *A,
+                        const double *const *b, double *const *x, const int32_t *order, unsigned *queue, double *ws,
+                        int slots, const bnc_refine_opts *o, bnc_batch_result *res, hipStream_t s)
 {
     const size_t lds = sizeof(BatchLds<K, PW, NT>);
     if (hipFuncSetAttribute((const void *)k_batch<K, PW, NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds) != hipSuccess)
         (void)hipGetLastError();
-    hipLaunchKernelGGL((k_batch<K, PW, NT>), dim3((unsigned)slots), dim3(NT), lds, s, count, n, A, b, x, order, queue,
-                       ws, *o, res);
+    hipLaunchKernelGGL((k_batch<K, PW, NT>), dim3((unsigned)slots), dim3(NT), lds, s, count, n, aw, A, b, x, order,
+                       queue, ws, *o, res);
     BNC_LAUNCH_CHECK();
     return BNC_OK;
 }
 
 template <int K, int NT>
-static int batch_launch_pw(int64_t count, const int64_t *n, const double *const *A, const double *const *b,
-                           double *const *x, const int32_t *order, unsigned *queue, double *ws, int slots,
-                           const bnc_refine_opts *o, bnc_batch_result *res, hipStream_t s)
+static int batch_launch_pw(int64_t count, const int64_t *n, const int32_t *aw, const double *const *A,
+                           const double *const *b, double *const *x, const int32_t *order, unsigned *queue,
+                           double *ws, int slots, const bnc_refine_opts *o, bnc_batch_result *res, hipStream_t s)
 {
-    if (o->batch_panel == 4)
-        return batch_launch<K, 4, NT>(count, n, A, b, x, order, queue, ws, slots, o, res, s);
-    return batch_launch<K, 8, NT>(count, n, A, b, x, order, queue, ws, slots, o, res, s);
+    if constexpr (sizeof(BatchLds<K, 8, NT>) <= BLDS_MAX) {
+        if (panel_fit<K, NT>(o->batch_panel) == 8)
+            return batch_launch<K, 8, NT>(count, n, aw, A, b, x, order, queue, ws, slots, o, res, s);
+    }
+    return batch_launch<K, 4, NT>(count, n, aw, A, b, x, order, queue, ws, slots, o, res, s);
 }
 
 template <int K>
-int batch_run(int64_t count, const int64_t *n, const double *const *A, const double *const *b, double *const *x,
-              const int32_t *order, void *work, int slots, const bnc_refine_opts *o, bnc_batch_result *res,
-              hipStream_t s)
+int batch_run(int64_t count, const int64_t *n, const int32_t *aw, const double *const *A, const double *const *b,
+              double *const *x, const int32_t *order, void *work, int slots, const bnc_refine_opts *o,
+              bnc_batch_result *res, hipStream_t s)
 {
     if (count == 0)
         return BNC_OK;
@@ -906,20 +982,22 @@ int batch_run(int64_t count, const int64_t *n, const double *const *A, const dou
     double *ws = (double *)((char *)work + 256);
     hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, queue);
     BNC_LAUNCH_CHECK();
-    switch (o->batch_threads) {
+    switch (o->batch_threads ? o->batch_threads : BT_DEFAULT) {
     case 64:
-        return batch_launch_pw<K, 64>(count, n, A, b, x, order, queue, ws, slots, o, res, s);
+        return batch_launch_pw<K, 64>(count, n, aw, A, b, x, order, queue, ws, slots, o, res, s);
     case 128:
-        return batch_launch_pw<K, 128>(count, n, A, b, x, order, queue, ws, slots, o, res, s);
+        return batch_launch_pw<K, 128>(count, n, aw, A, b, x, order, queue, ws, slots, o, res, s);
+    case 256:
+        return batch_launch_pw<K, 256>(count, n, aw, A, b, x, order, queue, ws, slots, o, res, s);
     default:
-        return batch_launch_pw<K, 256>(count, n, A, b, x, order, queue, ws, slots, o, res, s);
+        return batch_launch_pw<K, 512>(count, n, aw, A, b, x, order, queue, ws, slots, o, res, s);
     }
 }
 
 #define INST(K)                                                                                                 \
-    template int batch_run<K>(int64_t, const int64_t *, const double *const *, const double *const *,          \
-                              double *const *, const int32_t *, void *, int, const bnc_refine_opts *,          \
-                              bnc_batch_result *, hipStream_t);
+    template int batch_run<K>(int64_t, const int64_t *, const int32_t *, const double *const *,                 \
+                              const double *const *, double *const *, const int32_t *, void *, int,            \
+                              const bnc_refine_opts *, bnc_batch_result *, hipStream_t);
 INST(1)
 INST(2)
 INST(3)

@@ -2,7 +2,7 @@
 
 The batched kernel has two launch-shape knobs that leave every result
 unchanged: the LU panel width (4 or 8 columns staged in LDS) and the number
-of threads per workgroup (64, 128 or 256; one thread per row, so a
+of threads per workgroup (64, 128, 256 or 512; one thread per row, so a
 workgroup takes systems up to that order, and smaller workgroups let more
 small systems run at once).  tune() times every variant that fits each size
 class on a seeded sample of that class and keeps the fastest; the plan is a
@@ -18,9 +18,9 @@ import torch
 
 from . import bnc
 
-CLASSES = ((1, 64), (65, 128), (129, 256))
+CLASSES = ((1, 64), (65, 128), (129, 256), (257, 512))
 PANELS = (4, 8)
-THREADS = (64, 128, 256)
+THREADS = (64, 128, 256, 512)
 
 
 def _time(fn, reps: int) -> float:
@@ -37,14 +37,16 @@ def _time(fn, reps: int) -> float:
 
 
 def tune(K: int, sample: int = 1024, reps: int = 3, ctol: float = 2.0 ** -150, config: int = 9,
-         lc_lo: float = 2.0, lc_hi: float = 30.0, log=None) -> dict:
+         lc_lo: float = 2.0, lc_hi: float = 30.0, log=None, words_above: float | None = 1e15,
+         classes=CLASSES) -> dict:
     """Time every (panel, threads) variant on `sample` seeded randsvd systems
-    per size class (cond = 10^U(lc_lo, lc_hi)); returns the plan."""
+    per size class (cond = 10^U(lc_lo, lc_hi), quad-double-word entries
+    above `words_above`); returns the plan."""
     import synth
-    classes = []
-    for ci, (lo, hi) in enumerate(CLASSES):
+    out = []
+    for ci, (lo, hi) in enumerate(classes):
         As, bs, _, _ = synth.batch(sample, max(lo, 2), hi, lc_lo, lc_hi, config=config, workers=16,
-                                   first=ci * sample)
+                                   first=ci * sample, words_above=words_above)
         dA = [torch.from_numpy(a).cuda() for a in As]
         db = [torch.from_numpy(b).cuda() for b in bs]
         trials = []
@@ -58,8 +60,8 @@ def tune(K: int, sample: int = 1024, reps: int = 3, ctol: float = 2.0 ** -150, c
                 if log:
                     log(f"[tune] K={K} n in [{lo},{hi}] panel {pw} threads {nt} slots {S.slots}: {ms:.3f} ms")
         best = min(trials, key=lambda d: d["ms"])
-        classes.append(dict(n_lo=lo, n_hi=hi, panel=best["panel"], threads=best["threads"], trials=trials))
-    return dict(K=K, sample=sample, classes=classes)
+        out.append(dict(n_lo=lo, n_hi=hi, panel=best["panel"], threads=best["threads"], trials=trials))
+    return dict(K=K, sample=sample, classes=out)
 
 
 def save_plan(plan: dict, path: str):

@@ -268,11 +268,14 @@ def paper_problem(n: int, instance: int = 0, config: int = 7) -> tuple[np.ndarra
 
 
 def _batch_one(args):
-    config, i, n_lo, n_hi, lc_lo, lc_hi = args
+    config, i, n_lo, n_hi, lc_lo, lc_hi, words_above = args
     g = rng(config, i)
     n = int(g.integers(n_lo, n_hi + 1))
     cond = float(10.0 ** g.uniform(lc_lo, lc_hi))
-    Ap = planes(randsvd(n, cond, g))
+    if words_above is not None and cond > words_above:
+        Ap = randsvd_words(n, cond, g)
+    else:
+        Ap = planes(randsvd(n, cond, g))
     b, exact = rhs_ones(Ap)
     return Ap, b, exact, cond
 
@@ -286,14 +289,16 @@ def _one_blas_thread():
 
 
 def batch(count: int, n_lo: int, n_hi: int, lc_lo: float, lc_hi: float, config: int = 3, workers: int = 1,
-          progress=None, first: int = 0):
+          progress=None, first: int = 0, words_above: float | None = None):
     """`count` independent randsvd systems: system i draws n ~ U{n_lo..n_hi}
     and cond = 10^U(lc_lo, lc_hi) from its own seed (config, first + i), so
     the batch does not depend on the number of worker processes or on how a
-    long stream is cut into batches.  Returns lists of A planes (1, n, n),
-    b (4, n), exact flags and conds.  `progress(done)` is called every 512
-    systems."""
-    jobs = [(config, first + i, n_lo, n_hi, lc_lo, lc_hi) for i in range(count)]
+    long stream is cut into batches.  A system whose cond is above
+    `words_above` keeps quad-double-word entries (``randsvd_words``: a
+    binary64 copy could not hold that condition); the others are binary64.
+    Returns lists of A planes ((1 or 4), n, n), b (4, n), exact flags and
+    conds.  `progress(done)` is called every 512 systems."""
+    jobs = [(config, first + i, n_lo, n_hi, lc_lo, lc_hi, words_above) for i in range(count)]
     out = []
     if workers > 1:
         import multiprocessing as mp

@@ -1,7 +1,8 @@
 """GPU parity of the batched refined solves (bnc_refine_batched) with the
-oracle: every system of a mixed batch must come out bit for bit as the
-oracle's Listing-1 refinement of that system alone, whatever the order the
-systems are taken in, also through a captured HIP graph."""
+oracle: every system of a mixed batch (binary64 and quad-double-word
+entries, orders 1..512) must come out bit for bit as the oracle's
+Listing-1 refinement of that system alone, whatever the order the systems
+are taken in, also through a captured HIP graph."""
 import sys
 
 import numpy as np
@@ -52,6 +53,63 @@ def mixed_batch():
     return As, bs
 
 
+def words_batch():
+    """Quad-double-word systems (conditions a binary64 copy cannot hold),
+    binary64 ones beside them, and orders above 256."""
+    specs = [(40, 1e20, True), (97, 1e25, True), (130, 1e30, True), (64, 1e8, False), (257, 1e25, True),
+             (300, 1e12, False), (389, 1e28, True), (512, 1e5, False)]
+    As, bs = [], []
+    for i, (n, cond, words) in enumerate(specs):
+        Ap, b, _ = synth.problem("randsvd_words" if words else "randsvd", n, config=3, instance=900 + i, cond=cond)
+        As.append(Ap)
+        bs.append(b)
+    return As, bs
+
+
+def check_vs_oracle(S, refs):
+    res = S.results()
+    for i, ref in enumerate(refs):
+        assert res["status"][i] == ref["status"], i
+        if ref["status"] == O.SINGULAR:
+            assert res["info"][i] == ref["info"]
+        assert res["iters"][i] == ref["iters"], i
+        assert res["residual_inexact"][i] == 0
+        np.testing.assert_array_equal(S.xs[i].cpu().numpy(), ref["x"], err_msg=f"system {i}")
+
+
+@pytest.mark.parametrize("K", [2, 3])
+def test_batched_words_and_large_orders_vs_oracle(P, K):
+    """Quad-double-word A staged to K words, its exact residual over every
+    word, and orders up to 512 (512 threads per workgroup)."""
+    As, bs = words_batch()
+    refs = [O.refine(A, b, K, ctol=CTOL) for A, b in zip(As, bs)]
+    say("batched words/large K", K, "orders", [a.shape[-1] for a in As], "words", [a.shape[0] for a in As])
+    S = P.BatchSolver([dev(A) for A in As], [dev(b) for b in bs], K, ctol=CTOL)
+    assert S.opts.batch_threads == 512
+    S.run()
+    check_vs_oracle(S, refs)
+    # the systems of order <= 256 again, in a 256-thread launch
+    small = [i for i, a in enumerate(As) if a.shape[-1] <= 256]
+    say("batched words K", K, "256 threads")
+    S2 = P.BatchSolver([dev(As[i]) for i in small], [dev(bs[i]) for i in small], K, ctol=CTOL, threads=256)
+    S2.run()
+    check_vs_oracle(S2, [refs[i] for i in small])
+
+
+def test_batched_four_words_512_threads_panel_fallback(P):
+    """K = 4 at 512 threads: an 8-wide panel would not fit the LDS, the
+    launch takes 4-wide panels, and the words are those of the oracle."""
+    As, bs = words_batch()
+    sel = [0, 4, 7]
+    As, bs = [As[i] for i in sel], [bs[i] for i in sel]
+    refs = [O.refine(A, b, 4, ctol=CTOL) for A, b in zip(As, bs)]
+    for pw in (8, 4):
+        say("batched K 4 threads 512 panel", pw)
+        S = P.BatchSolver([dev(A) for A in As], [dev(b) for b in bs], 4, ctol=CTOL, panel=pw, threads=512)
+        S.run()
+        check_vs_oracle(S, refs)
+
+
 @pytest.mark.parametrize("K", [2, 3])
 def test_batched_bitexact_vs_oracle(P, K):
     As, bs = mixed_batch()
@@ -93,14 +151,22 @@ def test_batched_order_independent_and_graph(P):
 
 
 def test_batched_bad_size(P):
+    """Orders above the launch's threads (and above 512) and word counts
+    other than 1 or 4 are refused per system; the others still solve."""
     import torch
     K = 3
-    n = 300
-    Ap, b, _ = synth.problem("uniform", n, config=3, instance=777)
-    say("batched bad size")
-    S = P.BatchSolver([dev(Ap)], [dev(b)], K, ctol=CTOL)
+    A1, b1, _ = synth.problem("uniform", 300, config=3, instance=777)
+    A2, b2, _ = synth.problem("uniform", 600, config=3, instance=778)
+    A3, b3, _ = synth.problem("uniform", 30, config=3, instance=779)
+    A4 = np.concatenate([A3, np.zeros_like(A3)])  # two words per entry
+    say("batched bad size, 256 threads")
+    S = P.BatchSolver([dev(A1), dev(A3)], [dev(b1), dev(b3)], K, ctol=CTOL, threads=256)
     S.run()
-    assert S.results()["status"][0] == P.BNC_BAD_SIZE
+    assert list(S.results()["status"]) == [P.BNC_BAD_SIZE, P.BNC_CONVERGED]
+    say("batched bad size, 512 threads")
+    S = P.BatchSolver([dev(A2), dev(A1), dev(A4)], [dev(b2), dev(b1), dev(b3)], K, ctol=CTOL)
+    S.run()
+    assert list(S.results()["status"]) == [P.BNC_BAD_SIZE, P.BNC_CONVERGED, P.BNC_BAD_SIZE]
     torch.cuda.synchronize()
 
 
@@ -115,7 +181,7 @@ def test_launch_variants_bitexact(P):
     ref.run()
     r0 = ref.results()
     x0 = [x.cpu().numpy() for x in ref.xs]
-    for nt in (64, 128, 256):
+    for nt in (64, 128, 256, 512):
         for pw in (4, 8):
             say("variant threads", nt, "panel", pw)
             S = P.BatchSolver([dev(A) for A in As], [dev(b) for b in bs], K, ctol=CTOL, panel=pw, threads=nt)
