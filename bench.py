@@ -126,7 +126,7 @@ def batch_main(args):
     As, bs, exact, conds = synth.batch(args.count, 16, 256, 2.0, 30.0, config=3,
                                        workers=min(16, os.cpu_count() or 1),
                                        progress=lambda d: log(f"[bench] generated {d}/{args.count}"),
-                                       words_above=WORDS_ABOVE)
+                                       words_above=args.words_above or None)
     log(f"[bench] generated in {time.perf_counter() - t0:.1f} s")
     import torch
 
@@ -198,9 +198,10 @@ def batch_main(args):
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"{args.count} randsvd systems n~U[16,256] cond log-uniform [1e2,1e30], binary64 "
-                               f"entries up to cond 1e15, quad-double words above ({nwords} systems); "
-                               f"{WORD_NAME[K]} LU + QD refinement to 1e-45, one graph launch",
+        "config": {"workload": f"{args.count} randsvd systems n~U[16,256] cond log-uniform [1e2,1e30], "
+                               + (f"binary64 entries up to cond {args.words_above:g}, quad-double words above "
+                                  f"({nwords} systems); " if args.words_above else "binary64 entries; ")
+                               + f"{WORD_NAME[K]} LU + QD refinement to 1e-45, one graph launch",
                    "count": args.count, "factor": WORD_NAME[K], "ctol": ctol, "slots": S.slots,
                    "tuning": None if plan is None else [(c["n_lo"], c["n_hi"], c["panel"], c["threads"])
                                                         for c in plan["classes"]]},
@@ -596,6 +597,9 @@ def main():
     ap.add_argument("--count", type=int, default=8192, help="batch mode: number of systems")
     ap.add_argument("--slots", type=int, default=0, help="batch mode: persistent workgroups (0 = auto)")
     ap.add_argument("--tune", action="store_true", help="batch mode: tune the launch variants now")
+    ap.add_argument("--words-above", type=float, default=WORDS_ABOVE,
+                    help="batch mode: conditions above this keep quad-double-word entries (0: every system "
+                         "binary64)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (the reference kernel that "
                          "scales hardware byte counters)")

@@ -8,8 +8,9 @@
 // order as the single-system solver, so each result equals it bit for bit:
 //   stage A (binary64 or quad-double words per entry, system by system)
 //   to K words; blocked right-looking LU with 8-column panels held
-//   in LDS (pivot search by wave shuffles, whole-row swaps, reciprocal and
-//   scaling, rank-1 panel updates), U12 by forward substitution, trailing
+//   in LDS (pivot search by wave shuffles, row interchanges as swaps in a
+//   row map instead of data movement, reciprocal and scaling, rank-1 panel
+//   updates), U12 by forward substitution, trailing
 //   update with each thread's L21 row in registers and U12 in LDS; diagonal
 //   reciprocals; substitutions with one thread per row and one LDS broadcast
 //   per pivot; the exact residual with one thread per row; the stopping
@@ -47,8 +48,7 @@ struct BatchLds {
     int redi[NT];
     double wkey[NT / 64][K];       // per-wave argmax
     int wrow[NT / 64];
-    int perm[NT];
-    int ipiv[NT];
+    int perm[NT];  // row map of the factorisation, then its permutation
     int s_int[4];
 };
 
@@ -151,19 +151,20 @@ __device__ __forceinline__ void bsolve(int n, const double *__restrict__ lu, int
 {
     const int t = threadIdx.x;
     const int tc = t < n ? t : n - 1;  // in-bounds row for the prefetches
+    const int64_t pt = S.perm[tc];      // its stored row (rows are never moved)
     // forward: y_i <- y_i - l_ik y_k, k increasing; column k + 1's entry is
     // loaded a step ahead (unconditionally, from an in-bounds address)
     double ln[K];
 #pragma unroll
     for (int w = 0; w < K; ++w)
-        ln[w] = lu[w * ldp + tc];
+        ln[w] = lu[w * ldp + pt];
     for (int k = 0; k < n; ++k) {
         double l[K];
         const int kn = k + 1 < n ? k + 1 : k;
 #pragma unroll
         for (int w = 0; w < K; ++w) {
             l[w] = ln[w];
-            ln[w] = lu[w * ldp + (int64_t)kn * n + tc];
+            ln[w] = lu[w * ldp + (int64_t)kn * n + pt];
         }
         if (t == k) {
 #pragma unroll
@@ -188,14 +189,14 @@ __device__ __forceinline__ void bsolve(int n, const double *__restrict__ lu, int
     double un[K];
 #pragma unroll
     for (int w = 0; w < K; ++w)
-        un[w] = lu[w * ldp + (int64_t)(n - 1) * n + tc];
+        un[w] = lu[w * ldp + (int64_t)(n - 1) * n + pt];
     for (int k = n - 1; k >= 0; --k) {
         double u[K];
         const int kn = k > 0 ? k - 1 : 0;
 #pragma unroll
         for (int w = 0; w < K; ++w) {
             u[w] = un[w];
-            un[w] = lu[w * ldp + (int64_t)kn * n + tc];
+            un[w] = lu[w * ldp + (int64_t)kn * n + pt];
         }
         if (t == k) {
             double rk[K], xk[K];
@@ -416,16 +417,24 @@ __global__ void __launch_bounds__(NT)
         }
         __syncthreads();
 
-        // ---- blocked LU
+        // ---- blocked LU.  Rows are never moved in the workspace: S.perm[i]
+        // is the stored row that holds row i of the factorisation (the
+        // original row index, since A is staged unpermuted), and a pivot
+        // interchange swaps two entries of it.  Every access to row i goes
+        // through S.perm, so the values are those of whole-row swaps.
+        for (int i = t; i < n; i += NT)
+            S.perm[i] = i;
+        __syncthreads();
         int64_t info = 0;
         for (int j0 = 0; j0 < n; j0 += PW) {
             const int jb = (n - j0) < PW ? (n - j0) : PW;
             const int m = n - j0;
             for (int e = t; e < m * jb; e += NT) {
                 const int r = e % m, c = e / m;
+                const int pr = S.perm[j0 + r];
 #pragma unroll
                 for (int w = 0; w < K; ++w)
-                    S.tile[(w * PW + c) * NT + r] = lu[w * ldp + (int64_t)(j0 + c) * n + j0 + r];
+                    S.tile[(w * PW + c) * NT + r] = lu[w * ldp + (int64_t)(j0 + c) * n + pr];
             }
             __syncthreads();
             for (int kk = 0; kk < jb; ++kk) {
@@ -483,12 +492,11 @@ __global__ void __launch_bounds__(NT)
                         }
                     }
                     S.s_int[1] = br;
-                    S.ipiv[k] = j0 + br;
                 }
                 __syncthreads();
                 const int pr = S.s_int[1];  // tile row of the pivot
                 if (pr != kk) {
-                    // panel columns in the tile, other columns in the workspace
+                    // panel columns in the tile, the rest through the row map
                     for (int e = t; e < jb * K; e += NT) {
                         const int c = e % jb, w = e / jb;
                         double *a = &S.tile[(w * PW + c) * NT];
@@ -496,13 +504,10 @@ __global__ void __launch_bounds__(NT)
                         a[kk] = a[pr];
                         a[pr] = tmp;
                     }
-                    for (int e = t; e < (n - jb) * K; e += NT) {
-                        const int cc = e % (n - jb), w = e / (n - jb);
-                        const int c = cc < j0 ? cc : cc + jb;
-                        double *col = lu + w * ldp + (int64_t)c * n;
-                        const double tmp = col[k];
-                        col[k] = col[j0 + pr];
-                        col[j0 + pr] = tmp;
+                    if (t == 0) {
+                        const int tmp = S.perm[k];
+                        S.perm[k] = S.perm[j0 + pr];
+                        S.perm[j0 + pr] = tmp;
                     }
                 }
                 __syncthreads();
@@ -546,12 +551,14 @@ __global__ void __launch_bounds__(NT)
                 }
                 __syncthreads();
             }
-            // panel back to the workspace
+            // panel back to the workspace (rows through the map, final for
+            // this panel: later interchanges only swap entries past it)
             for (int e = t; e < m * jb; e += NT) {
                 const int r = e % m, c = e / m;
+                const int pr = S.perm[j0 + r];
 #pragma unroll
                 for (int w = 0; w < K; ++w)
-                    lu[w * ldp + (int64_t)(j0 + c) * n + j0 + r] = S.tile[(w * PW + c) * NT + r];
+                    lu[w * ldp + (int64_t)(j0 + c) * n + pr] = S.tile[(w * PW + c) * NT + r];
             }
             // every later phase reads the panel back from the workspace,
             // written above by other threads
@@ -576,13 +583,17 @@ __global__ void __launch_bounds__(NT)
             }
             __syncthreads();
             // U12 = L11^-1 A12: thread per column of A12
+            int prow[PW];  // stored rows of the panel's rows
+#pragma unroll
+            for (int kk = 0; kk < PW; ++kk)
+                prow[kk] = kk < jb ? S.perm[j0 + kk] : 0;
             for (int j = t; j < m2; j += NT) {
                 double u[PW][K];
 #pragma unroll
                 for (int kk = 0; kk < PW; ++kk)
 #pragma unroll
                     for (int w = 0; w < K; ++w)
-                        u[kk][w] = kk < jb ? lu[w * ldp + (int64_t)(c0 + j) * n + j0 + kk] : 0.0;
+                        u[kk][w] = kk < jb ? lu[w * ldp + (int64_t)(c0 + j) * n + prow[kk]] : 0.0;
 #pragma unroll
                 for (int kk = 0; kk < PW; ++kk) {
                     if (kk < jb) {
@@ -592,7 +603,7 @@ __global__ void __launch_bounds__(NT)
                                 double l[K], oo[K];
 #pragma unroll
                                 for (int w = 0; w < K; ++w)
-                                    l[w] = lu[w * ldp + (int64_t)(j0 + kk) * n + j0 + rr];
+                                    l[w] = lu[w * ldp + (int64_t)(j0 + kk) * n + prow[rr]];
                                 fms<K>(u[rr], l, u[kk], oo);
 #pragma unroll
                                 for (int w = 0; w < K; ++w)
@@ -606,7 +617,7 @@ __global__ void __launch_bounds__(NT)
                     if (kk < jb) {
 #pragma unroll
                         for (int w = 0; w < K; ++w) {
-                            lu[w * ldp + (int64_t)(c0 + j) * n + j0 + kk] = u[kk][w];
+                            lu[w * ldp + (int64_t)(c0 + j) * n + prow[kk]] = u[kk][w];
                             S.tile[(w * PW + kk) * NT + j] = u[kk][w];
                         }
                     }
@@ -618,6 +629,7 @@ __global__ void __launch_bounds__(NT)
             // other's latency (one chain per thread left the FP64 pipes
             // idle at one wave per SIMD)
             if (r < m2) {
+                const int64_t prr = S.perm[c0 + r];  // stored row of row c0 + r
                 int j = q;
                 // the next group's entries are loaded while this group is
                 // updated (unconditional loads from clamped columns)
@@ -626,7 +638,7 @@ __global__ void __launch_bounds__(NT)
 #pragma unroll
                     for (int bj = 0; bj < BJ; ++bj) {
                         const int jc = jg + bj * G < m2 ? jg + bj * G : m2 - 1;
-                        const double *cp = lu + (int64_t)(c0 + jc) * n + c0 + r;
+                        const double *cp = lu + (int64_t)(c0 + jc) * n + prr;
 #pragma unroll
                         for (int w = 0; w < K; ++w)
                             cc[bj][w] = cp[w * ldp];
@@ -655,7 +667,7 @@ __global__ void __launch_bounds__(NT)
                     }
 #pragma unroll
                     for (int bj = 0; bj < BJ; ++bj) {
-                        double *cp = lu + (int64_t)(c0 + j + bj * G) * n + c0 + r;
+                        double *cp = lu + (int64_t)(c0 + j + bj * G) * n + prr;
 #pragma unroll
                         for (int w = 0; w < K; ++w) {
                             cp[w * ldp] = c[bj][w];
@@ -665,7 +677,7 @@ __global__ void __launch_bounds__(NT)
                 }
                 for (; j < m2; j += G) {
                     double c[K];
-                    double *cp = lu + (int64_t)(c0 + j) * n + c0 + r;
+                    double *cp = lu + (int64_t)(c0 + j) * n + prr;
 #pragma unroll
                     for (int w = 0; w < K; ++w)
                         c[w] = cp[w * ldp];
@@ -704,26 +716,16 @@ __global__ void __launch_bounds__(NT)
             __syncthreads();
             continue;
         }
-        // diagonal reciprocals and the row permutation
+        // diagonal reciprocals; S.perm is the row permutation of P A = L U
         if (t < n) {
             double d[K], rc[K];
 #pragma unroll
             for (int w = 0; w < K; ++w)
-                d[w] = lu[w * ldp + (int64_t)t * n + t];
+                d[w] = lu[w * ldp + (int64_t)t * n + S.perm[t]];
             recip<K>(d, rc);
 #pragma unroll
             for (int w = 0; w < K; ++w)
                 rd[w * NT + t] = rc[w];
-        }
-        if (t == 0) {
-            for (int i = 0; i < n; ++i)
-                S.perm[i] = i;
-            for (int k = 0; k < n; ++k) {
-                const int p = S.ipiv[k];
-                const int tmp = S.perm[k];
-                S.perm[k] = S.perm[p];
-                S.perm[p] = tmp;
-            }
         }
         __syncthreads();
 
@@ -769,6 +771,12 @@ __global__ void __launch_bounds__(NT)
                         ex = e2 < ex ? e2 : ex;
                     }
             const double xmax = wg_max<NT>(fabs(xv0), S.red);
+            // the forward test needs no residual: when it decides, this
+            // pass's residual (whose test could only agree) is not formed
+            if (have_z && zmax <= o.ctol * xmax) {
+                status = BNC_CONVERGED;
+                break;
+            }
             ex = wg_min_i<NT>(ex, S.redi);
             // exact residual, thread per row; the wave's lanes deposit into
             // a common number of bins (the largest row's) so that the bin
