@@ -385,8 +385,9 @@ def paper_main(args):
 
 def selector_main(args):
     """Learned precision choice on a held-out stream: `count` randsvd systems
-    n ~ U{32..256}, cond = 10^U(1, 60), binary64 entries (seed stream 6, the
-    same law as the training stream 5); target max|x - 1| <= 1e-45.  Times
+    n ~ U{32..512}, cond = 10^U(1, 60), binary64 entries up to cond 1e15 and
+    quad-double words above (seed stream 6, the same law as the training
+    stream 5); target max|x - 1| <= 1e-45.  Times
     the selector path (features + network + solves, escalating on misses)
     against escalate-on-stagnation from one word, both in batched launches."""
     import numpy as np
@@ -396,6 +397,8 @@ def selector_main(args):
     from paper_2107_12550_amd import selector as SEL
     model = os.path.join(ROOT, "paper_2107_12550_amd", "selector_model.npz")
     net = SEL.load(model)
+    with open(os.path.join(ROOT, "paper_2107_12550_amd", "selector_model.json")) as f:
+        SEL_TRAINED = json.load(f).get("train_systems")
     chunk = 4096
     tot = dict(baseline_ms=0.0, selector_ms=0.0, selector_predict_ms=0.0, baseline_attempts=0, selector_attempts=0,
                baseline_solved=0, selector_solved=0, selector_escalations=0, baseline_wrong=0, selector_wrong=0,
@@ -403,8 +406,8 @@ def selector_main(args):
     for c0 in range(0, args.count, chunk):
         m = min(chunk, args.count - c0)
         log(f"[bench] generating held-out systems {c0}..{c0 + m}")
-        As, bs, exact, _ = synth.batch(m, 32, 256, 1.0, 60.0, config=6, workers=min(16, os.cpu_count() or 1),
-                                       first=c0)
+        As, bs, exact, _ = synth.batch(m, 32, 512, 1.0, 60.0, config=6, workers=min(16, os.cpu_count() or 1),
+                                       first=c0, words_above=args.words_above or None)
         dA = [torch.from_numpy(a).cuda() for a in As]
         db = [torch.from_numpy(b).cuda() for b in bs]
         SEL.evaluate(net, dA, db)  # warm-up
@@ -426,8 +429,9 @@ def selector_main(args):
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"{args.count} held-out randsvd systems n~U[32,256] cond 10^U(1,60) binary64 entries, "
-                               "target 1e-45; selector trained on 200000 method-labelled systems",
+        "config": {"workload": f"{args.count} held-out randsvd systems n~U[32,512] cond 10^U(1,60), binary64 "
+                               f"entries up to cond {args.words_above:g} and quad-double words above, target 1e-45; "
+                               f"selector trained on {SEL_TRAINED} method-labelled systems of the same law",
                    "count": args.count},
         "baseline": {"rule": "escalate-on-stagnation from one word", "ms": tot["baseline_ms"],
                      "solves_per_s": args.count * 1e3 / tot["baseline_ms"], "attempts": tot["baseline_attempts"],

@@ -240,7 +240,10 @@ typedef struct bnc_refine_opts {
                              (checked after the stopping tests); 0 disables.
                              Batched solves report BNC_STAGNATED (they take
                              escalate = 0). */
-    int32_t batch_panel;  /* batched solves: LU panel width 4 or 8 (0 = 8) */
+    int32_t batch_panel;  /* batched solves: LU panel width 4, 8 or 16 (0 = 8;
+                             a width whose panel would not fit the LDS of a
+                             compute unit, or 16 below 128 threads, runs as
+                             the next narrower one) */
     int32_t batch_threads; /* batched solves: threads per workgroup, 64, 128,
                              256 or 512 (0 = 256); systems of order above it get
                              BNC_BAD_SIZE.  Both are tuning knobs that leave
@@ -255,11 +258,11 @@ typedef struct bnc_refine_opts {
                              floats) and input normalisation (device, 48
                              floats), as for bnc_mlp_forward.  bnc_refine
                              computes the 24 features of the system
-                             (bnc_features; orders 1..256, the leading words
+                             (bnc_features; orders 1..512, the leading words
                              of A), runs the network and factors with the
                              predicted number of words; escalation (when
                              enabled) stays the fallback.  For orders above
-                             256 it starts at 2 words.  Ignored otherwise. */
+                             512 it starts at 2 words.  Ignored otherwise. */
     const float *selector_norm;
 } bnc_refine_opts;
 
@@ -417,8 +420,9 @@ size_t bnc_features_workspace_size(int32_t slots);
 int32_t bnc_features_default_slots(void);
 
 /*
- * 24 binary32 features per system, features[s * 24 + f] (orders 1..256;
- * others get zeros), each computed in binary64 and rounded:
+ * 24 binary32 features per system, features[s * 24 + f] (orders 1..512;
+ * others get zeros), each computed in binary64 from the leading words of A
+ * and b and rounded:
  *   0 log2 n;  1 log2 ||A||_F;  2-4 log2 of ||A||_1, ||A||_inf, max|a_ij|
  *   relative to ||A||_F;  5-7 diagonal dominance |a_ii| / sum_{j!=i} |a_ij|:
  *   log2 of its minimum and mean, fraction of rows above 1;  8 log2 of the
@@ -437,9 +441,10 @@ int32_t bnc_features_default_slots(void);
  *   singular binary64 factor gives 1000 + log2 ||A||_1 in 17-19, 1100 in
  *   20 and 0 in 21-22.  Sums run in index order, so the values do not
  *   depend on `slots`.
- *   count, n, A, b, order   as bnc_refine_batched (A binary64, lda = n;
- *             b 4-plane; order: the order systems are taken in, NULL =
- *             0..count-1, largest first balances the load)
+ *   count, n, A, b, order   as bnc_refine_batched (A[s]: its leading
+ *             plane, lda = n, is read; b 4-plane; order: the order systems
+ *             are taken in, NULL = 0..count-1, largest first balances the
+ *             load)
  *   features  device float[count * 24]
  *   work      >= bnc_features_workspace_size(slots) bytes;  slots 0 = default
  * Asynchronous on stream.

@@ -515,7 +515,7 @@ int32_t bnc_refine_batched_default_slots(int32_t factor_words, int32_t panel, in
     if (factor_words < 1 || factor_words > 4)
         return fail_arg(-1, "refine_batched_default_slots: factor_words outside 1..4");
     if (!batch_panel_ok(panel))
-        return fail_arg(-2, "refine_batched_default_slots: panel not 0, 4 or 8");
+        return fail_arg(-2, "refine_batched_default_slots: panel not 0, 4, 8 or 16");
     if (!batch_threads_ok(threads))
         return fail_arg(-3, "refine_batched_default_slots: threads not 0, 64, 128, 256 or 512");
     return batch_default_slots(factor_words, panel, threads);

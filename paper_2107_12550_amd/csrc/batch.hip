@@ -26,7 +26,7 @@ namespace bnc {
 constexpr int BT_MAX = 512;  // most threads per workgroup (= largest order)
 constexpr int BT_DEFAULT = 256;  // threads per workgroup unless chosen
 constexpr size_t BLDS_MAX = 160 * 1024;  // LDS of one compute unit
-constexpr int BNB_DEFAULT = 8;  // LU panel width unless tuned (4 or 8)
+constexpr int BNB_DEFAULT = 8;  // LU panel width unless tuned (4, 8 or 16)
 constexpr int BRB = 24;     // residual bins per row (816 bits)
 constexpr int BJ = 4;       // trailing-update columns per thread at once
 constexpr int RPF = 4;      // residual: columns of A loaded ahead
@@ -42,6 +42,7 @@ constexpr size_t slot_doubles()
 template <int K, int PW, int NT>
 struct BatchLds {
     double tile[K * PW * NT];  // panel [w][c][r]; reused as U12 [w][k][j]
+    double l11[K][PW][PW];      // the panel's unit lower triangle [w][k][r]
     double ybuf[NT][K];         // broadcast slots of the substitutions
     double xq[4][NT];           // current solution (quad-double)
     double red[NT];                // reduction scratch
@@ -381,10 +382,7 @@ __global__ void __launch_bounds__(NT)
         eb = wg_min_i<NT>(eb, S.redi);
         double anorm;
         {
-            double am = 0.0;
-            for (int64_t e = t; e < (int64_t)n * n; e += NT)
-                am = fmax(am, fabs(A[e]));
-            am = wg_max<NT>(am, S.red);
+            const double am = wg_max<NT>(rmax_i, S.red);  // max |a_ij| (leading words)
             const double sc = pow2(-(norm_exp(am) + 1));
             double acc = 0.0;
             for (int64_t e = t; e < (int64_t)n * n; e += NT) {
@@ -581,6 +579,11 @@ __global__ void __launch_bounds__(NT)
                     for (int w = 0; w < K; ++w)
                         l21[kk][w] = kk < jb ? S.tile[(w * PW + kk) * NT + jb + r] : 0.0;
             }
+            // L11 to its own block (U12 overwrites the tile below)
+            for (int e = t; e < K * PW * PW; e += NT) {
+                const int rr = e % PW, kk = (e / PW) % PW, w = e / (PW * PW);
+                S.l11[w][kk][rr] = (kk < jb && rr < jb) ? S.tile[(w * PW + kk) * NT + rr] : 0.0;
+            }
             __syncthreads();
             // U12 = L11^-1 A12: thread per column of A12
             int prow[PW];  // stored rows of the panel's rows
@@ -603,7 +606,7 @@ __global__ void __launch_bounds__(NT)
                                 double l[K], oo[K];
 #pragma unroll
                                 for (int w = 0; w < K; ++w)
-                                    l[w] = lu[w * ldp + (int64_t)(j0 + kk) * n + prow[rr]];
+                                    l[w] = S.l11[w][kk][rr];
                                 fms<K>(u[rr], l, u[kk], oo);
 #pragma unroll
                                 for (int w = 0; w < K; ++w)
@@ -899,21 +902,39 @@ static int occupancy_per_cu()
     return per;
 }
 
-// The panel width actually launched: 8-wide panels whose LDS would not fit
-// a compute unit (four words at 512 threads) fall back to 4 (the width
-// changes no result).
+// Panel widths a launch of NT threads offers: 16 from 128 threads up, when
+// its LDS fits a compute unit; 8 when it fits; 4 always.
+template <int K, int PW, int NT>
+constexpr bool panel_offered()
+{
+    return sizeof(BatchLds<K, PW, NT>) <= BLDS_MAX && (PW != 16 || NT >= 128);
+}
+
+// The panel width actually launched: the widest offered one not above the
+// request (0 = 8).  The width changes no result.
 template <int K, int NT>
 constexpr int panel_fit(int pw)
 {
-    return (pw == 4 || sizeof(BatchLds<K, 8, NT>) > BLDS_MAX) ? 4 : 8;
+    if (pw == 0)
+        pw = BNB_DEFAULT;
+    if (pw >= 16 && panel_offered<K, 16, NT>())
+        return 16;
+    if (pw >= 8 && panel_offered<K, 8, NT>())
+        return 8;
+    return 4;
 }
 
 template <int K, int NT>
 static int occupancy_pw(int pw)
 {
     static_assert(sizeof(BatchLds<K, 4, NT>) <= BLDS_MAX, "batched LDS exceeds a compute unit");
-    if constexpr (sizeof(BatchLds<K, 8, NT>) <= BLDS_MAX) {
-        if (panel_fit<K, NT>(pw) == 8)
+    const int f = panel_fit<K, NT>(pw);
+    if constexpr (panel_offered<K, 16, NT>()) {
+        if (f == 16)
+            return occupancy_per_cu<K, 16, NT>();
+    }
+    if constexpr (panel_offered<K, 8, NT>()) {
+        if (f == 8)
             return occupancy_per_cu<K, 8, NT>();
     }
     return occupancy_per_cu<K, 4, NT>();
@@ -934,7 +955,7 @@ static int occupancy_k(int pw, int nt)
     }
 }
 
-bool batch_panel_ok(int pw) { return pw == 0 || pw == 4 || pw == 8; }
+bool batch_panel_ok(int pw) { return pw == 0 || pw == 4 || pw == 8 || pw == 16; }
 bool batch_threads_ok(int nt) { return nt == 0 || nt == 64 || nt == 128 || nt == 256 || nt == 512; }
 
 int batch_default_slots(int K, int pw, int nt)
@@ -972,8 +993,13 @@ static int batch_launch_pw(int64_t count, const int64_t *n, const int32_t *aw, c
                            const double *const *b, double *const *x, const int32_t *order, unsigned *queue,
                            double *ws, int slots, const bnc_refine_opts *o, bnc_batch_result *res, hipStream_t s)
 {
-    if constexpr (sizeof(BatchLds<K, 8, NT>) <= BLDS_MAX) {
-        if (panel_fit<K, NT>(o->batch_panel) == 8)
+    const int f = panel_fit<K, NT>(o->batch_panel);
+    if constexpr (panel_offered<K, 16, NT>()) {
+        if (f == 16)
+            return batch_launch<K, 16, NT>(count, n, aw, A, b, x, order, queue, ws, slots, o, res, s);
+    }
+    if constexpr (panel_offered<K, 8, NT>()) {
+        if (f == 8)
             return batch_launch<K, 8, NT>(count, n, aw, A, b, x, order, queue, ws, slots, o, res, s);
     }
     return batch_launch<K, 4, NT>(count, n, aw, A, b, x, order, queue, ws, slots, o, res, s);

@@ -43,7 +43,7 @@ size_t features_workspace_bytes(int slots);
 int features_run(int64_t count, const int64_t *n, const double *const *A, const double *const *b,
                  const int32_t *order, float *F, void *work, int slots, hipStream_t s);
 int mlp_forward_run(int64_t B, const float *X, const float *norm, const float *P, float *O, hipStream_t s);
-constexpr int64_t SEL_NMAX = 256;  // orders the features kernel takes
+constexpr int64_t SEL_NMAX = 512;  // orders the features kernel takes
 template <int K>
 int diag_recip_run(int64_t n, const double *LU, int64_t lda, int64_t ldp, double *rd, hipStream_t s);
 int ipiv_to_perm(int64_t n, const int64_t *ipiv, int32_t *perm, hipStream_t s);

@@ -1,14 +1,16 @@
 // Learned choice of the factor precision (not in the paper; the project's
 // addition on top of its mixed-precision refinement, Sec. 2 / Listing 1).
 //
-//   k_features  24 cheap binary64 features of each system (order <= 256):
+//   k_features  24 cheap binary64 features of each system (order <= 512,
+//               the leading words of A):
 //               norms and their ratios, diagonal dominance, symmetry, a
 //               binary64 LU with partial pivoting (pivot growth, spread of
 //               U's diagonal), three steps of Hager's 1-norm estimate of
 //               ||A^-1||_1 (Hager 1984; Higham 1988) from solves with A and
 //               A^T, and the binary64 solution of A x = b (its size and
 //               backward error).  One workgroup per system, thread t owns
-//               row t; every sum runs in index order on one thread and
+//               row t (256 threads up to order 256, 512 above); every sum
+//               runs in index order on one thread and
 //               every maximum, minimum and arg-maximum is exact, so the
 //               numbers do not depend on the launch shape.
 //   k_mlp_*     a multilayer perceptron 24 -> 64 -> 64 -> 5 (ReLU) in
@@ -21,25 +23,26 @@
 
 namespace bnc {
 
-constexpr int FT = 256;     // threads per workgroup
-constexpr int FNMAX = 256;  // largest order
+constexpr int FNMAX = 512;  // largest order (workspace slots are FNMAX^2)
 constexpr int NFEAT = 24;
 constexpr int HAGER_STEPS = 3;
 constexpr int FB = 8;       // LU panel width
 constexpr double LG_CAP = 1100.0;
 
+// FT threads per workgroup = the largest order it takes
+template <int FT>
 struct FeatLds {
-    double y[FNMAX];    // vector being solved
-    double a[FNMAX];    // per-row / per-column partials
-    double b[FNMAX];
-    double c[FNMAX];
-    double d[FNMAX];
-    double e[FNMAX];
+    double y[FT];       // vector being solved
+    double a[FT];       // per-row / per-column partials
+    double b[FT];
+    double c[FT];
+    double d[FT];
+    double e[FT];
     double rv[FT / 64]; // reduction scratch: one value per wave
     int ri[FT / 64];
-    int ipiv[FNMAX];
+    int ipiv[FT];
     double prow[FB], rowk[FB], rowp[FB];  // pivot row and the two swapped rows of a panel
-    double ub[FB][FNMAX];                 // the panel's rows of U12
+    double ub[FB][FT];                    // the panel's rows of U12
     double bc[4];
     int s_i[4];
 };
@@ -54,7 +57,8 @@ __device__ __forceinline__ double lg(double x)
 
 // exact maximum of the threads' values (every thread gets it): a
 // butterfly inside each wave, then the four wave results in order
-__device__ double wg_max_exact(double v, FeatLds &S)
+template <int FT>
+__device__ double wg_max_exact(double v, FeatLds<FT> &S)
 {
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
 #pragma unroll
@@ -71,13 +75,15 @@ __device__ double wg_max_exact(double v, FeatLds &S)
     return r;
 }
 
-__device__ double wg_min_exact(double v, FeatLds &S)
+template <int FT>
+__device__ double wg_min_exact(double v, FeatLds<FT> &S)
 {
     return -wg_max_exact(-v, S);
 }
 
 // arg-maximum of key (ties: smallest index; keys < 0 never win)
-__device__ int wg_argmax(double key, FeatLds &S)
+template <int FT>
+__device__ int wg_argmax(double key, FeatLds<FT> &S)
 {
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     int idx = t;
@@ -108,7 +114,8 @@ __device__ int wg_argmax(double key, FeatLds &S)
 }
 
 // sum of p[0..n) in index order (thread 0), broadcast
-__device__ double seq_sum(const double *p, int n, FeatLds &S)
+template <int FT>
+__device__ double seq_sum(const double *p, int n, FeatLds<FT> &S)
 {
     if (threadIdx.x == 0) {
         double s = 0.0;
@@ -147,7 +154,8 @@ __device__ __forceinline__ double recip1(double a)
 // y_i -= u_ik x_k (decreasing k)
 constexpr int PF = 8;  // substitution steps whose factor entries are loaded together
 
-__device__ void lu_solve(const double *W, int n, FeatLds &S)
+template <int FT>
+__device__ void lu_solve(const double *W, int n, FeatLds<FT> &S)
 {
     const int t = threadIdx.x;
     if (t == 0)
@@ -209,7 +217,8 @@ __device__ void lu_solve(const double *W, int n, FeatLds &S)
 // S.y <- A^-T S.y: U^T w = c (forward: w_k = w_k (1/u_kk), then
 // w_i -= u_ki w_k for i > k), L^T v = w (backward: v_i -= l_ki v_k for
 // i < k), then the swaps undone in reverse order
-__device__ void lu_solve_t(const double *W, int n, FeatLds &S)
+template <int FT>
+__device__ void lu_solve_t(const double *W, int n, FeatLds<FT> &S)
 {
     const int t = threadIdx.x;
     for (int k0 = 0; k0 < n; k0 += PF) {
@@ -266,12 +275,16 @@ __device__ void lu_solve_t(const double *W, int n, FeatLds &S)
     __syncthreads();
 }
 
+// Systems of order in (n_lo, FT] get their features here; a launch with
+// n_lo = 0 writes zeros for orders outside 1..FT, a launch with n_lo > 0
+// leaves every other system alone.
+template <int FT>
 __global__ void __launch_bounds__(FT)
     k_features(int64_t count, const int64_t *__restrict__ nn, const double *const *__restrict__ As,
                const double *const *__restrict__ bs, const int32_t *__restrict__ order, float *__restrict__ F,
-               unsigned *__restrict__ queue, double *__restrict__ work)
+               unsigned *__restrict__ queue, double *__restrict__ work, int64_t n_lo)
 {
-    __shared__ FeatLds S;
+    __shared__ FeatLds<FT> S;
     const int t = threadIdx.x;
     double *W = work + (size_t)blockIdx.x * FNMAX * FNMAX;
     for (;;) {
@@ -285,7 +298,9 @@ __global__ void __launch_bounds__(FT)
         const int64_t sys = order ? order[qi] : qi;
         const int64_t n64 = nn[sys];
         float *out = F + sys * NFEAT;
-        if (n64 < 1 || n64 > FNMAX) {
+        if (n_lo > 0 && (n64 <= n_lo || n64 > FT))
+            continue;
+        if (n64 < 1 || n64 > FT) {
             if (t < NFEAT)
                 out[t] = 0.0f;
             continue;
@@ -576,7 +591,8 @@ int features_default_slots()
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return 256;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)k_features, FT, 0) != hipSuccess || per < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)k_features<256>, 256, 0) != hipSuccess ||
+        per < 1)
         per = 1;
     return per * ncu;
 }
@@ -589,9 +605,16 @@ int features_run(int64_t count, const int64_t *n, const double *const *A, const 
     unsigned *queue = (unsigned *)work;
     double *ws = (double *)((char *)work + 256);
     const int64_t g = count < slots ? count : slots;
+    // orders up to 256 (and zeros for the invalid ones), then 257..512
     hipLaunchKernelGGL(k_feat_queue_reset, dim3(1), dim3(64), 0, s, queue);
     BNC_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_features, dim3((unsigned)g), dim3(FT), 0, s, count, n, A, b, order, F, queue, ws);
+    hipLaunchKernelGGL(k_features<256>, dim3((unsigned)g), dim3(256), 0, s, count, n, A, b, order, F, queue, ws,
+                       (int64_t)0);
+    BNC_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_feat_queue_reset, dim3(1), dim3(64), 0, s, queue);
+    BNC_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_features<512>, dim3((unsigned)g), dim3(512), 0, s, count, n, A, b, order, F, queue, ws,
+                       (int64_t)256);
     BNC_LAUNCH_CHECK();
     return BNC_OK;
 }

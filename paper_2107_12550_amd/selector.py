@@ -56,23 +56,39 @@ def max_err_vs_ones(xs) -> np.ndarray:
 
 
 def solve_at(As, bs, K: int) -> dict:
-    """Refine every system with a K-word factor in one batched launch."""
-    S = bnc.BatchSolver(As, bs, K, max_iter=MAX_ITER, ctol=CTOL, stagnation_ratio=STAG_RATIO)
+    """Refine every system with a K-word factor: one batched launch for the
+    orders up to 256 (256 threads per workgroup) and one for those above
+    (512), back to back."""
+    count = len(As)
+    ns = np.array([int(a.shape[-1]) for a in As])
+    groups = [g for g in (np.nonzero(ns <= 256)[0], np.nonzero(ns > 256)[0]) if g.size]
+    solvers = [(g, bnc.BatchSolver([As[i] for i in g], [bs[i] for i in g], K, max_iter=MAX_ITER, ctol=CTOL,
+                                   stagnation_ratio=STAG_RATIO, threads=256 if ns[g].max() <= 256 else 512))
+               for g in groups]
     e0, e1 = _events()
     e0.record()
-    S.run()
+    for _, S in solvers:
+        S.run()
     e1.record()
-    res = S.results()
-    ms = e0.elapsed_time(e1)
+    status = np.zeros(count, dtype=np.int32)
+    iters = np.zeros(count, dtype=np.int64)
+    lat = np.zeros(count)
+    err = np.zeros(count)
+    xs = [None] * count
     khz = bnc.wall_clock_khz()
-    err = max_err_vs_ones(S.xs)
-    converged = res["status"] == bnc.BNC_CONVERGED
+    for g, S in solvers:
+        res = S.results()
+        status[g] = res["status"]
+        iters[g] = res["iters"]
+        lat[g] = (res["t_end"].astype(np.float64) - res["t_start"].astype(np.float64)) / khz
+        err[g] = max_err_vs_ones(S.xs)
+        for j, i in enumerate(g):
+            xs[i] = S.xs[j]
+        S.close()
+    ms = e0.elapsed_time(e1)
+    converged = status == bnc.BNC_CONVERGED
     ok = converged & (err <= TARGET)
-    lat = (res["t_end"].astype(np.float64) - res["t_start"].astype(np.float64)) / khz
-    out = dict(ok=ok, converged=converged, iters=res["iters"].astype(np.int64), status=res["status"].copy(),
-               latency_ms=lat, total_ms=ms, xs=S.xs, err=err)
-    S.close()
-    return out
+    return dict(ok=ok, converged=converged, iters=iters, status=status, latency_ms=lat, total_ms=ms, xs=xs, err=err)
 
 
 TIE = 1.05              # costs within 5 % count as a tie (fewer words win)
@@ -238,17 +254,19 @@ def load(path: str, device="cuda") -> bnc.MLP:
     return bnc.MLP(torch.tensor(z["params"], device=device), torch.tensor(z["norm"], device=device))
 
 
-def dataset(count: int, config: int, n_lo: int = 32, n_hi: int = 256, lc_lo: float = 1.0, lc_hi: float = 60.0,
-            chunk: int = 4096, workers: int = 16, log=None):
+def dataset(count: int, config: int, n_lo: int = 32, n_hi: int = 512, lc_lo: float = 1.0, lc_hi: float = 60.0,
+            chunk: int = 4096, workers: int = 16, log=None, words_above: float | None = 1e15):
     """Generate, label and featurise `count` seeded randsvd systems in chunks
-    (binary64 entries, exact right-hand side A * ones).  Returns host arrays
-    F (count, 24), cls, steps and the per-chunk labelling statistics."""
+    (binary64 entries up to cond `words_above`, quad-double words above;
+    exact right-hand side A * ones).  Returns host arrays F (count, 24), cls
+    and steps."""
     import synth
     Fs, cs, ss = [], [], []
     t0 = time.perf_counter()
     for c0 in range(0, count, chunk):
         m = min(chunk, count - c0)
-        As, bs, exact, _ = synth.batch(m, n_lo, n_hi, lc_lo, lc_hi, config=config, workers=workers, first=c0)
+        As, bs, exact, _ = synth.batch(m, n_lo, n_hi, lc_lo, lc_hi, config=config, workers=workers, first=c0,
+                                       words_above=words_above)
         dA = [torch.from_numpy(a).cuda() for a in As]
         db = [torch.from_numpy(b).cuda() for b in bs]
         lab = label(dA, db)

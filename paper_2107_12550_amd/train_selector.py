@@ -4,9 +4,11 @@ and evaluate it against escalate-on-stagnation on a held-out stream.
   python -m paper_2107_12550_amd.train_selector --train 200000 --test 16384 \\
       --out model.npz --report report.json
 
-Training systems: seeded randsvd, n ~ U{32..256}, cond = 10^U(1, 60),
-binary64 entries, b = A * ones exact (seed stream 5); held-out systems the
-same law from seed stream 6.  Runs on one GPU; prints progress per chunk.
+Training systems: seeded randsvd, n ~ U{32..512}, cond = 10^U(1, 60),
+binary64 entries up to cond 1e15 and quad-double-word entries above (a
+binary64 copy cannot hold a larger condition), b = A * ones exact (seed
+stream 5); held-out systems the same law from seed stream 6.  Runs on one
+GPU; prints progress per chunk.
 """
 from __future__ import annotations
 
@@ -30,7 +32,9 @@ def main():
     ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--chunk", type=int, default=4096)
     ap.add_argument("--n-lo", type=int, default=32)
-    ap.add_argument("--n-hi", type=int, default=256)
+    ap.add_argument("--n-hi", type=int, default=512)
+    ap.add_argument("--words-above", type=float, default=1e15,
+                    help="conditions above this keep quad-double-word entries (0: all binary64)")
     ap.add_argument("--out", required=True)
     ap.add_argument("--report", required=True)
     args = ap.parse_args()
@@ -40,7 +44,7 @@ def main():
     workers = min(16, os.cpu_count() or 1)
     t0 = time.perf_counter()
     F, cls, steps = SEL.dataset(args.train, config=5, n_lo=args.n_lo, n_hi=args.n_hi, chunk=args.chunk,
-                                workers=workers, log=log)
+                                workers=workers, log=log, words_above=args.words_above or None)
     t_data = time.perf_counter() - t0
     log(f"[selector] training set: {F.shape[0]} systems, classes {np.bincount(cls, minlength=4).tolist()}")
     Ft = torch.tensor(F, device="cuda")
@@ -54,7 +58,8 @@ def main():
     labels = []
     for c0 in range(0, args.test, args.chunk):
         m = min(args.chunk, args.test - c0)
-        As, bs, exact, _ = synth.batch(m, args.n_lo, args.n_hi, 1.0, 60.0, config=6, workers=workers, first=c0)
+        As, bs, exact, _ = synth.batch(m, args.n_lo, args.n_hi, 1.0, 60.0, config=6, workers=workers, first=c0,
+                                       words_above=args.words_above or None)
         dA = [torch.from_numpy(a).cuda() for a in As]
         db = [torch.from_numpy(b).cuda() for b in bs]
         r = SEL.evaluate(net, dA, db)
@@ -80,7 +85,9 @@ def main():
     tot["under_predicted_fraction"] = float(np.mean(lp < lc))
     tot["heldout_accuracy"] = float(np.mean(lp == lc))
     tot["heldout_label_counts"] = np.bincount(lc, minlength=4).tolist()
-    report = dict(train_systems=int(F.shape[0]), train_class_counts=np.bincount(cls, minlength=4).tolist(),
+    report = dict(workload=dict(n_lo=args.n_lo, n_hi=args.n_hi, cond="10^U(1, 60)",
+                                quad_double_words_above=args.words_above or None, train=args.train, test=args.test),
+                  train_systems=int(F.shape[0]), train_class_counts=np.bincount(cls, minlength=4).tolist(),
                   train_accuracy=train_acc, loss_history=hist, data_seconds=t_data, heldout=tot)
     with open(args.report, "w") as f:
         json.dump(report, f, indent=1)

@@ -1,7 +1,7 @@
 """Autotuning of the batched refined solves (bnc_refine_batched).
 
 The batched kernel has two launch-shape knobs that leave every result
-unchanged: the LU panel width (4 or 8 columns staged in LDS) and the number
+unchanged: the LU panel width (4, 8 or 16 columns staged in LDS) and the number
 of threads per workgroup (64, 128, 256 or 512; one thread per row, so a
 workgroup takes systems up to that order, and smaller workgroups let more
 small systems run at once).  tune() times every variant that fits each size
@@ -19,7 +19,7 @@ import torch
 from . import bnc
 
 CLASSES = ((1, 64), (65, 128), (129, 256), (257, 512))
-PANELS = (4, 8)
+PANELS = (4, 8, 16)
 THREADS = (64, 128, 256, 512)
 
 

@@ -83,10 +83,12 @@ def _sum_exact(a, b):
 def _exact_matmul(n: int):
     """a @ b.T for slice matrices whose every partial sum is exact in
     binary64 (so any summation order gives the same result): a library GEMM
-    on the GPU when torch has one and the matrices are large, else numpy."""
+    on the GPU when torch has one and the matrices are large, else numpy
+    (also in a worker forked from a process that already uses the GPU)."""
     try:
         import torch
-        if n >= 512 and torch.cuda.is_available():
+        bad_fork = getattr(torch.cuda, "_is_in_bad_fork", lambda: False)()
+        if n >= 512 and not bad_fork and torch.cuda.is_available():
             def mm(a, b):
                 ta = torch.from_numpy(a).cuda()
                 tb = torch.from_numpy(b).cuda()
@@ -273,7 +275,10 @@ def _batch_one(args):
     n = int(g.integers(n_lo, n_hi + 1))
     cond = float(10.0 ** g.uniform(lc_lo, lc_hi))
     if words_above is not None and cond > words_above:
-        Ap = randsvd_words(n, cond, g)
+        # 150 bits below each row's scale hold conditions up to ~1e45; the
+        # rest get 180 (the most the 4 x 50-bit limbs of the formation
+        # take with headroom), which caps the stored condition near 1e54
+        Ap = randsvd_words(n, cond, g, bits=150 if cond <= 1e30 else 180)
     else:
         Ap = planes(randsvd(n, cond, g))
     b, exact = rhs_ones(Ap)

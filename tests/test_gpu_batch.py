@@ -182,7 +182,7 @@ def test_launch_variants_bitexact(P):
     r0 = ref.results()
     x0 = [x.cpu().numpy() for x in ref.xs]
     for nt in (64, 128, 256, 512):
-        for pw in (4, 8):
+        for pw in (4, 8, 16):
             say("variant threads", nt, "panel", pw)
             S = P.BatchSolver([dev(A) for A in As], [dev(b) for b in bs], K, ctol=CTOL, panel=pw, threads=nt)
             S.run()

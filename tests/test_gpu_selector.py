@@ -29,10 +29,14 @@ def P():
 
 def systems():
     out = []
-    sizes = [1, 2, 7, 33, 64, 100, 129, 200, 256]
+    sizes = [1, 2, 7, 33, 64, 100, 129, 200, 256, 257, 300, 512]
     for i, n in enumerate(sizes):
         kind = "uniform" if i % 2 else "randsvd"
         Ap, b, _ = synth.problem(kind, n, config=4, instance=i, cond=[1e2, 1e9, 1e15, 1e25][i % 4])
+        out.append((Ap, b))
+    # quad-double-word entries: the features read the leading words
+    for i, n in enumerate((90, 280)):
+        Ap, b, _ = synth.problem("randsvd_words", n, config=4, instance=40 + i, cond=1e40)
         out.append((Ap, b))
     g = np.random.default_rng(8)
     Z = g.uniform(-1, 1, (40, 40))

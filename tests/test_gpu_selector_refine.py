@@ -41,7 +41,7 @@ def net(P):
 
 def test_auto_matches_the_separate_entry_points(P, net):
     import torch
-    As, bs, exact, conds = synth.batch(48, 32, 256, 1.0, 60.0, config=8)
+    As, bs, exact, conds = synth.batch(48, 32, 512, 1.0, 60.0, config=8, words_above=1e15)
     dA = [torch.from_numpy(a).cuda() for a in As]
     db = [torch.from_numpy(b).cuda() for b in bs]
     F = P.features(dA, db)
@@ -56,14 +56,14 @@ def test_auto_matches_the_separate_entry_points(P, net):
         assert out["status"] == ref["status"] and out["iters"] == ref["iters"]
         assert out["final_words"] == ref["final_words"] and out["escalations"] == ref["escalations"]
         np.testing.assert_array_equal(host(out["x"]), host(ref["x"]))
-        if i % 12 == 0:
+        if i % 12 == 0 and As[i].shape[-1] <= 300:
             o = O.refine(As[i], bs[i], int(cls[i]) + 1, escalate=True, stag_ratio=0.5, ctol=2.0 ** -150)
             assert o["status"] == out["status"] and o["iters"] == out["iters"]
             np.testing.assert_array_equal(host(out["x"]), o["x"])
 
 
 def test_auto_above_the_feature_limit_starts_at_two_words(P, net):
-    n = 300
+    n = 600
     Ap, b, _ = synth.problem("randsvd", n, config=8, instance=1, cond=1e8)
     out = P.refine(dev(Ap), dev(b), P.BNC_AUTO, selector=net, escalate=True, stagnation_ratio=0.5)
     assert out["first_words"] == 2 and out["status"] == P.BNC_CONVERGED
