@@ -278,6 +278,10 @@ __device__ __forceinline__ void resid_row_terms(int n, const double *__restrict_
             if (j < n) {
 #pragma unroll
                 for (int u = 0; u < AW; ++u) {
+                    // a word that is zero on every row of the wave adds
+                    // nothing (its products are exact zeros): skipped
+                    if (AW > 1 && !__any(a[u] != 0.0))
+                        continue;
                     double tt[8];
 #pragma unroll
                     for (int w = 0; w < 4; ++w) {
