@@ -364,7 +364,11 @@ int32_t bnc_refine_batched_default_slots(int32_t factor_words, int32_t panel, in
  * Batched mixed-precision iterative refinement: bnc_refine (Kouya 2021,
  * Sec. 2, Listing 1) on `count` independent systems of order 1..512 in one
  * persistent launch.  Each system's x, status and corrections equal those of
- * bnc_refine on that system alone, bit for bit.
+ * bnc_refine on that system alone, bit for bit, when the residual test is
+ * off (rtol = 0, the forward test deciding); with rtol > 0 its 2-norms are
+ * summed in another fixed order than bnc_refine's (one workgroup's tree), so
+ * a system whose residual norm lies within a rounding of the threshold can
+ * stop one correction apart.
  *   count      number of systems
  *   n          device int64[count]: orders
  *   a_words    device int32[count]: words per entry of A[s], 1 (binary64)

@@ -255,18 +255,18 @@ def load(path: str, device="cuda") -> bnc.MLP:
 
 
 def dataset(count: int, config: int, n_lo: int = 32, n_hi: int = 512, lc_lo: float = 1.0, lc_hi: float = 60.0,
-            chunk: int = 4096, workers: int = 16, log=None, words_above: float | None = 1e15):
+            chunk: int = 4096, workers: int = 16, log=None, words_above: float | None = 1e15, first: int = 0):
     """Generate, label and featurise `count` seeded randsvd systems in chunks
     (binary64 entries up to cond `words_above`, quad-double words above;
-    exact right-hand side A * ones).  Returns host arrays F (count, 24), cls
-    and steps."""
+    exact right-hand side A * ones), systems first .. first + count - 1 of
+    the seed stream.  Returns host arrays F (count, 24), cls and steps."""
     import synth
     Fs, cs, ss = [], [], []
     t0 = time.perf_counter()
     for c0 in range(0, count, chunk):
         m = min(chunk, count - c0)
-        As, bs, exact, _ = synth.batch(m, n_lo, n_hi, lc_lo, lc_hi, config=config, workers=workers, first=c0,
-                                       words_above=words_above)
+        As, bs, exact, _ = synth.batch(m, n_lo, n_hi, lc_lo, lc_hi, config=config, workers=workers,
+                                       first=first + c0, words_above=words_above)
         dA = [torch.from_numpy(a).cuda() for a in As]
         db = [torch.from_numpy(b).cuda() for b in bs]
         lab = label(dA, db)

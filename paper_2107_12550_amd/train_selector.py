@@ -4,6 +4,10 @@ and evaluate it against escalate-on-stagnation on a held-out stream.
   python -m paper_2107_12550_amd.train_selector --train 200000 --test 16384 \\
       --out model.npz --report report.json
 
+The labelled training set can also be made in shards (each a separate
+run: --shard-out shard.npz --first F --train C labels systems F..F+C-1 of
+the training stream) and trained from them (--shards a.npz b.npz ...).
+
 Training systems: seeded randsvd, n ~ U{32..512}, cond = 10^U(1, 60),
 binary64 entries up to cond 1e15 and quad-double-word entries above (a
 binary64 copy cannot hold a larger condition), b = A * ones exact (seed
@@ -35,17 +39,35 @@ def main():
     ap.add_argument("--n-hi", type=int, default=512)
     ap.add_argument("--words-above", type=float, default=1e15,
                     help="conditions above this keep quad-double-word entries (0: all binary64)")
-    ap.add_argument("--out", required=True)
-    ap.add_argument("--report", required=True)
+    ap.add_argument("--out")
+    ap.add_argument("--report")
+    ap.add_argument("--first", type=int, default=0, help="first training system (with --shard-out)")
+    ap.add_argument("--shard-out", help="label --train systems from --first, save them here and stop")
+    ap.add_argument("--shards", nargs="*", help="train on these labelled shards instead of labelling now")
     args = ap.parse_args()
+    if not args.shard_out and not (args.out and args.report):
+        ap.error("--out and --report are required unless --shard-out is given")
     import torch
 
     from . import selector as SEL
     workers = min(16, os.cpu_count() or 1)
     t0 = time.perf_counter()
-    F, cls, steps = SEL.dataset(args.train, config=5, n_lo=args.n_lo, n_hi=args.n_hi, chunk=args.chunk,
-                                workers=workers, log=log, words_above=args.words_above or None)
-    t_data = time.perf_counter() - t0
+    if args.shards:
+        parts = [np.load(p, allow_pickle=False) for p in args.shards]
+        F = np.concatenate([z["F"] for z in parts])
+        cls = np.concatenate([z["cls"] for z in parts])
+        steps = np.concatenate([z["steps"] for z in parts])
+        t_data = float(sum(float(z["seconds"]) for z in parts))
+        args.train = int(sum(int(z["count"]) for z in parts))
+    else:
+        F, cls, steps = SEL.dataset(args.train, config=5, n_lo=args.n_lo, n_hi=args.n_hi, chunk=args.chunk,
+                                    workers=workers, log=log, words_above=args.words_above or None,
+                                    first=args.first)
+        t_data = time.perf_counter() - t0
+        if args.shard_out:
+            np.savez(args.shard_out, F=F, cls=cls, steps=steps, seconds=t_data, count=args.train, first=args.first)
+            log(f"[selector] shard of {args.train} systems from {args.first} saved to {args.shard_out}")
+            return
     log(f"[selector] training set: {F.shape[0]} systems, classes {np.bincount(cls, minlength=4).tolist()}")
     Ft = torch.tensor(F, device="cuda")
     net, hist = SEL.train(Ft, torch.tensor(cls), torch.tensor(steps), epochs=args.epochs, log=log)

@@ -67,6 +67,14 @@ def test_workspace_queries():
     assert P.getrf_workspace_size(2, 16385) == 0 and P.getrs_workspace_size(0, 8) == 0
     assert 0 < P.residual_workspace_size(64) < P.residual_workspace_size(128)
     assert P.residual_workspace_size(0) == 0
+    # batched slots: K planes of NT^2 plus K of NT per workgroup, after a 256-byte queue counter
+    L.bnc_refine_batched_workspace_size.restype = ctypes.c_size_t
+    for K, nt in ((3, 256), (2, 512), (4, 64)):
+        assert L.bnc_refine_batched_workspace_size(K, 10, nt) == 10 * (K * nt * nt + K * nt) * 8 + 256
+    assert L.bnc_refine_batched_workspace_size(3, 10, 0) == L.bnc_refine_batched_workspace_size(3, 10, 256)
+    assert L.bnc_refine_batched_workspace_size(3, 10, 100) == 0
+    assert L.bnc_refine_batched_workspace_size(5, 10, 256) == 0
+    assert L.bnc_features_workspace_size(4) == 256 + 4 * 512 * 512 * 8
     # pointers are never dereferenced on these paths: fake non-NULL addresses
     A, ip, inf = 1 << 20, 2 << 20, 3 << 20
     need = P.getrf_workspace_size(3, 8)
