@@ -68,6 +68,10 @@ extern "C" {
 #define BNC_TIMED_OUT 6 /* bnc_refine_async: a bounded wait between
                            workgroups gave up (bnc_refine returns
                            BNC_ERR_TIMEOUT instead); x is invalid */
+#define BNC_SPLIT_RANGE 7 /* bnc_refine_async with ozaki_slices > 0: a row
+                           or column scale fell below the split scheme's
+                           exact range (bnc_getrf_ozaki info -3; bnc_refine
+                           refactors in the plain form instead); x = 0 */
 
 /*
  * LU decomposition with partial pivoting, in place: P A = L U (Kouya 2021,
@@ -111,8 +115,16 @@ int bnc_getrf_qd(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, 
  * row/column scale (5 slices of 22 bits match double-double, 5-6 of 21
  * come near triple-double, 11 of 20 quad-double); bnc_refine recovers full
  * accuracy.
- * Deterministic, and independent of tiling (every group sum is exact while
- * the row and column scales stay above about 2^-700).
+ * Deterministic, and independent of tiling: every slice and every group
+ * sum is exact while every nonzero row and column scale (the exponent E
+ * with max|leading word| < 2^E) is at least E_min(K, slices) = max(ceil(
+ * ((slices + 1) beta - 1022) / 2), slices beta - 1022), which keeps every
+ * slice and product grid at 2^-1022 or above (-456 for 2 words and 4
+ * slices).  When a row of L21 or a column of U12 falls below it, the
+ * factorisation still runs but reports info = -3 (if it is otherwise
+ * complete and nonsingular): its factors are not those of the exact scheme.
+ * bnc_refine then refactors in the plain form; bnc_refine_async ends with
+ * BNC_SPLIT_RANGE.
  *   factor_words  K in 1..4;  slices  1..12
  *   the remaining arguments as bnc_getrf_* (argument errors are numbered
  *   from n = 3); the workspace, bnc_getrf_workspace_size(K, slices, n)
@@ -327,7 +339,8 @@ int bnc_refine(int64_t n, int32_t a_words, const double *A, int64_t lda, int64_t
  *            ends the loop with BNC_STAGNATED
  *   result   DEVICE bnc_refine_result, valid once the stream has reached
  *            the end of the call; a timed-out bounded wait gives status
- *            BNC_TIMED_OUT
+ *            BNC_TIMED_OUT, a split factorisation out of its exact range
+ *            BNC_SPLIT_RANGE
  * x, status, corrections and norms equal those of bnc_refine bit for bit.
  * The first factorisation on a device creates the library's look-ahead
  * stream: make one call outside a capture first.

@@ -70,6 +70,8 @@ def lib() -> ctypes.CDLL:
         L.orc_gemm.argtypes = [ctypes.c_int, I64, I64, I64, P, I64, I64, P, I64, I64, P, I64, I64]
         L.orc_oz_beta.argtypes = [ctypes.c_int, ctypes.c_int]
         L.orc_oz_beta.restype = ctypes.c_int
+        L.orc_oz_emin.argtypes = [ctypes.c_int, ctypes.c_int]
+        L.orc_oz_emin.restype = ctypes.c_int
         L.orc_oz_update.argtypes = [ctypes.c_int, ctypes.c_int, I64, I64, I64, P, I64, I64, P, I64, I64,
                                     P, I64, I64, P]
         L.orc_oz_update.restype = ctypes.c_int
@@ -241,14 +243,22 @@ def oz_update(K: int, s: int, L, U, C):
     nc = U.shape[1]
     acc = np.empty((s, nc, m))
     rc = lib().orc_oz_update(K, s, m, nc, kb, _p(L), m, kb * m, _p(U), kb, nc * kb, _p(C), m, nc * m, _p(acc))
-    if rc:
+    if rc < 0:
         raise ValueError("oz_update: kb or s out of range")
     return C, acc
 
 
+def oz_emin(K: int, s: int) -> int:
+    """Smallest nonzero row/column scale for which the split scheme with s
+    slices keeps every slice and product grid at 2^-1022 or above."""
+    return int(lib().orc_oz_emin(K, s))
+
+
 def getrf_ozaki(K: int, A: np.ndarray, s: int, nb: int = 64):
     """Blocked PA = LU (panel width nb) whose trailing updates use the split
-    scheme with s slices; returns (LU, ipiv, info)."""
+    scheme with s slices; returns (LU, ipiv, info), info = -3 when a
+    nonsingular factorisation met a row of L21 or column of U12 whose scale
+    is below oz_emin(K, s) (the scheme was not exact there)."""
     LU = _c(A).copy()
     n = LU.shape[1]
     ipiv = np.zeros(n, dtype=np.int64)
@@ -368,7 +378,10 @@ def refine(A: np.ndarray, b: np.ndarray, K: int, max_iter: int = 30,
     while True:
         LU = stage(kc, A)
         if ozaki and kc == K:
-            LU, ipiv, info = getrf_ozaki(kc, LU, ozaki)
+            LU0 = LU
+            LU, ipiv, info = getrf_ozaki(kc, LU0, ozaki)
+            if info == -3:  # the split scheme left its exact range: the plain form
+                LU, ipiv, info = getrf(kc, LU0)
         else:
             LU, ipiv, info = getrf(kc, LU)
         if not info or not escalate or kc == 4:

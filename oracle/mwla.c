@@ -562,6 +562,22 @@ static int oz_beta(int K, int s)
 
 int orc_oz_beta(int K, int s) { return (K < 1 || K > KMAX || s < 1 || s > OZ_SMAX) ? -1 : oz_beta(K, s); }
 
+/* Smallest row/column scale for which every slice (grid 2^(E - (q+1)
+ * beta), q < s) and every kept product (grid 2^(E + F - (d+2) beta), d < s)
+ * stays on a grid of 2^-1022 or above when both scales reach it: the
+ * larger of ceil(((s+1) beta - 1022) / 2) and s beta - 1022.  Below it a
+ * product could round or flush, so the scheme would not be exact. */
+static int oz_emin(int K, int s)
+{
+    int b = oz_beta(K, s);
+    int x = (s + 1) * b - 1022;
+    int half = x >= 0 ? (x + 1) / 2 : -((-x) / 2);
+    int own = s * b - 1022;
+    return half > own ? half : own;
+}
+
+int orc_oz_emin(int K, int s) { return (K < 1 || K > KMAX || s < 1 || s > OZ_SMAX) ? -100000 : oz_emin(K, s); }
+
 
 /* Row/column scale: smallest E with |x_0| < 2^E for every leading word
  * x_0 of the m entries (stride inc); 0 when all are zero. */
@@ -613,7 +629,8 @@ int32_t orc_oz_scale(int64_t m, const double *x0) { return oz_scale(x0, m, 1); }
  * leading dimension ldl, plane stride ldpl); U: K planes kb x nc (ldu,
  * ldpu); C: K planes m x nc (ldc, ldpc).  acc (may be NULL) receives the
  * group sums, acc[(d*nc + j)*m + i].  Returns -1 when kb or s is out of
- * range, else 0.
+ * range, 1 when a nonzero row of L or column of U has its scale below
+ * oz_emin (the sums are then not guaranteed exact), else 0.
  */
 int orc_oz_update(int K, int s, int64_t m, int64_t nc, int64_t kb, const double *L, int64_t ldl, int64_t ldpl,
                   const double *U, int64_t ldu, int64_t ldpu, double *C, int64_t ldc, int64_t ldpc, double *acc)
@@ -624,11 +641,14 @@ int orc_oz_update(int K, int s, int64_t m, int64_t nc, int64_t kb, const double 
         return 0;
     double *Ls = malloc(sizeof(double) * (size_t)(s * m * (kb ? kb : 1)));
     double *Us = malloc(sizeof(double) * (size_t)(s * nc * (kb ? kb : 1)));
+    const int emin = oz_emin(K, s);
+    int low = 0; /* a scale below emin (a zero row or column has scale 0) */
     /* slices of the rows of L: Ls[(q*kb + k)*m + i] */
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) reduction(| : low)
     for (int64_t i = 0; i < m; ++i) {
         double v[WMAX], o[OZ_SMAX];
         int E = oz_scale(L + i, kb, ldl);
+        low |= E < emin;
         for (int64_t k = 0; k < kb; ++k) {
             for (int w = 0; w < K; ++w)
                 v[w] = L[w * ldpl + k * ldl + i];
@@ -638,10 +658,11 @@ int orc_oz_update(int K, int s, int64_t m, int64_t nc, int64_t kb, const double 
         }
     }
     /* slices of the columns of U: Us[(q*nc + j)*kb + k] */
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) reduction(| : low)
     for (int64_t j = 0; j < nc; ++j) {
         double v[WMAX], o[OZ_SMAX];
         int F = oz_scale(U + j * ldu, kb, 1);
+        low |= F < emin;
         for (int64_t k = 0; k < kb; ++k) {
             for (int w = 0; w < K; ++w)
                 v[w] = U[w * ldpu + j * ldu + k];
@@ -673,7 +694,7 @@ int orc_oz_update(int K, int s, int64_t m, int64_t nc, int64_t kb, const double 
         }
     free(Ls);
     free(Us);
-    return 0;
+    return low ? 1 : 0;
 }
 
 /*
@@ -683,13 +704,17 @@ int orc_oz_update(int K, int s, int64_t m, int64_t nc, int64_t kb, const double 
  * multipliers, rank-1 updates inside the panel, each entry's updates in
  * increasing k), then U12 <- L11^-1 A12 by column-oriented forward
  * substitution (increasing k), then the split update of A22.  Pivot rule,
- * ipiv and info as orc_getrf.  Returns -2 on bad nb or s.
+ * ipiv and info as orc_getrf, except that a factorisation with no zero
+ * pivot whose split updates met a row or column scale below oz_emin
+ * returns -3 (its factors are not those of the exact scheme).  Returns -2
+ * on bad nb or s.
  */
 int64_t orc_getrf_ozaki(int K, int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int64_t nb, int s)
 {
     if (nb < 1 || nb > OZ_KBMAX || s < 1 || s > OZ_SMAX)
         return -2;
     int64_t info = 0;
+    int low = 0;
     double best[WMAX], v[WMAX], r[WMAX], o[WMAX];
     for (int64_t j0 = 0; j0 < n; j0 += nb) {
         int64_t jb = n - j0 < nb ? n - j0 : nb;
@@ -750,10 +775,10 @@ int64_t orc_getrf_ozaki(int K, int64_t n, double *A, int64_t lda, int64_t ldp, i
                     store(K, A, lda, ldp, i, j, q);
                 }
             }
-        orc_oz_update(K, s, n - je, n - je, jb, &AT(A, je, j0, 0), lda, ldp, &AT(A, j0, je, 0), lda, ldp,
-                      &AT(A, je, je, 0), lda, ldp, NULL);
+        low |= orc_oz_update(K, s, n - je, n - je, jb, &AT(A, je, j0, 0), lda, ldp, &AT(A, j0, je, 0), lda, ldp,
+                             &AT(A, je, je, 0), lda, ldp, NULL) == 1;
     }
-    return info;
+    return (info == 0 && low) ? -3 : info;
 }
 
 /* ---------------------------------------------------------------------- */

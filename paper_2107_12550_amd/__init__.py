@@ -18,6 +18,7 @@ from .bnc import (  # noqa: F401
     BNC_NONFINITE,
     BNC_SINGULAR,
     BNC_STAGNATED,
+    BNC_SPLIT_RANGE,
     BNC_TIMED_OUT,
     OP_ADD,
     OP_FMS,

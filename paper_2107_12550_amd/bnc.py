@@ -19,6 +19,7 @@ lib_path = os.path.join(_HERE, "libbnc.so")
 BNC_CONVERGED, BNC_MAX_ITER, BNC_SINGULAR, BNC_NONFINITE, BNC_BAD_SIZE, BNC_STAGNATED = 0, 1, 2, 3, 4, 5
 BNC_AUTO = 0
 BNC_TIMED_OUT = 6
+BNC_SPLIT_RANGE = 7
 BNC_ERR_HIP, BNC_ERR_UNSUPPORTED, BNC_ERR_WORKSPACE, BNC_ERR_TIMEOUT = -100, -101, -102, -103
 OP_FMS, OP_MUL, OP_ADD, OP_RECIP, OP_ROUND4 = 0, 1, 2, 3, 4
 _SUFFIX = {1: "d", 2: "dd", 3: "td", 4: "qd"}

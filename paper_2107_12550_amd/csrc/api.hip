@@ -793,6 +793,8 @@ const char *bnc_status_string(int32_t status)
         return "stagnated";
     case BNC_TIMED_OUT:
         return "timed_out";
+    case BNC_SPLIT_RANGE:
+        return "split_range";
     default:
         return "unknown";
     }

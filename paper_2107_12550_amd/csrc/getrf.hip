@@ -534,6 +534,8 @@ __global__ void __launch_bounds__(PANEL_THREADS)
                 mx = fmax(mx, s_mx[t * R + r]);
             const int E = oz_scale(mx);
             const int beta = oz_beta(K, ozs);
+            if (mx != 0.0 && E < oz_emin(K, ozs))  // below the exact range: info -3 at the end
+                __hip_atomic_store(abort_flag + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             double *out = SL + (row - j0 - jb);
             for (int c = cb; c < ce; ++c) {
                 double v[K];
@@ -627,7 +629,8 @@ __global__ void __launch_bounds__(PANEL_THREADS)
 template <int K, bool TRSM>
 __global__ void __launch_bounds__(64)
     k_laswp_trsm(double *__restrict__ A, int64_t lda, int64_t ldp, int64_t j0, int jb, int64_t col0,
-                 const int64_t *__restrict__ pairs, int ozs, double *__restrict__ SU, int64_t ldsu)
+                 const int64_t *__restrict__ pairs, int ozs, double *__restrict__ SU, int64_t ldsu,
+                 int *__restrict__ ozlow)
 {
     const int64_t c = col0 + blockIdx.x;
     const int lane = threadIdx.x;
@@ -711,6 +714,8 @@ __global__ void __launch_bounds__(64)
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1)
             mx = fmax(mx, __shfl_xor(mx, off, 64));
+        if (lane == 0 && mx != 0.0 && oz_scale(mx) < oz_emin(K, ozs))
+            __hip_atomic_store(ozlow, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (lane < jb)
             oz_cut_store<K>(u, oz_scale(mx), ozs, oz_beta(K, ozs), SU + (int64_t)lane * ldsu + blockIdx.x,
                             (int64_t)jb * ldsu);
@@ -871,15 +876,18 @@ static size_t panel_lds_bytes(int K, int jb, int R)
     return ((size_t)K * jb * (R + 1) + 3 * (size_t)K * jb) * sizeof(double);
 }
 
-// start of a factorisation: clear the abort flag, and set words [0, nw) of
-// the first panel's exchange buffer to XSENT
+// start of a factorisation: clear the abort flag and the split form's
+// range flag after it, and set words [0, nw) of the first panel's exchange
+// buffer to XSENT
 __global__ void k_xbuf_init(uint64_t *x, int64_t nw, int *abort_flag)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nw; i += stride)
         x[i] = (uint64_t)XSENT;
-    if (blockIdx.x == 0 && threadIdx.x == 0)
-        *abort_flag = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        abort_flag[0] = 0;
+        abort_flag[1] = 0;
+    }
 }
 
 // the timeout test hook: every poll of the factorisation gives up at once
@@ -889,11 +897,17 @@ __global__ void k_xbuf_raise(int *abort_flag)
         *abort_flag = 1;
 }
 
-// end of a factorisation: a failed panel exchange makes info -1
+// end of a factorisation: a failed panel exchange makes info -1; else a
+// split-form row or column scale below the exact range makes a nonsingular
+// factorisation's info -3
 __global__ void k_abort_check(const int *abort_flag, int64_t *info)
 {
-    if (blockIdx.x == 0 && threadIdx.x == 0 && *abort_flag)
-        *info = -1;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (abort_flag[0])
+            *info = -1;
+        else if (abort_flag[1] && *info == 0)
+            *info = -3;
+    }
 }
 
 // Side stream and four events per device for the look-ahead: the panels
@@ -954,7 +968,7 @@ static int lookahead_get(LookAhead *&la)
 
 template <int K>
 int oz_split_cols_run(const double *A, int64_t lda, int64_t ldp, int64_t j0, int kb, int64_t c0, int64_t nc, int s,
-                      double *SU, int64_t ldsu, hipStream_t st);
+                      double *SU, int64_t ldsu, int *ozlow, hipStream_t st);
 template <int K>
 int oz_update_run(int s, bool thin, double *A, int64_t lda, int64_t ldp, int64_t r0, int64_t c0, int64_t m,
                   int64_t nc, int kb, const double *SL, int64_t ldsl, const double *SU, int64_t ldsu, hipStream_t st);
@@ -1053,10 +1067,10 @@ int getrf_run(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int
         const int ozs = osu ? oz : 0;
         if (trsm)
             hipLaunchKernelGGL((k_laswp_trsm<K, true>), dim3((unsigned)nc), dim3(64), 0, st, A, lda, ldp, j0, jb,
-                               c0, pr, ozs, osu, n);
+                               c0, pr, ozs, osu, n, abort_flag + 1);
         else
             hipLaunchKernelGGL((k_laswp_trsm<K, false>), dim3((unsigned)nc), dim3(64), 0, st, A, lda, ldp, j0, jb,
-                               c0, pr, 0, nullptr, n);
+                               c0, pr, 0, nullptr, n, abort_flag + 1);
         BNC_LAUNCH_CHECK();
         return BNC_OK;
     };
@@ -1068,7 +1082,7 @@ int getrf_run(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int
         if (m <= 0 || nc <= 0)
             return BNC_OK;
         if (oz) {
-            int rc2 = split ? BNC_OK : oz_split_cols_run<K>(A, lda, ldp, j0, jb, c0, nc, oz, SU + (c0 - r0), n, st);
+            int rc2 = split ? BNC_OK : oz_split_cols_run<K>(A, lda, ldp, j0, jb, c0, nc, oz, SU + (c0 - r0), n, abort_flag + 1, st);
             if (rc2)
                 return rc2;
             // profiling brackets the big-tile launches only: the thin ones sit
@@ -1139,7 +1153,7 @@ int getrf_run(int64_t n, double *A, int64_t lda, int64_t ldp, int64_t *ipiv, int
         if ((rc = swaps(j0, jb, 0, j0, pr, false, nullptr, s)) ||
             (rc = swaps(j0, jb, cr, n - cr, pr, true, nullptr, s)))
             return rc;
-        if (oz && cr < n && (rc = oz_split_cols_run<K>(A, lda, ldp, j0, jb, cr, n - cr, oz, SU + nbn, n, s)))
+        if (oz && cr < n && (rc = oz_split_cols_run<K>(A, lda, ldp, j0, jb, cr, n - cr, oz, SU + nbn, n, abort_flag + 1, s)))
             return rc;
         BNC_HIP(hipStreamWaitEvent(s, la->look, 0));
         if ((rc = update(cn, cr, n - cn, n - cr, j0, jb, false, SL, oz != 0, s)))

@@ -48,7 +48,7 @@ constexpr int OZ_SPLIT_Q = 4;   // threads per column
 template <int K>
 __global__ void __launch_bounds__(OZ_SPLIT_V *OZ_SPLIT_Q)
     k_oz_split_cols(const double *__restrict__ A, int64_t lda, int64_t ldp, int64_t j0, int kb, int64_t c0,
-                    int64_t nc, int s, double *__restrict__ SU, int64_t ldsu)
+                    int64_t nc, int s, double *__restrict__ SU, int64_t ldsu, int *__restrict__ ozlow)
 {
     __shared__ double smax[OZ_SPLIT_Q][OZ_SPLIT_V];
     const int v = threadIdx.x % OZ_SPLIT_V, qt = threadIdx.x / OZ_SPLIT_V;
@@ -69,6 +69,8 @@ __global__ void __launch_bounds__(OZ_SPLIT_V *OZ_SPLIT_Q)
         mx = fmax(mx, smax[t][v]);
     const int F = oz_scale(mx);
     const int beta = oz_beta(K, s);
+    if (qt == 0 && mx != 0.0 && F < oz_emin(K, s))  // below the exact range: info -3 at the end
+        __hip_atomic_store(ozlow, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     for (int k = k0; k < k1; ++k) {
         double w4[K];
 #pragma unroll
@@ -216,12 +218,12 @@ size_t oz_slices_bytes(int64_t n)
 
 template <int K>
 int oz_split_cols_run(const double *A, int64_t lda, int64_t ldp, int64_t j0, int kb, int64_t c0, int64_t nc, int s,
-                      double *SU, int64_t ldsu, hipStream_t st)
+                      double *SU, int64_t ldsu, int *ozlow, hipStream_t st)
 {
     if (nc <= 0)
         return BNC_OK;
     hipLaunchKernelGGL(k_oz_split_cols<K>, dim3((unsigned)ceil_div(nc, OZ_SPLIT_V)), dim3(OZ_SPLIT_V * OZ_SPLIT_Q), 0,
-                       st, A, lda, ldp, j0, kb, c0, nc, s, SU, ldsu);
+                       st, A, lda, ldp, j0, kb, c0, nc, s, SU, ldsu, ozlow);
     BNC_LAUNCH_CHECK();
     return BNC_OK;
 }
@@ -288,7 +290,7 @@ int oz_update_run(int s, bool thin, double *A, int64_t lda, int64_t ldp, int64_t
 
 #define OZ_INST(K)                                                                                                   \
     template int oz_split_cols_run<K>(const double *, int64_t, int64_t, int64_t, int, int64_t, int64_t, int,        \
-                                      double *, int64_t, hipStream_t);                                              \
+                                      double *, int64_t, int *, hipStream_t);                                       \
     template int oz_update_run<K>(int, bool, double *, int64_t, int64_t, int64_t, int64_t, int64_t, int64_t, int,   \
                                   const double *, int64_t, const double *, int64_t, hipStream_t);
 OZ_INST(1)

@@ -29,6 +29,21 @@ __host__ __device__ constexpr int oz_beta(int K, int s)
     return 1;
 }
 
+// Smallest row (column) scale E for which the split scheme stays exact:
+// slice q of a row with scale E sits on the grid 2^(E - (q+1) beta) and a
+// product of group d on 2^(E + F - (d+2) beta), so with both scales at
+// least this bound every slice grid and every product grid, down to group
+// s - 1, is at least 2^-1022 (normal binary64, no flush or rounding).  A
+// nonzero row or column below it makes the factorisation report info = -3.
+__host__ __device__ constexpr int oz_emin(int K, int s)
+{
+    const int b = oz_beta(K, s);
+    const int x = (s + 1) * b - 1022;                 // E + F must reach this
+    const int half = x >= 0 ? (x + 1) / 2 : -((-x) / 2);  // ceil(x / 2)
+    const int own = s * b - 1022;
+    return half > own ? half : own;
+}
+
 // Exponent e with |x| <= mx < 2^e for the largest leading word mx of a row
 // (column); 0 for an all-zero row.
 __device__ __forceinline__ int oz_scale(double mx)

@@ -865,6 +865,10 @@ int refine_drive(int K0, int64_t n, int aw, const double *A, int64_t lda, int64_
     int64_t info = 0;
     if ((rc = factor(o->ozaki_slices, &info)))
         return rc;
+    // the split scheme left its exact range (a row or column scale too
+    // small for its slice products): the same words in the plain form
+    if (info == -3 && (rc = factor(0, &info)))
+        return rc;
     while (info > 0 && o->escalate && kc < 4) {
         ++kc;
         ++res->escalations;
@@ -994,7 +998,7 @@ __global__ void k_async_factored(Scal *sc)
 {
     if (blockIdx.x == 0 && threadIdx.x == 0 && !sc->done && sc->info != 0) {
         sc->done = 1;
-        sc->status = sc->info > 0 ? BNC_SINGULAR : BNC_TIMED_OUT;
+        sc->status = sc->info > 0 ? BNC_SINGULAR : sc->info == -3 ? BNC_SPLIT_RANGE : BNC_TIMED_OUT;
     }
 }
 

@@ -102,3 +102,42 @@ def test_ozaki_argument_errors(P):
     with pytest.raises(P.BncError):
         P.refine(torch.zeros((1, 4, 4), dtype=torch.float64, device="cuda"),
                  torch.zeros((4, 4), dtype=torch.float64, device="cuda"), 3, ozaki=13)
+
+
+def test_split_range_reported_and_refinement_falls_back(P):
+    """Below the split scheme's exact range (U12 column scales under
+    oz_emin, the matrix scaled by 2^(oz_emin - 20)) the split factorisation
+    reports info = -3, as the oracle's does; bnc_refine then factors in the
+    plain form, bit for bit the oracle's refinement (which does the same),
+    and bnc_refine_async ends with BNC_SPLIT_RANGE.  Scaled well above the
+    bound nothing is reported and the factors equal the oracle's."""
+    import torch
+    K, s, n = 2, 4, 100
+    Ap, b, exact = synth.problem("uniform", n, config=1, instance=77)
+    assert exact
+    e = O.oz_emin(K, s)
+    low, ok = np.ldexp(Ap, e - 20), np.ldexp(Ap, e + 20)
+    bl = np.ldexp(b, e - 20)
+    say("split range: factorisations")
+    dA = dev(O.stage(K, low))
+    _, dinfo = P.getrf_ozaki(K, s, dA)
+    assert int(host(dinfo)[0]) == -3
+    LUo, ipo, info_o = O.getrf_ozaki(K, O.stage(K, ok), s)
+    dA = dev(O.stage(K, ok))
+    dip, dinfo = P.getrf_ozaki(K, s, dA)
+    assert int(host(dinfo)[0]) == info_o == 0
+    np.testing.assert_array_equal(host(dip), ipo)
+    np.testing.assert_array_equal(host(dA), LUo)
+    say("split range: refinement")
+    ref = O.refine(low, bl, K, ozaki=s)
+    out = P.refine(dev(low), dev(bl), K, ozaki=s)
+    assert out["status"] == ref["status"] == O.CONVERGED and out["iters"] == ref["iters"]
+    np.testing.assert_array_equal(host(out["x"]), ref["x"])
+    say("split range: asynchronous refinement")
+    x = torch.empty((4, n), dtype=torch.float64, device="cuda")
+    res = torch.zeros(P.refine_result_bytes(), dtype=torch.uint8, device="cuda")
+    work = torch.empty(P.refine_workspace_size(n, K), dtype=torch.uint8, device="cuda")
+    P.refine_async(dev(low), dev(bl), K, res, x, work, ozaki=s)
+    r = P.refine_result(res)
+    assert r["status"] == P.BNC_SPLIT_RANGE
+    assert not host(x).any()

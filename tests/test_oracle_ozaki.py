@@ -230,3 +230,68 @@ def test_refinement_on_split_factor_reaches_quad_double(K, s, cond):
     assert r["status"] == O.CONVERGED
     err = max(abs(X.value(r["x"][:, i]) - 1) for i in range(130))
     assert err <= Fraction(10) ** -60
+
+
+# ---- the exact range of the scheme ------------------------------------------
+
+@pytest.mark.parametrize("K,s", [(1, 3), (2, 4), (2, 5), (3, 7), (4, 11), (4, 16)])
+def test_exact_range_bound_is_the_tightest_symmetric_one(K, s):
+    """oz_emin(K, s) is the smallest scale E such that two scales at E keep
+    every slice grid 2^(E - (q+1) beta), q < s, and every kept product grid
+    2^(E + F - (d+2) beta), d < s, at 2^-1022 or above; one below it does
+    not.  Written out from the grids, not from the closed form."""
+    b = O.oz_beta(K, s)
+    e = O.oz_emin(K, s)
+
+    def normal(E, F):
+        return (all(E - (q + 1) * b >= -1022 and F - (q + 1) * b >= -1022 for q in range(s))
+                and all(E + F - (d + 2) * b >= -1022 for d in range(s)))
+    assert normal(e, e)
+    assert not normal(e - 1, e - 1)
+    assert normal(e, 0) and normal(0, e)  # one side larger only helps
+
+
+@pytest.mark.parametrize("K,s", [(2, 4), (3, 5), (4, 11)])
+def test_group_sums_are_exact_at_the_range_bound(K, s):
+    """Rows and columns scaled (by exact powers of two) to scale oz_emin:
+    every group sum is still the rational sum of its slice products."""
+    g = np.random.default_rng(940 + K + 17 * s)
+    m, kb, nc = 2, 64, 2
+    e = O.oz_emin(K, s)
+    L, U, C = blocks(g, K, m, kb, nc, spread=0)
+    L[0] = 1.0 - 2.0 ** -53
+    U[0] = 1.0 - 2.0 ** -53
+    L, U = np.ldexp(L, e), np.ldexp(U, e)
+    _, acc = O.oz_update(K, s, L, U, C)
+    for i in range(m):
+        E = O.oz_scale(L[0, :, i])
+        assert E == e
+        Ls, _ = O.oz_slices(K, s, L[:, :, i], E)
+        for j in range(nc):
+            Fc = O.oz_scale(U[0, j, :])
+            Us, _ = O.oz_slices(K, s, U[:, j, :], Fc)
+            for d in range(s):
+                exact = sum((F(Ls[p, k]) * F(Us[d - p, k]) for p in range(d + 1) for k in range(kb)), Fraction(0))
+                assert F(acc[d, j, i]) == exact, (i, j, d)
+
+
+def test_factorisation_below_the_range_reports_it_and_refinement_uses_the_plain_form():
+    """A matrix scaled well below the range (its U12 columns' scales under
+    oz_emin; U12 = L11^-1 A12 may grow a few bits over A) makes the split LU
+    report info = -3; the refinement then factors in the plain form, so its
+    result is the plain refinement's.  Scaled well above, nothing is
+    reported."""
+    K, s, n = 2, 4, 100
+    Ap, b, exact = synth.problem("uniform", n, config=1, instance=77)
+    assert exact
+    e = O.oz_emin(K, s)
+    low, ok = np.ldexp(Ap, e - 20), np.ldexp(Ap, e + 20)
+    _, _, info = O.getrf_ozaki(K, O.stage(K, low), s)
+    assert info == -3
+    _, _, info = O.getrf_ozaki(K, O.stage(K, ok), s)
+    assert info == 0
+    bl = np.ldexp(b, e - 20)
+    r = O.refine(low, bl, K, ozaki=s)
+    p = O.refine(low, bl, K)
+    assert r["status"] == p["status"] == O.CONVERGED and r["iters"] == p["iters"]
+    np.testing.assert_array_equal(r["x"], p["x"])
