@@ -46,6 +46,10 @@ MEASURED_TRAFFIC = {("ozaki", 3, 4096, 5): 4.270e8, ("plain", 3, 4096, 0): 3.598
 # HBM bytes per multi-word GEMM launch at m = n = k = 4096 (bench.py --mode gemm), the same two counter
 # passes and copy scaling: profiles/counters_gemm_n4096.md.  Valid for that kernel and size only.
 MEASURED_GEMM_TRAFFIC = {(2, 4096): 7.508e9, (3, 4096): 2.274e10}
+# HBM bytes of the batched workload's dominant launch (orders 129..256 of the 8192-system batch, triple-double
+# factor, quad-double-word entries above cond 1e15, 8-wide panels, 512 threads), the same two counter passes and
+# copy scaling: profiles/batch_td_randsvd_8192.md.  Valid for that launch only.
+MEASURED_BATCH_TRAFFIC = {(3, 8192, 1e15, 129, 256, 8, 512): 1.781e11}
 DEFAULT_SLICES = {1: 3, 2: 5, 3: 5, 4: 11}  # split form of the requested factor (TD: 5)
 # double-double split forms timed beside it (cond <= 1e15, above): the headline takes the faster
 DD_SLICES = {False: (4, 5), True: (6, 7)}
@@ -185,6 +189,29 @@ def batch_main(args):
     ns = np.array([a.shape[-1] for a in As], dtype=np.float64)
     nwords = int(sum(a.shape[0] == 4 for a in As))
     work = float(np.sum(2.0 * ns ** 3 / 3.0))
+    # the dominant launch (the largest orders' class), timed alone with
+    # events on its own stream: its LU multiply-subtracts per launch
+    # duration (a lower bound on its FP64 work: the refinement is not counted)
+    if plan is not None:
+        cls = max(S.parts, key=lambda p: max(p[1].ns))
+        dom, dom_cls = cls[1], [c for c in plan["classes"] if c["n_hi"] >= max(cls[1].ns) >= c["n_lo"]][0]
+    else:
+        dom, dom_cls = S, None
+    dom_ms = []
+    for _ in range(3):
+        dom.run(graph=True)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(dom.stream)
+        dom.run(graph=True)
+        e1.record(dom.stream)
+        torch.cuda.synchronize()
+        dom_ms.append(e0.elapsed_time(e1))
+    dom_ms = sorted(dom_ms)[1]
+    dom_ns = np.array(dom.ns, dtype=np.float64)
+    dom_flops = float(np.sum(dom_ns ** 3 / 3.0)) * FMS_FLOPS[K]
+    dom_key = None if dom_cls is None else (K, args.count, args.words_above or 0.0, dom_cls["n_lo"], dom_cls["n_hi"],
+                                            dom_cls["panel"], dom_cls["threads"])
     line = {
         "metric": "refined solves/sec (batched)",
         "value": args.count * 1e3 / ms,
@@ -213,12 +240,15 @@ def batch_main(args):
         # the batched kernel does the whole refined solve; the algorithmic
         # count is the LU's K-word multiply-subtracts alone (n^3/3 per system,
         # FMS_FLOPS[K] flops each), so the fraction is a lower bound
-        "roofline": {"kernel": f"k_batch<{K},panel,threads> (whole refined solves, one launch per size class)",
-                     "bound": "alu", "flops_per_launch": f"{FMS_FLOPS[K]} * sum(n^3/3) (LU multiply-subtracts only)",
-                     "achieved": work / 2.0 * FMS_FLOPS[K] / (ms / 1e3) / 1e12, "peak": FP64_PEAK_TFLOPS,
-                     "unit": "TFLOP/s",
-                     "frac": work / 2.0 * FMS_FLOPS[K] / (ms / 1e3) / 1e12 / FP64_PEAK_TFLOPS,
-                     "traffic": None},
+        "roofline": {"kernel": (f"k_batch<{K},{dom_cls['panel']},{dom_cls['threads']}> (orders "
+                                f"{dom_cls['n_lo']}..{dom_cls['n_hi']}, {len(dom.ns)} whole refined solves)")
+                     if dom_cls else f"k_batch<{K},panel,threads> (every system)",
+                     "bound": "alu", "flops_per_launch": f"{FMS_FLOPS[K]} * sum(n^3/3) over the launch's systems "
+                                                         f"(LU multiply-subtracts only) = {dom_flops:.4g}",
+                     "achieved": dom_flops / (dom_ms / 1e3) / 1e12, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": dom_flops / (dom_ms / 1e3) / 1e12 / FP64_PEAK_TFLOPS, "launch_ms": dom_ms,
+                     "traffic": MEASURED_BATCH_TRAFFIC.get(dom_key), "traffic_unit": "bytes per launch",
+                     "whole_batch_tflops": work / 2.0 * FMS_FLOPS[K] / (ms / 1e3) / 1e12},
         "device_time_split": {"factor_frac": float(fac_ms.sum() / lat_ms.sum()), "by_order": split},
         "status_counts": {int(k): int(v) for k, v in zip(*np.unique(res["status"], return_counts=True))},
         "iters_mean": float(res["iters"].mean()),
