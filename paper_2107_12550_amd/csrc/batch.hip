@@ -299,8 +299,13 @@ __device__ __forceinline__ void resid_row_terms(int n, const double *__restrict_
 
 // ---- the batched solver ---------------------------------------------------------
 
+// Register budget: two waves per SIMD (512 / NT workgroups of NT threads per
+// compute unit, where the LDS allows).  The whole solve in one kernel needs
+// about 430 registers; capped at 256 it spills (about 720 bytes per lane),
+// and the second wave still wins: orders 129..256 (8-wide panels, 256
+// threads) ran 24% faster than at one wave per SIMD without spills.
 template <int K, int PW, int NT>
-__global__ void __launch_bounds__(NT)
+__global__ void __launch_bounds__(NT, 512 / NT)
     k_batch(int64_t count, const int64_t *__restrict__ nn, const int32_t *__restrict__ aws,
             const double *const *__restrict__ As,
             const double *const *__restrict__ bs, double *const *__restrict__ xs, const int32_t *__restrict__ order,
