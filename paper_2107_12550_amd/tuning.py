@@ -41,14 +41,20 @@ def tune(K: int, sample: int = 1024, reps: int = 3, ctol: float = 2.0 ** -150, c
          classes=CLASSES) -> dict:
     """Time every (panel, threads) variant on `sample` seeded randsvd systems
     per size class (cond = 10^U(lc_lo, lc_hi), quad-double-word entries
-    above `words_above`); returns the plan."""
+    above `words_above`), then check whether the classes up to 256 run
+    faster as one launch with the largest of them's variant (no drain
+    between launches) than one launch each, and merge them if so; returns
+    the plan."""
     import synth
     out = []
+    pool = []  # the sampled systems of the classes up to 256
     for ci, (lo, hi) in enumerate(classes):
         As, bs, _, _ = synth.batch(sample, max(lo, 2), hi, lc_lo, lc_hi, config=config, workers=16,
                                    first=ci * sample, words_above=words_above)
         dA = [torch.from_numpy(a).cuda() for a in As]
         db = [torch.from_numpy(b).cuda() for b in bs]
+        if hi <= 256:
+            pool.append((dA, db))
         trials = []
         for nt in THREADS:
             if nt < hi:
@@ -61,7 +67,25 @@ def tune(K: int, sample: int = 1024, reps: int = 3, ctol: float = 2.0 ** -150, c
                     log(f"[tune] K={K} n in [{lo},{hi}] panel {pw} threads {nt} slots {S.slots}: {ms:.3f} ms")
         best = min(trials, key=lambda d: d["ms"])
         out.append(dict(n_lo=lo, n_hi=hi, panel=best["panel"], threads=best["threads"], trials=trials))
-    return dict(K=K, sample=sample, classes=out)
+    plan = dict(K=K, sample=sample, classes=out)
+    small = [c for c in out if c["n_hi"] <= 256]
+    if len(small) > 1:
+        dA = [a for p in pool for a in p[0]]
+        db = [b for p in pool for b in p[1]]
+        big = max(small, key=lambda c: c["n_hi"])
+        split = TunedBatchSolver(dA, db, K, dict(K=K, classes=small), ctol=ctol)
+        ms_split = _time(lambda: split.run(graph=True), reps)
+        one = bnc.BatchSolver(dA, db, K, ctol=ctol, panel=big["panel"], threads=big["threads"])
+        ms_one = _time(lambda: one.run(graph=True), reps)
+        if log:
+            log(f"[tune] orders up to 256: one launch per class {ms_split:.3f} ms, one launch "
+                f"(panel {big['panel']}, threads {big['threads']}) {ms_one:.3f} ms")
+        plan["merge"] = dict(split_ms=ms_split, one_ms=ms_one)
+        if ms_one < ms_split:
+            rest = [c for c in out if c["n_hi"] > 256]
+            plan["classes"] = [dict(n_lo=small[0]["n_lo"], n_hi=big["n_hi"], panel=big["panel"],
+                                    threads=big["threads"], trials=[])] + rest
+    return plan
 
 
 def save_plan(plan: dict, path: str):

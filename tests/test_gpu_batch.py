@@ -228,7 +228,11 @@ def test_tune_smoke(P):
     from paper_2107_12550_amd import tuning
     say("tune smoke")
     plan = tuning.tune(2, sample=16, reps=1)
-    assert [(c["n_lo"], c["n_hi"]) for c in plan["classes"]] == list(tuning.CLASSES)
+    # the classes tile 1..512 in order: the tuned ones, or those up to 256
+    # merged into one launch when that was faster
+    cl = [(c["n_lo"], c["n_hi"]) for c in plan["classes"]]
+    assert cl == list(tuning.CLASSES) or cl == [(1, 256), (257, 512)], cl
+    assert "merge" in plan and plan["merge"]["split_ms"] > 0 and plan["merge"]["one_ms"] > 0
     for c in plan["classes"]:
         assert c["threads"] >= c["n_hi"] and c["panel"] in tuning.PANELS
-        assert c["trials"]
+        assert c["trials"] or (c["n_lo"], c["n_hi"]) == (1, 256)
