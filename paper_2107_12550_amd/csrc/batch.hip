@@ -351,19 +351,21 @@ __global__ void __launch_bounds__(NT, 512 / NT)
         const int64_t nn2 = (int64_t)n * n;  // plane stride of A's words
 
         // ---- checks, row maxima (leading words), exponent bounds (every
-        // word), ||A||_F (leading words)
+        // word): the leading words by rows (thread t = row t, one pass),
+        // the other words, if any, after
         int bad = 0;
         double rmax_i = 0.0;
         int ea = 2000, eb = 2000;
-        for (int64_t e = t; e < (int64_t)aw * nn2; e += NT) {
-            const double v = A[e];
-            bad |= !isfinite(v);
-            if (v != 0.0) {
-                const int ex = ilogb_bits(v);
-                ea = ex < ea ? ex : ea;
-            }
-        }
         if (t < n) {
+            for (int j = 0; j < n; ++j) {
+                const double v = A[(int64_t)j * n + t];
+                bad |= !isfinite(v);
+                if (v != 0.0) {
+                    const int ex = ilogb_bits(v);
+                    ea = ex < ea ? ex : ea;
+                }
+                rmax_i = fmax(rmax_i, fabs(v));
+            }
             for (int w = 0; w < 4; ++w) {
                 const double v = b[w * n + t];
                 bad |= !isfinite(v);
@@ -372,8 +374,14 @@ __global__ void __launch_bounds__(NT, 512 / NT)
                     eb = ex < eb ? ex : eb;
                 }
             }
-            for (int j = 0; j < n; ++j)
-                rmax_i = fmax(rmax_i, fabs(A[(int64_t)j * n + t]));
+        }
+        for (int64_t e = nn2 + t; e < (int64_t)aw * nn2; e += NT) {
+            const double v = A[e];
+            bad |= !isfinite(v);
+            if (v != 0.0) {
+                const int ex = ilogb_bits(v);
+                ea = ex < ea ? ex : ea;
+            }
         }
         if (wg_or<NT>(bad, S.redi)) {
             for (int e = t; e < 4 * n; e += NT)
@@ -389,38 +397,41 @@ __global__ void __launch_bounds__(NT, 512 / NT)
         }
         ea = wg_min_i<NT>(ea, S.redi);
         eb = wg_min_i<NT>(eb, S.redi);
+
+        // ---- K-word copy of A (quad-double words renormalised to K) and,
+        // in the same pass, ||A||_F from the leading words (power-of-two
+        // scaled by the largest entry)
         double anorm;
         {
             const double am = wg_max<NT>(rmax_i, S.red);  // max |a_ij| (leading words)
             const double sc = pow2(-(norm_exp(am) + 1));
             double acc = 0.0;
-            for (int64_t e = t; e < (int64_t)n * n; e += NT) {
-                const double v = A[e] * sc;
-                acc = acc + v * v;
+            if (aw == 1) {
+                for (int64_t e = t; e < nn2; e += NT) {
+                    const double a0 = A[e];
+                    lu[e] = a0;
+#pragma unroll
+                    for (int w = 1; w < K; ++w)
+                        lu[w * ldp + e] = 0.0;
+                    const double v = a0 * sc;
+                    acc = acc + v * v;
+                }
+            } else {
+                for (int64_t e = t; e < nn2; e += NT) {
+                    double v[4], o[K];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        v[u] = A[u * nn2 + e];
+                    renorm<K, 4>(v, o);
+#pragma unroll
+                    for (int w = 0; w < K; ++w)
+                        lu[w * ldp + e] = o[w];
+                    const double s0 = v[0] * sc;
+                    acc = acc + s0 * s0;
+                }
             }
             const double ss = wg_sum<NT>(acc, S.red);
             anorm = am == 0.0 ? 0.0 : sqrt(ss) * pow2(norm_exp(am) + 1);
-        }
-
-        // ---- K-word copy of A (quad-double words renormalised to K)
-        if (aw == 1) {
-            for (int64_t e = t; e < nn2; e += NT) {
-                lu[e] = A[e];
-#pragma unroll
-                for (int w = 1; w < K; ++w)
-                    lu[w * ldp + e] = 0.0;
-            }
-        } else {
-            for (int64_t e = t; e < nn2; e += NT) {
-                double v[4], o[K];
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    v[u] = A[u * nn2 + e];
-                renorm<K, 4>(v, o);
-#pragma unroll
-                for (int w = 0; w < K; ++w)
-                    lu[w * ldp + e] = o[w];
-            }
         }
         __syncthreads();
 
