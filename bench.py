@@ -51,7 +51,7 @@ MEASURED_GEMM_TRAFFIC = {(2, 4096): 7.508e9, (3, 4096): 2.274e10}
 # copy scaling: profiles/batch_td_randsvd_8192.md.  Valid for that launch only.
 MEASURED_BATCH_TRAFFIC = {(3, 8192, 1e15, 129, 256, 8, 512): 1.781e11,  # one wave per SIMD (earlier build)
                           (3, 8192, 1e15, 129, 256, 8, 256): 1.867e11,  # two waves per SIMD
-                          (3, 8192, 1e15, 1, 256, 8, 256): 2.020e11}    # every order up to 256 in one launch
+                          (3, 8192, 1e15, 1, 256, 8, 256): 1.993e11}    # every order up to 256 in one launch
 DEFAULT_SLICES = {1: 3, 2: 5, 3: 5, 4: 11}  # split form of the requested factor (TD: 5)
 # double-double split forms timed beside it (cond <= 1e15, above): the headline takes the faster
 DD_SLICES = {False: (4, 5), True: (6, 7)}
