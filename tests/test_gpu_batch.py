@@ -110,6 +110,30 @@ def test_batched_four_words_512_threads_panel_fallback(P):
         check_vs_oracle(S, refs)
 
 
+def test_words_and_large_orders_through_a_graph(P):
+    """The quad-double-word batch with orders up to 512 (512 threads per
+    workgroup) through a captured HIP graph, replayed twice with the
+    solutions overwritten in between: every replay equals the eager run
+    word for word."""
+    As, bs = words_batch()
+    K = 3
+    say("words batch eager")
+    S = P.BatchSolver([dev(A) for A in As], [dev(b) for b in bs], K, ctol=CTOL)
+    S.run()
+    r0 = S.results()
+    x0 = [x.cpu().numpy() for x in S.xs]
+    for rep in range(2):
+        for x in S.xs:
+            x.fill_(5.0)
+        say("words batch graph replay", rep)
+        S.run(graph=True)
+        r = S.results()
+        assert np.array_equal(r["status"], r0["status"]) and np.array_equal(r["iters"], r0["iters"])
+        for a, b in zip(x0, S.xs):
+            np.testing.assert_array_equal(a, b.cpu().numpy())
+    S.close()
+
+
 @pytest.mark.parametrize("K", [2, 3])
 def test_batched_bitexact_vs_oracle(P, K):
     As, bs = mixed_batch()
