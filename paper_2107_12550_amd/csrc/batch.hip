@@ -17,6 +17,13 @@
 //   tests on workgroup reductions; the update x <- x + 2^e z.
 // Each system records its status, corrections, info and start/end wall-clock
 // ticks.
+//
+// Built once per factor word count: with BNC_BATCH_K = k this unit holds the
+// kernels of K = k only (the K-independent host functions go with k = 1), so
+// the four units compile in parallel; left undefined, it holds every K.
+#ifndef BNC_BATCH_K
+#define BNC_BATCH_K 0
+#endif
 #include "common.hpp"
 #include "exact.hpp"
 #include "mw.hpp"
@@ -897,18 +904,20 @@ __global__ void __launch_bounds__(NT, 512 / NT)
     }
 }
 
-__global__ void k_queue_reset(unsigned *q)
+static __global__ void k_queue_reset(unsigned *q)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0)
         *q = 0;
 }
 
+#if BNC_BATCH_K == 0 || BNC_BATCH_K == 1
 // the queue counter (256 bytes), then one slot per workgroup
 size_t batch_workspace_bytes(int K, int slots, int threads)
 {
     const size_t nt = threads ? (size_t)threads : (size_t)BT_DEFAULT;
     return (size_t)slots * ((size_t)K * nt * nt + (size_t)K * nt) * sizeof(double) + 256;
 }
+#endif
 
 // persistent workgroups per compute unit: as many as registers and LDS allow
 template <int K, int PW, int NT>
@@ -960,8 +969,10 @@ static int occupancy_pw(int pw)
     return occupancy_per_cu<K, 4, NT>();
 }
 
+// persistent workgroups per compute unit of the K-word launch of nt threads
+// (defined in the unit that holds that K's kernels)
 template <int K>
-static int occupancy_k(int pw, int nt)
+int occupancy_k(int pw, int nt)
 {
     switch (nt) {
     case 64:
@@ -975,6 +986,33 @@ static int occupancy_k(int pw, int nt)
     }
 }
 
+#if BNC_BATCH_K != 0
+// the other word counts' kernels live in their own units
+#define EXT(K)                                                                                                  \
+    extern template int occupancy_k<K>(int, int);                                                              \
+    extern template int batch_run<K>(int64_t, const int64_t *, const int32_t *, const double *const *,         \
+                                     const double *const *, double *const *, const int32_t *, void *, int,     \
+                                     const bnc_refine_opts *, bnc_batch_result *, hipStream_t);
+template <int K>
+int batch_run(int64_t count, const int64_t *n, const int32_t *aw, const double *const *A, const double *const *b,
+              double *const *x, const int32_t *order, void *work, int slots, const bnc_refine_opts *o,
+              bnc_batch_result *res, hipStream_t s);
+#if BNC_BATCH_K != 1
+EXT(1)
+#endif
+#if BNC_BATCH_K != 2
+EXT(2)
+#endif
+#if BNC_BATCH_K != 3
+EXT(3)
+#endif
+#if BNC_BATCH_K != 4
+EXT(4)
+#endif
+#undef EXT
+#endif
+
+#if BNC_BATCH_K == 0 || BNC_BATCH_K == 1
 bool batch_panel_ok(int pw) { return pw == 0 || pw == 4 || pw == 8 || pw == 16; }
 bool batch_threads_ok(int nt) { return nt == 0 || nt == 64 || nt == 128 || nt == 256 || nt == 512; }
 
@@ -992,6 +1030,7 @@ int batch_default_slots(int K, int pw, int nt)
                                                   : K == 3 ? occupancy_k<3>(pw, nt) : occupancy_k<4>(pw, nt);
     return per * ncu;
 }
+#endif
 
 template <int K, int PW, int NT>
 static int batch_launch(int64_t count, const int64_t *n, const int32_t *aw, const double *const *A,
@@ -1049,13 +1088,18 @@ int batch_run(int64_t count, const int64_t *n, const int32_t *aw, const double *
 }
 
 #define INST(K)                                                                                                 \
+    template int occupancy_k<K>(int, int);                                                                     \
     template int batch_run<K>(int64_t, const int64_t *, const int32_t *, const double *const *,                 \
                               const double *const *, double *const *, const int32_t *, void *, int,            \
                               const bnc_refine_opts *, bnc_batch_result *, hipStream_t);
+#if BNC_BATCH_K == 0
 INST(1)
 INST(2)
 INST(3)
 INST(4)
+#else
+INST(BNC_BATCH_K)
+#endif
 #undef INST
 
 }  // namespace bnc
