@@ -34,7 +34,11 @@ constexpr int BT_MAX = 512;  // most threads per workgroup (= largest order)
 constexpr int BT_DEFAULT = 256;  // threads per workgroup unless chosen
 constexpr size_t BLDS_MAX = 160 * 1024;  // LDS of one compute unit
 constexpr int BNB_DEFAULT = 8;  // LU panel width unless tuned (4, 8 or 16)
-constexpr int BRB = 24;     // residual bins per row (816 bits)
+// Residual bins: a row of order n <= 512 has at most 32 n + 4 < 2^15 terms
+// (eight per word of A and column, four of b), so 38-bit digits still sum
+// exactly; 22 of them span 836 bits (34-bit digits would need 24 bins)
+constexpr int BRB_W = 38;   // residual bin width (bits)
+constexpr int BRB = 22;     // residual bins per row
 constexpr int BJ = 4;       // trailing-update columns per thread at once
 constexpr int RPF = 4;      // residual: columns of A loaded ahead
 
@@ -297,7 +301,7 @@ __device__ __forceinline__ void resid_row_terms(int n, const double *__restrict_
                         tt[2 * w] = -hi;
                         tt[2 * w + 1] = -lo;
                     }
-                    deposit_many(tt, sg0, bins, nb, nbu, lim0, bd);
+                    deposit_many<BRB, 8, BRB_W>(tt, sg0, bins, nb, nbu, lim0, bd);
                 }
             }
         }
@@ -820,7 +824,7 @@ __global__ void __launch_bounds__(NT, 512 / NT)
                 ebnd.a = ea;
                 ebnd.x = ex;
                 ebnd.b = eb;
-                an = row_anchor<BRB>(rmax_i, xmax, b[t], h, lowest_bit(ebnd));
+                an = row_anchor<BRB, BRB_W>(rmax_i, xmax, b[t], h, lowest_bit(ebnd));
             }
             const int nbu = wave_max_nb(t < n && an.any ? an.nb : 0);
             if (t < n && an.any) {
@@ -839,8 +843,8 @@ __global__ void __launch_bounds__(NT, 512 / NT)
 #pragma unroll
                 for (int w = 0; w < 4; ++w)
                     tb[w] = b[w * n + t];
-                deposit_many(tb, sg0, bins, an.nb, nbu, lim0, bd);
-                bd = bins_to_qd(bins, an.nb, an.e0, rr) || bd;
+                deposit_many<BRB, 4, BRB_W>(tb, sg0, bins, an.nb, nbu, lim0, bd);
+                bd = bins_to_qd<BRB, BRB_W>(bins, an.nb, an.e0, rr) || bd;
                 rbad = bd ? 1 : 0;
             }
             inexact |= wg_or<NT>(rbad, S.redi);

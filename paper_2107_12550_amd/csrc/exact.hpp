@@ -3,12 +3,14 @@
 // as: products split exactly, summed exactly, rounded once).
 //
 // Terms are binary64 numbers (TwoProd halves of A_ij^(u) x_j^(w), and the
-// words of b_i).  Each term is cut into fixed-point digits of W = 34 bits
-// over up to 40 bins anchored at the row's largest possible term: the
-// extraction (sigma + t) - sigma with sigma = 1.5 * 2^(52 + e_bin) is exact
-// and rounds t to a multiple of 2^e_bin.  The bins a row uses reach down to
-// a bound on the lowest bit of any term (smallest exponents of the words of
-// A, x and b), so every digit sum is exact while the row has < 2^19 terms.
+// words of b_i).  Each term is cut into fixed-point digits of W bits (34
+// unless a caller sets another width) over up to 40 bins anchored at the
+// row's largest possible term: the extraction (sigma + t) - sigma with
+// sigma = 1.5 * 2^(52 + e_bin) is exact and rounds t to a multiple of
+// 2^e_bin.  The bins a row uses reach down to a bound on the lowest bit of
+// any term (smallest exponents of the words of A, x and b).  A digit past
+// the first bin is at most 2^(W-1) of its bin's quanta, so every digit sum
+// is exact while the row has fewer than 2^(53-W) terms (2^19 at W = 34).
 // The bins are then read as one signed integer (32-bit limbs in int64,
 // carry-save) and rounded greedily to four (or eight) binary64 words with
 // round-to-nearest-even.
@@ -64,7 +66,7 @@ __device__ __forceinline__ int lowest_bit(const ExpBounds &eb)
     return lo;
 }
 
-template <int NBMAX = RB_NB>
+template <int NBMAX = RB_NB, int W = RB_W>
 __device__ __forceinline__ RowAnchor row_anchor(double amax, double xmax, double b0, int h, int elow)
 {
     int eT = -100000;
@@ -83,13 +85,13 @@ __device__ __forceinline__ RowAnchor row_anchor(double amax, double xmax, double
         e0 = 900;
     r.e0 = e0;
     // bins q = 0..nb-1 have quanta 2^(e0 - W q); the last must reach elow
-    int nb = (e0 - elow + RB_W - 1) / RB_W + 1;
+    int nb = (e0 - elow + W - 1) / W + 1;
     if (nb < 1)
         nb = 1;
     if (nb > NBMAX)
         nb = NBMAX;
-    if (e0 - RB_W * (nb - 1) < -1074 + 0)  // keep every quantum a normal power of two
-        nb = (e0 + 1022) / RB_W + 1;
+    if (e0 - W * (nb - 1) < -1074 + 0)  // keep every quantum a normal power of two
+        nb = (e0 + 1022) / W + 1;
     r.nb = nb;
     return r;
 }
@@ -121,11 +123,11 @@ __device__ __forceinline__ void deposit(double t, const double (&sig)[NBMAX], do
 // the bins past them receive zero digits; a nonzero digit there, or a term
 // with bits left after nbu bins, marks the row as inexact, as a term with
 // bits left after nb bins does in deposit.
-template <int NBMAX, int NT>
+template <int NBMAX, int NT, int W = RB_W>
 __device__ __forceinline__ void deposit_many(double (&tt)[NT], double sg0, double (&bins)[NBMAX], int nb, int nbu,
                                              double lim0, bool &bad)
 {
-    constexpr double STEP = 1.0 / (double)(1ull << RB_W);
+    constexpr double STEP = 1.0 / (double)(1ull << W);
 #pragma unroll
     for (int k = 0; k < NT; ++k)
         bad = bad || !(fabs(tt[k]) <= lim0);
@@ -171,22 +173,22 @@ __device__ __forceinline__ int wave_max_nb(int nb)
 // ---- exact signed integer in 32-bit limbs (carry-save in int64) ------------
 // Limbs for the integer of NB bins: digits below 2^53 units of their bin, the
 // top bin's unit at bit W (NB - 1), plus carry and sign headroom.
-template <int NB>
+template <int NB, int W = RB_W>
 struct Big {
-    static constexpr int L = (NB * RB_W + 53 + 64 + 31) / 32;
+    static constexpr int L = (NB * W + 53 + 64 + 31) / 32;
     int64_t l[L];
 };
 
 // add v * 2^pos, v signed with |v| < 2^63, pos >= 0
-template <int NB>
-__device__ __forceinline__ void big_add(Big<NB> &B, int64_t v, int pos)
+template <int NB, int W>
+__device__ __forceinline__ void big_add(Big<NB, W> &B, int64_t v, int pos)
 {
     const int L = pos >> 5, sh = pos & 31;
     const uint64_t lo = (uint64_t)(v & 0xffffffffLL);
     const int64_t hi = v >> 32;  // arithmetic: v = lo + hi * 2^32
     const uint64_t los = lo << sh;
 #pragma unroll
-    for (int q = 0; q < Big<NB>::L; ++q) {
+    for (int q = 0; q < Big<NB, W>::L; ++q) {
         if (q == L)
             B.l[q] += (int64_t)(los & 0xffffffffULL);
         if (q == L + 1)
@@ -194,32 +196,32 @@ __device__ __forceinline__ void big_add(Big<NB> &B, int64_t v, int pos)
     }
 }
 
-template <int NB>
-__device__ __forceinline__ void big_norm(Big<NB> &B)
+template <int NB, int W>
+__device__ __forceinline__ void big_norm(Big<NB, W> &B)
 {
 #pragma unroll
-    for (int q = 0; q < Big<NB>::L - 1; ++q) {
+    for (int q = 0; q < Big<NB, W>::L - 1; ++q) {
         const int64_t c = B.l[q] >> 32;
         B.l[q] -= c * ((int64_t)1 << 32);
         B.l[q + 1] += c;
     }
 }
 
-template <int NB>
-__device__ __forceinline__ void big_neg(Big<NB> &B)
+template <int NB, int W>
+__device__ __forceinline__ void big_neg(Big<NB, W> &B)
 {
 #pragma unroll
-    for (int q = 0; q < Big<NB>::L; ++q)
+    for (int q = 0; q < Big<NB, W>::L; ++q)
         B.l[q] = -B.l[q];
 }
 
 // Round |B| (B normalised, non-negative) to nearest binary64 mantissa:
 // returns mant (0 if B == 0) and the bit position of its least significant
 // bit.
-template <int NB>
-__device__ __forceinline__ uint64_t big_round(const Big<NB> &M, int &lsb)
+template <int NB, int W>
+__device__ __forceinline__ uint64_t big_round(const Big<NB, W> &M, int &lsb)
 {
-    constexpr int BLN = Big<NB>::L;
+    constexpr int BLN = Big<NB, W>::L;
     int hl = -1;
 #pragma unroll
     for (int q = BLN - 1; q >= 0; --q)
@@ -272,23 +274,23 @@ __device__ __forceinline__ uint64_t big_round(const Big<NB> &M, int &lsb)
 // Add the digits of bins[0..cnt) = bins q0.. of a row with nb bins (bin q
 // holds multiples of 2^(e0 - W q)) into the row's integer, whose unit is the
 // last bin's quantum.
-template <int NB, int CNT>
-__device__ __forceinline__ void bins_into_big(Big<NB> &B, const double (&bins)[CNT], int q0, int nb, int e0)
+template <int NB, int W, int CNT>
+__device__ __forceinline__ void bins_into_big(Big<NB, W> &B, const double (&bins)[CNT], int q0, int nb, int e0)
 {
 #pragma unroll
     for (int c = 0; c < CNT; ++c) {
         const int q = q0 + c;
         if (q < nb) {
-            const double dig = ldexp(bins[c], -(e0 - RB_W * q));
-            big_add(B, (int64_t)dig, RB_W * (nb - 1 - q));
+            const double dig = ldexp(bins[c], -(e0 - W * q));
+            big_add(B, (int64_t)dig, W * (nb - 1 - q));
         }
     }
 }
 
 // Canonical LW-word rounding of the row's integer (unit 2^elow); returns
 // true if a word fell outside the binary64 normal range.
-template <int NB, int LW>
-__device__ __forceinline__ bool big_to_words(Big<NB> &B, int elow, double (&out)[LW])
+template <int NB, int W, int LW>
+__device__ __forceinline__ bool big_to_words(Big<NB, W> &B, int elow, double (&out)[LW])
 {
     bool bad = false;
 #pragma unroll
@@ -296,7 +298,7 @@ __device__ __forceinline__ bool big_to_words(Big<NB> &B, int elow, double (&out)
         out[w] = 0.0;
     for (int w = 0; w < LW; ++w) {
         big_norm(B);
-        const bool neg = B.l[Big<NB>::L - 1] < 0;
+        const bool neg = B.l[Big<NB, W>::L - 1] < 0;
         if (neg) {
             big_neg(B);
             big_norm(B);
@@ -322,21 +324,21 @@ __device__ __forceinline__ bool big_to_words(Big<NB> &B, int elow, double (&out)
     return bad;
 }
 
-template <int NBMAX, int LW>
+template <int NBMAX, int LW, int W = RB_W>
 __device__ __forceinline__ bool bins_to_words(const double (&bins)[NBMAX], int nb, int e0, double (&out)[LW])
 {
-    Big<NBMAX> B;
+    Big<NBMAX, W> B;
 #pragma unroll
-    for (int q = 0; q < Big<NBMAX>::L; ++q)
+    for (int q = 0; q < Big<NBMAX, W>::L; ++q)
         B.l[q] = 0;
     bins_into_big(B, bins, 0, nb, e0);
-    return big_to_words(B, e0 - RB_W * (nb - 1), out);
+    return big_to_words(B, e0 - W * (nb - 1), out);
 }
 
-template <int NBMAX>
+template <int NBMAX, int W = RB_W>
 __device__ __forceinline__ bool bins_to_qd(const double (&bins)[NBMAX], int nb, int e0, double (&out)[4])
 {
-    return bins_to_words<NBMAX, 4>(bins, nb, e0, out);
+    return bins_to_words<NBMAX, 4, W>(bins, nb, e0, out);
 }
 
 }  // namespace bnc
