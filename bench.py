@@ -47,11 +47,10 @@ MEASURED_TRAFFIC = {("ozaki", 3, 4096, 5): 4.270e8, ("plain", 3, 4096, 0): 3.598
 # passes and copy scaling: profiles/counters_gemm_n4096.md.  Valid for that kernel and size only.
 MEASURED_GEMM_TRAFFIC = {(2, 4096): 7.508e9, (3, 4096): 2.274e10}
 # HBM bytes of the batched workload's dominant launch (the 8192-system batch, triple-double
-# factor, quad-double-word entries above cond 1e15, 8-wide panels, 512 threads), the same two counter passes and
-# copy scaling: profiles/batch_td_randsvd_8192.md.  Valid for that launch only.
-MEASURED_BATCH_TRAFFIC = {(3, 8192, 1e15, 129, 256, 8, 512): 1.781e11,  # one wave per SIMD (earlier build)
-                          (3, 8192, 1e15, 129, 256, 8, 256): 1.867e11,  # two waves per SIMD
-                          (3, 8192, 1e15, 1, 256, 8, 256): 1.993e11}    # every order up to 256 in one launch
+# factor, quad-double-word entries above cond 1e15, every order up to 256 in one launch of 8-wide panels and 256
+# threads), the same two counter passes and copy scaling: profiles/batch_td_randsvd_8192.md.  Valid for that
+# launch of the current kernel only.
+MEASURED_BATCH_TRAFFIC = {(3, 8192, 1e15, 1, 256, 8, 256): 1.995e11}
 DEFAULT_SLICES = {1: 3, 2: 5, 3: 5, 4: 11}  # split form of the requested factor (TD: 5)
 # double-double split forms timed beside it (cond <= 1e15, above): the headline takes the faster
 DD_SLICES = {False: (4, 5), True: (6, 7)}
