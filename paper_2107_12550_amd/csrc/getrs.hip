@@ -130,7 +130,7 @@ __global__ void k_diag_recip(int64_t n, const double *__restrict__ LU, int64_t l
 // bounded (on timeout the abort flag releases all waits and the result is
 // garbage).  A right-hand side that holds the XSENT bit pattern can stall
 // a poll in the same way.
-constexpr int TS_G = 8;   // columns consumed together
+constexpr int TS_G = 4;   // columns consumed together (below 64)
 constexpr int TS_NG = TS_BS / TS_G;  // groups per block
 constexpr int TS_PF = 4;  // groups of entries in flight (wave 0)
 constexpr unsigned TS_SPIN = 1u << 22;
@@ -318,7 +318,7 @@ __global__ void __launch_bounds__(2 * TS_BS)
         for (int p = 0; p < TS_PF; ++p) {
             const int G = G0 + p;
             const int c = G / TS_NG, g0 = (G % TS_NG) * TS_G;
-            ts_wait(stamp[c & 1], 0xFFull << g0, c + 1, spins, abort_flag);
+            ts_wait(stamp[c & 1], ((1ull << TS_G) - 1) << g0, c + 1, spins, abort_flag);
 #pragma unroll
             for (int q = 0; q < TS_G; ++q) {
                 double yk[K], o[K];
