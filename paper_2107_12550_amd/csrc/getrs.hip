@@ -130,8 +130,14 @@ __global__ void k_diag_recip(int64_t n, const double *__restrict__ LU, int64_t l
 // bounded (on timeout the abort flag releases all waits and the result is
 // garbage).  A right-hand side that holds the XSENT bit pattern can stall
 // a poll in the same way.
-constexpr int TS_G = 4;   // columns consumed together (below 64)
-constexpr int TS_NG = TS_BS / TS_G;  // groups per block
+// Columns consumed together, a divisor of 64 below it, by word count (the
+// faster of 4 and 8 for each K at n = 4096; the solution does not depend on
+// it).  Each kernel names it TS_G and its groups per block TS_NG.
+template <int K>
+constexpr int ts_group()
+{
+    return (K == 2 || K == 4) ? 4 : 8;
+}
 constexpr int TS_PF = 4;  // groups of entries in flight (wave 0)
 constexpr unsigned TS_SPIN = 1u << 22;
 constexpr int64_t TS_SENT = (int64_t)0xFFF40000DEADBEEFull;
@@ -260,6 +266,7 @@ __global__ void __launch_bounds__(2 * TS_BS)
     k_trsv_lower(const double *__restrict__ LU, int64_t lda, int64_t ldp, const double *__restrict__ y, int64_t ldy,
                  int64_t n, double *__restrict__ x, int *__restrict__ abort_flag, const int *__restrict__ skip)
 {
+    constexpr int TS_G = ts_group<K>(), TS_NG = TS_BS / TS_G;
     TS_SKIP_IF(skip);  // every thread of the grid reads the same flag
     extern __shared__ double dblk[];  // own diagonal block [w][c][r]
     __shared__ double yb[2][TS_BS][K];
@@ -384,6 +391,7 @@ __global__ void __launch_bounds__(2 * TS_BS)
                  const double *__restrict__ x, double *__restrict__ xo, double *__restrict__ y, int64_t ldy, int64_t n,
                  int *__restrict__ abort_flag, const int *__restrict__ skip)
 {
+    constexpr int TS_G = ts_group<K>(), TS_NG = TS_BS / TS_G;
     TS_SKIP_IF(skip);
     extern __shared__ double dblk[];
     __shared__ double xb[2][TS_BS][K];
