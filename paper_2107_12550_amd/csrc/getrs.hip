@@ -267,6 +267,7 @@ __global__ void __launch_bounds__(2 * TS_BS)
                  int64_t n, double *__restrict__ x, int *__restrict__ abort_flag, const int *__restrict__ skip)
 {
     constexpr int TS_G = ts_group<K>(), TS_NG = TS_BS / TS_G;
+    static_assert(TS_G < 64 && TS_BS % TS_G == 0 && TS_NG % TS_PF == 0, "group size must tile the block");
     TS_SKIP_IF(skip);  // every thread of the grid reads the same flag
     extern __shared__ double dblk[];  // own diagonal block [w][c][r]
     __shared__ double yb[2][TS_BS][K];
@@ -392,6 +393,7 @@ __global__ void __launch_bounds__(2 * TS_BS)
                  int *__restrict__ abort_flag, const int *__restrict__ skip)
 {
     constexpr int TS_G = ts_group<K>(), TS_NG = TS_BS / TS_G;
+    static_assert(TS_G < 64 && TS_BS % TS_G == 0 && TS_NG % TS_PF == 0, "group size must tile the block");
     TS_SKIP_IF(skip);
     extern __shared__ double dblk[];
     __shared__ double xb[2][TS_BS][K];
